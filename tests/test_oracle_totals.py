@@ -1,0 +1,121 @@
+"""Pins of the whole oracle (history by direct sums + local asymptotics)
+against continuous closed forms, at the method's discretization accuracy.
+
+* radial sources on the unit disk: V[f](r) = -log r int_0^r f rho drho
+  - int_r^1 log(rho) f rho drho (Sec. 1 volume potential of a radial f);
+* unit-circle layer potentials: S[cos n t] = r^n cos(n t)/(2n) inside and
+  r^-n cos(n t)/(2n) outside, D[1] = -1 / -1/2 / 0 (Gauss, with the jump
+  relation of Sec. 1), D[cos n t] = -r^n cos(n t)/2 inside, +r^-n cos(n t)/2
+  outside (outward normal);
+* Green's representation inside the disk, u = V[-lap u] + S[du/dnu] - D[u]
+  (Sec. 1, eq. neu_rep), which fixes the relative signs of V, S and D.
+"""
+import numpy as np
+import pytest
+from scipy.special import exp1
+
+import oracle
+from workloads import circle_layer_problem, disk_problem
+from workloads.problems import Problem, panel_nodes, StarCurve, trig_density, gauss_jets
+
+
+def radial_gauss_V(r, a):
+    """Closed form of V for f = exp(-rho^2/a) on the unit disk."""
+    r = np.asarray(r, float)
+
+    def P(s):
+        s = np.asarray(s, float)
+        out = np.full_like(s, 0.5772156649015329)
+        nz = s > 0
+        out[nz] = -np.exp(-s[nz]) * np.log(s[nz]) - exp1(s[nz])
+        return out
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lr = np.where(r > 0, np.log(np.maximum(r, 1e-300)) * (1 - np.exp(-r * r / a)), 0.0)
+    return (-(a / 2) * lr
+            - (a / 4) * (np.log(a) * (np.exp(-r * r / a) - np.exp(-1 / a)) + P(1 / a) - P(r * r / a)))
+
+
+def test_radial_closed_form_values():
+    """The closed form reproduces values computed independently by quadrature."""
+    from scipy.integrate import quad
+    a = 0.1
+    for r in (0.25, 0.5, 0.9):
+        f = lambda p: np.exp(-p * p / a) * p
+        ref = -np.log(r) * quad(f, 0, r, epsabs=1e-15)[0] - quad(lambda p: np.log(p) * f(p), r, 1, epsabs=1e-15)[0]
+        assert abs(radial_gauss_V(r, a) - ref) < 1e-14
+
+
+def test_disk_gaussian_matches_closed_form():
+    P = disk_problem(2000, seed=1)
+    out = oracle.evaluate(P, kinds="V")
+    rr = np.hypot(P.tgt_x, P.tgt_y)
+    exact = radial_gauss_V(rr, 0.1)
+    e = oracle.rel_linf(out["V"], exact)
+    assert e < 1e-4, e
+    # the local part matters: dropping it is a 1e-2 error
+    assert oracle.rel_linf(out["V_hist"], exact) > 1e-3
+
+
+def test_disk_constant_source_matches_closed_form():
+    P = disk_problem(2000, seed=7, gauss=((1.0, 0.0, 0.0, 1e6),))  # f == 1 to 1e-12
+    out = oracle.evaluate(P, kinds="V")
+    rr = np.hypot(P.tgt_x, P.tgt_y)
+    e = oracle.rel_linf(out["V"], (1 - rr * rr) / 4)
+    assert e < 2e-4, e
+
+
+def _circle_targets(delta):
+    sd = np.sqrt(delta)
+    cs = np.array([0.0, 0.3, 1.0, 2.5, 6.0, 15.0, 40.0])
+    th = np.linspace(0.1, 2 * np.pi, 11, endpoint=False)
+    pts = []
+    for c in cs:
+        for sgn in ((1, -1) if c > 0 else (0,)):
+            rad = 1 - sgn * c * sd
+            pts.append(np.stack([rad * np.cos(th), rad * np.sin(th)], 1))
+    pts.append(np.array([[0.0, 0.3], [0.5, 0.1], [1.6, -0.4]]))
+    return np.concatenate(pts)
+
+
+@pytest.mark.parametrize("n", [0, 2, 3])
+def test_circle_layer_potentials_closed_forms(n):
+    nb = 600
+    delta = 3 * (2 * np.pi / nb) ** 2
+    tg = _circle_targets(delta)
+    _, ser = trig_density([0.0] * n + [1.0], [])
+    P = circle_layer_problem(nb, tg, sigma_fn=ser, mu_fn=ser)
+    out = oracle.evaluate(P, delta=delta, order_s=4, order_d=4)
+    r = np.hypot(tg[:, 0], tg[:, 1])
+    th = np.arctan2(tg[:, 1], tg[:, 0])
+    inside = P.geom["sgn"] > 0
+    on = P.geom["sgn"] == 0
+    if n == 0:
+        S_ex = np.where(r > 1, -np.log(r), 0.0)
+        D_ex = np.where(inside, -1.0, np.where(on, -0.5, 0.0))
+    else:
+        cn = np.cos(n * th)
+        S_ex = np.where(r <= 1, r ** n, r ** (-n)) * cn / (2 * n)
+        D_ex = np.where(inside, -r ** n * cn / 2, np.where(on, 0.0, r ** (-n) * cn / 2))
+    assert np.max(np.abs(out["S"] - S_ex)) < 2e-7
+    assert np.max(np.abs(out["D"] - D_ex)) < 2e-7
+
+
+def test_green_representation_on_disk():
+    """u = |x|^2: V[-4] + S[2] - D[1] = |x|^2 inside the unit disk."""
+    P = disk_problem(3000, seed=11, gauss=((1.0, 0.0, 0.0, 1e6),))
+    curve = StarCurve(1.0, (1.0,))
+    bx, by, bnx, bny, bw, bt = panel_nodes(curve, 64, 16)
+    n = P.n_tgt
+    f = -4.0 * np.ones(P.n_src)
+    jet = np.zeros((6, n))
+    jet[0] = -4.0
+    sig_jet = np.zeros((3, n))
+    sig_jet[0] = 2.0
+    mu_jet = np.zeros((5, n))
+    mu_jet[0] = 1.0
+    Q = Problem("green", P.src_x, P.src_y, P.src_w, bx, by, bnx, bny, bw, P.tgt_x, P.tgt_y,
+                P.geom, f, jet, 2.0 * np.ones(bx.size), sig_jet, np.ones(bx.size), mu_jet)
+    out = oracle.evaluate(Q, order_s=4, order_d=4)
+    u = out["V"] + out["S"] - out["D"]
+    exact = P.tgt_x ** 2 + P.tgt_y ** 2
+    assert np.max(np.abs(u - exact)) < 1e-4
