@@ -1,0 +1,222 @@
+"""Benchmark: target points/s for V[f] + D[mu] through the C ABI on one MI355X.
+
+Workload (timed step = one vp_eval of V[f] + D[mu], all stages of the path):
+  square [-1,1]^2, 200k triangles with 10% sliver splits, degenerate
+  triangles and 0.2% gaps (~1.2M volume nodes = targets), f = 5 Gaussians,
+  D[mu] from 20k Gauss-Legendre boundary nodes with mu = cos(3 theta),
+  float64 at tolerance 1e-10.
+A second leg runs the float32 path (tolerance 1e-6) on the unit disk with
+~2M triangles (~12M nodes, V[f]).
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region;
+the timed region is bracketed by torch.cuda.synchronize().  Per-stage times
+come from HIP events recorded on the plan's stream (vp_set_timing) in a
+separate pass of the same number of steps.  The CPU baseline is the float64
+oracle (direct sums + local asymptotics) on a bounded sample of targets on
+this host's cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "target pts/s for V[f]+D[mu] at 1e-6 FP32 vs 1e-10 FP64; p50/p99 request latency"
+HBM_PEAK_GBS = 8000.0
+STAGES = ["strengths", "spread", "row_fft", "col_fft_mul", "row_ifft", "interp", "local"]
+KERNELS = {"strengths": "k_strengths", "spread": "k_spread", "row_fft": "k_row_r2c",
+           "col_fft_mul": "k_col", "row_ifft": "k_row_c2r", "interp": "k_interp", "local": "k_local"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(info, P, kinds, b):
+    """Bytes each stage must move at minimum (one read of each input, one write of each output)."""
+    n_v = P.n_src if "V" in kinds else 0
+    n_b = P.n_bnd if ("S" in kinds or "D" in kinds) else 0
+    C = 3 if "D" in kinds else 1
+    cb = 1 if "D" not in kinds else 3
+    out = dict.fromkeys(STAGES, 0.0)
+    out["strengths"] = n_v * (16 + b) + n_b * (8 * 4 + cb * b)
+    nt = P.n_tgt
+    for l in range(2):
+        F = info["fine"][l]
+        M = (info["modes"][l] - 1) // 2
+        half = (M + 1) * F * 2 * b
+        out["spread"] += n_v * (4 + 2 * b + b) + n_b * (4 + 2 * b + cb * b) + C * F * F * b
+        out["row_fft"] += C * F * F * b + C * half
+        out["col_fft_mul"] += C * half + half + (M + 1) ** 2 * b
+        out["row_ifft"] += half + F * F * b
+        out["interp"] += F * F * b + nt * (4 + 2 * b + 4) + nt * b
+    loc = nt * (6 * 8 + 1 + 2 * b + 8)
+    if "V" in kinds:
+        loc += nt * 6 * 8
+    if "D" in kinds:
+        loc += nt * 5 * 8
+    if "S" in kinds:
+        loc += nt * 3 * 8
+    out["local"] = loc
+    return out
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("vp_kernels.hip", "vp_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2409_11998_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, workload):
+    """HBM bytes per launch from committed counter summaries, if taken on the current kernels."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        e = d.get(workload, {}).get(kernel)
+        if e and e.get("source_hash") == kernel_source_hash():
+            return e["hbm_bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
+def time_steps(torch, fn, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def stage_times(torch, plan, fn, steps):
+    plan.set_timing(True)
+    acc = dict.fromkeys(STAGES + ["total"], 0.0)
+    for _ in range(steps):
+        fn()
+        t = plan.timing()
+        for k in acc:
+            acc[k] += t[k]
+    plan.set_timing(False)
+    torch.cuda.synchronize()
+    return {k: v / steps for k, v in acc.items()}
+
+
+def run_leg(torch, P, kinds, tol, precision, steps, warmup, oracle_sample, seed):
+    from workloads.device import make_plan, run, to_device
+    dev = to_device(P)
+    mask = (1 if "V" in kinds else 0) | (2 if "S" in kinds else 0) | (4 if "D" in kinds else 0)
+    t0 = time.perf_counter()
+    plan = make_plan(dev, tol=tol, precision=precision, kinds=mask)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+    out = torch.empty(P.n_tgt, dtype=torch.float64, device="cuda")
+    fn = lambda: run(plan, dev, kinds, out=out)
+    for _ in range(warmup):
+        fn()
+    el = time_steps(torch, fn, steps)
+    st = stage_times(torch, plan, fn, steps)
+    res = dict(info=info, plan_s=plan_s, elapsed=el, stages=st)
+    # parity on a seeded target sample against the float64 oracle (also the CPU baseline)
+    fn()
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    if oracle_sample:
+        import oracle
+        from oracle import direct
+        rng = np.random.default_rng(seed)
+        idx = np.sort(rng.choice(P.n_tgt, size=min(oracle_sample, P.n_tgt), replace=False))
+        sub = P.subset_targets(idx)
+        t1 = time.perf_counter()
+        ref = oracle.evaluate(sub, kinds=kinds)["total"]
+        res["oracle_s"] = time.perf_counter() - t1
+        res["oracle_n"] = len(idx)
+        res["oracle_threads"] = direct.num_threads()
+        res["e_inf_sample"] = float(np.max(np.abs(got[idx] - ref)) / np.max(np.abs(ref)))
+    plan.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--oracle-sample", type=int, default=192, help="targets for the CPU oracle leg")
+    ap.add_argument("--no-fp32-leg", action="store_true")
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink the workloads (quick runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    import paper_2409_11998_amd
+    paper_2409_11998_amd.lib()
+    from workloads import config_problem
+
+    log("bench: generating square-200k workload")
+    P = config_problem(2, scale=args.scale)
+    log("bench: fp64 V+D leg, n_tgt=%d n_bnd=%d" % (P.n_tgt, P.n_bnd))
+    r64 = run_leg(torch, P, "VD", 1e-10, 1, args.steps, args.warmup, args.oracle_sample, seed=20)
+    value = P.n_tgt * args.steps / r64["elapsed"]
+    ms = 1000.0 * r64["elapsed"] / args.steps
+    alg = algorithmic_bytes(r64["info"], P, "VD", 8)
+    st = r64["stages"]
+    dom = max(STAGES, key=lambda k: st[k])
+    achieved = alg[dom] / (st[dom] * 1e-3) / 1e9
+    workload = "square-200k-slivers-gaps V+D fp64 tol1e-10"
+    roof = {"bound": "hbm", "kernel": KERNELS[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profiles(KERNELS[dom], workload),
+            "algorithmic_bytes_per_launch": int(alg[dom]), "avg_ms": round(st[dom], 4)}
+    stages_gbs = {k: round(alg[k] / (st[k] * 1e-3) / 1e9, 1) for k in STAGES if st[k] > 0}
+    cpu = None
+    if args.oracle_sample:
+        cpu = {"value": round(r64["oracle_n"] / r64["oracle_s"], 2), "unit": "target pts/s",
+               "cores": r64["oracle_threads"], "kind": "oracle",
+               "sample": "%d seeded targets of the same workload against all %d sources and %d boundary nodes"
+                         % (r64["oracle_n"], P.n_src, P.n_bnd)}
+    rec = {"metric": METRIC, "value": round(value, 1), "unit": "target pts/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": workload, "n_src": P.n_src, "n_bnd": P.n_bnd, "n_tgt": P.n_tgt,
+                      "fine_grid": list(r64["info"]["fine"]), "modes": list(r64["info"]["modes"]),
+                      "spread_width": list(r64["info"]["width"]), "tol": 1e-10},
+           "roofline": roof, "cpu_baseline": cpu,
+           "stages_ms": {k: round(v, 4) for k, v in st.items()}, "stages_gbs": stages_gbs,
+           "plan_s": round(r64["plan_s"], 3), "e_inf_vs_oracle_sample": r64.get("e_inf_sample")}
+    if not args.no_fp32_leg:
+        log("bench: generating disk-2M workload")
+        Q = config_problem(3, scale=args.scale)
+        log("bench: fp32 V leg, n_tgt=%d" % Q.n_tgt)
+        r32 = run_leg(torch, Q, "V", 1e-6, 0, args.steps, args.warmup, max(16, args.oracle_sample // 4), seed=30)
+        alg32 = algorithmic_bytes(r32["info"], Q, "V", 4)
+        st32 = r32["stages"]
+        rec["fp32"] = {"workload": "disk-2M V fp32 tol1e-6", "n_tgt": Q.n_tgt,
+                       "value": round(Q.n_tgt * args.steps / r32["elapsed"], 1), "unit": "target pts/s",
+                       "ms_per_step": round(1000.0 * r32["elapsed"] / args.steps, 4),
+                       "fine_grid": list(r32["info"]["fine"]), "spread_width": list(r32["info"]["width"]),
+                       "stages_ms": {k: round(v, 4) for k, v in st32.items()},
+                       "stages_gbs": {k: round(alg32[k] / (st32[k] * 1e-3) / 1e9, 1) for k in STAGES if st32[k] > 0},
+                       "e_inf_vs_oracle_sample": r32.get("e_inf_sample"), "plan_s": round(r32["plan_s"], 3)}
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * vp.h -- C ABI of the MI355X layer/volume potential library (libvp.so).
+ *
+ * Evaluates, at a set of targets, the 2-D Laplace potentials of the paper
+ * "A lightweight, geometrically flexible fast algorithm for the evaluation of
+ * layer and volume potentials" (Fryklund, Greengard, Jiang, Potter):
+ *
+ *   V[f](x)     = int_Omega G(x-y) f(y) dy                     (Sec. 1, eq. volpotposgreen)
+ *   S[sigma](x) = int_dOmega G(x-y) sigma(y) ds_y              (Sec. 1, eq. slpot)
+ *   D[mu](x)    = int_dOmega dG/dnu_y (x-y) mu(y) ds_y         (Sec. 1, eq. dlpot)
+ *
+ * with G(x) = -log|x| / (2 pi) and nu the outward normal.  Each potential is
+ * split in time (Sec. 2) into a local part, evaluated per target from the
+ * small-delta asymptotic expansions (Sec. 4), and a near/far history part,
+ * evaluated on Fourier grids (Sec. 3: spread -> FFT -> diagonal multiply ->
+ * inverse FFT -> interpolation).  All device work is hand-written HIP.
+ *
+ * Conventions common to every entry point
+ *  - Array arguments are DEVICE pointers (hipMalloc / PyTorch CUDA tensors)
+ *    unless a comment says "host".  Arrays are structure-of-arrays, float64
+ *    (the geometry sign array is int8).  Jets are row-major [k][n]: row k of
+ *    a jet array starts at element k*n.
+ *  - The library copies what it keeps; it never retains a caller pointer
+ *    after the call returns.  Outputs are written, not accumulated.
+ *  - Every call returns a vp_status and never aborts.  On error nothing is
+ *    written to outputs that the call did not already start writing, and
+ *    vp_last_error() returns a message for the calling thread.
+ *  - A plan is bound to the stream in its options; calls on one plan are not
+ *    re-entrant (they share the plan's device workspace) and must be
+ *    serialized by the caller.  Distinct plans may be used from different
+ *    threads.  vp_eval/vp_volume/vp_layer only enqueue work on that stream:
+ *    the output is ready once the stream is synchronized.
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vp_plan_s* vp_plan_t;
+
+typedef enum {
+    VP_OK = 0,
+    VP_ERR_ARG = 1,       /* invalid argument (NaN/inf, negative weight, bad sgn, n < 0, ...) */
+    VP_ERR_OOM = 2,       /* device or host allocation failed                                  */
+    VP_ERR_DEVICE = 3,    /* a HIP runtime call or kernel launch failed                        */
+    VP_ERR_GEOMETRY = 4,  /* inputs violate the method's geometric assumptions                 */
+    VP_ERR_TOL = 5,       /* tolerance cannot be met with the supported grid sizes             */
+    VP_ERR_BUSY = 6,      /* resource in use (server capacity)                                 */
+    VP_ERR_INTERNAL = 7
+} vp_status;
+
+typedef enum {
+    VP_FP32 = 0,  /* spread / FFT / interpolation in float32 with float32 accumulation;
+                     multiplier table built in float64, the zero-frequency (DC) term, the
+                     local part and the final sum in float64                             */
+    VP_FP64 = 1   /* everything in float64                                               */
+} vp_precision;
+
+enum { VP_KIND_V = 1, VP_KIND_S = 2, VP_KIND_D = 4 };
+
+typedef struct {
+    double tol;          /* target relative l_inf error of each result (default 1e-10)     */
+    int precision;       /* vp_precision (default VP_FP64)                                  */
+    double c_delta;      /* delta_1 = c_delta * dx^2, dx^2 = sum(w)/N (Sec. 6; default 3)  */
+    double delta_ratio;  /* delta_2 / delta_1 (Sec. 2.4 uses 32; default 32)               */
+    int order_v;         /* highest power of sqrt(delta) kept in V_L (default 4: delta^2)   */
+    int order_s;         /* ... in S_L (default 3: delta^{3/2})                             */
+    int order_d;         /* ... in D_L (default 3)                                          */
+    int kinds;           /* VP_KIND_* bitmask this plan must support (default V|S|D)        */
+    int fine_grid[2];    /* force fine-grid sizes F_NH, F_FH (0 = planner's choice)         */
+    int spread_width[2]; /* force spreading widths w_NH, w_FH in grid cells (0 = planner)   */
+    int tile;            /* tile edge in grid cells for spread/interp (0 = planner)         */
+    void* stream;        /* hipStream_t the plan's work is enqueued on (NULL = null stream) */
+} vp_opts;
+
+/* Fill opts with the defaults listed above. opts: host pointer. */
+void vp_opts_default(vp_opts* opts);
+
+/* Per-target local frame (Sec. 4): b = closest boundary point, r = |x - b|,
+ * (nx, ny) = outward unit normal at b, x = b - sgn*r*nu_b, sgn = +1 inside,
+ * 0 on the boundary, -1 outside; kappa = curvature at b (gamma''(0) in the
+ * tangent-line frame whose second axis is the inward normal: > 0 on convex
+ * arcs); gamma3, gamma4 = third and fourth derivatives of that local graph
+ * (may be NULL: taken as 0; needed only by delta^{3/2} and higher layer
+ * terms).  All arrays have n_tgt entries.  The closest-point computation is
+ * the caller's (the paper treats it as geometry preprocessing, Sec. 2.3). */
+typedef struct {
+    const double* r;
+    const double* nx;
+    const double* ny;
+    const double* kappa;
+    const double* gamma3;
+    const double* gamma4;
+    const int8_t* sgn;
+} vp_local_geom;
+
+/* Build a plan for fixed nodes (the inputs of the history algorithm, Sec. 3):
+ *   n_src volume quadrature nodes (src_x, src_y) with weights src_w >= 0
+ *     (zero weights -- degenerate triangles -- and coincident nodes are legal);
+ *   n_bnd boundary nodes (bnd_x, bnd_y) with outward unit normals
+ *     (bnd_nx, bnd_ny) and weights bnd_w >= 0 (may be 0 / NULL if no layer
+ *     potential is requested);
+ *   n_tgt targets (tgt_x, tgt_y) with their local frame geom.
+ * delta_1 = c_delta * sum(src_w)/n_src (or c_delta * mean(bnd_w)^2 without
+ * volume nodes), delta_2 = delta_ratio * delta_1.  The planner chooses the
+ * Fourier periods, mode counts, fine grids, spreading widths and tiles for
+ * opts->tol, sorts nodes and targets into tiles and builds the float64
+ * multiplier tables; it copies node data to the host for this (synchronizes
+ * the stream).  Targets within 12 sqrt(delta_1) of the boundary with sgn=-1
+ * are rejected (VP_ERR_GEOMETRY) if kinds includes V: the volume local
+ * expansion is stated for targets in the closed domain.
+ * out: host pointer receiving the plan.  opts: host pointer (NULL = defaults). */
+vp_status vp_plan(vp_plan_t* out,
+                  int64_t n_src, const double* src_x, const double* src_y, const double* src_w,
+                  int64_t n_bnd, const double* bnd_x, const double* bnd_y,
+                  const double* bnd_nx, const double* bnd_ny, const double* bnd_w,
+                  int64_t n_tgt, const double* tgt_x, const double* tgt_y,
+                  const vp_local_geom* geom, const vp_opts* opts);
+
+/* Evaluate V[f] + S[sigma] + D[mu] at the plan's targets (history part with
+ * one shared inverse FFT and interpolation per level, plus local parts; Secs.
+ * 3-4).  Any density may be NULL (omitted); its kind must be in the plan.
+ *   f_src      [n_src]     density at the volume nodes (the weights are the plan's)
+ *   jet6       [6][n_tgt]  f, f_x, f_y, f_xx, f_xy, f_yy at each target (global axes);
+ *                          required with f_src
+ *   sigma      [n_bnd]     single-layer density at the boundary nodes
+ *   sigma_jet3 [3][n_tgt]  sigma, sigma', sigma'' at each target's b, derivatives in
+ *                          the tangent-line parametrization (Sec. 4); required with sigma
+ *   mu         [n_bnd]     double-layer density at the boundary nodes
+ *   mu_jet5    [5][n_tgt]  mu, mu', mu'', mu''', mu'''' at b (same parametrization);
+ *                          required with mu
+ *   out        [n_tgt]     float64 result (sum of the requested potentials)
+ * Enqueues on the plan's stream and returns. */
+vp_status vp_eval(vp_plan_t plan, const double* f_src, const double* jet6,
+                  const double* sigma, const double* sigma_jet3,
+                  const double* mu, const double* mu_jet5, double* out);
+
+/* V[f] only: vp_eval(plan, f_src, jet6, NULL, NULL, NULL, NULL, out). */
+vp_status vp_volume(vp_plan_t plan, const double* f_src, const double* jet6, double* out);
+
+/* S[sigma] + D[mu] (either may be NULL): vp_eval without the volume density. */
+vp_status vp_layer(vp_plan_t plan, const double* sigma, const double* sigma_jet3,
+                   const double* mu, const double* mu_jet5, double* out);
+
+/* Release the plan and its device memory (synchronizes its stream). NULL is a no-op. */
+vp_status vp_destroy(vp_plan_t plan);
+
+/* Message for the last failing call on this thread ("" if none). Host string, owned
+ * by the library, valid until the next call on this thread. */
+const char* vp_last_error(void);
+
+/* Planned parameters, for reporting.  All fields host values. */
+typedef struct {
+    double delta1, delta2, eps_hist;
+    double period[2];     /* Fourier period P_NH, P_FH (history grids are P-periodic)        */
+    double kmax[2];       /* cutoff wavenumbers                                               */
+    double trunc_L;       /* far-history kernel truncation radius (Sec. 2.2, Vico truncation) */
+    int modes[2];         /* 2*M+1 Fourier modes per dimension, NH and FH                     */
+    int fine[2];          /* fine-grid sizes F_NH, F_FH                                       */
+    int width[2];         /* spreading widths                                                 */
+    int tile;             /* tile edge in grid cells                                          */
+    int precision;
+    int64_t n_src, n_bnd, n_tgt;
+    int64_t spread_records[2];  /* (node, tile) pairs per level                              */
+    size_t device_bytes;  /* device memory held by the plan                                   */
+} vp_plan_info;
+
+/* Fill info (host pointer) with the plan's parameters. */
+vp_status vp_get_plan_info(vp_plan_t plan, vp_plan_info* info);
+
+/* Per-stage device timing of the most recent vp_eval on this plan, measured with
+ * HIP events on the plan's stream (milliseconds, host array of 8):
+ * [0] strengths, [1] spread, [2] row FFT, [3] column FFT+multiply+inverse,
+ * [4] row inverse FFT, [5] interpolation, [6] local part + final sum, [7] total.
+ * Enabled by vp_set_timing(plan, 1); synchronizes the stream when read. */
+vp_status vp_set_timing(vp_plan_t plan, int enable);
+vp_status vp_get_timing(vp_plan_t plan, double* ms8);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VP_H */

@@ -1,0 +1,10 @@
+"""MI355X-native layer and volume potentials (heat-kernel split, Fourier history + local asymptotics).
+
+The computation lives in libvp.so (C ABI in include/vp.h, HIP kernels for
+gfx950); this package is its Python binding.
+"""
+from .binding import (VP_FP32, VP_FP64, VP_KIND_D, VP_KIND_S, VP_KIND_V, Plan, VPError,  # noqa: F401
+                      default_opts, lib)
+
+__all__ = ["Plan", "VPError", "VP_FP32", "VP_FP64", "VP_KIND_V", "VP_KIND_S", "VP_KIND_D", "lib",
+           "default_opts"]

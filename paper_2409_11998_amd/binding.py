@@ -1,0 +1,209 @@
+"""ctypes binding of libvp.so (include/vp.h): argument marshalling only.
+
+Device memory comes from PyTorch CUDA tensors (float64; int8 for sgn); every
+step of the computation runs in the library's HIP kernels.  There is no CPU
+fallback: without the built library or a HIP device the calls raise.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvp.so")
+
+VP_FP32, VP_FP64 = 0, 1
+VP_KIND_V, VP_KIND_S, VP_KIND_D = 1, 2, 4
+STATUS = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_OOM", 3: "VP_ERR_DEVICE", 4: "VP_ERR_GEOMETRY",
+          5: "VP_ERR_TOL", 6: "VP_ERR_BUSY", 7: "VP_ERR_INTERNAL"}
+
+EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "vp_destroy",
+            "vp_last_error", "vp_get_plan_info", "vp_set_timing", "vp_get_timing"]
+
+
+class VPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class VPOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("precision", ctypes.c_int), ("c_delta", ctypes.c_double),
+                ("delta_ratio", ctypes.c_double), ("order_v", ctypes.c_int), ("order_s", ctypes.c_int),
+                ("order_d", ctypes.c_int), ("kinds", ctypes.c_int), ("fine_grid", ctypes.c_int * 2),
+                ("spread_width", ctypes.c_int * 2), ("tile", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class VPLocalGeom(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_void_p), ("nx", ctypes.c_void_p), ("ny", ctypes.c_void_p),
+                ("kappa", ctypes.c_void_p), ("gamma3", ctypes.c_void_p), ("gamma4", ctypes.c_void_p),
+                ("sgn", ctypes.c_void_p)]
+
+
+class VPPlanInfo(ctypes.Structure):
+    _fields_ = [("delta1", ctypes.c_double), ("delta2", ctypes.c_double), ("eps_hist", ctypes.c_double),
+                ("period", ctypes.c_double * 2), ("kmax", ctypes.c_double * 2), ("trunc_L", ctypes.c_double),
+                ("modes", ctypes.c_int * 2), ("fine", ctypes.c_int * 2), ("width", ctypes.c_int * 2),
+                ("tile", ctypes.c_int), ("precision", ctypes.c_int), ("n_src", ctypes.c_int64),
+                ("n_bnd", ctypes.c_int64), ("n_tgt", ctypes.c_int64), ("spread_records", ctypes.c_int64 * 2),
+                ("device_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libvp.so is not built (run __graft_entry__.build() or "
+                               "python paper_2409_11998_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.vp_opts_default.argtypes = [ctypes.POINTER(VPOpts)]
+        L.vp_opts_default.restype = None
+        L.vp_plan.argtypes = [ctypes.POINTER(vp), i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, i64, vp, vp,
+                              ctypes.POINTER(VPLocalGeom), ctypes.POINTER(VPOpts)]
+        L.vp_plan.restype = ctypes.c_int
+        L.vp_eval.argtypes = [vp] * 8
+        L.vp_eval.restype = ctypes.c_int
+        L.vp_volume.argtypes = [vp] * 4
+        L.vp_volume.restype = ctypes.c_int
+        L.vp_layer.argtypes = [vp] * 6
+        L.vp_layer.restype = ctypes.c_int
+        L.vp_destroy.argtypes = [vp]
+        L.vp_destroy.restype = ctypes.c_int
+        L.vp_last_error.argtypes = []
+        L.vp_last_error.restype = ctypes.c_char_p
+        L.vp_get_plan_info.argtypes = [vp, ctypes.POINTER(VPPlanInfo)]
+        L.vp_get_plan_info.restype = ctypes.c_int
+        L.vp_set_timing.argtypes = [vp, ctypes.c_int]
+        L.vp_set_timing.restype = ctypes.c_int
+        L.vp_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.vp_get_timing.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise VPError(status, lib().vp_last_error().decode(errors="replace"))
+
+
+def default_opts():
+    o = VPOpts()
+    lib().vp_opts_default(ctypes.byref(o))
+    return o
+
+
+def _ptr(t, dtype=None):
+    """Device pointer of a CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device (CUDA/HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("expected dtype %s, got %s" % (dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan bound to fixed nodes and targets (vp_plan); see include/vp.h."""
+
+    def __init__(self, src_x, src_y, src_w, bnd_x=None, bnd_y=None, bnd_nx=None, bnd_ny=None, bnd_w=None,
+                 tgt_x=None, tgt_y=None, geom=None, tol=1e-10, precision=VP_FP64, kinds=7, stream=None,
+                 c_delta=3.0, delta_ratio=32.0, order_v=4, order_s=3, order_d=3, fine_grid=(0, 0),
+                 spread_width=(0, 0), tile=0):
+        import torch
+        f64 = torch.float64
+        o = default_opts()
+        o.tol = tol
+        o.precision = precision
+        o.c_delta = c_delta
+        o.delta_ratio = delta_ratio
+        o.order_v, o.order_s, o.order_d = order_v, order_s, order_d
+        o.kinds = kinds
+        o.fine_grid[0], o.fine_grid[1] = fine_grid
+        o.spread_width[0], o.spread_width[1] = spread_width
+        o.tile = tile
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        n_src = 0 if src_x is None else src_x.numel()
+        n_bnd = 0 if bnd_x is None else bnd_x.numel()
+        n_tgt = tgt_x.numel()
+        g = VPLocalGeom()
+        g.r = _ptr(geom["r"], f64)
+        g.nx = _ptr(geom["nx"], f64)
+        g.ny = _ptr(geom["ny"], f64)
+        g.kappa = _ptr(geom["kappa"], f64)
+        g.gamma3 = _ptr(geom.get("gamma3"), f64)
+        g.gamma4 = _ptr(geom.get("gamma4"), f64)
+        g.sgn = _ptr(geom["sgn"], torch.int8)
+        h = ctypes.c_void_p()
+        _check(lib().vp_plan(ctypes.byref(h), n_src, _ptr(src_x, f64), _ptr(src_y, f64), _ptr(src_w, f64),
+                             n_bnd, _ptr(bnd_x, f64), _ptr(bnd_y, f64), _ptr(bnd_nx, f64), _ptr(bnd_ny, f64),
+                             _ptr(bnd_w, f64), n_tgt, _ptr(tgt_x, f64), _ptr(tgt_y, f64), ctypes.byref(g),
+                             ctypes.byref(o)))
+        self.handle = h
+        self.n_src, self.n_bnd, self.n_tgt = n_src, n_bnd, n_tgt
+        self.device = tgt_x.device
+
+    def eval(self, f=None, jet6=None, sigma=None, sigma_jet=None, mu=None, mu_jet=None, out=None):
+        """V[f] + S[sigma] + D[mu] at the targets (vp_eval); returns out (float64)."""
+        import torch
+        f64 = torch.float64
+        if out is None:
+            out = torch.empty(self.n_tgt, dtype=f64, device=self.device)
+        _check(lib().vp_eval(self.handle, _ptr(f, f64), _ptr(jet6, f64), _ptr(sigma, f64), _ptr(sigma_jet, f64),
+                             _ptr(mu, f64), _ptr(mu_jet, f64), _ptr(out, f64)))
+        return out
+
+    def volume(self, f, jet6, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n_tgt, dtype=torch.float64, device=self.device)
+        _check(lib().vp_volume(self.handle, _ptr(f, torch.float64), _ptr(jet6, torch.float64),
+                               _ptr(out, torch.float64)))
+        return out
+
+    def layer(self, sigma=None, sigma_jet=None, mu=None, mu_jet=None, out=None):
+        import torch
+        f64 = torch.float64
+        if out is None:
+            out = torch.empty(self.n_tgt, dtype=f64, device=self.device)
+        _check(lib().vp_layer(self.handle, _ptr(sigma, f64), _ptr(sigma_jet, f64), _ptr(mu, f64),
+                              _ptr(mu_jet, f64), _ptr(out, f64)))
+        return out
+
+    def info(self):
+        i = VPPlanInfo()
+        _check(lib().vp_get_plan_info(self.handle, ctypes.byref(i)))
+        return dict(delta1=i.delta1, delta2=i.delta2, eps_hist=i.eps_hist, period=tuple(i.period),
+                    kmax=tuple(i.kmax), trunc_L=i.trunc_L, modes=tuple(i.modes), fine=tuple(i.fine),
+                    width=tuple(i.width), tile=i.tile, precision=i.precision, n_src=i.n_src, n_bnd=i.n_bnd,
+                    n_tgt=i.n_tgt, spread_records=tuple(i.spread_records), device_bytes=i.device_bytes)
+
+    def set_timing(self, on=True):
+        _check(lib().vp_set_timing(self.handle, 1 if on else 0))
+
+    def timing(self):
+        a = (ctypes.c_double * 8)()
+        _check(lib().vp_get_timing(self.handle, a))
+        names = ["strengths", "spread", "row_fft", "col_fft_mul", "row_ifft", "interp", "local", "total"]
+        return dict(zip(names, list(a)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().vp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,109 @@
+// Internal structures shared by the planner (vp_plan.hip) and the kernels
+// (vp_kernels.hip).  Not part of the public ABI (include/vp.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vp.h"
+
+namespace vp {
+
+constexpr int kWMax = 16;        // largest spreading width (grid cells per dimension)
+constexpr int kThreads = 256;    // threads per workgroup for grid kernels
+constexpr int kMaxChannels = 3;  // f*w + sigma*wG | mu*nu1*wG | mu*nu2*wG
+
+template <typename R> struct cplx { R x, y; };
+
+// One history level (near or far history, Sec. 3) as the kernels see it.
+struct LevelGeom {
+    int F;          // fine grid points per dimension (power of two)
+    int logF;
+    int M;          // retained Fourier modes: |m1|, |m2| <= M
+    int w;          // spreading width (grid cells)
+    int T;          // tile edge (grid cells); F % T == 0
+    int ntx;        // tiles per dimension
+    double beta;    // exponential-of-semicircle shape parameter
+    double h;       // grid spacing P / F
+    double x0, y0;  // coordinates of grid index 0
+    double period;  // P
+    double dk;      // 2 pi / P
+    double dc_coef; // (dk/2pi)^2 * multiplier(0): the zero mode's kernel weight
+};
+
+// Device buffers of one level.  R = float or double (plan precision).
+struct LevelBufs {
+    int* src_start = nullptr;  // [ntiles+1] CSR of (node, tile) spread records
+    int* src_ij = nullptr;     // packed absolute support corner i0 | j0 << 16
+    void* src_sx = nullptr;    // R: i0 - t_x + w/2, in [0, 1)
+    void* src_sy = nullptr;
+    int* src_idx = nullptr;    // node index (volume nodes first, then boundary nodes)
+    int* tgt_start = nullptr;  // [ntiles+1] CSR of targets by tile (each target once)
+    int* tgt_ij = nullptr;
+    void* tgt_sx = nullptr;
+    void* tgt_sy = nullptr;
+    int* tgt_idx = nullptr;
+    void* grid = nullptr;      // R [C][F][F] spread grids, reused for the inverse output
+    void* spec = nullptr;      // cplx<R> [C][M+1][F] (x-frequency major)
+    void* spec2 = nullptr;     // cplx<R> [M+1][F]
+    void* mult = nullptr;      // R [M+1][M+1] (dk/2pi)^2 M(k) / (phihat(m1) phihat(m2))^2
+    void* tw = nullptr;        // cplx<R> [F/2] twiddles exp(-2 pi i k / F)
+    void* hist = nullptr;      // R [n_tgt] history value at each target
+    int64_t n_src_rec = 0, n_tgt_rec = 0;
+};
+
+struct LocalParams {
+    double delta;       // delta_1
+    int order_v, order_s, order_d;
+};
+
+struct Plan {
+    vp_opts opts{};
+    int precision = VP_FP64;
+    int kinds = 0;
+    int64_t n_src = 0, n_bnd = 0, n_tgt = 0;
+    double delta1 = 0, delta2 = 0, eps = 0, L = 0;
+    LevelGeom lv[2]{};
+    LevelBufs lb[2]{};
+    LocalParams loc{};
+    hipStream_t stream = nullptr;
+    // node data in original order (device, float64)
+    double* d_w = nullptr;       // [n_src + n_bnd]: volume weights then boundary weights
+    double* d_nx = nullptr;      // [n_bnd] outward normal
+    double* d_ny = nullptr;
+    void* d_str = nullptr;       // R [3][n_src + n_bnd] strengths (channels)
+    double* d_dc = nullptr;      // [1] float64 sum of channel-0 strengths
+    // target geometry (device, float64 / int8)
+    double* g_r = nullptr;
+    double* g_nx = nullptr;
+    double* g_ny = nullptr;
+    double* g_kappa = nullptr;
+    double* g_g3 = nullptr;
+    double* g_g4 = nullptr;
+    int8_t* g_sgn = nullptr;
+    size_t device_bytes = 0;
+    std::vector<void*> allocs;
+    bool timing = false;
+    hipEvent_t ev[8]{};
+    bool ev_made = false;
+};
+
+// Kernel launchers (vp_kernels.hip).  All enqueue on p.stream.
+hipError_t launch_zero_dc(Plan& p);
+hipError_t launch_strengths(Plan& p, const double* f, const double* sigma, const double* mu, int C);
+hipError_t launch_spread(Plan& p, int level, int C);
+hipError_t launch_row_fft(Plan& p, int level, int C);
+hipError_t launch_col_fft(Plan& p, int level, int C);
+hipError_t launch_row_ifft(Plan& p, int level);
+hipError_t launch_interp(Plan& p, int level);
+hipError_t launch_local(Plan& p, const double* jet6, const double* sig_jet, const double* mu_jet,
+                        bool use_v, bool use_s, bool use_d, double* out);
+size_t row_fft_lds_bytes(const Plan& p, int level);
+size_t col_fft_lds_bytes(const Plan& p, int level);
+
+}  // namespace vp
+
+// The opaque handle of the C ABI is the plan itself.
+struct vp_plan_s : vp::Plan {};

@@ -1,0 +1,46 @@
+"""Move a Problem to device tensors and drive the library through its binding.
+
+Marshalling only (no arithmetic of the method): used by the GPU tests, the
+smoke check and the benchmark.
+"""
+import numpy as np
+
+
+def to_device(problem, device="cuda"):
+    import torch
+
+    def t(a, dtype=torch.float64):
+        if a is None:
+            return None
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+    g = problem.geom
+    d = dict(
+        src_x=t(problem.src_x) if problem.n_src else None,
+        src_y=t(problem.src_y) if problem.n_src else None,
+        src_w=t(problem.src_w) if problem.n_src else None,
+        bnd_x=t(problem.bnd_x) if problem.n_bnd else None,
+        bnd_y=t(problem.bnd_y) if problem.n_bnd else None,
+        bnd_nx=t(problem.bnd_nx) if problem.n_bnd else None,
+        bnd_ny=t(problem.bnd_ny) if problem.n_bnd else None,
+        bnd_w=t(problem.bnd_w) if problem.n_bnd else None,
+        tgt_x=t(problem.tgt_x), tgt_y=t(problem.tgt_y),
+        geom=dict(r=t(g["r"]), nx=t(g["nx"]), ny=t(g["ny"]), kappa=t(g["kappa"]), gamma3=t(g["gamma3"]),
+                  gamma4=t(g["gamma4"]), sgn=t(g["sgn"], torch.int8)),
+        f=t(problem.f_src), jet6=t(problem.jet6), sigma=t(problem.sigma), sigma_jet=t(problem.sigma_jet),
+        mu=t(problem.mu), mu_jet=t(problem.mu_jet))
+    return d
+
+
+def make_plan(dev, **opts):
+    from paper_2409_11998_amd import Plan
+    return Plan(dev["src_x"], dev["src_y"], dev["src_w"], dev["bnd_x"], dev["bnd_y"], dev["bnd_nx"],
+                dev["bnd_ny"], dev["bnd_w"], dev["tgt_x"], dev["tgt_y"], dev["geom"], **opts)
+
+
+def run(plan, dev, kinds="VSD", out=None):
+    return plan.eval(f=dev["f"] if "V" in kinds else None, jet6=dev["jet6"] if "V" in kinds else None,
+                     sigma=dev["sigma"] if "S" in kinds else None,
+                     sigma_jet=dev["sigma_jet"] if "S" in kinds else None,
+                     mu=dev["mu"] if "D" in kinds else None, mu_jet=dev["mu_jet"] if "D" in kinds else None,
+                     out=out)

@@ -120,8 +120,10 @@ def curve_mesh(curve, n_tri, seed, margin=0.5):
     Pi = hex_lattice(h, ((lo[0], hi[0]), (lo[1], hi[1])), rng)
     Pi = Pi[curve.inside(Pi)]
     dense = curve.point(curve.t_of_s(np.linspace(0, curve.length, 16 * nb, endpoint=False)))
-    dist, _ = cKDTree(dense).query(Pi)
-    Pi = Pi[dist > margin * h]
+    # only "closer than margin*h" matters; a bounded query avoids the degenerate
+    # all-equidistant search for points deep inside a circle
+    dist, _ = cKDTree(dense).query(Pi, distance_upper_bound=margin * h)
+    Pi = Pi[~np.isfinite(dist)]
     P = np.concatenate([Pb, Pi])
     tri = Delaunay(P).simplices
     cen = P[tri].mean(axis=1)

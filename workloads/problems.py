@@ -125,12 +125,17 @@ class StarCurve:
         rho = self.r * self.rho_series(np.mod(th, 2 * np.pi))[0]
         return np.hypot(dx, dy) < rho
 
-    def closest(self, p, iters=6):
-        """Parameter of the closest curve point (nearest dense sample + Newton)."""
+    def closest(self, p, near=np.inf, iters=6):
+        """Parameter of the closest curve point: nearest dense sample + Newton
+        for points within `near` of the curve; points farther away start Newton
+        from their polar angle (star-shaped curves), which lands on a stationary
+        point of the distance, whose distance is >= the true one."""
         n = 16 * 1024
         tt = np.linspace(0, 2 * np.pi, n, endpoint=False)
-        _, j = cKDTree(self.point(tt)).query(p)
-        t = tt[j]
+        d, j = cKDTree(self.point(tt)).query(p, distance_upper_bound=near)
+        th = np.mod(np.arctan2(p[:, 1] - self.y0, p[:, 0] - self.x0) / self.s, 2 * np.pi)
+        ok = np.isfinite(d)
+        t = np.where(ok, tt[np.minimum(j, n - 1)], th)
         for _ in range(iters):
             g = self.point(t) - p
             d1 = self.deriv(t, 1)
@@ -335,7 +340,10 @@ def star_problem(n_tri, seed, kinds="VSD", name="star", n_bnd=None, r=0.8):
     # target geometry: closest point for targets near the boundary; far ones get
     # the exact distance via the same Newton solve (cheap enough at these sizes)
     P = np.stack([x, y], 1)
-    t_b = curve.closest(P)
+    # exact closest points within 18 sqrt(delta_1) of the boundary (delta_1 = 3 sum(w)/N,
+    # the experiments' rule); beyond, only r > 12 sqrt(delta_1) matters to the local part
+    near = 18.0 * np.sqrt(3.0 * np.sum(w) / x.size)
+    t_b = curve.closest(P, near=near)
     fr, (sj, mj) = curve_frame_jets(curve, t_b, [sig_s, mu_s])
     rvec = np.hypot(x - fr["bx"], y - fr["by"])
     sgn = np.where(((x - fr["bx"]) * fr["nx"] + (y - fr["by"]) * fr["ny"]) < 0, 1, -1).astype(np.int8)

@@ -7,6 +7,7 @@ derive a fully symmetric 6-point rule made of two 3-point orbits
 equations for every symmetric polynomial up to degree four.  The solution is
 exact for all polynomials of total degree <= 4 (checked in the tests).
 """
+import warnings
 from functools import lru_cache
 from math import factorial
 
@@ -42,7 +43,9 @@ def _residual(p):
 @lru_cache(maxsize=1)
 def six_point_rule():
     """Return (bary[6,3], weights[6]) with weights summing to 1 (times area)."""
-    sol = fsolve(_residual, [0.45, 0.09, 0.22], xtol=1e-15)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        sol = fsolve(_residual, [0.45, 0.09, 0.22], xtol=1e-15)
     if max(abs(v) for v in _residual(sol)) > 1e-15:
         raise RuntimeError("moment equations did not converge")
     a, b, wa = sol
