@@ -12,6 +12,7 @@
 namespace vp {
 
 constexpr int kWMax = 16;        // largest spreading width (grid cells per dimension)
+constexpr int kWMin = 4;         // smallest spreading width
 constexpr int kThreads = 256;    // threads per workgroup for grid kernels
 constexpr int kMaxChannels = 3;  // f*w + sigma*wG | mu*nu1*wG | mu*nu2*wG
 
@@ -33,25 +34,43 @@ struct LevelGeom {
     double dc_coef; // (dk/2pi)^2 * multiplier(0): the zero mode's kernel weight
 };
 
+// A tile-sorted list of points of one level (CSR by tile).  For spreading a
+// point appears once per tile its w x w support meets; for interpolation each
+// target appears once, in the tile holding its support corner.
+struct RecList {
+    int* start = nullptr;  // [ntiles+1]
+    int* ij = nullptr;     // packed absolute support corner i0 | j0 << 16
+    void* dx = nullptr;    // R: i0 - t_x + w/2, in [0, 1)
+    void* dy = nullptr;
+    int* idx = nullptr;    // node index (volume nodes first, then boundary nodes) or target index
+    int64_t n = 0;
+};
+
+template <typename R> struct RecView {
+    const int* __restrict__ start;
+    const int* __restrict__ ij;
+    const R* __restrict__ dx;
+    const R* __restrict__ dy;
+    const int* __restrict__ idx;
+};
+
+template <typename R> inline RecView<R> view(const RecList& l)
+{
+    return RecView<R>{l.start, l.ij, (const R*)l.dx, (const R*)l.dy, l.idx};
+}
+
 // Device buffers of one level.  R = float or double (plan precision).
 struct LevelBufs {
-    int* src_start = nullptr;  // [ntiles+1] CSR of (node, tile) spread records
-    int* src_ij = nullptr;     // packed absolute support corner i0 | j0 << 16
-    void* src_sx = nullptr;    // R: i0 - t_x + w/2, in [0, 1)
-    void* src_sy = nullptr;
-    int* src_idx = nullptr;    // node index (volume nodes first, then boundary nodes)
-    int* tgt_start = nullptr;  // [ntiles+1] CSR of targets by tile (each target once)
-    int* tgt_ij = nullptr;
-    void* tgt_sx = nullptr;
-    void* tgt_sy = nullptr;
-    int* tgt_idx = nullptr;
+    RecList vol;               // volume nodes (spread)
+    RecList bnd;               // boundary nodes (spread)
+    RecList tgt;               // targets (interpolation)
     void* grid = nullptr;      // R [C][F][F] spread grids, reused for the inverse output
     void* spec = nullptr;      // cplx<R> [C][M+1][F] (x-frequency major)
     void* spec2 = nullptr;     // cplx<R> [M+1][F]
     void* mult = nullptr;      // R [M+1][M+1] (dk/2pi)^2 M(k) / (phihat(m1) phihat(m2))^2
     void* tw = nullptr;        // cplx<R> [F/2] twiddles exp(-2 pi i k / F)
     void* hist = nullptr;      // R [n_tgt] history value at each target
-    int64_t n_src_rec = 0, n_tgt_rec = 0;
+    double* horner = nullptr;  // [w][w+2] per-tap polynomial of the spreading kernel in u = 2d - 1
 };
 
 struct LocalParams {
@@ -93,7 +112,8 @@ struct Plan {
 // Kernel launchers (vp_kernels.hip).  All enqueue on p.stream.
 hipError_t launch_zero_dc(Plan& p);
 hipError_t launch_strengths(Plan& p, const double* f, const double* sigma, const double* mu, int C);
-hipError_t launch_spread(Plan& p, int level, int C);
+hipError_t launch_spread(Plan& p, int level, int C, bool use_vol, bool use_bnd);
+size_t spread_lds_bytes(const Plan& p, int level, int C, bool use_bnd);
 hipError_t launch_row_fft(Plan& p, int level, int C);
 hipError_t launch_col_fft(Plan& p, int level, int C);
 hipError_t launch_row_ifft(Plan& p, int level);

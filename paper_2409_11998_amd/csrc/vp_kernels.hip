@@ -25,21 +25,25 @@ namespace vp {
 
 namespace {
 
-// Exponential-of-semicircle spreading kernel exp(beta (sqrt(1 - z^2) - 1)) on
-// |z| < 1, written as exp(-beta z^2 / (1 + sqrt(1 - z^2))): the direct form
-// loses the exponent to cancellation near z = 0, where the kernel is largest.
-// Tap a of a node with fractional offset d in [0,1) sits at
-// z = ((2a - w) + 2d) / w.  Only 2w values are needed per node, so they are
-// always evaluated in float64 (the exponent reaches beta ~ 20-35, and its
-// float32 rounding would cost ~1e-7 relative per tap) and rounded once to the
-// working precision for the w^2 products and sums.
-template <typename R>
-__device__ __forceinline__ R es_tap(int a, int w, R d, double beta, double inv_w)
+// Spreading kernel values of one node at its w taps.  The kernel is the
+// exponential of semicircle exp(beta (sqrt(1 - z^2) - 1)), |z| < 1; tap a of a
+// node with offset d in [0, 1) sits at z = ((2a - w) + 2d) / w.  The planner
+// fits each tap as a polynomial of degree w+1 in u = 2d - 1 (Chebyshev
+// interpolation in float64, monomial form, error at the kernel's own e^-beta
+// level), so the values cost w(w+2) float64 FMAs with uniform (scalar-loaded)
+// coefficients instead of w exponentials, square roots and divisions.
+template <int W>
+__device__ __forceinline__ void kernel_taps(double d, const double* __restrict__ coef, double* out)
 {
-    const double z = ((double)(2 * a - w) + 2.0 * (double)d) * inv_w;
-    const double z2 = z * z;
-    const double q = 1.0 - z2;
-    return q > 0.0 ? (R)exp(-beta * z2 / (1.0 + sqrt(q))) : R(0);
+    constexpr int P = W + 2;
+    const double u = 2.0 * d - 1.0;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+        double acc = coef[a * P + P - 1];
+#pragma unroll
+        for (int k = P - 2; k >= 0; --k) acc = fma(acc, u, coef[a * P + k]);
+        out[a] = acc;
+    }
 }
 
 __device__ __forceinline__ int bitrev(int k, int logn)
@@ -122,67 +126,182 @@ __global__ void k_zero_dc(double* dc) { if (threadIdx.x == 0 && blockIdx.x == 0)
 
 // ---------------------------------------------------------------------------
 // Spread (type-1 spreading, Sec. 3 Step 2 via the NUFFT): one workgroup owns a
-// T x T tile of the fine grid, accumulates in LDS the contributions of every
-// node whose w x w support meets the tile, and writes the tile once (no
-// global atomics, no zero-fill pass).  A node's support starts at grid index
-// i0 = ceil(t - w/2); its offset is stored as d = i0 - t + w/2 in [0, 1).
-template <typename R, int C>
-__global__ __launch_bounds__(kThreads) void k_spread(LevelGeom g, const int* __restrict__ start,
-                                                     const int* __restrict__ ij, const R* __restrict__ sx,
-                                                     const R* __restrict__ sy, const int* __restrict__ idx,
-                                                     const R* __restrict__ str, int64_t nstr, R* __restrict__ grid)
+// T x T tile of the fine grid and writes it once (no global atomics, no
+// zero-fill pass).  A node's support starts at grid index i0 = ceil(t - w/2);
+// its offset is stored as d = i0 - t + w/2 in [0, 1).
+//
+// The tile accumulates in LDS with float64 atomic adds in both precisions:
+// on gfx950 a 64-lane ds_add_f32 costs ~190 cycles per CU against ~8.5 for
+// ds_add_f64 (measured), so float32 plans form their products in float32 and
+// round the tile to float32 once, when it is written to the grid.
+//
+// Single-channel records (volume nodes; boundary nodes when only sigma is
+// spread): each wavefront stages a chunk of its records in LDS (the next
+// chunk's loads are in flight meanwhile), computes their 2w kernel values
+// with one (record, value) pair per lane, then walks the records one at a
+// time with lanes mapped to taps: the 64 lanes of one no-return atomic touch
+// 64 distinct cells of a w x w patch.  Double-layer boundary records (three
+// strengths, few nodes) use one lane per record.
+template <typename R> struct SpreadShape {
+    static constexpr int kWaves = kThreads / 64;
+    static constexpr int kRecs = 32;            // records staged per wave chunk (2 lanes each)
+    static constexpr int kVals = 2 * kWMax;     // staged kernel values per record
+};
+
+// Dynamic LDS layout of k_spread (bytes): C padded float64 tiles | per-wave staging.
+__host__ __device__ inline size_t spread_lds_layout(int T, int C, size_t rb, int waves, int recs, int vals,
+                                                    size_t* off_stage)
 {
+    const size_t tiles = (size_t)C * T * (T + 1) * sizeof(double);
+    const size_t stage = (size_t)waves * recs * ((vals + 3) * rb + sizeof(int));
+    *off_stage = tiles;
+    return tiles + stage;
+}
+
+template <typename R, int W, int C>
+__global__ __launch_bounds__(kThreads) void k_spread(LevelGeom g, RecView<R> vol, RecView<R> bnd,
+                                                     const R* __restrict__ str, int64_t nstr, R* __restrict__ grid,
+                                                     int use_vol, int use_bnd, const double* __restrict__ coef)
+{
+    using SS = SpreadShape<R>;
+    constexpr int NW = SS::kWaves;
+    constexpr int RECS = SS::kRecs;
+    constexpr int VS = SS::kVals;
+    constexpr int WW = W * W;
+    constexpr int NTAP = (WW + 63) / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    R* tile = reinterpret_cast<R*>(smem_raw);
     const int T = g.T;
-    const int TT = T * T;
+    const int TP = T + 1;
+    const int TS = T * TP;
+    size_t off_st;
+    spread_lds_layout(T, C, sizeof(R), NW, RECS, VS, &off_st);
+    double* tile = reinterpret_cast<double*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    R* stage = reinterpret_cast<R*>(smem_raw + off_st);
+    R* vals = stage + (size_t)wv * RECS * (VS + 3);  // [RECS][VS] kernel values (x taps, then y taps)
+    R* my_s = vals + RECS * VS;                     // [RECS] strengths
+    R* my_d = my_s + RECS;                          // [RECS][2] offsets
+    int* my_ij = reinterpret_cast<int*>(stage + (size_t)NW * RECS * (VS + 3)) + wv * RECS;
+
     const int t = blockIdx.x;
     const int gx0 = (t % g.ntx) * T;
     const int gy0 = (t / g.ntx) * T;
-    for (int i = threadIdx.x; i < C * TT; i += blockDim.x) tile[i] = R(0);
+    for (int i = threadIdx.x; i < C * TS; i += blockDim.x) tile[i] = 0.0;
     __syncthreads();
-    const double beta = g.beta;
-    const double inv_w = 1.0 / g.w;
-    const int w = g.w;
-    const int r1 = start[t + 1];
-    for (int r = start[t] + threadIdx.x; r < r1; r += blockDim.x) {
-        const int p = ij[r];
-        const int i0 = (p & 0xffff) - gx0;
-        const int j0 = (p >> 16) - gy0;
-        const R ox = sx[r];
-        const R oy = sy[r];
-        const int k = idx[r];
-        R s[C];
+
+    // this lane's taps: tap = lane + 64 k, (a, b) = (tap % W, tap / W)
+    int ta[NTAP], tb[NTAP];
 #pragma unroll
-        for (int c = 0; c < C; ++c) s[c] = str[c * nstr + k];
-        R px[kWMax], py[kWMax];
-#pragma unroll
-        for (int a = 0; a < kWMax; ++a) {
-            px[a] = a < w ? es_tap(a, w, ox, beta, inv_w) : R(0);
-            py[a] = a < w ? es_tap(a, w, oy, beta, inv_w) : R(0);
+    for (int k = 0; k < NTAP; ++k) {
+        const int tap = lane + 64 * k;
+        tb[k] = tap / W;
+        ta[k] = tap - tb[k] * W;
+    }
+
+    auto wave_path = [&](const RecView<R>& L) {
+        const int r1 = L.start[t + 1];
+        int base = L.start[t] + wv * RECS;
+        int c_ij = 0, c_idx = 0;
+        R c_dx = R(0), c_dy = R(0);
+        if (lane < RECS && base + lane < r1) {
+            c_ij = L.ij[base + lane];
+            c_idx = L.idx[base + lane];
+            c_dx = L.dx[base + lane];
+            c_dy = L.dy[base + lane];
         }
+        R c_s = (lane < RECS && base + lane < r1) ? str[c_idx] : R(0);
+        for (; base < r1; base += NW * RECS) {
+            const int nrec = min(RECS, r1 - base);
+            if (lane < nrec) {
+                my_ij[lane] = c_ij;
+                my_s[lane] = c_s;
+                my_d[2 * lane] = c_dx;
+                my_d[2 * lane + 1] = c_dy;
+            }
+            const int nb = base + NW * RECS;
+            const bool pre = lane < RECS && nb + lane < r1;
+            if (pre) {
+                c_ij = L.ij[nb + lane];
+                c_idx = L.idx[nb + lane];
+                c_dx = L.dx[nb + lane];
+                c_dy = L.dy[nb + lane];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // kernel values: lane -> (record lane/2, axis lane%2), all W taps
+            if ((lane >> 1) < nrec) {
+                double pv[W];
+                kernel_taps<W>((double)my_d[lane], coef, pv);
+                R* dst = vals + (lane >> 1) * VS + (lane & 1) * W;
 #pragma unroll
-        for (int b = 0; b < kWMax; ++b) {
-            const int y = j0 + b;
-            if (b >= w || y < 0 || y >= T) continue;
+                for (int a = 0; a < W; ++a) dst[a] = (R)pv[a];
+            }
+            if (pre) c_s = str[c_idx];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int rr = 0; rr < nrec; ++rr) {
+                const int p = my_ij[rr];
+                const R sv = my_s[rr];
+                const int i0 = (p & 0xffff) - gx0;
+                const int j0 = (p >> 16) - gy0;
+                const R* v = vals + rr * VS;
 #pragma unroll
-            for (int a = 0; a < kWMax; ++a) {
-                const int x = i0 + a;
-                if (a >= w || x < 0 || x >= T) continue;
-                const R v = px[a] * py[b];
+                for (int k = 0; k < NTAP; ++k) {
+                    if (k + 1 < NTAP || lane + 64 * k < WW) {
+                        const int x = i0 + ta[k];
+                        const int y = j0 + tb[k];
+                        if ((unsigned)x < (unsigned)T && (unsigned)y < (unsigned)T)
+                            atomicAdd(&tile[y * TP + x], (double)(sv * v[ta[k]] * v[W + tb[k]]));
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    };
+
+    if (use_vol) wave_path(vol);
+    if (use_bnd && C == 1) wave_path(bnd);
+    if (use_bnd && C == 3) {
+        const int r1 = bnd.start[t + 1];
+        for (int r = bnd.start[t] + threadIdx.x; r < r1; r += blockDim.x) {
+            const int p = bnd.ij[r];
+            const int i0 = (p & 0xffff) - gx0;
+            const int j0 = (p >> 16) - gy0;
+            const int k = bnd.idx[r];
+            R sc[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) atomicAdd(&tile[c * TT + y * T + x], s[c] * v);
+            for (int c = 0; c < C; ++c) sc[c] = str[c * nstr + k];
+            double px[W], py[W];
+            kernel_taps<W>((double)bnd.dx[r], coef, px);
+            kernel_taps<W>((double)bnd.dy[r], coef, py);
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                const int y = j0 + b;
+                if (y < 0 || y >= T) continue;
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    const int x = i0 + a;
+                    if (x < 0 || x >= T) continue;
+                    const R v = (R)px[a] * (R)py[b];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) atomicAdd(&tile[c * TS + y * TP + x], (double)(sc[c] * v));
+                }
             }
         }
     }
     __syncthreads();
     const size_t F = g.F;
-    for (int i = threadIdx.x; i < C * TT; i += blockDim.x) {
-        const int c = i / TT;
-        const int l = i - c * TT;
+    for (int i = threadIdx.x; i < C * T * T; i += blockDim.x) {
+        const int c = i / (T * T);
+        const int l = i - c * T * T;
         const int y = l / T;
         const int x = l - y * T;
-        grid[(size_t)c * F * F + (size_t)(gy0 + y) * F + gx0 + x] = tile[i];
+        grid[(size_t)c * F * F + (size_t)(gy0 + y) * F + gx0 + x] = (R)tile[c * TS + y * TP + x];
     }
 }
 
@@ -319,17 +438,17 @@ __global__ __launch_bounds__(kThreads) void k_row_c2r(LevelGeom g, const cplx<R>
 // ---------------------------------------------------------------------------
 // Interpolation (type-2, Sec. 3 Step 4 via the NUFFT): one workgroup per tile
 // stages the (T+w-1)^2 grid window in LDS; each thread evaluates one target.
-template <typename R>
+template <typename R, int W>
 __global__ __launch_bounds__(kThreads) void k_interp(LevelGeom g, const R* __restrict__ grid,
                                                      const int* __restrict__ start, const int* __restrict__ ij,
                                                      const R* __restrict__ sx, const R* __restrict__ sy,
-                                                     const int* __restrict__ idx, R* __restrict__ hist)
+                                                     const int* __restrict__ idx, R* __restrict__ hist,
+                                                     const double* __restrict__ coef)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R* reg = reinterpret_cast<R*>(smem_raw);
     const int T = g.T;
-    const int w = g.w;
-    const int E = T + w - 1;
+    const int E = T + W - 1;
     const int F = g.F;
     const int t = blockIdx.x;
     const int r0 = start[t];
@@ -345,31 +464,21 @@ __global__ __launch_bounds__(kThreads) void k_interp(LevelGeom g, const R* __res
         reg[i] = (gx < F && gy < F) ? grid[(size_t)gy * F + gx] : R(0);
     }
     __syncthreads();
-    const double beta = g.beta;
-    const double inv_w = 1.0 / w;
     for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
         const int p = ij[r];
         const int i0 = (p & 0xffff) - gx0;
         const int j0 = (p >> 16) - gy0;
-        const R ox = sx[r];
-        const R oy = sy[r];
-        R px[kWMax], py[kWMax];
-#pragma unroll
-        for (int a = 0; a < kWMax; ++a) {
-            px[a] = a < w ? es_tap(a, w, ox, beta, inv_w) : R(0);
-            py[a] = a < w ? es_tap(a, w, oy, beta, inv_w) : R(0);
-        }
+        double px[W], py[W];
+        kernel_taps<W>((double)sx[r], coef, px);
+        kernel_taps<W>((double)sy[r], coef, py);
         R sum = R(0);
 #pragma unroll
-        for (int b = 0; b < kWMax; ++b) {
-            if (b < w) {
-                const R* rowp = reg + (j0 + b) * E + i0;
-                R acc = R(0);
+        for (int b = 0; b < W; ++b) {
+            const R* rowp = reg + (j0 + b) * E + i0;
+            R acc = R(0);
 #pragma unroll
-                for (int a = 0; a < kWMax; ++a)
-                    if (a < w) acc += px[a] * rowp[a];
-                sum += py[b] * acc;
-            }
+            for (int a = 0; a < W; ++a) acc += (R)px[a] * rowp[a];
+            sum += (R)py[b] * acc;
         }
         hist[idx[r]] = sum;
     }
@@ -537,26 +646,56 @@ hipError_t launch_strengths(Plan& p, const double* f, const double* sigma, const
     return hipGetLastError();
 }
 
-template <typename R>
-static hipError_t spread_t(Plan& p, int l, int C)
+size_t spread_lds_bytes(const Plan& p, int level, int C, bool use_bnd)
+{
+    (void)use_bnd;
+    size_t a;
+    if (p.precision == VP_FP32)
+        return spread_lds_layout(p.lv[level].T, C, sizeof(float), SpreadShape<float>::kWaves,
+                                 SpreadShape<float>::kRecs, SpreadShape<float>::kVals, &a);
+    return spread_lds_layout(p.lv[level].T, C, sizeof(double), SpreadShape<double>::kWaves,
+                             SpreadShape<double>::kRecs, SpreadShape<double>::kVals, &a);
+}
+
+#define VP_W_CASES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+template <typename R, int W, int C>
+static void spread_launch(Plan& p, int l, size_t lds, int uv, int ub)
 {
     const LevelGeom& g = p.lv[l];
     LevelBufs& b = p.lb[l];
     const unsigned ntiles = (unsigned)(g.ntx * g.ntx);
-    const size_t lds = (size_t)C * g.T * g.T * sizeof(R);
-    const int64_t nstr = p.n_src + p.n_bnd;
-    if (C == 1)
-        hipLaunchKernelGGL((k_spread<R, 1>), dim3(ntiles), dim3(kThreads), lds, p.stream, g, b.src_start, b.src_ij,
-                           (const R*)b.src_sx, (const R*)b.src_sy, b.src_idx, (const R*)p.d_str, nstr, (R*)b.grid);
-    else
-        hipLaunchKernelGGL((k_spread<R, 3>), dim3(ntiles), dim3(kThreads), lds, p.stream, g, b.src_start, b.src_ij,
-                           (const R*)b.src_sx, (const R*)b.src_sy, b.src_idx, (const R*)p.d_str, nstr, (R*)b.grid);
+    hipFuncSetAttribute((const void*)k_spread<R, W, C>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_spread<R, W, C>), dim3(ntiles), dim3(kThreads), lds, p.stream, g, view<R>(b.vol),
+                       view<R>(b.bnd), (const R*)p.d_str, p.n_src + p.n_bnd, (R*)b.grid, uv, ub,
+                       (const double*)b.horner);
+}
+
+template <typename R>
+static hipError_t spread_t(Plan& p, int l, int C, bool use_vol, bool use_bnd)
+{
+    LevelBufs& b = p.lb[l];
+    const size_t lds = spread_lds_bytes(p, l, C, use_bnd);
+    const int uv = use_vol && b.vol.start != nullptr;
+    const int ub = use_bnd && b.bnd.start != nullptr;
+    switch (p.lv[l].w) {
+#define VP_CASE(W)                                      \
+    case W:                                             \
+        if (C == 1) spread_launch<R, W, 1>(p, l, lds, uv, ub); \
+        else spread_launch<R, W, 3>(p, l, lds, uv, ub);        \
+        break;
+        VP_W_CASES(VP_CASE)
+#undef VP_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_spread(Plan& p, int level, int C)
+hipError_t launch_spread(Plan& p, int level, int C, bool use_vol, bool use_bnd)
 {
-    return p.precision == VP_FP32 ? spread_t<float>(p, level, C) : spread_t<double>(p, level, C);
+    return p.precision == VP_FP32 ? spread_t<float>(p, level, C, use_vol, use_bnd)
+                                  : spread_t<double>(p, level, C, use_vol, use_bnd);
 }
 
 template <typename R>
@@ -609,15 +748,31 @@ hipError_t launch_row_ifft(Plan& p, int level)
     return p.precision == VP_FP32 ? row_ifft_t<float>(p, level) : row_ifft_t<double>(p, level);
 }
 
-template <typename R>
-static hipError_t interp_t(Plan& p, int l)
+template <typename R, int W>
+static void interp_launch(Plan& p, int l)
 {
     const LevelGeom& g = p.lv[l];
     LevelBufs& b = p.lb[l];
-    const int E = g.T + g.w - 1;
+    const int E = g.T + W - 1;
     const size_t lds = (size_t)E * E * sizeof(R);
-    hipLaunchKernelGGL(k_interp<R>, dim3(g.ntx * g.ntx), dim3(kThreads), lds, p.stream, g, (const R*)b.grid,
-                       b.tgt_start, b.tgt_ij, (const R*)b.tgt_sx, (const R*)b.tgt_sy, b.tgt_idx, (R*)b.hist);
+    hipLaunchKernelGGL((k_interp<R, W>), dim3(g.ntx * g.ntx), dim3(kThreads), lds, p.stream, g, (const R*)b.grid,
+                       b.tgt.start, b.tgt.ij, (const R*)b.tgt.dx, (const R*)b.tgt.dy, b.tgt.idx, (R*)b.hist,
+                       (const double*)b.horner);
+}
+
+template <typename R>
+static hipError_t interp_t(Plan& p, int l)
+{
+    switch (p.lv[l].w) {
+#define VP_CASE(W)               \
+    case W:                      \
+        interp_launch<R, W>(p, l); \
+        break;
+        VP_W_CASES(VP_CASE)
+#undef VP_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

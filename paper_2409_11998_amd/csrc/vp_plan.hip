@@ -239,10 +239,9 @@ void free_plan(vp_plan_s* p)
 // touched tile, spread=false one record per point (tile of its support corner).
 template <typename R>
 vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std::vector<double>& y,
-                        const std::vector<int>& ids, bool spread)
+                        const std::vector<int>& ids, bool spread, RecList* list)
 {
     const LevelGeom& g = p.lv[l];
-    LevelBufs& b = p.lb[l];
     const int T = g.T, ntx = g.ntx, w = g.w;
     const int ntiles = ntx * ntx;
     const size_t n = ids.size();
@@ -297,22 +296,14 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
                 ridx[at] = ids[q];
             }
     }
+    RecList* L = list;
     vp_status s;
-    if (spread) {
-        if ((s = upload(p, &b.src_start, cnt, "spread tiles")) != VP_OK) return s;
-        if ((s = upload(p, &b.src_ij, rij, "spread ij")) != VP_OK) return s;
-        if ((s = upload(p, (R**)&b.src_sx, rsx, "spread sx")) != VP_OK) return s;
-        if ((s = upload(p, (R**)&b.src_sy, rsy, "spread sy")) != VP_OK) return s;
-        if ((s = upload(p, &b.src_idx, ridx, "spread idx")) != VP_OK) return s;
-        b.n_src_rec = nrec;
-    } else {
-        if ((s = upload(p, &b.tgt_start, cnt, "target tiles")) != VP_OK) return s;
-        if ((s = upload(p, &b.tgt_ij, rij, "target ij")) != VP_OK) return s;
-        if ((s = upload(p, (R**)&b.tgt_sx, rsx, "target sx")) != VP_OK) return s;
-        if ((s = upload(p, (R**)&b.tgt_sy, rsy, "target sy")) != VP_OK) return s;
-        if ((s = upload(p, &b.tgt_idx, ridx, "target idx")) != VP_OK) return s;
-        b.n_tgt_rec = nrec;
-    }
+    if ((s = upload(p, &L->start, cnt, "tile starts")) != VP_OK) return s;
+    if ((s = upload(p, &L->ij, rij, "records ij")) != VP_OK) return s;
+    if ((s = upload(p, (R**)&L->dx, rsx, "records dx")) != VP_OK) return s;
+    if ((s = upload(p, (R**)&L->dy, rsy, "records dy")) != VP_OK) return s;
+    if ((s = upload(p, &L->idx, ridx, "records idx")) != VP_OK) return s;
+    L->n = nrec;
     return VP_OK;
 }
 
@@ -333,6 +324,45 @@ vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, 
             mult[(size_t)a * (M + 1) + c] = (R)(scale * m / (ph * ph));
         }
     g.dc_coef = scale * ((l == 0) ? mult_nh(0.0, d1, d2) : mult_fh(0.0, d2, p.L));
+    // Spreading kernel per tap as a polynomial in the node offset: tap a of a
+    // node with offset d in [0,1) sits at z = ((2a - w) + (u + 1)) / w, u = 2d - 1.
+    // Chebyshev interpolation at w+2 points, converted to monomials in u.
+    {
+        const int W = g.w, P = W + 2;
+        std::vector<double> coef((size_t)W * P);
+        std::vector<double> cn(P), fv(P);
+        for (int j = 0; j < P; ++j) cn[j] = std::cos(M_PI * (j + 0.5) / P);
+        for (int a = 0; a < W; ++a) {
+            for (int j = 0; j < P; ++j) {
+                const double z = ((2.0 * a - W) + (cn[j] + 1.0)) / W;
+                const double q = 1.0 - z * z;
+                fv[j] = q > 0 ? std::exp(-g.beta * z * z / (1.0 + std::sqrt(q))) : 0.0;
+            }
+            // Chebyshev coefficients
+            std::vector<double> ch(P);
+            for (int k = 0; k < P; ++k) {
+                double sacc = 0.0;
+                for (int j = 0; j < P; ++j) sacc += fv[j] * std::cos(M_PI * k * (j + 0.5) / P);
+                ch[k] = (k == 0 ? 1.0 : 2.0) * sacc / P;
+            }
+            // monomial coefficients: T_k(u) via the recurrence on coefficient vectors
+            std::vector<double> mono(P, 0.0), tkm1(P, 0.0), tk(P, 0.0), tkp1(P, 0.0);
+            tkm1[0] = 1.0;                     // T_0
+            if (P > 1) tk[1] = 1.0;            // T_1
+            for (int i = 0; i < P; ++i) mono[i] += ch[0] * tkm1[i];
+            if (P > 1)
+                for (int i = 0; i < P; ++i) mono[i] += ch[1] * tk[i];
+            for (int k = 2; k < P; ++k) {
+                for (int i = 0; i < P; ++i) tkp1[i] = -tkm1[i] + ((i > 0) ? 2.0 * tk[i - 1] : 0.0);
+                for (int i = 0; i < P; ++i) mono[i] += ch[k] * tkp1[i];
+                tkm1.swap(tk);
+                tk.swap(tkp1);
+            }
+            for (int i = 0; i < P; ++i) coef[(size_t)a * P + i] = mono[i];
+        }
+        vp_status st2;
+        if ((st2 = upload(p, &b.horner, coef, "kernel polynomials")) != VP_OK) return st2;
+    }
     std::vector<cplx<R>> tw(g.F / 2);
     for (int k = 0; k < g.F / 2; ++k) {
         const double ang = -2.0 * M_PI * (double)k / g.F;
@@ -346,7 +376,7 @@ vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, 
 
 template <typename R>
 vp_status build_plan_t(Plan& p, const std::vector<double>& sxv, const std::vector<double>& syv,
-                       const std::vector<int>& spread_ids, const std::vector<double>& tx,
+                       const std::vector<int>& vol_ids, const std::vector<int>& bnd_ids, const std::vector<double>& tx,
                        const std::vector<double>& ty, const std::vector<std::vector<double>>& phihat)
 {
     vp_status s;
@@ -356,8 +386,9 @@ vp_status build_plan_t(Plan& p, const std::vector<double>& sxv, const std::vecto
     for (int l = 0; l < 2; ++l) {
         LevelGeom& g = p.lv[l];
         LevelBufs& b = p.lb[l];
-        if ((s = build_records<R>(p, l, sxv, syv, spread_ids, true)) != VP_OK) return s;
-        if ((s = build_records<R>(p, l, tx, ty, tids, false)) != VP_OK) return s;
+        if ((s = build_records<R>(p, l, sxv, syv, vol_ids, true, &b.vol)) != VP_OK) return s;
+        if ((s = build_records<R>(p, l, sxv, syv, bnd_ids, true, &b.bnd)) != VP_OK) return s;
+        if ((s = build_records<R>(p, l, tx, ty, tids, false, &b.tgt)) != VP_OK) return s;
         if ((s = build_level_tables<R>(p, l, phihat[l], p.delta1, p.delta2)) != VP_OK) return s;
         const size_t FF = (size_t)g.F * g.F;
         if ((s = dalloc_bytes(p, &b.grid, Cmax * FF * sizeof(R), "grid")) != VP_OK) return s;
@@ -570,6 +601,7 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
                 if (o.fine_grid[l] > 0 && F != o.fine_grid[l]) continue;
                 const double sigma = (double)F / (double)nmodes;
                 int w = o.spread_width[l] > 0 ? o.spread_width[l] : spread_width_for(eps_s, sigma);
+                w = std::max(w, kWMin);
                 if (w > kWMax) continue;
                 const double h = P / F;
                 // keep every support inside the grid without wrap-around
@@ -613,11 +645,11 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
     std::vector<double> ax(sx), ay(sy);
     ax.insert(ax.end(), bx.begin(), bx.end());
     ay.insert(ay.end(), by.begin(), by.end());
-    std::vector<int> ids;
+    std::vector<int> vol_ids, bnd_ids;
     if (o.kinds & VP_KIND_V)
-        for (int64_t i = 0; i < n_src; ++i) ids.push_back((int)i);
+        for (int64_t i = 0; i < n_src; ++i) vol_ids.push_back((int)i);
     if (need_b)
-        for (int64_t j = 0; j < p->n_bnd; ++j) ids.push_back((int)(n_src + j));
+        for (int64_t j = 0; j < p->n_bnd; ++j) bnd_ids.push_back((int)(n_src + j));
 
     // ---- device node data
     std::vector<double> wall(sw);
@@ -638,12 +670,14 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
         if (!g4.empty() && (s = upload(*p, &p->g_g4, g4, "geom")) != VP_OK) return bail(s);
         if ((s = upload(*p, &p->g_sgn, gs, "geom")) != VP_OK) return bail(s);
     }
-    s = (o.precision == VP_FP32) ? build_plan_t<float>(*p, ax, ay, ids, tx, ty, phihat)
-                                 : build_plan_t<double>(*p, ax, ay, ids, tx, ty, phihat);
+    s = (o.precision == VP_FP32) ? build_plan_t<float>(*p, ax, ay, vol_ids, bnd_ids, tx, ty, phihat)
+                                 : build_plan_t<double>(*p, ax, ay, vol_ids, bnd_ids, tx, ty, phihat);
     if (s != VP_OK) return bail(s);
     for (int l = 0; l < 2; ++l) {
         const size_t lds_row = row_fft_lds_bytes(*p, l), lds_col = col_fft_lds_bytes(*p, l);
-        if (lds_row > 160 * 1024 || lds_col > 160 * 1024) return bail(fail(VP_ERR_TOL, "FFT too long for LDS"));
+        const size_t lds_sp = spread_lds_bytes(*p, l, Cmax, need_b);
+        if (lds_row > 160 * 1024 || lds_col > 160 * 1024 || lds_sp > 160 * 1024)
+            return bail(fail(VP_ERR_TOL, "working set too large for LDS"));
     }
     *out = p;
     return VP_OK;
@@ -676,7 +710,7 @@ vp_status vp_eval(vp_plan_t p, const double* f, const double* jet6, const double
     VP_HIP(launch_zero_dc(*p), "zero dc");
     VP_HIP(launch_strengths(*p, f, sigma, mu, C), "strengths");
     VP_HIP(mark(1), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_spread(*p, l, C), "spread");
+    for (int l = 0; l < 2; ++l) VP_HIP(launch_spread(*p, l, C, use_v, use_s || use_d), "spread");
     VP_HIP(mark(2), "event");
     for (int l = 0; l < 2; ++l) VP_HIP(launch_row_fft(*p, l, C), "row fft");
     VP_HIP(mark(3), "event");
@@ -723,7 +757,7 @@ vp_status vp_get_plan_info(vp_plan_t p, vp_plan_info* info)
         info->modes[l] = 2 * p->lv[l].M + 1;
         info->fine[l] = p->lv[l].F;
         info->width[l] = p->lv[l].w;
-        info->spread_records[l] = p->lb[l].n_src_rec;
+        info->spread_records[l] = p->lb[l].vol.n + p->lb[l].bnd.n;
     }
     info->tile = p->lv[0].T;
     info->precision = p->precision;
