@@ -181,6 +181,46 @@ vp_status vp_get_plan_info(vp_plan_t plan, vp_plan_info* info);
 vp_status vp_set_timing(vp_plan_t plan, int enable);
 vp_status vp_get_timing(vp_plan_t plan, double* ms8);
 
+/* ------------------------------------------------------------------------
+ * Batched evaluation.  Plans of uneven size are executed together: one
+ * persistent kernel per stage (spreading and interpolation: one per history
+ * level) walks a device work table of (instance, level, tile/row/column)
+ * items, so every stage of every instance shares the whole GPU.  Not in the
+ * paper (which evaluates one problem on one core); it serves workloads made of
+ * many independent meshes and densities.
+ */
+typedef struct vp_batch_s* vp_batch_t;
+
+/* Per-instance arguments of one batched call (device pointers, as in vp_eval). */
+typedef struct {
+    const double* f_src;
+    const double* jet6;
+    const double* sigma;
+    const double* sigma_jet3;
+    const double* mu;
+    const double* mu_jet5;
+    double* out;
+} vp_eval_args;
+
+/* Group n plans (host array of handles; the plans must outlive the batch) for
+ * batched calls that always pass the densities in kinds (VP_KIND_* mask).
+ * All plans must share the precision and the spreading width of each level
+ * (fine grids may differ).  stream: hipStream_t for the batch (must not be the
+ * null stream if graphs are used).  Reads the plans' tile tables (synchronous). */
+vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int kinds, void* stream);
+
+/* Evaluate every instance: args is a host array of n entries.  use_graph != 0
+ * captures the stage sequence into a hipGraph on the first call and replays it
+ * afterwards (the per-call pointer table is copied to the device before each
+ * replay).  Enqueues on the batch stream and returns. */
+vp_status vp_batch_eval(vp_batch_t batch, const vp_eval_args* args, int use_graph);
+
+/* Release the batch (synchronizes its stream); the plans are not destroyed. */
+vp_status vp_batch_destroy(vp_batch_t batch);
+
+/* Message for the last failing batch call on this thread. */
+const char* vp_batch_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,8 @@ STATUS = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_OOM", 3: "VP_ERR_DEVICE", 4: "
           5: "VP_ERR_TOL", 6: "VP_ERR_BUSY", 7: "VP_ERR_INTERNAL"}
 
 EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "vp_destroy",
-            "vp_last_error", "vp_get_plan_info", "vp_set_timing", "vp_get_timing"]
+            "vp_last_error", "vp_get_plan_info", "vp_set_timing", "vp_get_timing",
+            "vp_batch_create", "vp_batch_eval", "vp_batch_destroy", "vp_batch_last_error"]
 
 
 class VPError(RuntimeError):
@@ -36,6 +37,12 @@ class VPLocalGeom(ctypes.Structure):
     _fields_ = [("r", ctypes.c_void_p), ("nx", ctypes.c_void_p), ("ny", ctypes.c_void_p),
                 ("kappa", ctypes.c_void_p), ("gamma3", ctypes.c_void_p), ("gamma4", ctypes.c_void_p),
                 ("sgn", ctypes.c_void_p)]
+
+
+class VPEvalArgs(ctypes.Structure):
+    _fields_ = [("f_src", ctypes.c_void_p), ("jet6", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("sigma_jet3", ctypes.c_void_p), ("mu", ctypes.c_void_p), ("mu_jet5", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
 
 
 class VPPlanInfo(ctypes.Structure):
@@ -81,6 +88,14 @@ def lib():
         L.vp_set_timing.restype = ctypes.c_int
         L.vp_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.vp_get_timing.restype = ctypes.c_int
+        L.vp_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int, vp]
+        L.vp_batch_create.restype = ctypes.c_int
+        L.vp_batch_eval.argtypes = [vp, ctypes.POINTER(VPEvalArgs), ctypes.c_int]
+        L.vp_batch_eval.restype = ctypes.c_int
+        L.vp_batch_destroy.argtypes = [vp]
+        L.vp_batch_destroy.restype = ctypes.c_int
+        L.vp_batch_last_error.argtypes = []
+        L.vp_batch_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -200,6 +215,55 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             lib().vp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bcheck(status):
+    if status != 0:
+        raise VPError(status, lib().vp_batch_last_error().decode(errors="replace"))
+
+
+class Batch:
+    """Plans executed together by one persistent kernel per stage (vp_batch_*)."""
+
+    def __init__(self, plans, kinds, stream=None):
+        import torch
+        self.plans = list(plans)  # keep the plans alive
+        if stream is None:
+            stream = torch.cuda.Stream()
+        self.stream = stream
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle for p in self.plans])
+        h = ctypes.c_void_p()
+        _bcheck(lib().vp_batch_create(ctypes.byref(h), len(self.plans), arr, kinds,
+                                      ctypes.c_void_p(stream.cuda_stream)))
+        self.handle = h
+        self.kinds = kinds
+
+    def eval(self, args, graph=True):
+        """args: list of dicts with tensors f, jet6, sigma, sigma_jet, mu, mu_jet, out (per instance)."""
+        import torch
+        f64 = torch.float64
+        n = len(self.plans)
+        a = (VPEvalArgs * n)()
+        for i, d in enumerate(args):
+            a[i].f_src = _ptr(d.get("f"), f64)
+            a[i].jet6 = _ptr(d.get("jet6"), f64)
+            a[i].sigma = _ptr(d.get("sigma"), f64)
+            a[i].sigma_jet3 = _ptr(d.get("sigma_jet"), f64)
+            a[i].mu = _ptr(d.get("mu"), f64)
+            a[i].mu_jet5 = _ptr(d.get("mu_jet"), f64)
+            a[i].out = _ptr(d["out"], f64)
+        _bcheck(lib().vp_batch_eval(self.handle, a, 1 if graph else 0))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().vp_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -597,11 +597,14 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
             const int nmodes = 2 * M + 1;
             int F0 = 64;
             while (F0 < (int)std::ceil(1.2 * nmodes)) F0 *= 2;
-            for (int F = F0; F <= std::min(4 * F0, Fmax); F *= 2) {
+            const int Flim = o.spread_width[l] > 0 ? Fmax : std::min(4 * F0, Fmax);
+            for (int F = F0; F <= Flim; F *= 2) {
                 if (o.fine_grid[l] > 0 && F != o.fine_grid[l]) continue;
                 const double sigma = (double)F / (double)nmodes;
-                int w = o.spread_width[l] > 0 ? o.spread_width[l] : spread_width_for(eps_s, sigma);
-                w = std::max(w, kWMin);
+                const int w_req = std::max(spread_width_for(eps_s, sigma), kWMin);
+                // a forced width is accepted only on grids fine enough for it to meet the tolerance
+                if (o.spread_width[l] > 0 && w_req > o.spread_width[l]) continue;
+                const int w = o.spread_width[l] > 0 ? o.spread_width[l] : w_req;
                 if (w > kWMax) continue;
                 const double h = P / F;
                 // keep every support inside the grid without wrap-around

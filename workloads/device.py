@@ -44,3 +44,19 @@ def run(plan, dev, kinds="VSD", out=None):
                      sigma_jet=dev["sigma_jet"] if "S" in kinds else None,
                      mu=dev["mu"] if "D" in kinds else None, mu_jet=dev["mu_jet"] if "D" in kinds else None,
                      out=out)
+
+
+def make_batch_plans(devs, **opts):
+    """Plans for a batch: one spreading width per level for all instances (the
+    largest the planner picks for any of them); each instance then gets the
+    smallest fine grid on which that width meets the tolerance."""
+    plans = [make_plan(d, **opts) for d in devs]
+    w = [max(p.info()["width"][l] for p in plans) for l in range(2)]
+    out = []
+    for p, d in zip(plans, devs):
+        if tuple(p.info()["width"]) == tuple(w):
+            out.append(p)
+        else:
+            p.close()
+            out.append(make_plan(d, spread_width=tuple(w), **opts))
+    return out
