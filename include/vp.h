@@ -76,6 +76,9 @@ typedef struct {
     int spread_width[2]; /* force spreading widths w_NH, w_FH in grid cells (0 = planner)   */
     int tile;            /* tile edge in grid cells for spread/interp (0 = planner)         */
     void* stream;        /* hipStream_t the plan's work is enqueued on (NULL = null stream) */
+    int no_workspace;    /* 1: keep only the plan's resident data (sorted nodes, tables, geometry);
+                            every evaluation then takes a stream-ordered workspace (grids,
+                            spectra, strengths) -- the form the serving loop uses (default 0) */
 } vp_opts;
 
 /* Fill opts with the defaults listed above. opts: host pointer. */
@@ -168,6 +171,8 @@ typedef struct {
     int64_t n_src, n_bnd, n_tgt;
     int64_t spread_records[2];  /* (node, tile) pairs per level                              */
     size_t device_bytes;  /* device memory held by the plan                                   */
+    size_t workspace_bytes; /* device memory one evaluation writes (the plan's own workspace, or
+                               the stream-ordered one of a plan created with no_workspace)     */
 } vp_plan_info;
 
 /* Fill info (host pointer) with the plan's parameters. */
@@ -220,6 +225,64 @@ vp_status vp_batch_destroy(vp_batch_t batch);
 
 /* Message for the last failing batch call on this thread. */
 const char* vp_batch_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Serving loop (continuous admission).  A host worker thread keeps a FIFO of
+ * submitted requests and starts any of them as soon as an in-flight slot and
+ * enough HBM are free, on one of n_streams streams, so requests arriving
+ * while others run start without waiting for a batch boundary and their
+ * kernels overlap on the device.  Plans stay resident; each running request
+ * holds a stream-ordered workspace (grids, spectra, strengths) whose size is
+ * its HBM footprint, and the in-flight footprints never exceed the budget.
+ * Not in the paper; it serves streams of independent evaluations.
+ */
+typedef struct vp_server_s* vp_server_t;
+
+typedef struct {
+    size_t hbm_budget_bytes;  /* cap on the summed workspace of in-flight requests           */
+    int max_in_flight;        /* cap on concurrently running requests                        */
+    int n_streams;            /* streams requests are spread over (1..16)                    */
+} vp_server_opts;
+
+/* One request: a plan (resident; create it with opts.no_workspace = 1 so it holds no
+ * workspace of its own) and the densities/output of vp_eval (device pointers, ready --
+ * their producing stream synchronized -- when submitted; they must stay valid and the
+ * output untouched until the request completes). */
+typedef struct {
+    vp_plan_t plan;
+    const double* f_src;
+    const double* jet6;
+    const double* sigma;
+    const double* sigma_jet3;
+    const double* mu;
+    const double* mu_jet5;
+    double* out;
+} vp_request;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, failed, deferred;  /* deferred: requests that waited for room */
+    size_t peak_bytes;        /* largest in-flight workspace total                             */
+    int peak_in_flight;       /* largest number of concurrently running requests              */
+    double p50_s, p99_s, max_s, mean_s;  /* latency: submission -> completion observed        */
+    double span_s;            /* first submission -> last completion                           */
+    double targets_per_s;     /* completed target points / span_s                              */
+} vp_server_stats;
+
+/* Start a server on the current device (opts: host pointer). */
+vp_status vp_server_create(vp_server_t* out, const vp_server_opts* opts);
+/* Queue a request (host struct); returns at once with a ticket (host pointer). */
+vp_status vp_server_submit(vp_server_t srv, const vp_request* req, uint64_t* ticket);
+/* done = 1 once the request finished; then result is its status (VP_ERR_OOM if it
+ * exceeds the whole budget) and latency_s its latency.  result/latency_s may be NULL. */
+vp_status vp_server_poll(vp_server_t srv, uint64_t ticket, int* done, vp_status* result, double* latency_s);
+/* Block until the request finished or timeout_s passed (VP_ERR_BUSY on timeout). */
+vp_status vp_server_wait(vp_server_t srv, uint64_t ticket, double timeout_s, vp_status* result, double* latency_s);
+/* Counters and latency percentiles over all completed requests (stats: host pointer). */
+vp_status vp_server_get_stats(vp_server_t srv, vp_server_stats* stats);
+/* Finish queued and running requests, then stop the worker and free the server. */
+vp_status vp_server_destroy(vp_server_t srv);
+/* Message for the last failing server call on this thread. */
+const char* vp_server_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -12,12 +12,16 @@ LIB_PATH = os.path.join(HERE, "libvp.so")
 
 VP_FP32, VP_FP64 = 0, 1
 VP_KIND_V, VP_KIND_S, VP_KIND_D = 1, 2, 4
+(VP_OK, VP_ERR_ARG, VP_ERR_OOM, VP_ERR_DEVICE, VP_ERR_GEOMETRY, VP_ERR_TOL, VP_ERR_BUSY,
+ VP_ERR_INTERNAL) = range(8)
 STATUS = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_OOM", 3: "VP_ERR_DEVICE", 4: "VP_ERR_GEOMETRY",
           5: "VP_ERR_TOL", 6: "VP_ERR_BUSY", 7: "VP_ERR_INTERNAL"}
 
 EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "vp_destroy",
             "vp_last_error", "vp_get_plan_info", "vp_set_timing", "vp_get_timing",
-            "vp_batch_create", "vp_batch_eval", "vp_batch_destroy", "vp_batch_last_error"]
+            "vp_batch_create", "vp_batch_eval", "vp_batch_destroy", "vp_batch_last_error",
+            "vp_server_create", "vp_server_submit", "vp_server_poll", "vp_server_wait", "vp_server_get_stats",
+            "vp_server_destroy", "vp_server_last_error"]
 
 
 class VPError(RuntimeError):
@@ -30,7 +34,8 @@ class VPOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("precision", ctypes.c_int), ("c_delta", ctypes.c_double),
                 ("delta_ratio", ctypes.c_double), ("order_v", ctypes.c_int), ("order_s", ctypes.c_int),
                 ("order_d", ctypes.c_int), ("kinds", ctypes.c_int), ("fine_grid", ctypes.c_int * 2),
-                ("spread_width", ctypes.c_int * 2), ("tile", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("spread_width", ctypes.c_int * 2), ("tile", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("no_workspace", ctypes.c_int)]
 
 
 class VPLocalGeom(ctypes.Structure):
@@ -45,13 +50,31 @@ class VPEvalArgs(ctypes.Structure):
                 ("out", ctypes.c_void_p)]
 
 
+class VPServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_in_flight", ctypes.c_int), ("n_streams", ctypes.c_int)]
+
+
+class VPRequest(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("f_src", ctypes.c_void_p), ("jet6", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p), ("sigma_jet3", ctypes.c_void_p), ("mu", ctypes.c_void_p),
+                ("mu_jet5", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class VPServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("deferred", ctypes.c_uint64), ("peak_bytes", ctypes.c_size_t),
+                ("peak_in_flight", ctypes.c_int), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
+                ("max_s", ctypes.c_double), ("mean_s", ctypes.c_double), ("span_s", ctypes.c_double),
+                ("targets_per_s", ctypes.c_double)]
+
+
 class VPPlanInfo(ctypes.Structure):
     _fields_ = [("delta1", ctypes.c_double), ("delta2", ctypes.c_double), ("eps_hist", ctypes.c_double),
                 ("period", ctypes.c_double * 2), ("kmax", ctypes.c_double * 2), ("trunc_L", ctypes.c_double),
                 ("modes", ctypes.c_int * 2), ("fine", ctypes.c_int * 2), ("width", ctypes.c_int * 2),
                 ("tile", ctypes.c_int), ("precision", ctypes.c_int), ("n_src", ctypes.c_int64),
                 ("n_bnd", ctypes.c_int64), ("n_tgt", ctypes.c_int64), ("spread_records", ctypes.c_int64 * 2),
-                ("device_bytes", ctypes.c_size_t)]
+                ("device_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -96,6 +119,22 @@ def lib():
         L.vp_batch_destroy.restype = ctypes.c_int
         L.vp_batch_last_error.argtypes = []
         L.vp_batch_last_error.restype = ctypes.c_char_p
+        L.vp_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(VPServerOpts)]
+        L.vp_server_create.restype = ctypes.c_int
+        L.vp_server_submit.argtypes = [vp, ctypes.POINTER(VPRequest), ctypes.POINTER(ctypes.c_uint64)]
+        L.vp_server_submit.restype = ctypes.c_int
+        L.vp_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.vp_server_poll.restype = ctypes.c_int
+        L.vp_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.vp_server_wait.restype = ctypes.c_int
+        L.vp_server_get_stats.argtypes = [vp, ctypes.POINTER(VPServerStats)]
+        L.vp_server_get_stats.restype = ctypes.c_int
+        L.vp_server_destroy.argtypes = [vp]
+        L.vp_server_destroy.restype = ctypes.c_int
+        L.vp_server_last_error.argtypes = []
+        L.vp_server_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -131,7 +170,7 @@ class Plan:
     def __init__(self, src_x, src_y, src_w, bnd_x=None, bnd_y=None, bnd_nx=None, bnd_ny=None, bnd_w=None,
                  tgt_x=None, tgt_y=None, geom=None, tol=1e-10, precision=VP_FP64, kinds=7, stream=None,
                  c_delta=3.0, delta_ratio=32.0, order_v=4, order_s=3, order_d=3, fine_grid=(0, 0),
-                 spread_width=(0, 0), tile=0):
+                 spread_width=(0, 0), tile=0, no_workspace=False):
         import torch
         f64 = torch.float64
         o = default_opts()
@@ -144,6 +183,7 @@ class Plan:
         o.fine_grid[0], o.fine_grid[1] = fine_grid
         o.spread_width[0], o.spread_width[1] = spread_width
         o.tile = tile
+        o.no_workspace = 1 if no_workspace else 0
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -201,7 +241,8 @@ class Plan:
         return dict(delta1=i.delta1, delta2=i.delta2, eps_hist=i.eps_hist, period=tuple(i.period),
                     kmax=tuple(i.kmax), trunc_L=i.trunc_L, modes=tuple(i.modes), fine=tuple(i.fine),
                     width=tuple(i.width), tile=i.tile, precision=i.precision, n_src=i.n_src, n_bnd=i.n_bnd,
-                    n_tgt=i.n_tgt, spread_records=tuple(i.spread_records), device_bytes=i.device_bytes)
+                    n_tgt=i.n_tgt, spread_records=tuple(i.spread_records), device_bytes=i.device_bytes,
+                    workspace_bytes=i.workspace_bytes)
 
     def set_timing(self, on=True):
         _check(lib().vp_set_timing(self.handle, 1 if on else 0))
@@ -264,6 +305,63 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             lib().vp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _scheck(status):
+    if status != 0:
+        raise VPError(status, lib().vp_server_last_error().decode(errors="replace"))
+
+
+class Server:
+    """Continuous-admission serving loop (vp_server_*); requests name resident plans."""
+
+    def __init__(self, hbm_budget_bytes, max_in_flight=8, n_streams=4):
+        o = VPServerOpts(int(hbm_budget_bytes), int(max_in_flight), int(n_streams))
+        h = ctypes.c_void_p()
+        _scheck(lib().vp_server_create(ctypes.byref(h), ctypes.byref(o)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, plan, out, f=None, jet6=None, sigma=None, sigma_jet=None, mu=None, mu_jet=None):
+        """Queue one evaluation (inputs must be ready on the device); returns a ticket."""
+        import torch
+        f64 = torch.float64
+        r = VPRequest(plan.handle, _ptr(f, f64), _ptr(jet6, f64), _ptr(sigma, f64), _ptr(sigma_jet, f64),
+                      _ptr(mu, f64), _ptr(mu_jet, f64), _ptr(out, f64))
+        t = ctypes.c_uint64()
+        _scheck(lib().vp_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = (plan, out, f, jet6, sigma, sigma_jet, mu, mu_jet)
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int()
+        st = ctypes.c_int()
+        lat = ctypes.c_double()
+        _scheck(lib().vp_server_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(lat)))
+        return (bool(done.value), st.value, lat.value) if done.value else (False, None, None)
+
+    def wait(self, ticket, timeout=60.0):
+        st = ctypes.c_int()
+        lat = ctypes.c_double()
+        _scheck(lib().vp_server_wait(self.handle, ticket, float(timeout), ctypes.byref(st), ctypes.byref(lat)))
+        self._keep.pop(ticket, None)
+        return st.value, lat.value
+
+    def stats(self):
+        s = VPServerStats()
+        _scheck(lib().vp_server_get_stats(self.handle, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in VPServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().vp_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -357,6 +357,8 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
             b->w[1] = p.lv[1].w;
         }
         if (p.precision != b->precision) return bail(bfail(VP_ERR_ARG, "plans differ in precision"));
+        if (!p.ws.block) return bail(bfail(VP_ERR_ARG, "batched plans need their own workspace"));
+        if (b->C > p.cmax) return bail(bfail(VP_ERR_ARG, "a plan's workspace lacks the double-layer channels"));
         if (p.lv[0].w != b->w[0] || p.lv[1].w != b->w[1])
             return bail(bfail(VP_ERR_ARG, "plans differ in spreading width (use one width per level per batch)"));
         if ((kinds & VP_KIND_V) && !(p.kinds & VP_KIND_V)) return bail(bfail(VP_ERR_ARG, "a plan lacks V"));
@@ -386,8 +388,8 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
         I.w = p.d_w;
         I.nx = p.d_nx;
         I.ny = p.d_ny;
-        I.dc = p.d_dc;
-        I.str = p.d_str;
+        I.dc = p.ws.dc;
+        I.str = p.ws.str;
         I.has_vol = p.lb[0].vol.start != nullptr;
         I.has_bnd = p.lb[0].bnd.start != nullptr;
         dev::LocalArgs& a = I.loc;
@@ -404,11 +406,11 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
         a.g3 = p.g_g3;
         a.g4 = p.g_g4;
         a.sgn = p.g_sgn;
-        a.h0 = p.lb[0].hist;
-        a.h1 = p.lb[1].hist;
+        a.h0 = p.ws.hist[0];
+        a.h1 = p.ws.hist[1];
         a.fp32 = fp32;
         a.dc_weight = p.lv[0].dc_coef + p.lv[1].dc_coef;
-        a.dc = fp32 ? p.d_dc : nullptr;
+        a.dc = fp32 ? p.ws.dc : nullptr;
         const int64_t nn = p.n_src + p.n_bnd;
         for (int64_t u = 0; u * (int64_t)dev::kStrChunk < nn; ++u) {
             st[ST_STR].push_back({i, 0, (int)u});
@@ -429,12 +431,12 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
             D.bnd_idx = lb.bnd.idx;
             D.tgt_start = lb.tgt.start; D.tgt_ij = lb.tgt.ij; D.tgt_dx = lb.tgt.dx; D.tgt_dy = lb.tgt.dy;
             D.tgt_idx = lb.tgt.idx;
-            D.grid = lb.grid;
-            D.spec = lb.spec;
-            D.spec2 = lb.spec2;
+            D.grid = p.ws.grid[l];
+            D.spec = p.ws.spec[l];
+            D.spec2 = p.ws.spec2[l];
             D.mult = lb.mult;
             D.tw = lb.tw;
-            D.hist = lb.hist;
+            D.hist = p.ws.hist[l];
             D.horner = lb.horner;
             // tile record counts for cost-sorted spreading items
             const int ntiles = g.ntx * g.ntx;

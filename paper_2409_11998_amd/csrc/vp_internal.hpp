@@ -64,13 +64,23 @@ struct LevelBufs {
     RecList vol;               // volume nodes (spread)
     RecList bnd;               // boundary nodes (spread)
     RecList tgt;               // targets (interpolation)
-    void* grid = nullptr;      // R [C][F][F] spread grids, reused for the inverse output
-    void* spec = nullptr;      // cplx<R> [C][M+1][F] (x-frequency major)
-    void* spec2 = nullptr;     // cplx<R> [M+1][F]
     void* mult = nullptr;      // R [M+1][M+1] (dk/2pi)^2 M(k) / (phihat(m1) phihat(m2))^2
     void* tw = nullptr;        // cplx<R> [F/2] twiddles exp(-2 pi i k / F)
-    void* hist = nullptr;      // R [n_tgt] history value at each target
     double* horner = nullptr;  // [w][w+2] per-tap polynomial of the spreading kernel in u = 2d - 1
+};
+
+// Per-evaluation device memory (everything an evaluation writes).  A plan may
+// own one; the serving loop gives every in-flight request its own, so
+// requests on one plan can overlap.
+struct Workspace {
+    void* grid[2] = {nullptr, nullptr};   // R [C][F][F] spread grids, reused for the inverse output
+    void* spec[2] = {nullptr, nullptr};   // cplx<R> [C][M+1][F] (x-frequency major)
+    void* spec2[2] = {nullptr, nullptr};  // cplx<R> [M+1][F]
+    void* hist[2] = {nullptr, nullptr};   // R [n_tgt] history value at each target
+    void* str = nullptr;                  // R [C][n_src + n_bnd] strengths
+    double* dc = nullptr;                 // [1] float64 sum of channel-0 strengths
+    void* block = nullptr;                // single allocation holding all of the above
+    size_t bytes = 0;
 };
 
 struct LocalParams {
@@ -92,8 +102,8 @@ struct Plan {
     double* d_w = nullptr;       // [n_src + n_bnd]: volume weights then boundary weights
     double* d_nx = nullptr;      // [n_bnd] outward normal
     double* d_ny = nullptr;
-    void* d_str = nullptr;       // R [3][n_src + n_bnd] strengths (channels)
-    double* d_dc = nullptr;      // [1] float64 sum of channel-0 strengths
+    Workspace ws;                // the plan's own workspace (absent with opts.no_workspace)
+    int cmax = 1;                // channels the workspace holds (3 with the double layer)
     // target geometry (device, float64 / int8)
     double* g_r = nullptr;
     double* g_nx = nullptr;
@@ -109,19 +119,33 @@ struct Plan {
     bool ev_made = false;
 };
 
-// Kernel launchers (vp_kernels.hip).  All enqueue on p.stream.
-hipError_t launch_zero_dc(Plan& p);
-hipError_t launch_strengths(Plan& p, const double* f, const double* sigma, const double* mu, int C);
-hipError_t launch_spread(Plan& p, int level, int C, bool use_vol, bool use_bnd);
-size_t spread_lds_bytes(const Plan& p, int level, int C, bool use_bnd);
-hipError_t launch_row_fft(Plan& p, int level, int C);
-hipError_t launch_col_fft(Plan& p, int level, int C);
-hipError_t launch_row_ifft(Plan& p, int level);
-hipError_t launch_interp(Plan& p, int level);
-hipError_t launch_local(Plan& p, const double* jet6, const double* sig_jet, const double* mu_jet,
-                        bool use_v, bool use_s, bool use_d, double* out);
+// Kernel launchers (vp_kernels.hip).  All enqueue on stream st and write into ws.
+hipError_t launch_zero_dc(const Plan& p, const Workspace& ws, hipStream_t st);
+hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* sigma,
+                            const double* mu, int C);
+hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C, bool use_vol,
+                         bool use_bnd);
+hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C);
+hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C);
+hipError_t launch_row_ifft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
+hipError_t launch_interp(const Plan& p, const Workspace& ws, hipStream_t st, int level);
+hipError_t launch_local(const Plan& p, const Workspace& ws, hipStream_t st, const double* jet6, const double* sig_jet,
+                        const double* mu_jet, bool use_v, bool use_s, bool use_d, double* out);
 size_t row_fft_lds_bytes(const Plan& p, int level);
 size_t col_fft_lds_bytes(const Plan& p, int level);
+size_t spread_lds_bytes(const Plan& p, int level, int C, bool use_bnd);
+
+// Workspace layout / allocation (vp_plan.hip).  async: stream-ordered
+// (hipMallocAsync/hipFreeAsync on st), else plain hipMalloc/hipFree.
+size_t workspace_bytes(const Plan& p);
+hipError_t workspace_alloc(const Plan& p, Workspace& ws, hipStream_t st, bool async);
+hipError_t workspace_free(Workspace& ws, hipStream_t st, bool async);
+// Validate densities against the plan and enqueue one evaluation on st into ws.
+vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* jet6,
+                       const double* sigma, const double* sigma_jet3, const double* mu, const double* mu_jet5,
+                       double* out, bool timing);
+// Thread-local error message shared by the C ABI entry points.
+vp_status set_error(vp_status s, const std::string& msg);
 
 }  // namespace vp
 

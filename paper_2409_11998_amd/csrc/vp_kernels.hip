@@ -97,22 +97,24 @@ size_t col_fft_lds_bytes(const Plan& p, int level)
     return (size_t)p.lv[level].F * cb;
 }
 
-hipError_t launch_zero_dc(Plan& p)
+hipError_t launch_zero_dc(const Plan& p, const Workspace& ws, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_zero_dc, dim3(1), dim3(64), 0, p.stream, p.d_dc);
+    (void)p;
+    hipLaunchKernelGGL(k_zero_dc, dim3(1), dim3(64), 0, st, ws.dc);
     return hipGetLastError();
 }
 
-hipError_t launch_strengths(Plan& p, const double* f, const double* sigma, const double* mu, int C)
+hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* sigma,
+                            const double* mu, int C)
 {
     const int64_t n = p.n_src + p.n_bnd;
     const unsigned blocks = grid_for(n, kStrChunk);
     if (p.precision == VP_FP32)
-        hipLaunchKernelGGL(k_strengths<float>, dim3(blocks), dim3(kThreads), 0, p.stream, p.n_src, p.n_bnd, f, sigma,
-                           mu, p.d_w, p.d_nx, p.d_ny, (float*)p.d_str, C, p.d_dc);
+        hipLaunchKernelGGL(k_strengths<float>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
+                           p.d_w, p.d_nx, p.d_ny, (float*)ws.str, C, ws.dc);
     else
-        hipLaunchKernelGGL(k_strengths<double>, dim3(blocks), dim3(kThreads), 0, p.stream, p.n_src, p.n_bnd, f, sigma,
-                           mu, p.d_w, p.d_nx, p.d_ny, (double*)p.d_str, C, p.d_dc);
+        hipLaunchKernelGGL(k_strengths<double>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
+                           p.d_w, p.d_nx, p.d_ny, (double*)ws.str, C, ws.dc);
     return hipGetLastError();
 }
 
@@ -130,29 +132,30 @@ size_t spread_lds_bytes(const Plan& p, int level, int C, bool use_bnd)
 #define VP_W_CASES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
 template <typename R, int W, int C>
-static void spread_launch(Plan& p, int l, size_t lds, int uv, int ub)
+static void spread_launch(const Plan& p, const Workspace& ws, hipStream_t st, int l, size_t lds, int uv, int ub)
 {
     const LevelGeom& g = p.lv[l];
-    LevelBufs& b = p.lb[l];
+    const LevelBufs& b = p.lb[l];
     const unsigned ntiles = (unsigned)(g.ntx * g.ntx);
     hipFuncSetAttribute((const void*)k_spread<R, W, C>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_spread<R, W, C>), dim3(ntiles), dim3(kThreads), lds, p.stream, g, view<R>(b.vol),
-                       view<R>(b.bnd), (const R*)p.d_str, p.n_src + p.n_bnd, (R*)b.grid, uv, ub,
+    hipLaunchKernelGGL((k_spread<R, W, C>), dim3(ntiles), dim3(kThreads), lds, st, g, view<R>(b.vol),
+                       view<R>(b.bnd), (const R*)ws.str, p.n_src + p.n_bnd, (R*)ws.grid[l], uv, ub,
                        (const double*)b.horner);
 }
 
 template <typename R>
-static hipError_t spread_t(Plan& p, int l, int C, bool use_vol, bool use_bnd)
+static hipError_t spread_t(const Plan& p, const Workspace& ws, hipStream_t st, int l, int C, bool use_vol,
+                           bool use_bnd)
 {
-    LevelBufs& b = p.lb[l];
+    const LevelBufs& b = p.lb[l];
     const size_t lds = spread_lds_bytes(p, l, C, use_bnd);
     const int uv = use_vol && b.vol.start != nullptr;
     const int ub = use_bnd && b.bnd.start != nullptr;
     switch (p.lv[l].w) {
-#define VP_CASE(W)                                      \
-    case W:                                             \
-        if (C == 1) spread_launch<R, W, 1>(p, l, lds, uv, ub); \
-        else spread_launch<R, W, 3>(p, l, lds, uv, ub);        \
+#define VP_CASE(W)                                                       \
+    case W:                                                              \
+        if (C == 1) spread_launch<R, W, 1>(p, ws, st, l, lds, uv, ub);   \
+        else spread_launch<R, W, 3>(p, ws, st, l, lds, uv, ub);          \
         break;
         VP_W_CASES(VP_CASE)
 #undef VP_CASE
@@ -162,80 +165,83 @@ static hipError_t spread_t(Plan& p, int l, int C, bool use_vol, bool use_bnd)
     return hipGetLastError();
 }
 
-hipError_t launch_spread(Plan& p, int level, int C, bool use_vol, bool use_bnd)
+hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C, bool use_vol,
+                         bool use_bnd)
 {
-    return p.precision == VP_FP32 ? spread_t<float>(p, level, C, use_vol, use_bnd)
-                                  : spread_t<double>(p, level, C, use_vol, use_bnd);
+    return p.precision == VP_FP32 ? spread_t<float>(p, ws, st, level, C, use_vol, use_bnd)
+                                  : spread_t<double>(p, ws, st, level, C, use_vol, use_bnd);
 }
 
 template <typename R>
-static hipError_t row_fft_t(Plan& p, int l, int C)
+static hipError_t row_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l, int C)
 {
     const LevelGeom& g = p.lv[l];
-    LevelBufs& b = p.lb[l];
-    hipLaunchKernelGGL(k_row_r2c<R>, dim3(g.F * C), dim3(kThreads), row_fft_lds_bytes(p, l), p.stream, g,
-                       (const R*)b.grid, (const cplx<R>*)b.tw, (cplx<R>*)b.spec);
+    const LevelBufs& b = p.lb[l];
+    hipLaunchKernelGGL(k_row_r2c<R>, dim3(g.F * C), dim3(kThreads), row_fft_lds_bytes(p, l), st, g,
+                       (const R*)ws.grid[l], (const cplx<R>*)b.tw, (cplx<R>*)ws.spec[l]);
     return hipGetLastError();
 }
 
-hipError_t launch_row_fft(Plan& p, int level, int C)
+hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C)
 {
-    return p.precision == VP_FP32 ? row_fft_t<float>(p, level, C) : row_fft_t<double>(p, level, C);
+    return p.precision == VP_FP32 ? row_fft_t<float>(p, ws, st, level, C) : row_fft_t<double>(p, ws, st, level, C);
 }
 
 template <typename R>
-static hipError_t col_fft_t(Plan& p, int l, int C)
+static hipError_t col_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l, int C)
 {
     const LevelGeom& g = p.lv[l];
-    LevelBufs& b = p.lb[l];
+    const LevelBufs& b = p.lb[l];
     const int zero_dc = p.precision == VP_FP32 ? 1 : 0;
     if (C == 1)
-        hipLaunchKernelGGL((k_col<R, 1>), dim3(g.M + 1), dim3(kThreads), col_fft_lds_bytes(p, l), p.stream, g,
-                           (const cplx<R>*)b.spec, (const R*)b.mult, (const cplx<R>*)b.tw, (cplx<R>*)b.spec2, zero_dc);
+        hipLaunchKernelGGL((k_col<R, 1>), dim3(g.M + 1), dim3(kThreads), col_fft_lds_bytes(p, l), st, g,
+                           (const cplx<R>*)ws.spec[l], (const R*)b.mult, (const cplx<R>*)b.tw,
+                           (cplx<R>*)ws.spec2[l], zero_dc);
     else
-        hipLaunchKernelGGL((k_col<R, 3>), dim3(g.M + 1), dim3(kThreads), col_fft_lds_bytes(p, l), p.stream, g,
-                           (const cplx<R>*)b.spec, (const R*)b.mult, (const cplx<R>*)b.tw, (cplx<R>*)b.spec2, zero_dc);
+        hipLaunchKernelGGL((k_col<R, 3>), dim3(g.M + 1), dim3(kThreads), col_fft_lds_bytes(p, l), st, g,
+                           (const cplx<R>*)ws.spec[l], (const R*)b.mult, (const cplx<R>*)b.tw,
+                           (cplx<R>*)ws.spec2[l], zero_dc);
     return hipGetLastError();
 }
 
-hipError_t launch_col_fft(Plan& p, int level, int C)
+hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C)
 {
-    return p.precision == VP_FP32 ? col_fft_t<float>(p, level, C) : col_fft_t<double>(p, level, C);
+    return p.precision == VP_FP32 ? col_fft_t<float>(p, ws, st, level, C) : col_fft_t<double>(p, ws, st, level, C);
 }
 
 template <typename R>
-static hipError_t row_ifft_t(Plan& p, int l)
+static hipError_t row_ifft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l)
 {
     const LevelGeom& g = p.lv[l];
-    LevelBufs& b = p.lb[l];
-    hipLaunchKernelGGL(k_row_c2r<R>, dim3(g.F), dim3(kThreads), row_fft_lds_bytes(p, l), p.stream, g,
-                       (const cplx<R>*)b.spec2, (const cplx<R>*)b.tw, (R*)b.grid);
+    const LevelBufs& b = p.lb[l];
+    hipLaunchKernelGGL(k_row_c2r<R>, dim3(g.F), dim3(kThreads), row_fft_lds_bytes(p, l), st, g,
+                       (const cplx<R>*)ws.spec2[l], (const cplx<R>*)b.tw, (R*)ws.grid[l]);
     return hipGetLastError();
 }
 
-hipError_t launch_row_ifft(Plan& p, int level)
+hipError_t launch_row_ifft(const Plan& p, const Workspace& ws, hipStream_t st, int level)
 {
-    return p.precision == VP_FP32 ? row_ifft_t<float>(p, level) : row_ifft_t<double>(p, level);
+    return p.precision == VP_FP32 ? row_ifft_t<float>(p, ws, st, level) : row_ifft_t<double>(p, ws, st, level);
 }
 
 template <typename R, int W>
-static void interp_launch(Plan& p, int l)
+static void interp_launch(const Plan& p, const Workspace& ws, hipStream_t st, int l)
 {
     const LevelGeom& g = p.lv[l];
-    LevelBufs& b = p.lb[l];
+    const LevelBufs& b = p.lb[l];
     const int E = g.T + W - 1;
     const size_t lds = (size_t)E * E * sizeof(R);
-    hipLaunchKernelGGL((k_interp<R, W>), dim3(g.ntx * g.ntx), dim3(kThreads), lds, p.stream, g, (const R*)b.grid,
-                       view<R>(b.tgt), (R*)b.hist, (const double*)b.horner);
+    hipLaunchKernelGGL((k_interp<R, W>), dim3(g.ntx * g.ntx), dim3(kThreads), lds, st, g, (const R*)ws.grid[l],
+                       view<R>(b.tgt), (R*)ws.hist[l], (const double*)b.horner);
 }
 
 template <typename R>
-static hipError_t interp_t(Plan& p, int l)
+static hipError_t interp_t(const Plan& p, const Workspace& ws, hipStream_t st, int l)
 {
     switch (p.lv[l].w) {
-#define VP_CASE(W)               \
-    case W:                      \
-        interp_launch<R, W>(p, l); \
+#define VP_CASE(W)                           \
+    case W:                                  \
+        interp_launch<R, W>(p, ws, st, l);   \
         break;
         VP_W_CASES(VP_CASE)
 #undef VP_CASE
@@ -245,13 +251,13 @@ static hipError_t interp_t(Plan& p, int l)
     return hipGetLastError();
 }
 
-hipError_t launch_interp(Plan& p, int level)
+hipError_t launch_interp(const Plan& p, const Workspace& ws, hipStream_t st, int level)
 {
-    return p.precision == VP_FP32 ? interp_t<float>(p, level) : interp_t<double>(p, level);
+    return p.precision == VP_FP32 ? interp_t<float>(p, ws, st, level) : interp_t<double>(p, ws, st, level);
 }
 
-hipError_t launch_local(Plan& p, const double* jet6, const double* sig_jet, const double* mu_jet, bool use_v,
-                        bool use_s, bool use_d, double* out)
+hipError_t launch_local(const Plan& p, const Workspace& ws, hipStream_t st, const double* jet6, const double* sig_jet,
+                        const double* mu_jet, bool use_v, bool use_s, bool use_d, double* out)
 {
     LocalArgs a{};
     a.n = p.n_tgt;
@@ -269,14 +275,14 @@ hipError_t launch_local(Plan& p, const double* jet6, const double* sig_jet, cons
     a.jet6 = use_v ? jet6 : nullptr;
     a.sj = use_s ? sig_jet : nullptr;
     a.mj = use_d ? mu_jet : nullptr;
-    a.h0 = p.lb[0].hist;
-    a.h1 = p.lb[1].hist;
+    a.h0 = ws.hist[0];
+    a.h1 = ws.hist[1];
     a.fp32 = p.precision == VP_FP32;
     a.dc_weight = p.lv[0].dc_coef + p.lv[1].dc_coef;
-    a.dc = a.fp32 ? p.d_dc : nullptr;
+    a.dc = a.fp32 ? ws.dc : nullptr;
     a.out = out;
     if (p.n_tgt == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_local, dim3(grid_for(p.n_tgt)), dim3(kThreads), 0, p.stream, a);
+    hipLaunchKernelGGL(k_local, dim3(grid_for(p.n_tgt)), dim3(kThreads), 0, st, a);
     return hipGetLastError();
 }
 

@@ -41,6 +41,8 @@ vp_status fail(vp_status s, const std::string& msg)
     return s;
 }
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 #define VP_HIP(call, what)                                                                       \
     do {                                                                                         \
         hipError_t e_ = (call);                                                                  \
@@ -230,6 +232,7 @@ void free_plan(vp_plan_s* p)
     else hipDeviceSynchronize();
     for (void* q : p->allocs) hipFree(q);
     p->allocs.clear();
+    workspace_free(p->ws, nullptr, false);
     if (p->ev_made)
         for (auto& e : p->ev) hipEventDestroy(e);
     delete p;
@@ -380,33 +383,111 @@ vp_status build_plan_t(Plan& p, const std::vector<double>& sxv, const std::vecto
                        const std::vector<double>& ty, const std::vector<std::vector<double>>& phihat)
 {
     vp_status s;
-    const int Cmax = (p.kinds & VP_KIND_D) ? 3 : 1;
     std::vector<int> tids(p.n_tgt);
     std::iota(tids.begin(), tids.end(), 0);
     for (int l = 0; l < 2; ++l) {
-        LevelGeom& g = p.lv[l];
         LevelBufs& b = p.lb[l];
         if ((s = build_records<R>(p, l, sxv, syv, vol_ids, true, &b.vol)) != VP_OK) return s;
         if ((s = build_records<R>(p, l, sxv, syv, bnd_ids, true, &b.bnd)) != VP_OK) return s;
         if ((s = build_records<R>(p, l, tx, ty, tids, false, &b.tgt)) != VP_OK) return s;
         if ((s = build_level_tables<R>(p, l, phihat[l], p.delta1, p.delta2)) != VP_OK) return s;
-        const size_t FF = (size_t)g.F * g.F;
-        if ((s = dalloc_bytes(p, &b.grid, Cmax * FF * sizeof(R), "grid")) != VP_OK) return s;
-        if ((s = dalloc_bytes(p, &b.spec, (size_t)Cmax * (g.M + 1) * g.F * sizeof(cplx<R>), "spectrum")) != VP_OK)
-            return s;
-        if ((s = dalloc_bytes(p, &b.spec2, (size_t)(g.M + 1) * g.F * sizeof(cplx<R>), "spectrum2")) != VP_OK)
-            return s;
-        if ((s = dalloc_bytes(p, &b.hist, (size_t)std::max<int64_t>(p.n_tgt, 1) * sizeof(R), "hist")) != VP_OK)
-            return s;
     }
-    const int64_t nn = p.n_src + p.n_bnd;
-    if ((s = dalloc_bytes(p, &p.d_str, (size_t)3 * std::max<int64_t>(nn, 1) * sizeof(R), "strengths")) != VP_OK)
-        return s;
-    VP_HIP(hipMemset(p.d_str, 0, (size_t)3 * std::max<int64_t>(nn, 1) * sizeof(R)), "strengths memset");
     return VP_OK;
 }
 
 }  // namespace
+
+vp_status set_error(vp_status s, const std::string& msg) { return fail(s, msg); }
+
+// Workspace layout: grid, spec, spec2, hist per level, then strengths and dc,
+// each 256-byte aligned inside one allocation.
+static size_t workspace_layout(const Plan& p, Workspace* ws, unsigned char* base)
+{
+    const size_t rb = p.precision == VP_FP32 ? sizeof(float) : sizeof(double);
+    size_t off = 0;
+    auto take = [&](void** slot, size_t bytes) {
+        if (slot) *slot = base ? base + off : nullptr;
+        off += align256(std::max<size_t>(bytes, 1));
+    };
+    for (int l = 0; l < 2; ++l) {
+        const LevelGeom& g = p.lv[l];
+        const size_t F = g.F, M1 = g.M + 1;
+        take(ws ? &ws->grid[l] : nullptr, (size_t)p.cmax * F * F * rb);
+        take(ws ? &ws->spec[l] : nullptr, (size_t)p.cmax * M1 * F * 2 * rb);
+        take(ws ? &ws->spec2[l] : nullptr, M1 * F * 2 * rb);
+        take(ws ? &ws->hist[l] : nullptr, (size_t)std::max<int64_t>(p.n_tgt, 1) * rb);
+    }
+    take(ws ? &ws->str : nullptr, (size_t)p.cmax * std::max<int64_t>(p.n_src + p.n_bnd, 1) * rb);
+    void* dcp = nullptr;
+    take(ws ? &dcp : nullptr, sizeof(double));
+    if (ws) ws->dc = (double*)dcp;
+    return off;
+}
+
+size_t workspace_bytes(const Plan& p) { return workspace_layout(p, nullptr, nullptr); }
+
+hipError_t workspace_alloc(const Plan& p, Workspace& ws, hipStream_t st, bool async)
+{
+    const size_t bytes = workspace_bytes(p);
+    void* blk = nullptr;
+    hipError_t e = async ? hipMallocAsync(&blk, bytes, st) : hipMalloc(&blk, bytes);
+    if (e != hipSuccess) return e;
+    ws = Workspace{};
+    ws.block = blk;
+    ws.bytes = bytes;
+    workspace_layout(p, &ws, (unsigned char*)blk);
+    return hipSuccess;
+}
+
+hipError_t workspace_free(Workspace& ws, hipStream_t st, bool async)
+{
+    hipError_t e = hipSuccess;
+    if (ws.block) e = async ? hipFreeAsync(ws.block, st) : hipFree(ws.block);
+    ws = Workspace{};
+    return e;
+}
+
+vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* jet6,
+                       const double* sigma, const double* sigma_jet3, const double* mu, const double* mu_jet5,
+                       double* out, bool timing)
+{
+    if (!out && p.n_tgt) return fail(VP_ERR_ARG, "out is NULL");
+    const bool use_v = f != nullptr;
+    const bool use_s = sigma != nullptr;
+    const bool use_d = mu != nullptr;
+    if (!use_v && !use_s && !use_d) return fail(VP_ERR_ARG, "no density given");
+    if (use_v && !(p.kinds & VP_KIND_V)) return fail(VP_ERR_ARG, "plan does not support V");
+    if (use_s && !(p.kinds & VP_KIND_S)) return fail(VP_ERR_ARG, "plan does not support S");
+    if (use_d && !(p.kinds & VP_KIND_D)) return fail(VP_ERR_ARG, "plan does not support D");
+    if (use_v && !jet6) return fail(VP_ERR_ARG, "jet6 is required with f");
+    if (use_s && !sigma_jet3) return fail(VP_ERR_ARG, "sigma_jet3 is required with sigma");
+    if (use_d && !mu_jet5) return fail(VP_ERR_ARG, "mu_jet5 is required with mu");
+    if (!ws.block) return fail(VP_ERR_ARG, "no workspace");
+    const int C = use_d ? 3 : 1;
+    if (timing && !p.ev_made) {
+        for (auto& e : p.ev) VP_HIP(hipEventCreate(&e), "event create");
+        p.ev_made = true;
+    }
+    auto mark = [&](int k) -> hipError_t { return timing ? hipEventRecord(p.ev[k], st) : hipSuccess; };
+    // stage boundaries: ev[0] before strengths ... ev[7] after local
+    VP_HIP(mark(0), "event");
+    VP_HIP(launch_zero_dc(p, ws, st), "zero dc");
+    VP_HIP(launch_strengths(p, ws, st, f, sigma, mu, C), "strengths");
+    VP_HIP(mark(1), "event");
+    for (int l = 0; l < 2; ++l) VP_HIP(launch_spread(p, ws, st, l, C, use_v, use_s || use_d), "spread");
+    VP_HIP(mark(2), "event");
+    for (int l = 0; l < 2; ++l) VP_HIP(launch_row_fft(p, ws, st, l, C), "row fft");
+    VP_HIP(mark(3), "event");
+    for (int l = 0; l < 2; ++l) VP_HIP(launch_col_fft(p, ws, st, l, C), "column fft");
+    VP_HIP(mark(4), "event");
+    for (int l = 0; l < 2; ++l) VP_HIP(launch_row_ifft(p, ws, st, l), "row ifft");
+    VP_HIP(mark(5), "event");
+    for (int l = 0; l < 2; ++l) VP_HIP(launch_interp(p, ws, st, l), "interp");
+    VP_HIP(mark(6), "event");
+    VP_HIP(launch_local(p, ws, st, jet6, sigma_jet3, mu_jet5, use_v, use_s, use_d, out), "local");
+    VP_HIP(mark(7), "event");
+    return VP_OK;
+}
 
 }  // namespace vp
 
@@ -426,6 +507,7 @@ void vp_opts_default(vp_opts* o)
     o->order_s = 3;
     o->order_d = 3;
     o->kinds = VP_KIND_V | VP_KIND_S | VP_KIND_D;
+    o->no_workspace = 0;
 }
 
 const char* vp_last_error(void) { return g_last_error.c_str(); }
@@ -663,7 +745,6 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
         if ((s = upload(*p, &p->d_nx, bnx, "normals")) != VP_OK) return bail(s);
         if ((s = upload(*p, &p->d_ny, bny, "normals")) != VP_OK) return bail(s);
     }
-    if ((s = dalloc(*p, &p->d_dc, 1, "dc")) != VP_OK) return bail(s);
     if (n_tgt) {
         if ((s = upload(*p, &p->g_r, gr, "geom")) != VP_OK) return bail(s);
         if ((s = upload(*p, &p->g_nx, gnx, "geom")) != VP_OK) return bail(s);
@@ -676,6 +757,14 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
     s = (o.precision == VP_FP32) ? build_plan_t<float>(*p, ax, ay, vol_ids, bnd_ids, tx, ty, phihat)
                                  : build_plan_t<double>(*p, ax, ay, vol_ids, bnd_ids, tx, ty, phihat);
     if (s != VP_OK) return bail(s);
+    p->cmax = Cmax;
+    if (!o.no_workspace) {
+        hipError_t e = workspace_alloc(*p, p->ws, p->stream, false);
+        if (e != hipSuccess)
+            return bail(fail(e == hipErrorOutOfMemory ? VP_ERR_OOM : VP_ERR_DEVICE,
+                             std::string("workspace: ") + hipGetErrorString(e)));
+        p->device_bytes += p->ws.bytes;
+    }
     for (int l = 0; l < 2; ++l) {
         const size_t lds_row = row_fft_lds_bytes(*p, l), lds_col = col_fft_lds_bytes(*p, l);
         const size_t lds_sp = spread_lds_bytes(*p, l, Cmax, need_b);
@@ -691,41 +780,16 @@ vp_status vp_eval(vp_plan_t p, const double* f, const double* jet6, const double
 {
     g_last_error.clear();
     if (!p) return fail(VP_ERR_ARG, "plan is NULL");
-    if (!out && p->n_tgt) return fail(VP_ERR_ARG, "out is NULL");
-    const bool use_v = f != nullptr;
-    const bool use_s = sigma != nullptr;
-    const bool use_d = mu != nullptr;
-    if (!use_v && !use_s && !use_d) return fail(VP_ERR_ARG, "no density given");
-    if (use_v && !(p->kinds & VP_KIND_V)) return fail(VP_ERR_ARG, "plan does not support V");
-    if (use_s && !(p->kinds & VP_KIND_S)) return fail(VP_ERR_ARG, "plan does not support S");
-    if (use_d && !(p->kinds & VP_KIND_D)) return fail(VP_ERR_ARG, "plan does not support D");
-    if (use_v && !jet6) return fail(VP_ERR_ARG, "jet6 is required with f");
-    if (use_s && !sigma_jet3) return fail(VP_ERR_ARG, "sigma_jet3 is required with sigma");
-    if (use_d && !mu_jet5) return fail(VP_ERR_ARG, "mu_jet5 is required with mu");
-    const int C = use_d ? 3 : 1;
-    if (p->timing && !p->ev_made) {
-        for (auto& e : p->ev) VP_HIP(hipEventCreate(&e), "event create");
-        p->ev_made = true;
-    }
-    auto mark = [&](int k) -> hipError_t { return p->timing ? hipEventRecord(p->ev[k], p->stream) : hipSuccess; };
-    // stage boundaries: ev[0] before strengths ... ev[7] after local
-    VP_HIP(mark(0), "event");
-    VP_HIP(launch_zero_dc(*p), "zero dc");
-    VP_HIP(launch_strengths(*p, f, sigma, mu, C), "strengths");
-    VP_HIP(mark(1), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_spread(*p, l, C, use_v, use_s || use_d), "spread");
-    VP_HIP(mark(2), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_row_fft(*p, l, C), "row fft");
-    VP_HIP(mark(3), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_col_fft(*p, l, C), "column fft");
-    VP_HIP(mark(4), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_row_ifft(*p, l), "row ifft");
-    VP_HIP(mark(5), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_interp(*p, l), "interp");
-    VP_HIP(mark(6), "event");
-    VP_HIP(launch_local(*p, jet6, sigma_jet3, mu_jet5, use_v, use_s, use_d, out), "local");
-    VP_HIP(mark(7), "event");
-    return VP_OK;
+    if (p->ws.block) return eval_enqueue(*p, p->ws, p->stream, f, jet6, sigma, sigma_jet3, mu, mu_jet5, out, p->timing);
+    // plan without its own workspace: a stream-ordered temporary one
+    Workspace ws;
+    hipError_t e = workspace_alloc(*p, ws, p->stream, true);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? VP_ERR_OOM : VP_ERR_DEVICE,
+                    std::string("workspace: ") + hipGetErrorString(e));
+    vp_status s = eval_enqueue(*p, ws, p->stream, f, jet6, sigma, sigma_jet3, mu, mu_jet5, out, p->timing);
+    workspace_free(ws, p->stream, true);
+    return s;
 }
 
 vp_status vp_volume(vp_plan_t p, const double* f, const double* jet6, double* out)
@@ -768,6 +832,7 @@ vp_status vp_get_plan_info(vp_plan_t p, vp_plan_info* info)
     info->n_bnd = p->n_bnd;
     info->n_tgt = p->n_tgt;
     info->device_bytes = p->device_bytes;
+    info->workspace_bytes = workspace_bytes(*p);
     return VP_OK;
 }
 
