@@ -157,11 +157,35 @@ def main():
     ap.add_argument("--oracle-sample", type=int, default=192, help="targets for the CPU oracle leg")
     ap.add_argument("--no-fp32-leg", action="store_true")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workloads (quick runs)")
+    ap.add_argument("--no-batch-leg", action="store_true")
+    ap.add_argument("--no-serve-leg", action="store_true")
+    ap.add_argument("--batch-instances", type=int, default=64)
+    ap.add_argument("--batch-max-tri", type=float, default=5e4)
+    ap.add_argument("--serve-meshes", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=1500)
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / saturated rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    # inputs of the batch and serving legs are generated in a process pool before any GPU use
+    rng = np.random.default_rng(4)
+    batch_specs, serve_specs = [], []
+    if not args.no_batch_leg:
+        tri = np.exp(rng.uniform(np.log(1e3), np.log(args.batch_max_tri), args.batch_instances)) * args.scale
+        batch_specs = [(max(200, int(t)), 4000 + i, "VD") for i, t in enumerate(tri)]
+    if not args.no_serve_leg:
+        rs = np.random.default_rng(5)
+        nodes = np.exp(rs.uniform(np.log(2e3), np.log(5e5), args.serve_meshes)) * args.scale
+        serve_specs = [(max(200, int(n / 6)), 5000 + i, "VSD") for i, n in enumerate(nodes)]
+    pool_probs = []
+    if batch_specs or serve_specs:
+        from workloads.pool import stars
+        log("bench: generating %d batch and %d serving meshes" % (len(batch_specs), len(serve_specs)))
+        pool_probs = stars(batch_specs + serve_specs)
+    batch_probs = pool_probs[:len(batch_specs)]
+    serve_probs = pool_probs[len(batch_specs):]
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
@@ -215,7 +239,147 @@ def main():
                        "stages_ms": {k: round(v, 4) for k, v in st32.items()},
                        "stages_gbs": {k: round(alg32[k] / (st32[k] * 1e-3) / 1e9, 1) for k in STAGES if st32[k] > 0},
                        "e_inf_vs_oracle_sample": r32.get("e_inf_sample"), "plan_s": round(r32["plan_s"], 3)}
+    if batch_probs:
+        log("bench: batch leg, %d instances, %d targets" % (len(batch_probs), sum(P.n_tgt for P in batch_probs)))
+        rec["batch"] = batch_leg(torch, batch_probs, args.steps, args.warmup)
+    if serve_probs:
+        log("bench: serving leg, %d meshes" % len(serve_probs))
+        rec["serve"] = serve_leg(torch, serve_probs, args.serve_requests, args.serve_load)
+        rec["latency_p50_s"] = rec["serve"]["served"]["p50_s"]
+        rec["latency_p99_s"] = rec["serve"]["served"]["p99_s"]
     print(json.dumps(rec), flush=True)
+
+
+def batch_leg(torch, probs, steps, warmup):
+    """Float32 V+D on many star instances: one persistent launch per stage (hipGraph)
+    against the same plans launched one after another."""
+    from paper_2409_11998_amd import Batch
+    from workloads.device import make_batch_plans, run, to_device
+    devs = [to_device(P) for P in probs]
+    t0 = time.perf_counter()
+    plans = make_batch_plans(devs, tol=1e-6, precision=0, kinds=5)
+    plan_s = time.perf_counter() - t0
+    batch = Batch(plans, 5)
+    outs = [torch.empty(P.n_tgt, dtype=torch.float64, device="cuda") for P in probs]
+    args = [dict(f=d["f"], jet6=d["jet6"], mu=d["mu"], mu_jet=d["mu_jet"], out=o) for d, o in zip(devs, outs)]
+    for _ in range(warmup):
+        batch.eval(args, graph=True)
+    batch.stream.synchronize()
+    n_t = sum(P.n_tgt for P in probs)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.eval(args, graph=True)
+    batch.stream.synchronize()
+    el_b = time.perf_counter() - t0
+    got = [o.cpu().numpy() for o in outs]
+    # the same plans, one plain launch sequence each
+    seq_outs = [torch.empty_like(o) for o in outs]
+    for p, d, o in zip(plans, devs, seq_outs):
+        run(p, d, "VD", out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for p, d, o in zip(plans, devs, seq_outs):
+            run(p, d, "VD", out=o)
+    torch.cuda.synchronize()
+    el_s = time.perf_counter() - t0
+    dev_single = max(float(np.max(np.abs(g - s.cpu().numpy())) / max(np.max(np.abs(s.cpu().numpy())), 1e-300))
+                     for g, s in zip(got, seq_outs))
+    # oracle check on the two smallest instances
+    import oracle
+    small = sorted(range(len(probs)), key=lambda i: probs[i].n_tgt)[:2]
+    e_or = max(oracle.rel_linf(got[i], oracle.evaluate(probs[i], kinds="VD")["total"]) for i in small)
+    sizes = [P.n_src for P in probs]
+    batch.close()
+    for p in plans:
+        p.close()
+    return {"workload": "%d star instances, triangles log-U[1e3,%g], V+D fp32 tol1e-6" % (len(probs), max(
+                P.info["n_tri"] for P in probs)),
+            "instances": len(probs), "n_tgt_total": n_t, "nodes_min": int(min(sizes)), "nodes_max": int(max(sizes)),
+            "value": round(n_t * steps / el_b, 1), "unit": "target pts/s", "ms_per_step": round(1e3 * el_b / steps, 4),
+            "sequential_value": round(n_t * steps / el_s, 1), "sequential_ms_per_step": round(1e3 * el_s / steps, 4),
+            "max_rel_dev_vs_single_plans": dev_single, "e_inf_vs_oracle_smallest2": e_or,
+            "plan_s": round(plan_s, 2)}
+
+
+def serve_leg(torch, probs, n_req, load):
+    """Poisson stream of V/S/D requests (70% float32 1e-6, 30% float64 1e-10) on resident
+    plans through the serving loop, against the plain float64 path run one by one."""
+    from paper_2409_11998_amd import Server
+    from workloads.device import make_plan, to_device
+    devs = [to_device(P) for P in probs]
+    plans = {}
+    for i, d in enumerate(devs):
+        for prec, tol in ((0, 1e-6), (1, 1e-10)):
+            plans[(i, prec)] = make_plan(d, tol=tol, precision=prec, kinds=7, no_workspace=True)
+    rng = np.random.default_rng(55)
+    reqs = []
+    for _ in range(n_req):
+        i = int(rng.integers(len(probs)))
+        kind = "VSD"[int(rng.integers(3))]
+        prec = 0 if rng.uniform() < 0.7 else 1
+        reqs.append((i, kind, prec))
+
+    def kw(d, kind):
+        return dict(f=d["f"] if kind == "V" else None, jet6=d["jet6"] if kind == "V" else None,
+                    sigma=d["sigma"] if kind == "S" else None, sigma_jet=d["sigma_jet"] if kind == "S" else None,
+                    mu=d["mu"] if kind == "D" else None, mu_jet=d["mu_jet"] if kind == "D" else None)
+    outs = {i: torch.empty(P.n_tgt, dtype=torch.float64, device="cuda") for i, P in enumerate(probs)}
+    budget = int(0.8 * torch.cuda.mem_get_info()[0])
+    torch.cuda.synchronize()
+    # saturated rate: the whole request list submitted at once
+    srv = Server(hbm_budget_bytes=budget, max_in_flight=8, n_streams=4)
+    sat_out = [torch.empty_like(outs[i]) for i, _, _ in reqs[:min(300, n_req)]]
+    torch.cuda.synchronize()
+    tk = [srv.submit(plans[(i, p)], o, **kw(devs[i], k)) for (i, k, p), o in zip(reqs, sat_out)]
+    for t in tk:
+        srv.wait(t, timeout=300)
+    sat = srv.stats()
+    srv.close()
+    rate_sat = sat["completed"] / max(sat["span_s"], 1e-9)
+    lam = load * rate_sat
+    # Poisson arrivals at lam
+    gaps = rng.exponential(1.0 / lam, n_req)
+    srv = Server(hbm_budget_bytes=budget, max_in_flight=8, n_streams=4)
+    req_out = [torch.empty_like(outs[i]) for i, _, _ in reqs]   # one output per request
+    torch.cuda.synchronize()
+    tickets = []
+    t_next = time.perf_counter()
+    for r, (i, k, p) in enumerate(reqs):
+        t_next += gaps[r]
+        while time.perf_counter() < t_next:
+            pass
+        tickets.append(srv.submit(plans[(i, p)], req_out[r], **kw(devs[i], k)))
+    for t in tickets:
+        srv.wait(t, timeout=600)
+    st = srv.stats()
+    srv.close()
+    # plain float64 path, one request at a time (same requests, float64 1e-10, no queueing)
+    fp64_plans = {i: make_plan(d, tol=1e-10, precision=1, kinds=7) for i, d in enumerate(devs)}
+    lat64 = []
+    n_t = 0
+    t0 = time.perf_counter()
+    for i, k, p in reqs[:min(500, n_req)]:
+        t1 = time.perf_counter()
+        fp64_plans[i].eval(out=outs[i], **kw(devs[i], k))
+        torch.cuda.synchronize()
+        lat64.append(time.perf_counter() - t1)
+        n_t += probs[i].n_tgt
+    el64 = time.perf_counter() - t0
+    lat64 = np.sort(lat64)
+    for p in list(plans.values()) + list(fp64_plans.values()):
+        p.close()
+    return {"workload": "%d requests on %d seeded star meshes (nodes log-U[2e3,5e5]); kinds V/S/D uniform; "
+                        "70%% fp32 1e-6 / 30%% fp64 1e-10; Poisson arrivals at %.2f x saturated rate"
+                        % (n_req, len(probs), load),
+            "saturated_req_per_s": round(rate_sat, 1), "arrival_req_per_s": round(lam, 1),
+            "served": {"p50_s": st["p50_s"], "p99_s": st["p99_s"], "max_s": st["max_s"],
+                       "targets_per_s": round(st["targets_per_s"], 1), "completed": st["completed"],
+                       "deferred": st["deferred"], "peak_in_flight": st["peak_in_flight"],
+                       "peak_workspace_bytes": st["peak_bytes"], "hbm_budget_bytes": budget},
+            "plain_fp64_sequential": {"p50_s": float(lat64[len(lat64) // 2]),
+                                      "p99_s": float(lat64[min(len(lat64) - 1, int(0.99 * len(lat64)))]),
+                                      "targets_per_s": round(n_t / el64, 1), "requests": len(lat64)}}
 
 
 if __name__ == "__main__":

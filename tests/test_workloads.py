@@ -36,8 +36,13 @@ def test_square_mesh_has_slivers_degenerates_and_gaps():
 def test_star_geometry_closest_point():
     P = star_problem(800, seed=4)
     g = P.geom
-    bx = P.tgt_x + g["sgn"] * g["r"] * g["nx"]
-    by = P.tgt_y + g["sgn"] * g["r"] * g["ny"]
+    m = P.info["near_mask"]
+    assert m.sum() > 100
+    # far targets carry a lower bound of their distance, above 12 sqrt(delta_1)
+    d1 = 3 * P.src_w.sum() / P.n_src
+    assert np.all(g["r"][~m] > 12 * np.sqrt(d1))
+    bx = (P.tgt_x + g["sgn"] * g["r"] * g["nx"])[m]
+    by = (P.tgt_y + g["sgn"] * g["r"] * g["ny"])[m]
     # b lies on the boundary: its distance to the dense boundary nodes is tiny
     from scipy.spatial import cKDTree
     d, _ = cKDTree(np.stack([P.bnd_x, P.bnd_y], 1)).query(np.stack([bx, by], 1))
