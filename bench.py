@@ -30,8 +30,10 @@ sys.path.insert(0, ROOT)
 METRIC = "target pts/s for V[f]+D[mu] at 1e-6 FP32 vs 1e-10 FP64; p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
 STAGES = ["strengths", "spread", "row_fft", "col_fft_mul", "row_ifft", "interp", "local"]
-KERNELS = {"strengths": "k_strengths", "spread": "k_spread", "row_fft": "k_row_r2c",
-           "col_fft_mul": "k_col", "row_ifft": "k_row_c2r", "interp": "k_interp", "local": "k_local"}
+LAUNCHES = ["strengths", "spread_nh", "spread_fh", "row_fft_nh", "row_fft_fh", "col_fft_mul_nh", "col_fft_mul_fh",
+            "row_ifft_nh", "row_ifft_fh", "interp_nh", "interp_fh", "local"]
+KERNELS = {"strengths": "k_strengths", "spread": "k_spread", "row_fft": "k_row_r2c", "col_fft_mul": "k_col",
+           "row_ifft": "k_row_c2r", "interp": "k_interp", "local": "k_local"}
 
 
 def log(*a):
@@ -39,23 +41,24 @@ def log(*a):
 
 
 def algorithmic_bytes(info, P, kinds, b):
-    """Bytes each stage must move at minimum (one read of each input, one write of each output)."""
+    """Bytes each launch must move at minimum: one read of each input, one write of each output.
+    Node records count their packed support corner (4 B), two offsets and their strengths."""
     n_v = P.n_src if "V" in kinds else 0
     n_b = P.n_bnd if ("S" in kinds or "D" in kinds) else 0
     C = 3 if "D" in kinds else 1
     cb = 1 if "D" not in kinds else 3
-    out = dict.fromkeys(STAGES, 0.0)
+    out = {}
     out["strengths"] = n_v * (16 + b) + n_b * (8 * 4 + cb * b)
     nt = P.n_tgt
-    for l in range(2):
+    for l, tag in enumerate(("nh", "fh")):
         F = info["fine"][l]
         M = (info["modes"][l] - 1) // 2
         half = (M + 1) * F * 2 * b
-        out["spread"] += n_v * (4 + 2 * b + b) + n_b * (4 + 2 * b + cb * b) + C * F * F * b
-        out["row_fft"] += C * F * F * b + C * half
-        out["col_fft_mul"] += C * half + half + (M + 1) ** 2 * b
-        out["row_ifft"] += half + F * F * b
-        out["interp"] += F * F * b + nt * (4 + 2 * b + 4) + nt * b
+        out["spread_" + tag] = n_v * (4 + 3 * b) + n_b * (4 + 2 * b + cb * b) + C * F * F * b
+        out["row_fft_" + tag] = C * F * F * b + C * half
+        out["col_fft_mul_" + tag] = C * half + half + (M + 1) ** 2 * b
+        out["row_ifft_" + tag] = half + F * F * b
+        out["interp_" + tag] = F * F * b + nt * (4 + 2 * b) + nt * b
     loc = nt * (6 * 8 + 1 + 2 * b + 8)
     if "V" in kinds:
         loc += nt * 6 * 8
@@ -64,12 +67,14 @@ def algorithmic_bytes(info, P, kinds, b):
     if "S" in kinds:
         loc += nt * 3 * 8
     out["local"] = loc
+    for st in ("spread", "row_fft", "col_fft_mul", "row_ifft", "interp"):
+        out[st] = out[st + "_nh"] + out[st + "_fh"]
     return out
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("vp_kernels.hip", "vp_internal.hpp"):
+    for f in ("vp_device.hpp", "vp_kernels.hip", "vp_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2409_11998_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -102,12 +107,12 @@ def time_steps(torch, fn, steps):
 
 def stage_times(torch, plan, fn, steps):
     plan.set_timing(True)
-    acc = dict.fromkeys(STAGES + ["total"], 0.0)
+    acc = {}
     for _ in range(steps):
         fn()
         t = plan.timing()
-        for k in acc:
-            acc[k] += t[k]
+        for k, v in t.items():
+            acc[k] = acc.get(k, 0.0) + v
     plan.set_timing(False)
     torch.cuda.synchronize()
     return {k: v / steps for k, v in acc.items()}
@@ -164,6 +169,8 @@ def main():
     ap.add_argument("--serve-meshes", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=1500)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / saturated rate")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -192,6 +199,14 @@ def main():
         sys.exit(1)
     import paper_2409_11998_amd
     paper_2409_11998_amd.lib()
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b_ = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b_.copy_(a)
+        torch.cuda.synchronize()
+        del a, b_
     from workloads import config_problem
 
     log("bench: generating square-200k workload")
@@ -202,14 +217,19 @@ def main():
     ms = 1000.0 * r64["elapsed"] / args.steps
     alg = algorithmic_bytes(r64["info"], P, "VD", 8)
     st = r64["stages"]
-    dom = max(STAGES, key=lambda k: st[k])
+    dom = max(LAUNCHES, key=lambda k: st[k])
     achieved = alg[dom] / (st[dom] * 1e-3) / 1e9
     workload = "square-200k-slivers-gaps V+D fp64 tol1e-10"
-    roof = {"bound": "hbm", "kernel": KERNELS[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    lvl = {"nh": 0, "fh": 1}.get(dom.rsplit("_", 1)[-1])
+    kname = KERNELS[dom.rsplit("_", 1)[0] if lvl is not None else dom]
+    if lvl is not None:
+        kname += " (%s level, w=%d, F=%d)" % (("near-history", "far-history")[lvl], r64["info"]["width"][lvl],
+                                             r64["info"]["fine"][lvl])
+    roof = {"bound": "hbm", "kernel": kname, "launch": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profiles(KERNELS[dom], workload),
+            "traffic": traffic_from_profiles(dom, workload),
             "algorithmic_bytes_per_launch": int(alg[dom]), "avg_ms": round(st[dom], 4)}
-    stages_gbs = {k: round(alg[k] / (st[k] * 1e-3) / 1e9, 1) for k in STAGES if st[k] > 0}
+    stages_gbs = {k: round(alg[k] / (st[k] * 1e-3) / 1e9, 1) for k in LAUNCHES if st.get(k, 0) > 0}
     cpu = None
     if args.oracle_sample:
         cpu = {"value": round(r64["oracle_n"] / r64["oracle_s"], 2), "unit": "target pts/s",
@@ -232,12 +252,16 @@ def main():
         r32 = run_leg(torch, Q, "V", 1e-6, 0, args.steps, args.warmup, max(16, args.oracle_sample // 4), seed=30)
         alg32 = algorithmic_bytes(r32["info"], Q, "V", 4)
         st32 = r32["stages"]
+        dom32 = max(LAUNCHES, key=lambda k: st32[k])
         rec["fp32"] = {"workload": "disk-2M V fp32 tol1e-6", "n_tgt": Q.n_tgt,
                        "value": round(Q.n_tgt * args.steps / r32["elapsed"], 1), "unit": "target pts/s",
                        "ms_per_step": round(1000.0 * r32["elapsed"] / args.steps, 4),
                        "fine_grid": list(r32["info"]["fine"]), "spread_width": list(r32["info"]["width"]),
                        "stages_ms": {k: round(v, 4) for k, v in st32.items()},
-                       "stages_gbs": {k: round(alg32[k] / (st32[k] * 1e-3) / 1e9, 1) for k in STAGES if st32[k] > 0},
+                       "stages_gbs": {k: round(alg32[k] / (st32[k] * 1e-3) / 1e9, 1) for k in LAUNCHES
+                                      if st32.get(k, 0) > 0},
+                       "dominant_launch": dom32,
+                       "dominant_frac_of_hbm_peak": round(alg32[dom32] / (st32[dom32] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                        "e_inf_vs_oracle_sample": r32.get("e_inf_sample"), "plan_s": round(r32["plan_s"], 3)}
     if batch_probs:
         log("bench: batch leg, %d instances, %d targets" % (len(batch_probs), sum(P.n_tgt for P in batch_probs)))

@@ -178,13 +178,15 @@ typedef struct {
 /* Fill info (host pointer) with the plan's parameters. */
 vp_status vp_get_plan_info(vp_plan_t plan, vp_plan_info* info);
 
-/* Per-stage device timing of the most recent vp_eval on this plan, measured with
- * HIP events on the plan's stream (milliseconds, host array of 8):
- * [0] strengths, [1] spread, [2] row FFT, [3] column FFT+multiply+inverse,
- * [4] row inverse FFT, [5] interpolation, [6] local part + final sum, [7] total.
- * Enabled by vp_set_timing(plan, 1); synchronizes the stream when read. */
+/* Per-launch device timing of the most recent vp_eval on this plan, measured
+ * with HIP events on the plan's stream (milliseconds, host array of 13):
+ * [0] strengths, [1] spread NH, [2] spread FH, [3] row FFT NH, [4] row FFT FH,
+ * [5] column FFT+multiply+inverse NH, [6] same FH, [7] row inverse FFT NH,
+ * [8] same FH, [9] interpolation NH, [10] interpolation FH, [11] local part and
+ * final sum, [12] total.  Enabled by vp_set_timing(plan, 1); reading it
+ * synchronizes on the last event. */
 vp_status vp_set_timing(vp_plan_t plan, int enable);
-vp_status vp_get_timing(vp_plan_t plan, double* ms8);
+vp_status vp_get_timing(vp_plan_t plan, double* ms13);
 
 /* ------------------------------------------------------------------------
  * Batched evaluation.  Plans of uneven size are executed together: one

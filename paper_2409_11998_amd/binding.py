@@ -247,11 +247,17 @@ class Plan:
     def set_timing(self, on=True):
         _check(lib().vp_set_timing(self.handle, 1 if on else 0))
 
+    LAUNCHES = ["strengths", "spread_nh", "spread_fh", "row_fft_nh", "row_fft_fh", "col_fft_mul_nh",
+                "col_fft_mul_fh", "row_ifft_nh", "row_ifft_fh", "interp_nh", "interp_fh", "local", "total"]
+
     def timing(self):
-        a = (ctypes.c_double * 8)()
+        """Per-launch milliseconds of the last evaluation (see vp_get_timing), plus per-stage sums."""
+        a = (ctypes.c_double * 13)()
         _check(lib().vp_get_timing(self.handle, a))
-        names = ["strengths", "spread", "row_fft", "col_fft_mul", "row_ifft", "interp", "local", "total"]
-        return dict(zip(names, list(a)))
+        d = dict(zip(self.LAUNCHES, list(a)))
+        for st in ("spread", "row_fft", "col_fft_mul", "row_ifft", "interp"):
+            d[st] = d[st + "_nh"] + d[st + "_fh"]
+        return d
 
     def close(self):
         if getattr(self, "handle", None):

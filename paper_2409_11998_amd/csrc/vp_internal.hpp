@@ -15,6 +15,9 @@ constexpr int kWMax = 16;        // largest spreading width (grid cells per dime
 constexpr int kWMin = 4;         // smallest spreading width
 constexpr int kThreads = 256;    // threads per workgroup for grid kernels
 constexpr int kMaxChannels = 3;  // f*w + sigma*wG | mu*nu1*wG | mu*nu2*wG
+// Launches timed by vp_set_timing, in order: strengths; spread NH, FH; row FFT NH,
+// FH; column FFT NH, FH; row inverse NH, FH; interpolation NH, FH; local part.
+constexpr int kTimedLaunches = 12;
 
 template <typename R> struct cplx { R x, y; };
 
@@ -115,7 +118,7 @@ struct Plan {
     size_t device_bytes = 0;
     std::vector<void*> allocs;
     bool timing = false;
-    hipEvent_t ev[8]{};
+    hipEvent_t ev[kTimedLaunches + 1]{};  // before the first and after each timed launch
     bool ev_made = false;
 };
 

@@ -469,23 +469,32 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
         p.ev_made = true;
     }
     auto mark = [&](int k) -> hipError_t { return timing ? hipEventRecord(p.ev[k], st) : hipSuccess; };
-    // stage boundaries: ev[0] before strengths ... ev[7] after local
     VP_HIP(mark(0), "event");
     VP_HIP(launch_zero_dc(p, ws, st), "zero dc");
     VP_HIP(launch_strengths(p, ws, st, f, sigma, mu, C), "strengths");
     VP_HIP(mark(1), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_spread(p, ws, st, l, C, use_v, use_s || use_d), "spread");
-    VP_HIP(mark(2), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_row_fft(p, ws, st, l, C), "row fft");
-    VP_HIP(mark(3), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_col_fft(p, ws, st, l, C), "column fft");
-    VP_HIP(mark(4), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_row_ifft(p, ws, st, l), "row ifft");
-    VP_HIP(mark(5), "event");
-    for (int l = 0; l < 2; ++l) VP_HIP(launch_interp(p, ws, st, l), "interp");
-    VP_HIP(mark(6), "event");
+    for (int l = 0; l < 2; ++l) {
+        VP_HIP(launch_spread(p, ws, st, l, C, use_v, use_s || use_d), "spread");
+        VP_HIP(mark(2 + l), "event");
+    }
+    for (int l = 0; l < 2; ++l) {
+        VP_HIP(launch_row_fft(p, ws, st, l, C), "row fft");
+        VP_HIP(mark(4 + l), "event");
+    }
+    for (int l = 0; l < 2; ++l) {
+        VP_HIP(launch_col_fft(p, ws, st, l, C), "column fft");
+        VP_HIP(mark(6 + l), "event");
+    }
+    for (int l = 0; l < 2; ++l) {
+        VP_HIP(launch_row_ifft(p, ws, st, l), "row ifft");
+        VP_HIP(mark(8 + l), "event");
+    }
+    for (int l = 0; l < 2; ++l) {
+        VP_HIP(launch_interp(p, ws, st, l), "interp");
+        VP_HIP(mark(10 + l), "event");
+    }
     VP_HIP(launch_local(p, ws, st, jet6, sigma_jet3, mu_jet5, use_v, use_s, use_d, out), "local");
-    VP_HIP(mark(7), "event");
+    VP_HIP(mark(12), "event");
     return VP_OK;
 }
 
@@ -843,19 +852,19 @@ vp_status vp_set_timing(vp_plan_t p, int enable)
     return VP_OK;
 }
 
-vp_status vp_get_timing(vp_plan_t p, double* ms8)
+vp_status vp_get_timing(vp_plan_t p, double* ms)
 {
-    if (!p || !ms8) return fail(VP_ERR_ARG, "NULL argument");
+    if (!p || !ms) return fail(VP_ERR_ARG, "NULL argument");
     if (!p->ev_made) return fail(VP_ERR_ARG, "timing was not enabled before the last evaluation");
-    VP_HIP(hipEventSynchronize(p->ev[7]), "event sync");
-    for (int k = 0; k < 7; ++k) {
-        float ms = 0;
-        VP_HIP(hipEventElapsedTime(&ms, p->ev[k], p->ev[k + 1]), "elapsed");
-        ms8[k] = ms;
+    VP_HIP(hipEventSynchronize(p->ev[kTimedLaunches]), "event sync");
+    for (int k = 0; k < kTimedLaunches; ++k) {
+        float t = 0;
+        VP_HIP(hipEventElapsedTime(&t, p->ev[k], p->ev[k + 1]), "elapsed");
+        ms[k] = t;
     }
     float tot = 0;
-    VP_HIP(hipEventElapsedTime(&tot, p->ev[0], p->ev[7]), "elapsed");
-    ms8[7] = tot;
+    VP_HIP(hipEventElapsedTime(&tot, p->ev[0], p->ev[kTimedLaunches]), "elapsed");
+    ms[kTimedLaunches] = tot;
     return VP_OK;
 }
 
