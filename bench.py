@@ -173,8 +173,8 @@ def main():
                     help="first run one device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(instances and requests would be placed one GPU each); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
     # inputs of the batch and serving legs are generated in a process pool before any GPU use
     rng = np.random.default_rng(4)

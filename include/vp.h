@@ -67,7 +67,7 @@ typedef struct {
     double tol;          /* target relative l_inf error of each result (default 1e-10)     */
     int precision;       /* vp_precision (default VP_FP64)                                  */
     double c_delta;      /* delta_1 = c_delta * dx^2, dx^2 = sum(w)/N (Sec. 6; default 3)  */
-    double delta_ratio;  /* delta_2 / delta_1 (Sec. 2.4 uses 32; default 32)               */
+    double delta_ratio;  /* delta_2 / delta_1 (Sec. 2.2 uses 32; default 32)               */
     int order_v;         /* highest power of sqrt(delta) kept in V_L (default 4: delta^2)   */
     int order_s;         /* ... in S_L (default 3: delta^{3/2})                             */
     int order_d;         /* ... in D_L (default 3)                                          */
@@ -91,7 +91,7 @@ void vp_opts_default(vp_opts* opts);
  * arcs); gamma3, gamma4 = third and fourth derivatives of that local graph
  * (may be NULL: taken as 0; needed only by delta^{3/2} and higher layer
  * terms).  All arrays have n_tgt entries.  The closest-point computation is
- * the caller's (the paper treats it as geometry preprocessing, Sec. 2.3). */
+ * the caller's (the paper treats it as geometry preprocessing, Sec. 2.2). */
 typedef struct {
     const double* r;
     const double* nx;
@@ -162,7 +162,7 @@ typedef struct {
     double delta1, delta2, eps_hist;
     double period[2];     /* Fourier period P_NH, P_FH (history grids are P-periodic)        */
     double kmax[2];       /* cutoff wavenumbers                                               */
-    double trunc_L;       /* far-history kernel truncation radius (Sec. 2.2, Vico truncation) */
+    double trunc_L;       /* far-history kernel truncation radius (far-history lemma, Sec. 2)   */
     int modes[2];         /* 2*M+1 Fourier modes per dimension, NH and FH                     */
     int fine[2];          /* fine-grid sizes F_NH, F_FH                                       */
     int width[2];         /* spreading widths                                                 */

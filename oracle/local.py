@@ -27,7 +27,7 @@ import numpy as np
 from scipy.special import erf, erfc
 
 SQPI = np.sqrt(np.pi)
-C_FAR = 12.0   # beyond 12 sqrt(delta) the local layer parts are below 1e-14 (Sec. 2.3)
+C_FAR = 12.0   # beyond 12 sqrt(delta) the local layer parts are below 1e-14 (Sec. 2.2)
 
 
 def _c(r, delta):

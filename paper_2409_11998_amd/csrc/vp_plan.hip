@@ -1,16 +1,16 @@
 // Host planner and C ABI (include/vp.h).
 //
-// The planner turns the paper's parameter choices (Sec. 2.3 and Sec. 3) into
+// The planner turns the paper's parameter choices (Sec. 2.2 and Sec. 3) into
 // a concrete, alias-free discretization of the near- and far-history Fourier
 // integrals:
 //   delta_1 = c_delta * dx^2 (Sec. 6), delta_2 = ratio * delta_1;
 //   k_max from k^p exp(-k^2 delta) < eps (p = 1 when the double layer is
-//   present, Sec. 2.3);
+//   present, Sec. 3, input of the history algorithm);
 //   the trapezoid rule in k with spacing dk = 2 pi / P periodizes the kernel
 //   with period P, so P is chosen from the geometry: P_NH >= E + R (E =
 //   largest extent of nodes and targets, R = reach of the near-history
 //   kernel), and for the far history the kernel is truncated at radius
-//   L = D + R (D = diameter bound) as in the Vico-type truncation of Sec. 2.2,
+//   L = D + R (D = diameter bound) as in the Vico-type truncation of the far-history lemma (Sec. 2),
 //   with P_FH >= E + L + R;
 //   the sums of Step 2 and Step 4 are evaluated by type-1 spreading and
 //   type-2 interpolation on a fine grid F >= sigma * (2M+1) with the
@@ -147,7 +147,7 @@ double mult_nh(double k2, double d1, double d2)
 }
 
 // Far-history multiplier exp(-k^2 d2) W_L(k) with the truncated-kernel transform
-// W_L(k) = (1 - J0(L k))/k^2 - L log L J1(L k)/k (Sec. 2.2, eq. Wdef with radius L);
+// W_L(k) = (1 - J0(L k))/k^2 - L log L J1(L k)/k (far-history lemma of Sec. 2, with radius L);
 // for small L k the Bessel quotients use their Taylor series (limit L^2 (1 - 2 log L)/4).
 double mult_fh(double k2, double d2, double L)
 {
