@@ -123,7 +123,7 @@ def run_leg(torch, P, kinds, tol, precision, steps, warmup, oracle_sample, seed)
     dev = to_device(P)
     mask = (1 if "V" in kinds else 0) | (2 if "S" in kinds else 0) | (4 if "D" in kinds else 0)
     t0 = time.perf_counter()
-    plan = make_plan(dev, tol=tol, precision=precision, kinds=mask)
+    plan = make_plan(dev, tol=tol, precision=precision, kinds=mask, autotune=True)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = plan.info()
@@ -241,7 +241,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": workload, "n_src": P.n_src, "n_bnd": P.n_bnd, "n_tgt": P.n_tgt,
                       "fine_grid": list(r64["info"]["fine"]), "modes": list(r64["info"]["modes"]),
-                      "spread_width": list(r64["info"]["width"]), "tol": 1e-10},
+                      "spread_width": list(r64["info"]["width"]), "tile": r64["info"]["tile"],
+                      "autotuned": r64["info"]["autotuned"], "tol": 1e-10},
            "roofline": roof, "cpu_baseline": cpu,
            "stages_ms": {k: round(v, 4) for k, v in st.items()}, "stages_gbs": stages_gbs,
            "plan_s": round(r64["plan_s"], 3), "e_inf_vs_oracle_sample": r64.get("e_inf_sample")}
@@ -257,6 +258,7 @@ def main():
                        "value": round(Q.n_tgt * args.steps / r32["elapsed"], 1), "unit": "target pts/s",
                        "ms_per_step": round(1000.0 * r32["elapsed"] / args.steps, 4),
                        "fine_grid": list(r32["info"]["fine"]), "spread_width": list(r32["info"]["width"]),
+                       "tile": r32["info"]["tile"],
                        "stages_ms": {k: round(v, 4) for k, v in st32.items()},
                        "stages_gbs": {k: round(alg32[k] / (st32[k] * 1e-3) / 1e9, 1) for k in LAUNCHES
                                       if st32.get(k, 0) > 0},

@@ -79,6 +79,12 @@ typedef struct {
     int no_workspace;    /* 1: keep only the plan's resident data (sorted nodes, tables, geometry);
                             every evaluation then takes a stream-ordered workspace (grids,
                             spectra, strengths) -- the form the serving loop uses (default 0) */
+    int autotune;        /* 1: choose each level's fine grid, spreading width and tile edge by
+                            timing that level's kernels (spread, FFTs, interpolation) on the
+                            device for every candidate that meets the tolerance, instead of the
+                            static cost model; plan creation then runs kernels on the stream
+                            and takes longer (default 0).  Forced fine_grid / spread_width /
+                            tile values restrict the candidates.                              */
 } vp_opts;
 
 /* Fill opts with the defaults listed above. opts: host pointer. */
@@ -169,10 +175,13 @@ typedef struct {
     int tile;             /* tile edge in grid cells                                          */
     int precision;
     int64_t n_src, n_bnd, n_tgt;
-    int64_t spread_records[2];  /* (node, tile) pairs per level                              */
+    int64_t spread_records[2];  /* spread records per level (one per node)                   */
     size_t device_bytes;  /* device memory held by the plan                                   */
     size_t workspace_bytes; /* device memory one evaluation writes (the plan's own workspace, or
                                the stream-ordered one of a plan created with no_workspace)     */
+    int autotuned;        /* 1 if the levels were chosen by measurement (opts.autotune)      */
+    int tune_candidates[2]; /* candidates timed per level (0 without autotune)               */
+    double level_ms[2];   /* measured time of the chosen candidate's level kernels (ms)      */
 } vp_plan_info;
 
 /* Fill info (host pointer) with the plan's parameters. */

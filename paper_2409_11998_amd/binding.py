@@ -35,7 +35,7 @@ class VPOpts(ctypes.Structure):
                 ("delta_ratio", ctypes.c_double), ("order_v", ctypes.c_int), ("order_s", ctypes.c_int),
                 ("order_d", ctypes.c_int), ("kinds", ctypes.c_int), ("fine_grid", ctypes.c_int * 2),
                 ("spread_width", ctypes.c_int * 2), ("tile", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("no_workspace", ctypes.c_int)]
+                ("no_workspace", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class VPLocalGeom(ctypes.Structure):
@@ -74,7 +74,8 @@ class VPPlanInfo(ctypes.Structure):
                 ("modes", ctypes.c_int * 2), ("fine", ctypes.c_int * 2), ("width", ctypes.c_int * 2),
                 ("tile", ctypes.c_int), ("precision", ctypes.c_int), ("n_src", ctypes.c_int64),
                 ("n_bnd", ctypes.c_int64), ("n_tgt", ctypes.c_int64), ("spread_records", ctypes.c_int64 * 2),
-                ("device_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t)]
+                ("device_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+                ("autotuned", ctypes.c_int), ("tune_candidates", ctypes.c_int * 2), ("level_ms", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -170,7 +171,7 @@ class Plan:
     def __init__(self, src_x, src_y, src_w, bnd_x=None, bnd_y=None, bnd_nx=None, bnd_ny=None, bnd_w=None,
                  tgt_x=None, tgt_y=None, geom=None, tol=1e-10, precision=VP_FP64, kinds=7, stream=None,
                  c_delta=3.0, delta_ratio=32.0, order_v=4, order_s=3, order_d=3, fine_grid=(0, 0),
-                 spread_width=(0, 0), tile=0, no_workspace=False):
+                 spread_width=(0, 0), tile=0, no_workspace=False, autotune=False):
         import torch
         f64 = torch.float64
         o = default_opts()
@@ -184,6 +185,7 @@ class Plan:
         o.spread_width[0], o.spread_width[1] = spread_width
         o.tile = tile
         o.no_workspace = 1 if no_workspace else 0
+        o.autotune = 1 if autotune else 0
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -242,7 +244,8 @@ class Plan:
                     kmax=tuple(i.kmax), trunc_L=i.trunc_L, modes=tuple(i.modes), fine=tuple(i.fine),
                     width=tuple(i.width), tile=i.tile, precision=i.precision, n_src=i.n_src, n_bnd=i.n_bnd,
                     n_tgt=i.n_tgt, spread_records=tuple(i.spread_records), device_bytes=i.device_bytes,
-                    workspace_bytes=i.workspace_bytes)
+                    workspace_bytes=i.workspace_bytes, autotuned=bool(i.autotuned),
+                    tune_candidates=tuple(i.tune_candidates), level_ms=tuple(i.level_ms))
 
     def set_timing(self, on=True):
         _check(lib().vp_set_timing(self.handle, 1 if on else 0))

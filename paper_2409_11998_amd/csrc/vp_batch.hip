@@ -39,11 +39,12 @@ struct LevelDesc {
     const int* tgt_start; const int* tgt_ij; const void* tgt_dx; const void* tgt_dy; const int* tgt_idx;
     void* grid;
     void* spec;
-    void* spec2;
     const void* mult;
     const void* tw;
     void* hist;
     const double* horner;
+    const WorkUnit* sp_units;
+    const WorkUnit* in_units;
 };
 
 struct InstDesc {
@@ -85,24 +86,39 @@ __global__ void kb_zero_dc(const InstDesc* __restrict__ inst, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) *inst[i].dc = 0.0;
 }
 
+constexpr int kZeroChunk = kThreads * 64;  // grid cells per zeroing work unit
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void kb_zero(const LevelDesc* __restrict__ lv, const Item* __restrict__ items,
+                                                    int n_items)
+{
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item x = items[it];
+        const LevelDesc& D = lv[2 * x.inst + x.level];
+        const int64_t n = (int64_t)D.g.F * D.g.F;
+        const int64_t i0 = (int64_t)x.unit * kZeroChunk;
+        for (int64_t i = i0 + threadIdx.x; i < i0 + kZeroChunk; i += blockDim.x) dev::dev_zero<R>((R*)D.grid, n, i);
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void kb_strengths(const InstDesc* __restrict__ inst,
                                                          const CallDesc* __restrict__ call,
-                                                         const Item* __restrict__ items, int n_items, int C)
+                                                         const Item* __restrict__ items, int n_items)
 {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item x = items[it];
         const InstDesc& I = inst[x.inst];
         const CallDesc& K = call[x.inst];
-        dev::dev_strengths<R>(I.n_src, I.n_bnd, K.f, K.sigma, K.mu, I.w, I.nx, I.ny, (R*)I.str, C, I.dc, x.unit);
+        dev::dev_strengths<R>(I.n_src, I.n_bnd, K.f, K.sigma, K.mu, I.w, I.nx, I.ny, (R*)I.str, I.dc, x.unit);
     }
 }
 
-template <typename R, int W, int C>
+template <typename R, int W>
 __global__ __launch_bounds__(kThreads) void kb_spread(const InstDesc* __restrict__ inst,
                                                       const LevelDesc* __restrict__ lv,
                                                       const Item* __restrict__ items, int n_items, int use_vol,
-                                                      int use_bnd)
+                                                      int use_bnd, int use_d)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -110,8 +126,9 @@ __global__ __launch_bounds__(kThreads) void kb_spread(const InstDesc* __restrict
         const InstDesc& I = inst[x.inst];
         const LevelDesc& D = lv[2 * x.inst + x.level];
         const LevelGeom g = D.g;
-        dev::dev_spread<R, W, C>(smem_raw, g, vol_view<R>(D), bnd_view<R>(D), (const R*)I.str, I.n_src + I.n_bnd,
-                                 (R*)D.grid, use_vol && I.has_vol, use_bnd && I.has_bnd, D.horner, x.unit);
+        dev::dev_spread<R, W>(smem_raw, g, vol_view<R>(D), bnd_view<R>(D), (const R*)I.str, I.n_src, I.n_bnd,
+                              (R*)D.grid, use_vol && I.has_vol, use_bnd && I.has_bnd, use_d, D.horner,
+                              D.sp_units[x.unit]);
         __syncthreads();
     }
 }
@@ -130,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void kb_row_r2c(const LevelDesc* __restri
     }
 }
 
-template <typename R, int C>
+template <typename R>
 __global__ __launch_bounds__(kThreads) void kb_col(const LevelDesc* __restrict__ lv, const Item* __restrict__ items,
                                                    int n_items, int zero_dc)
 {
@@ -139,8 +156,7 @@ __global__ __launch_bounds__(kThreads) void kb_col(const LevelDesc* __restrict__
         const Item x = items[it];
         const LevelDesc& D = lv[2 * x.inst + x.level];
         const LevelGeom g = D.g;
-        dev::dev_col<R, C>(smem_raw, g, (const cplx<R>*)D.spec, (const R*)D.mult, (const cplx<R>*)D.tw,
-                           (cplx<R>*)D.spec2, zero_dc, x.unit);
+        dev::dev_col<R>(smem_raw, g, (cplx<R>*)D.spec, (const R*)D.mult, (const cplx<R>*)D.tw, zero_dc, x.unit);
         __syncthreads();
     }
 }
@@ -154,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void kb_row_c2r(const LevelDesc* __restri
         const Item x = items[it];
         const LevelDesc& D = lv[2 * x.inst + x.level];
         const LevelGeom g = D.g;
-        dev::dev_row_c2r<R>(smem_raw, g, (const cplx<R>*)D.spec2, (const cplx<R>*)D.tw, (R*)D.grid, x.unit);
+        dev::dev_row_c2r<R>(smem_raw, g, (const cplx<R>*)D.spec, (const cplx<R>*)D.tw, (R*)D.grid, x.unit);
         __syncthreads();
     }
 }
@@ -168,7 +184,8 @@ __global__ __launch_bounds__(kThreads) void kb_interp(const LevelDesc* __restric
         const Item x = items[it];
         const LevelDesc& D = lv[2 * x.inst + x.level];
         const LevelGeom g = D.g;
-        dev::dev_interp<R, W>(smem_raw, g, (const R*)D.grid, tgt_view<R>(D), (R*)D.hist, D.horner, x.unit);
+        dev::dev_interp<R, W>(smem_raw, g, (const R*)D.grid, tgt_view<R>(D), (R*)D.hist, D.horner,
+                              D.in_units[x.unit]);
         __syncthreads();
     }
 }
@@ -196,13 +213,16 @@ __global__ __launch_bounds__(kThreads) void kb_local(const InstDesc* __restrict_
 
 using namespace vp;
 
+// Stages of one batched evaluation (one persistent launch each, per level for
+// the width-templated ones).
+enum { ST_ZERO = 0, ST_STR, ST_SPREAD0, ST_SPREAD1, ST_ROW, ST_COL, ST_C2R, ST_INTERP0, ST_INTERP1, ST_LOCAL, ST_N };
+
 // One group of plans executed together.
 struct vp_batch_s {
     std::vector<vp_plan_t> plans;
     int n = 0;
     int precision = VP_FP64;
     int kinds = 0;  // densities every call passes (VP_KIND_*)
-    int C = 1;
     int w[2] = {0, 0};
     hipStream_t stream = nullptr;
     InstDesc* d_inst = nullptr;
@@ -210,8 +230,8 @@ struct vp_batch_s {
     CallDesc* d_call = nullptr;
     std::vector<CallDesc> h_call;  // host copy of the per-call table (pageable: reusable once copied)
     Item* d_items = nullptr;
-    int off[10] = {0};   // stage offsets into d_items
-    int cnt[10] = {0};   // stage item counts
+    int off[ST_N] = {0};   // stage offsets into d_items
+    int cnt[ST_N] = {0};   // stage item counts
     size_t lds_spread[2] = {0, 0}, lds_interp[2] = {0, 0}, lds_row = 0, lds_col = 0;
     int cus = 256;
     hipGraph_t graph = nullptr;
@@ -221,7 +241,6 @@ struct vp_batch_s {
 
 namespace {
 
-enum { ST_STR = 0, ST_SPREAD0, ST_SPREAD1, ST_ROW, ST_COL, ST_C2R, ST_INTERP0, ST_INTERP1, ST_LOCAL, ST_N };
 
 vp_status bfail(vp_status s, const std::string& m)
 {
@@ -249,29 +268,22 @@ template <typename R>
 hipError_t launch_all(vp_batch_s& b, int use_v, int use_s, int use_d)
 {
     hipStream_t st = b.stream;
-    const int C = b.C;
     hipLaunchKernelGGL(kb_zero_dc, dim3(std::max(1, (b.n + 255) / 256)), dim3(256), 0, st, b.d_inst, b.n);
     const Item* it = b.d_items;
+    hipLaunchKernelGGL(kb_zero<R>, dim3(persistent_grid(b, b.cnt[ST_ZERO], 8)), dim3(kThreads), 0, st, b.d_lv,
+                       it + b.off[ST_ZERO], b.cnt[ST_ZERO]);
     hipLaunchKernelGGL(kb_strengths<R>, dim3(persistent_grid(b, b.cnt[ST_STR], 8)), dim3(kThreads), 0, st, b.d_inst,
-                       b.d_call, it + b.off[ST_STR], b.cnt[ST_STR], C);
+                       b.d_call, it + b.off[ST_STR], b.cnt[ST_STR]);
     for (int l = 0; l < 2; ++l) {
         const int s = l ? ST_SPREAD1 : ST_SPREAD0;
         if (!b.cnt[s]) continue;
         const size_t lds = b.lds_spread[l];
         switch (b.w[l]) {
-#define VP_CASE(W)                                                                                                \
-    case W:                                                                                                       \
-        if (C == 1) {                                                                                             \
-            hipFuncSetAttribute((const void*)kb_spread<R, W, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,      \
-                                (int)lds);                                                                        \
-            hipLaunchKernelGGL((kb_spread<R, W, 1>), dim3(persistent_grid(b, b.cnt[s], 4)), dim3(kThreads), lds,  \
-                               st, b.d_inst, b.d_lv, it + b.off[s], b.cnt[s], use_v, use_s || use_d);             \
-        } else {                                                                                                  \
-            hipFuncSetAttribute((const void*)kb_spread<R, W, 3>, hipFuncAttributeMaxDynamicSharedMemorySize,      \
-                                (int)lds);                                                                        \
-            hipLaunchKernelGGL((kb_spread<R, W, 3>), dim3(persistent_grid(b, b.cnt[s], 4)), dim3(kThreads), lds,  \
-                               st, b.d_inst, b.d_lv, it + b.off[s], b.cnt[s], use_v, use_s || use_d);             \
-        }                                                                                                         \
+#define VP_CASE(W)                                                                                               \
+    case W:                                                                                                      \
+        hipFuncSetAttribute((const void*)kb_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL((kb_spread<R, W>), dim3(persistent_grid(b, b.cnt[s], 4)), dim3(kThreads), lds, st,   \
+                           b.d_inst, b.d_lv, it + b.off[s], b.cnt[s], use_v, use_s || use_d, use_d);            \
         break;
             VP_W_CASES(VP_CASE)
 #undef VP_CASE
@@ -282,12 +294,8 @@ hipError_t launch_all(vp_batch_s& b, int use_v, int use_s, int use_d)
     hipLaunchKernelGGL(kb_row_r2c<R>, dim3(persistent_grid(b, b.cnt[ST_ROW], 8)), dim3(kThreads), b.lds_row, st,
                        b.d_lv, it + b.off[ST_ROW], b.cnt[ST_ROW]);
     const int zero_dc = b.precision == VP_FP32 ? 1 : 0;
-    if (C == 1)
-        hipLaunchKernelGGL((kb_col<R, 1>), dim3(persistent_grid(b, b.cnt[ST_COL], 4)), dim3(kThreads), b.lds_col,
-                           st, b.d_lv, it + b.off[ST_COL], b.cnt[ST_COL], zero_dc);
-    else
-        hipLaunchKernelGGL((kb_col<R, 3>), dim3(persistent_grid(b, b.cnt[ST_COL], 4)), dim3(kThreads), b.lds_col,
-                           st, b.d_lv, it + b.off[ST_COL], b.cnt[ST_COL], zero_dc);
+    hipLaunchKernelGGL((kb_col<R>), dim3(persistent_grid(b, b.cnt[ST_COL], 4)), dim3(kThreads), b.lds_col, st,
+                       b.d_lv, it + b.off[ST_COL], b.cnt[ST_COL], zero_dc);
     hipLaunchKernelGGL(kb_row_c2r<R>, dim3(persistent_grid(b, b.cnt[ST_C2R], 8)), dim3(kThreads), b.lds_row, st,
                        b.d_lv, it + b.off[ST_C2R], b.cnt[ST_C2R]);
     for (int l = 0; l < 2; ++l) {
@@ -342,7 +350,6 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
     b->plans.assign(plans, plans + n);
     b->n = n;
     b->kinds = kinds;
-    b->C = (kinds & VP_KIND_D) ? 3 : 1;
     b->stream = (hipStream_t)stream;
     auto bail = [&](vp_status s) {
         free_batch(b);
@@ -358,7 +365,6 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
         }
         if (p.precision != b->precision) return bail(bfail(VP_ERR_ARG, "plans differ in precision"));
         if (!p.ws.block) return bail(bfail(VP_ERR_ARG, "batched plans need their own workspace"));
-        if (b->C > p.cmax) return bail(bfail(VP_ERR_ARG, "a plan's workspace lacks the double-layer channels"));
         if (p.lv[0].w != b->w[0] || p.lv[1].w != b->w[1])
             return bail(bfail(VP_ERR_ARG, "plans differ in spreading width (use one width per level per batch)"));
         if ((kinds & VP_KIND_V) && !(p.kinds & VP_KIND_V)) return bail(bfail(VP_ERR_ARG, "a plan lacks V"));
@@ -433,29 +439,30 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
             D.tgt_idx = lb.tgt.idx;
             D.grid = p.ws.grid[l];
             D.spec = p.ws.spec[l];
-            D.spec2 = p.ws.spec2[l];
             D.mult = lb.mult;
             D.tw = lb.tw;
             D.hist = p.ws.hist[l];
             D.horner = lb.horner;
-            // tile record counts for cost-sorted spreading items
-            const int ntiles = g.ntx * g.ntx;
-            std::vector<int> vs(ntiles + 1, 0), bs(ntiles + 1, 0), ts(ntiles + 1, 0);
-            if (lb.vol.start) hipMemcpy(vs.data(), lb.vol.start, (ntiles + 1) * sizeof(int), hipMemcpyDeviceToHost);
-            if (lb.bnd.start) hipMemcpy(bs.data(), lb.bnd.start, (ntiles + 1) * sizeof(int), hipMemcpyDeviceToHost);
-            if (lb.tgt.start) hipMemcpy(ts.data(), lb.tgt.start, (ntiles + 1) * sizeof(int), hipMemcpyDeviceToHost);
+            D.sp_units = lb.sp_units;
+            D.in_units = lb.in_units;
+            // cost-sorted spreading and interpolation items: one per work unit
             const int ss = l ? ST_SPREAD1 : ST_SPREAD0;
             const int si = l ? ST_INTERP1 : ST_INTERP0;
-            for (int t = 0; t < ntiles; ++t) {
-                st[ss].push_back({i, l, t});
-                cost[ss].push_back(1.0 + (double)(vs[t + 1] - vs[t]) + 3.0 * (bs[t + 1] - bs[t]));
-                const int nt = ts[t + 1] - ts[t];
-                if (nt) {  // interpolation tiles without targets do nothing
-                    st[si].push_back({i, l, t});
-                    cost[si].push_back(1.0 + nt);
-                }
+            for (size_t k = 0; k < lb.h_sp_units.size(); ++k) {
+                const WorkUnit& u = lb.h_sp_units[k];
+                st[ss].push_back({i, l, (int)k});
+                cost[ss].push_back(1.0 + (double)(u.a1 - u.a0) + 4.0 * (u.b1 - u.b0));
             }
-            for (int r = 0; r < g.F * b->C; ++r) {
+            for (size_t k = 0; k < lb.h_in_units.size(); ++k) {
+                const WorkUnit& u = lb.h_in_units[k];
+                st[si].push_back({i, l, (int)k});
+                cost[si].push_back(1.0 + (double)(u.a1 - u.a0));
+            }
+            for (int64_t u = 0; u * kZeroChunk < (int64_t)g.F * g.F; ++u) {
+                st[ST_ZERO].push_back({i, l, (int)u});
+                cost[ST_ZERO].push_back(1.0);
+            }
+            for (int r = 0; r < g.F; ++r) {
                 st[ST_ROW].push_back({i, l, r});
                 cost[ST_ROW].push_back((double)g.F);
             }
@@ -469,9 +476,8 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
             }
             lds_row = std::max(lds_row, (size_t)(g.F / 2) * 2 * rb);
             lds_col = std::max(lds_col, (size_t)g.F * 2 * rb);
-            lds_sp[l] = std::max(lds_sp[l], spread_lds_bytes(p, l, b->C, true));
-            const int E = g.T + g.w - 1;
-            lds_in[l] = std::max(lds_in[l], (size_t)E * E * rb);
+            lds_sp[l] = std::max(lds_sp[l], spread_lds_bytes(p, l));
+            lds_in[l] = std::max(lds_in[l], dev::interp_lds_bytes(g.T, g.w, rb));
         }
     }
     if (lds_row > 160 * 1024 || lds_col > 160 * 1024) return bail(bfail(VP_ERR_TOL, "FFT too long for LDS"));

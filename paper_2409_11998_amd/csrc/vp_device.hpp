@@ -6,10 +6,11 @@
 // Data flow of one evaluation (history part, Sec. 3 Steps 1-4; local part,
 // Sec. 4), per level (near history NH, far history FH):
 //
-//   strengths  c_j (per node, channel)          k_strengths
-//   spread     b[g] = sum_j c_j phi(g - t_j)     k_spread     (tile-owned LDS accumulation)
+//   strengths  c_j per node (and mu nu wG)       k_strengths
+//   spread     b[g] = sum_j c_j phi(g - t_j)     k_spread     (LDS tile windows, global atomics)
+//              + mu_j nu_j . grad_y phi(g - t_j)
 //   row FFT    along x, real -> half spectrum    k_row_r2c    (keeps |m1| <= M only)
-//   column     along y: FFT, multiply by         k_col        (channels combined: B0 - i k.B12)
+//   column     along y: FFT, multiply by         k_col        (in place)
 //              (dk/2pi)^2 M(k)/phihat^2, IFFT
 //   row IFFT   half spectrum -> real              k_row_c2r
 //   interp     u(x_i) = sum_g a[g] phi(t_i - g)  k_interp     (tile grid staged in LDS)
@@ -20,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "vp_internal.hpp"
 
@@ -46,6 +48,20 @@ __device__ __forceinline__ void kernel_taps(double d, const double* __restrict__
         for (int k = P - 2; k >= 0; --k) acc = fma(acc, u, coef[a * P + k]);
         out[a] = acc;
     }
+}
+
+// XCD-aware unit order.  Workgroups are dealt round-robin to the 8 XCDs
+// (each with its own L2), so consecutive block indices land on different
+// XCDs.  Giving each XCD a contiguous range of units (rows, columns, tiles)
+// keeps neighbouring units -- which share cache lines of the strided spectrum
+// and the tiles' overlapping windows -- in one L2.  Identity when n is not a
+// multiple of 8.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_unit(int b, int n)
+{
+    if (n % kXcds) return b;
+    return (b % kXcds) * (n / kXcds) + b / kXcds;
 }
 
 __device__ __forceinline__ int bitrev(int k, int logn)
@@ -80,24 +96,53 @@ __device__ void lds_fft(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw, in
     }
 }
 
+// In-place radix-2 decimation-in-frequency FFT: input in natural order, output
+// in bit-reversed order (same twiddle convention as lds_fft).  Ends with a
+// barrier.
+template <typename R>
+__device__ void lds_fft_dif(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw, int tw_stride, bool inverse)
+{
+    const int n = 1 << logn;
+    for (int s = logn; s >= 1; --s) {
+        const int half = 1 << (s - 1);
+        const int step = (n >> s) * tw_stride;
+        for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
+            const int pos = b & (half - 1);
+            const int i = ((b >> (s - 1)) << s) + pos;
+            const int j = i + half;
+            cplx<R> wv = tw[pos * step];
+            if (inverse) wv.y = -wv.y;
+            const cplx<R> u = a[i];
+            const cplx<R> v = a[j];
+            const R dx = u.x - v.x, dy = u.y - v.y;
+            a[i] = {u.x + v.x, u.y + v.y};
+            a[j] = {dx * wv.x - dy * wv.y, dx * wv.y + dy * wv.x};
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Strengths per node and channel (the sums of Sec. 3, Step 2):
-//   ch0 = f w (volume) + sigma wG (boundary), ch1 = mu nu1 wG, ch2 = mu nu2 wG.
-// Also accumulates sum(ch0) in float64 (the zero-frequency term).
+// Strengths per node (the sums of Sec. 3, Step 2):
+//   str[i]               = f w (volume node) or sigma wG (boundary node),
+//   str[n + j]           = mu nu1 wG,   str[n + nb + j] = mu nu2 wG
+// for boundary node j (n = all nodes, nb = boundary nodes; present only when
+// mu is given).  Also accumulates sum(str[0..n)) in float64 (the
+// zero-frequency term).
 constexpr int kStrChunk = kThreads * 8;  // nodes per strengths work unit
 
 template <typename R>
 __device__ void dev_strengths(int64_t n_src, int64_t n_bnd, const double* __restrict__ f,
                               const double* __restrict__ sigma, const double* __restrict__ mu,
                               const double* __restrict__ w, const double* __restrict__ nx,
-                              const double* __restrict__ ny, R* __restrict__ str, int C,
-                              double* __restrict__ dc, int64_t unit)
+                              const double* __restrict__ ny, R* __restrict__ str, double* __restrict__ dc,
+                              int64_t unit)
 {
     const int64_t n = n_src + n_bnd;
     double part = 0.0;
     const int64_t i1 = min(n, (unit + 1) * (int64_t)kStrChunk);
     for (int64_t i = unit * (int64_t)kStrChunk + threadIdx.x; i < i1; i += blockDim.x) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        double s0 = 0.0;
         if (i < n_src) {
             if (f) s0 = f[i] * w[i];
         } else {
@@ -106,15 +151,11 @@ __device__ void dev_strengths(int64_t n_src, int64_t n_bnd, const double* __rest
             if (sigma) s0 = sigma[j] * wg;
             if (mu) {
                 const double m = mu[j] * wg;
-                s1 = m * nx[j];
-                s2 = m * ny[j];
+                str[n + j] = (R)(m * nx[j]);
+                str[n + n_bnd + j] = (R)(m * ny[j]);
             }
         }
         str[i] = (R)s0;
-        if (C == 3) {
-            str[n + i] = (R)s1;
-            str[2 * n + i] = (R)s2;
-        }
         part += s0;
     }
     // wave reduction, then one float64 atomic per wave
@@ -122,183 +163,280 @@ __device__ void dev_strengths(int64_t n_src, int64_t n_bnd, const double* __rest
     if ((threadIdx.x & 63) == 0 && part != 0.0) atomicAdd(dc, part);
 }
 
-
-// ---------------------------------------------------------------------------
-// Spread (type-1 spreading, Sec. 3 Step 2 via the NUFFT): one workgroup owns a
-// T x T tile of the fine grid and writes it once (no global atomics, no
-// zero-fill pass).  A node's support starts at grid index i0 = ceil(t - w/2);
-// its offset is stored as d = i0 - t + w/2 in [0, 1).
-//
-// The tile accumulates in LDS with float64 atomic adds in both precisions:
-// on gfx950 a 64-lane ds_add_f32 costs ~190 cycles per CU against ~8.5 for
-// ds_add_f64 (measured), so float32 plans form their products in float32 and
-// round the tile to float32 once, when it is written to the grid.
-//
-// Single-channel records (volume nodes; boundary nodes when only sigma is
-// spread): each wavefront stages a chunk of its records in LDS (the next
-// chunk's loads are in flight meanwhile), computes their 2w kernel values
-// with one (record, value) pair per lane, then walks the records one at a
-// time with lanes mapped to taps: the 64 lanes of one no-return atomic touch
-// 64 distinct cells of a w x w patch.  Double-layer boundary records (three
-// strengths, few nodes) use one lane per record.
-template <typename R> struct SpreadShape {
-    static constexpr int kWaves = kThreads / 64;
-    static constexpr int kRecs = 32;            // records staged per wave chunk (2 lanes each)
-    static constexpr int kVals = 2 * kWMax;     // staged kernel values per record
-};
-
-// Dynamic LDS layout of k_spread (bytes): C padded float64 tiles | per-wave staging.
-__host__ __device__ inline size_t spread_lds_layout(int T, int C, size_t rb, int waves, int recs, int vals,
-                                                    size_t* off_stage)
+// Zero fill of a spread grid (the spread accumulates into it with atomics).
+template <typename R>
+__device__ void dev_zero(R* __restrict__ p, int64_t n, int64_t i)
 {
-    const size_t tiles = (size_t)C * T * (T + 1) * sizeof(double);
-    const size_t stage = (size_t)waves * recs * ((vals + 3) * rb + sizeof(int));
-    *off_stage = tiles;
-    return tiles + stage;
+    if (i < n) p[i] = R(0);
 }
 
-template <typename R, int W, int C>
+// ---------------------------------------------------------------------------
+// Spread (type-1 spreading, Sec. 3 Step 2 via the NUFFT).
+//
+// Every node is assigned to the T x T tile holding its support corner
+// i0 = ceil(t - w/2) (its offset is stored as d = i0 - t + w/2 in [0, 1)), so
+// its whole w x w support lies inside the tile's extended window of
+// (T+w-1)^2 cells.  One workgroup accumulates a tile's window in LDS and adds
+// the window to the grid with global atomics (the grid is zeroed first); the
+// windows of neighbouring tiles overlap by w-1 cells.
+//
+// The window accumulates with float64 LDS atomics in both precisions: on
+// gfx950 a 64-lane ds_add_f32 costs ~190 cycles per CU against ~8.5 for
+// ds_add_f64 (measured), so float32 plans form their products in float32 and
+// round the window to float32 once, when it is added to the grid.
+//
+// Single-strength nodes (volume nodes, and boundary nodes without a double
+// layer): each wavefront takes chunks of 32 of the tile's nodes; lane pairs
+// evaluate the kernel values of one node (x taps and y taps) into LDS, then
+// the wavefront walks the chunk node by node with the 64 lanes mapped to taps
+// (lane -> column a = lane % w, rows b = lane / w + k (64 / w)).  The next
+// node's values are read before the current node's atomics are issued, and
+// the node's corner and strength come from registers (readlane), so the loop
+// keeps several LDS operations in flight.
+//
+// Double layer (Sec. 3, Step 2; Sec. 2.1): the transform factor -i k of the
+// double-layer kernel is applied in space, by spreading mu nu . grad_y phi
+// (the gradient of the spreading kernel in the source position) into the same
+// grid: its Fourier transform is phihat(k) (-i k . nu mu) exp(-i k.y), which
+// is exactly the double-layer term of the combined spectrum.  These boundary
+// nodes take the same wavefront path with the tap derivatives staged beside
+// the tap values.
+template <typename R> struct SpreadShape {
+    static constexpr int kWaves = kThreads / 64;
+    // nodes per wavefront chunk (half as many double-layer nodes, which stage
+    // twice the values); sized so that four workgroups fit in LDS
+    static constexpr int kRecs = sizeof(R) == 4 ? 32 : 16;
+};
+
+__host__ __device__ inline int spread_pitch(int T, int W)
+{
+    const int E = T + W - 1;
+    return E | 1;  // odd pitch: consecutive rows start in different LDS banks
+}
+
+// Dynamic LDS layout of the spread (bytes): float64 window | per wave: kernel
+// values of a chunk (2 w per node; 4 w per double-layer node: x, y taps and
+// their derivatives) and the chunk's offsets.
+__host__ __device__ inline size_t spread_lds_layout(int T, int W, size_t rb, size_t* off_stage)
+{
+    const int E = T + W - 1;
+    const size_t win = ((size_t)E * spread_pitch(T, W) * sizeof(double) + 15) & ~(size_t)15;
+    const int recs = rb == 4 ? SpreadShape<float>::kRecs : SpreadShape<double>::kRecs;
+    const size_t stage = (size_t)SpreadShape<float>::kWaves * (recs * 2 * W + 2 * recs) * rb;
+    *off_stage = win;
+    return win + stage;
+}
+
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int lane)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+    } else {
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __builtin_bit_cast(T, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    }
+}
+
+// Horner evaluation of one tap's polynomial and its derivative in u.
+template <int P>
+__device__ __forceinline__ void tap_value_deriv(const double* __restrict__ c, double u, double& v, double& dv)
+{
+    double p = c[P - 1], dp = 0.0;
+#pragma unroll
+    for (int k = P - 2; k >= 0; --k) {
+        dp = fma(dp, u, p);
+        p = fma(p, u, c[k]);
+    }
+    v = p;
+    dv = dp;
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename R, int W>
 __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const RecView<R>& vol, const RecView<R>& bnd,
-                           const R* __restrict__ str, int64_t nstr, R* __restrict__ grid, int use_vol, int use_bnd,
-                           const double* __restrict__ coef, int t)
+                           const R* __restrict__ str, int64_t n_src, int64_t n_bnd, R* __restrict__ grid,
+                           int use_vol, int use_bnd, int use_d, const double* __restrict__ coef, const WorkUnit unit)
 {
     using SS = SpreadShape<R>;
     constexpr int NW = SS::kWaves;
     constexpr int RECS = SS::kRecs;
-    constexpr int VS = SS::kVals;
-    constexpr int WW = W * W;
-    constexpr int NTAP = (WW + 63) / 64;
+    constexpr int VST = RECS * 2 * W;     // staged values per wave chunk
+    constexpr int RW = 64 / W;            // tap rows per atomic instruction
+    constexpr int NI = (W + RW - 1) / RW; // atomic instructions per node
+    constexpr int P = W + 2;
+    constexpr int G = 64 / W;             // offset groups of the kernel-value evaluation
     const int T = g.T;
-    const int TP = T + 1;
-    const int TS = T * TP;
+    const int E = T + W - 1;
+    const int EP = spread_pitch(T, W);
+    const int t = unit.tile;
+    const int nv = use_vol ? unit.a1 - unit.a0 : 0;
+    const int nbd = use_bnd ? unit.b1 - unit.b0 : 0;
+    if (nv == 0 && nbd == 0) return;  // nothing lands in this unit (uniform across the workgroup)
     size_t off_st;
-    spread_lds_layout(T, C, sizeof(R), NW, RECS, VS, &off_st);
-    double* tile = reinterpret_cast<double*>(smem_raw);
+    spread_lds_layout(T, W, sizeof(R), &off_st);
+    double* win = reinterpret_cast<double*>(smem_raw);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    R* stage = reinterpret_cast<R*>(smem_raw + off_st);
-    R* vals = stage + (size_t)wv * RECS * (VS + 3);  // [RECS][VS] kernel values (x taps, then y taps)
-    R* my_s = vals + RECS * VS;                     // [RECS] strengths
-    R* my_d = my_s + RECS;                          // [RECS][2] offsets
-    int* my_ij = reinterpret_cast<int*>(stage + (size_t)NW * RECS * (VS + 3)) + wv * RECS;
+    R* vals = reinterpret_cast<R*>(smem_raw + off_st) + (size_t)wv * (VST + 2 * RECS);
+    R* dd = vals + VST;  // [2 RECS] offsets of the chunk (x, y per node)
 
     const int gx0 = (t % g.ntx) * T;
     const int gy0 = (t / g.ntx) * T;
-    for (int i = threadIdx.x; i < C * TS; i += blockDim.x) tile[i] = 0.0;
+    for (int i = threadIdx.x; i < E * EP; i += blockDim.x) win[i] = 0.0;
     __syncthreads();
 
-    // this lane's taps: tap = lane + 64 k, (a, b) = (tap % W, tap / W)
-    int ta[NTAP], tb[NTAP];
+    // tap of this lane: column ta, rows tb0 + k RW (k < NI)
+    const int ta = lane % W;
+    const int tb0 = lane / W;
+    const bool lane_on = lane < RW * W;
+    // kernel-value evaluation: lane -> tap ta, offset group tb0 (G groups); the
+    // tap's polynomial coefficients stay in this lane's registers
+    double cf[P];
 #pragma unroll
-    for (int k = 0; k < NTAP; ++k) {
-        const int tap = lane + 64 * k;
-        tb[k] = tap / W;
-        ta[k] = tap - tb[k] * W;
-    }
+    for (int k = 0; k < P; ++k) cf[k] = coef[ta * P + k];
+    const int64_t n_all = n_src + n_bnd;
+    const double dscale = -2.0 / g.h;  // d/dy of a tap value = -(2/h) d/du
 
-    auto wave_path = [&](const RecView<R>& L) {
-        const int r1 = L.start[t + 1];
-        int base = L.start[t] + wv * RECS;
-        int c_ij = 0, c_idx = 0;
-        R c_dx = R(0), c_dy = R(0);
-        if (lane < RECS && base + lane < r1) {
-            c_ij = L.ij[base + lane];
-            c_idx = L.idx[base + lane];
-            c_dx = L.dx[base + lane];
-            c_dy = L.dy[base + lane];
+    // DL = false: one strength per node; DL = true: double-layer boundary nodes,
+    // value s phi_x phi_y + gx phi_x' phi_y + gy phi_x phi_y'.
+    auto wave_path = [&](const RecView<R>& L, int r0, int r1, auto dl_tag) {
+        constexpr bool DL = decltype(dl_tag)::value;
+        constexpr int VS = DL ? 4 * W : 2 * W;
+        constexpr int NR = DL ? RECS / 2 : RECS;  // nodes per chunk
+        int base = r0 + wv * NR;
+        int n_ij = 0, n_idx = 0;
+        R n_dx = R(0), n_dy = R(0);
+        if (lane < NR && base + lane < r1) {
+            n_ij = L.ij[base + lane];
+            n_idx = L.idx[base + lane];
+            n_dx = L.dx[base + lane];
+            n_dy = L.dy[base + lane];
         }
-        R c_s = (lane < RECS && base + lane < r1) ? str[c_idx] : R(0);
-        for (; base < r1; base += NW * RECS) {
-            const int nrec = min(RECS, r1 - base);
-            if (lane < nrec) {
-                my_ij[lane] = c_ij;
-                my_s[lane] = c_s;
-                my_d[2 * lane] = c_dx;
-                my_d[2 * lane + 1] = c_dy;
-            }
-            const int nb = base + NW * RECS;
-            const bool pre = lane < RECS && nb + lane < r1;
+        const bool have0 = lane < NR && base + lane < r1;
+        R n_s = have0 ? str[n_idx] : R(0);
+        R n_gx = R(0), n_gy = R(0);
+        if (DL && have0) {
+            n_gx = str[n_all + (n_idx - n_src)];
+            n_gy = str[n_all + n_bnd + (n_idx - n_src)];
+        }
+        for (; base < r1; base += NW * NR) {
+            const int nrec = min(NR, r1 - base);
+            const int c_ij = n_ij;
+            const R c_s = n_s, c_gx = n_gx, c_gy = n_gy;
+            const R c_dx = n_dx, c_dy = n_dy;
+            // prefetch the next chunk of this wavefront
+            const int nb = base + NW * NR;
+            const bool pre = lane < NR && nb + lane < r1;
             if (pre) {
-                c_ij = L.ij[nb + lane];
-                c_idx = L.idx[nb + lane];
-                c_dx = L.dx[nb + lane];
-                c_dy = L.dy[nb + lane];
+                n_ij = L.ij[nb + lane];
+                n_idx = L.idx[nb + lane];
+                n_dx = L.dx[nb + lane];
+                n_dy = L.dy[nb + lane];
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // kernel values: lane -> (record lane/2, axis lane%2), all W taps
-            if ((lane >> 1) < nrec) {
-                double pv[W];
-                kernel_taps<W>((double)my_d[lane], coef, pv);
-                R* dst = vals + (lane >> 1) * VS + (lane & 1) * W;
+            // kernel values: the chunk's offsets go to LDS (lane = 2 node + axis),
+            // then lane (tap ta, group tb0) evaluates its tap for offsets tb0, tb0+G, ...
+            {
+                const R dxv = __shfl(c_dx, lane >> 1);
+                const R dyv = __shfl(c_dy, lane >> 1);
+                if (lane < 2 * NR) dd[lane] = (lane & 1) ? dyv : dxv;
+                wave_sync_lds();
+                if (lane_on) {
+                    const int nv2 = 2 * nrec;
+                    for (int q = tb0; q < nv2; q += G) {
+                        const double u = 2.0 * (double)dd[q] - 1.0;
+                        R* dst = vals + (q >> 1) * VS + (q & 1) * W + ta;
+                        if constexpr (DL) {
+                            double v, dv;
+                            tap_value_deriv<P>(cf, u, v, dv);
+                            dst[0] = (R)v;
+                            dst[2 * W] = (R)(dscale * dv);
+                        } else {
+                            double acc = cf[P - 1];
 #pragma unroll
-                for (int a = 0; a < W; ++a) dst[a] = (R)pv[a];
-            }
-            if (pre) c_s = str[c_idx];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (int rr = 0; rr < nrec; ++rr) {
-                const int p = my_ij[rr];
-                const R sv = my_s[rr];
-                const int i0 = (p & 0xffff) - gx0;
-                const int j0 = (p >> 16) - gy0;
-                const R* v = vals + rr * VS;
-#pragma unroll
-                for (int k = 0; k < NTAP; ++k) {
-                    if (k + 1 < NTAP || lane + 64 * k < WW) {
-                        const int x = i0 + ta[k];
-                        const int y = j0 + tb[k];
-                        if ((unsigned)x < (unsigned)T && (unsigned)y < (unsigned)T)
-                            atomicAdd(&tile[y * TP + x], (double)(sv * v[ta[k]] * v[W + tb[k]]));
+                            for (int k = P - 2; k >= 0; --k) acc = fma(acc, u, cf[k]);
+                            dst[0] = (R)acc;
+                        }
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (pre) {
+                n_s = str[n_idx];
+                if (DL) {
+                    n_gx = str[n_all + (n_idx - n_src)];
+                    n_gy = str[n_all + n_bnd + (n_idx - n_src)];
+                }
+            }
+            wave_sync_lds();
+            // node loop: lanes -> taps; the next node's values are read before
+            // this node's atomics are issued
+            auto load = [&](int rr, R& vx, R* vy, R& dvx, R* dvy) {
+                const R* v = vals + rr * VS;
+                vx = v[ta];
+                if (DL) dvx = v[2 * W + ta];
+#pragma unroll
+                for (int k = 0; k < NI; ++k) {
+                    const int b = min(tb0 + k * RW, W - 1);
+                    vy[k] = v[W + b];
+                    if (DL) dvy[k] = v[3 * W + b];
+                }
+            };
+            R vx, vy[NI], dvx = R(0), dvy[NI];
+            load(0, vx, vy, dvx, dvy);
+            for (int rr = 0; rr < nrec; ++rr) {
+                R vxn = R(0), vyn[NI], dvxn = R(0), dvyn[NI];
+                if (rr + 1 < nrec) load(rr + 1, vxn, vyn, dvxn, dvyn);
+                const int p = __builtin_amdgcn_readlane(c_ij, rr);
+                const R s = lane_value(c_s, rr);
+                const int i0 = (p & 0xffff) - gx0;
+                const int j0 = (p >> 16) - gy0;
+                double* row = win + (j0 + tb0) * EP + i0 + ta;
+                if constexpr (DL) {
+                    const R gx = lane_value(c_gx, rr), gy = lane_value(c_gy, rr);
+                    const R sx = s * vx, gxx = gx * dvx, gyx = gy * vx;
+#pragma unroll
+                    for (int k = 0; k < NI; ++k)
+                        if (lane_on && tb0 + k * RW < W)
+                            atomicAdd(row + k * RW * EP, (double)(sx * vy[k] + gxx * vy[k] + gyx * dvy[k]));
+                } else {
+                    const R vxs = vx * s;
+#pragma unroll
+                    for (int k = 0; k < NI; ++k)
+                        if (lane_on && tb0 + k * RW < W) atomicAdd(row + k * RW * EP, (double)(vxs * vy[k]));
+                }
+                vx = vxn;
+                dvx = dvxn;
+#pragma unroll
+                for (int k = 0; k < NI; ++k) {
+                    vy[k] = vyn[k];
+                    dvy[k] = dvyn[k];
+                }
+            }
+            wave_sync_lds();
         }
     };
 
-    if (use_vol) wave_path(vol);
-    if (use_bnd && C == 1) wave_path(bnd);
-    if (use_bnd && C == 3) {
-        const int r1 = bnd.start[t + 1];
-        for (int r = bnd.start[t] + threadIdx.x; r < r1; r += blockDim.x) {
-            const int p = bnd.ij[r];
-            const int i0 = (p & 0xffff) - gx0;
-            const int j0 = (p >> 16) - gy0;
-            const int k = bnd.idx[r];
-            R sc[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) sc[c] = str[c * nstr + k];
-            double px[W], py[W];
-            kernel_taps<W>((double)bnd.dx[r], coef, px);
-            kernel_taps<W>((double)bnd.dy[r], coef, py);
-#pragma unroll
-            for (int b = 0; b < W; ++b) {
-                const int y = j0 + b;
-                if (y < 0 || y >= T) continue;
-#pragma unroll
-                for (int a = 0; a < W; ++a) {
-                    const int x = i0 + a;
-                    if (x < 0 || x >= T) continue;
-                    const R v = (R)px[a] * (R)py[b];
-#pragma unroll
-                    for (int c = 0; c < C; ++c) atomicAdd(&tile[c * TS + y * TP + x], (double)(sc[c] * v));
-                }
-            }
-        }
-    }
+    if (nv) wave_path(vol, unit.a0, unit.a1, std::false_type{});
+    if (nbd && !use_d) wave_path(bnd, unit.b0, unit.b1, std::false_type{});
+    if (nbd && use_d) wave_path(bnd, unit.b0, unit.b1, std::true_type{});
     __syncthreads();
-    const size_t F = g.F;
-    for (int i = threadIdx.x; i < C * T * T; i += blockDim.x) {
-        const int c = i / (T * T);
-        const int l = i - c * T * T;
-        const int y = l / T;
-        const int x = l - y * T;
-        grid[(size_t)c * F * F + (size_t)(gy0 + y) * F + gx0 + x] = (R)tile[c * TS + y * TP + x];
+    const int F = g.F;
+    for (int i = threadIdx.x; i < E * E; i += blockDim.x) {
+        const int y = i / E;
+        const int x = i - y * E;
+        const int gx = gx0 + x, gy = gy0 + y;
+        if (gx < F && gy < F) {
+            const double v = win[y * EP + x];
+            if (v != 0.0) unsafeAtomicAdd(grid + (size_t)gy * F + gx, (R)v);
+        }
     }
 }
 
@@ -315,9 +453,8 @@ __device__ void dev_row_r2c(unsigned char* smem_raw, const LevelGeom& g, const R
     const int N = F >> 1;
     const int logN = g.logF - 1;
     const int M = g.M;
-    const int row = unit % F;
-    const int c = unit / F;
-    const R* x = grid + ((size_t)c * F + row) * F;
+    const int row = unit;
+    const R* x = grid + (size_t)row * F;
     for (int n = threadIdx.x; n < N; n += blockDim.x) z[bitrev(n, logN)] = {x[2 * n], x[2 * n + 1]};
     __syncthreads();
     lds_fft(z, logN, tw, 2, false);
@@ -330,74 +467,45 @@ __device__ void dev_row_r2c(unsigned char* smem_raw, const LevelGeom& g, const R
         cplx<R> X;
         X.x = ex + wk.x * ox - wk.y * oy;
         X.y = ey + wk.x * oy + wk.y * ox;
-        spec[((size_t)c * (M + 1) + k) * F + row] = X;
+        spec[(size_t)k * F + row] = X;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Column pass for x-frequency m1 = unit: FFT along y of each channel,
-// combine B0 - i k1 B1 - i k2 B2 (double layer: derivative of the kernel in
-// the source variable), multiply by the level's table, inverse FFT along y.
-template <typename R, int C>
-__device__ void dev_col(unsigned char* smem_raw, const LevelGeom& g, const cplx<R>* __restrict__ spec,
-                        const R* __restrict__ mult, const cplx<R>* __restrict__ tw, cplx<R>* __restrict__ spec2,
-                        int zero_dc, int unit)
+// Column pass for x-frequency m1 = unit, in place: FFT along y, multiply by the
+// level's table ((dk/2pi)^2 M(k) / phihat^2, zero outside |m2| <= M), inverse
+// FFT along y.
+template <typename R>
+__device__ void dev_col(unsigned char* smem_raw, const LevelGeom& g, cplx<R>* __restrict__ spec,
+                        const R* __restrict__ mult, const cplx<R>* __restrict__ tw, int zero_dc, int unit)
 {
     cplx<R>* z = reinterpret_cast<cplx<R>*>(smem_raw);
-    constexpr int PER = 8192 / kThreads;
     const int F = g.F;
     const int logF = g.logF;
     const int M = g.M;
     const int m1 = unit;
-    const R dk = (R)g.dk;
-    cplx<R> acc[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) acc[i] = {R(0), R(0)};
-    for (int c = 0; c < C; ++c) {
-        const cplx<R>* col = spec + ((size_t)c * (M + 1) + m1) * F;
-        for (int q = threadIdx.x; q < F; q += blockDim.x) z[bitrev(q, logF)] = col[q];
-        __syncthreads();
-        lds_fft(z, logF, tw, 1, false);
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int q = threadIdx.x + i * kThreads;
-            if (q < F) {
-                const cplx<R> v = z[q];
-                if (c == 0) {
-                    acc[i].x += v.x;
-                    acc[i].y += v.y;
-                } else {
-                    const int m2 = q < (F >> 1) ? q : q - F;
-                    const R kk = (c == 1) ? dk * R(m1) : dk * R(m2);
-                    acc[i].x += kk * v.y;     // -i kk v
-                    acc[i].y -= kk * v.x;
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int q = threadIdx.x + i * kThreads;
-        if (q < F) {
-            const int m2 = q < (F >> 1) ? q : q - F;
-            const int am = m2 < 0 ? -m2 : m2;
-            R t = am <= M ? mult[(size_t)m1 * (M + 1) + am] : R(0);
-            if (zero_dc && m1 == 0 && q == 0) t = R(0);
-            z[bitrev(q, logF)] = {acc[i].x * t, acc[i].y * t};
-        }
+    cplx<R>* col = spec + (size_t)m1 * F;
+    for (int q = threadIdx.x; q < F; q += blockDim.x) z[bitrev(q, logF)] = col[q];
+    __syncthreads();
+    lds_fft(z, logF, tw, 1, false);
+    for (int q = threadIdx.x; q < F; q += blockDim.x) {
+        const int m2 = q < (F >> 1) ? q : q - F;
+        const int am = m2 < 0 ? -m2 : m2;
+        R t = am <= M ? mult[(size_t)m1 * (M + 1) + am] : R(0);
+        if (zero_dc && m1 == 0 && q == 0) t = R(0);
+        z[q].x *= t;
+        z[q].y *= t;
     }
     __syncthreads();
-    lds_fft(z, logF, tw, 1, true);
-    cplx<R>* out = spec2 + (size_t)m1 * F;
-    for (int q = threadIdx.x; q < F; q += blockDim.x) out[q] = z[q];
+    lds_fft_dif(z, logF, tw, 1, true);
+    for (int q = threadIdx.x; q < F; q += blockDim.x) col[q] = z[bitrev(q, logF)];
 }
 
 // ---------------------------------------------------------------------------
 // Row inverse: rebuild each row's Hermitian x-spectrum from m1 = 0..M (zero
 // elsewhere) and inverse real FFT (complex FFT of length F/2).
 template <typename R>
-__device__ void dev_row_c2r(unsigned char* smem_raw, const LevelGeom& g, const cplx<R>* __restrict__ spec2,
+__device__ void dev_row_c2r(unsigned char* smem_raw, const LevelGeom& g, const cplx<R>* __restrict__ spec,
                             const cplx<R>* __restrict__ tw, R* __restrict__ out, int unit)
 {
     cplx<R>* z = reinterpret_cast<cplx<R>*>(smem_raw);
@@ -409,9 +517,9 @@ __device__ void dev_row_c2r(unsigned char* smem_raw, const LevelGeom& g, const c
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         cplx<R> a = {R(0), R(0)};
         cplx<R> b = {R(0), R(0)};
-        if (k <= M) a = spec2[(size_t)k * F + row];
+        if (k <= M) a = spec[(size_t)k * F + row];
         const int kk = N - k;
-        if (kk <= M) b = spec2[(size_t)kk * F + row];
+        if (kk <= M) b = spec[(size_t)kk * F + row];
         const R ex = a.x + b.x, ey = a.y - b.y;       // X[k] + conj(X[N-k])
         const R dx = a.x - b.x, dy = a.y + b.y;       // X[k] - conj(X[N-k])
         const cplx<R> wk = tw[k];                     // exp(-2 pi i k/F); use its conjugate
@@ -431,23 +539,42 @@ __device__ void dev_row_c2r(unsigned char* smem_raw, const LevelGeom& g, const c
 
 // ---------------------------------------------------------------------------
 // Interpolation (type-2, Sec. 3 Step 4 via the NUFFT): one workgroup per tile
-// stages the (T+w-1)^2 grid window in LDS; each thread evaluates one target.
+// stages the (T+w-1)^2 grid window in LDS (a target's support lies in the
+// window because the target is filed under the tile of its support corner).
+// Each wavefront takes chunks of 32 targets: lane (tap a, group) evaluates
+// tap a's polynomial (coefficients in its registers) for the chunk's offsets
+// into LDS, then lane pairs sum one target each (rows split in two halves).
+constexpr int kInterpTargets = 32;  // targets per wavefront chunk
+
+__host__ __device__ inline size_t interp_lds_bytes(int T, int W, size_t rb)
+{
+    const size_t win = ((size_t)(T + W - 1) * (T + W - 1) * rb + 15) & ~(size_t)15;
+    return win + (size_t)(kThreads / 64) * (kInterpTargets * 2 * W + 2 * kInterpTargets) * rb;
+}
+
 template <typename R, int W>
 __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R* __restrict__ grid,
-                           const RecView<R>& L, R* __restrict__ hist, const double* __restrict__ coef, int t)
+                           const RecView<R>& L, R* __restrict__ hist, const double* __restrict__ coef,
+                           const WorkUnit unit)
 {
-    const int* __restrict__ start = L.start;
-    const int* __restrict__ ij = L.ij;
-    const R* __restrict__ sx = L.dx;
-    const R* __restrict__ sy = L.dy;
-    const int* __restrict__ idx = L.idx;
-    R* reg = reinterpret_cast<R*>(smem_raw);
+    constexpr int P = W + 2;
+    constexpr int NT = kInterpTargets;
+    constexpr int VS = 2 * W;
+    constexpr int G = 64 / W;
+    constexpr int HB = (W + 1) / 2;  // rows of the first half
+    const int t = unit.tile;
+    const int r0 = unit.a0;
+    const int r1 = unit.a1;
+    if (r0 == r1) return;
     const int T = g.T;
     const int E = T + W - 1;
     const int F = g.F;
-    const int r0 = start[t];
-    const int r1 = start[t + 1];
-    if (r0 == r1) return;
+    R* reg = reinterpret_cast<R*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    R* vals = reinterpret_cast<R*>(smem_raw + (((size_t)E * E * sizeof(R) + 15) & ~(size_t)15)) +
+              (size_t)wv * (NT * VS + 2 * NT);
+    R* dd = vals + NT * VS;
     const int gx0 = (t % g.ntx) * T;
     const int gy0 = (t / g.ntx) * T;
     for (int i = threadIdx.x; i < E * E; i += blockDim.x) {
@@ -457,24 +584,62 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
         const int gx = gx0 + x;
         reg[i] = (gx < F && gy < F) ? grid[(size_t)gy * F + gx] : R(0);
     }
+    const int ka = lane % W;
+    const int kg = lane / W;
+    const bool kon = lane < G * W;
+    double cf[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) cf[k] = coef[ka * P + k];
     __syncthreads();
-    for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const int p = ij[r];
-        const int i0 = (p & 0xffff) - gx0;
-        const int j0 = (p >> 16) - gy0;
-        double px[W], py[W];
-        kernel_taps<W>((double)sx[r], coef, px);
-        kernel_taps<W>((double)sy[r], coef, py);
-        R sum = R(0);
-#pragma unroll
-        for (int b = 0; b < W; ++b) {
-            const R* rowp = reg + (j0 + b) * E + i0;
-            R acc = R(0);
-#pragma unroll
-            for (int a = 0; a < W; ++a) acc += (R)px[a] * rowp[a];
-            sum += (R)py[b] * acc;
+    const int q = lane >> 1;    // target of this lane within the chunk
+    const int half = lane & 1;  // rows [0, HB) or [HB, W)
+    for (int base = r0 + wv * NT; base < r1; base += (kThreads / 64) * NT) {
+        const int nt = min(NT, r1 - base);
+        int my_ij = 0, my_idx = 0;
+        if (lane < nt) {
+            my_ij = L.ij[base + lane];
+            my_idx = L.idx[base + lane];
+            dd[2 * lane] = L.dx[base + lane];
+            dd[2 * lane + 1] = L.dy[base + lane];
         }
-        hist[idx[r]] = sum;
+        wave_sync_lds();
+        if (kon) {
+            for (int pq = kg; pq < 2 * nt; pq += G) {
+                const double u = 2.0 * (double)dd[pq] - 1.0;
+                double acc = cf[P - 1];
+#pragma unroll
+                for (int k = P - 2; k >= 0; --k) acc = fma(acc, u, cf[k]);
+                vals[(pq >> 1) * VS + (pq & 1) * W + ka] = (R)acc;
+            }
+        }
+        wave_sync_lds();
+        const int p = __shfl(my_ij, q);
+        const int id = __shfl(my_idx, q);
+        R sum = R(0);
+        if (q < nt) {
+            const int i0 = (p & 0xffff) - gx0;
+            const int j0 = (p >> 16) - gy0;
+            const R* v = vals + q * VS;
+            R px[W];
+#pragma unroll
+            for (int a2 = 0; a2 < W; ++a2) px[a2] = v[a2];
+            const int b0 = half ? HB : 0;
+            const int b1 = half ? W : HB;
+#pragma unroll
+            for (int bb = 0; bb < HB; ++bb) {
+                const int b = b0 + bb;
+                if (b < b1) {
+                    const R* rowp = reg + (j0 + b) * E + i0;
+                    R acc = R(0);
+#pragma unroll
+                    for (int a2 = 0; a2 < W; ++a2) acc += px[a2] * rowp[a2];
+                    sum += v[W + b] * acc;
+                }
+            }
+        }
+        sum += __shfl_xor(sum, 1);
+        if (q < nt && half == 0) hist[id] = sum;
+        wave_sync_lds();
     }
 }
 

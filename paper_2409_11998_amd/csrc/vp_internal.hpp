@@ -14,8 +14,7 @@ namespace vp {
 constexpr int kWMax = 16;        // largest spreading width (grid cells per dimension)
 constexpr int kWMin = 4;         // smallest spreading width
 constexpr int kThreads = 256;    // threads per workgroup for grid kernels
-constexpr int kMaxChannels = 3;  // f*w + sigma*wG | mu*nu1*wG | mu*nu2*wG
-// Launches timed by vp_set_timing, in order: strengths; spread NH, FH; row FFT NH,
+// Launches timed by vp_set_timing, in order: grid zeroing + strengths; spread NH, FH; row FFT NH,
 // FH; column FFT NH, FH; row inverse NH, FH; interpolation NH, FH; local part.
 constexpr int kTimedLaunches = 12;
 
@@ -37,10 +36,10 @@ struct LevelGeom {
     double dc_coef; // (dk/2pi)^2 * multiplier(0): the zero mode's kernel weight
 };
 
-// A tile-sorted list of points of one level (CSR by tile).  For spreading a
-// point appears once per tile its w x w support meets; for interpolation each
-// target appears once, in the tile holding its support corner.
+// A tile-sorted list of points of one level (CSR by tile): each point appears
+// once, in the tile holding its support corner (i0, j0).
 struct RecList {
+    std::vector<int> h_start;  // host copy of start
     int* start = nullptr;  // [ntiles+1]
     int* ij = nullptr;     // packed absolute support corner i0 | j0 << 16
     void* dx = nullptr;    // R: i0 - t_x + w/2, in [0, 1)
@@ -62,11 +61,27 @@ template <typename R> inline RecView<R> view(const RecList& l)
     return RecView<R>{l.start, l.ij, (const R*)l.dx, (const R*)l.dy, l.idx};
 }
 
+// A workgroup's share of a tile: records [a0, a1) of one list and [b0, b1) of
+// another (spreading: volume and boundary nodes; interpolation: targets).
+// Dense tiles are split into several units, so that the number of
+// workgroups follows the number of points rather than the number of tiles.
+struct WorkUnit {
+    int tile;
+    int a0, a1;
+    int b0, b1;
+};
+constexpr int kUnitNodes = 1024;     // volume nodes per spreading unit
+constexpr int kUnitBnd = 256;        // boundary nodes per spreading unit
+constexpr int kUnitTargets = 2048;   // targets per interpolation unit
+
 // Device buffers of one level.  R = float or double (plan precision).
 struct LevelBufs {
     RecList vol;               // volume nodes (spread)
     RecList bnd;               // boundary nodes (spread)
     RecList tgt;               // targets (interpolation)
+    WorkUnit* sp_units = nullptr;  // spreading work units (tiles with nodes)
+    WorkUnit* in_units = nullptr;  // interpolation work units (tiles with targets)
+    std::vector<WorkUnit> h_sp_units, h_in_units;
     void* mult = nullptr;      // R [M+1][M+1] (dk/2pi)^2 M(k) / (phihat(m1) phihat(m2))^2
     void* tw = nullptr;        // cplx<R> [F/2] twiddles exp(-2 pi i k / F)
     double* horner = nullptr;  // [w][w+2] per-tap polynomial of the spreading kernel in u = 2d - 1
@@ -76,11 +91,10 @@ struct LevelBufs {
 // own one; the serving loop gives every in-flight request its own, so
 // requests on one plan can overlap.
 struct Workspace {
-    void* grid[2] = {nullptr, nullptr};   // R [C][F][F] spread grids, reused for the inverse output
-    void* spec[2] = {nullptr, nullptr};   // cplx<R> [C][M+1][F] (x-frequency major)
-    void* spec2[2] = {nullptr, nullptr};  // cplx<R> [M+1][F]
+    void* grid[2] = {nullptr, nullptr};   // R [F][F] spread grids, reused for the inverse output
+    void* spec[2] = {nullptr, nullptr};   // cplx<R> [M+1][F] half spectra (x-frequency major)
     void* hist[2] = {nullptr, nullptr};   // R [n_tgt] history value at each target
-    void* str = nullptr;                  // R [C][n_src + n_bnd] strengths
+    void* str = nullptr;                  // R [n_src + n_bnd (+ 2 n_bnd)] strengths (+ mu nu wG)
     double* dc = nullptr;                 // [1] float64 sum of channel-0 strengths
     void* block = nullptr;                // single allocation holding all of the above
     size_t bytes = 0;
@@ -106,7 +120,6 @@ struct Plan {
     double* d_nx = nullptr;      // [n_bnd] outward normal
     double* d_ny = nullptr;
     Workspace ws;                // the plan's own workspace (absent with opts.no_workspace)
-    int cmax = 1;                // channels the workspace holds (3 with the double layer)
     // target geometry (device, float64 / int8)
     double* g_r = nullptr;
     double* g_nx = nullptr;
@@ -118,6 +131,10 @@ struct Plan {
     size_t device_bytes = 0;
     std::vector<void*> allocs;
     bool timing = false;
+    // measured selection of the levels (opts.autotune)
+    int autotuned = 0;
+    int tune_cands[2] = {0, 0};
+    double level_ms[2] = {0.0, 0.0};
     hipEvent_t ev[kTimedLaunches + 1]{};  // before the first and after each timed launch
     bool ev_made = false;
 };
@@ -125,18 +142,20 @@ struct Plan {
 // Kernel launchers (vp_kernels.hip).  All enqueue on stream st and write into ws.
 hipError_t launch_zero_dc(const Plan& p, const Workspace& ws, hipStream_t st);
 hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* sigma,
-                            const double* mu, int C);
-hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C, bool use_vol,
-                         bool use_bnd);
-hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C);
-hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C);
+                            const double* mu);
+hipError_t launch_zero_grids(const Plan& p, const Workspace& ws, hipStream_t st);
+hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool use_vol, bool use_bnd,
+                         bool use_d);
+hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
+hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
 hipError_t launch_row_ifft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
 hipError_t launch_interp(const Plan& p, const Workspace& ws, hipStream_t st, int level);
 hipError_t launch_local(const Plan& p, const Workspace& ws, hipStream_t st, const double* jet6, const double* sig_jet,
                         const double* mu_jet, bool use_v, bool use_s, bool use_d, double* out);
 size_t row_fft_lds_bytes(const Plan& p, int level);
 size_t col_fft_lds_bytes(const Plan& p, int level);
-size_t spread_lds_bytes(const Plan& p, int level, int C, bool use_bnd);
+size_t spread_lds_bytes(const Plan& p, int level);
+size_t interp_lds_bytes_of(const Plan& p, int level);
 
 // Workspace layout / allocation (vp_plan.hip).  async: stream-ordered
 // (hipMallocAsync/hipFreeAsync on st), else plain hipMalloc/hipFree.

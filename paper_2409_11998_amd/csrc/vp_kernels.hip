@@ -3,6 +3,8 @@
 // their launchers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "vp_device.hpp"
 
 namespace vp {
@@ -15,10 +17,18 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void k_strengths(int64_t n_src, int64_t n_bnd, const double* __restrict__ f,
                                                         const double* __restrict__ sigma, const double* __restrict__ mu,
                                                         const double* __restrict__ w, const double* __restrict__ nx,
-                                                        const double* __restrict__ ny, R* __restrict__ str, int C,
+                                                        const double* __restrict__ ny, R* __restrict__ str,
                                                         double* __restrict__ dc)
 {
-    dev_strengths<R>(n_src, n_bnd, f, sigma, mu, w, nx, ny, str, C, dc, blockIdx.x);
+    dev_strengths<R>(n_src, n_bnd, f, sigma, mu, w, nx, ny, str, dc, blockIdx.x);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_zero2(R* __restrict__ a, int64_t na, R* __restrict__ b, int64_t nb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    dev_zero<R>(a, na, i);
+    dev_zero<R>(b, nb, i);
 }
 
 __global__ void k_zero_dc(double* dc)
@@ -26,13 +36,16 @@ __global__ void k_zero_dc(double* dc)
     if (threadIdx.x == 0 && blockIdx.x == 0) *dc = 0.0;
 }
 
-template <typename R, int W, int C>
+template <typename R, int W>
 __global__ __launch_bounds__(kThreads) void k_spread(LevelGeom g, RecView<R> vol, RecView<R> bnd,
-                                                     const R* __restrict__ str, int64_t nstr, R* __restrict__ grid,
-                                                     int use_vol, int use_bnd, const double* __restrict__ coef)
+                                                     const R* __restrict__ str, int64_t n_src, int64_t n_bnd,
+                                                     R* __restrict__ grid, int use_vol, int use_bnd, int use_d,
+                                                     const double* __restrict__ coef,
+                                                     const WorkUnit* __restrict__ units)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    dev_spread<R, W, C>(smem_raw, g, vol, bnd, str, nstr, grid, use_vol, use_bnd, coef, blockIdx.x);
+    dev_spread<R, W>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d, coef,
+                     units[xcd_unit(blockIdx.x, gridDim.x)]);
 }
 
 template <typename R>
@@ -40,32 +53,33 @@ __global__ __launch_bounds__(kThreads) void k_row_r2c(LevelGeom g, const R* __re
                                                       const cplx<R>* __restrict__ tw, cplx<R>* __restrict__ spec)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    dev_row_r2c<R>(smem_raw, g, grid, tw, spec, blockIdx.x);
-}
-
-template <typename R, int C>
-__global__ __launch_bounds__(kThreads) void k_col(LevelGeom g, const cplx<R>* __restrict__ spec,
-                                                  const R* __restrict__ mult, const cplx<R>* __restrict__ tw,
-                                                  cplx<R>* __restrict__ spec2, int zero_dc)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    dev_col<R, C>(smem_raw, g, spec, mult, tw, spec2, zero_dc, blockIdx.x);
+    dev_row_r2c<R>(smem_raw, g, grid, tw, spec, xcd_unit(blockIdx.x, gridDim.x));
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_row_c2r(LevelGeom g, const cplx<R>* __restrict__ spec2,
+__global__ __launch_bounds__(kThreads) void k_col(LevelGeom g, cplx<R>* __restrict__ spec,
+                                                  const R* __restrict__ mult, const cplx<R>* __restrict__ tw,
+                                                  int zero_dc)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    dev_col<R>(smem_raw, g, spec, mult, tw, zero_dc, xcd_unit(blockIdx.x, gridDim.x));
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row_c2r(LevelGeom g, const cplx<R>* __restrict__ spec,
                                                       const cplx<R>* __restrict__ tw, R* __restrict__ out)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    dev_row_c2r<R>(smem_raw, g, spec2, tw, out, blockIdx.x);
+    dev_row_c2r<R>(smem_raw, g, spec, tw, out, xcd_unit(blockIdx.x, gridDim.x));
 }
 
 template <typename R, int W>
 __global__ __launch_bounds__(kThreads) void k_interp(LevelGeom g, const R* __restrict__ grid, RecView<R> tgt,
-                                                     R* __restrict__ hist, const double* __restrict__ coef)
+                                                     R* __restrict__ hist, const double* __restrict__ coef,
+                                                     const WorkUnit* __restrict__ units)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    dev_interp<R, W>(smem_raw, g, grid, tgt, hist, coef, blockIdx.x);
+    dev_interp<R, W>(smem_raw, g, grid, tgt, hist, coef, units[xcd_unit(blockIdx.x, gridDim.x)]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_local(LocalArgs a)
@@ -105,57 +119,75 @@ hipError_t launch_zero_dc(const Plan& p, const Workspace& ws, hipStream_t st)
 }
 
 hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* sigma,
-                            const double* mu, int C)
+                            const double* mu)
 {
     const int64_t n = p.n_src + p.n_bnd;
     const unsigned blocks = grid_for(n, kStrChunk);
     if (p.precision == VP_FP32)
         hipLaunchKernelGGL(k_strengths<float>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
-                           p.d_w, p.d_nx, p.d_ny, (float*)ws.str, C, ws.dc);
+                           p.d_w, p.d_nx, p.d_ny, (float*)ws.str, ws.dc);
     else
         hipLaunchKernelGGL(k_strengths<double>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
-                           p.d_w, p.d_nx, p.d_ny, (double*)ws.str, C, ws.dc);
+                           p.d_w, p.d_nx, p.d_ny, (double*)ws.str, ws.dc);
     return hipGetLastError();
 }
 
-size_t spread_lds_bytes(const Plan& p, int level, int C, bool use_bnd)
+hipError_t launch_zero_grids(const Plan& p, const Workspace& ws, hipStream_t st)
 {
-    (void)use_bnd;
-    size_t a;
+    // a level without a grid in ws (the planner's level timing) is skipped
+    const int64_t n0 = ws.grid[0] ? (int64_t)p.lv[0].F * p.lv[0].F : 0;
+    const int64_t n1 = ws.grid[1] ? (int64_t)p.lv[1].F * p.lv[1].F : 0;
+    const unsigned blocks = grid_for(std::max(n0, n1));
     if (p.precision == VP_FP32)
-        return spread_lds_layout(p.lv[level].T, C, sizeof(float), SpreadShape<float>::kWaves,
-                                 SpreadShape<float>::kRecs, SpreadShape<float>::kVals, &a);
-    return spread_lds_layout(p.lv[level].T, C, sizeof(double), SpreadShape<double>::kWaves,
-                             SpreadShape<double>::kRecs, SpreadShape<double>::kVals, &a);
+        hipLaunchKernelGGL(k_zero2<float>, dim3(blocks), dim3(kThreads), 0, st, (float*)ws.grid[0], n0,
+                           (float*)ws.grid[1], n1);
+    else
+        hipLaunchKernelGGL(k_zero2<double>, dim3(blocks), dim3(kThreads), 0, st, (double*)ws.grid[0], n0,
+                           (double*)ws.grid[1], n1);
+    return hipGetLastError();
+}
+
+size_t interp_lds_bytes_of(const Plan& p, int level)
+{
+    return interp_lds_bytes(p.lv[level].T, p.lv[level].w, p.precision == VP_FP32 ? sizeof(float) : sizeof(double));
+}
+
+size_t spread_lds_bytes(const Plan& p, int level)
+{
+    size_t a;
+    return spread_lds_layout(p.lv[level].T, p.lv[level].w, p.precision == VP_FP32 ? sizeof(float) : sizeof(double),
+                             &a);
 }
 
 #define VP_W_CASES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-template <typename R, int W, int C>
-static void spread_launch(const Plan& p, const Workspace& ws, hipStream_t st, int l, size_t lds, int uv, int ub)
+template <typename R, int W>
+static void spread_launch(const Plan& p, const Workspace& ws, hipStream_t st, int l, size_t lds, int uv, int ub,
+                          int ud)
 {
     const LevelGeom& g = p.lv[l];
     const LevelBufs& b = p.lb[l];
-    const unsigned ntiles = (unsigned)(g.ntx * g.ntx);
-    hipFuncSetAttribute((const void*)k_spread<R, W, C>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_spread<R, W, C>), dim3(ntiles), dim3(kThreads), lds, st, g, view<R>(b.vol),
-                       view<R>(b.bnd), (const R*)ws.str, p.n_src + p.n_bnd, (R*)ws.grid[l], uv, ub,
-                       (const double*)b.horner);
+    const unsigned nu = (unsigned)b.h_sp_units.size();
+    if (nu == 0) return;
+    (void)hipFuncSetAttribute((const void*)k_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_spread<R, W>), dim3(nu), dim3(kThreads), lds, st, g, view<R>(b.vol), view<R>(b.bnd),
+                       (const R*)ws.str, p.n_src, p.n_bnd, (R*)ws.grid[l], uv, ub, ud, (const double*)b.horner,
+                       (const WorkUnit*)b.sp_units);
 }
 
 template <typename R>
-static hipError_t spread_t(const Plan& p, const Workspace& ws, hipStream_t st, int l, int C, bool use_vol,
-                           bool use_bnd)
+static hipError_t spread_t(const Plan& p, const Workspace& ws, hipStream_t st, int l, bool use_vol, bool use_bnd,
+                           bool use_d)
 {
     const LevelBufs& b = p.lb[l];
-    const size_t lds = spread_lds_bytes(p, l, C, use_bnd);
+    const size_t lds = spread_lds_bytes(p, l);
     const int uv = use_vol && b.vol.start != nullptr;
     const int ub = use_bnd && b.bnd.start != nullptr;
+    const int ud = use_d ? 1 : 0;
     switch (p.lv[l].w) {
-#define VP_CASE(W)                                                       \
-    case W:                                                              \
-        if (C == 1) spread_launch<R, W, 1>(p, ws, st, l, lds, uv, ub);   \
-        else spread_launch<R, W, 3>(p, ws, st, l, lds, uv, ub);          \
+#define VP_CASE(W)                                               \
+    case W:                                                      \
+        spread_launch<R, W>(p, ws, st, l, lds, uv, ub, ud);      \
         break;
         VP_W_CASES(VP_CASE)
 #undef VP_CASE
@@ -165,48 +197,42 @@ static hipError_t spread_t(const Plan& p, const Workspace& ws, hipStream_t st, i
     return hipGetLastError();
 }
 
-hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C, bool use_vol,
-                         bool use_bnd)
+hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool use_vol, bool use_bnd,
+                         bool use_d)
 {
-    return p.precision == VP_FP32 ? spread_t<float>(p, ws, st, level, C, use_vol, use_bnd)
-                                  : spread_t<double>(p, ws, st, level, C, use_vol, use_bnd);
+    return p.precision == VP_FP32 ? spread_t<float>(p, ws, st, level, use_vol, use_bnd, use_d)
+                                  : spread_t<double>(p, ws, st, level, use_vol, use_bnd, use_d);
 }
 
 template <typename R>
-static hipError_t row_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l, int C)
+static hipError_t row_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l)
 {
     const LevelGeom& g = p.lv[l];
     const LevelBufs& b = p.lb[l];
-    hipLaunchKernelGGL(k_row_r2c<R>, dim3(g.F * C), dim3(kThreads), row_fft_lds_bytes(p, l), st, g,
+    hipLaunchKernelGGL(k_row_r2c<R>, dim3(g.F), dim3(kThreads), row_fft_lds_bytes(p, l), st, g,
                        (const R*)ws.grid[l], (const cplx<R>*)b.tw, (cplx<R>*)ws.spec[l]);
     return hipGetLastError();
 }
 
-hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C)
+hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level)
 {
-    return p.precision == VP_FP32 ? row_fft_t<float>(p, ws, st, level, C) : row_fft_t<double>(p, ws, st, level, C);
+    return p.precision == VP_FP32 ? row_fft_t<float>(p, ws, st, level) : row_fft_t<double>(p, ws, st, level);
 }
 
 template <typename R>
-static hipError_t col_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l, int C)
+static hipError_t col_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l)
 {
     const LevelGeom& g = p.lv[l];
     const LevelBufs& b = p.lb[l];
     const int zero_dc = p.precision == VP_FP32 ? 1 : 0;
-    if (C == 1)
-        hipLaunchKernelGGL((k_col<R, 1>), dim3(g.M + 1), dim3(kThreads), col_fft_lds_bytes(p, l), st, g,
-                           (const cplx<R>*)ws.spec[l], (const R*)b.mult, (const cplx<R>*)b.tw,
-                           (cplx<R>*)ws.spec2[l], zero_dc);
-    else
-        hipLaunchKernelGGL((k_col<R, 3>), dim3(g.M + 1), dim3(kThreads), col_fft_lds_bytes(p, l), st, g,
-                           (const cplx<R>*)ws.spec[l], (const R*)b.mult, (const cplx<R>*)b.tw,
-                           (cplx<R>*)ws.spec2[l], zero_dc);
+    hipLaunchKernelGGL((k_col<R>), dim3(g.M + 1), dim3(kThreads), col_fft_lds_bytes(p, l), st, g,
+                       (cplx<R>*)ws.spec[l], (const R*)b.mult, (const cplx<R>*)b.tw, zero_dc);
     return hipGetLastError();
 }
 
-hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, int C)
+hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level)
 {
-    return p.precision == VP_FP32 ? col_fft_t<float>(p, ws, st, level, C) : col_fft_t<double>(p, ws, st, level, C);
+    return p.precision == VP_FP32 ? col_fft_t<float>(p, ws, st, level) : col_fft_t<double>(p, ws, st, level);
 }
 
 template <typename R>
@@ -215,7 +241,7 @@ static hipError_t row_ifft_t(const Plan& p, const Workspace& ws, hipStream_t st,
     const LevelGeom& g = p.lv[l];
     const LevelBufs& b = p.lb[l];
     hipLaunchKernelGGL(k_row_c2r<R>, dim3(g.F), dim3(kThreads), row_fft_lds_bytes(p, l), st, g,
-                       (const cplx<R>*)ws.spec2[l], (const cplx<R>*)b.tw, (R*)ws.grid[l]);
+                       (const cplx<R>*)ws.spec[l], (const cplx<R>*)b.tw, (R*)ws.grid[l]);
     return hipGetLastError();
 }
 
@@ -229,10 +255,11 @@ static void interp_launch(const Plan& p, const Workspace& ws, hipStream_t st, in
 {
     const LevelGeom& g = p.lv[l];
     const LevelBufs& b = p.lb[l];
-    const int E = g.T + W - 1;
-    const size_t lds = (size_t)E * E * sizeof(R);
-    hipLaunchKernelGGL((k_interp<R, W>), dim3(g.ntx * g.ntx), dim3(kThreads), lds, st, g, (const R*)ws.grid[l],
-                       view<R>(b.tgt), (R*)ws.hist[l], (const double*)b.horner);
+    const size_t lds = interp_lds_bytes(g.T, W, sizeof(R));
+    const unsigned nu = (unsigned)b.h_in_units.size();
+    if (nu == 0) return;
+    hipLaunchKernelGGL((k_interp<R, W>), dim3(nu), dim3(kThreads), lds, st, g, (const R*)ws.grid[l],
+                       view<R>(b.tgt), (R*)ws.hist[l], (const double*)b.horner, (const WorkUnit*)b.in_units);
 }
 
 template <typename R>

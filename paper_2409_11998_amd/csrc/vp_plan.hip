@@ -238,11 +238,11 @@ void free_plan(vp_plan_s* p)
     delete p;
 }
 
-// Sort points into tiles of one level; spread=true gives one record per
-// touched tile, spread=false one record per point (tile of its support corner).
+// Sort points into tiles of one level: one record per point, in the tile
+// holding its support corner.
 template <typename R>
 vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std::vector<double>& y,
-                        const std::vector<int>& ids, bool spread, RecList* list)
+                        const std::vector<int>& ids, RecList* list)
 {
     const LevelGeom& g = p.lv[l];
     const int T = g.T, ntx = g.ntx, w = g.w;
@@ -264,23 +264,7 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
         sy[q] = (R)(ay - ty + 0.5 * w);
     }
     std::vector<int> cnt(ntiles + 1, 0);
-    auto tiles_of = [&](size_t q, int& ax0, int& ax1, int& ay0, int& ay1) {
-        if (spread) {
-            ax0 = i0[q] / T;
-            ax1 = (i0[q] + w - 1) / T;
-            ay0 = j0[q] / T;
-            ay1 = (j0[q] + w - 1) / T;
-        } else {
-            ax0 = ax1 = i0[q] / T;
-            ay0 = ay1 = j0[q] / T;
-        }
-    };
-    for (size_t q = 0; q < n; ++q) {
-        int ax0, ax1, ay0, ay1;
-        tiles_of(q, ax0, ax1, ay0, ay1);
-        for (int ty = ay0; ty <= ay1; ++ty)
-            for (int tx = ax0; tx <= ax1; ++tx) cnt[ty * ntx + tx + 1]++;
-    }
+    for (size_t q = 0; q < n; ++q) cnt[(j0[q] / T) * ntx + i0[q] / T + 1]++;
     for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
     const int64_t nrec = cnt[ntiles];
     if (nrec > INT32_MAX) return fail(VP_ERR_ARG, "too many (node, tile) records");
@@ -288,25 +272,59 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
     std::vector<int> rij(nrec), ridx(nrec);
     std::vector<R> rsx(nrec), rsy(nrec);
     for (size_t q = 0; q < n; ++q) {
-        int ax0, ax1, ay0, ay1;
-        tiles_of(q, ax0, ax1, ay0, ay1);
-        for (int ty = ay0; ty <= ay1; ++ty)
-            for (int tx = ax0; tx <= ax1; ++tx) {
-                const int at = pos[ty * ntx + tx]++;
-                rij[at] = i0[q] | (j0[q] << 16);
-                rsx[at] = sx[q];
-                rsy[at] = sy[q];
-                ridx[at] = ids[q];
-            }
+        const int at = pos[(j0[q] / T) * ntx + i0[q] / T]++;
+        rij[at] = i0[q] | (j0[q] << 16);
+        rsx[at] = sx[q];
+        rsy[at] = sy[q];
+        ridx[at] = ids[q];
     }
     RecList* L = list;
     vp_status s;
+    L->h_start = cnt;
     if ((s = upload(p, &L->start, cnt, "tile starts")) != VP_OK) return s;
     if ((s = upload(p, &L->ij, rij, "records ij")) != VP_OK) return s;
     if ((s = upload(p, (R**)&L->dx, rsx, "records dx")) != VP_OK) return s;
     if ((s = upload(p, (R**)&L->dy, rsy, "records dy")) != VP_OK) return s;
     if ((s = upload(p, &L->idx, ridx, "records idx")) != VP_OK) return s;
     L->n = nrec;
+    return VP_OK;
+}
+
+// Work units of one level: each tile with records becomes one or more units
+// of at most kUnitNodes volume / kUnitBnd boundary nodes (spreading) or
+// kUnitTargets targets (interpolation).
+vp_status build_units(Plan& p, int l)
+{
+    LevelBufs& b = p.lb[l];
+    const int ntiles = p.lv[l].ntx * p.lv[l].ntx;
+    auto cnt_of = [&](const RecList& L, int t) { return L.h_start.empty() ? 0 : L.h_start[t + 1] - L.h_start[t]; };
+    auto beg_of = [&](const RecList& L, int t) { return L.h_start.empty() ? 0 : L.h_start[t]; };
+    b.h_sp_units.clear();
+    b.h_in_units.clear();
+    for (int t = 0; t < ntiles; ++t) {
+        const int nv = cnt_of(b.vol, t), nb = cnt_of(b.bnd, t), nt = cnt_of(b.tgt, t);
+        const int ku = std::max((nv + kUnitNodes - 1) / kUnitNodes, (nb + kUnitBnd - 1) / kUnitBnd);
+        for (int k = 0; k < ku; ++k) {
+            WorkUnit u;
+            u.tile = t;
+            u.a0 = beg_of(b.vol, t) + std::min(nv, k * kUnitNodes);
+            u.a1 = beg_of(b.vol, t) + std::min(nv, (k + 1) * kUnitNodes);
+            u.b0 = beg_of(b.bnd, t) + std::min(nb, k * kUnitBnd);
+            u.b1 = beg_of(b.bnd, t) + std::min(nb, (k + 1) * kUnitBnd);
+            b.h_sp_units.push_back(u);
+        }
+        for (int k = 0; k * kUnitTargets < nt; ++k) {
+            WorkUnit u;
+            u.tile = t;
+            u.a0 = beg_of(b.tgt, t) + k * kUnitTargets;
+            u.a1 = beg_of(b.tgt, t) + std::min(nt, (k + 1) * kUnitTargets);
+            u.b0 = u.b1 = 0;
+            b.h_in_units.push_back(u);
+        }
+    }
+    vp_status s;
+    if ((s = upload(p, &b.sp_units, b.h_sp_units, "spreading units")) != VP_OK) return s;
+    if ((s = upload(p, &b.in_units, b.h_in_units, "interpolation units")) != VP_OK) return s;
     return VP_OK;
 }
 
@@ -377,21 +395,136 @@ vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, 
     return VP_OK;
 }
 
+// Records, work units and tables of level l for the plan's current geometry.
 template <typename R>
-vp_status build_plan_t(Plan& p, const std::vector<double>& sxv, const std::vector<double>& syv,
-                       const std::vector<int>& vol_ids, const std::vector<int>& bnd_ids, const std::vector<double>& tx,
-                       const std::vector<double>& ty, const std::vector<std::vector<double>>& phihat)
+vp_status build_level(Plan& p, int l, const std::vector<double>& sxv, const std::vector<double>& syv,
+                      const std::vector<int>& vol_ids, const std::vector<int>& bnd_ids, const std::vector<double>& tx,
+                      const std::vector<double>& ty, const std::vector<double>& phihat)
 {
     vp_status s;
     std::vector<int> tids(p.n_tgt);
     std::iota(tids.begin(), tids.end(), 0);
-    for (int l = 0; l < 2; ++l) {
-        LevelBufs& b = p.lb[l];
-        if ((s = build_records<R>(p, l, sxv, syv, vol_ids, true, &b.vol)) != VP_OK) return s;
-        if ((s = build_records<R>(p, l, sxv, syv, bnd_ids, true, &b.bnd)) != VP_OK) return s;
-        if ((s = build_records<R>(p, l, tx, ty, tids, false, &b.tgt)) != VP_OK) return s;
-        if ((s = build_level_tables<R>(p, l, phihat[l], p.delta1, p.delta2)) != VP_OK) return s;
+    LevelBufs& b = p.lb[l];
+    if ((s = build_records<R>(p, l, sxv, syv, vol_ids, &b.vol)) != VP_OK) return s;
+    if ((s = build_records<R>(p, l, sxv, syv, bnd_ids, &b.bnd)) != VP_OK) return s;
+    if ((s = build_records<R>(p, l, tx, ty, tids, &b.tgt)) != VP_OK) return s;
+    if ((s = build_units(p, l)) != VP_OK) return s;
+    if ((s = build_level_tables<R>(p, l, phihat, p.delta1, p.delta2)) != VP_OK) return s;
+    return VP_OK;
+}
+
+// A feasible discretization of one level.
+struct LevelCand {
+    int F, w, M;
+    double P;       // period
+    double cost;    // static cost model (used without autotune)
+};
+
+// Geometry of level l for candidate c and tile edge T; phihat receives the
+// spreading kernel's transform at modes 0..M.
+vp_status set_level_geom(Plan& p, int l, const LevelCand& c, int T, double cx, double cy,
+                         std::vector<double>& phihat)
+{
+    LevelGeom& g = p.lv[l];
+    g.F = c.F;
+    g.logF = ilog2(c.F);
+    g.M = c.M;
+    g.w = c.w;
+    g.period = c.P;
+    g.dk = 2.0 * M_PI / c.P;
+    g.h = c.P / c.F;
+    g.x0 = cx - 0.5 * c.P;
+    g.y0 = cy - 0.5 * c.P;
+    const double sigma = (double)c.F / (2.0 * c.M + 1.0);
+    g.beta = 0.97 * M_PI * c.w * (1.0 - 0.5 / sigma);
+    while (T > c.F) T /= 2;
+    if (T < 1 || c.F % T) return fail(VP_ERR_ARG, "tile must divide the fine grid");
+    g.T = T;
+    g.ntx = c.F / T;
+    phihat = kernel_ft(c.w, g.beta, c.F, c.M);
+    for (double v : phihat)
+        if (!(v > 0)) return fail(VP_ERR_INTERNAL, "spreading kernel transform not positive");
+    return VP_OK;
+}
+
+bool level_fits_lds(const Plan& p, int l)
+{
+    const size_t lim = 160 * 1024;
+    return row_fft_lds_bytes(p, l) <= lim && col_fft_lds_bytes(p, l) <= lim && spread_lds_bytes(p, l) <= lim &&
+           interp_lds_bytes_of(p, l) <= lim;
+}
+
+// Release what build_level allocated (allocations made after index mark).
+void drop_level(Plan& p, int l, size_t mark, size_t bytes_before)
+{
+    for (size_t i = mark; i < p.allocs.size(); ++i) hipFree(p.allocs[i]);
+    p.allocs.resize(mark);
+    p.device_bytes = bytes_before;
+    p.lb[l] = LevelBufs{};
+}
+
+// Device time (ms, best of 3 after one warm-up) of one level's kernels:
+// grid zeroing, strengths, spread, row FFT, column pass, row inverse FFT and
+// interpolation, with the node weights standing in for the densities.
+vp_status time_level(Plan& p, int l, double* ms)
+{
+    const LevelGeom& g = p.lv[l];
+    const size_t rb = p.precision == VP_FP32 ? sizeof(float) : sizeof(double);
+    const size_t F = g.F, M1 = g.M + 1;
+    const int64_t nstr = p.n_src + p.n_bnd + ((p.kinds & VP_KIND_D) ? 2 * p.n_bnd : 0);
+    size_t off = 0;
+    const size_t o_grid = off;
+    off += align256(F * F * rb);
+    const size_t o_spec = off;
+    off += align256(M1 * F * 2 * rb);
+    const size_t o_hist = off;
+    off += align256((size_t)std::max<int64_t>(p.n_tgt, 1) * rb);
+    const size_t o_str = off;
+    off += align256((size_t)std::max<int64_t>(nstr, 1) * rb);
+    const size_t o_dc = off;
+    off += 256;
+    unsigned char* blk = nullptr;
+    VP_HIP(hipMalloc((void**)&blk, off), "autotune workspace");
+    Workspace ws;
+    ws.block = blk;
+    ws.bytes = off;
+    ws.grid[l] = blk + o_grid;
+    ws.spec[l] = blk + o_spec;
+    ws.hist[l] = blk + o_hist;
+    ws.str = blk + o_str;
+    ws.dc = (double*)(blk + o_dc);
+    const bool uv = (p.kinds & VP_KIND_V) && p.n_src > 0;
+    const bool ub = (p.kinds & (VP_KIND_S | VP_KIND_D)) && p.n_bnd > 0;
+    const bool ud = (p.kinds & VP_KIND_D) && p.n_bnd > 0;
+    const double* f = uv ? p.d_w : nullptr;
+    const double* sig = ub && !ud ? p.d_w + p.n_src : nullptr;
+    const double* mu = ud ? p.d_w + p.n_src : nullptr;
+    hipStream_t st = p.stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    double best = INFINITY;
+    for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+        err = hipEventRecord(e0, st);
+        if (err == hipSuccess) err = launch_zero_dc(p, ws, st);
+        if (err == hipSuccess) err = launch_zero_grids(p, ws, st);
+        if (err == hipSuccess) err = launch_strengths(p, ws, st, f, sig, mu);
+        if (err == hipSuccess) err = launch_spread(p, ws, st, l, uv, ub, ud);
+        if (err == hipSuccess) err = launch_row_fft(p, ws, st, l);
+        if (err == hipSuccess) err = launch_col_fft(p, ws, st, l);
+        if (err == hipSuccess) err = launch_row_ifft(p, ws, st, l);
+        if (err == hipSuccess) err = launch_interp(p, ws, st, l);
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        if (err == hipSuccess && rep > 0) best = std::min(best, (double)t);
     }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(blk);
+    if (err != hipSuccess) return fail(VP_ERR_DEVICE, std::string("autotune timing: ") + hipGetErrorString(err));
+    *ms = best;
     return VP_OK;
 }
 
@@ -399,8 +532,8 @@ vp_status build_plan_t(Plan& p, const std::vector<double>& sxv, const std::vecto
 
 vp_status set_error(vp_status s, const std::string& msg) { return fail(s, msg); }
 
-// Workspace layout: grid, spec, spec2, hist per level, then strengths and dc,
-// each 256-byte aligned inside one allocation.
+// Workspace layout: grid, spec, hist per level, then strengths and dc, each
+// 256-byte aligned inside one allocation.
 static size_t workspace_layout(const Plan& p, Workspace* ws, unsigned char* base)
 {
     const size_t rb = p.precision == VP_FP32 ? sizeof(float) : sizeof(double);
@@ -412,12 +545,12 @@ static size_t workspace_layout(const Plan& p, Workspace* ws, unsigned char* base
     for (int l = 0; l < 2; ++l) {
         const LevelGeom& g = p.lv[l];
         const size_t F = g.F, M1 = g.M + 1;
-        take(ws ? &ws->grid[l] : nullptr, (size_t)p.cmax * F * F * rb);
-        take(ws ? &ws->spec[l] : nullptr, (size_t)p.cmax * M1 * F * 2 * rb);
-        take(ws ? &ws->spec2[l] : nullptr, M1 * F * 2 * rb);
+        take(ws ? &ws->grid[l] : nullptr, F * F * rb);
+        take(ws ? &ws->spec[l] : nullptr, M1 * F * 2 * rb);
         take(ws ? &ws->hist[l] : nullptr, (size_t)std::max<int64_t>(p.n_tgt, 1) * rb);
     }
-    take(ws ? &ws->str : nullptr, (size_t)p.cmax * std::max<int64_t>(p.n_src + p.n_bnd, 1) * rb);
+    const int64_t nstr = p.n_src + p.n_bnd + ((p.kinds & VP_KIND_D) ? 2 * p.n_bnd : 0);
+    take(ws ? &ws->str : nullptr, (size_t)std::max<int64_t>(nstr, 1) * rb);
     void* dcp = nullptr;
     take(ws ? &dcp : nullptr, sizeof(double));
     if (ws) ws->dc = (double*)dcp;
@@ -463,7 +596,6 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
     if (use_s && !sigma_jet3) return fail(VP_ERR_ARG, "sigma_jet3 is required with sigma");
     if (use_d && !mu_jet5) return fail(VP_ERR_ARG, "mu_jet5 is required with mu");
     if (!ws.block) return fail(VP_ERR_ARG, "no workspace");
-    const int C = use_d ? 3 : 1;
     if (timing && !p.ev_made) {
         for (auto& e : p.ev) VP_HIP(hipEventCreate(&e), "event create");
         p.ev_made = true;
@@ -471,18 +603,19 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
     auto mark = [&](int k) -> hipError_t { return timing ? hipEventRecord(p.ev[k], st) : hipSuccess; };
     VP_HIP(mark(0), "event");
     VP_HIP(launch_zero_dc(p, ws, st), "zero dc");
-    VP_HIP(launch_strengths(p, ws, st, f, sigma, mu, C), "strengths");
+    VP_HIP(launch_zero_grids(p, ws, st), "zero grids");
+    VP_HIP(launch_strengths(p, ws, st, f, sigma, mu), "strengths");
     VP_HIP(mark(1), "event");
     for (int l = 0; l < 2; ++l) {
-        VP_HIP(launch_spread(p, ws, st, l, C, use_v, use_s || use_d), "spread");
+        VP_HIP(launch_spread(p, ws, st, l, use_v, use_s || use_d, use_d), "spread");
         VP_HIP(mark(2 + l), "event");
     }
     for (int l = 0; l < 2; ++l) {
-        VP_HIP(launch_row_fft(p, ws, st, l, C), "row fft");
+        VP_HIP(launch_row_fft(p, ws, st, l), "row fft");
         VP_HIP(mark(4 + l), "event");
     }
     for (int l = 0; l < 2; ++l) {
-        VP_HIP(launch_col_fft(p, ws, st, l, C), "column fft");
+        VP_HIP(launch_col_fft(p, ws, st, l), "column fft");
         VP_HIP(mark(6 + l), "event");
     }
     for (int l = 0; l < 2; ++l) {
@@ -517,6 +650,7 @@ void vp_opts_default(vp_opts* o)
     o->order_d = 3;
     o->kinds = VP_KIND_V | VP_KIND_S | VP_KIND_D;
     o->no_workspace = 0;
+    o->autotune = 0;
 }
 
 const char* vp_last_error(void) { return g_last_error.c_str(); }
@@ -672,23 +806,25 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
     const double kmax[2] = {kmax_for(p->delta1, p->eps, pk),
                             kmax_for(p->delta2, p->eps / std::max(1.0, p->L * p->L), pk)};
     double period[2] = {E + R, E + p->L + R};
-    const int Cmax = (o.kinds & VP_KIND_D) ? 3 : 1;
     const int64_t n_pts = ((o.kinds & VP_KIND_V) ? n_src : 0) + (need_b ? n_bnd : 0);
     const int Fmax = (o.precision == VP_FP32) ? 8192 : 4096;
-    std::vector<std::vector<double>> phihat(2);
+    std::vector<LevelCand> cands[2];
     for (int l = 0; l < 2; ++l) {
-        LevelGeom& g = p->lv[l];
-        const double eps_s = p->eps * 0.1;
-        int bestF = 0, bestw = 0, bestM = 0;
-        double bestP = 0, bestcost = INFINITY;
-        for (int attempt = 0; attempt < 4 && bestF == 0; ++attempt) {
+        // The double layer is spread with the derivative of the spreading kernel,
+        // whose aliasing error is amplified relative to the kernel's own; the
+        // far-history multiplier weights the lowest wavenumbers most, where the
+        // amplification is largest, so that level gets a 20x tighter kernel
+        // tolerance (on the square workload one extra tap of width takes the
+        // double-layer error from 1.3e-10 to 6e-12).
+        const double eps_s = p->eps * 0.1 / ((l == 1 && (o.kinds & VP_KIND_D)) ? 20.0 : 1.0);
+        for (int attempt = 0; attempt < 4 && cands[l].empty(); ++attempt) {
             const double P = period[l] * (1.0 + 0.02 * attempt);
             const double dk = 2.0 * M_PI / P;
             const int M = (int)std::ceil(kmax[l] / dk);
             const int nmodes = 2 * M + 1;
             int F0 = 64;
             while (F0 < (int)std::ceil(1.2 * nmodes)) F0 *= 2;
-            const int Flim = o.spread_width[l] > 0 ? Fmax : std::min(4 * F0, Fmax);
+            const int Flim = (o.spread_width[l] > 0 || o.fine_grid[l] > 0) ? Fmax : std::min(4 * F0, Fmax);
             for (int F = F0; F <= Flim; F *= 2) {
                 if (o.fine_grid[l] > 0 && F != o.fine_grid[l]) continue;
                 const double sigma = (double)F / (double)nmodes;
@@ -700,39 +836,16 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
                 const double h = P / F;
                 // keep every support inside the grid without wrap-around
                 if ((P - E) * 0.5 < (0.5 * w + 2.0) * h) continue;
-                const double cost = (double)F * F * Cmax * 12.0 + (double)n_pts * w * w * 1.5 +
+                const double cost = (double)F * F * 12.0 + (double)n_pts * w * w * 1.5 +
                                     (double)n_tgt * w * w * 1.0;
-                if (cost < bestcost) {
-                    bestcost = cost;
-                    bestF = F;
-                    bestw = w;
-                    bestM = M;
-                    bestP = P;
-                }
+                cands[l].push_back({F, w, M, P, cost});
             }
         }
-        if (bestF == 0)
+        if (cands[l].empty())
             return bail(fail(VP_ERR_TOL, "no supported fine grid meets the tolerance (level " + std::to_string(l) +
                                              ")"));
-        g.F = bestF;
-        g.logF = ilog2(bestF);
-        g.M = bestM;
-        g.w = bestw;
-        g.period = bestP;
-        g.dk = 2.0 * M_PI / bestP;
-        g.h = bestP / bestF;
-        g.x0 = cx - 0.5 * bestP;
-        g.y0 = cy - 0.5 * bestP;
-        const double sigma = (double)bestF / (2.0 * bestM + 1.0);
-        g.beta = 0.97 * M_PI * bestw * (1.0 - 0.5 / sigma);
-        int T = o.tile > 0 ? o.tile : 32;
-        while (T > bestF) T /= 2;
-        if (bestF % T) return bail(fail(VP_ERR_ARG, "tile must divide the fine grid"));
-        g.T = T;
-        g.ntx = bestF / T;
-        phihat[l] = kernel_ft(bestw, g.beta, bestF, bestM);
-        for (double v : phihat[l])
-            if (!(v > 0)) return bail(fail(VP_ERR_INTERNAL, "spreading kernel transform not positive"));
+        std::stable_sort(cands[l].begin(), cands[l].end(),
+                         [](const LevelCand& a2, const LevelCand& b2) { return a2.cost < b2.cost; });
     }
 
     // ---- spread sources: volume nodes then boundary nodes
@@ -763,22 +876,60 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
         if (!g4.empty() && (s = upload(*p, &p->g_g4, g4, "geom")) != VP_OK) return bail(s);
         if ((s = upload(*p, &p->g_sgn, gs, "geom")) != VP_OK) return bail(s);
     }
-    s = (o.precision == VP_FP32) ? build_plan_t<float>(*p, ax, ay, vol_ids, bnd_ids, tx, ty, phihat)
-                                 : build_plan_t<double>(*p, ax, ay, vol_ids, bnd_ids, tx, ty, phihat);
-    if (s != VP_OK) return bail(s);
-    p->cmax = Cmax;
+
+    // ---- levels: static cost model, or measured selection (opts.autotune)
+    const bool fp32 = o.precision == VP_FP32;
+    auto build = [&](int l, const std::vector<double>& ph) {
+        return fp32 ? build_level<float>(*p, l, ax, ay, vol_ids, bnd_ids, tx, ty, ph)
+                    : build_level<double>(*p, l, ax, ay, vol_ids, bnd_ids, tx, ty, ph);
+    };
+    std::vector<int> tiles;
+    if (o.tile > 0) tiles.push_back(o.tile);
+    else if (o.autotune) tiles = {32, 16};
+    else tiles.push_back(32);
+    p->autotuned = o.autotune ? 1 : 0;
+    for (int l = 0; l < 2; ++l) {
+        std::vector<double> ph;
+        int best_c = -1, best_T = 0;
+        if (o.autotune) {
+            double best_ms = INFINITY;
+            for (size_t ci = 0; ci < cands[l].size(); ++ci)
+                for (int T : tiles) {
+                    if ((s = set_level_geom(*p, l, cands[l][ci], T, cx, cy, ph)) != VP_OK) return bail(s);
+                    if (!level_fits_lds(*p, l)) continue;
+                    const size_t mark = p->allocs.size(), bytes0 = p->device_bytes;
+                    if ((s = build(l, ph)) != VP_OK) return bail(s);
+                    double ms = INFINITY;
+                    s = time_level(*p, l, &ms);
+                    drop_level(*p, l, mark, bytes0);
+                    if (s != VP_OK) return bail(s);
+                    p->tune_cands[l]++;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best_c = (int)ci;
+                        best_T = T;
+                    }
+                }
+            p->level_ms[l] = best_ms;
+        } else {
+            for (size_t ci = 0; ci < cands[l].size() && best_c < 0; ++ci) {
+                if ((s = set_level_geom(*p, l, cands[l][ci], tiles[0], cx, cy, ph)) != VP_OK) return bail(s);
+                if (level_fits_lds(*p, l)) {
+                    best_c = (int)ci;
+                    best_T = tiles[0];
+                }
+            }
+        }
+        if (best_c < 0) return bail(fail(VP_ERR_TOL, "working set too large for LDS"));
+        if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy, ph)) != VP_OK) return bail(s);
+        if ((s = build(l, ph)) != VP_OK) return bail(s);
+    }
     if (!o.no_workspace) {
         hipError_t e = workspace_alloc(*p, p->ws, p->stream, false);
         if (e != hipSuccess)
             return bail(fail(e == hipErrorOutOfMemory ? VP_ERR_OOM : VP_ERR_DEVICE,
                              std::string("workspace: ") + hipGetErrorString(e)));
         p->device_bytes += p->ws.bytes;
-    }
-    for (int l = 0; l < 2; ++l) {
-        const size_t lds_row = row_fft_lds_bytes(*p, l), lds_col = col_fft_lds_bytes(*p, l);
-        const size_t lds_sp = spread_lds_bytes(*p, l, Cmax, need_b);
-        if (lds_row > 160 * 1024 || lds_col > 160 * 1024 || lds_sp > 160 * 1024)
-            return bail(fail(VP_ERR_TOL, "working set too large for LDS"));
     }
     *out = p;
     return VP_OK;
@@ -842,6 +993,11 @@ vp_status vp_get_plan_info(vp_plan_t p, vp_plan_info* info)
     info->n_tgt = p->n_tgt;
     info->device_bytes = p->device_bytes;
     info->workspace_bytes = workspace_bytes(*p);
+    info->autotuned = p->autotuned;
+    for (int l = 0; l < 2; ++l) {
+        info->tune_candidates[l] = p->tune_cands[l];
+        info->level_ms[l] = p->level_ms[l];
+    }
     return VP_OK;
 }
 

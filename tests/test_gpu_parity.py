@@ -55,3 +55,72 @@ def test_disk_fp32_volume_matches_oracle():
     e = oracle.rel_linf(got, ref)
     print("disk fp32 e_inf", e, plan.info())
     assert e <= 1e-6
+
+
+def test_star_fp32_all_kinds_match_oracle():
+    P = star_problem(1500, seed=6)
+    for kinds in ("S", "D", "VSD"):
+        mask = (1 if "V" in kinds else 0) | (2 if "S" in kinds else 0) | (4 if "D" in kinds else 0)
+        got, plan = _run(P, kinds, tol=1e-6, precision=0, kinds=mask)
+        ref = oracle.evaluate(P, kinds=kinds)["total"]
+        e = oracle.rel_linf(got, ref)
+        print("star fp32", kinds, "e_inf", e)
+        assert e <= 1e-6, (kinds, e)
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-10), (0, 1e-6)])
+def test_autotuned_plans_match_oracle(precision, tol):
+    """The measured level selection changes grids, widths and tiles, never the result."""
+    P = star_problem(4000, seed=7)
+    got, plan = _run(P, "VSD", tol=tol, precision=precision, kinds=7, autotune=True)
+    info = plan.info()
+    assert info["autotuned"] and min(info["tune_candidates"]) >= 1
+    ref = oracle.evaluate(P, kinds="VSD")["total"]
+    e = oracle.rel_linf(got, ref)
+    print("autotuned", precision, "e_inf", e, info["fine"], info["width"], info["tile"], info["level_ms"])
+    assert e <= tol
+
+
+def test_boundary_only_layer_plan():
+    """No volume nodes: delta_1 from the boundary spacing, S + D only."""
+    P = star_problem(1500, seed=8)
+    P.src_x = P.src_x[:0]
+    P.src_y = P.src_y[:0]
+    P.src_w = P.src_w[:0]
+    P.f_src = None
+    got, plan = _run(P, "SD", tol=1e-10, kinds=6)
+    ref = oracle.evaluate(P, kinds="SD")["total"]
+    e = oracle.rel_linf(got, ref)
+    print("boundary-only e_inf", e, plan.info()["delta1"])
+    assert e <= 1e-10
+
+
+def test_largest_float32_grid():
+    """F = 8192 (the largest float32 fine grid) with a ragged target count."""
+    P = disk_problem(1500, seed=9)
+    idx = np.arange(0, P.n_tgt, 3)
+    P = P.subset_targets(idx)
+    got, plan = _run(P, "V", tol=1e-6, precision=0, kinds=1, fine_grid=(8192, 0))
+    assert plan.info()["fine"][0] == 8192
+    ref = oracle.evaluate(P, kinds="V")["V"]
+    e = oracle.rel_linf(got, ref)
+    print("F=8192 e_inf", e)
+    assert e <= 1e-6
+
+
+@pytest.mark.parametrize("workload", ["square-200k V+D fp64", "disk-2M V fp32"])
+def test_full_size_sampled_parity(workload):
+    """Full benchmark sizes in the benchmark's launch configuration (autotuned
+    plans), checked on seeded target samples the oracle computes one by one."""
+    from workloads import config_problem
+    if workload.startswith("square"):
+        P, kinds, mask, tol, prec = config_problem(2), "VD", 5, 1e-10, 1
+    else:
+        P, kinds, mask, tol, prec = config_problem(3), "V", 1, 1e-6, 0
+    got, plan = _run(P, kinds, tol=tol, precision=prec, kinds=mask, autotune=True)
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(P.n_tgt, size=64, replace=False))
+    ref = oracle.evaluate(P.subset_targets(idx), kinds=kinds)["total"]
+    e = float(np.max(np.abs(got[idx] - ref)) / np.max(np.abs(ref)))
+    print(workload, "sampled e_inf", e, plan.info()["fine"], plan.info()["width"])
+    assert e <= tol
