@@ -53,6 +53,7 @@ struct InstDesc {
     const double* nx;
     const double* ny;
     double* dc;
+    unsigned long long* smax;
     void* str;
     dev::LocalArgs loc;  // geometry pointers and constants; per-call fields filled from CallDesc
     int has_vol, has_bnd;
@@ -83,7 +84,10 @@ template <typename R> __device__ inline RecView<R> tgt_view(const LevelDesc& d)
 
 __global__ void kb_zero_dc(const InstDesc* __restrict__ inst, int n)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) *inst[i].dc = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * kDcParts; i += gridDim.x * blockDim.x) {
+        inst[i / kDcParts].dc[i % kDcParts] = 0.0;
+        if (i % kDcParts < 2) inst[i / kDcParts].smax[i % kDcParts] = 0ull;
+    }
 }
 
 constexpr int kZeroChunk = kThreads * 64;  // grid cells per zeroing work unit
@@ -110,7 +114,8 @@ __global__ __launch_bounds__(kThreads) void kb_strengths(const InstDesc* __restr
         const Item x = items[it];
         const InstDesc& I = inst[x.inst];
         const CallDesc& K = call[x.inst];
-        dev::dev_strengths<R>(I.n_src, I.n_bnd, K.f, K.sigma, K.mu, I.w, I.nx, I.ny, (R*)I.str, I.dc, x.unit);
+        dev::dev_strengths<R>(I.n_src, I.n_bnd, K.f, K.sigma, K.mu, I.w, I.nx, I.ny, (R*)I.str,
+                              sizeof(R) == 4 ? I.dc : nullptr, I.smax, x.unit);
     }
 }
 
@@ -127,7 +132,7 @@ __global__ __launch_bounds__(kThreads) void kb_spread(const InstDesc* __restrict
         const LevelDesc& D = lv[2 * x.inst + x.level];
         const LevelGeom g = D.g;
         dev::dev_spread<R, W>(smem_raw, g, vol_view<R>(D), bnd_view<R>(D), (const R*)I.str, I.n_src, I.n_bnd,
-                              (R*)D.grid, use_vol && I.has_vol, use_bnd && I.has_bnd, use_d, D.horner,
+                              (R*)D.grid, use_vol && I.has_vol, use_bnd && I.has_bnd, use_d, D.horner, I.smax,
                               D.sp_units[x.unit]);
         __syncthreads();
     }
@@ -268,7 +273,7 @@ template <typename R>
 hipError_t launch_all(vp_batch_s& b, int use_v, int use_s, int use_d)
 {
     hipStream_t st = b.stream;
-    hipLaunchKernelGGL(kb_zero_dc, dim3(std::max(1, (b.n + 255) / 256)), dim3(256), 0, st, b.d_inst, b.n);
+    hipLaunchKernelGGL(kb_zero_dc, dim3(std::max(1, (b.n * kDcParts + 255) / 256)), dim3(256), 0, st, b.d_inst, b.n);
     const Item* it = b.d_items;
     hipLaunchKernelGGL(kb_zero<R>, dim3(persistent_grid(b, b.cnt[ST_ZERO], 8)), dim3(kThreads), 0, st, b.d_lv,
                        it + b.off[ST_ZERO], b.cnt[ST_ZERO]);
@@ -395,6 +400,7 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
         I.nx = p.d_nx;
         I.ny = p.d_ny;
         I.dc = p.ws.dc;
+        I.smax = p.ws.smax;
         I.str = p.ws.str;
         I.has_vol = p.lb[0].vol.start != nullptr;
         I.has_bnd = p.lb[0].bnd.start != nullptr;

@@ -129,17 +129,17 @@ __device__ void lds_fft_dif(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw
 // for boundary node j (n = all nodes, nb = boundary nodes; present only when
 // mu is given).  Also accumulates sum(str[0..n)) in float64 (the
 // zero-frequency term).
-constexpr int kStrChunk = kThreads * 8;  // nodes per strengths work unit
+constexpr int kStrChunk = kThreads * 16;  // nodes per strengths work unit
 
 template <typename R>
 __device__ void dev_strengths(int64_t n_src, int64_t n_bnd, const double* __restrict__ f,
                               const double* __restrict__ sigma, const double* __restrict__ mu,
                               const double* __restrict__ w, const double* __restrict__ nx,
                               const double* __restrict__ ny, R* __restrict__ str, double* __restrict__ dc,
-                              int64_t unit)
+                              unsigned long long* __restrict__ smax, int64_t unit)
 {
     const int64_t n = n_src + n_bnd;
-    double part = 0.0;
+    double part = 0.0, m0 = 0.0, m1 = 0.0;
     const int64_t i1 = min(n, (unit + 1) * (int64_t)kStrChunk);
     for (int64_t i = unit * (int64_t)kStrChunk + threadIdx.x; i < i1; i += blockDim.x) {
         double s0 = 0.0;
@@ -151,16 +151,45 @@ __device__ void dev_strengths(int64_t n_src, int64_t n_bnd, const double* __rest
             if (sigma) s0 = sigma[j] * wg;
             if (mu) {
                 const double m = mu[j] * wg;
-                str[n + j] = (R)(m * nx[j]);
-                str[n + n_bnd + j] = (R)(m * ny[j]);
+                const R gx = (R)(m * nx[j]), gy = (R)(m * ny[j]);
+                str[n + j] = gx;
+                str[n + n_bnd + j] = gy;
+                m1 = fmax(m1, fabs((double)gx) + fabs((double)gy));
             }
         }
-        str[i] = (R)s0;
+        const R sr = (R)s0;
+        str[i] = sr;
         part += s0;
+        m0 = fmax(m0, fabs((double)sr));
     }
-    // wave reduction, then one float64 atomic per wave
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-    if ((threadIdx.x & 63) == 0 && part != 0.0) atomicAdd(dc, part);
+    // workgroup reductions (wavefront shuffles, then LDS): the zero-frequency sum
+    // (one float64 atomic per unit into one of kDcParts partial sums) and the
+    // strength maxima the spread scales its fixed-point windows by (unsigned
+    // atomic max on the bit patterns of non-negative doubles)
+    __shared__ double red[3][kThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        part += __shfl_xor(part, o);
+        m0 = fmax(m0, __shfl_xor(m0, o));
+        m1 = fmax(m1, __shfl_xor(m1, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = part;
+        red[1][threadIdx.x >> 6] = m0;
+        red[2][threadIdx.x >> 6] = m1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0, a = 0.0, b = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+            t += red[0][k];
+            a = fmax(a, red[1][k]);
+            b = fmax(b, red[2][k]);
+        }
+        if (dc && t != 0.0) atomicAdd(dc + (unit % kDcParts), t);
+        if (a > 0.0) atomicMax(smax, (unsigned long long)__double_as_longlong(a));
+        if (b > 0.0) atomicMax(smax + 1, (unsigned long long)__double_as_longlong(b));
+    }
+    __syncthreads();
 }
 
 // Zero fill of a spread grid (the spread accumulates into it with atomics).
@@ -180,10 +209,19 @@ __device__ void dev_zero(R* __restrict__ p, int64_t n, int64_t i)
 // the window to the grid with global atomics (the grid is zeroed first); the
 // windows of neighbouring tiles overlap by w-1 cells.
 //
-// The window accumulates with float64 LDS atomics in both precisions: on
-// gfx950 a 64-lane ds_add_f32 costs ~190 cycles per CU against ~8.5 for
-// ds_add_f64 (measured), so float32 plans form their products in float32 and
-// round the window to float32 once, when it is added to the grid.
+// Window accumulation (measured on gfx950, cycles per 64-lane LDS atomic per
+// CU: ds_add_u32 4.4, ds_add_u64 6.5, ds_add_f64 8.5, ds_add_f32 ~190):
+//  - float64 plans: float64 atomics;
+//  - float32 plans: 64-bit fixed point (int64 atomics).  Integer sums are
+//    exact and independent of the order of the atomics.  Each unit's scale
+//    comes from a bound on its window values, cover * max contribution, where
+//    cover (from the planner) is the most records of the unit sharing one cell
+//    and the maximum contribution follows from the evaluation's largest
+//    strengths (|phi| <= 1, |d phi/dy| <= dmax); a contribution v becomes
+//    round(v q) with q = 2^49 / bound.  The double-layer terms make the bound
+//    up to ~1e4 times the volume contributions near a boundary; the 49-bit
+//    range still resolves those to ~1e-11, far below float32 rounding (a
+//    32-bit window, with 29 bits, would not).
 //
 // Single-strength nodes (volume nodes, and boundary nodes without a double
 // layer): each wavefront takes chunks of 32 of the tile's nodes; lane pairs
@@ -214,13 +252,14 @@ __host__ __device__ inline int spread_pitch(int T, int W)
     return E | 1;  // odd pitch: consecutive rows start in different LDS banks
 }
 
-// Dynamic LDS layout of the spread (bytes): float64 window | per wave: kernel
-// values of a chunk (2 w per node; 4 w per double-layer node: x, y taps and
-// their derivatives) and the chunk's offsets.
+// Dynamic LDS layout of the spread (bytes): window of 8-byte cells (int64 for
+// float32 plans, float64 for float64 plans) | per wave: kernel values of a chunk
+// (2 w per node; 4 w per double-layer node: x, y taps and their derivatives)
+// and the chunk's offsets.
 __host__ __device__ inline size_t spread_lds_layout(int T, int W, size_t rb, size_t* off_stage)
 {
     const int E = T + W - 1;
-    const size_t win = ((size_t)E * spread_pitch(T, W) * sizeof(double) + 15) & ~(size_t)15;
+    const size_t win = ((size_t)E * spread_pitch(T, W) * 8 + 15) & ~(size_t)15;  // 8-byte cells
     const int recs = rb == 4 ? SpreadShape<float>::kRecs : SpreadShape<double>::kRecs;
     const size_t stage = (size_t)SpreadShape<float>::kWaves * (recs * 2 * W + 2 * recs) * rb;
     *off_stage = win;
@@ -261,11 +300,37 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Window cell type and conversions (see above).
+template <typename R> struct FixedPoint;
+template <> struct FixedPoint<float> {
+    using T = unsigned long long;
+    static constexpr bool kScaled = true;
+    static constexpr double kRange = 562949953421312.0;  // 2^49
+    // round(v) via the 1.5 2^52 shift: exact for |v| < 2^51
+    __device__ static T enc(float v)
+    {
+        const double t = (double)v + 6755399441055744.0;
+        return (T)(__double_as_longlong(t) - 0x4338000000000000LL);
+    }
+    __device__ static double dec(T a, double inv_q) { return (double)(long long)a * inv_q; }
+};
+template <> struct FixedPoint<double> {
+    using T = double;
+    static constexpr bool kScaled = false;
+    static constexpr double kRange = 1.0;
+    __device__ static T enc(double v) { return v; }
+    __device__ static double dec(T a, double) { return a; }
+};
+
 template <typename R, int W>
 __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const RecView<R>& vol, const RecView<R>& bnd,
                            const R* __restrict__ str, int64_t n_src, int64_t n_bnd, R* __restrict__ grid,
-                           int use_vol, int use_bnd, int use_d, const double* __restrict__ coef, const WorkUnit unit)
+                           int use_vol, int use_bnd, int use_d, const double* __restrict__ coef,
+                           const unsigned long long* __restrict__ smax, const WorkUnit unit)
 {
+    using FP = FixedPoint<R>;
+    using A = typename FP::T;
+    static_assert(sizeof(A) == 8, "spread_lds_layout sizes the window for 8-byte cells");
     using SS = SpreadShape<R>;
     constexpr int NW = SS::kWaves;
     constexpr int RECS = SS::kRecs;
@@ -281,9 +346,20 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
     const int nv = use_vol ? unit.a1 - unit.a0 : 0;
     const int nbd = use_bnd ? unit.b1 - unit.b0 : 0;
     if (nv == 0 && nbd == 0) return;  // nothing lands in this unit (uniform across the workgroup)
+    // scale of this unit's fixed-point window (float32 plans)
+    R q = R(1);
+    double inv_q = 1.0;
+    if constexpr (FP::kScaled) {
+        const double cmax = __longlong_as_double((long long)smax[0]) +
+                            (use_d ? __longlong_as_double((long long)smax[1]) * g.dmax : 0.0);
+        const double bound = 1.01 * (double)unit.cover * cmax;
+        if (!(bound > 0.0)) return;  // every contribution is zero
+        q = (R)(FP::kRange / bound);
+        inv_q = 1.0 / (double)q;
+    }
     size_t off_st;
     spread_lds_layout(T, W, sizeof(R), &off_st);
-    double* win = reinterpret_cast<double*>(smem_raw);
+    A* win = reinterpret_cast<A*>(smem_raw);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     R* vals = reinterpret_cast<R*>(smem_raw + off_st) + (size_t)wv * (VST + 2 * RECS);
@@ -291,7 +367,7 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
 
     const int gx0 = (t % g.ntx) * T;
     const int gy0 = (t / g.ntx) * T;
-    for (int i = threadIdx.x; i < E * EP; i += blockDim.x) win[i] = 0.0;
+    for (int i = threadIdx.x; i < E * EP; i += blockDim.x) win[i] = A(0);
     __syncthreads();
 
     // tap of this lane: column ta, rows tb0 + k RW (k < NI)
@@ -398,19 +474,19 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
                 const R s = lane_value(c_s, rr);
                 const int i0 = (p & 0xffff) - gx0;
                 const int j0 = (p >> 16) - gy0;
-                double* row = win + (j0 + tb0) * EP + i0 + ta;
+                A* row = win + (j0 + tb0) * EP + i0 + ta;
                 if constexpr (DL) {
                     const R gx = lane_value(c_gx, rr), gy = lane_value(c_gy, rr);
-                    const R sx = s * vx, gxx = gx * dvx, gyx = gy * vx;
+                    const R sx = s * vx * q, gxx = gx * dvx * q, gyx = gy * vx * q;
 #pragma unroll
                     for (int k = 0; k < NI; ++k)
                         if (lane_on && tb0 + k * RW < W)
-                            atomicAdd(row + k * RW * EP, (double)(sx * vy[k] + gxx * vy[k] + gyx * dvy[k]));
+                            atomicAdd(row + k * RW * EP, FP::enc(sx * vy[k] + gxx * vy[k] + gyx * dvy[k]));
                 } else {
-                    const R vxs = vx * s;
+                    const R vxs = vx * s * q;
 #pragma unroll
                     for (int k = 0; k < NI; ++k)
-                        if (lane_on && tb0 + k * RW < W) atomicAdd(row + k * RW * EP, (double)(vxs * vy[k]));
+                        if (lane_on && tb0 + k * RW < W) atomicAdd(row + k * RW * EP, FP::enc(vxs * vy[k]));
                 }
                 vx = vxn;
                 dvx = dvxn;
@@ -434,8 +510,8 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
         const int x = i - y * E;
         const int gx = gx0 + x, gy = gy0 + y;
         if (gx < F && gy < F) {
-            const double v = win[y * EP + x];
-            if (v != 0.0) unsafeAtomicAdd(grid + (size_t)gy * F + gx, (R)v);
+            const A a = win[y * EP + x];
+            if (a != A(0)) unsafeAtomicAdd(grid + (size_t)gy * F + gx, (R)FP::dec(a, inv_q));
         }
     }
 }
@@ -671,6 +747,15 @@ struct LocalArgs {
     double* out;
 };
 
+// Sum of the kDcParts zero-frequency partial sums, by one wavefront (every
+// lane of the wavefront must call it).
+__device__ __forceinline__ double dc_total(const double* __restrict__ dc)
+{
+    double v = dc[threadIdx.x & 63];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 __device__ __forceinline__ double hist_at(const void* h, int fp32, int64_t i)
 {
     return fp32 ? (double)((const float*)h)[i] : ((const double*)h)[i];
@@ -678,6 +763,7 @@ __device__ __forceinline__ double hist_at(const void* h, int fp32, int64_t i)
 
 __device__ void dev_local(const LocalArgs& a, int64_t i)
 {
+    const double dcv = a.dc ? dc_total(a.dc) : 0.0;  // before any lane leaves
     if (i >= a.n) return;
     const double SQPI = 1.7724538509055160273;
     const double d = a.delta;
@@ -685,6 +771,21 @@ __device__ void dev_local(const LocalArgs& a, int64_t i)
     const double r = a.r[i];
     const double c = r / sd;
     const bool near = c <= 12.0;
+    double u = hist_at(a.h0, a.fp32, i) + hist_at(a.h1, a.fp32, i);
+    if (a.dc) u += a.dc_weight * dcv;
+    const int64_t n = a.n;
+    if (!near) {
+        // beyond 12 sqrt(delta): only the interior limit of V_L (frame and layer data not read)
+        if (a.jet6) {
+            const double f = a.jet6[i], lap = a.jet6[3 * n + i] + a.jet6[5 * n + i];
+            double v = 0.0;
+            if (a.order_v >= 2) v += d * f;
+            if (a.order_v >= 4) v += 0.5 * d * d * lap;
+            u += v;
+        }
+        a.out[i] = u;
+        return;
+    }
     const double kap = a.kappa[i];
     const double g3 = a.g3 ? a.g3[i] : 0.0;
     const double g4 = a.g4 ? a.g4[i] : 0.0;
@@ -692,38 +793,28 @@ __device__ void dev_local(const LocalArgs& a, int64_t i)
     const double E = erfc(0.5 * c);
     const double e = exp(-0.25 * c * c);
     const double c2 = c * c, c3 = c2 * c;
-    double u = hist_at(a.h0, a.fp32, i) + hist_at(a.h1, a.fp32, i);
-    if (a.dc) u += a.dc_weight * (*a.dc);
-    const int64_t n = a.n;
     if (a.jet6) {
         const double f = a.jet6[i], fx = a.jet6[n + i], fy = a.jet6[2 * n + i];
         const double fxx = a.jet6[3 * n + i], fxy = a.jet6[4 * n + i], fyy = a.jet6[5 * n + i];
-        const double lap = fxx + fyy;
         double v = 0.0;
-        if (!near) {
-            if (a.order_v >= 2) v += d * f;
-            if (a.order_v >= 4) v += 0.5 * d * d * lap;
-        } else {
-            const double ex = -a.nx[i], ey = -a.ny[i];     // inward normal (eta)
-            const double tx = a.ny[i], ty = -a.nx[i];      // tangent (xi), sign irrelevant
-            const double fe = fx * ex + fy * ey;
-            const double fee = fxx * ex * ex + 2.0 * fxy * ex * ey + fyy * ey * ey;
-            const double ftt = fxx * tx * tx + 2.0 * fxy * tx * ty + fyy * ty * ty;
-            if (a.order_v >= 2)
-                v += 0.25 * d * (2.0 * erf(0.5 * c) + 2.0 * e * c / SQPI - c2 * E + 2.0) * f;
-            if (a.order_v >= 3)
-                v += d * sd * ((4.0 - 2.0 * c2) * e + SQPI * c3 * E) * (2.0 * fe - kap * f) / (12.0 * SQPI);
-            if (a.order_v >= 4) {
-                const double c4 = c2 * c2;
-                v += d * d / 48.0 *
-                     (E * (4.0 * c4 * kap * fe - 3.0 * (c4 + 4.0) * fee + (c4 - 12.0) * ftt - 3.0 * c4 * kap * kap * f) +
-                      2.0 * c * (c2 - 2.0) * e * (-4.0 * kap * fe + 3.0 * fee - ftt + 3.0 * kap * kap * f) / SQPI +
-                      24.0 * (ftt + fee));
-            }
+        const double ex = -a.nx[i], ey = -a.ny[i];     // inward normal (eta)
+        const double tx = a.ny[i], ty = -a.nx[i];      // tangent (xi), sign irrelevant
+        const double fe = fx * ex + fy * ey;
+        const double fee = fxx * ex * ex + 2.0 * fxy * ex * ey + fyy * ey * ey;
+        const double ftt = fxx * tx * tx + 2.0 * fxy * tx * ty + fyy * ty * ty;
+        if (a.order_v >= 2) v += 0.25 * d * (2.0 * erf(0.5 * c) + 2.0 * e * c / SQPI - c2 * E + 2.0) * f;
+        if (a.order_v >= 3)
+            v += d * sd * ((4.0 - 2.0 * c2) * e + SQPI * c3 * E) * (2.0 * fe - kap * f) / (12.0 * SQPI);
+        if (a.order_v >= 4) {
+            const double c4 = c2 * c2;
+            v += d * d / 48.0 *
+                 (E * (4.0 * c4 * kap * fe - 3.0 * (c4 + 4.0) * fee + (c4 - 12.0) * ftt - 3.0 * c4 * kap * kap * f) +
+                  2.0 * c * (c2 - 2.0) * e * (-4.0 * kap * fe + 3.0 * fee - ftt + 3.0 * kap * kap * f) / SQPI +
+                  24.0 * (ftt + fee));
         }
         u += v;
     }
-    if (near && a.sj) {
+    if (a.sj) {
         const double s0 = a.sj[i], s1 = a.sj[n + i], s2 = a.sj[2 * n + i];
         const double P1 = c * E - 2.0 * e / SQPI;
         const double Q = 2.0 * (c2 - 2.0) * e / SQPI - c3 * E;
@@ -738,7 +829,7 @@ __device__ void dev_local(const LocalArgs& a, int64_t i)
                   c * kap * s2 / 8.0 * Q + c * s0 * g4 / 48.0 * Q + c * s1 * g3 / 12.0 * Q);
         u -= s;
     }
-    if (near && a.mj) {
+    if (a.mj) {
         const double m0 = a.mj[i], m1 = a.mj[n + i], m2 = a.mj[2 * n + i], m4 = a.mj[4 * n + i];
         double s = sg * 0.5 * m0 * E;
         if (a.order_d >= 1) s += sd * kap * m0 / (2.0 * SQPI) * e;

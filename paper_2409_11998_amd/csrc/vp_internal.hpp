@@ -14,6 +14,7 @@ namespace vp {
 constexpr int kWMax = 16;        // largest spreading width (grid cells per dimension)
 constexpr int kWMin = 4;         // smallest spreading width
 constexpr int kThreads = 256;    // threads per workgroup for grid kernels
+constexpr int kDcParts = 64;     // partial sums of the zero-frequency term (one wavefront reads them)
 // Launches timed by vp_set_timing, in order: grid zeroing + strengths; spread NH, FH; row FFT NH,
 // FH; column FFT NH, FH; row inverse NH, FH; interpolation NH, FH; local part.
 constexpr int kTimedLaunches = 12;
@@ -34,12 +35,14 @@ struct LevelGeom {
     double period;  // P
     double dk;      // 2 pi / P
     double dc_coef; // (dk/2pi)^2 * multiplier(0): the zero mode's kernel weight
+    double dmax;    // max over taps and offsets of |d/dy tap value| (double-layer spreading bound)
 };
 
 // A tile-sorted list of points of one level (CSR by tile): each point appears
 // once, in the tile holding its support corner (i0, j0).
 struct RecList {
     std::vector<int> h_start;  // host copy of start
+    std::vector<int> h_ij;     // host copy of ij
     int* start = nullptr;  // [ntiles+1]
     int* ij = nullptr;     // packed absolute support corner i0 | j0 << 16
     void* dx = nullptr;    // R: i0 - t_x + w/2, in [0, 1)
@@ -69,6 +72,7 @@ struct WorkUnit {
     int tile;
     int a0, a1;
     int b0, b1;
+    int cover;  // spreading: most records of the unit whose supports share one window cell
 };
 constexpr int kUnitNodes = 1024;     // volume nodes per spreading unit
 constexpr int kUnitBnd = 256;        // boundary nodes per spreading unit
@@ -95,7 +99,8 @@ struct Workspace {
     void* spec[2] = {nullptr, nullptr};   // cplx<R> [M+1][F] half spectra (x-frequency major)
     void* hist[2] = {nullptr, nullptr};   // R [n_tgt] history value at each target
     void* str = nullptr;                  // R [n_src + n_bnd (+ 2 n_bnd)] strengths (+ mu nu wG)
-    double* dc = nullptr;                 // [1] float64 sum of channel-0 strengths
+    double* dc = nullptr;                 // [kDcParts] float64 partial sums of the spread strengths
+    unsigned long long* smax = nullptr;   // [2] bit patterns of max |strength| and max |mu nu wG|_1
     void* block = nullptr;                // single allocation holding all of the above
     size_t bytes = 0;
 };

@@ -18,9 +18,9 @@ __global__ __launch_bounds__(kThreads) void k_strengths(int64_t n_src, int64_t n
                                                         const double* __restrict__ sigma, const double* __restrict__ mu,
                                                         const double* __restrict__ w, const double* __restrict__ nx,
                                                         const double* __restrict__ ny, R* __restrict__ str,
-                                                        double* __restrict__ dc)
+                                                        double* __restrict__ dc, unsigned long long* __restrict__ smax)
 {
-    dev_strengths<R>(n_src, n_bnd, f, sigma, mu, w, nx, ny, str, dc, blockIdx.x);
+    dev_strengths<R>(n_src, n_bnd, f, sigma, mu, w, nx, ny, str, dc, smax, blockIdx.x);
 }
 
 template <typename R>
@@ -31,9 +31,10 @@ __global__ __launch_bounds__(kThreads) void k_zero2(R* __restrict__ a, int64_t n
     dev_zero<R>(b, nb, i);
 }
 
-__global__ void k_zero_dc(double* dc)
+__global__ void k_zero_dc(double* dc, unsigned long long* smax)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *dc = 0.0;
+    if (threadIdx.x < kDcParts) dc[threadIdx.x] = 0.0;
+    if (threadIdx.x < 2) smax[threadIdx.x] = 0ull;
 }
 
 template <typename R, int W>
@@ -41,10 +42,11 @@ __global__ __launch_bounds__(kThreads) void k_spread(LevelGeom g, RecView<R> vol
                                                      const R* __restrict__ str, int64_t n_src, int64_t n_bnd,
                                                      R* __restrict__ grid, int use_vol, int use_bnd, int use_d,
                                                      const double* __restrict__ coef,
+                                                     const unsigned long long* __restrict__ smax,
                                                      const WorkUnit* __restrict__ units)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    dev_spread<R, W>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d, coef,
+    dev_spread<R, W>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d, coef, smax,
                      units[xcd_unit(blockIdx.x, gridDim.x)]);
 }
 
@@ -114,7 +116,7 @@ size_t col_fft_lds_bytes(const Plan& p, int level)
 hipError_t launch_zero_dc(const Plan& p, const Workspace& ws, hipStream_t st)
 {
     (void)p;
-    hipLaunchKernelGGL(k_zero_dc, dim3(1), dim3(64), 0, st, ws.dc);
+    hipLaunchKernelGGL(k_zero_dc, dim3(1), dim3(64), 0, st, ws.dc, ws.smax);
     return hipGetLastError();
 }
 
@@ -125,10 +127,10 @@ hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, 
     const unsigned blocks = grid_for(n, kStrChunk);
     if (p.precision == VP_FP32)
         hipLaunchKernelGGL(k_strengths<float>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
-                           p.d_w, p.d_nx, p.d_ny, (float*)ws.str, ws.dc);
-    else
+                           p.d_w, p.d_nx, p.d_ny, (float*)ws.str, ws.dc, ws.smax);
+    else  // the zero-frequency sum is used by the float32 path only
         hipLaunchKernelGGL(k_strengths<double>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
-                           p.d_w, p.d_nx, p.d_ny, (double*)ws.str, ws.dc);
+                           p.d_w, p.d_nx, p.d_ny, (double*)ws.str, (double*)nullptr, ws.smax);
     return hipGetLastError();
 }
 
@@ -172,7 +174,7 @@ static void spread_launch(const Plan& p, const Workspace& ws, hipStream_t st, in
     (void)hipFuncSetAttribute((const void*)k_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_spread<R, W>), dim3(nu), dim3(kThreads), lds, st, g, view<R>(b.vol), view<R>(b.bnd),
                        (const R*)ws.str, p.n_src, p.n_bnd, (R*)ws.grid[l], uv, ub, ud, (const double*)b.horner,
-                       (const WorkUnit*)b.sp_units);
+                       (const unsigned long long*)ws.smax, (const WorkUnit*)b.sp_units);
 }
 
 template <typename R>

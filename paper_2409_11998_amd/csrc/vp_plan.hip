@@ -239,10 +239,13 @@ void free_plan(vp_plan_s* p)
 }
 
 // Sort points into tiles of one level: one record per point, in the tile
-// holding its support corner.
+// holding its support corner.  With pitch > 0 (interpolation targets) the
+// records of each tile are dealt round-robin over the residues of their
+// window offset (j0 - gy0) * pitch + (i0 - gx0) modulo 32, so that the 32
+// targets a wavefront handles together read 32 different LDS banks.
 template <typename R>
 vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std::vector<double>& y,
-                        const std::vector<int>& ids, RecList* list)
+                        const std::vector<int>& ids, RecList* list, int pitch = 0)
 {
     const LevelGeom& g = p.lv[l];
     const int T = g.T, ntx = g.ntx, w = g.w;
@@ -278,9 +281,48 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
         rsy[at] = sy[q];
         ridx[at] = ids[q];
     }
+    if (pitch > 0) {
+        constexpr int NB = 32;
+        std::vector<int> perm, bucket_pos(NB + 1);
+        std::vector<int> rij2(rij), ridx2(ridx);
+        std::vector<R> rsx2(rsx), rsy2(rsy);
+        for (int t = 0; t < ntiles; ++t) {
+            const int b0 = cnt[t], b1 = cnt[t + 1];
+            if (b1 - b0 < 2) continue;
+            const int gx0 = (t % ntx) * T, gy0 = (t / ntx) * T;
+            auto key = [&](int r) {
+                const int ii = (rij[r] & 0xffff) - gx0, jj = (rij[r] >> 16) - gy0;
+                return (jj * pitch + ii) % NB;
+            };
+            std::fill(bucket_pos.begin(), bucket_pos.end(), 0);
+            for (int r = b0; r < b1; ++r) bucket_pos[key(r) + 1]++;
+            for (int k = 0; k < NB; ++k) bucket_pos[k + 1] += bucket_pos[k];
+            perm.assign(b1 - b0, 0);
+            std::vector<int> fill(bucket_pos.begin(), bucket_pos.end() - 1);
+            for (int r = b0; r < b1; ++r) perm[fill[key(r)]++] = r;  // grouped by residue, stable
+            // deal round-robin over the residue groups
+            int out = b0;
+            std::vector<int> next(bucket_pos.begin(), bucket_pos.end() - 1);
+            while (out < b1)
+                for (int k = 0; k < NB && out < b1; ++k)
+                    if (next[k] < bucket_pos[k + 1]) {
+                        const int r = perm[next[k]++];
+                        rij2[out] = rij[r];
+                        ridx2[out] = ridx[r];
+                        rsx2[out] = rsx[r];
+                        rsy2[out] = rsy[r];
+                        ++out;
+                    }
+        }
+        rij.swap(rij2);
+        ridx.swap(ridx2);
+        rsx.swap(rsx2);
+        rsy.swap(rsy2);
+    }
     RecList* L = list;
     vp_status s;
     L->h_start = cnt;
+    L->h_ij = rij;
     if ((s = upload(p, &L->start, cnt, "tile starts")) != VP_OK) return s;
     if ((s = upload(p, &L->ij, rij, "records ij")) != VP_OK) return s;
     if ((s = upload(p, (R**)&L->dx, rsx, "records dx")) != VP_OK) return s;
@@ -301,6 +343,35 @@ vp_status build_units(Plan& p, int l)
     auto beg_of = [&](const RecList& L, int t) { return L.h_start.empty() ? 0 : L.h_start[t]; };
     b.h_sp_units.clear();
     b.h_in_units.clear();
+    const int T = p.lv[l].T, w = p.lv[l].w, E = T + w - 1, ntx = p.lv[l].ntx;
+    std::vector<int> cov((size_t)(E + 1) * (E + 1));
+    // most records of [a0, a1) of va and [b0, b1) of vb whose w x w supports share a window cell
+    auto cover_of = [&](int t, int a0, int a1, int b0, int b1) {
+        std::fill(cov.begin(), cov.end(), 0);
+        const int gx0 = (t % ntx) * T, gy0 = (t / ntx) * T;
+        auto add = [&](const std::vector<int>& ij, int r0, int r1) {
+            for (int r = r0; r < r1; ++r) {
+                const int ii = (ij[r] & 0xffff) - gx0, jj = (ij[r] >> 16) - gy0;
+                cov[(size_t)jj * (E + 1) + ii] += 1;
+                cov[(size_t)jj * (E + 1) + ii + w] -= 1;
+                cov[(size_t)(jj + w) * (E + 1) + ii] -= 1;
+                cov[(size_t)(jj + w) * (E + 1) + ii + w] += 1;
+            }
+        };
+        add(b.vol.h_ij, a0, a1);
+        add(b.bnd.h_ij, b0, b1);
+        int best = 0;
+        for (int y = 0; y <= E; ++y)
+            for (int x = 0; x <= E; ++x) {
+                int v = cov[(size_t)y * (E + 1) + x];
+                if (x > 0) v += cov[(size_t)y * (E + 1) + x - 1];
+                if (y > 0) v += cov[(size_t)(y - 1) * (E + 1) + x];
+                if (x > 0 && y > 0) v -= cov[(size_t)(y - 1) * (E + 1) + x - 1];
+                cov[(size_t)y * (E + 1) + x] = v;
+                best = std::max(best, v);
+            }
+        return best;
+    };
     for (int t = 0; t < ntiles; ++t) {
         const int nv = cnt_of(b.vol, t), nb = cnt_of(b.bnd, t), nt = cnt_of(b.tgt, t);
         const int ku = std::max((nv + kUnitNodes - 1) / kUnitNodes, (nb + kUnitBnd - 1) / kUnitBnd);
@@ -311,6 +382,7 @@ vp_status build_units(Plan& p, int l)
             u.a1 = beg_of(b.vol, t) + std::min(nv, (k + 1) * kUnitNodes);
             u.b0 = beg_of(b.bnd, t) + std::min(nb, k * kUnitBnd);
             u.b1 = beg_of(b.bnd, t) + std::min(nb, (k + 1) * kUnitBnd);
+            u.cover = cover_of(t, u.a0, u.a1, u.b0, u.b1);
             b.h_sp_units.push_back(u);
         }
         for (int k = 0; k * kUnitTargets < nt; ++k) {
@@ -319,6 +391,7 @@ vp_status build_units(Plan& p, int l)
             u.a0 = beg_of(b.tgt, t) + k * kUnitTargets;
             u.a1 = beg_of(b.tgt, t) + std::min(nt, (k + 1) * kUnitTargets);
             u.b0 = u.b1 = 0;
+            u.cover = 0;
             b.h_in_units.push_back(u);
         }
     }
@@ -381,6 +454,16 @@ vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, 
             }
             for (int i = 0; i < P; ++i) coef[(size_t)a * P + i] = mono[i];
         }
+        // bound on |d/dy tap value| = (2/h) |dp/du| over taps and offsets (sampled, 5% margin)
+        double dm = 0.0;
+        for (int a = 0; a < W; ++a)
+            for (int k = 0; k <= 256; ++k) {
+                const double u = -1.0 + 2.0 * k / 256.0;
+                double pv = 0.0;
+                for (int i = P - 1; i >= 1; --i) pv = pv * u + i * coef[(size_t)a * P + i];
+                dm = std::max(dm, std::fabs(pv));
+            }
+        g.dmax = 1.05 * dm * 2.0 / g.h;
         vp_status st2;
         if ((st2 = upload(p, &b.horner, coef, "kernel polynomials")) != VP_OK) return st2;
     }
@@ -407,7 +490,7 @@ vp_status build_level(Plan& p, int l, const std::vector<double>& sxv, const std:
     LevelBufs& b = p.lb[l];
     if ((s = build_records<R>(p, l, sxv, syv, vol_ids, &b.vol)) != VP_OK) return s;
     if ((s = build_records<R>(p, l, sxv, syv, bnd_ids, &b.bnd)) != VP_OK) return s;
-    if ((s = build_records<R>(p, l, tx, ty, tids, &b.tgt)) != VP_OK) return s;
+    if ((s = build_records<R>(p, l, tx, ty, tids, &b.tgt, p.lv[l].T + p.lv[l].w - 1)) != VP_OK) return s;
     if ((s = build_units(p, l)) != VP_OK) return s;
     if ((s = build_level_tables<R>(p, l, phihat, p.delta1, p.delta2)) != VP_OK) return s;
     return VP_OK;
@@ -482,6 +565,8 @@ vp_status time_level(Plan& p, int l, double* ms)
     const size_t o_str = off;
     off += align256((size_t)std::max<int64_t>(nstr, 1) * rb);
     const size_t o_dc = off;
+    off += align256(kDcParts * sizeof(double));
+    const size_t o_smax = off;
     off += 256;
     unsigned char* blk = nullptr;
     VP_HIP(hipMalloc((void**)&blk, off), "autotune workspace");
@@ -493,6 +578,7 @@ vp_status time_level(Plan& p, int l, double* ms)
     ws.hist[l] = blk + o_hist;
     ws.str = blk + o_str;
     ws.dc = (double*)(blk + o_dc);
+    ws.smax = (unsigned long long*)(blk + o_smax);
     const bool uv = (p.kinds & VP_KIND_V) && p.n_src > 0;
     const bool ub = (p.kinds & (VP_KIND_S | VP_KIND_D)) && p.n_bnd > 0;
     const bool ud = (p.kinds & VP_KIND_D) && p.n_bnd > 0;
@@ -552,8 +638,11 @@ static size_t workspace_layout(const Plan& p, Workspace* ws, unsigned char* base
     const int64_t nstr = p.n_src + p.n_bnd + ((p.kinds & VP_KIND_D) ? 2 * p.n_bnd : 0);
     take(ws ? &ws->str : nullptr, (size_t)std::max<int64_t>(nstr, 1) * rb);
     void* dcp = nullptr;
-    take(ws ? &dcp : nullptr, sizeof(double));
+    take(ws ? &dcp : nullptr, kDcParts * sizeof(double));
     if (ws) ws->dc = (double*)dcp;
+    void* smp = nullptr;
+    take(ws ? &smp : nullptr, 2 * sizeof(unsigned long long));
+    if (ws) ws->smax = (unsigned long long*)smp;
     return off;
 }
 

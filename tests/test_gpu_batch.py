@@ -50,6 +50,8 @@ def test_batch_matches_single_plans_and_oracle(precision):
             assert np.all(np.isfinite(got)), (rep, i)
             e_single = oracle.rel_linf(got, s1.cpu().numpy())
             e_oracle = oracle.rel_linf(got, ref)
+            print("rep", rep, "inst", i, "batch vs single", e_single, "batch vs oracle", e_oracle,
+                  "single vs oracle", oracle.rel_linf(s1.cpu().numpy(), ref))
             assert e_single <= (1e-13 if precision == 1 else 1e-6), (rep, i, e_single)
             assert e_oracle <= tol, (rep, i, e_oracle)
     batch.close()
