@@ -41,31 +41,39 @@ def log(*a):
 
 
 def algorithmic_bytes(info, P, kinds, b):
-    """Bytes each launch must move at minimum: one read of each input, one write of each output.
-    Node records count their packed support corner (4 B), two offsets and their strengths."""
+    """Bytes each timed launch must move at minimum: one read of each input and one write of
+    each output (b = bytes of the plan's real type).  A spread node record is its packed
+    support corner and node index (4 B each), two offsets and the strength it gathers (two
+    more for double-layer boundary nodes); a target record likewise, plus its history value.
+    The spread writes its level's grid once; the first slot also zeroes both grids."""
     n_v = P.n_src if "V" in kinds else 0
     n_b = P.n_bnd if ("S" in kinds or "D" in kinds) else 0
-    C = 3 if "D" in kinds else 1
-    cb = 1 if "D" not in kinds else 3
+    dl = "D" in kinds
     out = {}
-    out["strengths"] = n_v * (16 + b) + n_b * (8 * 4 + cb * b)
+    grids = sum(F * F * b for F in info["fine"])
+    out["strengths"] = grids + n_v * (16 + b) + n_b * (16 + b + (16 + 2 * b if dl else 0))
     nt = P.n_tgt
     for l, tag in enumerate(("nh", "fh")):
         F = info["fine"][l]
         M = (info["modes"][l] - 1) // 2
         half = (M + 1) * F * 2 * b
-        out["spread_" + tag] = n_v * (4 + 3 * b) + n_b * (4 + 2 * b + cb * b) + C * F * F * b
-        out["row_fft_" + tag] = C * F * F * b + C * half
-        out["col_fft_mul_" + tag] = C * half + half + (M + 1) ** 2 * b
+        rec = 8 + 2 * b
+        out["spread_" + tag] = n_v * (rec + b) + n_b * (rec + b + (2 * b if dl else 0)) + F * F * b
+        out["row_fft_" + tag] = F * F * b + half
+        out["col_fft_mul_" + tag] = 2 * half + (M + 1) ** 2 * b
         out["row_ifft_" + tag] = half + F * F * b
-        out["interp_" + tag] = F * F * b + nt * (4 + 2 * b) + nt * b
-    loc = nt * (6 * 8 + 1 + 2 * b + 8)
+        out["interp_" + tag] = F * F * b + nt * (8 + 2 * b) + nt * b
+    # local part: every target reads r, both history values and writes its result; targets
+    # within 12 sqrt(delta_1) of the boundary also read their frame and layer jets
+    near = int(np.count_nonzero(np.asarray(P.geom["r"]) <= 12.0 * np.sqrt(info["delta1"])))
+    loc = nt * (8 + 2 * b + 8)
     if "V" in kinds:
-        loc += nt * 6 * 8
+        loc += nt * 3 * 8 + near * (3 * 8)
+    loc += near * (3 * 8 + 1 + 16)  # nx, ny, kappa, sgn, gamma3, gamma4
     if "D" in kinds:
-        loc += nt * 5 * 8
+        loc += near * 5 * 8
     if "S" in kinds:
-        loc += nt * 3 * 8
+        loc += near * 3 * 8
     out["local"] = loc
     for st in ("spread", "row_fft", "col_fft_mul", "row_ifft", "interp"):
         out[st] = out[st + "_nh"] + out[st + "_fh"]
@@ -159,16 +167,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--oracle-sample", type=int, default=192, help="targets for the CPU oracle leg")
+    ap.add_argument("--oracle-sample", type=int, default=16384,
+                    help="targets of the main workload the CPU oracle evaluates (its timing is the "
+                         "cpu_baseline, about 10 s on 16 cores; its values check the GPU result)")
     ap.add_argument("--no-fp32-leg", action="store_true")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workloads (quick runs)")
     ap.add_argument("--no-batch-leg", action="store_true")
     ap.add_argument("--no-serve-leg", action="store_true")
-    ap.add_argument("--batch-instances", type=int, default=64)
-    ap.add_argument("--batch-max-tri", type=float, default=5e4)
+    ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--batch-max-tri", type=float, default=2e5)
+    ap.add_argument("--batch-tune-sample", type=int, default=8,
+                    help="instances timed by the autotuner to choose the batch's spreading widths")
     ap.add_argument("--serve-meshes", type=int, default=16)
-    ap.add_argument("--serve-requests", type=int, default=1500)
-    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / saturated rate")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.95",
+                    help="arrival rates as fractions of the saturated rate")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -250,7 +263,7 @@ def main():
         log("bench: generating disk-2M workload")
         Q = config_problem(3, scale=args.scale)
         log("bench: fp32 V leg, n_tgt=%d" % Q.n_tgt)
-        r32 = run_leg(torch, Q, "V", 1e-6, 0, args.steps, args.warmup, max(16, args.oracle_sample // 4), seed=30)
+        r32 = run_leg(torch, Q, "V", 1e-6, 0, args.steps, args.warmup, min(256, args.oracle_sample), seed=30)
         alg32 = algorithmic_bytes(r32["info"], Q, "V", 4)
         st32 = r32["stages"]
         dom32 = max(LAUNCHES, key=lambda k: st32[k])
@@ -267,23 +280,26 @@ def main():
                        "e_inf_vs_oracle_sample": r32.get("e_inf_sample"), "plan_s": round(r32["plan_s"], 3)}
     if batch_probs:
         log("bench: batch leg, %d instances, %d targets" % (len(batch_probs), sum(P.n_tgt for P in batch_probs)))
-        rec["batch"] = batch_leg(torch, batch_probs, args.steps, args.warmup)
+        rec["batch"] = batch_leg(torch, batch_probs, args.steps, args.warmup, args.batch_tune_sample)
     if serve_probs:
         log("bench: serving leg, %d meshes" % len(serve_probs))
-        rec["serve"] = serve_leg(torch, serve_probs, args.serve_requests, args.serve_load)
-        rec["latency_p50_s"] = rec["serve"]["served"]["p50_s"]
-        rec["latency_p99_s"] = rec["serve"]["served"]["p99_s"]
+        loads = [float(x) for x in args.serve_loads.split(",")]
+        rec["serve"] = serve_leg(torch, serve_probs, args.serve_requests, loads)
+        ref_load = min(rec["serve"]["loads"], key=lambda k: abs(float(k) - 0.8))
+        rec["latency_p50_s"] = rec["serve"]["loads"][ref_load]["served"]["p50_s"]
+        rec["latency_p99_s"] = rec["serve"]["loads"][ref_load]["served"]["p99_s"]
+        rec["latency_load"] = float(ref_load)
     print(json.dumps(rec), flush=True)
 
 
-def batch_leg(torch, probs, steps, warmup):
+def batch_leg(torch, probs, steps, warmup, tune_sample):
     """Float32 V+D on many star instances: one persistent launch per stage (hipGraph)
     against the same plans launched one after another."""
     from paper_2409_11998_amd import Batch
     from workloads.device import make_batch_plans, run, to_device
     devs = [to_device(P) for P in probs]
     t0 = time.perf_counter()
-    plans = make_batch_plans(devs, tol=1e-6, precision=0, kinds=5)
+    plans = make_batch_plans(devs, autotune_sample=tune_sample, tol=1e-6, precision=0, kinds=5)
     plan_s = time.perf_counter() - t0
     batch = Batch(plans, 5)
     outs = [torch.empty(P.n_tgt, dtype=torch.float64, device="cuda") for P in probs]
@@ -316,6 +332,8 @@ def batch_leg(torch, probs, steps, warmup):
     small = sorted(range(len(probs)), key=lambda i: probs[i].n_tgt)[:2]
     e_or = max(oracle.rel_linf(got[i], oracle.evaluate(probs[i], kinds="VD")["total"]) for i in small)
     sizes = [P.n_src for P in probs]
+    widths = list(plans[0].info()["width"])
+    grids = sorted({tuple(p.info()["fine"]) for p in plans})
     batch.close()
     for p in plans:
         p.close()
@@ -325,12 +343,15 @@ def batch_leg(torch, probs, steps, warmup):
             "value": round(n_t * steps / el_b, 1), "unit": "target pts/s", "ms_per_step": round(1e3 * el_b / steps, 4),
             "sequential_value": round(n_t * steps / el_s, 1), "sequential_ms_per_step": round(1e3 * el_s / steps, 4),
             "max_rel_dev_vs_single_plans": dev_single, "e_inf_vs_oracle_smallest2": e_or,
+            "spread_width": widths, "fine_grids": [list(g) for g in grids], "autotune_sample": tune_sample,
             "plan_s": round(plan_s, 2)}
 
 
-def serve_leg(torch, probs, n_req, load):
-    """Poisson stream of V/S/D requests (70% float32 1e-6, 30% float64 1e-10) on resident
-    plans through the serving loop, against the plain float64 path run one by one."""
+def serve_leg(torch, probs, n_req, loads):
+    """Poisson streams of V/S/D requests (70% float32 1e-6, 30% float64 1e-10) on
+    resident plans through the serving loop, at several arrival rates (fractions of
+    the measured saturated rate); the same arrival stream is also served by the
+    plain float64 path (every request at 1e-10, one at a time in arrival order)."""
     from paper_2409_11998_amd import Server
     from workloads.device import make_plan, to_device
     devs = [to_device(P) for P in probs]
@@ -338,74 +359,82 @@ def serve_leg(torch, probs, n_req, load):
     for i, d in enumerate(devs):
         for prec, tol in ((0, 1e-6), (1, 1e-10)):
             plans[(i, prec)] = make_plan(d, tol=tol, precision=prec, kinds=7, no_workspace=True)
+    fp64_plans = {i: make_plan(d, tol=1e-10, precision=1, kinds=7) for i, d in enumerate(devs)}
     rng = np.random.default_rng(55)
-    reqs = []
-    for _ in range(n_req):
-        i = int(rng.integers(len(probs)))
-        kind = "VSD"[int(rng.integers(3))]
-        prec = 0 if rng.uniform() < 0.7 else 1
-        reqs.append((i, kind, prec))
+
+    def draw(n):
+        out = []
+        for _ in range(n):
+            i = int(rng.integers(len(probs)))
+            kind = "VSD"[int(rng.integers(3))]
+            prec = 0 if rng.uniform() < 0.7 else 1
+            out.append((i, kind, prec))
+        return out
 
     def kw(d, kind):
         return dict(f=d["f"] if kind == "V" else None, jet6=d["jet6"] if kind == "V" else None,
                     sigma=d["sigma"] if kind == "S" else None, sigma_jet=d["sigma_jet"] if kind == "S" else None,
                     mu=d["mu"] if kind == "D" else None, mu_jet=d["mu_jet"] if kind == "D" else None)
-    outs = {i: torch.empty(P.n_tgt, dtype=torch.float64, device="cuda") for i, P in enumerate(probs)}
     budget = int(0.8 * torch.cuda.mem_get_info()[0])
-    torch.cuda.synchronize()
-    # saturated rate: the whole request list submitted at once
+    # saturated rate: a request list submitted at once
+    sat_reqs = draw(min(400, n_req))
     srv = Server(hbm_budget_bytes=budget, max_in_flight=8, n_streams=4)
-    sat_out = [torch.empty_like(outs[i]) for i, _, _ in reqs[:min(300, n_req)]]
+    sat_out = [torch.empty(probs[i].n_tgt, dtype=torch.float64, device="cuda") for i, _, _ in sat_reqs]
     torch.cuda.synchronize()
-    tk = [srv.submit(plans[(i, p)], o, **kw(devs[i], k)) for (i, k, p), o in zip(reqs, sat_out)]
+    tk = [srv.submit(plans[(i, p)], o, **kw(devs[i], k)) for (i, k, p), o in zip(sat_reqs, sat_out)]
     for t in tk:
         srv.wait(t, timeout=300)
     sat = srv.stats()
     srv.close()
+    del sat_out
     rate_sat = sat["completed"] / max(sat["span_s"], 1e-9)
-    lam = load * rate_sat
-    # Poisson arrivals at lam
-    gaps = rng.exponential(1.0 / lam, n_req)
-    srv = Server(hbm_budget_bytes=budget, max_in_flight=8, n_streams=4)
-    req_out = [torch.empty_like(outs[i]) for i, _, _ in reqs]   # one output per request
-    torch.cuda.synchronize()
-    tickets = []
-    t_next = time.perf_counter()
-    for r, (i, k, p) in enumerate(reqs):
-        t_next += gaps[r]
-        while time.perf_counter() < t_next:
-            pass
-        tickets.append(srv.submit(plans[(i, p)], req_out[r], **kw(devs[i], k)))
-    for t in tickets:
-        srv.wait(t, timeout=600)
-    st = srv.stats()
-    srv.close()
-    # plain float64 path, one request at a time (same requests, float64 1e-10, no queueing)
-    fp64_plans = {i: make_plan(d, tol=1e-10, precision=1, kinds=7) for i, d in enumerate(devs)}
-    lat64 = []
-    n_t = 0
-    t0 = time.perf_counter()
-    for i, k, p in reqs[:min(500, n_req)]:
-        t1 = time.perf_counter()
-        fp64_plans[i].eval(out=outs[i], **kw(devs[i], k))
+    res = {"workload": "%d requests per load on %d seeded star meshes (nodes log-U[2e3,5e5]); kinds V/S/D "
+                       "uniform; 70%% fp32 1e-6 / 30%% fp64 1e-10; Poisson arrivals" % (n_req, len(probs)),
+           "saturated_req_per_s": round(rate_sat, 1), "hbm_budget_bytes": budget, "loads": {}}
+    for load in loads:
+        reqs = draw(n_req)
+        lam = load * rate_sat
+        arrive = np.cumsum(rng.exponential(1.0 / lam, n_req))
+        n_t = sum(probs[i].n_tgt for i, _, _ in reqs)
+        # served: mixed precision plans through the serving loop
+        srv = Server(hbm_budget_bytes=budget, max_in_flight=8, n_streams=4)
+        req_out = [torch.empty(probs[i].n_tgt, dtype=torch.float64, device="cuda") for i, _, _ in reqs]
         torch.cuda.synchronize()
-        lat64.append(time.perf_counter() - t1)
-        n_t += probs[i].n_tgt
-    el64 = time.perf_counter() - t0
-    lat64 = np.sort(lat64)
-    for p in list(plans.values()) + list(fp64_plans.values()):
-        p.close()
-    return {"workload": "%d requests on %d seeded star meshes (nodes log-U[2e3,5e5]); kinds V/S/D uniform; "
-                        "70%% fp32 1e-6 / 30%% fp64 1e-10; Poisson arrivals at %.2f x saturated rate"
-                        % (n_req, len(probs), load),
-            "saturated_req_per_s": round(rate_sat, 1), "arrival_req_per_s": round(lam, 1),
+        tickets = []
+        t0 = time.perf_counter()
+        for r, (i, k, p) in enumerate(reqs):
+            while time.perf_counter() - t0 < arrive[r]:
+                pass
+            tickets.append(srv.submit(plans[(i, p)], req_out[r], **kw(devs[i], k)))
+        for t in tickets:
+            srv.wait(t, timeout=600)
+        st = srv.stats()
+        srv.close()
+        del req_out
+        # plain float64: the same arrivals, one request at a time, each synchronized
+        lat = np.empty(n_req)
+        outs = {i: torch.empty(P.n_tgt, dtype=torch.float64, device="cuda") for i, P in enumerate(probs)}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r, (i, k, p) in enumerate(reqs):
+            while time.perf_counter() - t0 < arrive[r]:
+                pass
+            fp64_plans[i].eval(out=outs[i], **kw(devs[i], k))
+            torch.cuda.synchronize()
+            lat[r] = time.perf_counter() - t0 - arrive[r]
+        span64 = time.perf_counter() - t0
+        lat.sort()
+        res["loads"]["%.2f" % load] = {
+            "arrival_req_per_s": round(lam, 1),
             "served": {"p50_s": st["p50_s"], "p99_s": st["p99_s"], "max_s": st["max_s"],
                        "targets_per_s": round(st["targets_per_s"], 1), "completed": st["completed"],
                        "deferred": st["deferred"], "peak_in_flight": st["peak_in_flight"],
-                       "peak_workspace_bytes": st["peak_bytes"], "hbm_budget_bytes": budget},
-            "plain_fp64_sequential": {"p50_s": float(lat64[len(lat64) // 2]),
-                                      "p99_s": float(lat64[min(len(lat64) - 1, int(0.99 * len(lat64)))]),
-                                      "targets_per_s": round(n_t / el64, 1), "requests": len(lat64)}}
+                       "peak_workspace_bytes": st["peak_bytes"]},
+            "plain_fp64": {"p50_s": float(lat[n_req // 2]), "p99_s": float(lat[min(n_req - 1, int(0.99 * n_req))]),
+                           "max_s": float(lat[-1]), "targets_per_s": round(n_t / span64, 1)}}
+    for p in list(plans.values()) + list(fp64_plans.values()):
+        p.close()
+    return res
 
 
 if __name__ == "__main__":

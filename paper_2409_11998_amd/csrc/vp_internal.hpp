@@ -145,12 +145,13 @@ struct Plan {
 };
 
 // Kernel launchers (vp_kernels.hip).  All enqueue on stream st and write into ws.
-hipError_t launch_zero_dc(const Plan& p, const Workspace& ws, hipStream_t st);
 hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* sigma,
                             const double* mu);
-hipError_t launch_zero_grids(const Plan& p, const Workspace& ws, hipStream_t st);
+// Grids present in ws, zero-frequency partial sums and strength maxima to zero.
+hipError_t launch_zero(const Plan& p, const Workspace& ws, hipStream_t st);
 hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool use_vol, bool use_bnd,
                          bool use_d);
+// FFT passes: level 0 or 1, or both levels in one launch (level < 0).
 hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
 hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
 hipError_t launch_row_ifft(const Plan& p, const Workspace& ws, hipStream_t st, int level);

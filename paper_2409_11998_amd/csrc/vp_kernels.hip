@@ -23,18 +23,16 @@ __global__ __launch_bounds__(kThreads) void k_strengths(int64_t n_src, int64_t n
     dev_strengths<R>(n_src, n_bnd, f, sigma, mu, w, nx, ny, str, dc, smax, blockIdx.x);
 }
 
+// Zero the spread grids of both levels and the zero-frequency / maximum accumulators.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_zero2(R* __restrict__ a, int64_t na, R* __restrict__ b, int64_t nb)
+__global__ __launch_bounds__(kThreads) void k_zero(R* __restrict__ a, int64_t na, R* __restrict__ b, int64_t nb,
+                                                   double* __restrict__ dc, unsigned long long* __restrict__ smax)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     dev_zero<R>(a, na, i);
     dev_zero<R>(b, nb, i);
-}
-
-__global__ void k_zero_dc(double* dc, unsigned long long* smax)
-{
-    if (threadIdx.x < kDcParts) dc[threadIdx.x] = 0.0;
-    if (threadIdx.x < 2) smax[threadIdx.x] = 0ull;
+    if (i < kDcParts) dc[i] = 0.0;
+    if (i < 2) smax[i] = 0ull;
 }
 
 template <typename R, int W>
@@ -50,29 +48,54 @@ __global__ __launch_bounds__(kThreads) void k_spread(LevelGeom g, RecView<R> vol
                      units[xcd_unit(blockIdx.x, gridDim.x)]);
 }
 
+// The FFT passes of one or two levels in one launch: blocks [0, n[0]) work on
+// the first level given, blocks [n[0], n[0] + n[1]) on the second.
+template <typename R> struct LevelPair {
+    LevelGeom g[2];
+    R* grid[2];
+    cplx<R>* spec[2];
+    const cplx<R>* tw[2];
+    const R* mult[2];
+    int n[2];
+};
+
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_row_r2c(LevelGeom g, const R* __restrict__ grid,
-                                                      const cplx<R>* __restrict__ tw, cplx<R>* __restrict__ spec)
+__device__ __forceinline__ int pair_unit(const LevelPair<R>& P, int* lv)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    dev_row_r2c<R>(smem_raw, g, grid, tw, spec, xcd_unit(blockIdx.x, gridDim.x));
+    const int b = blockIdx.x;
+    if (b < P.n[0]) {
+        *lv = 0;
+        return xcd_unit(b, P.n[0]);
+    }
+    *lv = 1;
+    return xcd_unit(b - P.n[0], P.n[1]);
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_col(LevelGeom g, cplx<R>* __restrict__ spec,
-                                                  const R* __restrict__ mult, const cplx<R>* __restrict__ tw,
-                                                  int zero_dc)
+__global__ __launch_bounds__(kThreads) void k_row_r2c(LevelPair<R> P)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    dev_col<R>(smem_raw, g, spec, mult, tw, zero_dc, xcd_unit(blockIdx.x, gridDim.x));
+    int l;
+    const int u = pair_unit(P, &l);
+    dev_row_r2c<R>(smem_raw, P.g[l], P.grid[l], P.tw[l], P.spec[l], u);
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_row_c2r(LevelGeom g, const cplx<R>* __restrict__ spec,
-                                                      const cplx<R>* __restrict__ tw, R* __restrict__ out)
+__global__ __launch_bounds__(kThreads) void k_col(LevelPair<R> P, int zero_dc)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    dev_row_c2r<R>(smem_raw, g, spec, tw, out, xcd_unit(blockIdx.x, gridDim.x));
+    int l;
+    const int u = pair_unit(P, &l);
+    dev_col<R>(smem_raw, P.g[l], P.spec[l], P.mult[l], P.tw[l], zero_dc, u);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row_c2r(LevelPair<R> P)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int l;
+    const int u = pair_unit(P, &l);
+    dev_row_c2r<R>(smem_raw, P.g[l], P.spec[l], P.tw[l], P.grid[l], u);
 }
 
 template <typename R, int W>
@@ -113,13 +136,6 @@ size_t col_fft_lds_bytes(const Plan& p, int level)
     return (size_t)p.lv[level].F * cb;
 }
 
-hipError_t launch_zero_dc(const Plan& p, const Workspace& ws, hipStream_t st)
-{
-    (void)p;
-    hipLaunchKernelGGL(k_zero_dc, dim3(1), dim3(64), 0, st, ws.dc, ws.smax);
-    return hipGetLastError();
-}
-
 hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* sigma,
                             const double* mu)
 {
@@ -134,18 +150,18 @@ hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, 
     return hipGetLastError();
 }
 
-hipError_t launch_zero_grids(const Plan& p, const Workspace& ws, hipStream_t st)
+hipError_t launch_zero(const Plan& p, const Workspace& ws, hipStream_t st)
 {
     // a level without a grid in ws (the planner's level timing) is skipped
     const int64_t n0 = ws.grid[0] ? (int64_t)p.lv[0].F * p.lv[0].F : 0;
     const int64_t n1 = ws.grid[1] ? (int64_t)p.lv[1].F * p.lv[1].F : 0;
-    const unsigned blocks = grid_for(std::max(n0, n1));
+    const unsigned blocks = grid_for(std::max<int64_t>({n0, n1, kDcParts}));
     if (p.precision == VP_FP32)
-        hipLaunchKernelGGL(k_zero2<float>, dim3(blocks), dim3(kThreads), 0, st, (float*)ws.grid[0], n0,
-                           (float*)ws.grid[1], n1);
+        hipLaunchKernelGGL(k_zero<float>, dim3(blocks), dim3(kThreads), 0, st, (float*)ws.grid[0], n0,
+                           (float*)ws.grid[1], n1, ws.dc, ws.smax);
     else
-        hipLaunchKernelGGL(k_zero2<double>, dim3(blocks), dim3(kThreads), 0, st, (double*)ws.grid[0], n0,
-                           (double*)ws.grid[1], n1);
+        hipLaunchKernelGGL(k_zero<double>, dim3(blocks), dim3(kThreads), 0, st, (double*)ws.grid[0], n0,
+                           (double*)ws.grid[1], n1, ws.dc, ws.smax);
     return hipGetLastError();
 }
 
@@ -206,13 +222,42 @@ hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int
                                   : spread_t<double>(p, ws, st, level, use_vol, use_bnd, use_d);
 }
 
+// Levels of a fused FFT launch: level 0 or 1 alone, or both (level < 0).
 template <typename R>
-static hipError_t row_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l)
+static LevelPair<R> level_pair(const Plan& p, const Workspace& ws, int level, int (*units)(const LevelGeom&))
 {
-    const LevelGeom& g = p.lv[l];
-    const LevelBufs& b = p.lb[l];
-    hipLaunchKernelGGL(k_row_r2c<R>, dim3(g.F), dim3(kThreads), row_fft_lds_bytes(p, l), st, g,
-                       (const R*)ws.grid[l], (const cplx<R>*)b.tw, (cplx<R>*)ws.spec[l]);
+    LevelPair<R> P{};
+    int k = 0;
+    for (int l = 0; l < 2; ++l) {
+        if (level >= 0 && l != level) continue;
+        P.g[k] = p.lv[l];
+        P.grid[k] = (R*)ws.grid[l];
+        P.spec[k] = (cplx<R>*)ws.spec[l];
+        P.tw[k] = (const cplx<R>*)p.lb[l].tw;
+        P.mult[k] = (const R*)p.lb[l].mult;
+        P.n[k] = units(p.lv[l]);
+        ++k;
+    }
+    return P;
+}
+
+static int rows_of(const LevelGeom& g) { return g.F; }
+static int cols_of(const LevelGeom& g) { return g.M + 1; }
+
+static size_t pair_lds(const Plan& p, int level, size_t (*lds)(const Plan&, int))
+{
+    size_t m = 0;
+    for (int l = 0; l < 2; ++l)
+        if (level < 0 || l == level) m = std::max(m, lds(p, l));
+    return m;
+}
+
+template <typename R>
+static hipError_t row_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level)
+{
+    const LevelPair<R> P = level_pair<R>(p, ws, level, rows_of);
+    hipLaunchKernelGGL(k_row_r2c<R>, dim3(P.n[0] + P.n[1]), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st,
+                       P);
     return hipGetLastError();
 }
 
@@ -222,13 +267,12 @@ hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, in
 }
 
 template <typename R>
-static hipError_t col_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l)
+static hipError_t col_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level)
 {
-    const LevelGeom& g = p.lv[l];
-    const LevelBufs& b = p.lb[l];
+    const LevelPair<R> P = level_pair<R>(p, ws, level, cols_of);
     const int zero_dc = p.precision == VP_FP32 ? 1 : 0;
-    hipLaunchKernelGGL((k_col<R>), dim3(g.M + 1), dim3(kThreads), col_fft_lds_bytes(p, l), st, g,
-                       (cplx<R>*)ws.spec[l], (const R*)b.mult, (const cplx<R>*)b.tw, zero_dc);
+    hipLaunchKernelGGL((k_col<R>), dim3(P.n[0] + P.n[1]), dim3(kThreads), pair_lds(p, level, col_fft_lds_bytes), st,
+                       P, zero_dc);
     return hipGetLastError();
 }
 
@@ -238,12 +282,11 @@ hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, in
 }
 
 template <typename R>
-static hipError_t row_ifft_t(const Plan& p, const Workspace& ws, hipStream_t st, int l)
+static hipError_t row_ifft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level)
 {
-    const LevelGeom& g = p.lv[l];
-    const LevelBufs& b = p.lb[l];
-    hipLaunchKernelGGL(k_row_c2r<R>, dim3(g.F), dim3(kThreads), row_fft_lds_bytes(p, l), st, g,
-                       (const cplx<R>*)ws.spec[l], (const cplx<R>*)b.tw, (R*)ws.grid[l]);
+    const LevelPair<R> P = level_pair<R>(p, ws, level, rows_of);
+    hipLaunchKernelGGL(k_row_c2r<R>, dim3(P.n[0] + P.n[1]), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st,
+                       P);
     return hipGetLastError();
 }
 

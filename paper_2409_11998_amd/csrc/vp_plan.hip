@@ -592,8 +592,7 @@ vp_status time_level(Plan& p, int l, double* ms)
     double best = INFINITY;
     for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
         err = hipEventRecord(e0, st);
-        if (err == hipSuccess) err = launch_zero_dc(p, ws, st);
-        if (err == hipSuccess) err = launch_zero_grids(p, ws, st);
+        if (err == hipSuccess) err = launch_zero(p, ws, st);
         if (err == hipSuccess) err = launch_strengths(p, ws, st, f, sig, mu);
         if (err == hipSuccess) err = launch_spread(p, ws, st, l, uv, ub, ud);
         if (err == hipSuccess) err = launch_row_fft(p, ws, st, l);
@@ -691,25 +690,32 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
     }
     auto mark = [&](int k) -> hipError_t { return timing ? hipEventRecord(p.ev[k], st) : hipSuccess; };
     VP_HIP(mark(0), "event");
-    VP_HIP(launch_zero_dc(p, ws, st), "zero dc");
-    VP_HIP(launch_zero_grids(p, ws, st), "zero grids");
+    VP_HIP(launch_zero(p, ws, st), "zero");
     VP_HIP(launch_strengths(p, ws, st, f, sigma, mu), "strengths");
     VP_HIP(mark(1), "event");
     for (int l = 0; l < 2; ++l) {
         VP_HIP(launch_spread(p, ws, st, l, use_v, use_s || use_d, use_d), "spread");
         VP_HIP(mark(2 + l), "event");
     }
-    for (int l = 0; l < 2; ++l) {
-        VP_HIP(launch_row_fft(p, ws, st, l), "row fft");
-        VP_HIP(mark(4 + l), "event");
-    }
-    for (int l = 0; l < 2; ++l) {
-        VP_HIP(launch_col_fft(p, ws, st, l), "column fft");
-        VP_HIP(mark(6 + l), "event");
-    }
-    for (int l = 0; l < 2; ++l) {
-        VP_HIP(launch_row_ifft(p, ws, st, l), "row ifft");
-        VP_HIP(mark(8 + l), "event");
+    // the FFT passes of both levels share one launch each, except when every
+    // launch is timed (then one per level, in the order of the timing slots)
+    if (timing) {
+        for (int l = 0; l < 2; ++l) {
+            VP_HIP(launch_row_fft(p, ws, st, l), "row fft");
+            VP_HIP(mark(4 + l), "event");
+        }
+        for (int l = 0; l < 2; ++l) {
+            VP_HIP(launch_col_fft(p, ws, st, l), "column fft");
+            VP_HIP(mark(6 + l), "event");
+        }
+        for (int l = 0; l < 2; ++l) {
+            VP_HIP(launch_row_ifft(p, ws, st, l), "row ifft");
+            VP_HIP(mark(8 + l), "event");
+        }
+    } else {
+        VP_HIP(launch_row_fft(p, ws, st, -1), "row fft");
+        VP_HIP(launch_col_fft(p, ws, st, -1), "column fft");
+        VP_HIP(launch_row_ifft(p, ws, st, -1), "row ifft");
     }
     for (int l = 0; l < 2; ++l) {
         VP_HIP(launch_interp(p, ws, st, l), "interp");

@@ -80,6 +80,7 @@ struct vp_server_s {
     clk::time_point t_first, t_last;
     bool any = false;
     int device = 0;
+    std::vector<hipEvent_t> free_events;  // completion events, reused across requests
 };
 
 namespace {
@@ -115,7 +116,7 @@ void worker_main(vp_server_s* S)
             finish(S, q, e == hipSuccess ? VP_OK : VP_ERR_DEVICE);
             S->in_flight_bytes -= q->bytes;
             S->stream_load[q->stream]--;
-            hipEventDestroy(q->ev);
+            S->free_events.push_back(q->ev);
             q->ev = nullptr;
             S->running[i] = S->running.back();
             S->running.pop_back();
@@ -155,12 +156,20 @@ void worker_main(vp_server_s* S)
                 vs = eval_enqueue(p, q->ws, st, q->r.f_src, q->r.jet6, q->r.sigma, q->r.sigma_jet3, q->r.mu,
                                   q->r.mu_jet5, q->r.out, false);
             if (q->ws.block) workspace_free(q->ws, st, true);
-            if (vs == VP_OK && hipEventCreateWithFlags(&q->ev, hipEventDisableTiming) != hipSuccess) vs = VP_ERR_DEVICE;
+            if (vs == VP_OK) {
+                if (!S->free_events.empty()) {
+                    q->ev = S->free_events.back();
+                    S->free_events.pop_back();
+                } else if (hipEventCreateWithFlags(&q->ev, hipEventDisableTiming) != hipSuccess) {
+                    q->ev = nullptr;
+                    vs = VP_ERR_DEVICE;
+                }
+            }
             if (vs == VP_OK && hipEventRecord(q->ev, st) != hipSuccess) vs = VP_ERR_DEVICE;
             it = S->queue.erase(it);
             progressed = true;
             if (vs != VP_OK) {
-                if (q->ev) hipEventDestroy(q->ev);
+                if (q->ev) S->free_events.push_back(q->ev);
                 q->ev = nullptr;
                 finish(S, q, vs);
                 S->cv_done.notify_all();
@@ -178,8 +187,9 @@ void worker_main(vp_server_s* S)
         if (!progressed) {
             if (S->running.empty()) S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
             else {
+                // requests on the device: poll again soon (completion latency is what is measured)
                 lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                std::this_thread::yield();
                 lk.lock();
             }
         }
@@ -203,6 +213,14 @@ vp_status vp_server_create(vp_server_t* out, const vp_server_opts* opts)
     if (!S) return sfail(VP_ERR_OOM, "host allocation");
     S->opts = *opts;
     hipGetDevice(&S->device);
+    // Keep freed workspace memory in the device's stream-ordered pool instead of
+    // returning it at every synchronization, so admitting a request costs no
+    // operating-system allocation once the pool has grown to the working set.
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, S->device) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
     for (int i = 0; i < opts->n_streams; ++i) {
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -322,6 +340,7 @@ vp_status vp_server_destroy(vp_server_t S)
         hipStreamSynchronize(st);
         hipStreamDestroy(st);
     }
+    for (auto e : S->free_events) hipEventDestroy(e);
     for (auto& kv : S->reqs) delete kv.second;
     delete S;
     return VP_OK;

@@ -46,17 +46,44 @@ def run(plan, dev, kinds="VSD", out=None):
                      out=out)
 
 
-def make_batch_plans(devs, **opts):
-    """Plans for a batch: one spreading width per level for all instances (the
-    largest the planner picks for any of them); each instance then gets the
-    smallest fine grid on which that width meets the tolerance."""
-    plans = [make_plan(d, **opts) for d in devs]
-    w = [max(p.info()["width"][l] for p in plans) for l in range(2)]
-    out = []
-    for p, d in zip(plans, devs):
-        if tuple(p.info()["width"]) == tuple(w):
-            out.append(p)
-        else:
+def make_batch_plans(devs, autotune_sample=0, **opts):
+    """Plans for a batch: one spreading width per level for all instances.
+
+    Without autotune_sample, the width is the largest the static planner picks
+    for any instance.  With autotune_sample = k > 0, k instances spread over
+    the size range are planned with the measured level selection (autotune)
+    and the batch takes the widest of their chosen widths.  Every instance is
+    then planned at that width, which fixes its fine grids (the smallest on
+    which the width meets the tolerance)."""
+    order = sorted(range(len(devs)), key=lambda i: devs[i]["tgt_x"].numel())
+    if autotune_sample > 0:
+        pick = sorted({order[int(round(j * (len(order) - 1) / max(1, autotune_sample - 1)))]
+                       for j in range(autotune_sample)})
+        w = [0, 0]
+        for i in pick:
+            p = make_plan(devs[i], autotune=True, **opts)
+            w = [max(w[l], p.info()["width"][l]) for l in range(2)]
             p.close()
-            out.append(make_plan(d, spread_width=tuple(w), **opts))
-    return out
+    else:
+        w = [0, 0]
+        for d in devs:
+            p = make_plan(d, **opts)
+            w = [max(w[l], p.info()["width"][l]) for l in range(2)]
+            p.close()
+    while True:
+        out, widen = [], None
+        for d in devs:
+            try:
+                out.append(make_plan(d, spread_width=tuple(w), **opts))
+            except Exception:  # this instance needs a wider kernel: widen the batch and start over
+                p = make_plan(d, **opts)
+                widen = [max(w[l], p.info()["width"][l]) for l in range(2)]
+                p.close()
+                break
+        if widen is None:
+            return out
+        for p in out:
+            p.close()
+        if widen == w:
+            raise RuntimeError("no common spreading width for the batch")
+        w = widen
