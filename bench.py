@@ -180,7 +180,7 @@ def main():
                     help="instances timed by the autotuner to choose the batch's spreading widths")
     ap.add_argument("--serve-meshes", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
-    ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.95",
+    ap.add_argument("--serve-loads", type=str, default="0.2,0.5,0.8,0.95",
                     help="arrival rates as fractions of the saturated rate")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (HBM counter calibration)")
@@ -378,7 +378,7 @@ def serve_leg(torch, probs, n_req, loads):
     budget = int(0.8 * torch.cuda.mem_get_info()[0])
     # saturated rate: a request list submitted at once
     sat_reqs = draw(min(400, n_req))
-    srv = Server(hbm_budget_bytes=budget, max_in_flight=8, n_streams=4)
+    srv = Server(hbm_budget_bytes=budget, max_in_flight=64, n_streams=4)
     sat_out = [torch.empty(probs[i].n_tgt, dtype=torch.float64, device="cuda") for i, _, _ in sat_reqs]
     torch.cuda.synchronize()
     tk = [srv.submit(plans[(i, p)], o, **kw(devs[i], k)) for (i, k, p), o in zip(sat_reqs, sat_out)]
@@ -390,14 +390,15 @@ def serve_leg(torch, probs, n_req, loads):
     rate_sat = sat["completed"] / max(sat["span_s"], 1e-9)
     res = {"workload": "%d requests per load on %d seeded star meshes (nodes log-U[2e3,5e5]); kinds V/S/D "
                        "uniform; 70%% fp32 1e-6 / 30%% fp64 1e-10; Poisson arrivals" % (n_req, len(probs)),
-           "saturated_req_per_s": round(rate_sat, 1), "hbm_budget_bytes": budget, "loads": {}}
+           "saturated_req_per_s": round(rate_sat, 1), "saturated_mean_group": round(sat["mean_group"], 2),
+           "hbm_budget_bytes": budget, "loads": {}}
     for load in loads:
         reqs = draw(n_req)
         lam = load * rate_sat
         arrive = np.cumsum(rng.exponential(1.0 / lam, n_req))
         n_t = sum(probs[i].n_tgt for i, _, _ in reqs)
         # served: mixed precision plans through the serving loop
-        srv = Server(hbm_budget_bytes=budget, max_in_flight=8, n_streams=4)
+        srv = Server(hbm_budget_bytes=budget, max_in_flight=64, n_streams=4)
         req_out = [torch.empty(probs[i].n_tgt, dtype=torch.float64, device="cuda") for i, _, _ in reqs]
         torch.cuda.synchronize()
         tickets = []
@@ -429,6 +430,8 @@ def serve_leg(torch, probs, n_req, loads):
             "served": {"p50_s": st["p50_s"], "p99_s": st["p99_s"], "max_s": st["max_s"],
                        "targets_per_s": round(st["targets_per_s"], 1), "completed": st["completed"],
                        "deferred": st["deferred"], "peak_in_flight": st["peak_in_flight"],
+                       "groups": st["groups"], "mean_group": round(st["mean_group"], 2),
+                       "peak_held_bytes": st["peak_held_bytes"], "device_allocs": st["device_allocs"],
                        "peak_workspace_bytes": st["peak_bytes"]},
             "plain_fp64": {"p50_s": float(lat[n_req // 2]), "p99_s": float(lat[min(n_req - 1, int(0.99 * n_req))]),
                            "max_s": float(lat[-1]), "targets_per_s": round(n_t / span64, 1)}}

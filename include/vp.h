@@ -199,9 +199,10 @@ vp_status vp_get_timing(vp_plan_t plan, double* ms13);
 
 /* ------------------------------------------------------------------------
  * Batched evaluation.  Plans of uneven size are executed together: one
- * persistent kernel per stage (spreading and interpolation: one per history
- * level) walks a device work table of (instance, level, tile/row/column)
- * items, so every stage of every instance shares the whole GPU.  Not in the
+ * persistent kernel per stage (spreading and interpolation: one per distinct
+ * spreading width) walks a device table of (instance, level, unit) segments
+ * -- units are tiles, rows, columns or node chunks -- so every stage of every
+ * instance shares the whole GPU.  Not in the
  * paper (which evaluates one problem on one core); it serves workloads made of
  * many independent meshes and densities.
  */
@@ -220,9 +221,10 @@ typedef struct {
 
 /* Group n plans (host array of handles; the plans must outlive the batch) for
  * batched calls that always pass the densities in kinds (VP_KIND_* mask).
- * All plans must share the precision and the spreading width of each level
- * (fine grids may differ).  stream: hipStream_t for the batch (must not be the
- * null stream if graphs are used).  Reads the plans' tile tables (synchronous). */
+ * All plans must share the precision; fine grids and spreading widths may
+ * differ (spreading and interpolation take one launch per distinct width).
+ * stream: hipStream_t for the batch (must not be the null stream if graphs are
+ * used).  Copies its tables to the device (synchronous). */
 vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int kinds, void* stream);
 
 /* Evaluate every instance: args is a host array of n entries.  use_graph != 0
@@ -238,21 +240,30 @@ vp_status vp_batch_destroy(vp_batch_t batch);
 const char* vp_batch_last_error(void);
 
 /* ------------------------------------------------------------------------
- * Serving loop (continuous admission).  A host worker thread keeps a FIFO of
- * submitted requests and starts any of them as soon as an in-flight slot and
- * enough HBM are free, on one of n_streams streams, so requests arriving
- * while others run start without waiting for a batch boundary and their
- * kernels overlap on the device.  Plans stay resident; each running request
- * holds a stream-ordered workspace (grids, spectra, strengths) whose size is
- * its HBM footprint, and the in-flight footprints never exceed the budget.
- * Not in the paper; it serves streams of independent evaluations.
+ * Serving loop (continuous batching).  A host worker thread keeps a FIFO of
+ * submitted requests.  Whenever in-flight slots and HBM are free it admits the
+ * queued requests that fit -- in FIFO order, one precision at a time, a
+ * request that does not fit never blocking smaller ones behind it -- and runs
+ * them as one group: one persistent kernel per stage for all of them (the
+ * batched execution of vp_batch_*), on one of n_streams streams, so requests
+ * arriving while others run join the next group without waiting for the
+ * running ones and groups overlap on the device.  Plans stay resident; each
+ * running request holds a workspace block (grids, spectra, strengths) of its
+ * HBM footprint rounded up to a size class (at most 1/8 more); blocks are
+ * cached and reused once the group that used them completes, and the blocks
+ * held -- in use plus cached -- never exceed the budget.  A group completes as a whole.  With max_wait_us
+ * > 0 the worker holds the oldest queued request up to that long (unless a
+ * full group is already queued) so that more requests join its group: larger
+ * groups at the cost of up to that much added latency.  Not in the paper; it
+ * serves streams of independent evaluations.
  */
 typedef struct vp_server_s* vp_server_t;
 
 typedef struct {
-    size_t hbm_budget_bytes;  /* cap on the summed workspace of in-flight requests           */
+    size_t hbm_budget_bytes;  /* cap on the workspace memory held (in use + cached)          */
     int max_in_flight;        /* cap on concurrently running requests                        */
     int n_streams;            /* streams requests are spread over (1..16)                    */
+    int max_wait_us;          /* admission delay to gather a group (0: admit at once; >= 0)  */
 } vp_server_opts;
 
 /* One request: a plan (resident; create it with opts.no_workspace = 1 so it holds no
@@ -277,6 +288,10 @@ typedef struct {
     double p50_s, p99_s, max_s, mean_s;  /* latency: submission -> completion observed        */
     double span_s;            /* first submission -> last completion                           */
     double targets_per_s;     /* completed target points / span_s                              */
+    uint64_t groups;          /* launched groups (requests admitted together run as one group) */
+    double mean_group;        /* requests per group                                            */
+    size_t peak_held_bytes;   /* largest workspace memory held (in use + cached), <= budget    */
+    uint64_t device_allocs;   /* workspace blocks allocated (the rest were reused from cache)  */
 } vp_server_stats;
 
 /* Start a server on the current device (opts: host pointer). */

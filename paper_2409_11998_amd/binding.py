@@ -51,7 +51,8 @@ class VPEvalArgs(ctypes.Structure):
 
 
 class VPServerOpts(ctypes.Structure):
-    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_in_flight", ctypes.c_int), ("n_streams", ctypes.c_int)]
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_in_flight", ctypes.c_int), ("n_streams", ctypes.c_int),
+                ("max_wait_us", ctypes.c_int)]
 
 
 class VPRequest(ctypes.Structure):
@@ -65,7 +66,8 @@ class VPServerStats(ctypes.Structure):
                 ("failed", ctypes.c_uint64), ("deferred", ctypes.c_uint64), ("peak_bytes", ctypes.c_size_t),
                 ("peak_in_flight", ctypes.c_int), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
                 ("max_s", ctypes.c_double), ("mean_s", ctypes.c_double), ("span_s", ctypes.c_double),
-                ("targets_per_s", ctypes.c_double)]
+                ("targets_per_s", ctypes.c_double), ("groups", ctypes.c_uint64), ("mean_group", ctypes.c_double),
+                ("peak_held_bytes", ctypes.c_size_t), ("device_allocs", ctypes.c_uint64)]
 
 
 class VPPlanInfo(ctypes.Structure):
@@ -331,8 +333,8 @@ def _scheck(status):
 class Server:
     """Continuous-admission serving loop (vp_server_*); requests name resident plans."""
 
-    def __init__(self, hbm_budget_bytes, max_in_flight=8, n_streams=4):
-        o = VPServerOpts(int(hbm_budget_bytes), int(max_in_flight), int(n_streams))
+    def __init__(self, hbm_budget_bytes, max_in_flight=8, n_streams=4, max_wait_us=0):
+        o = VPServerOpts(int(hbm_budget_bytes), int(max_in_flight), int(n_streams), int(max_wait_us))
         h = ctypes.c_void_p()
         _scheck(lib().vp_server_create(ctypes.byref(h), ctypes.byref(o)))
         self.handle = h

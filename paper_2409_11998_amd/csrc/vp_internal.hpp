@@ -168,6 +168,11 @@ size_t interp_lds_bytes_of(const Plan& p, int level);
 size_t workspace_bytes(const Plan& p);
 hipError_t workspace_alloc(const Plan& p, Workspace& ws, hipStream_t st, bool async);
 hipError_t workspace_free(Workspace& ws, hipStream_t st, bool async);
+// Lay out a workspace in a caller-owned block of at least workspace_bytes(p).
+void workspace_bind(const Plan& p, Workspace& ws, void* block, size_t bytes);
+// Validate the densities of one evaluation against the plan.
+vp_status eval_validate(const Plan& p, const double* f, const double* jet6, const double* sigma,
+                        const double* sigma_jet3, const double* mu, const double* mu_jet5, const double* out);
 // Validate densities against the plan and enqueue one evaluation on st into ws.
 vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* jet6,
                        const double* sigma, const double* sigma_jet3, const double* mu, const double* mu_jet5,

@@ -660,6 +660,14 @@ hipError_t workspace_alloc(const Plan& p, Workspace& ws, hipStream_t st, bool as
     return hipSuccess;
 }
 
+void workspace_bind(const Plan& p, Workspace& ws, void* block, size_t bytes)
+{
+    ws = Workspace{};
+    ws.block = block;
+    ws.bytes = bytes;
+    workspace_layout(p, &ws, (unsigned char*)block);
+}
+
 hipError_t workspace_free(Workspace& ws, hipStream_t st, bool async)
 {
     hipError_t e = hipSuccess;
@@ -668,9 +676,8 @@ hipError_t workspace_free(Workspace& ws, hipStream_t st, bool async)
     return e;
 }
 
-vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* jet6,
-                       const double* sigma, const double* sigma_jet3, const double* mu, const double* mu_jet5,
-                       double* out, bool timing)
+vp_status eval_validate(const Plan& p, const double* f, const double* jet6, const double* sigma,
+                        const double* sigma_jet3, const double* mu, const double* mu_jet5, const double* out)
 {
     if (!out && p.n_tgt) return fail(VP_ERR_ARG, "out is NULL");
     const bool use_v = f != nullptr;
@@ -683,6 +690,18 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
     if (use_v && !jet6) return fail(VP_ERR_ARG, "jet6 is required with f");
     if (use_s && !sigma_jet3) return fail(VP_ERR_ARG, "sigma_jet3 is required with sigma");
     if (use_d && !mu_jet5) return fail(VP_ERR_ARG, "mu_jet5 is required with mu");
+    return VP_OK;
+}
+
+vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* jet6,
+                       const double* sigma, const double* sigma_jet3, const double* mu, const double* mu_jet5,
+                       double* out, bool timing)
+{
+    vp_status vs = eval_validate(p, f, jet6, sigma, sigma_jet3, mu, mu_jet5, out);
+    if (vs != VP_OK) return vs;
+    const bool use_v = f != nullptr;
+    const bool use_s = sigma != nullptr;
+    const bool use_d = mu != nullptr;
     if (!ws.block) return fail(VP_ERR_ARG, "no workspace");
     if (timing && !p.ev_made) {
         for (auto& e : p.ev) VP_HIP(hipEventCreate(&e), "event create");

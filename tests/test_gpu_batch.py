@@ -57,14 +57,26 @@ def test_batch_matches_single_plans_and_oracle(precision):
     batch.close()
 
 
-def test_batch_rejects_mixed_widths_and_precisions():
+def test_batch_mixed_widths_run_and_mixed_precisions_are_rejected():
+    """Instances may differ in spreading width (one launch per distinct width);
+    they may not differ in precision."""
     from paper_2409_11998_amd import Batch, VPError
     torch, probs, devs, plans, run, mask = _setup(1, [300, 400])
     from workloads.device import make_plan
     loose = make_plan(devs[1], tol=1e-5, precision=1, kinds=mask)       # narrower kernel
     assert tuple(loose.info()["width"]) != tuple(plans[0].info()["width"])
+    pair = [plans[0], loose]
+    single = [run(p, d, "VD").clone() for p, d in zip(pair, devs)]
+    torch.cuda.synchronize()
+    batch = Batch(pair, mask)
+    outs = [torch.full((P.n_tgt,), np.nan, dtype=torch.float64, device="cuda") for P in probs]
+    args = [dict(f=d["f"], jet6=d["jet6"], mu=d["mu"], mu_jet=d["mu_jet"], out=o) for d, o in zip(devs, outs)]
+    for graph in (False, True, True):
+        batch.eval(args, graph=graph)
+        batch.stream.synchronize()
+        for o, s1 in zip(outs, single):
+            assert oracle.rel_linf(o.cpu().numpy(), s1.cpu().numpy()) <= 1e-13
+    batch.close()
+    fp32 = make_plan(devs[1], tol=1e-6, precision=0, kinds=mask)
     with pytest.raises(VPError):
-        Batch([plans[0], loose], mask)
-    single = make_plan(devs[1], tol=1e-6, precision=0, kinds=mask)
-    with pytest.raises(VPError):
-        Batch([plans[0], single], mask)
+        Batch([plans[0], fp32], mask)

@@ -40,14 +40,13 @@ def test_results_same_alone_and_in_the_mix():
     for p, d, k in zip(plans, devs, KINDS):
         alone.append(p.eval(**_args(d, k)).clone())   # temporary stream-ordered workspace
     torch.cuda.synchronize()
-    srv = Server(hbm_budget_bytes=2 << 30, max_in_flight=6, n_streams=4)
+    # a 200 ms admission window: requests submitted back to back share groups
+    srv = Server(hbm_budget_bytes=2 << 30, max_in_flight=6, n_streams=4, max_wait_us=200000)
     reps = 4
-    outs, tickets = [], []
-    for rep in range(reps):
-        for i in np.random.default_rng(rep).permutation(len(plans)):
-            o = torch.full((probs[i].n_tgt,), np.nan, dtype=torch.float64, device="cuda")
-            tickets.append((i, srv.submit(plans[i], o, **_args(devs[i], KINDS[i]))))
-            outs.append(o)
+    order = [i for rep in range(reps) for i in np.random.default_rng(rep).permutation(len(plans))]
+    outs = [torch.full((probs[i].n_tgt,), np.nan, dtype=torch.float64, device="cuda") for i in order]
+    torch.cuda.synchronize()
+    tickets = [(i, srv.submit(plans[i], o, **_args(devs[i], KINDS[i]))) for i, o in zip(order, outs)]
     for (i, t), o in zip(tickets, outs):
         st, lat = srv.wait(t, timeout=120)
         assert st == 0
@@ -59,15 +58,26 @@ def test_results_same_alone_and_in_the_mix():
     s = srv.stats()
     assert s["completed"] == reps * len(plans) and s["failed"] == 0
     assert s["peak_in_flight"] >= 2        # requests actually overlapped
+    assert s["groups"] < s["completed"]    # some requests ran together in one group
+    assert s["device_allocs"] < s["completed"]  # workspace blocks were reused
     assert s["p99_s"] >= s["p50_s"] > 0
     srv.close()
+
+
+def _size_class(b):
+    """The server's workspace size class: b rounded up to a multiple of 1/8 of
+    the largest power of two not above it (4 KiB at least)."""
+    if b <= 4096:
+        return 4096
+    q = 1 << (b.bit_length() - 1 - 3)
+    return -(-b // q) * q
 
 
 def test_budget_admission_and_rejection():
     from paper_2409_11998_amd import Server
     from paper_2409_11998_amd.binding import VP_ERR_OOM
     torch, probs, devs, plans = _problems()
-    ws = [p.info()["workspace_bytes"] for p in plans]
+    ws = [_size_class(p.info()["workspace_bytes"]) for p in plans]
     budget = int(1.3 * sorted(ws)[len(ws) // 2])   # about half the requests fit, never two big ones
     assert max(ws) > budget
     srv = Server(hbm_budget_bytes=budget, max_in_flight=8, n_streams=2)
@@ -80,7 +90,7 @@ def test_budget_admission_and_rejection():
         st, _ = srv.wait(t, timeout=120)
         assert st == (VP_ERR_OOM if ws[i] > budget else 0), (i, st, ws[i], budget)
     s = srv.stats()
-    assert s["peak_bytes"] <= budget
+    assert s["peak_bytes"] <= budget and s["peak_held_bytes"] <= budget
     assert s["completed"] == len(tickets)
     assert s["rejected"] == 3 * sum(1 for w in ws if w > budget)
     assert s["deferred"] >= 1              # requests waited for room
