@@ -74,7 +74,9 @@ typedef struct {
     int kinds;           /* VP_KIND_* bitmask this plan must support (default V|S|D)        */
     int fine_grid[2];    /* force fine-grid sizes F_NH, F_FH (0 = planner's choice)         */
     int spread_width[2]; /* force spreading widths w_NH, w_FH in grid cells (0 = planner)   */
-    int tile;            /* tile edge in grid cells for spread/interp (0 = planner)         */
+    int tile;            /* tile edge in grid cells for spread/interp (0 = planner); 16 on a
+                            float32 plan spreads on matrix cores (one 32x32 window of each
+                            tile in the MFMA accumulators), 32 through LDS windows          */
     void* stream;        /* hipStream_t the plan's work is enqueued on (NULL = null stream) */
     int no_workspace;    /* 1: keep only the plan's resident data (sorted nodes, tables, geometry);
                             every evaluation then takes a stream-ordered workspace (grids,
@@ -172,7 +174,8 @@ typedef struct {
     int modes[2];         /* 2*M+1 Fourier modes per dimension, NH and FH                     */
     int fine[2];          /* fine-grid sizes F_NH, F_FH                                       */
     int width[2];         /* spreading widths                                                 */
-    int tile;             /* tile edge in grid cells                                          */
+    int tile[2];          /* tile edge in grid cells, NH and FH                                */
+    int spread_mma[2];    /* 1: the level spreads on matrix cores                              */
     int precision;
     int64_t n_src, n_bnd, n_tgt;
     int64_t spread_records[2];  /* spread records per level (one per node)                   */

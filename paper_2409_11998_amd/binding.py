@@ -74,7 +74,8 @@ class VPPlanInfo(ctypes.Structure):
     _fields_ = [("delta1", ctypes.c_double), ("delta2", ctypes.c_double), ("eps_hist", ctypes.c_double),
                 ("period", ctypes.c_double * 2), ("kmax", ctypes.c_double * 2), ("trunc_L", ctypes.c_double),
                 ("modes", ctypes.c_int * 2), ("fine", ctypes.c_int * 2), ("width", ctypes.c_int * 2),
-                ("tile", ctypes.c_int), ("precision", ctypes.c_int), ("n_src", ctypes.c_int64),
+                ("tile", ctypes.c_int * 2), ("spread_mma", ctypes.c_int * 2), ("precision", ctypes.c_int),
+                ("n_src", ctypes.c_int64),
                 ("n_bnd", ctypes.c_int64), ("n_tgt", ctypes.c_int64), ("spread_records", ctypes.c_int64 * 2),
                 ("device_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
                 ("autotuned", ctypes.c_int), ("tune_candidates", ctypes.c_int * 2), ("level_ms", ctypes.c_double * 2)]
@@ -244,7 +245,7 @@ class Plan:
         _check(lib().vp_get_plan_info(self.handle, ctypes.byref(i)))
         return dict(delta1=i.delta1, delta2=i.delta2, eps_hist=i.eps_hist, period=tuple(i.period),
                     kmax=tuple(i.kmax), trunc_L=i.trunc_L, modes=tuple(i.modes), fine=tuple(i.fine),
-                    width=tuple(i.width), tile=i.tile, precision=i.precision, n_src=i.n_src, n_bnd=i.n_bnd,
+                    width=tuple(i.width), tile=tuple(i.tile), spread_mma=tuple(i.spread_mma), precision=i.precision, n_src=i.n_src, n_bnd=i.n_bnd,
                     n_tgt=i.n_tgt, spread_records=tuple(i.spread_records), device_bytes=i.device_bytes,
                     workspace_bytes=i.workspace_bytes, autotuned=bool(i.autotuned),
                     tune_candidates=tuple(i.tune_candidates), level_ms=tuple(i.level_ms))

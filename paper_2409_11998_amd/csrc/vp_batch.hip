@@ -123,6 +123,32 @@ __global__ __launch_bounds__(kThreads) void kg_spread(const InstDesc* __restrict
     }
 }
 
+// Matrix-core spread of float32 levels: an item is four work units, one per wavefront.
+template <int W>
+__global__ __launch_bounds__(kThreads) void kg_spread_mma(const InstDesc* __restrict__ inst,
+                                                          const LevelDesc* __restrict__ lv,
+                                                          const CallDesc* __restrict__ call, StageTab t)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
+        int i, l, u;
+        if (!decode(t, it, i, l, u)) continue;
+        const InstDesc& I = inst[i];
+        const CallDesc& K = call[i];
+        const LevelDesc& D = lv[2 * i + l];
+        const int unit = u * (kThreads / 64) + (threadIdx.x >> 6);
+        if (unit < D.n_sp_units) {
+            const int use_vol = K.f != nullptr && I.has_vol;
+            const int use_bnd = (K.sigma != nullptr || K.mu != nullptr) && I.has_bnd;
+            const int use_d = K.mu != nullptr;
+            dev::dev_spread_mma<W>(smem_raw, D.g, vol_view<float>(D), bnd_view<float>(D), (const float*)I.str,
+                                   I.n_src, I.n_bnd, (float*)D.grid, use_vol, use_bnd, use_d, D.horner,
+                                   D.sp_units[unit]);
+        }
+        __syncthreads();  // LDS reuse by the next item
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void kg_row_r2c(const LevelDesc* __restrict__ lv, StageTab t)
 {
@@ -263,6 +289,7 @@ void fill_instance(const Plan& p, const Workspace& ws, InstDesc& I, LevelDesc* D
         d.horner = lb.horner;
         d.sp_units = lb.sp_units;
         d.in_units = lb.in_units;
+        d.n_sp_units = (int)lb.h_sp_units.size();
     }
 }
 
@@ -315,20 +342,24 @@ vp_status group_build(const std::vector<const Plan*>& plans, const std::vector<W
             G.row.lds = std::max(G.row.lds, row_fft_lds_bytes(p, l));
             G.c2r.lds = G.row.lds;
             G.col.lds = std::max(G.col.lds, col_fft_lds_bytes(p, l));
-            auto stage_for = [&](std::map<int, int>& idx, std::vector<HostStage>& v) -> HostStage& {
-                auto f = idx.find(g.w);
+            // one stage per (width, spreading method)
+            auto stage_for = [&](std::map<int, int>& idx, std::vector<HostStage>& v, int mma) -> HostStage& {
+                const int key = 2 * g.w + mma;
+                auto f = idx.find(key);
                 if (f == idx.end()) {
-                    idx[g.w] = (int)v.size();
+                    idx[key] = (int)v.size();
                     v.emplace_back();
                     v.back().w = g.w;
+                    v.back().mma = mma;
                     return v.back();
                 }
                 return v[f->second];
             };
-            HostStage& sp = stage_for(sp_of_w, G.spread);
-            sp.add(i, l, (int)lb.h_sp_units.size());
+            HostStage& sp = stage_for(sp_of_w, G.spread, g.mma);
+            const int nsu = (int)lb.h_sp_units.size();
+            sp.add(i, l, g.mma ? (nsu + kThreads / 64 - 1) / (kThreads / 64) : nsu);
             sp.lds = std::max(sp.lds, spread_lds_bytes(p, l));
-            HostStage& in = stage_for(in_of_w, G.interp);
+            HostStage& in = stage_for(in_of_w, G.interp, 0);
             in.add(i, l, (int)lb.h_in_units.size());
             in.lds = std::max(in.lds, interp_lds_bytes_of(p, l));
         }
@@ -390,6 +421,23 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
         const StageTab& t = T.spread[k];
         if (!t.nitems) continue;
         const size_t lds = G.spread[k].lds;
+        if (G.spread[k].mma) {
+            if constexpr (!std::is_same<R, float>::value) return hipErrorInvalidValue;
+            switch (G.spread[k].w) {
+#define VP_CASE(W)                                                                                              \
+    case W:                                                                                                     \
+        (void)hipFuncSetAttribute((const void*)kg_spread_mma<W>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                                  (int)lds);                                                                    \
+        hipLaunchKernelGGL((kg_spread_mma<W>), dim3(persistent_grid(t.nitems, cus, 4)), dim3(kThreads), lds,   \
+                           st, T.inst, T.lv, T.call, t);                                                        \
+        break;
+                VP_W_CASES(VP_CASE)
+#undef VP_CASE
+            default:
+                return hipErrorInvalidValue;
+            }
+            continue;
+        }
         switch (G.spread[k].w) {
 #define VP_CASE(W)                                                                                              \
     case W:                                                                                                     \

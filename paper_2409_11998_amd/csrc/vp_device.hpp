@@ -29,27 +29,6 @@ namespace vp {
 namespace dev {
 
 
-// Spreading kernel values of one node at its w taps.  The kernel is the
-// exponential of semicircle exp(beta (sqrt(1 - z^2) - 1)), |z| < 1; tap a of a
-// node with offset d in [0, 1) sits at z = ((2a - w) + 2d) / w.  The planner
-// fits each tap as a polynomial of degree w+1 in u = 2d - 1 (Chebyshev
-// interpolation in float64, monomial form, error at the kernel's own e^-beta
-// level), so the values cost w(w+2) float64 FMAs with uniform (scalar-loaded)
-// coefficients instead of w exponentials, square roots and divisions.
-template <int W>
-__device__ __forceinline__ void kernel_taps(double d, const double* __restrict__ coef, double* out)
-{
-    constexpr int P = W + 2;
-    const double u = 2.0 * d - 1.0;
-#pragma unroll
-    for (int a = 0; a < W; ++a) {
-        double acc = coef[a * P + P - 1];
-#pragma unroll
-        for (int k = P - 2; k >= 0; --k) acc = fma(acc, u, coef[a * P + k]);
-        out[a] = acc;
-    }
-}
-
 // XCD-aware unit order.  Workgroups are dealt round-robin to the 8 XCDs
 // (each with its own L2), so consecutive block indices land on different
 // XCDs.  Giving each XCD a contiguous range of units (rows, columns, tiles)
@@ -279,11 +258,18 @@ __device__ __forceinline__ T lane_value(T v, int lane)
     }
 }
 
+// The tap polynomials are evaluated in float64 for both precisions.  An error
+// in the kernel values that is the same for every node at a given offset acts
+// as a change of the kernel's shape, which the deconvolution by 1/phihat^2
+// amplifies near the band edge: float32 Horner (about one ulp, coherent across
+// nodes) tripled the float32 path's end-to-end error.  One rounding of a
+// float64 value to float32 carries no such bias.
+
 // Horner evaluation of one tap's polynomial and its derivative in u.
-template <int P>
-__device__ __forceinline__ void tap_value_deriv(const double* __restrict__ c, double u, double& v, double& dv)
+template <int P, typename H>
+__device__ __forceinline__ void tap_value_deriv(const H* __restrict__ c, H u, H& v, H& dv)
 {
-    double p = c[P - 1], dp = 0.0;
+    H p = c[P - 1], dp = H(0);
 #pragma unroll
     for (int k = P - 2; k >= 0; --k) {
         dp = fma(dp, u, p);
@@ -337,7 +323,8 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
     constexpr int VST = RECS * 2 * W;     // staged values per wave chunk
     constexpr int RW = 64 / W;            // tap rows per atomic instruction
     constexpr int NI = (W + RW - 1) / RW; // atomic instructions per node
-    constexpr int P = W + 2;
+    using H = double;
+    constexpr int P = horner_terms(W);
     constexpr int G = 64 / W;             // offset groups of the kernel-value evaluation
     const int T = g.T;
     const int E = T + W - 1;
@@ -376,11 +363,11 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
     const bool lane_on = lane < RW * W;
     // kernel-value evaluation: lane -> tap ta, offset group tb0 (G groups); the
     // tap's polynomial coefficients stay in this lane's registers
-    double cf[P];
+    H cf[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) cf[k] = coef[ta * P + k];
+    for (int k = 0; k < P; ++k) cf[k] = (H)coef[ta * P + k];
     const int64_t n_all = n_src + n_bnd;
-    const double dscale = -2.0 / g.h;  // d/dy of a tap value = -(2/h) d/du
+    const H dscale = (H)(-2.0 / g.h);  // d/dy of a tap value = -(2/h) d/du
 
     // DL = false: one strength per node; DL = true: double-layer boundary nodes,
     // value s phi_x phi_y + gx phi_x' phi_y + gy phi_x phi_y'.
@@ -428,15 +415,15 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
                 if (lane_on) {
                     const int nv2 = 2 * nrec;
                     for (int q = tb0; q < nv2; q += G) {
-                        const double u = 2.0 * (double)dd[q] - 1.0;
+                        const H u = H(2) * (H)dd[q] - H(1);
                         R* dst = vals + (q >> 1) * VS + (q & 1) * W + ta;
                         if constexpr (DL) {
-                            double v, dv;
+                            H v, dv;
                             tap_value_deriv<P>(cf, u, v, dv);
                             dst[0] = (R)v;
                             dst[2 * W] = (R)(dscale * dv);
                         } else {
-                            double acc = cf[P - 1];
+                            H acc = cf[P - 1];
 #pragma unroll
                             for (int k = P - 2; k >= 0; --k) acc = fma(acc, u, cf[k]);
                             dst[0] = (R)acc;
@@ -513,6 +500,179 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
             const A a = win[y * EP + x];
             if (a != A(0)) unsafeAtomicAdd(grid + (size_t)gy * F + gx, (R)FP::dec(a, inv_q));
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Spread on matrix cores (float32 plans, 16 x 16 tiles).
+//
+// A tile's window of 32 x 32 cells (the tile plus the w - 1 cells its nodes'
+// supports reach beyond it, padded) receives
+//     window[y][x] = sum_j phi_y,j(y) * (s_j phi_x,j(x)),
+// a sum of outer products of two 32-vectors per node, each with w nonzero
+// entries at the node's corner offset -- a rank-n update that one
+// v_mfma_f32_32x32x2_f32 advances by two nodes while the whole window stays in
+// the wavefront's accumulation registers (no LDS atomics).  A double-layer
+// node adds gx phi_x' phi_y + gy phi_x phi_y' (Sec. 3, Step 2, through the
+// kernel derivative as in the LDS path), which is two outer products:
+// phi_y (x) (s phi_x + gx phi_x') and (gy phi_y') (x) phi_x.
+//
+// One wavefront per work unit.  Per chunk of 32 rank-1 terms the wavefront
+// writes their factors into LDS rows of 32 entries (lane pairs: one record,
+// x or y; each lane zeroes its own row, then evaluates the w taps in float64
+// with the tap's coefficients uniform across the wavefront), then runs 16 matrix
+// instructions reading the rows.  The next chunk's records are loaded while
+// the current one is processed.  Each chunk's products accumulate in float32 in
+// the matrix registers and are then added to a float64 copy of the window, which
+// is added to the grid (float32) with global atomics.
+//
+// Measured on gfx950 (disk with 12M nodes, F = 4096 / 2048, w = 13 / 10):
+// 0.51 / 0.44 ms against 1.01 / 0.67 ms for the LDS path.  The float64 form
+// (four 16x16x4 blocks) was slower than the LDS path: float64 matrix
+// instructions run at the vector rate on this chip.
+constexpr int kMmaChunk = 32;  // rank-1 terms (factor-row pairs) per chunk
+using mma_f32x16 = float __attribute__((ext_vector_type(16)));
+
+__host__ __device__ constexpr size_t mma_wave_bytes() { return (size_t)kMmaChunk * 64 * sizeof(float); }
+
+template <int W>
+__device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, const RecView<float>& vol,
+                               const RecView<float>& bnd, const float* __restrict__ str, int64_t n_src,
+                               int64_t n_bnd, float* __restrict__ grid, int use_vol, int use_bnd, int use_d,
+                               const double* __restrict__ coef, const WorkUnit unit)
+{
+    constexpr int NPC = kMmaChunk;
+    constexpr int P = horner_terms(W);
+    static_assert(kMmaTile + W - 1 <= 32, "window of 32 cells");
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    float* Ay = reinterpret_cast<float*>(smem_raw + (size_t)wv * mma_wave_bytes());  // [NPC][32] y factors
+    float* Bx = Ay + NPC * 32;                                                          // [NPC][32] x factors
+    const int t = unit.tile;
+    const int gx0 = (t % g.ntx) * kMmaTile, gy0 = (t / g.ntx) * kMmaTile;
+    const int nv = use_vol ? unit.a1 - unit.a0 : 0;
+    const int nbd = use_bnd ? unit.b1 - unit.b0 : 0;
+    if (nv == 0 && nbd == 0) return;  // uniform across the wavefront
+    const int64_t n_all = n_src + n_bnd;
+    const double dscale = -2.0 / g.h;  // d/dy of a tap value = -(2/h) d/du
+    const int axis = lane & 1;         // 0: x factor, 1: y factor
+    const int rec = lane >> 1;
+    // each chunk accumulates from zero in the matrix registers (16 roundings);
+    // the chunk's window is then added in float64, so the float32 rounding
+    // does not build up over the unit's hundreds of nodes
+    double win[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) win[r] = 0.0;
+
+    auto path = [&](const RecView<float>& L, int r0, int r1, auto dl_tag) {
+        constexpr bool DL = decltype(dl_tag)::value;
+        constexpr int NRC = DL ? NPC / 2 : NPC;  // records per chunk
+        int p_off = 0;
+        float p_d = 0.f, p_s = 0.f, p_gx = 0.f, p_gy = 0.f;
+        auto fetch = [&](int c0) {  // this lane's record of the chunk at c0, its axis
+            const int r = c0 + rec;
+            if (rec < NRC && r < r1) {
+                const int ij = L.ij[r];
+                const int idx = L.idx[r];
+                p_d = axis ? L.dy[r] : L.dx[r];
+                p_off = axis ? (ij >> 16) - gy0 : (ij & 0xffff) - gx0;
+                p_s = str[idx];
+                if (DL) {
+                    p_gx = str[n_all + (idx - n_src)];
+                    p_gy = str[n_all + n_bnd + (idx - n_src)];
+                }
+            }
+        };
+        fetch(r0);
+        for (int c0 = r0; c0 < r1; c0 += NRC) {
+            const int n = min(NRC, r1 - c0);
+            const int np = DL ? 2 * n : n;
+            const double u = 2.0 * (double)p_d - 1.0;
+            const int off = p_off;
+            const double s_ = p_s, gx_ = p_gx, gy_ = p_gy;
+            if (c0 + NRC < r1) fetch(c0 + NRC);
+            // this lane's factor row(s): zero, then the w taps at the corner offset
+            float* row = (axis ? Ay : Bx) + (DL ? 2 * rec : rec) * 32;
+            if (rec < NRC) {
+                const float4 z{};
+#pragma unroll
+                for (int k = 0; k < (DL ? 16 : 8); ++k) reinterpret_cast<float4*>(row)[k] = z;
+            }
+            const bool on = rec < n;
+            if constexpr (!DL) {
+                // the kernel is even: tap w-1-a at offset u is tap a at -u, so with
+                // tap a's polynomial split as E(u^2) + u O(u^2) one evaluation gives both
+                const double u2 = u * u;
+                const double sc = axis == 0 ? s_ : 1.0;
+#pragma unroll 2
+                for (int a = 0; a < W / 2; ++a) {
+                    const double* ca = coef + a * P;  // uniform: scalar loads
+                    double e = ca[2 * ((P - 1) / 2)];
+#pragma unroll
+                    for (int k = (P - 1) / 2 - 1; k >= 0; --k) e = fma(e, u2, ca[2 * k]);
+                    double o = ca[2 * ((P - 2) / 2) + 1];
+#pragma unroll
+                    for (int k = (P - 2) / 2 - 1; k >= 0; --k) o = fma(o, u2, ca[2 * k + 1]);
+                    if (on) {
+                        row[off + a] = (float)(sc * fma(u, o, e));
+                        row[off + W - 1 - a] = (float)(sc * fma(-u, o, e));
+                    }
+                }
+                if (W & 1) {  // the middle tap
+                    const double* ca = coef + (W / 2) * P;
+                    double v = ca[P - 1];
+#pragma unroll
+                    for (int k = P - 2; k >= 0; --k) v = fma(v, u, ca[k]);
+                    if (on) row[off + W / 2] = (float)(sc * v);
+                }
+            }
+#pragma unroll 2
+            for (int a = 0; a < (DL ? W : 0); ++a) {
+                const double* ca = coef + a * P;  // uniform: scalar loads
+                if constexpr (DL) {
+                    double v = ca[P - 1], dv = 0.0;
+#pragma unroll
+                    for (int k = P - 2; k >= 0; --k) {
+                        dv = fma(dv, u, v);
+                        v = fma(v, u, ca[k]);
+                    }
+                    dv *= dscale;
+                    if (on) {
+                        if (axis == 0) {
+                            row[off + a] = (float)(s_ * v + gx_ * dv);
+                            row[32 + off + a] = (float)v;
+                        } else {
+                            row[off + a] = (float)v;
+                            row[32 + off + a] = (float)(gy_ * dv);
+                        }
+                    }
+                }
+            }
+            wave_sync_lds();
+            // rank-1 terms [0, np) (rows up to the next even index are zero)
+            const int i = lane & 31;
+            mma_f32x16 acc = {};
+#pragma unroll 4
+            for (int m = 0; m < np; m += 2) {
+                const int r = m + (lane >> 5);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Ay[r * 32 + i], Bx[r * 32 + i], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) win[r] += (double)acc[r];
+            wave_sync_lds();
+        }
+    };
+    if (nv) path(vol, unit.a0, unit.a1, std::false_type{});
+    if (nbd && !use_d) path(bnd, unit.b0, unit.b1, std::false_type{});
+    if (nbd && use_d) path(bnd, unit.b0, unit.b1, std::true_type{});
+    // result element r of lane l: window row (r % 4) + 8 (r / 4) + 4 (l / 32), column l % 32
+    const int F = g.F;
+    const int gx = gx0 + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int gy = gy0 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+        const float v = (float)win[r];
+        if (v != 0.f && gx < F && gy < F) unsafeAtomicAdd(grid + (size_t)gy * F + gx, v);
     }
 }
 
@@ -633,7 +793,8 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
                            const RecView<R>& L, R* __restrict__ hist, const double* __restrict__ coef,
                            const WorkUnit unit)
 {
-    constexpr int P = W + 2;
+    using H = double;
+    constexpr int P = horner_terms(W);
     constexpr int NT = kInterpTargets;
     constexpr int VS = 2 * W;
     constexpr int G = 64 / W;
@@ -663,9 +824,9 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
     const int ka = lane % W;
     const int kg = lane / W;
     const bool kon = lane < G * W;
-    double cf[P];
+    H cf[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) cf[k] = coef[ka * P + k];
+    for (int k = 0; k < P; ++k) cf[k] = (H)coef[ka * P + k];
     __syncthreads();
     const int q = lane >> 1;    // target of this lane within the chunk
     const int half = lane & 1;  // rows [0, HB) or [HB, W)
@@ -681,8 +842,8 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
         wave_sync_lds();
         if (kon) {
             for (int pq = kg; pq < 2 * nt; pq += G) {
-                const double u = 2.0 * (double)dd[pq] - 1.0;
-                double acc = cf[P - 1];
+                const H u = H(2) * (H)dd[pq] - H(1);
+                H acc = cf[P - 1];
 #pragma unroll
                 for (int k = P - 2; k >= 0; --k) acc = fma(acc, u, cf[k]);
                 vals[(pq >> 1) * VS + (pq & 1) * W + ka] = (R)acc;

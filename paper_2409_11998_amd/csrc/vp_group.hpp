@@ -24,6 +24,7 @@ struct LevelDesc {
     const double* horner;
     const WorkUnit* sp_units;
     const WorkUnit* in_units;
+    int n_sp_units;
 };
 
 struct InstDesc {
@@ -68,6 +69,7 @@ struct HostStage {
     std::vector<Seg> seg;
     int nitems = 0;
     int w = 0;       // spreading width (spread / interpolation stages)
+    int mma = 0;     // spread stage on matrix cores (float32 levels on kMmaTile tiles)
     size_t lds = 0;  // dynamic LDS bytes of the launch
     void add(int inst, int level, int count);
 };

@@ -15,6 +15,15 @@ constexpr int kWMax = 16;        // largest spreading width (grid cells per dime
 constexpr int kWMin = 4;         // smallest spreading width
 constexpr int kThreads = 256;    // threads per workgroup for grid kernels
 constexpr int kDcParts = 64;     // partial sums of the zero-frequency term (one wavefront reads them)
+// Terms of the per-tap polynomials of the spreading kernel (degree + 1).  Each
+// tap's piece of the kernel over one grid cell is fitted in u = 2d - 1 by
+// Chebyshev interpolation (converted to monomial form) with w + 2 terms: fit
+// error at the kernel's own exp(-beta) level.  Fewer terms for float32 plans
+// (10: value error below 2e-10) measurably raised the double-layer error,
+// whose derivative taps need the fuller fit.
+__host__ __device__ constexpr int horner_terms(int w) { return w + 2; }
+constexpr int kMmaTile = 16;     // tile edge of the matrix-core spread (window of 32 x 32 cells)
+
 // Launches timed by vp_set_timing, in order: grid zeroing + strengths; spread NH, FH; row FFT NH,
 // FH; column FFT NH, FH; row inverse NH, FH; interpolation NH, FH; local part.
 constexpr int kTimedLaunches = 12;
@@ -36,6 +45,7 @@ struct LevelGeom {
     double dk;      // 2 pi / P
     double dc_coef; // (dk/2pi)^2 * multiplier(0): the zero mode's kernel weight
     double dmax;    // max over taps and offsets of |d/dy tap value| (double-layer spreading bound)
+    int mma;        // spread on matrix cores (float32 plans on kMmaTile tiles), else LDS atomics
 };
 
 // A tile-sorted list of points of one level (CSR by tile): each point appears

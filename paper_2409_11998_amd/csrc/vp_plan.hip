@@ -420,9 +420,9 @@ vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, 
     g.dc_coef = scale * ((l == 0) ? mult_nh(0.0, d1, d2) : mult_fh(0.0, d2, p.L));
     // Spreading kernel per tap as a polynomial in the node offset: tap a of a
     // node with offset d in [0,1) sits at z = ((2a - w) + (u + 1)) / w, u = 2d - 1.
-    // Chebyshev interpolation at w+2 points, converted to monomials in u.
+    // Chebyshev interpolation at horner_terms(w) points, converted to monomials in u.
     {
-        const int W = g.w, P = W + 2;
+        const int W = g.w, P = horner_terms(W);
         std::vector<double> coef((size_t)W * P);
         std::vector<double> cn(P), fv(P);
         for (int j = 0; j < P; ++j) cn[j] = std::cos(M_PI * (j + 0.5) / P);
@@ -524,6 +524,7 @@ vp_status set_level_geom(Plan& p, int l, const LevelCand& c, int T, double cx, d
     if (T < 1 || c.F % T) return fail(VP_ERR_ARG, "tile must divide the fine grid");
     g.T = T;
     g.ntx = c.F / T;
+    g.mma = (p.precision == VP_FP32 && T == kMmaTile) ? 1 : 0;
     phihat = kernel_ft(c.w, g.beta, c.F, c.M);
     for (double v : phihat)
         if (!(v > 0)) return fail(VP_ERR_INTERNAL, "spreading kernel transform not positive");
@@ -1000,7 +1001,7 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
     std::vector<int> tiles;
     if (o.tile > 0) tiles.push_back(o.tile);
     else if (o.autotune) tiles = {32, 16};
-    else tiles.push_back(32);
+    else tiles.push_back(0);  // by width, below
     p->autotuned = o.autotune ? 1 : 0;
     for (int l = 0; l < 2; ++l) {
         std::vector<double> ph;
@@ -1027,10 +1028,14 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
             p->level_ms[l] = best_ms;
         } else {
             for (size_t ci = 0; ci < cands[l].size() && best_c < 0; ++ci) {
-                if ((s = set_level_geom(*p, l, cands[l][ci], tiles[0], cx, cy, ph)) != VP_OK) return bail(s);
+                // without a measurement: the matrix-core spread for float32 levels of width >= 12
+                // (measured faster there; at narrower widths the LDS path is as fast and its
+                // exact fixed-point windows round less), 32-cell tiles otherwise
+                const int T = tiles[0] > 0 ? tiles[0] : (fp32 && cands[l][ci].w >= 12 ? kMmaTile : 32);
+                if ((s = set_level_geom(*p, l, cands[l][ci], T, cx, cy, ph)) != VP_OK) return bail(s);
                 if (level_fits_lds(*p, l)) {
                     best_c = (int)ci;
-                    best_T = tiles[0];
+                    best_T = T;
                 }
             }
         }
@@ -1100,7 +1105,10 @@ vp_status vp_get_plan_info(vp_plan_t p, vp_plan_info* info)
         info->width[l] = p->lv[l].w;
         info->spread_records[l] = p->lb[l].vol.n + p->lb[l].bnd.n;
     }
-    info->tile = p->lv[0].T;
+    for (int l = 0; l < 2; ++l) {
+        info->tile[l] = p->lv[l].T;
+        info->spread_mma[l] = p->lv[l].mma;
+    }
     info->precision = p->precision;
     info->n_src = p->n_src;
     info->n_bnd = p->n_bnd;
