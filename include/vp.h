@@ -248,9 +248,10 @@ const char* vp_batch_last_error(void);
  * queued requests that fit -- in FIFO order, one precision at a time, a
  * request that does not fit never blocking smaller ones behind it -- and runs
  * them as one group: one persistent kernel per stage for all of them (the
- * batched execution of vp_batch_*), on one of n_streams streams, so requests
- * arriving while others run join the next group without waiting for the
- * running ones and groups overlap on the device.  Plans stay resident; each
+ * batched execution of vp_batch_*), on an idle one of n_streams streams.  At
+ * most one group per stream is in flight: while every stream is busy,
+ * arrivals wait on the host and join the next group, so groups grow with the
+ * load; groups on different streams overlap on the device.  Plans stay resident; each
  * running request holds a workspace block (grids, spectra, strengths) of its
  * HBM footprint rounded up to a size class (at most 1/8 more); blocks are
  * cached and reused once the group that used them completes, and the blocks
@@ -265,7 +266,7 @@ typedef struct vp_server_s* vp_server_t;
 typedef struct {
     size_t hbm_budget_bytes;  /* cap on the workspace memory held (in use + cached)          */
     int max_in_flight;        /* cap on concurrently running requests                        */
-    int n_streams;            /* streams requests are spread over (1..16)                    */
+    int n_streams;            /* streams, and groups in flight (1..16)                       */
     int max_wait_us;          /* admission delay to gather a group (0: admit at once; >= 0)  */
 } vp_server_opts;
 

@@ -7,9 +7,11 @@
 // in FIFO order, all of one precision (the first admissible request's), a
 // request that does not fit never blocking smaller ones behind it -- and runs
 // them as one group: the persistent per-stage kernels of the batched
-// execution, one launch per stage for the whole group, on the least-loaded of
-// several streams.  Requests that arrive while groups run wait only for the
-// next admission, and groups on different streams overlap on the GPU.
+// execution, one launch per stage for the whole group, on an idle one of
+// several streams.  At most one group per stream is in flight: while every
+// stream is busy, arrivals wait on the host and the next free stream takes
+// them all as one group, so groups grow with the load instead of work queueing
+// on the device.  Groups on different streams overlap on the GPU.
 //
 // Memory.  Every admitted request gets a workspace block (grids, spectra,
 // strengths) of its plan's footprint rounded up to a size class (at most
@@ -250,6 +252,9 @@ bool select_group(vp_server_s* S, std::vector<Req*>& take, size_t& bytes)
     bool finished_any = false;
     int precision = -1;
     bytes = 0;
+    // at most one group per stream in flight: while every stream is busy, arrivals
+    // wait on the host and join the next group instead of queueing on the device
+    const bool room = (int)S->running.size() < S->opts.n_streams;
     for (auto it = S->queue.begin(); it != S->queue.end();) {
         Req* q = *it;
         if (q->bytes > S->opts.hbm_budget_bytes) {
@@ -268,7 +273,7 @@ bool select_group(vp_server_s* S, std::vector<Req*>& take, size_t& bytes)
             finished_any = true;
             continue;
         }
-        const bool fits = S->in_flight + (int)take.size() < S->opts.max_in_flight &&
+        const bool fits = room && S->in_flight + (int)take.size() < S->opts.max_in_flight &&
                           S->in_flight_bytes + bytes + q->bytes <= S->opts.hbm_budget_bytes &&
                           (int)take.size() < kMaxGroup;
         if (!fits || (precision >= 0 && p.precision != precision)) {
