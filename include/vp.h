@@ -158,6 +158,41 @@ vp_status vp_volume(vp_plan_t plan, const double* f_src, const double* jet6, dou
 vp_status vp_layer(vp_plan_t plan, const double* sigma, const double* sigma_jet3,
                    const double* mu, const double* mu_jet5, double* out);
 
+/* Dyadic refinement of the local layer parts (Sec. 4, subsection on computing
+ * the local part with arbitrary precision).  S_L and D_L are accurate to the
+ * truncation order of their small-time expansions in delta_1.  With J levels
+ * the expansions are taken at delta* = delta_1 / 4^J, and the time slices
+ * [delta_1/4^j, delta_1/4^(j-1)], j = 1..J, are added by direct quadrature
+ * over an oversampled boundary (the slice kernels narrow by a factor two per
+ * level, so the boundary must resolve the last one: e.g. every panel split
+ * into 2^J).  The slices telescope into one kernel per boundary node, which
+ * is what the device evaluates:
+ *   S: (E1(rho^2 / 4 delta_1) - E1(rho^2 / 4 delta*)) / (4 pi),
+ *   D: nu_y.(x - y) (exp(-rho^2 / 4 delta_1) - exp(-rho^2 / 4 delta*)) / (2 pi rho^2),
+ * rho = |x - y|, summed over the nodes within 12 sqrt(delta_1) of the target.
+ *
+ * vp_refine_attach: attach J (1..8) and the oversampled boundary: n_fine nodes
+ * (fine_x, fine_y) with outward unit normals (fine_nx, fine_ny) and quadrature
+ * weights fine_w >= 0, plus the plan's targets again (tgt_x, tgt_y; n_tgt
+ * entries) -- all device float64 arrays, copied.  Bins the nodes and lists the
+ * targets within 12 sqrt(delta_1) of the boundary (synchronizes the plan's
+ * stream).  Replaces an earlier attachment.  VP_ERR_ARG for NULL or
+ * non-finite input, negative weights or J out of range.
+ *
+ * vp_layer_refine: ADD the refinement to out[n_tgt] (after vp_eval or
+ * vp_layer has written it):
+ *   S_L(delta*) - S_L(delta_1) + slices of S   (sigma_jet3 as in vp_eval; fine_sigma
+ *                                               = sigma at the attached nodes)
+ *   D_L(delta*) - D_L(delta_1) + slices of D   (mu_jet5, fine_mu likewise)
+ * A pair may be NULL (kind omitted); its kind must be in the plan.  Computed
+ * in float64 for either plan precision.  Enqueues on the plan's stream.
+ * VP_ERR_ARG without an attachment. */
+vp_status vp_refine_attach(vp_plan_t plan, int levels, int64_t n_fine, const double* fine_x,
+                           const double* fine_y, const double* fine_nx, const double* fine_ny,
+                           const double* fine_w, const double* tgt_x, const double* tgt_y);
+vp_status vp_layer_refine(vp_plan_t plan, const double* sigma_jet3, const double* fine_sigma,
+                          const double* mu_jet5, const double* fine_mu, double* out);
+
 /* Release the plan and its device memory (synchronizes its stream). NULL is a no-op. */
 vp_status vp_destroy(vp_plan_t plan);
 

@@ -21,7 +21,7 @@ EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "v
             "vp_last_error", "vp_get_plan_info", "vp_set_timing", "vp_get_timing",
             "vp_batch_create", "vp_batch_eval", "vp_batch_destroy", "vp_batch_last_error",
             "vp_server_create", "vp_server_submit", "vp_server_poll", "vp_server_wait", "vp_server_get_stats",
-            "vp_server_destroy", "vp_server_last_error"]
+            "vp_server_destroy", "vp_server_last_error", "vp_refine_attach", "vp_layer_refine"]
 
 
 class VPError(RuntimeError):
@@ -105,6 +105,10 @@ def lib():
         L.vp_volume.restype = ctypes.c_int
         L.vp_layer.argtypes = [vp] * 6
         L.vp_layer.restype = ctypes.c_int
+        L.vp_refine_attach.argtypes = [vp, ctypes.c_int, ctypes.c_int64] + [vp] * 7
+        L.vp_refine_attach.restype = ctypes.c_int
+        L.vp_layer_refine.argtypes = [vp] * 6
+        L.vp_layer_refine.restype = ctypes.c_int
         L.vp_destroy.argtypes = [vp]
         L.vp_destroy.restype = ctypes.c_int
         L.vp_last_error.argtypes = []
@@ -238,6 +242,23 @@ class Plan:
             out = torch.empty(self.n_tgt, dtype=f64, device=self.device)
         _check(lib().vp_layer(self.handle, _ptr(sigma, f64), _ptr(sigma_jet, f64), _ptr(mu, f64),
                               _ptr(mu_jet, f64), _ptr(out, f64)))
+        return out
+
+    def refine_attach(self, levels, fine_x, fine_y, fine_nx, fine_ny, fine_w, tgt_x, tgt_y):
+        """Attach the oversampled boundary of the dyadic refinement (vp_refine_attach)."""
+        import torch
+        f64 = torch.float64
+        _check(lib().vp_refine_attach(self.handle, int(levels), int(fine_x.numel()), _ptr(fine_x, f64),
+                                      _ptr(fine_y, f64), _ptr(fine_nx, f64), _ptr(fine_ny, f64), _ptr(fine_w, f64),
+                                      _ptr(tgt_x, f64), _ptr(tgt_y, f64)))
+        self._refine_keep = (fine_x, fine_y, fine_nx, fine_ny, fine_w)
+
+    def layer_refine(self, out, sigma_jet=None, fine_sigma=None, mu_jet=None, fine_mu=None):
+        """Add the dyadic refinement of the local layer parts to out (vp_layer_refine)."""
+        import torch
+        f64 = torch.float64
+        _check(lib().vp_layer_refine(self.handle, _ptr(sigma_jet, f64), _ptr(fine_sigma, f64), _ptr(mu_jet, f64),
+                                     _ptr(fine_mu, f64), _ptr(out, f64)))
         return out
 
     def info(self):

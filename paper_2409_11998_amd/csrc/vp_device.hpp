@@ -922,6 +922,62 @@ __device__ __forceinline__ double hist_at(const void* h, int fp32, int64_t i)
     return fp32 ? (double)((const float*)h)[i] : ((const double*)h)[i];
 }
 
+// Local single-layer part S_L[sigma] at one target (Lemma 4.1 with the overall
+// sign reversed, as pinned against brute-force quadrature), for c = r/sqrt(d) <= 12.
+__device__ inline double s_local_value(double d, double r, double sg, double kap, double g3, double g4, double s0,
+                                       double s1, double s2, int order)
+{
+    const double SQPI = 1.7724538509055160273;
+    const double sd = sqrt(d);
+    const double c = r / sd;
+    if (c > 12.0) return 0.0;
+    const double E = erfc(0.5 * c);
+    const double e = exp(-0.25 * c * c);
+    const double c2 = c * c, c3 = c2 * c;
+    const double P1 = c * E - 2.0 * e / SQPI;
+    const double Q = 2.0 * (c2 - 2.0) * e / SQPI - c3 * E;
+    double s = 0.0;
+    if (order >= 1) s += sd * 0.5 * s0 * P1;
+    if (order >= 2) s += sg * d * c * kap * s0 * 0.25 * P1;
+    if (order >= 3) s += d * sd * (s0 * kap * kap / 12.0 * (2.0 * c3 * E - (4.0 * c2 + 1.0) * e / SQPI) + s2 / 12.0 * Q);
+    if (order >= 4)
+        s += d * d * sg *
+             (c * kap * kap * kap * s0 / 16.0 * (3.0 * c3 * E - (6.0 * c2 - 2.0) * e / SQPI) + c * kap * s2 / 8.0 * Q +
+              c * s0 * g4 / 48.0 * Q + c * s1 * g3 / 12.0 * Q);
+    return -s;
+}
+
+// Local double-layer part D_L[mu] at one target (Lemma 4.3 with the overall
+// sign reversed), for c = r/sqrt(d) <= 12; m[0..4] = mu and its derivatives at b.
+__device__ inline double d_local_value(double d, double r, double sg, double kap, double g3, double g4,
+                                       const double* m, int order)
+{
+    const double SQPI = 1.7724538509055160273;
+    const double sd = sqrt(d);
+    const double c = r / sd;
+    if (c > 12.0) return 0.0;
+    const double E = erfc(0.5 * c);
+    const double e = exp(-0.25 * c * c);
+    const double c2 = c * c, c3 = c2 * c;
+    const double m0 = m[0], m1 = m[1], m2 = m[2], m4 = m[4];
+    double s = sg * 0.5 * m0 * E;
+    if (order >= 1) s += sd * kap * m0 / (2.0 * SQPI) * e;
+    if (order >= 2) s += d * sg * (3.0 * c * kap * kap * m0 / (8.0 * SQPI) * e + c * m2 * 0.25 * (2.0 * e / SQPI - c * E));
+    const double A = 2.0 * (c2 + 1.0) * e / SQPI - c3 * E;
+    const double B = 2.0 * (c2 + 4.0) * e / SQPI - c3 * E;
+    if (order >= 3)
+        s += d * sd * (5.0 * (c2 - 2.0) * kap * kap * kap * m0 / (16.0 * SQPI) * e + g4 * m0 / (4.0 * SQPI) * e +
+                       kap * m2 * 0.25 * A + g3 * m1 / 12.0 * B);
+    if (order >= 4) {
+        s += d * d * sg *
+             (35.0 * c * kap * kap * kap * kap * m0 * (c2 - 6.0) / (128.0 * SQPI) * e +
+              5.0 * c * g3 * g3 * m0 / (12.0 * SQPI) * e + 5.0 * c * kap * g4 * m0 / (8.0 * SQPI) * e);
+        s += d * d * sg * 5.0 * c * (kap * kap * m2 / 16.0 * A + kap * g3 * m1 / 24.0 * B);
+        s += d * d * sg * c * m4 / 48.0 * (c3 * E - 2.0 * (c2 - 2.0) * e / SQPI);
+    }
+    return -s;
+}
+
 __device__ void dev_local(const LocalArgs& a, int64_t i)
 {
     const double dcv = a.dc ? dc_total(a.dc) : 0.0;  // before any lane leaves
@@ -975,39 +1031,10 @@ __device__ void dev_local(const LocalArgs& a, int64_t i)
         }
         u += v;
     }
-    if (a.sj) {
-        const double s0 = a.sj[i], s1 = a.sj[n + i], s2 = a.sj[2 * n + i];
-        const double P1 = c * E - 2.0 * e / SQPI;
-        const double Q = 2.0 * (c2 - 2.0) * e / SQPI - c3 * E;
-        double s = 0.0;
-        if (a.order_s >= 1) s += sd * 0.5 * s0 * P1;
-        if (a.order_s >= 2) s += sg * d * c * kap * s0 * 0.25 * P1;
-        if (a.order_s >= 3)
-            s += d * sd * (s0 * kap * kap / 12.0 * (2.0 * c3 * E - (4.0 * c2 + 1.0) * e / SQPI) + s2 / 12.0 * Q);
-        if (a.order_s >= 4)
-            s += d * d * sg *
-                 (c * kap * kap * kap * s0 / 16.0 * (3.0 * c3 * E - (6.0 * c2 - 2.0) * e / SQPI) +
-                  c * kap * s2 / 8.0 * Q + c * s0 * g4 / 48.0 * Q + c * s1 * g3 / 12.0 * Q);
-        u -= s;
-    }
+    if (a.sj) u += s_local_value(d, r, sg, kap, g3, g4, a.sj[i], a.sj[n + i], a.sj[2 * n + i], a.order_s);
     if (a.mj) {
-        const double m0 = a.mj[i], m1 = a.mj[n + i], m2 = a.mj[2 * n + i], m4 = a.mj[4 * n + i];
-        double s = sg * 0.5 * m0 * E;
-        if (a.order_d >= 1) s += sd * kap * m0 / (2.0 * SQPI) * e;
-        if (a.order_d >= 2) s += d * sg * (3.0 * c * kap * kap * m0 / (8.0 * SQPI) * e + c * m2 * 0.25 * (2.0 * e / SQPI - c * E));
-        const double A = 2.0 * (c2 + 1.0) * e / SQPI - c3 * E;
-        const double B = 2.0 * (c2 + 4.0) * e / SQPI - c3 * E;
-        if (a.order_d >= 3)
-            s += d * sd * (5.0 * (c2 - 2.0) * kap * kap * kap * m0 / (16.0 * SQPI) * e + g4 * m0 / (4.0 * SQPI) * e +
-                           kap * m2 * 0.25 * A + g3 * m1 / 12.0 * B);
-        if (a.order_d >= 4) {
-            s += d * d * sg *
-                 (35.0 * c * kap * kap * kap * kap * m0 * (c2 - 6.0) / (128.0 * SQPI) * e +
-                  5.0 * c * g3 * g3 * m0 / (12.0 * SQPI) * e + 5.0 * c * kap * g4 * m0 / (8.0 * SQPI) * e);
-            s += d * d * sg * 5.0 * c * (kap * kap * m2 / 16.0 * A + kap * g3 * m1 / 24.0 * B);
-            s += d * d * sg * c * m4 / 48.0 * (c3 * E - 2.0 * (c2 - 2.0) * e / SQPI);
-        }
-        u -= s;
+        const double m[5] = {a.mj[i], a.mj[n + i], a.mj[2 * n + i], a.mj[3 * n + i], a.mj[4 * n + i]};
+        u += d_local_value(d, r, sg, kap, g3, g4, m, a.order_d);
     }
     a.out[i] = u;
 }

@@ -120,6 +120,24 @@ struct LocalParams {
     int order_v, order_s, order_d;
 };
 
+// Oversampled boundary of the dyadic refinement of the local layer parts
+// (vp_refine_attach): nodes sorted by cell of a uniform grid of cell edge
+// 12 sqrt(delta_1), and the targets within that distance of the boundary.
+struct Refinement {
+    int levels = 0;
+    double delta_star = 0.0;
+    int64_t n_fine = 0;
+    double *x = nullptr, *y = nullptr, *nx = nullptr, *ny = nullptr, *w = nullptr;  // sorted by cell
+    int* perm = nullptr;        // original index of each sorted node
+    int* cell_start = nullptr;  // [ncx * ncy + 1]
+    int ncx = 0, ncy = 0;
+    double x0 = 0.0, y0 = 0.0, cell = 1.0;
+    int n_near = 0;
+    int* near = nullptr;        // target indices
+    double *near_x = nullptr, *near_y = nullptr;
+    std::vector<void*> allocs;
+};
+
 struct Plan {
     vp_opts opts{};
     int precision = VP_FP64;
@@ -152,7 +170,11 @@ struct Plan {
     double level_ms[2] = {0.0, 0.0};
     hipEvent_t ev[kTimedLaunches + 1]{};  // before the first and after each timed launch
     bool ev_made = false;
+    Refinement ref;               // dyadic refinement of the local layer parts (optional)
 };
+
+// Free a plan's refinement data (vp_refine.hip).
+void refinement_free(Refinement& r);
 
 // Kernel launchers (vp_kernels.hip).  All enqueue on stream st and write into ws.
 hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* sigma,

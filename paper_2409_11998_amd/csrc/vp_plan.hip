@@ -232,6 +232,7 @@ void free_plan(vp_plan_s* p)
     else hipDeviceSynchronize();
     for (void* q : p->allocs) hipFree(q);
     p->allocs.clear();
+    refinement_free(p->ref);
     workspace_free(p->ws, nullptr, false);
     if (p->ev_made)
         for (auto& e : p->ev) hipEventDestroy(e);

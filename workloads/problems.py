@@ -325,7 +325,7 @@ def square_problem(n_tri=180_000, n_split=20_000, seed=2, n_panels=250, q=20, na
                 gamma4=np.zeros_like(x), sgn=np.ones(x.size, np.int8))
     # second-nearest side distance (corner proximity), informational
     d_sorted = np.sort(d, axis=0)
-    info.update(kind="square", gauss=gauss, r2=d_sorted[1])
+    info.update(kind="square", gauss=gauss, r2=d_sorted[1], n_panels=n_panels, q=q)
     # mu jets along the nearest side: mu(xi) = cos(3 atan2(b + xi t))
     bxp = x + r * nxs
     byp = y + r * nys
@@ -403,12 +403,44 @@ def star_problem(n_tri, seed, kinds="VSD", name="star", n_bnd=None, r=0.8):
                                         1, -1).astype(np.int8)
         sj[:, is_near] = sjn[:3]
         mj[:, is_near] = mjn
-    info.update(kind="star", params=prm, gauss=gauss, seed=seed, near=near, near_mask=is_near)
+    info.update(kind="star", params=prm, gauss=gauss, seed=seed, near=near, near_mask=is_near,
+                npan=npan, q=q, sigma_trig=(sc, ss), mu_trig=(mc, ms))
     sigma = sig_f(bt) if "S" in kinds else None
     mu = mu_f(bt) if "D" in kinds else None
     return Problem(name, x, y, w, bx, by, bnx, bny, bw, x.copy(), y.copy(), geom,
                    jet[0].copy() if "V" in kinds else None, jet if "V" in kinds else None,
                    sigma, sj if "S" in kinds else None, mu, mj if "D" in kinds else None, info)
+
+
+def fine_boundary(problem, levels):
+    """The problem's boundary with every panel split into 2^levels panels (same
+    Gauss-Legendre order), densities evaluated there: the oversampled boundary
+    of the dyadic refinement of the local layer parts (Sec. 4), whose slice
+    kernels narrow by a factor two per level.  Returns dict(x, y, nx, ny, w,
+    sigma, mu) (sigma / mu None when the problem has no such density)."""
+    info = problem.info
+    m = 2 ** int(levels)
+    if info.get("kind") == "square":
+        xg, wg = leggauss(info["q"])
+        edges = np.linspace(-1, 1, info["n_panels"] * m + 1)
+        u = (0.5 * (edges[:-1, None] + edges[1:, None]) + 0.5 * (edges[1:, None] - edges[:-1, None]) * xg).ravel()
+        wu = (0.5 * (edges[1:, None] - edges[:-1, None]) * wg).ravel()
+        one = np.ones_like(u)
+        sides = [(u, -one, 0 * one, -one), (one, u, one, 0 * one),
+                 (-u, one, 0 * one, one), (-one, -u, -one, 0 * one)]
+        x = np.concatenate([t[0] for t in sides])
+        y = np.concatenate([t[1] for t in sides])
+        return dict(x=x, y=y, nx=np.concatenate([t[2] for t in sides]), ny=np.concatenate([t[3] for t in sides]),
+                    w=np.concatenate([wu] * 4), sigma=None,
+                    mu=np.cos(3 * np.arctan2(y, x)) if problem.mu is not None else None)
+    if info.get("kind") == "star":
+        curve = StarCurve(**info["params"])
+        x, y, nx, ny, w, t = panel_nodes(curve, info["npan"] * m, info["q"])
+        sig_f, _ = trig_density(*info["sigma_trig"])
+        mu_f, _ = trig_density(*info["mu_trig"])
+        return dict(x=x, y=y, nx=nx, ny=ny, w=w, sigma=sig_f(t) if problem.sigma is not None else None,
+                    mu=mu_f(t) if problem.mu is not None else None)
+    raise ValueError("no panel description for this problem")
 
 
 def circle_layer_problem(n_bnd, tgt_xy, sigma_fn=None, mu_fn=None, radius=1.0):
