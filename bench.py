@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--no-fp32-leg", action="store_true")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workloads (quick runs)")
     ap.add_argument("--no-batch-leg", action="store_true")
+    ap.add_argument("--no-refine-leg", action="store_true")
+    ap.add_argument("--refine-levels", type=int, default=3)
     ap.add_argument("--no-serve-leg", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-max-tri", type=float, default=2e5)
@@ -259,6 +261,9 @@ def main():
            "roofline": roof, "cpu_baseline": cpu,
            "stages_ms": {k: round(v, 4) for k, v in st.items()}, "stages_gbs": stages_gbs,
            "plan_s": round(r64["plan_s"], 3), "e_inf_vs_oracle_sample": r64.get("e_inf_sample")}
+    if not args.no_refine_leg:
+        log("bench: dyadic refinement leg, %d levels" % args.refine_levels)
+        rec["refine"] = refine_leg(torch, P, args.refine_levels, args.steps, min(64, args.oracle_sample or 64))
     if not args.no_fp32_leg:
         log("bench: generating disk-2M workload")
         Q = config_problem(3, scale=args.scale)
@@ -290,6 +295,48 @@ def main():
         rec["latency_p99_s"] = rec["serve"]["loads"][ref_load]["served"]["p99_s"]
         rec["latency_load"] = float(ref_load)
     print(json.dumps(rec), flush=True)
+
+
+def refine_leg(torch, P, levels, steps, n_sample):
+    """Dyadic refinement of the local double-layer part on the square workload:
+    every boundary panel split into 2^levels; time of the correction launch alone
+    and of evaluation + correction; parity on seeded targets near the boundary."""
+    from oracle import refine
+    from workloads.device import make_plan, run, to_device
+    from workloads.problems import fine_boundary
+    dev = to_device(P)
+    plan = make_plan(dev, tol=1e-10, precision=1, kinds=5)
+    delta = plan.info()["delta1"]
+    fine = fine_boundary(P, levels)
+    fd = {k: (torch.as_tensor(v, dtype=torch.float64, device="cuda") if v is not None else None)
+          for k, v in fine.items()}
+    t0 = time.perf_counter()
+    plan.refine_attach(levels, fd["x"], fd["y"], fd["nx"], fd["ny"], fd["w"], dev["tgt_x"], dev["tgt_y"])
+    attach_s = time.perf_counter() - t0
+    out = torch.empty(P.n_tgt, dtype=torch.float64, device="cuda")
+    corr_only = lambda: plan.layer_refine(out, mu_jet=dev["mu_jet"], fine_mu=fd["mu"])
+    both = lambda: (run(plan, dev, "VD", out=out), corr_only())
+    for _ in range(3):
+        both()
+    el_c = time_steps(torch, corr_only, steps)
+    el_b = time_steps(torch, both, steps)
+    both()
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    near = np.flatnonzero(np.asarray(P.geom["r"]) <= 12.0 * np.sqrt(delta))
+    rng = np.random.default_rng(40)
+    idx = np.sort(rng.choice(near, size=min(n_sample, near.size), replace=False))
+    sub = P.subset_targets(idx)
+    import oracle
+    ref = oracle.evaluate(sub, kinds="VD")["total"] + refine.layer_refinement(sub, fine, levels, delta, kinds="D")
+    corr = refine.layer_refinement(sub, fine, levels, delta, kinds="D")
+    plan.close()
+    return {"workload": "square-200k V+D fp64 tol1e-10, D_L refined", "levels": levels,
+            "n_fine": int(fine["x"].size), "near_targets": int(near.size),
+            "refine_ms": round(1e3 * el_c / steps, 4), "eval_plus_refine_ms": round(1e3 * el_b / steps, 4),
+            "attach_s": round(attach_s, 3),
+            "e_inf_vs_oracle_sample": float(np.max(np.abs(got[idx] - ref)) / np.max(np.abs(ref))),
+            "max_abs_correction_sample": float(np.max(np.abs(corr))), "sample": int(idx.size)}
 
 
 def batch_leg(torch, probs, steps, warmup, tune_sample):

@@ -122,7 +122,7 @@ struct LocalParams {
 
 // Oversampled boundary of the dyadic refinement of the local layer parts
 // (vp_refine_attach): nodes sorted by cell of a uniform grid of cell edge
-// 12 sqrt(delta_1), and the targets within that distance of the boundary.
+// 6 sqrt(delta_1), and the targets within 12 sqrt(delta_1) of the boundary.
 struct Refinement {
     int levels = 0;
     double delta_star = 0.0;
@@ -133,6 +133,8 @@ struct Refinement {
     int ncx = 0, ncy = 0;
     double x0 = 0.0, y0 = 0.0, cell = 1.0;
     int n_near = 0;
+    int n_units = 0;
+    int4* units = nullptr;      // (cell, first, end) runs of near targets
     int* near = nullptr;        // target indices
     double *near_x = nullptr, *near_y = nullptr;
     std::vector<void*> allocs;

@@ -16,9 +16,11 @@
 // with one pass over the nodes.
 //
 // Device layout: the oversampled nodes sorted by cell of a uniform grid of
-// cell edge 12 sqrt(delta_1) (beyond that both kernels are below 1e-17 of
-// their peak), a cell index, and the targets within 12 sqrt(delta_1) of the
-// boundary.  One thread per such target scans the 3 x 3 cells around it.
+// cell edge 6 sqrt(delta_1) (both kernels are below 1e-17 of their peak
+// beyond 12 sqrt(delta_1)), a cell index, and the targets within
+// 12 sqrt(delta_1) of the boundary, grouped by cell into units of at most 128.
+// A workgroup takes a unit, one target per thread, and streams the nodes of
+// the 5 x 5 surrounding cells through LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,6 +37,8 @@ namespace vp {
 namespace {
 
 constexpr double kRefineCut = 12.0;  // slice support, in units of sqrt(delta_1)
+constexpr int kRefineReach = 2;      // cells of edge kRefineCut sqrt(delta_1) / 2: scan 5 x 5
+constexpr int kRefineThreads = 128;  // targets per workgroup (one cell's)
 
 // Exponential integral E1(z), z > 0, in float64: the power series
 // (Abramowitz & Stegun 5.1.11) for z <= 1.5, otherwise the continued fraction
@@ -68,7 +72,8 @@ __device__ double e1(double z)
 }
 
 struct RefineArgs {
-    int n_near;
+    int n_units;
+    const int4* units;         // (cell, first, end) of near targets, one cell's targets per unit
     const int* near;
     const double* near_x;
     const double* near_y;
@@ -76,7 +81,6 @@ struct RefineArgs {
     const int* perm;
     const int* cell_start;
     int ncx, ncy;
-    double x0, y0, cell;
     double delta1, delta_star;
     int64_t n_tgt;
     const double *r, *kappa, *g3, *g4;
@@ -89,37 +93,71 @@ struct RefineArgs {
     double* out;
 };
 
-__global__ __launch_bounds__(kThreads) void k_refine(RefineArgs a)
+// One workgroup per unit: its targets (one per thread) share the cell, so the
+// nodes of the surrounding cells are staged once per workgroup through LDS
+// (with strength times weight folded in) and read by all threads as broadcasts.
+__global__ __launch_bounds__(kRefineThreads) void k_refine(RefineArgs a)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.n_near) return;
-    const int i = a.near[t];
-    const double x = a.near_x[t], y = a.near_y[t];
+    __shared__ double sx[kRefineThreads], sy[kRefineThreads], snx[kRefineThreads], sny[kRefineThreads];
+    __shared__ double ss[kRefineThreads], sm[kRefineThreads];
+    const int4 u = a.units[blockIdx.x];
+    const int t = u.y + (int)threadIdx.x;
+    const bool on = t < u.z;
+    int i = 0;
+    double x = 0.0, y = 0.0;
+    if (on) {
+        i = a.near[t];
+        x = a.near_x[t];
+        y = a.near_y[t];
+    }
     const double q1 = 0.25 / a.delta1, qs = 0.25 / a.delta_star;
     const double cut2 = kRefineCut * kRefineCut * a.delta1;
     const double ln_ratio = log(a.delta1 / a.delta_star);
-    const int cx = min(max((int)floor((x - a.x0) / a.cell), 0), a.ncx - 1);
-    const int cy = min(max((int)floor((y - a.y0) / a.cell), 0), a.ncy - 1);
+    const int cx = u.x % a.ncx, cy = u.x / a.ncx;
+    const bool use_s = a.fine_sigma != nullptr, use_d = a.fine_mu != nullptr;
     double acc_s = 0.0, acc_d = 0.0;
-    for (int jy = max(cy - 1, 0); jy <= min(cy + 1, a.ncy - 1); ++jy)
-        for (int jx = max(cx - 1, 0); jx <= min(cx + 1, a.ncx - 1); ++jx) {
-            const int c = jy * a.ncx + jx;
-            for (int k = a.cell_start[c]; k < a.cell_start[c + 1]; ++k) {
-                const double dx = x - a.fx[k], dy = y - a.fy[k];
-                const double rho2 = dx * dx + dy * dy;
-                if (rho2 >= cut2) continue;
-                const int o = a.perm[k];
-                if (a.fine_sigma) {
-                    const double ks = rho2 > 0.0 ? e1(rho2 * q1) - e1(rho2 * qs) : ln_ratio;
-                    acc_s += ks * a.fw[k] * a.fine_sigma[o];
-                }
-                if (a.fine_mu && rho2 > 0.0) {
-                    // exp(-q1 rho^2) - exp(-qs rho^2) = -exp(-q1 rho^2) expm1(-(qs - q1) rho^2)
-                    const double diff = -exp(-q1 * rho2) * expm1(-(qs - q1) * rho2);
-                    acc_d += (a.fnx[k] * dx + a.fny[k] * dy) / rho2 * diff * a.fw[k] * a.fine_mu[o];
+    for (int jy = max(cy - kRefineReach, 0); jy <= min(cy + kRefineReach, a.ncy - 1); ++jy) {
+        // the row's cells cx - reach .. cx + reach are contiguous in cell order
+        const int k0 = a.cell_start[jy * a.ncx + max(cx - kRefineReach, 0)];
+        const int k1 = a.cell_start[jy * a.ncx + min(cx + kRefineReach, a.ncx - 1) + 1];
+        for (int kb = k0; kb < k1; kb += kRefineThreads) {
+            const int kl = kb + (int)threadIdx.x;
+            __syncthreads();  // the previous chunk has been read
+            if (kl < k1) {
+                const int o = a.perm[kl];
+                sx[threadIdx.x] = a.fx[kl];
+                sy[threadIdx.x] = a.fy[kl];
+                snx[threadIdx.x] = a.fnx[kl];
+                sny[threadIdx.x] = a.fny[kl];
+                ss[threadIdx.x] = use_s ? a.fw[kl] * a.fine_sigma[o] : 0.0;
+                sm[threadIdx.x] = use_d ? a.fw[kl] * a.fine_mu[o] : 0.0;
+            }
+            __syncthreads();
+            const int nk = min(kRefineThreads, k1 - kb);
+            if (on) {
+                for (int k = 0; k < nk; ++k) {
+                    const double dx = x - sx[k], dy = y - sy[k];
+                    const double rho2 = dx * dx + dy * dy;
+                    if (rho2 >= cut2) continue;
+                    // the delta* terms vanish (below 1e-17) once qs rho^2 > 40, i.e. for
+                    // most pairs: rho > 12.6 sqrt(delta*)
+                    const double zs = rho2 * qs;
+                    if (use_s) {
+                        double ks = ln_ratio;
+                        if (rho2 > 0.0) ks = zs > 40.0 ? e1(rho2 * q1) : e1(rho2 * q1) - e1(zs);
+                        acc_s += ks * ss[k];
+                    }
+                    if (use_d && rho2 > 0.0) {
+                        // exp(-q1 rho^2) - exp(-qs rho^2) = -exp(-q1 rho^2) expm1(-(qs - q1) rho^2)
+                        const double e = exp(-q1 * rho2);
+                        const double diff = zs > 40.0 ? e : -e * expm1(-(qs - q1) * rho2);
+                        acc_d += (snx[k] * dx + sny[k] * dy) / rho2 * diff * sm[k];
+                    }
                 }
             }
         }
+    }
+    if (!on) return;
     const double PI = 3.14159265358979323846;
     double corr = acc_s / (4.0 * PI) + acc_d / (2.0 * PI);
     const double r = a.r[i], kap = a.kappa[i], sg = (double)a.sgn[i];
@@ -137,7 +175,6 @@ __global__ __launch_bounds__(kThreads) void k_refine(RefineArgs a)
     }
     a.out[i] += corr;
 }
-
 
 vp_status rfail(vp_status s, const std::string& m) { return set_error(s, m); }
 
@@ -210,7 +247,7 @@ vp_status vp_refine_attach(vp_plan_t p, int levels, int64_t n_fine, const double
     R.levels = levels;
     R.delta_star = p->delta1 / std::pow(4.0, levels);
     R.n_fine = n_fine;
-    R.cell = kRefineCut * std::sqrt(p->delta1);
+    R.cell = kRefineCut * std::sqrt(p->delta1) / kRefineReach;
     R.x0 = xmin;
     R.y0 = ymin;
     R.ncx = std::max(1, (int)std::ceil((xmax - xmin) / R.cell) + 1);
@@ -260,11 +297,22 @@ vp_status vp_refine_attach(vp_plan_t p, int levels, int64_t n_fine, const double
         nys[t] = ty[nsorted[t]];
     }
     R.n_near = (int)nsorted.size();
+    // work units: runs of at most kRefineThreads near targets of one cell
+    std::vector<int4> units;
+    for (size_t t = 0; t < nsorted.size();) {
+        const int c = ncid[ord[t]];
+        size_t e = t;
+        while (e < nsorted.size() && ncid[ord[e]] == c && e - t < (size_t)kRefineThreads) ++e;
+        units.push_back(make_int4(c, (int)t, (int)e, 0));
+        t = e;
+    }
+    R.n_units = (int)units.size();
     if ((s = ul(R, &R.x, sx, "fine nodes")) != VP_OK || (s = ul(R, &R.y, sy, "fine nodes")) != VP_OK ||
         (s = ul(R, &R.nx, snx, "fine normals")) != VP_OK || (s = ul(R, &R.ny, sny, "fine normals")) != VP_OK ||
         (s = ul(R, &R.w, sw, "fine weights")) != VP_OK || (s = ul(R, &R.perm, order, "fine order")) != VP_OK ||
         (s = ul(R, &R.cell_start, start, "cells")) != VP_OK || (s = ul(R, &R.near, nsorted, "near targets")) != VP_OK ||
-        (s = ul(R, &R.near_x, nxs, "near targets")) != VP_OK || (s = ul(R, &R.near_y, nys, "near targets")) != VP_OK) {
+        (s = ul(R, &R.near_x, nxs, "near targets")) != VP_OK || (s = ul(R, &R.near_y, nys, "near targets")) != VP_OK ||
+        (s = ul(R, &R.units, units, "refinement units")) != VP_OK) {
         refinement_free(R);
         return s;
     }
@@ -287,7 +335,8 @@ vp_status vp_layer_refine(vp_plan_t p, const double* sigma_jet3, const double* f
     const Refinement& R = p->ref;
     if (R.n_near == 0) return VP_OK;
     RefineArgs a;
-    a.n_near = R.n_near;
+    a.n_units = R.n_units;
+    a.units = R.units;
     a.near = R.near;
     a.near_x = R.near_x;
     a.near_y = R.near_y;
@@ -300,9 +349,6 @@ vp_status vp_layer_refine(vp_plan_t p, const double* sigma_jet3, const double* f
     a.cell_start = R.cell_start;
     a.ncx = R.ncx;
     a.ncy = R.ncy;
-    a.x0 = R.x0;
-    a.y0 = R.y0;
-    a.cell = R.cell;
     a.delta1 = p->delta1;
     a.delta_star = R.delta_star;
     a.n_tgt = p->n_tgt;
@@ -318,8 +364,7 @@ vp_status vp_layer_refine(vp_plan_t p, const double* sigma_jet3, const double* f
     a.mj = mu_jet5;
     a.fine_mu = fine_mu;
     a.out = out;
-    const unsigned nb = (unsigned)((R.n_near + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_refine, dim3(nb), dim3(kThreads), 0, p->stream, a);
+    hipLaunchKernelGGL(k_refine, dim3(R.n_units), dim3(kRefineThreads), 0, p->stream, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rfail(VP_ERR_DEVICE, std::string("refinement launch: ") + hipGetErrorString(e));
     return VP_OK;
