@@ -48,54 +48,119 @@ __device__ __forceinline__ int bitrev(int k, int logn)
     return logn ? (int)(__brev((unsigned)k) >> (32 - logn)) : 0;
 }
 
+// Complex helpers of the LDS FFTs.
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> w)
+{
+    return {a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x};
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> twiddle(const cplx<R>* __restrict__ tw, int k, bool inverse)
+{
+    cplx<R> w = tw[k];
+    if (inverse) w.y = -w.y;
+    return w;
+}
+
 // In-place radix-2 decimation-in-time FFT of n = 2^logn points held in LDS in
 // bit-reversed order; output in natural order.  tw[k*tw_stride] =
 // exp(-2 pi i k / n) for k < n/2.  Ends with a barrier.
+//
+// Stage s combines pairs half = 2^(s-1) apart with twiddle tw[pos (n >> s)].
+// Two consecutive stages run as one pass over quads (i, i+h, i+2h, i+3h),
+// h = 2^(s-1): the same butterflies, twiddles and order, with half the
+// barriers and half the LDS traffic; an odd last stage runs alone.
 template <typename R>
 __device__ void lds_fft(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw, int tw_stride, bool inverse)
 {
     const int n = 1 << logn;
-    for (int s = 1; s <= logn; ++s) {
+    int s = 1;
+    for (; s + 1 <= logn; s += 2) {
+        const int h = 1 << (s - 1);
+        const int st1 = (n >> s) * tw_stride;        // stage s
+        const int st2 = (n >> (s + 1)) * tw_stride;  // stage s + 1
+        for (int q = threadIdx.x; q < (n >> 2); q += blockDim.x) {
+            const int pos = q & (h - 1);
+            const int i = ((q >> (s - 1)) << (s + 1)) + pos;
+            const cplx<R> w1 = twiddle(tw, pos * st1, inverse);
+            cplx<R> e0 = a[i], e1 = a[i + h], e2 = a[i + 2 * h], e3 = a[i + 3 * h];
+            cplx<R> t = cmul(e1, w1);
+            e1 = {e0.x - t.x, e0.y - t.y};
+            e0 = {e0.x + t.x, e0.y + t.y};
+            t = cmul(e3, w1);
+            e3 = {e2.x - t.x, e2.y - t.y};
+            e2 = {e2.x + t.x, e2.y + t.y};
+            const cplx<R> w2a = twiddle(tw, pos * st2, inverse);
+            const cplx<R> w2b = twiddle(tw, (pos + h) * st2, inverse);
+            t = cmul(e2, w2a);
+            a[i] = {e0.x + t.x, e0.y + t.y};
+            a[i + 2 * h] = {e0.x - t.x, e0.y - t.y};
+            t = cmul(e3, w2b);
+            a[i + h] = {e1.x + t.x, e1.y + t.y};
+            a[i + 3 * h] = {e1.x - t.x, e1.y - t.y};
+        }
+        __syncthreads();
+    }
+    if (s == logn) {
         const int half = 1 << (s - 1);
         const int step = (n >> s) * tw_stride;
         for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
             const int pos = b & (half - 1);
             const int i = ((b >> (s - 1)) << s) + pos;
             const int j = i + half;
-            cplx<R> wv = tw[pos * step];
-            if (inverse) wv.y = -wv.y;
+            const cplx<R> t = cmul(a[j], twiddle(tw, pos * step, inverse));
             const cplx<R> u = a[i];
-            const cplx<R> v = a[j];
-            const R tx = v.x * wv.x - v.y * wv.y;
-            const R ty = v.x * wv.y + v.y * wv.x;
-            a[i] = {u.x + tx, u.y + ty};
-            a[j] = {u.x - tx, u.y - ty};
+            a[i] = {u.x + t.x, u.y + t.y};
+            a[j] = {u.x - t.x, u.y - t.y};
         }
         __syncthreads();
     }
 }
 
 // In-place radix-2 decimation-in-frequency FFT: input in natural order, output
-// in bit-reversed order (same twiddle convention as lds_fft).  Ends with a
-// barrier.
+// in bit-reversed order (same twiddle convention as lds_fft).  Stages run from
+// s = logn down to 1 (pairs 2^(s-1) apart: sum, and difference times
+// tw[pos (n >> s)]), two consecutive stages per pass as in lds_fft.  Ends with
+// a barrier.
 template <typename R>
 __device__ void lds_fft_dif(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw, int tw_stride, bool inverse)
 {
     const int n = 1 << logn;
-    for (int s = logn; s >= 1; --s) {
-        const int half = 1 << (s - 1);
-        const int step = (n >> s) * tw_stride;
+    int s = logn;
+    for (; s - 1 >= 1; s -= 2) {
+        const int h = 1 << (s - 2);                  // half of stage s - 1
+        const int st1 = (n >> s) * tw_stride;        // stage s (pairs 2h apart)
+        const int st2 = (n >> (s - 1)) * tw_stride;  // stage s - 1 (pairs h apart)
+        for (int q = threadIdx.x; q < (n >> 2); q += blockDim.x) {
+            const int pos = q & (h - 1);
+            const int i = ((q >> (s - 2)) << s) + pos;
+            cplx<R> e0 = a[i], e1 = a[i + h], e2 = a[i + 2 * h], e3 = a[i + 3 * h];
+            const cplx<R> wa = twiddle(tw, pos * st1, inverse);
+            const cplx<R> wb = twiddle(tw, (pos + h) * st1, inverse);
+            cplx<R> d = {e0.x - e2.x, e0.y - e2.y};
+            e0 = {e0.x + e2.x, e0.y + e2.y};
+            e2 = cmul(d, wa);
+            d = {e1.x - e3.x, e1.y - e3.y};
+            e1 = {e1.x + e3.x, e1.y + e3.y};
+            e3 = cmul(d, wb);
+            const cplx<R> w2 = twiddle(tw, pos * st2, inverse);
+            d = {e0.x - e1.x, e0.y - e1.y};
+            a[i] = {e0.x + e1.x, e0.y + e1.y};
+            a[i + h] = cmul(d, w2);
+            d = {e2.x - e3.x, e2.y - e3.y};
+            a[i + 2 * h] = {e2.x + e3.x, e2.y + e3.y};
+            a[i + 3 * h] = cmul(d, w2);
+        }
+        __syncthreads();
+    }
+    if (s == 1) {
         for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
-            const int pos = b & (half - 1);
-            const int i = ((b >> (s - 1)) << s) + pos;
-            const int j = i + half;
-            cplx<R> wv = tw[pos * step];
-            if (inverse) wv.y = -wv.y;
+            const int i = b << 1;  // half = 1, pos = 0: twiddle tw[0] = 1
             const cplx<R> u = a[i];
-            const cplx<R> v = a[j];
-            const R dx = u.x - v.x, dy = u.y - v.y;
+            const cplx<R> v = a[i + 1];
+            const cplx<R> w = twiddle(tw, 0, inverse);
             a[i] = {u.x + v.x, u.y + v.y};
-            a[j] = {dx * wv.x - dy * wv.y, dx * wv.y + dy * wv.x};
+            a[i + 1] = cmul(cplx<R>{u.x - v.x, u.y - v.y}, w);
         }
         __syncthreads();
     }
@@ -279,6 +344,23 @@ __device__ __forceinline__ void tap_value_deriv(const H* __restrict__ c, H u, H&
     dv = dp;
 }
 
+// The kernel is even: tap w-1-a at offset u equals tap a at -u.  With tap a's
+// polynomial split as E(u^2) + u O(u^2) (ce[k] = c[2k], co[k] = c[2k+1]), one
+// evaluation gives both taps.
+template <int P>
+__device__ __forceinline__ void tap_pair(const double* ce, const double* co, double u, double& v_a, double& v_mirror)
+{
+    const double u2 = u * u;
+    double e = ce[(P + 1) / 2 - 1];
+#pragma unroll
+    for (int k = (P + 1) / 2 - 2; k >= 0; --k) e = fma(e, u2, ce[k]);
+    double o = co[P / 2 - 1];
+#pragma unroll
+    for (int k = P / 2 - 2; k >= 0; --k) o = fma(o, u2, co[k]);
+    v_a = fma(u, o, e);
+    v_mirror = fma(-u, o, e);
+}
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -363,9 +445,20 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
     const bool lane_on = lane < RW * W;
     // kernel-value evaluation: lane -> tap ta, offset group tb0 (G groups); the
     // tap's polynomial coefficients stay in this lane's registers
-    H cf[P];
+    // single-strength nodes: lane (tap pair kp, group kg) evaluates taps kp and
+    // w-1-kp from tap kp's polynomial in even and odd parts (coefficients in
+    // registers); double-layer nodes: lane (tap ta, group tb0) evaluates value
+    // and derivative with the tap's coefficients read from the (cached) table
+    constexpr int NP = (W + 1) / 2;
+    constexpr int GP = 64 / NP;
+    const int kp = lane % NP;
+    const int kg = lane / NP;
+    const bool kon = lane < GP * NP;
+    double ce[(P + 1) / 2], co[P / 2];
 #pragma unroll
-    for (int k = 0; k < P; ++k) cf[k] = (H)coef[ta * P + k];
+    for (int k = 0; k < (P + 1) / 2; ++k) ce[k] = coef[kp * P + 2 * k];
+#pragma unroll
+    for (int k = 0; k < P / 2; ++k) co[k] = coef[kp * P + 2 * k + 1];
     const int64_t n_all = n_src + n_bnd;
     const H dscale = (H)(-2.0 / g.h);  // d/dy of a tap value = -(2/h) d/du
 
@@ -412,22 +505,27 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
                 const R dyv = __shfl(c_dy, lane >> 1);
                 if (lane < 2 * NR) dd[lane] = (lane & 1) ? dyv : dxv;
                 wave_sync_lds();
-                if (lane_on) {
-                    const int nv2 = 2 * nrec;
-                    for (int q = tb0; q < nv2; q += G) {
-                        const H u = H(2) * (H)dd[q] - H(1);
-                        R* dst = vals + (q >> 1) * VS + (q & 1) * W + ta;
-                        if constexpr (DL) {
+                const int nv2 = 2 * nrec;
+                if constexpr (DL) {
+                    if (lane_on) {
+                        const double* cf = coef + ta * P;
+                        for (int q = tb0; q < nv2; q += G) {
+                            const H u = H(2) * (H)dd[q] - H(1);
+                            R* dst = vals + (q >> 1) * VS + (q & 1) * W + ta;
                             H v, dv;
                             tap_value_deriv<P>(cf, u, v, dv);
                             dst[0] = (R)v;
                             dst[2 * W] = (R)(dscale * dv);
-                        } else {
-                            H acc = cf[P - 1];
-#pragma unroll
-                            for (int k = P - 2; k >= 0; --k) acc = fma(acc, u, cf[k]);
-                            dst[0] = (R)acc;
                         }
+                    }
+                } else if (kon) {
+                    for (int q = kg; q < nv2; q += GP) {
+                        const double u = 2.0 * (double)dd[q] - 1.0;
+                        double va, vm;
+                        tap_pair<P>(ce, co, u, va, vm);
+                        R* dst = vals + (q >> 1) * VS + (q & 1) * W;
+                        dst[kp] = (R)va;
+                        if (kp != W - 1 - kp) dst[W - 1 - kp] = (R)vm;
                     }
                 }
             }
@@ -793,11 +891,9 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
                            const RecView<R>& L, R* __restrict__ hist, const double* __restrict__ coef,
                            const WorkUnit unit)
 {
-    using H = double;
     constexpr int P = horner_terms(W);
     constexpr int NT = kInterpTargets;
     constexpr int VS = 2 * W;
-    constexpr int G = 64 / W;
     constexpr int HB = (W + 1) / 2;  // rows of the first half
     const int t = unit.tile;
     const int r0 = unit.a0;
@@ -821,12 +917,17 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
         const int gx = gx0 + x;
         reg[i] = (gx < F && gy < F) ? grid[(size_t)gy * F + gx] : R(0);
     }
-    const int ka = lane % W;
-    const int kg = lane / W;
-    const bool kon = lane < G * W;
-    H cf[P];
+    // kernel values: lane (tap pair kp, group kg) evaluates taps kp and w-1-kp
+    constexpr int NP = (W + 1) / 2;
+    constexpr int GP = 64 / NP;
+    const int kp = lane % NP;
+    const int kg = lane / NP;
+    const bool kon = lane < GP * NP;
+    double ce[(P + 1) / 2], co[P / 2];
 #pragma unroll
-    for (int k = 0; k < P; ++k) cf[k] = (H)coef[ka * P + k];
+    for (int k = 0; k < (P + 1) / 2; ++k) ce[k] = coef[kp * P + 2 * k];
+#pragma unroll
+    for (int k = 0; k < P / 2; ++k) co[k] = coef[kp * P + 2 * k + 1];
     __syncthreads();
     const int q = lane >> 1;    // target of this lane within the chunk
     const int half = lane & 1;  // rows [0, HB) or [HB, W)
@@ -841,12 +942,13 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
         }
         wave_sync_lds();
         if (kon) {
-            for (int pq = kg; pq < 2 * nt; pq += G) {
-                const H u = H(2) * (H)dd[pq] - H(1);
-                H acc = cf[P - 1];
-#pragma unroll
-                for (int k = P - 2; k >= 0; --k) acc = fma(acc, u, cf[k]);
-                vals[(pq >> 1) * VS + (pq & 1) * W + ka] = (R)acc;
+            for (int pq = kg; pq < 2 * nt; pq += GP) {
+                const double u = 2.0 * (double)dd[pq] - 1.0;
+                double va, vm;
+                tap_pair<P>(ce, co, u, va, vm);
+                R* dst = vals + (pq >> 1) * VS + (pq & 1) * W;
+                dst[kp] = (R)va;
+                if (kp != W - 1 - kp) dst[W - 1 - kp] = (R)vm;
             }
         }
         wave_sync_lds();
