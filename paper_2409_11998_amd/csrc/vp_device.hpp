@@ -631,7 +631,11 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
 constexpr int kMmaChunk = 32;  // rank-1 terms (factor-row pairs) per chunk
 using mma_f32x16 = float __attribute__((ext_vector_type(16)));
 
-__host__ __device__ constexpr size_t mma_wave_bytes() { return (size_t)kMmaChunk * 64 * sizeof(float); }
+// Factor rows are kMmaRow floats apart (32 used): a multiple of 4 for the
+// 16-byte zeroing stores, and not a multiple of 64 dwords, so that the lanes'
+// rows fall in different LDS banks.
+constexpr int kMmaRow = 36;
+__host__ __device__ constexpr size_t mma_wave_bytes() { return (size_t)kMmaChunk * 2 * kMmaRow * sizeof(float); }
 
 template <int W>
 __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, const RecView<float>& vol,
@@ -644,8 +648,8 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
     static_assert(kMmaTile + W - 1 <= 32, "window of 32 cells");
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    float* Ay = reinterpret_cast<float*>(smem_raw + (size_t)wv * mma_wave_bytes());  // [NPC][32] y factors
-    float* Bx = Ay + NPC * 32;                                                          // [NPC][32] x factors
+    float* Ay = reinterpret_cast<float*>(smem_raw + (size_t)wv * mma_wave_bytes());  // [NPC][kMmaRow] y factors
+    float* Bx = Ay + NPC * kMmaRow;                                                     // [NPC][kMmaRow] x factors
     const int t = unit.tile;
     const int gx0 = (t % g.ntx) * kMmaTile, gy0 = (t / g.ntx) * kMmaTile;
     const int nv = use_vol ? unit.a1 - unit.a0 : 0;
@@ -690,11 +694,15 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
             const double s_ = p_s, gx_ = p_gx, gy_ = p_gy;
             if (c0 + NRC < r1) fetch(c0 + NRC);
             // this lane's factor row(s): zero, then the w taps at the corner offset
-            float* row = (axis ? Ay : Bx) + (DL ? 2 * rec : rec) * 32;
+            float* row = (axis ? Ay : Bx) + (DL ? 2 * rec : rec) * kMmaRow;
             if (rec < NRC) {
                 const float4 z{};
 #pragma unroll
-                for (int k = 0; k < (DL ? 16 : 8); ++k) reinterpret_cast<float4*>(row)[k] = z;
+                for (int k = 0; k < 8; ++k) reinterpret_cast<float4*>(row)[k] = z;
+                if (DL) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) reinterpret_cast<float4*>(row + kMmaRow)[k] = z;
+                }
             }
             const bool on = rec < n;
             if constexpr (!DL) {
@@ -738,10 +746,10 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
                     if (on) {
                         if (axis == 0) {
                             row[off + a] = (float)(s_ * v + gx_ * dv);
-                            row[32 + off + a] = (float)v;
+                            row[kMmaRow + off + a] = (float)v;
                         } else {
                             row[off + a] = (float)v;
-                            row[32 + off + a] = (float)(gy_ * dv);
+                            row[kMmaRow + off + a] = (float)(gy_ * dv);
                         }
                     }
                 }
@@ -753,7 +761,7 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
 #pragma unroll 4
             for (int m = 0; m < np; m += 2) {
                 const int r = m + (lane >> 5);
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Ay[r * 32 + i], Bx[r * 32 + i], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Ay[r * kMmaRow + i], Bx[r * kMmaRow + i], acc, 0, 0, 0);
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) win[r] += (double)acc[r];
@@ -883,7 +891,7 @@ constexpr int kInterpTargets = 32;  // targets per wavefront chunk
 __host__ __device__ inline size_t interp_lds_bytes(int T, int W, size_t rb)
 {
     const size_t win = ((size_t)(T + W - 1) * (T + W - 1) * rb + 15) & ~(size_t)15;
-    return win + (size_t)(kThreads / 64) * (kInterpTargets * 2 * W + 2 * kInterpTargets) * rb;
+    return win + (size_t)(kThreads / 64) * (kInterpTargets * (2 * W + 1) + 2 * kInterpTargets) * rb;
 }
 
 template <typename R, int W>
@@ -893,7 +901,7 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
 {
     constexpr int P = horner_terms(W);
     constexpr int NT = kInterpTargets;
-    constexpr int VS = 2 * W;
+    constexpr int VS = 2 * W + 1;  // odd stride: the targets' rows fall in different LDS banks
     constexpr int HB = (W + 1) / 2;  // rows of the first half
     const int t = unit.tile;
     const int r0 = unit.a0;
