@@ -48,6 +48,12 @@ __device__ __forceinline__ int bitrev(int k, int logn)
     return logn ? (int)(__brev((unsigned)k) >> (32 - logn)) : 0;
 }
 
+// LDS FFT arrays are padded by one element per 16: bit-reversed and
+// power-of-two strided accesses would otherwise put a whole wavefront on a
+// few of the 64 LDS banks.
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_padded_len(int n) { return n + (n >> 4); }
+
 // Complex helpers of the LDS FFTs.
 template <typename R>
 __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> w)
@@ -83,7 +89,7 @@ __device__ void lds_fft(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw, in
             const int pos = q & (h - 1);
             const int i = ((q >> (s - 1)) << (s + 1)) + pos;
             const cplx<R> w1 = twiddle(tw, pos * st1, inverse);
-            cplx<R> e0 = a[i], e1 = a[i + h], e2 = a[i + 2 * h], e3 = a[i + 3 * h];
+            cplx<R> e0 = a[lds_pad(i)], e1 = a[lds_pad(i + h)], e2 = a[lds_pad(i + 2 * h)], e3 = a[lds_pad(i + 3 * h)];
             cplx<R> t = cmul(e1, w1);
             e1 = {e0.x - t.x, e0.y - t.y};
             e0 = {e0.x + t.x, e0.y + t.y};
@@ -93,11 +99,11 @@ __device__ void lds_fft(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw, in
             const cplx<R> w2a = twiddle(tw, pos * st2, inverse);
             const cplx<R> w2b = twiddle(tw, (pos + h) * st2, inverse);
             t = cmul(e2, w2a);
-            a[i] = {e0.x + t.x, e0.y + t.y};
-            a[i + 2 * h] = {e0.x - t.x, e0.y - t.y};
+            a[lds_pad(i)] = {e0.x + t.x, e0.y + t.y};
+            a[lds_pad(i + 2 * h)] = {e0.x - t.x, e0.y - t.y};
             t = cmul(e3, w2b);
-            a[i + h] = {e1.x + t.x, e1.y + t.y};
-            a[i + 3 * h] = {e1.x - t.x, e1.y - t.y};
+            a[lds_pad(i + h)] = {e1.x + t.x, e1.y + t.y};
+            a[lds_pad(i + 3 * h)] = {e1.x - t.x, e1.y - t.y};
         }
         __syncthreads();
     }
@@ -108,10 +114,10 @@ __device__ void lds_fft(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw, in
             const int pos = b & (half - 1);
             const int i = ((b >> (s - 1)) << s) + pos;
             const int j = i + half;
-            const cplx<R> t = cmul(a[j], twiddle(tw, pos * step, inverse));
-            const cplx<R> u = a[i];
-            a[i] = {u.x + t.x, u.y + t.y};
-            a[j] = {u.x - t.x, u.y - t.y};
+            const cplx<R> t = cmul(a[lds_pad(j)], twiddle(tw, pos * step, inverse));
+            const cplx<R> u = a[lds_pad(i)];
+            a[lds_pad(i)] = {u.x + t.x, u.y + t.y};
+            a[lds_pad(j)] = {u.x - t.x, u.y - t.y};
         }
         __syncthreads();
     }
@@ -134,7 +140,7 @@ __device__ void lds_fft_dif(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw
         for (int q = threadIdx.x; q < (n >> 2); q += blockDim.x) {
             const int pos = q & (h - 1);
             const int i = ((q >> (s - 2)) << s) + pos;
-            cplx<R> e0 = a[i], e1 = a[i + h], e2 = a[i + 2 * h], e3 = a[i + 3 * h];
+            cplx<R> e0 = a[lds_pad(i)], e1 = a[lds_pad(i + h)], e2 = a[lds_pad(i + 2 * h)], e3 = a[lds_pad(i + 3 * h)];
             const cplx<R> wa = twiddle(tw, pos * st1, inverse);
             const cplx<R> wb = twiddle(tw, (pos + h) * st1, inverse);
             cplx<R> d = {e0.x - e2.x, e0.y - e2.y};
@@ -145,22 +151,22 @@ __device__ void lds_fft_dif(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw
             e3 = cmul(d, wb);
             const cplx<R> w2 = twiddle(tw, pos * st2, inverse);
             d = {e0.x - e1.x, e0.y - e1.y};
-            a[i] = {e0.x + e1.x, e0.y + e1.y};
-            a[i + h] = cmul(d, w2);
+            a[lds_pad(i)] = {e0.x + e1.x, e0.y + e1.y};
+            a[lds_pad(i + h)] = cmul(d, w2);
             d = {e2.x - e3.x, e2.y - e3.y};
-            a[i + 2 * h] = {e2.x + e3.x, e2.y + e3.y};
-            a[i + 3 * h] = cmul(d, w2);
+            a[lds_pad(i + 2 * h)] = {e2.x + e3.x, e2.y + e3.y};
+            a[lds_pad(i + 3 * h)] = cmul(d, w2);
         }
         __syncthreads();
     }
     if (s == 1) {
         for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
             const int i = b << 1;  // half = 1, pos = 0: twiddle tw[0] = 1
-            const cplx<R> u = a[i];
-            const cplx<R> v = a[i + 1];
+            const cplx<R> u = a[lds_pad(i)];
+            const cplx<R> v = a[lds_pad(i + 1)];
             const cplx<R> w = twiddle(tw, 0, inverse);
-            a[i] = {u.x + v.x, u.y + v.y};
-            a[i + 1] = cmul(cplx<R>{u.x - v.x, u.y - v.y}, w);
+            a[lds_pad(i)] = {u.x + v.x, u.y + v.y};
+            a[lds_pad(i + 1)] = cmul(cplx<R>{u.x - v.x, u.y - v.y}, w);
         }
         __syncthreads();
     }
@@ -797,12 +803,12 @@ __device__ void dev_row_r2c(unsigned char* smem_raw, const LevelGeom& g, const R
     const int M = g.M;
     const int row = unit;
     const R* x = grid + (size_t)row * F;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) z[bitrev(n, logN)] = {x[2 * n], x[2 * n + 1]};
+    for (int n = threadIdx.x; n < N; n += blockDim.x) z[lds_pad(bitrev(n, logN))] = {x[2 * n], x[2 * n + 1]};
     __syncthreads();
     lds_fft(z, logN, tw, 2, false);
     for (int k = threadIdx.x; k <= M; k += blockDim.x) {
-        const cplx<R> a = z[k];
-        const cplx<R> b = z[(N - k) & (N - 1)];
+        const cplx<R> a = z[lds_pad(k)];
+        const cplx<R> b = z[lds_pad((N - k) & (N - 1))];
         const R ex = (a.x + b.x) * R(0.5), ey = (a.y - b.y) * R(0.5);   // even-sample spectrum
         const R ox = (a.y + b.y) * R(0.5), oy = (b.x - a.x) * R(0.5);   // odd-sample spectrum
         const cplx<R> wk = tw[k];                                       // exp(-2 pi i k / F)
@@ -827,7 +833,7 @@ __device__ void dev_col(unsigned char* smem_raw, const LevelGeom& g, cplx<R>* __
     const int M = g.M;
     const int m1 = unit;
     cplx<R>* col = spec + (size_t)m1 * F;
-    for (int q = threadIdx.x; q < F; q += blockDim.x) z[bitrev(q, logF)] = col[q];
+    for (int q = threadIdx.x; q < F; q += blockDim.x) z[lds_pad(bitrev(q, logF))] = col[q];
     __syncthreads();
     lds_fft(z, logF, tw, 1, false);
     for (int q = threadIdx.x; q < F; q += blockDim.x) {
@@ -835,12 +841,12 @@ __device__ void dev_col(unsigned char* smem_raw, const LevelGeom& g, cplx<R>* __
         const int am = m2 < 0 ? -m2 : m2;
         R t = am <= M ? mult[(size_t)m1 * (M + 1) + am] : R(0);
         if (zero_dc && m1 == 0 && q == 0) t = R(0);
-        z[q].x *= t;
-        z[q].y *= t;
+        z[lds_pad(q)].x *= t;
+        z[lds_pad(q)].y *= t;
     }
     __syncthreads();
     lds_fft_dif(z, logF, tw, 1, true);
-    for (int q = threadIdx.x; q < F; q += blockDim.x) col[q] = z[bitrev(q, logF)];
+    for (int q = threadIdx.x; q < F; q += blockDim.x) col[q] = z[lds_pad(bitrev(q, logF))];
 }
 
 // ---------------------------------------------------------------------------
@@ -867,13 +873,13 @@ __device__ void dev_row_c2r(unsigned char* smem_raw, const LevelGeom& g, const c
         const cplx<R> wk = tw[k];                     // exp(-2 pi i k/F); use its conjugate
         const R ox = dx * wk.x + dy * wk.y;
         const R oy = dy * wk.x - dx * wk.y;
-        z[bitrev(k, logN)] = {ex - oy, ey + ox};      // E + i O
+        z[lds_pad(bitrev(k, logN))] = {ex - oy, ey + ox};      // E + i O
     }
     __syncthreads();
     lds_fft(z, logN, tw, 2, true);
     R* o = out + (size_t)row * F;
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
-        const cplx<R> v = z[n];
+        const cplx<R> v = z[lds_pad(n)];
         o[2 * n] = v.x;
         o[2 * n + 1] = v.y;
     }

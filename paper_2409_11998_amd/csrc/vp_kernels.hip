@@ -141,13 +141,13 @@ inline unsigned grid_for(int64_t n, int per = kThreads)
 size_t row_fft_lds_bytes(const Plan& p, int level)
 {
     const size_t cb = p.precision == VP_FP32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
-    return (size_t)(p.lv[level].F / 2) * cb;
+    return (size_t)lds_padded_len(p.lv[level].F / 2) * cb;
 }
 
 size_t col_fft_lds_bytes(const Plan& p, int level)
 {
     const size_t cb = p.precision == VP_FP32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
-    return (size_t)p.lv[level].F * cb;
+    return (size_t)lds_padded_len(p.lv[level].F) * cb;
 }
 
 hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* sigma,
