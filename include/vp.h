@@ -220,6 +220,10 @@ typedef struct {
     int autotuned;        /* 1 if the levels were chosen by measurement (opts.autotune)      */
     int tune_candidates[2]; /* candidates timed per level (0 without autotune)               */
     double level_ms[2];   /* measured time of the chosen candidate's level kernels (ms)      */
+    int spread_terms[2];  /* terms of the per-tap kernel polynomials used in spreading         */
+    int interp_terms[2];  /* terms of the values-only polynomials used in interpolation        */
+    double spread_fit_err[2]; /* sampled max |polynomial - kernel| of the spreading table      */
+    double interp_fit_err[2]; /* the same for the interpolation table                          */
 } vp_plan_info;
 
 /* Fill info (host pointer) with the plan's parameters. */

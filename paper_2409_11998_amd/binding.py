@@ -78,7 +78,9 @@ class VPPlanInfo(ctypes.Structure):
                 ("n_src", ctypes.c_int64),
                 ("n_bnd", ctypes.c_int64), ("n_tgt", ctypes.c_int64), ("spread_records", ctypes.c_int64 * 2),
                 ("device_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
-                ("autotuned", ctypes.c_int), ("tune_candidates", ctypes.c_int * 2), ("level_ms", ctypes.c_double * 2)]
+                ("autotuned", ctypes.c_int), ("tune_candidates", ctypes.c_int * 2), ("level_ms", ctypes.c_double * 2),
+                ("spread_terms", ctypes.c_int * 2), ("interp_terms", ctypes.c_int * 2),
+                ("spread_fit_err", ctypes.c_double * 2), ("interp_fit_err", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -269,7 +271,9 @@ class Plan:
                     width=tuple(i.width), tile=tuple(i.tile), spread_mma=tuple(i.spread_mma), precision=i.precision, n_src=i.n_src, n_bnd=i.n_bnd,
                     n_tgt=i.n_tgt, spread_records=tuple(i.spread_records), device_bytes=i.device_bytes,
                     workspace_bytes=i.workspace_bytes, autotuned=bool(i.autotuned),
-                    tune_candidates=tuple(i.tune_candidates), level_ms=tuple(i.level_ms))
+                    tune_candidates=tuple(i.tune_candidates), level_ms=tuple(i.level_ms),
+                    spread_terms=tuple(i.spread_terms), interp_terms=tuple(i.interp_terms),
+                    spread_fit_err=tuple(i.spread_fit_err), interp_fit_err=tuple(i.interp_fit_err))
 
     def set_timing(self, on=True):
         _check(lib().vp_set_timing(self.handle, 1 if on else 0))

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void kg_interp(const LevelDesc* __restric
         if (!decode(t, it, i, l, u)) continue;
         const LevelDesc& D = lv[2 * i + l];
         const LevelGeom g = D.g;
-        dev::dev_interp<R, W>(smem_raw, g, (const R*)D.grid, tgt_view<R>(D), (R*)D.hist, D.horner, D.in_units[u]);
+        dev::dev_interp<R, W>(smem_raw, g, (const R*)D.grid, tgt_view<R>(D), (R*)D.hist, D.horner_i, D.in_units[u]);
         __syncthreads();
     }
 }
@@ -287,6 +287,7 @@ void fill_instance(const Plan& p, const Workspace& ws, InstDesc& I, LevelDesc* D
         d.tw = lb.tw;
         d.hist = ws.hist[l];
         d.horner = lb.horner;
+        d.horner_i = lb.horner_i;
         d.sp_units = lb.sp_units;
         d.in_units = lb.in_units;
         d.n_sp_units = (int)lb.h_sp_units.size();

@@ -367,6 +367,29 @@ __device__ __forceinline__ void tap_pair(const double* ce, const double* co, dou
     v_mirror = fma(-u, o, e);
 }
 
+// The same tap pair from coefficients that are equal on every lane (scalar
+// registers): each polynomial is summed from its top term down as
+// coefficient x power of u^2, the powers pw[k] = u^(2k) being shared by all
+// pairs of a lane, so every coefficient is a multiplicand (or the final
+// addend) and none has to be copied into a vector register first.
+template <int P>
+__device__ __forceinline__ void tap_pair_pow(const double* __restrict__ c, const double* pw, double u,
+                                             double& v_a, double& v_mirror)
+{
+    constexpr int NE = (P + 1) / 2, NO = P / 2;
+    static_assert(NO >= 2, "at least four terms");
+    double e = c[2 * (NE - 1)] * pw[NE - 1];
+#pragma unroll
+    for (int k = NE - 2; k >= 1; --k) e = fma(c[2 * k], pw[k], e);
+    e += c[0];
+    double o = c[2 * (NO - 1) + 1] * pw[NO - 1];
+#pragma unroll
+    for (int k = NO - 2; k >= 1; --k) o = fma(c[2 * k + 1], pw[k], o);
+    o += c[1];
+    v_a = fma(u, o, e);
+    v_mirror = fma(-u, o, e);
+}
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -889,15 +912,19 @@ __device__ void dev_row_c2r(unsigned char* smem_raw, const LevelGeom& g, const c
 // Interpolation (type-2, Sec. 3 Step 4 via the NUFFT): one workgroup per tile
 // stages the (T+w-1)^2 grid window in LDS (a target's support lies in the
 // window because the target is filed under the tile of its support corner).
-// Each wavefront takes chunks of 32 targets: lane (tap a, group) evaluates
-// tap a's polynomial (coefficients in its registers) for the chunk's offsets
-// into LDS, then lane pairs sum one target each (rows split in two halves).
+// Each wavefront takes chunks of 32 targets, two lanes per target: lane
+// (target q, coordinate c) evaluates the w kernel values of q's offset along
+// c (tap pairs a, w-1-a from one polynomial in u^2; the coefficients are the
+// same for every lane, so they come through scalar loads) into LDS, then the
+// lane sums half of q's support rows (odd w: the second half ends on a zero
+// row below the window, with weight zero, so both halves run alike).
 constexpr int kInterpTargets = 32;  // targets per wavefront chunk
 
 __host__ __device__ inline size_t interp_lds_bytes(int T, int W, size_t rb)
 {
-    const size_t win = ((size_t)(T + W - 1) * (T + W - 1) * rb + 15) & ~(size_t)15;
-    return win + (size_t)(kThreads / 64) * (kInterpTargets * (2 * W + 1) + 2 * kInterpTargets) * rb;
+    const size_t E = (size_t)(T + W - 1);
+    const size_t win = ((E + 1) * E * rb + 15) & ~(size_t)15;  // window rows and the zero row
+    return win + (size_t)(kThreads / 64) * kInterpTargets * (2 * W + 1) * rb;
 }
 
 template <typename R, int W>
@@ -905,10 +932,11 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
                            const RecView<R>& L, R* __restrict__ hist, const double* __restrict__ coef,
                            const WorkUnit unit)
 {
-    constexpr int P = horner_terms(W);
+    constexpr int P = interp_terms(W, sizeof(R) == 4);
     constexpr int NT = kInterpTargets;
     constexpr int VS = 2 * W + 1;  // odd stride: the targets' rows fall in different LDS banks
-    constexpr int HB = (W + 1) / 2;  // rows of the first half
+    constexpr int HB = (W + 1) / 2;  // rows per half; slot 2W of a target holds the zero row's weight
+    constexpr int NP = (W + 1) / 2;  // tap pairs (the middle tap of odd w pairs with itself)
     const int t = unit.tile;
     const int r0 = unit.a0;
     const int r1 = unit.a1;
@@ -919,79 +947,68 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
     R* reg = reinterpret_cast<R*>(smem_raw);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    R* vals = reinterpret_cast<R*>(smem_raw + (((size_t)E * E * sizeof(R) + 15) & ~(size_t)15)) +
-              (size_t)wv * (NT * VS + 2 * NT);
-    R* dd = vals + NT * VS;
+    R* vals = reinterpret_cast<R*>(smem_raw + (((size_t)(E + 1) * E * sizeof(R) + 15) & ~(size_t)15)) +
+              (size_t)wv * (NT * VS);
     const int gx0 = (t % g.ntx) * T;
     const int gy0 = (t / g.ntx) * T;
-    for (int i = threadIdx.x; i < E * E; i += blockDim.x) {
-        const int y = i / E;
-        const int x = i - y * E;
+    // window rows 0..E-1 from the grid, row E zero (32 lanes per row, no division)
+    for (int y = threadIdx.x >> 5; y <= E; y += blockDim.x >> 5) {
         const int gy = gy0 + y;
-        const int gx = gx0 + x;
-        reg[i] = (gx < F && gy < F) ? grid[(size_t)gy * F + gx] : R(0);
-    }
-    // kernel values: lane (tap pair kp, group kg) evaluates taps kp and w-1-kp
-    constexpr int NP = (W + 1) / 2;
-    constexpr int GP = 64 / NP;
-    const int kp = lane % NP;
-    const int kg = lane / NP;
-    const bool kon = lane < GP * NP;
-    double ce[(P + 1) / 2], co[P / 2];
-#pragma unroll
-    for (int k = 0; k < (P + 1) / 2; ++k) ce[k] = coef[kp * P + 2 * k];
-#pragma unroll
-    for (int k = 0; k < P / 2; ++k) co[k] = coef[kp * P + 2 * k + 1];
-    __syncthreads();
-    const int q = lane >> 1;    // target of this lane within the chunk
-    const int half = lane & 1;  // rows [0, HB) or [HB, W)
-    for (int base = r0 + wv * NT; base < r1; base += (kThreads / 64) * NT) {
-        const int nt = min(NT, r1 - base);
-        int my_ij = 0, my_idx = 0;
-        if (lane < nt) {
-            my_ij = L.ij[base + lane];
-            my_idx = L.idx[base + lane];
-            dd[2 * lane] = L.dx[base + lane];
-            dd[2 * lane + 1] = L.dy[base + lane];
+        for (int x = threadIdx.x & 31; x < E; x += 32) {
+            const int gx = gx0 + x;
+            reg[y * E + x] = (y < E && gx < F && gy < F) ? grid[(size_t)gy * F + gx] : R(0);
         }
-        wave_sync_lds();
-        if (kon) {
-            for (int pq = kg; pq < 2 * nt; pq += GP) {
-                const double u = 2.0 * (double)dd[pq] - 1.0;
+    }
+    __syncthreads();
+    // Lane (q, half): target q = lane % 32 of the chunk; half = lane / 32 is the
+    // coordinate of its kernel values (0: x, 1: y) and its rows [half HB, half HB + HB).
+    // Each half-wavefront thus reads one relative row of 32 targets, whose window
+    // offsets the target order makes distinct modulo 32: 32 different LDS banks.
+    const int q = lane & 31;
+    const int half = lane >> 5;
+    R* const v = vals + q * VS;
+    for (int base = r0 + wv * NT; base < r1; base += (kThreads / 64) * NT) {
+        const bool on = q < r1 - base;
+        int p = 0, id = 0;
+        if (on) {
+            p = L.ij[base + q];
+            id = L.idx[base + q];
+            const double u = 2.0 * (double)(half ? L.dy[base + q] : L.dx[base + q]) - 1.0;
+            double pw[(P + 1) / 2];
+            pw[0] = 1.0;
+            pw[1] = u * u;
+#pragma unroll
+            for (int k = 2; k < (P + 1) / 2; ++k) pw[k] = pw[k - 1] * pw[1];
+            R* dst = v + half * W;
+#pragma unroll
+            for (int kp = 0; kp < NP; ++kp) {
                 double va, vm;
-                tap_pair<P>(ce, co, u, va, vm);
-                R* dst = vals + (pq >> 1) * VS + (pq & 1) * W;
+                tap_pair_pow<P>(coef + kp * P, pw, u, va, vm);
                 dst[kp] = (R)va;
                 if (kp != W - 1 - kp) dst[W - 1 - kp] = (R)vm;
             }
+            if ((W & 1) && half) dst[W] = R(0);
         }
         wave_sync_lds();
-        const int p = __shfl(my_ij, q);
-        const int id = __shfl(my_idx, q);
         R sum = R(0);
-        if (q < nt) {
+        if (on) {
             const int i0 = (p & 0xffff) - gx0;
             const int j0 = (p >> 16) - gy0;
-            const R* v = vals + q * VS;
             R px[W];
 #pragma unroll
             for (int a2 = 0; a2 < W; ++a2) px[a2] = v[a2];
-            const int b0 = half ? HB : 0;
-            const int b1 = half ? W : HB;
+            const R* rowp = reg + (j0 + half * HB) * E + i0;
+            const R* wy = v + W + half * HB;
 #pragma unroll
             for (int bb = 0; bb < HB; ++bb) {
-                const int b = b0 + bb;
-                if (b < b1) {
-                    const R* rowp = reg + (j0 + b) * E + i0;
-                    R acc = R(0);
+                R acc = R(0);
 #pragma unroll
-                    for (int a2 = 0; a2 < W; ++a2) acc += px[a2] * rowp[a2];
-                    sum += v[W + b] * acc;
-                }
+                for (int a2 = 0; a2 < W; ++a2) acc += px[a2] * rowp[bb * E + a2];
+                sum += wy[bb] * acc;
             }
         }
-        sum += __shfl_xor(sum, 1);
-        if (q < nt && half == 0) hist[id] = sum;
+        sum += __shfl_xor(sum, 32);
+        if (on && half == 0) hist[id] = sum;
         wave_sync_lds();
     }
 }

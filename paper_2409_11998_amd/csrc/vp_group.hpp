@@ -22,6 +22,7 @@ struct LevelDesc {
     const void* tw;
     void* hist;
     const double* horner;
+    const double* horner_i;
     const WorkUnit* sp_units;
     const WorkUnit* in_units;
     int n_sp_units;

@@ -22,6 +22,15 @@ constexpr int kDcParts = 64;     // partial sums of the zero-frequency term (one
 // (10: value error below 2e-10) measurably raised the double-layer error,
 // whose derivative taps need the fuller fit.
 __host__ __device__ constexpr int horner_terms(int w) { return w + 2; }
+// Interpolation evaluates kernel values only, so its table keeps just the
+// terms the plan's arithmetic resolves: 10 for float32 (sampled fit error
+// below 2e-10, or equal to the w + 2 fit's where the exp(-beta) floor rules,
+// for every width and upsampling factor >= 1.1) and 13 for float64 (within
+// 10% of the w + 2 fit for upsampling <= 1.5 and below 5e-14 beyond).
+__host__ __device__ constexpr int interp_terms(int w, bool fp32)
+{
+    return (w + 2 < (fp32 ? 10 : 13)) ? w + 2 : (fp32 ? 10 : 13);
+}
 constexpr int kMmaTile = 16;     // tile edge of the matrix-core spread (window of 32 x 32 cells)
 
 // Launches timed by vp_set_timing, in order: grid zeroing + strengths; spread NH, FH; row FFT NH,
@@ -45,6 +54,7 @@ struct LevelGeom {
     double dk;      // 2 pi / P
     double dc_coef; // (dk/2pi)^2 * multiplier(0): the zero mode's kernel weight
     double dmax;    // max over taps and offsets of |d/dy tap value| (double-layer spreading bound)
+    double fit_err[2]; // sampled max |polynomial - kernel| of the spreading and interpolation tables
     int mma;        // spread on matrix cores (float32 plans on kMmaTile tiles), else LDS atomics
 };
 
@@ -99,6 +109,7 @@ struct LevelBufs {
     void* mult = nullptr;      // R [M+1][M+1] (dk/2pi)^2 M(k) / (phihat(m1) phihat(m2))^2
     void* tw = nullptr;        // cplx<R> [F/2] twiddles exp(-2 pi i k / F)
     double* horner = nullptr;  // [w][w+2] per-tap polynomial of the spreading kernel in u = 2d - 1
+    double* horner_i = nullptr; // [w][interp_terms] the same pieces, values-only fit for interpolation
 };
 
 // Per-evaluation device memory (everything an evaluation writes).  A plan may

@@ -330,7 +330,7 @@ static void interp_launch(const Plan& p, const Workspace& ws, hipStream_t st, in
     const unsigned nu = (unsigned)b.h_in_units.size();
     if (nu == 0) return;
     hipLaunchKernelGGL((k_interp<R, W>), dim3(nu), dim3(kThreads), lds, st, g, (const R*)ws.grid[l],
-                       view<R>(b.tgt), (R*)ws.hist[l], (const double*)b.horner, (const WorkUnit*)b.in_units);
+                       view<R>(b.tgt), (R*)ws.hist[l], (const double*)b.horner_i, (const WorkUnit*)b.in_units);
 }
 
 template <typename R>

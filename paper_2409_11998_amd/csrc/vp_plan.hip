@@ -402,6 +402,62 @@ vp_status build_units(Plan& p, int l)
     return VP_OK;
 }
 
+// Spreading kernel piece of tap a over one grid cell, as a function of the
+// node offset: the tap sits at z = ((2a - w) + (u + 1)) / w, u = 2d - 1.
+static double tap_kernel(int W, int a, double u, double beta)
+{
+    const double z = ((2.0 * a - W) + (u + 1.0)) / W;
+    const double q = 1.0 - z * z;
+    return q > 0 ? std::exp(-beta * z * z / (1.0 + std::sqrt(q))) : 0.0;
+}
+
+// Chebyshev interpolation of every tap's piece at P points in u, converted
+// to monomial coefficients ([W][P], constant term first).
+static std::vector<double> fit_tap_polynomials(int W, int P, double beta)
+{
+    std::vector<double> coef((size_t)W * P);
+    std::vector<double> cn(P), fv(P);
+    for (int j = 0; j < P; ++j) cn[j] = std::cos(M_PI * (j + 0.5) / P);
+    for (int a = 0; a < W; ++a) {
+        for (int j = 0; j < P; ++j) fv[j] = tap_kernel(W, a, cn[j], beta);
+        std::vector<double> ch(P);
+        for (int k = 0; k < P; ++k) {
+            double sacc = 0.0;
+            for (int j = 0; j < P; ++j) sacc += fv[j] * std::cos(M_PI * k * (j + 0.5) / P);
+            ch[k] = (k == 0 ? 1.0 : 2.0) * sacc / P;
+        }
+        // T_k(u) as monomials by the three-term recurrence on coefficient vectors
+        std::vector<double> mono(P, 0.0), tkm1(P, 0.0), tk(P, 0.0), tkp1(P, 0.0);
+        tkm1[0] = 1.0;
+        if (P > 1) tk[1] = 1.0;
+        for (int i = 0; i < P; ++i) mono[i] += ch[0] * tkm1[i];
+        if (P > 1)
+            for (int i = 0; i < P; ++i) mono[i] += ch[1] * tk[i];
+        for (int k = 2; k < P; ++k) {
+            for (int i = 0; i < P; ++i) tkp1[i] = -tkm1[i] + ((i > 0) ? 2.0 * tk[i - 1] : 0.0);
+            for (int i = 0; i < P; ++i) mono[i] += ch[k] * tkp1[i];
+            tkm1.swap(tk);
+            tk.swap(tkp1);
+        }
+        for (int i = 0; i < P; ++i) coef[(size_t)a * P + i] = mono[i];
+    }
+    return coef;
+}
+
+// max |polynomial - kernel| over taps and 513 offsets per tap
+static double tap_fit_error(const std::vector<double>& coef, int W, int P, double beta)
+{
+    double e = 0.0;
+    for (int a = 0; a < W; ++a)
+        for (int k = 0; k <= 512; ++k) {
+            const double u = -1.0 + 2.0 * k / 512.0;
+            double v = 0.0;
+            for (int i = P - 1; i >= 0; --i) v = v * u + coef[(size_t)a * P + i];
+            e = std::max(e, std::fabs(v - tap_kernel(W, a, u, beta)));
+        }
+    return e;
+}
+
 template <typename R>
 vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, double d1, double d2)
 {
@@ -419,42 +475,15 @@ vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, 
             mult[(size_t)a * (M + 1) + c] = (R)(scale * m / (ph * ph));
         }
     g.dc_coef = scale * ((l == 0) ? mult_nh(0.0, d1, d2) : mult_fh(0.0, d2, p.L));
-    // Spreading kernel per tap as a polynomial in the node offset: tap a of a
-    // node with offset d in [0,1) sits at z = ((2a - w) + (u + 1)) / w, u = 2d - 1.
-    // Chebyshev interpolation at horner_terms(w) points, converted to monomials in u.
+    // Spreading kernel per tap as a polynomial in the node offset (spreading
+    // table, horner_terms(w) terms; interpolation table, interp_terms(w)).
     {
         const int W = g.w, P = horner_terms(W);
-        std::vector<double> coef((size_t)W * P);
-        std::vector<double> cn(P), fv(P);
-        for (int j = 0; j < P; ++j) cn[j] = std::cos(M_PI * (j + 0.5) / P);
-        for (int a = 0; a < W; ++a) {
-            for (int j = 0; j < P; ++j) {
-                const double z = ((2.0 * a - W) + (cn[j] + 1.0)) / W;
-                const double q = 1.0 - z * z;
-                fv[j] = q > 0 ? std::exp(-g.beta * z * z / (1.0 + std::sqrt(q))) : 0.0;
-            }
-            // Chebyshev coefficients
-            std::vector<double> ch(P);
-            for (int k = 0; k < P; ++k) {
-                double sacc = 0.0;
-                for (int j = 0; j < P; ++j) sacc += fv[j] * std::cos(M_PI * k * (j + 0.5) / P);
-                ch[k] = (k == 0 ? 1.0 : 2.0) * sacc / P;
-            }
-            // monomial coefficients: T_k(u) via the recurrence on coefficient vectors
-            std::vector<double> mono(P, 0.0), tkm1(P, 0.0), tk(P, 0.0), tkp1(P, 0.0);
-            tkm1[0] = 1.0;                     // T_0
-            if (P > 1) tk[1] = 1.0;            // T_1
-            for (int i = 0; i < P; ++i) mono[i] += ch[0] * tkm1[i];
-            if (P > 1)
-                for (int i = 0; i < P; ++i) mono[i] += ch[1] * tk[i];
-            for (int k = 2; k < P; ++k) {
-                for (int i = 0; i < P; ++i) tkp1[i] = -tkm1[i] + ((i > 0) ? 2.0 * tk[i - 1] : 0.0);
-                for (int i = 0; i < P; ++i) mono[i] += ch[k] * tkp1[i];
-                tkm1.swap(tk);
-                tk.swap(tkp1);
-            }
-            for (int i = 0; i < P; ++i) coef[(size_t)a * P + i] = mono[i];
-        }
+        const int PI = interp_terms(W, p.precision == VP_FP32);
+        const std::vector<double> coef = fit_tap_polynomials(W, P, g.beta);
+        const std::vector<double> coef_i = fit_tap_polynomials(W, PI, g.beta);
+        g.fit_err[0] = tap_fit_error(coef, W, P, g.beta);
+        g.fit_err[1] = tap_fit_error(coef_i, W, PI, g.beta);
         // bound on |d/dy tap value| = (2/h) |dp/du| over taps and offsets (sampled, 5% margin)
         double dm = 0.0;
         for (int a = 0; a < W; ++a)
@@ -467,6 +496,7 @@ vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, 
         g.dmax = 1.05 * dm * 2.0 / g.h;
         vp_status st2;
         if ((st2 = upload(p, &b.horner, coef, "kernel polynomials")) != VP_OK) return st2;
+        if ((st2 = upload(p, &b.horner_i, coef_i, "interpolation kernel polynomials")) != VP_OK) return st2;
     }
     std::vector<cplx<R>> tw(g.F / 2);
     for (int k = 0; k < g.F / 2; ++k) {
@@ -1109,6 +1139,10 @@ vp_status vp_get_plan_info(vp_plan_t p, vp_plan_info* info)
     for (int l = 0; l < 2; ++l) {
         info->tile[l] = p->lv[l].T;
         info->spread_mma[l] = p->lv[l].mma;
+        info->spread_terms[l] = horner_terms(p->lv[l].w);
+        info->interp_terms[l] = interp_terms(p->lv[l].w, p->precision == VP_FP32);
+        info->spread_fit_err[l] = p->lv[l].fit_err[0];
+        info->interp_fit_err[l] = p->lv[l].fit_err[1];
     }
     info->precision = p->precision;
     info->n_src = p->n_src;

@@ -84,6 +84,16 @@ def test_spread_paths_match_oracle(precision, tile):
     e = oracle.rel_linf(got, ref)
     print("spread path precision", precision, "tile", tile, "e_inf", e, plan.info()["width"])
     assert e <= tol
+    # the interpolation's values-only kernel table: fewer terms, fit as good as the
+    # spreading table's up to what the plan's arithmetic resolves
+    cap = 10 if precision == 0 else 13
+    floor = 5e-10 if precision == 0 else 5e-14
+    for lv in range(2):
+        w = info["width"][lv]
+        assert info["spread_terms"][lv] == w + 2
+        assert info["interp_terms"][lv] == min(w + 2, cap)
+        assert info["interp_fit_err"][lv] <= max(1.5 * info["spread_fit_err"][lv], floor)
+        assert info["interp_fit_err"][lv] <= 0.1 * tol
 
 
 @pytest.mark.parametrize("precision,tol", [(1, 1e-10), (0, 1e-6)])
