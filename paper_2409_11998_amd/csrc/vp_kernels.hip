@@ -94,8 +94,13 @@ __global__ __launch_bounds__(kThreads) void k_row_r2c(LevelPair<R> P)
     dev_row_r2c<R>(smem_raw, P.g[l], P.grid[l], P.tw[l], P.spec[l], u);
 }
 
+// The column pass runs one thread per radix-4 butterfly of its length-F FFTs
+// (F / 4 threads, at least kThreads): few columns per CU, each a chain of
+// dependent LDS passes, so the threads shorten every pass instead of queuing.
+constexpr int kColThreadsMax = 1024;
+
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_col(LevelPair<R> P, int zero_dc)
+__global__ __launch_bounds__(kColThreadsMax) void k_col(LevelPair<R> P, int zero_dc)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int l;
@@ -146,8 +151,7 @@ size_t row_fft_lds_bytes(const Plan& p, int level)
 
 size_t col_fft_lds_bytes(const Plan& p, int level)
 {
-    const size_t cb = p.precision == VP_FP32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
-    return (size_t)lds_padded_len(p.lv[level].F) * cb;
+    return p.precision == VP_FP32 ? col_lds_bytes<float>(p.lv[level].F) : col_lds_bytes<double>(p.lv[level].F);
 }
 
 hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, const double* f, const double* sigma,
@@ -297,7 +301,11 @@ static hipError_t col_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, 
 {
     const LevelPair<R> P = level_pair<R>(p, ws, level, cols_of);
     const int zero_dc = p.precision == VP_FP32 ? 1 : 0;
-    hipLaunchKernelGGL((k_col<R>), dim3(P.n[0] + P.n[1]), dim3(kThreads), pair_lds(p, level, col_fft_lds_bytes), st,
+    int f = 0;
+    for (int l = 0; l < 2; ++l)
+        if (level < 0 || l == level) f = std::max(f, p.lv[l].F);
+    const int threads = std::min(kColThreadsMax, std::max(kThreads, f / 4));
+    hipLaunchKernelGGL((k_col<R>), dim3(P.n[0] + P.n[1]), dim3(threads), pair_lds(p, level, col_fft_lds_bytes), st,
                        P, zero_dc);
     return hipGetLastError();
 }

@@ -241,9 +241,10 @@ void free_plan(vp_plan_s* p)
 
 // Sort points into tiles of one level: one record per point, in the tile
 // holding its support corner.  With pitch > 0 (interpolation targets) the
-// records of each tile are dealt round-robin over the residues of their
-// window offset (j0 - gy0) * pitch + (i0 - gx0) modulo 32, so that the 32
-// targets a wavefront handles together read 32 different LDS banks.
+// records of each tile are ordered in chunks of 32 with distinct residues of
+// their window offset (j0 - gy0) * pitch + (i0 - gx0) modulo 32 wherever the
+// tile allows, so that the 32 targets a wavefront handles together read 32
+// different LDS banks.
 template <typename R>
 vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std::vector<double>& y,
                         const std::vector<int>& ids, RecList* list, int pitch = 0)
@@ -284,36 +285,52 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
     }
     if (pitch > 0) {
         constexpr int NB = 32;
-        std::vector<int> perm, bucket_pos(NB + 1);
         std::vector<int> rij2(rij), ridx2(ridx);
         std::vector<R> rsx2(rsx), rsy2(rsy);
+        std::vector<std::vector<int>> grp(NB);
+        std::vector<int> next(NB), order(NB);
+        std::vector<std::pair<int, int>> chunk;  // (residue, record) of the chunk being formed
         for (int t = 0; t < ntiles; ++t) {
             const int b0 = cnt[t], b1 = cnt[t + 1];
             if (b1 - b0 < 2) continue;
             const int gx0 = (t % ntx) * T, gy0 = (t / ntx) * T;
-            auto key = [&](int r) {
+            for (auto& v : grp) v.clear();
+            for (int r = b0; r < b1; ++r) {
                 const int ii = (rij[r] & 0xffff) - gx0, jj = (rij[r] >> 16) - gy0;
-                return (jj * pitch + ii) % NB;
-            };
-            std::fill(bucket_pos.begin(), bucket_pos.end(), 0);
-            for (int r = b0; r < b1; ++r) bucket_pos[key(r) + 1]++;
-            for (int k = 0; k < NB; ++k) bucket_pos[k + 1] += bucket_pos[k];
-            perm.assign(b1 - b0, 0);
-            std::vector<int> fill(bucket_pos.begin(), bucket_pos.end() - 1);
-            for (int r = b0; r < b1; ++r) perm[fill[key(r)]++] = r;  // grouped by residue, stable
-            // deal round-robin over the residue groups
+                grp[(jj * pitch + ii) % NB].push_back(r);
+            }
+            std::fill(next.begin(), next.end(), 0);
+            // chunks of NB records: each takes one record from each of the residues
+            // with the most records left (so all NB residues last as long as they
+            // can), more from the largest only when fewer than NB remain; within a
+            // chunk the records go in ascending residue (a full chunk: record q has
+            // residue q, so any grouping of its lanes reads distinct banks)
             int out = b0;
-            std::vector<int> next(bucket_pos.begin(), bucket_pos.end() - 1);
-            while (out < b1)
-                for (int k = 0; k < NB && out < b1; ++k)
-                    if (next[k] < bucket_pos[k + 1]) {
-                        const int r = perm[next[k]++];
-                        rij2[out] = rij[r];
-                        ridx2[out] = ridx[r];
-                        rsx2[out] = rsx[r];
-                        rsy2[out] = rsy[r];
-                        ++out;
+            while (out < b1) {
+                const int chunk_end = std::min(b1, out + NB);
+                chunk.clear();
+                while ((int)chunk.size() < chunk_end - out) {
+                    for (int k = 0; k < NB; ++k) order[k] = k;
+                    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+                        return (int)grp[x].size() - next[x] > (int)grp[y].size() - next[y];
+                    });
+                    for (int k = 0; k < NB && (int)chunk.size() < chunk_end - out; ++k) {
+                        const int g = order[k];
+                        if (next[g] == (int)grp[g].size()) break;  // sorted: the rest are empty too
+                        chunk.push_back({g, grp[g][next[g]++]});
                     }
+                }
+                std::stable_sort(chunk.begin(), chunk.end(),
+                                 [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.first < y.first; });
+                for (const auto& c : chunk) {
+                    const int r = c.second;
+                    rij2[out] = rij[r];
+                    ridx2[out] = ridx[r];
+                    rsx2[out] = rsx[r];
+                    rsy2[out] = rsy[r];
+                    ++out;
+                }
+            }
         }
         rij.swap(rij2);
         ridx.swap(ridx2);
