@@ -236,6 +236,11 @@ void free_plan(vp_plan_s* p)
     workspace_free(p->ws, nullptr, false);
     if (p->ev_made)
         for (auto& e : p->ev) hipEventDestroy(e);
+    if (p->side_made) {
+        hipStreamSynchronize(p->side);
+        for (auto& e : p->fork) hipEventDestroy(e);
+        hipStreamDestroy(p->side);
+    }
     delete p;
 }
 
@@ -756,7 +761,36 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
         for (auto& e : p.ev) VP_HIP(hipEventCreate(&e), "event create");
         p.ev_made = true;
     }
-    auto mark = [&](int k) -> hipError_t { return timing ? hipEventRecord(p.ev[k], st) : hipSuccess; };
+    if (!timing) {
+        // the two levels are independent from the strengths to the history values:
+        // the far-history level's spread and interpolation run on the side stream
+        if (!p.side_made) {
+            VP_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking), "side stream");
+            for (auto& e : p.fork) VP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
+            p.side_made = true;
+        }
+        hipStream_t sd = p.side;
+        VP_HIP(launch_zero(p, ws, st), "zero");
+        VP_HIP(launch_strengths(p, ws, st, f, sigma, mu), "strengths");
+        VP_HIP(hipEventRecord(p.fork[0], st), "fork");
+        VP_HIP(hipStreamWaitEvent(sd, p.fork[0], 0), "fork");
+        VP_HIP(launch_spread(p, ws, sd, 1, use_v, use_s || use_d, use_d), "spread");
+        VP_HIP(hipEventRecord(p.fork[1], sd), "join");
+        VP_HIP(launch_spread(p, ws, st, 0, use_v, use_s || use_d, use_d), "spread");
+        VP_HIP(hipStreamWaitEvent(st, p.fork[1], 0), "join");
+        VP_HIP(launch_row_fft(p, ws, st, -1), "row fft");
+        VP_HIP(launch_col_fft(p, ws, st, -1), "column fft");
+        VP_HIP(launch_row_ifft(p, ws, st, -1), "row ifft");
+        VP_HIP(hipEventRecord(p.fork[2], st), "fork");
+        VP_HIP(hipStreamWaitEvent(sd, p.fork[2], 0), "fork");
+        VP_HIP(launch_interp(p, ws, sd, 1), "interp");
+        VP_HIP(hipEventRecord(p.fork[3], sd), "join");
+        VP_HIP(launch_interp(p, ws, st, 0), "interp");
+        VP_HIP(hipStreamWaitEvent(st, p.fork[3], 0), "join");
+        VP_HIP(launch_local(p, ws, st, jet6, sigma_jet3, mu_jet5, use_v, use_s, use_d, out), "local");
+        return VP_OK;
+    }
+    auto mark = [&](int k) -> hipError_t { return hipEventRecord(p.ev[k], st); };
     VP_HIP(mark(0), "event");
     VP_HIP(launch_zero(p, ws, st), "zero");
     VP_HIP(launch_strengths(p, ws, st, f, sigma, mu), "strengths");
@@ -765,25 +799,18 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
         VP_HIP(launch_spread(p, ws, st, l, use_v, use_s || use_d, use_d), "spread");
         VP_HIP(mark(2 + l), "event");
     }
-    // the FFT passes of both levels share one launch each, except when every
-    // launch is timed (then one per level, in the order of the timing slots)
-    if (timing) {
-        for (int l = 0; l < 2; ++l) {
-            VP_HIP(launch_row_fft(p, ws, st, l), "row fft");
-            VP_HIP(mark(4 + l), "event");
-        }
-        for (int l = 0; l < 2; ++l) {
-            VP_HIP(launch_col_fft(p, ws, st, l), "column fft");
-            VP_HIP(mark(6 + l), "event");
-        }
-        for (int l = 0; l < 2; ++l) {
-            VP_HIP(launch_row_ifft(p, ws, st, l), "row ifft");
-            VP_HIP(mark(8 + l), "event");
-        }
-    } else {
-        VP_HIP(launch_row_fft(p, ws, st, -1), "row fft");
-        VP_HIP(launch_col_fft(p, ws, st, -1), "column fft");
-        VP_HIP(launch_row_ifft(p, ws, st, -1), "row ifft");
+    // timed: every launch on one stream, one per level, in the order of the timing slots
+    for (int l = 0; l < 2; ++l) {
+        VP_HIP(launch_row_fft(p, ws, st, l), "row fft");
+        VP_HIP(mark(4 + l), "event");
+    }
+    for (int l = 0; l < 2; ++l) {
+        VP_HIP(launch_col_fft(p, ws, st, l), "column fft");
+        VP_HIP(mark(6 + l), "event");
+    }
+    for (int l = 0; l < 2; ++l) {
+        VP_HIP(launch_row_ifft(p, ws, st, l), "row ifft");
+        VP_HIP(mark(8 + l), "event");
     }
     for (int l = 0; l < 2; ++l) {
         VP_HIP(launch_interp(p, ws, st, l), "interp");
