@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void kg_strengths(const InstDesc* __restr
         const InstDesc& I = inst[i];
         const CallDesc& K = call[i];
         dev::dev_strengths<R>(I.n_src, I.n_bnd, K.f, K.sigma, K.mu, I.w, I.nx, I.ny, (R*)I.str,
-                              sizeof(R) == 4 ? I.dc : nullptr, I.smax, u);
+                              sizeof(R) == 4 ? I.dc : nullptr, sizeof(R) == 4 ? I.smax : nullptr, u);
     }
 }
 
@@ -331,7 +331,8 @@ vp_status group_build(const std::vector<const Plan*>& plans, const std::vector<W
         fill_instance(p, ws[i], G.inst[i], &G.lv[2 * i]);
         G.call[i] = make_call(args[i]);
         const int64_t nn = p.n_src + p.n_bnd;
-        G.str.add(i, 0, (int)((nn + dev::kStrChunk - 1) / dev::kStrChunk));
+        const int sc = G.precision == VP_FP32 ? dev::str_chunk<float>() : dev::str_chunk<double>();
+        G.str.add(i, 0, (int)((nn + sc - 1) / sc));
         G.local.add(i, 0, (int)((p.n_tgt + kThreads - 1) / kThreads));
         for (int l = 0; l < 2; ++l) {
             const LevelGeom& g = p.lv[l];

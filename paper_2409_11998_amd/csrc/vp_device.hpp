@@ -179,7 +179,13 @@ __device__ void lds_fft_dif(cplx<R>* a, int logn, const cplx<R>* __restrict__ tw
 // for boundary node j (n = all nodes, nb = boundary nodes; present only when
 // mu is given).  Also accumulates sum(str[0..n)) in float64 (the
 // zero-frequency term).
-constexpr int kStrChunk = kThreads * 16;  // nodes per strengths work unit
+// Nodes per thread of a strengths work unit: float32 plans reduce strength
+// maxima (and the zero-frequency sum) by one atomic per unit, so their units
+// stay long; float64 plans reduce nothing and use short units (more of them in
+// flight).  Loads go out kStrBatch nodes at a time.
+constexpr int kStrBatch = 4;
+template <typename R> __host__ __device__ constexpr int str_per() { return sizeof(R) == 4 ? 16 : 4; }
+template <typename R> __host__ __device__ constexpr int str_chunk() { return kThreads * str_per<R>(); }
 
 template <typename R>
 __device__ void dev_strengths(int64_t n_src, int64_t n_bnd, const double* __restrict__ f,
@@ -190,27 +196,43 @@ __device__ void dev_strengths(int64_t n_src, int64_t n_bnd, const double* __rest
 {
     const int64_t n = n_src + n_bnd;
     double part = 0.0, m0 = 0.0, m1 = 0.0;
-    const int64_t i1 = min(n, (unit + 1) * (int64_t)kStrChunk);
-    for (int64_t i = unit * (int64_t)kStrChunk + threadIdx.x; i < i1; i += blockDim.x) {
-        double s0 = 0.0;
-        if (i < n_src) {
-            if (f) s0 = f[i] * w[i];
-        } else {
-            const int64_t j = i - n_src;
-            const double wg = w[i];
-            if (sigma) s0 = sigma[j] * wg;
-            if (mu) {
-                const double m = mu[j] * wg;
-                const R gx = (R)(m * nx[j]), gy = (R)(m * ny[j]);
-                str[n + j] = gx;
-                str[n + n_bnd + j] = gy;
-                m1 = fmax(m1, fabs((double)gx) + fabs((double)gy));
+    constexpr int NB = str_per<R>() / kStrBatch;
+    const int64_t i1 = min(n, (unit + 1) * (int64_t)str_chunk<R>());
+    for (int bt = 0; bt < NB; ++bt) {
+    const int64_t ib = unit * (int64_t)str_chunk<R>() + (int64_t)bt * kStrBatch * blockDim.x + threadIdx.x;
+    double wv[kStrBatch], dv[kStrBatch];
+#pragma unroll
+    for (int k = 0; k < kStrBatch; ++k) {
+        const int64_t i = ib + (int64_t)k * blockDim.x;
+        wv[k] = 0.0;
+        dv[k] = 0.0;
+        if (i < i1) {
+            wv[k] = w[i];
+            if (i < n_src) {
+                if (f) dv[k] = f[i];
+            } else if (sigma) {
+                dv[k] = sigma[i - n_src];
             }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kStrBatch; ++k) {
+        const int64_t i = ib + (int64_t)k * blockDim.x;
+        if (i >= i1) break;
+        const double s0 = dv[k] * wv[k];
+        if (i >= n_src && mu) {
+            const int64_t j = i - n_src;
+            const double m = mu[j] * wv[k];
+            const R gx = (R)(m * nx[j]), gy = (R)(m * ny[j]);
+            str[n + j] = gx;
+            str[n + n_bnd + j] = gy;
+            m1 = fmax(m1, fabs((double)gx) + fabs((double)gy));
         }
         const R sr = (R)s0;
         str[i] = sr;
         part += s0;
         m0 = fmax(m0, fabs((double)sr));
+    }
     }
     // workgroup reductions (wavefront shuffles, then LDS): the zero-frequency sum
     // (one float64 atomic per unit into one of kDcParts partial sums) and the
@@ -236,8 +258,8 @@ __device__ void dev_strengths(int64_t n_src, int64_t n_bnd, const double* __rest
             b = fmax(b, red[2][k]);
         }
         if (dc && t != 0.0) atomicAdd(dc + (unit % kDcParts), t);
-        if (a > 0.0) atomicMax(smax, (unsigned long long)__double_as_longlong(a));
-        if (b > 0.0) atomicMax(smax + 1, (unsigned long long)__double_as_longlong(b));
+        if (smax && a > 0.0) atomicMax(smax, (unsigned long long)__double_as_longlong(a));
+        if (smax && b > 0.0) atomicMax(smax + 1, (unsigned long long)__double_as_longlong(b));
     }
     __syncthreads();
 }

@@ -158,13 +158,14 @@ hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, 
                             const double* mu)
 {
     const int64_t n = p.n_src + p.n_bnd;
-    const unsigned blocks = grid_for(n, kStrChunk);
+    const unsigned blocks = grid_for(n, p.precision == VP_FP32 ? str_chunk<float>() : str_chunk<double>());
     if (p.precision == VP_FP32)
         hipLaunchKernelGGL(k_strengths<float>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
                            p.d_w, p.d_nx, p.d_ny, (float*)ws.str, ws.dc, ws.smax);
-    else  // the zero-frequency sum is used by the float32 path only
+    else  // the zero-frequency sum and the strength maxima are used by the float32 path only
         hipLaunchKernelGGL(k_strengths<double>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
-                           p.d_w, p.d_nx, p.d_ny, (double*)ws.str, (double*)nullptr, ws.smax);
+                           p.d_w, p.d_nx, p.d_ny, (double*)ws.str, (double*)nullptr,
+                           (unsigned long long*)nullptr);
     return hipGetLastError();
 }
 
