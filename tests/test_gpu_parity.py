@@ -152,3 +152,38 @@ def test_full_size_sampled_parity(workload):
     e = float(np.max(np.abs(got[idx] - ref)) / np.max(np.abs(ref)))
     print(workload, "sampled e_inf", e, plan.info()["fine"], plan.info()["width"])
     assert e <= tol
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_timed_and_overlapped_evaluations_agree(precision):
+    """An untimed evaluation runs the far-history level on a second stream beside
+    the near-history one; a timed evaluation runs every launch in order on one
+    stream.  Both, repeated (events reused) and on a plan whose workspace is
+    allocated stream-ordered per call, match the oracle and each other."""
+    torch = _gpu()
+    from workloads.device import make_plan, run, to_device
+    P = star_problem(2000, seed=31)
+    tol = 1e-10 if precision == 1 else 1e-6
+    ref = oracle.evaluate(P, kinds="VSD")["total"]
+    dev = to_device(P)
+    results = []
+    for no_ws in (False, True):
+        plan = make_plan(dev, tol=tol, precision=precision, kinds=7, no_workspace=no_ws)
+        for timed in (False, True, False):
+            plan.set_timing(timed)
+            out = run(plan, dev, "VSD")
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            e = oracle.rel_linf(got, ref)
+            print("precision", precision, "no_workspace", no_ws, "timed", timed, "e_inf", e)
+            assert e <= tol
+            results.append(got)
+            if timed:
+                t = plan.timing()
+                assert all(t[k] > 0 for k in ("spread_nh", "spread_fh", "interp_nh", "interp_fh", "local"))
+                assert t["total"] >= max(v for k, v in t.items() if k != "total")
+        plan.close()
+    # float64: the runs differ only in the order of floating-point atomic additions
+    agree = 1e-13 if precision == 1 else 2e-6
+    for r in results[1:]:
+        assert oracle.rel_linf(r, results[0]) <= agree
