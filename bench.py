@@ -9,9 +9,11 @@ A second leg runs the float32 path (tolerance 1e-6) on the unit disk with
 ~2M triangles (~12M nodes, V[f]).
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region;
-the timed region is bracketed by torch.cuda.synchronize().  Per-stage times
-come from HIP events recorded on the plan's stream (vp_set_timing) in a
-separate pass of the same number of steps.  The CPU baseline is the float64
+the timed region is bracketed by torch.cuda.synchronize().  In the timed
+steps the far-history level's spread and interpolation run on a second stream
+beside the near-history level's.  Per-stage times come from HIP events
+recorded on the plan's stream (vp_set_timing) in a separate pass of the same
+number of steps, in which every launch runs alone, in order, on that stream.  The CPU baseline is the float64
 oracle (direct sums + local asymptotics) on a bounded sample of targets on
 this host's cores.
 """
@@ -243,7 +245,8 @@ def main():
     roof = {"bound": "hbm", "kernel": kname, "launch": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_from_profiles(dom, workload),
-            "algorithmic_bytes_per_launch": int(alg[dom]), "avg_ms": round(st[dom], 4)}
+            "algorithmic_bytes_per_launch": int(alg[dom]), "avg_ms": round(st[dom], 4),
+            "avg_ms_from": "HIP events, timing pass (each launch alone on the plan's stream)"}
     stages_gbs = {k: round(alg[k] / (st[k] * 1e-3) / 1e9, 1) for k in LAUNCHES if st.get(k, 0) > 0}
     cpu = None
     if args.oracle_sample:
