@@ -29,7 +29,11 @@
  *    re-entrant (they share the plan's device workspace) and must be
  *    serialized by the caller.  Distinct plans may be used from different
  *    threads.  vp_eval/vp_volume/vp_layer only enqueue work on that stream:
- *    the output is ready once the stream is synchronized.
+ *    the output is ready once the stream is synchronized.  Without timing
+ *    (vp_set_timing) an evaluation also runs the far-history level on a
+ *    second stream the plan owns (default priority), forked from and joined
+ *    back into the plan's stream by events inside the same call, so ordering
+ *    against the plan's stream (and stream capture of it) is unchanged.
  */
 #ifndef VP_H
 #define VP_H
@@ -234,8 +238,10 @@ vp_status vp_get_plan_info(vp_plan_t plan, vp_plan_info* info);
  * [0] strengths, [1] spread NH, [2] spread FH, [3] row FFT NH, [4] row FFT FH,
  * [5] column FFT+multiply+inverse NH, [6] same FH, [7] row inverse FFT NH,
  * [8] same FH, [9] interpolation NH, [10] interpolation FH, [11] local part and
- * final sum, [12] total.  Enabled by vp_set_timing(plan, 1); reading it
- * synchronizes on the last event. */
+ * final sum, [12] total.  Enabled by vp_set_timing(plan, 1): a timed
+ * evaluation runs every launch alone, in this order, on the plan's stream (an
+ * untimed one overlaps the two levels on two streams and takes less than
+ * [12]).  Reading it synchronizes on the last event. */
 vp_status vp_set_timing(vp_plan_t plan, int enable);
 vp_status vp_get_timing(vp_plan_t plan, double* ms13);
 
