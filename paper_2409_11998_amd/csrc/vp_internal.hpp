@@ -183,10 +183,11 @@ struct Plan {
     double level_ms[2] = {0.0, 0.0};
     hipEvent_t ev[kTimedLaunches + 1]{};  // before the first and after each timed launch
     bool ev_made = false;
-    // An untimed evaluation runs the far-history level's spread and interpolation
-    // on a second stream beside the near-history level's (fork/join by events).
+    // An untimed evaluation runs the far-history level's chain (spread, FFT
+    // passes, interpolation) on a second stream beside the near-history
+    // level's: fork after the strengths, join before the local part.
     hipStream_t side = nullptr;
-    hipEvent_t fork[4]{};
+    hipEvent_t fork[2]{};
     bool side_made = false;
     Refinement ref;               // dyadic refinement of the local layer parts (optional)
 };

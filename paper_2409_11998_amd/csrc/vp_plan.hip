@@ -763,7 +763,8 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
     }
     if (!timing) {
         // the two levels are independent from the strengths to the history values:
-        // the far-history level's spread and interpolation run on the side stream
+        // the far-history level's whole chain (spread, FFT passes, interpolation)
+        // runs on the side stream beside the near-history level's
         if (!p.side_made) {
             VP_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking), "side stream");
             for (auto& e : p.fork) VP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
@@ -775,18 +776,17 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
         VP_HIP(hipEventRecord(p.fork[0], st), "fork");
         VP_HIP(hipStreamWaitEvent(sd, p.fork[0], 0), "fork");
         VP_HIP(launch_spread(p, ws, sd, 1, use_v, use_s || use_d, use_d), "spread");
+        VP_HIP(launch_row_fft(p, ws, sd, 1), "row fft");
+        VP_HIP(launch_col_fft(p, ws, sd, 1), "column fft");
+        VP_HIP(launch_row_ifft(p, ws, sd, 1), "row ifft");
+        VP_HIP(launch_interp(p, ws, sd, 1), "interp");
         VP_HIP(hipEventRecord(p.fork[1], sd), "join");
         VP_HIP(launch_spread(p, ws, st, 0, use_v, use_s || use_d, use_d), "spread");
-        VP_HIP(hipStreamWaitEvent(st, p.fork[1], 0), "join");
-        VP_HIP(launch_row_fft(p, ws, st, -1), "row fft");
-        VP_HIP(launch_col_fft(p, ws, st, -1), "column fft");
-        VP_HIP(launch_row_ifft(p, ws, st, -1), "row ifft");
-        VP_HIP(hipEventRecord(p.fork[2], st), "fork");
-        VP_HIP(hipStreamWaitEvent(sd, p.fork[2], 0), "fork");
-        VP_HIP(launch_interp(p, ws, sd, 1), "interp");
-        VP_HIP(hipEventRecord(p.fork[3], sd), "join");
+        VP_HIP(launch_row_fft(p, ws, st, 0), "row fft");
+        VP_HIP(launch_col_fft(p, ws, st, 0), "column fft");
+        VP_HIP(launch_row_ifft(p, ws, st, 0), "row ifft");
         VP_HIP(launch_interp(p, ws, st, 0), "interp");
-        VP_HIP(hipStreamWaitEvent(st, p.fork[3], 0), "join");
+        VP_HIP(hipStreamWaitEvent(st, p.fork[1], 0), "join");
         VP_HIP(launch_local(p, ws, st, jet6, sigma_jet3, mu_jet5, use_v, use_s, use_d, out), "local");
         return VP_OK;
     }
