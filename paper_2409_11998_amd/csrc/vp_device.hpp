@@ -759,28 +759,22 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
             if constexpr (!DL) {
                 // the kernel is even: tap w-1-a at offset u is tap a at -u, so with
                 // tap a's polynomial split as E(u^2) + u O(u^2) one evaluation gives both
-                const double u2 = u * u;
+                // (coefficients uniform across the wavefront: power form, so they stay
+                // in scalar registers; the powers of u^2 serve every pair)
+                double pw[(P + 1) / 2];
+                pw[0] = 1.0;
+                pw[1] = u * u;
+#pragma unroll
+                for (int k = 2; k < (P + 1) / 2; ++k) pw[k] = pw[k - 1] * pw[1];
                 const double sc = axis == 0 ? s_ : 1.0;
-#pragma unroll 2
-                for (int a = 0; a < W / 2; ++a) {
-                    const double* ca = coef + a * P;  // uniform: scalar loads
-                    double e = ca[2 * ((P - 1) / 2)];
 #pragma unroll
-                    for (int k = (P - 1) / 2 - 1; k >= 0; --k) e = fma(e, u2, ca[2 * k]);
-                    double o = ca[2 * ((P - 2) / 2) + 1];
-#pragma unroll
-                    for (int k = (P - 2) / 2 - 1; k >= 0; --k) o = fma(o, u2, ca[2 * k + 1]);
+                for (int a = 0; a < (W + 1) / 2; ++a) {
+                    double va, vm;
+                    tap_pair_pow<P>(coef + a * P, pw, u, va, vm);
                     if (on) {
-                        row[off + a] = (float)(sc * fma(u, o, e));
-                        row[off + W - 1 - a] = (float)(sc * fma(-u, o, e));
+                        row[off + a] = (float)(sc * va);
+                        if (a != W - 1 - a) row[off + W - 1 - a] = (float)(sc * vm);
                     }
-                }
-                if (W & 1) {  // the middle tap
-                    const double* ca = coef + (W / 2) * P;
-                    double v = ca[P - 1];
-#pragma unroll
-                    for (int k = P - 2; k >= 0; --k) v = fma(v, u, ca[k]);
-                    if (on) row[off + W / 2] = (float)(sc * v);
                 }
             }
 #pragma unroll 2
