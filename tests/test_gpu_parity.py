@@ -187,3 +187,17 @@ def test_timed_and_overlapped_evaluations_agree(precision):
     agree = 1e-13 if precision == 1 else 2e-6
     for r in results[1:]:
         assert oracle.rel_linf(r, results[0]) <= agree
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-3), (0, 1e-4), (0, 1e-5), (1, 1e-4), (1, 1e-6), (1, 1e-8)])
+def test_looser_tolerances_narrow_widths(precision, tol):
+    """Looser tolerances plan narrow spreading widths (odd and even, down to the
+    smallest), which the default tolerances never reach; every kind must still
+    meet the tolerance against the oracle."""
+    P = star_problem(2500, seed=41)
+    got, plan = _run(P, "VSD", tol=tol, precision=precision, kinds=7)
+    info = plan.info()
+    ref = oracle.evaluate(P, kinds="VSD")["total"]
+    e = oracle.rel_linf(got, ref)
+    print("precision", precision, "tol", tol, "widths", info["width"], "tiles", info["tile"], "e_inf", e)
+    assert e <= tol
