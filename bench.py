@@ -167,8 +167,8 @@ def run_leg(torch, P, kinds, tol, precision, steps, warmup, oracle_sample, seed)
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--oracle-sample", type=int, default=16384,
                     help="targets of the main workload the CPU oracle evaluates (its timing is the "
                          "cpu_baseline, about 10 s on 16 cores; its values check the GPU result)")
