@@ -766,8 +766,19 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
         // the far-history level's whole chain (spread, FFT passes, interpolation)
         // runs on the side stream beside the near-history level's
         if (!p.side_made) {
-            VP_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking), "side stream");
-            for (auto& e : p.fork) VP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
+            hipStream_t sd = nullptr;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            hipError_t err = hipStreamCreateWithFlags(&sd, hipStreamNonBlocking);
+            if (err == hipSuccess) err = hipEventCreateWithFlags(&e0, hipEventDisableTiming);
+            if (err == hipSuccess) err = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
+            if (err != hipSuccess) {  // release what was made; the next call tries again
+                if (e0) (void)hipEventDestroy(e0);
+                if (sd) (void)hipStreamDestroy(sd);
+                VP_HIP(err, "side stream and events");
+            }
+            p.side = sd;
+            p.fork[0] = e0;
+            p.fork[1] = e1;
             p.side_made = true;
         }
         hipStream_t sd = p.side;
