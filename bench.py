@@ -176,6 +176,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workloads (quick runs)")
     ap.add_argument("--no-batch-leg", action="store_true")
     ap.add_argument("--no-refine-leg", action="store_true")
+    ap.add_argument("--no-geometry-leg", action="store_true")
     ap.add_argument("--refine-levels", type=int, default=3)
     ap.add_argument("--no-serve-leg", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
@@ -267,6 +268,9 @@ def main():
     if not args.no_refine_leg:
         log("bench: dyadic refinement leg, %d levels" % args.refine_levels)
         rec["refine"] = refine_leg(torch, P, args.refine_levels, args.steps, min(64, args.oracle_sample or 64))
+    if not args.no_geometry_leg:
+        log("bench: geometry leg")
+        rec["geometry"] = geometry_leg(torch, P, args.steps, 2000)
     if not args.no_fp32_leg:
         log("bench: generating disk-2M workload")
         Q = config_problem(3, scale=args.scale)
@@ -298,6 +302,44 @@ def main():
         rec["latency_p99_s"] = rec["serve"]["loads"][ref_load]["served"]["p99_s"]
         rec["latency_load"] = float(ref_load)
     print(json.dumps(rec), flush=True)
+
+
+def geometry_leg(torch, P, steps, n_sample):
+    """Local frame and double-layer jets of every target from the boundary panels
+    alone (vp_boundary_frame, vp_boundary_jets) on the square workload; parity
+    of the distance and side against the exact square and the geometry oracle."""
+    from paper_2409_11998_amd import boundary_frame, boundary_jets
+    from oracle import geometry as G
+    q = P.info["q"]
+    f64 = torch.float64
+    bx, by = (torch.as_tensor(a, dtype=f64, device="cuda") for a in (P.bnd_x, P.bnd_y))
+    tx, ty = (torch.as_tensor(a, dtype=f64, device="cuda") for a in (P.tgt_x, P.tgt_y))
+    mu = torch.as_tensor(P.mu, dtype=f64, device="cuda")
+    fr = {}
+    frame = lambda: fr.update(boundary_frame(bx, by, q, tx, ty))
+    jets = lambda: boundary_jets(bx, by, q, mu, fr["pan"], fr["u"], 4)
+    for _ in range(3):
+        frame()
+        jets()
+    el_f = time_steps(torch, frame, steps)
+    el_j = time_steps(torch, jets, steps)
+    r = fr["r"].cpu().numpy()
+    sgn = fr["sgn"].cpu().numpy()
+    rng = np.random.default_rng(41)
+    idx = np.sort(rng.choice(P.n_tgt, size=min(n_sample, P.n_tgt), replace=False))
+    ref = G.boundary_frame(P.bnd_x, P.bnd_y, q, P.tgt_x[idx], P.tgt_y[idx])
+    return {"workload": "square-200k targets (%d) against %d boundary nodes in %d panels of %d" %
+                        (P.n_tgt, P.n_bnd, P.n_bnd // q, q),
+            "frame_ms": round(1e3 * el_f / steps, 4), "jets4_ms": round(1e3 * el_j / steps, 4),
+            "targets_per_s": round(P.n_tgt * steps / el_f, 1),
+            "max_abs_r_vs_exact": float(np.max(np.abs(r - np.asarray(P.geom["r"])))),
+            # the workload labels targets on the curve (mesh nodes on the square's edges)
+            # with their interior limit +1; the frame reports them as on the curve, 0
+            "sgn_differs_from_exact": int(np.count_nonzero(sgn != np.asarray(P.geom["sgn"]))),
+            "sgn_differs_only_on_curve": bool(np.all(np.asarray(P.geom["r"])[sgn != np.asarray(P.geom["sgn"])] == 0.0)
+                                              and np.all(sgn[sgn != np.asarray(P.geom["sgn"])] == 0)),
+            "max_abs_r_vs_oracle_sample": float(np.max(np.abs(r[idx] - ref["r"]))),
+            "sgn_matches_oracle_sample": bool(np.array_equal(sgn[idx], ref["sgn"])), "sample": int(idx.size)}
 
 
 def refine_leg(torch, P, levels, steps, n_sample):

@@ -197,6 +197,50 @@ vp_status vp_refine_attach(vp_plan_t plan, int levels, int64_t n_fine, const dou
 vp_status vp_layer_refine(vp_plan_t plan, const double* sigma_jet3, const double* fine_sigma,
                           const double* mu_jet5, const double* fine_mu, double* out);
 
+/* ------------------------------------------------------------------------
+ * Local frame and layer-density jets from a boundary given as panels.  The
+ * local expansions of Sec. 4 need, per target, its closest boundary point b,
+ * the distance r, the side, the outward normal and the curve's derivatives as
+ * a graph over its tangent line at b (kappa, gamma3, gamma4: the second to
+ * fourth derivatives), and the layer densities' derivatives along that line;
+ * the paper leaves them to a geometry preprocessing step.  These two calls
+ * compute them from the boundary nodes alone, for vp_plan's vp_local_geom and
+ * vp_eval's jets.
+ *
+ * Boundary: n_pan >= 2 panels in order along the curve, counter-clockwise
+ * (interior on the left), each with q nodes (5 <= q <= 32) at the
+ * Gauss-Legendre points of its own parameter u in [-1, 1], ascending: node j
+ * of panel p at bnd_x[p*q + j], bnd_y[p*q + j] (device, float64).  On a panel
+ * each coordinate or density is its degree q-1 interpolant in u.
+ *
+ * vp_boundary_frame: per target (tgt_x, tgt_y: device, n_tgt), the closest
+ * point b on the interpolated curve -- nearest node, then Newton on its panel,
+ * continuing on the neighbouring panel when u leaves [-1, 1] (the closest point
+ * for targets within the curve's local radius of curvature, a stationary
+ * point of the distance at least as far otherwise) -- and at b:
+ *   r, nx/ny (outward normal), kappa, gamma3, gamma4 (may be NULL), sgn (+1
+ *   inside, -1 outside, 0 when r <= 1e-12 |x'(u)|, i.e. on the curve), and
+ *   pan[i], u[i]: the panel and parameter of b, for vp_boundary_jets.
+ * All outputs are device arrays of n_tgt.  Fourth derivatives of the
+ * interpolant carry the nodal coordinates' rounding amplified near panel ends
+ * (about 1e-5 relative in gamma4 on strongly curved boundaries).
+ *
+ * vp_boundary_jets: d^k s / d xi^k (k = 0..nder, nder <= 4) at each target's
+ * b of a density s given at the nodes (dens, device, n_pan*q), xi along the
+ * counter-clockwise tangent at b: out[k*n_tgt + i] -- the sigma_jet3 (nder =
+ * 2) and mu_jet5 (nder = 4) layouts of vp_eval.  pan, u from
+ * vp_boundary_frame (a pan outside [0, n_pan) gives NaN jets).
+ *
+ * Both enqueue on stream (a hipStream_t; NULL: the null stream), allocate
+ * stream-ordered scratch of 3 n_pan q doubles, and return VP_ERR_ARG for q or
+ * n_pan out of range and NULL arrays (n_tgt = 0 is a no-op). */
+vp_status vp_boundary_frame(int64_t n_pan, int q, const double* bnd_x, const double* bnd_y, int64_t n_tgt,
+                            const double* tgt_x, const double* tgt_y, double* r, double* nx, double* ny,
+                            double* kappa, double* gamma3, double* gamma4, int8_t* sgn, int32_t* pan, double* u,
+                            void* stream);
+vp_status vp_boundary_jets(int64_t n_pan, int q, const double* bnd_x, const double* bnd_y, const double* dens,
+                           int64_t n_tgt, const int32_t* pan, const double* u, int nder, double* out, void* stream);
+
 /* Release the plan and its device memory (synchronizes its stream). NULL is a no-op. */
 vp_status vp_destroy(vp_plan_t plan);
 

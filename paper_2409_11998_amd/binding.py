@@ -21,7 +21,8 @@ EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "v
             "vp_last_error", "vp_get_plan_info", "vp_set_timing", "vp_get_timing",
             "vp_batch_create", "vp_batch_eval", "vp_batch_destroy", "vp_batch_last_error",
             "vp_server_create", "vp_server_submit", "vp_server_poll", "vp_server_wait", "vp_server_get_stats",
-            "vp_server_destroy", "vp_server_last_error", "vp_refine_attach", "vp_layer_refine"]
+            "vp_server_destroy", "vp_server_last_error", "vp_refine_attach", "vp_layer_refine",
+            "vp_boundary_frame", "vp_boundary_jets"]
 
 
 class VPError(RuntimeError):
@@ -111,6 +112,10 @@ def lib():
         L.vp_refine_attach.restype = ctypes.c_int
         L.vp_layer_refine.argtypes = [vp] * 6
         L.vp_layer_refine.restype = ctypes.c_int
+        L.vp_boundary_frame.argtypes = [i64, ctypes.c_int, vp, vp, i64] + [vp] * 11 + [vp]
+        L.vp_boundary_frame.restype = ctypes.c_int
+        L.vp_boundary_jets.argtypes = [i64, ctypes.c_int, vp, vp, vp, i64, vp, vp, ctypes.c_int, vp, vp]
+        L.vp_boundary_jets.restype = ctypes.c_int
         L.vp_destroy.argtypes = [vp]
         L.vp_destroy.restype = ctypes.c_int
         L.vp_last_error.argtypes = []
@@ -406,3 +411,42 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def boundary_frame(bnd_x, bnd_y, q, tgt_x, tgt_y):
+    """Local frame of each target from a boundary of Gauss-Legendre panels
+    (vp_boundary_frame): dict of device tensors r, nx, ny, kappa, gamma3,
+    gamma4 (float64), sgn (int8), pan (int32), u (float64)."""
+    import torch
+    f64 = torch.float64
+    nb, n = bnd_x.numel(), tgt_x.numel()
+    if q <= 0 or nb % q:
+        raise ValueError("the boundary must hold whole panels of q nodes")
+    dev = tgt_x.device
+    out = {k: torch.empty(n, dtype=f64, device=dev) for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "u")}
+    out["sgn"] = torch.empty(n, dtype=torch.int8, device=dev)
+    out["pan"] = torch.empty(n, dtype=torch.int32, device=dev)
+    _check(lib().vp_boundary_frame(nb // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64), n, _ptr(tgt_x, f64),
+                                   _ptr(tgt_y, f64), _ptr(out["r"]), _ptr(out["nx"]), _ptr(out["ny"]),
+                                   _ptr(out["kappa"]), _ptr(out["gamma3"]), _ptr(out["gamma4"]), _ptr(out["sgn"]),
+                                   _ptr(out["pan"]), _ptr(out["u"]), _stream(tgt_x)))
+    return out
+
+
+def boundary_jets(bnd_x, bnd_y, q, dens, pan, u, nder):
+    """d^k dens / d xi^k, k = 0..nder, at each target's closest boundary point
+    (vp_boundary_jets): device tensor [nder + 1, n_tgt]."""
+    import torch
+    f64 = torch.float64
+    nb, n = bnd_x.numel(), pan.numel()
+    if q <= 0 or nb % q:
+        raise ValueError("the boundary must hold whole panels of q nodes")
+    out = torch.empty((nder + 1, n), dtype=f64, device=pan.device)
+    _check(lib().vp_boundary_jets(nb // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64), _ptr(dens, f64), n,
+                                  _ptr(pan, torch.int32), _ptr(u, f64), nder, _ptr(out), _stream(pan)))
+    return out

@@ -1,0 +1,158 @@
+"""GPU parity of vp_boundary_frame / vp_boundary_jets (local frame and layer
+jets from Gauss-Legendre panels) against the geometry oracle, the exact circle
+frame, and the whole evaluation run on panel-derived geometry."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import geometry as G
+from workloads import star_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def _t(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def _frame(torch, bx, by, q, tx, ty):
+    from paper_2409_11998_amd import boundary_frame
+    fr = boundary_frame(_t(torch, bx), _t(torch, by), q, _t(torch, tx), _t(torch, ty))
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in fr.items()}
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("seed", [4, 9])
+def test_frames_and_jets_match_oracle(seed):
+    torch = _gpu()
+    from paper_2409_11998_amd import boundary_jets
+    P = star_problem(3000, seed=seed)
+    q = P.info["q"]
+    rng = np.random.default_rng(seed)
+    near = np.flatnonzero(P.info["near_mask"])
+    far = np.flatnonzero(~P.info["near_mask"])
+    pick = np.concatenate([rng.choice(near, 600, replace=False), rng.choice(far, min(200, far.size), replace=False)])
+    # targets: volume nodes near and far, boundary nodes themselves (on the curve), points outside
+    k = rng.integers(0, P.n_bnd, 100)
+    out_x = P.bnd_x[k] + 0.02 * P.bnd_nx[k]
+    out_y = P.bnd_y[k] + 0.02 * P.bnd_ny[k]
+    tx = np.concatenate([P.tgt_x[pick], P.bnd_x[k[:50]], out_x])
+    ty = np.concatenate([P.tgt_y[pick], P.bnd_y[k[:50]], out_y])
+    got = _frame(torch, P.bnd_x, P.bnd_y, q, tx, ty)
+    ref = G.boundary_frame(P.bnd_x, P.bnd_y, q, tx, ty)
+    print("seed", seed, "r", np.max(np.abs(got["r"] - ref["r"])), "kappa", _rel(got["kappa"], ref["kappa"]),
+          "gamma3", _rel(got["gamma3"], ref["gamma3"]), "gamma4", _rel(got["gamma4"], ref["gamma4"]))
+    assert np.array_equal(got["sgn"], ref["sgn"])
+    assert np.all(got["sgn"][len(pick):len(pick) + 50] == 0)
+    assert np.all(got["sgn"][len(pick) + 50:] == -1)
+    assert np.max(np.abs(got["r"] - ref["r"])) <= 1e-13
+    assert np.max(np.abs(got["nx"] - ref["nx"])) <= 1e-10
+    assert np.max(np.abs(got["ny"] - ref["ny"])) <= 1e-10
+    # both sides differentiate the same interpolant from coefficients computed
+    # two ways (discrete transform / least squares): the derivatives differ by
+    # rounding amplified as in the oracle's own pins
+    assert _rel(got["kappa"], ref["kappa"]) <= 1e-8
+    assert _rel(got["gamma3"], ref["gamma3"]) <= 1e-5
+    assert _rel(got["gamma4"], ref["gamma4"]) <= 1e-3
+    # the same closest point (a point at a panel end may be found from either
+    # panel); far from the curve the distance is flat along it to second order,
+    # so u is settled less tightly than r
+    same = (got["pan"] == ref["pan"])
+    assert np.max(np.abs(got["u"][same] - ref["u"][same])) <= 1e-9
+    assert np.mean(same) >= 0.99
+    pan_t = _t(torch, got["pan"], torch.int32)
+    u_t = _t(torch, got["u"])
+    bx, by = _t(torch, P.bnd_x), _t(torch, P.bnd_y)
+    sj = boundary_jets(bx, by, q, _t(torch, P.sigma), pan_t, u_t, 2).cpu().numpy()
+    mj = boundary_jets(bx, by, q, _t(torch, P.mu), pan_t, u_t, 4).cpu().numpy()
+    rs = G.density_jets(P.bnd_x, P.bnd_y, q, P.sigma, got["pan"], got["u"], 2)
+    rm = G.density_jets(P.bnd_x, P.bnd_y, q, P.mu, got["pan"], got["u"], 4)
+    for kk, tol in enumerate((1e-12, 1e-10, 1e-7)):
+        assert _rel(sj[kk], rs[kk]) <= tol, (kk, _rel(sj[kk], rs[kk]))
+    for kk, tol in enumerate((1e-12, 1e-10, 1e-7, 1e-5, 1e-3)):
+        assert _rel(mj[kk], rm[kk]) <= tol, (kk, _rel(mj[kk], rm[kk]))
+
+
+def test_circle_frame_is_exact_on_device():
+    torch = _gpu()
+    from numpy.polynomial.legendre import leggauss
+    R, c, q, n_pan = 1.3, (0.2, -0.1), 16, 24
+    xg, _ = leggauss(q)
+    e = np.linspace(0, 2 * np.pi, n_pan + 1)
+    t = (0.5 * (e[:-1, None] + e[1:, None]) + 0.5 * (e[1:, None] - e[:-1, None]) * xg[None]).ravel()
+    bx, by = c[0] + R * np.cos(t), c[1] + R * np.sin(t)
+    rng = np.random.default_rng(3)
+    ang = rng.uniform(0, 2 * np.pi, 500)
+    rad = R * np.concatenate([rng.uniform(0.2, 0.999, 250), rng.uniform(1.001, 2.0, 250)])
+    tx, ty = c[0] + rad * np.cos(ang), c[1] + rad * np.sin(ang)
+    fr = _frame(torch, bx, by, q, tx, ty)
+    d = np.hypot(tx - c[0], ty - c[1])
+    assert np.max(np.abs(fr["r"] - np.abs(R - d))) <= 1e-13
+    assert np.array_equal(fr["sgn"], np.where(d < R, 1, -1))
+    assert np.max(np.abs(fr["kappa"] - 1 / R)) <= 1e-9
+    assert np.max(np.abs(fr["gamma3"])) <= 2e-6
+    assert np.max(np.abs(fr["gamma4"] - 3 / R ** 3)) <= 2e-4
+
+
+def test_evaluation_on_panel_geometry():
+    """vp_eval with the local frame and layer jets from the boundary calls
+    matches the oracle evaluated on the analytic geometry (float64: the bound
+    of the panel geometry itself, see the oracle pin; float32: its tolerance)."""
+    torch = _gpu()
+    from paper_2409_11998_amd import boundary_jets
+    from workloads.device import make_plan, run, to_device
+    P = star_problem(1500, seed=6)
+    q = P.info["q"]
+    ref = oracle.evaluate(P, kinds="VSD")["total"]
+    dev = to_device(P)
+    fr = _frame(torch, P.bnd_x, P.bnd_y, q, P.tgt_x, P.tgt_y)
+    for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4"):
+        dev["geom"][k] = _t(torch, fr[k])
+    dev["geom"]["sgn"] = _t(torch, fr["sgn"], torch.int8)
+    pan_t, u_t = _t(torch, fr["pan"], torch.int32), _t(torch, fr["u"])
+    dev["sigma_jet"] = boundary_jets(dev["bnd_x"], dev["bnd_y"], q, dev["sigma"], pan_t, u_t, 2).contiguous()
+    dev["mu_jet"] = boundary_jets(dev["bnd_x"], dev["bnd_y"], q, dev["mu"], pan_t, u_t, 4).contiguous()
+    for precision, tol in ((1, 5e-9), (0, 1e-6)):
+        plan = make_plan(dev, tol=1e-10 if precision else 1e-6, precision=precision, kinds=7)
+        out = run(plan, dev, "VSD")
+        torch.cuda.synchronize()
+        e = oracle.rel_linf(out.cpu().numpy(), ref)
+        print("precision", precision, "panel geometry e_inf", e)
+        assert e <= tol
+        plan.close()
+
+
+def test_argument_errors():
+    torch = _gpu()
+    from paper_2409_11998_amd import boundary_frame, boundary_jets
+    from paper_2409_11998_amd.binding import VP_ERR_ARG, VPError
+    bx = torch.zeros(16, dtype=torch.float64, device="cuda")
+    t = torch.zeros(3, dtype=torch.float64, device="cuda")
+    with pytest.raises(VPError) as ei:
+        boundary_frame(bx, bx, 4, t, t)          # q below 5
+    assert ei.value.status == VP_ERR_ARG
+    with pytest.raises(VPError):
+        boundary_frame(bx, bx, 16, t, t)         # a single panel
+    pan = torch.zeros(3, dtype=torch.int32, device="cuda")
+    with pytest.raises(VPError):
+        boundary_jets(torch.zeros(32, dtype=torch.float64, device="cuda"),
+                      torch.zeros(32, dtype=torch.float64, device="cuda"), 16,
+                      torch.zeros(32, dtype=torch.float64, device="cuda"), pan, t, 5)   # nder above 4
+    # no targets: nothing to do
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    P = star_problem(600, seed=2)
+    fr = boundary_frame(torch.as_tensor(P.bnd_x, device="cuda"), torch.as_tensor(P.bnd_y, device="cuda"),
+                        P.info["q"], e, e)
+    torch.cuda.synchronize()
+    assert fr["r"].numel() == 0
