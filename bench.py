@@ -336,7 +336,7 @@ def geometry_leg(torch, P, steps, n_sample):
             # the workload labels targets on the curve (mesh nodes on the square's edges)
             # with their interior limit +1; the frame reports them as on the curve, 0
             "sgn_differs_from_exact": int(np.count_nonzero(sgn != np.asarray(P.geom["sgn"]))),
-            "sgn_differs_only_on_curve": bool(np.all(np.asarray(P.geom["r"])[sgn != np.asarray(P.geom["sgn"])] == 0.0)
+            "sgn_differs_only_on_curve": bool(np.all(np.asarray(P.geom["r"])[sgn != np.asarray(P.geom["sgn"])] <= 1e-12)
                                               and np.all(sgn[sgn != np.asarray(P.geom["sgn"])] == 0)),
             "max_abs_r_vs_oracle_sample": float(np.max(np.abs(r[idx] - ref["r"]))),
             "sgn_matches_oracle_sample": bool(np.array_equal(sgn[idx], ref["sgn"])), "sample": int(idx.size)}

@@ -181,9 +181,13 @@ __global__ __launch_bounds__(kGeomThreads) void k_frame(FrameArgs a)
         __syncthreads();
         for (int k = threadIdx.x; k < 3 * nt; k += blockDim.x) sc[k] = a.circ[3 * p0 + k];
         __syncthreads();
-        for (int k = 0; k < nt; ++k) U = fmin(U, hypot(px - sc[3 * k], py - sc[3 * k + 1]) + sc[3 * k + 2]);
+        for (int k = 0; k < nt; ++k) {
+            const double ex = px - sc[3 * k], ey = py - sc[3 * k + 1];
+            U = fmin(U, sqrt(ex * ex + ey * ey) + sc[3 * k + 2]);
+        }
     }
-    // pass 2: nodes of the panels whose circle comes within U (lowest index on ties)
+    // pass 2: nodes of the panels whose circle comes within U (lowest index on
+    // ties), on squared distances
     double best = INFINITY;
     int64_t jbest = 0;
     for (int64_t p0 = 0; p0 < a.n_pan; p0 += kPanTile) {
@@ -192,10 +196,12 @@ __global__ __launch_bounds__(kGeomThreads) void k_frame(FrameArgs a)
         for (int k = threadIdx.x; k < 3 * nt; k += blockDim.x) sc[k] = a.circ[3 * p0 + k];
         __syncthreads();
         for (int k = 0; k < nt; ++k) {
-            if (!on || hypot(px - sc[3 * k], py - sc[3 * k + 1]) - sc[3 * k + 2] > U) continue;
+            const double ex = px - sc[3 * k], ey = py - sc[3 * k + 1], reach = U + sc[3 * k + 2];
+            if (!on || ex * ex + ey * ey > reach * reach) continue;
             const int64_t jb = (p0 + k) * a.q;
             for (int j = 0; j < a.q; ++j) {
-                const double d = hypot(px - a.bx[jb + j], py - a.by[jb + j]);
+                const double dx0 = px - a.bx[jb + j], dy0 = py - a.by[jb + j];
+                const double d = dx0 * dx0 + dy0 * dy0;
                 if (d < best) {
                     best = d;
                     jbest = jb + j;
