@@ -127,7 +127,7 @@ def test_panel_geometry_serves_the_method_at_fp64_tolerance():
     """The whole evaluation (history + local parts of V, S, D) with frames and
     layer jets taken from the panels agrees with the one from the analytic
     curve: the layer jets are float64-grade, and the curve's fourth derivative,
-    which the double layer's delta^2 term uses, is limited by the nodal
+    which the double layer's local part uses, is limited by the nodal
     coordinates' rounding amplified by the panel interpolant (finer panels
     amplify it more): ~1.5e-9 on this lobed star (gamma4 up to 7e3)."""
     import copy
