@@ -150,6 +150,7 @@ vp_status vp_plan(vp_plan_t* out,
  *   mu_jet5    [5][n_tgt]  mu, mu', mu'', mu''', mu'''' at b (same parametrization);
  *                          required with mu
  *   out        [n_tgt]     float64 result (sum of the requested potentials)
+ * (The jets and out are per target: with n_tgt = 0 they may be NULL.)
  * Enqueues on the plan's stream and returns. */
 vp_status vp_eval(vp_plan_t plan, const double* f_src, const double* jet6,
                   const double* sigma, const double* sigma_jet3,

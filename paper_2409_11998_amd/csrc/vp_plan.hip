@@ -741,9 +741,10 @@ vp_status eval_validate(const Plan& p, const double* f, const double* jet6, cons
     if (use_v && !(p.kinds & VP_KIND_V)) return fail(VP_ERR_ARG, "plan does not support V");
     if (use_s && !(p.kinds & VP_KIND_S)) return fail(VP_ERR_ARG, "plan does not support S");
     if (use_d && !(p.kinds & VP_KIND_D)) return fail(VP_ERR_ARG, "plan does not support D");
-    if (use_v && !jet6) return fail(VP_ERR_ARG, "jet6 is required with f");
-    if (use_s && !sigma_jet3) return fail(VP_ERR_ARG, "sigma_jet3 is required with sigma");
-    if (use_d && !mu_jet5) return fail(VP_ERR_ARG, "mu_jet5 is required with mu");
+    // the jets are per target: with no targets they may be NULL
+    if (use_v && !jet6 && p.n_tgt) return fail(VP_ERR_ARG, "jet6 is required with f");
+    if (use_s && !sigma_jet3 && p.n_tgt) return fail(VP_ERR_ARG, "sigma_jet3 is required with sigma");
+    if (use_d && !mu_jet5 && p.n_tgt) return fail(VP_ERR_ARG, "mu_jet5 is required with mu");
     return VP_OK;
 }
 
