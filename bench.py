@@ -260,7 +260,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": workload, "n_src": P.n_src, "n_bnd": P.n_bnd, "n_tgt": P.n_tgt,
                       "fine_grid": list(r64["info"]["fine"]), "modes": list(r64["info"]["modes"]),
-                      "spread_width": list(r64["info"]["width"]), "tile": list(r64["info"]["tile"]), "spread_mma": list(r64["info"]["spread_mma"]),
+                      "spread_width": list(r64["info"]["width"]), "tile": list(r64["info"]["tile"]), "interp_tile": list(r64["info"]["interp_tile"]),
+                      "spread_mma": list(r64["info"]["spread_mma"]),
                       "autotuned": r64["info"]["autotuned"], "tol": 1e-10},
            "roofline": roof, "cpu_baseline": cpu,
            "stages_ms": {k: round(v, 4) for k, v in st.items()}, "stages_gbs": stages_gbs,
@@ -283,7 +284,8 @@ def main():
                        "value": round(Q.n_tgt * args.steps / r32["elapsed"], 1), "unit": "target pts/s",
                        "ms_per_step": round(1000.0 * r32["elapsed"] / args.steps, 4),
                        "fine_grid": list(r32["info"]["fine"]), "spread_width": list(r32["info"]["width"]),
-                       "tile": list(r32["info"]["tile"]), "spread_mma": list(r32["info"]["spread_mma"]),
+                       "tile": list(r32["info"]["tile"]), "interp_tile": list(r32["info"]["interp_tile"]),
+                       "spread_mma": list(r32["info"]["spread_mma"]),
                        "stages_ms": {k: round(v, 4) for k, v in st32.items()},
                        "stages_gbs": {k: round(alg32[k] / (st32[k] * 1e-3) / 1e9, 1) for k in LAUNCHES
                                       if st32.get(k, 0) > 0},

@@ -273,6 +273,8 @@ typedef struct {
     int interp_terms[2];  /* terms of the values-only polynomials used in interpolation        */
     double spread_fit_err[2]; /* sampled max |polynomial - kernel| of the spreading table      */
     double interp_fit_err[2]; /* the same for the interpolation table                          */
+    int interp_tile[2];   /* tile edge the targets are binned on for interpolation (autotune may
+                             choose it apart from the spreading tile)                          */
 } vp_plan_info;
 
 /* Fill info (host pointer) with the plan's parameters. */

@@ -81,7 +81,8 @@ class VPPlanInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
                 ("autotuned", ctypes.c_int), ("tune_candidates", ctypes.c_int * 2), ("level_ms", ctypes.c_double * 2),
                 ("spread_terms", ctypes.c_int * 2), ("interp_terms", ctypes.c_int * 2),
-                ("spread_fit_err", ctypes.c_double * 2), ("interp_fit_err", ctypes.c_double * 2)]
+                ("spread_fit_err", ctypes.c_double * 2), ("interp_fit_err", ctypes.c_double * 2),
+                ("interp_tile", ctypes.c_int * 2)]
 
 
 _lib = None
@@ -278,7 +279,8 @@ class Plan:
                     workspace_bytes=i.workspace_bytes, autotuned=bool(i.autotuned),
                     tune_candidates=tuple(i.tune_candidates), level_ms=tuple(i.level_ms),
                     spread_terms=tuple(i.spread_terms), interp_terms=tuple(i.interp_terms),
-                    spread_fit_err=tuple(i.spread_fit_err), interp_fit_err=tuple(i.interp_fit_err))
+                    spread_fit_err=tuple(i.spread_fit_err), interp_fit_err=tuple(i.interp_fit_err),
+                    interp_tile=tuple(i.interp_tile))
 
     def set_timing(self, on=True):
         _check(lib().vp_set_timing(self.handle, 1 if on else 0))

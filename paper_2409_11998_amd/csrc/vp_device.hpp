@@ -1004,7 +1004,7 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
     const int r0 = unit.a0;
     const int r1 = unit.a1;
     if (r0 == r1) return;
-    const int T = g.T;
+    const int T = g.Ti;
     const int E = T + W - 1;
     const int F = g.F;
     R* reg = reinterpret_cast<R*>(smem_raw);
@@ -1012,8 +1012,8 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
     const int wv = threadIdx.x >> 6;
     R* vals = reinterpret_cast<R*>(smem_raw + (((size_t)(E + 1) * E * sizeof(R) + 15) & ~(size_t)15)) +
               (size_t)wv * (NT * VS);
-    const int gx0 = (t % g.ntx) * T;
-    const int gy0 = (t / g.ntx) * T;
+    const int gx0 = (t % g.ntxi) * T;
+    const int gy0 = (t / g.ntxi) * T;
     // window rows 0..E-1 from the grid, row E zero (32 lanes per row, no division)
     for (int y = threadIdx.x >> 5; y <= E; y += blockDim.x >> 5) {
         const int gy = gy0 + y;

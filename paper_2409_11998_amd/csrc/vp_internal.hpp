@@ -56,6 +56,7 @@ struct LevelGeom {
     double dmax;    // max over taps and offsets of |d/dy tap value| (double-layer spreading bound)
     double fit_err[2]; // sampled max |polynomial - kernel| of the spreading and interpolation tables
     int mma;        // spread on matrix cores (float32 plans on kMmaTile tiles), else LDS atomics
+    int Ti, ntxi;   // interpolation tile edge and tiles per dimension (targets are binned on their own tiles)
 };
 
 // A tile-sorted list of points of one level (CSR by tile): each point appears

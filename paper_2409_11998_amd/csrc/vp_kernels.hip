@@ -186,7 +186,7 @@ hipError_t launch_zero(const Plan& p, const Workspace& ws, hipStream_t st)
 
 size_t interp_lds_bytes_of(const Plan& p, int level)
 {
-    return interp_lds_bytes(p.lv[level].T, p.lv[level].w, p.precision == VP_FP32 ? sizeof(float) : sizeof(double));
+    return interp_lds_bytes(p.lv[level].Ti, p.lv[level].w, p.precision == VP_FP32 ? sizeof(float) : sizeof(double));
 }
 
 size_t spread_lds_bytes(const Plan& p, int level)
@@ -335,7 +335,7 @@ static void interp_launch(const Plan& p, const Workspace& ws, hipStream_t st, in
 {
     const LevelGeom& g = p.lv[l];
     const LevelBufs& b = p.lb[l];
-    const size_t lds = interp_lds_bytes(g.T, W, sizeof(R));
+    const size_t lds = interp_lds_bytes(g.Ti, W, sizeof(R));
     const unsigned nu = (unsigned)b.h_in_units.size();
     if (nu == 0) return;
     hipLaunchKernelGGL((k_interp<R, W>), dim3(nu), dim3(kThreads), lds, st, g, (const R*)ws.grid[l],

@@ -252,10 +252,10 @@ void free_plan(vp_plan_s* p)
 // different LDS banks.
 template <typename R>
 vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std::vector<double>& y,
-                        const std::vector<int>& ids, RecList* list, int pitch = 0)
+                        const std::vector<int>& ids, RecList* list, int pitch = 0, int tile = 0)
 {
     const LevelGeom& g = p.lv[l];
-    const int T = g.T, ntx = g.ntx, w = g.w;
+    const int T = tile > 0 ? tile : g.T, ntx = g.F / T, w = g.w;
     const int ntiles = ntx * ntx;
     const size_t n = ids.size();
     std::vector<int> i0(n), j0(n);
@@ -396,7 +396,7 @@ vp_status build_units(Plan& p, int l)
         return best;
     };
     for (int t = 0; t < ntiles; ++t) {
-        const int nv = cnt_of(b.vol, t), nb = cnt_of(b.bnd, t), nt = cnt_of(b.tgt, t);
+        const int nv = cnt_of(b.vol, t), nb = cnt_of(b.bnd, t);
         const int ku = std::max((nv + kUnitNodes - 1) / kUnitNodes, (nb + kUnitBnd - 1) / kUnitBnd);
         for (int k = 0; k < ku; ++k) {
             WorkUnit u;
@@ -408,6 +408,11 @@ vp_status build_units(Plan& p, int l)
             u.cover = cover_of(t, u.a0, u.a1, u.b0, u.b1);
             b.h_sp_units.push_back(u);
         }
+    }
+    // targets on the interpolation's own tiles
+    const int ntiles_i = p.lv[l].ntxi * p.lv[l].ntxi;
+    for (int t = 0; t < ntiles_i; ++t) {
+        const int nt = cnt_of(b.tgt, t);
         for (int k = 0; k * kUnitTargets < nt; ++k) {
             WorkUnit u;
             u.tile = t;
@@ -543,10 +548,20 @@ vp_status build_level(Plan& p, int l, const std::vector<double>& sxv, const std:
     LevelBufs& b = p.lb[l];
     if ((s = build_records<R>(p, l, sxv, syv, vol_ids, &b.vol)) != VP_OK) return s;
     if ((s = build_records<R>(p, l, sxv, syv, bnd_ids, &b.bnd)) != VP_OK) return s;
-    if ((s = build_records<R>(p, l, tx, ty, tids, &b.tgt, p.lv[l].T + p.lv[l].w - 1)) != VP_OK) return s;
+    if ((s = build_records<R>(p, l, tx, ty, tids, &b.tgt, p.lv[l].Ti + p.lv[l].w - 1, p.lv[l].Ti)) != VP_OK) return s;
     if ((s = build_units(p, l)) != VP_OK) return s;
     if ((s = build_level_tables<R>(p, l, phihat, p.delta1, p.delta2)) != VP_OK) return s;
     return VP_OK;
+}
+
+// Give the interpolation its own tile edge (a divisor of the grid): false if none.
+bool set_interp_tile(LevelGeom& g, int Ti)
+{
+    while (Ti > g.F) Ti /= 2;
+    if (Ti < 1 || g.F % Ti) return false;
+    g.Ti = Ti;
+    g.ntxi = g.F / Ti;
+    return true;
 }
 
 // A feasible discretization of one level.
@@ -577,6 +592,8 @@ vp_status set_level_geom(Plan& p, int l, const LevelCand& c, int T, double cx, d
     if (T < 1 || c.F % T) return fail(VP_ERR_ARG, "tile must divide the fine grid");
     g.T = T;
     g.ntx = c.F / T;
+    g.Ti = T;
+    g.ntxi = g.ntx;
     g.mma = (p.precision == VP_FP32 && T == kMmaTile) ? 1 : 0;
     phihat = kernel_ft(c.w, g.beta, c.F, c.M);
     for (double v : phihat)
@@ -1127,7 +1144,27 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
             }
         }
         if (best_c < 0) return bail(fail(VP_ERR_TOL, "working set too large for LDS"));
+        int best_Ti = 0;
+        if (o.autotune) {
+            // the interpolation's own tile: the chosen level timed again with each other tile
+            for (int Ti : tiles) {
+                if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy, ph)) != VP_OK) return bail(s);
+                if (Ti == p->lv[l].T || !set_interp_tile(p->lv[l], Ti) || !level_fits_lds(*p, l)) continue;
+                const size_t mark = p->allocs.size(), bytes0 = p->device_bytes;
+                if ((s = build(l, ph)) != VP_OK) return bail(s);
+                double ms = INFINITY;
+                s = time_level(*p, l, &ms);
+                drop_level(*p, l, mark, bytes0);
+                if (s != VP_OK) return bail(s);
+                p->tune_cands[l]++;
+                if (ms < p->level_ms[l]) {
+                    p->level_ms[l] = ms;
+                    best_Ti = p->lv[l].Ti;
+                }
+            }
+        }
         if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy, ph)) != VP_OK) return bail(s);
+        if (best_Ti > 0) set_interp_tile(p->lv[l], best_Ti);
         if ((s = build(l, ph)) != VP_OK) return bail(s);
     }
     if (!o.no_workspace) {
@@ -1195,6 +1232,7 @@ vp_status vp_get_plan_info(vp_plan_t p, vp_plan_info* info)
     for (int l = 0; l < 2; ++l) {
         info->tile[l] = p->lv[l].T;
         info->spread_mma[l] = p->lv[l].mma;
+        info->interp_tile[l] = p->lv[l].Ti;
         info->spread_terms[l] = horner_terms(p->lv[l].w);
         info->interp_terms[l] = interp_terms(p->lv[l].w, p->precision == VP_FP32);
         info->spread_fit_err[l] = p->lv[l].fit_err[0];
