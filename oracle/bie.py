@@ -1,0 +1,95 @@
+"""Oracle: the interior Dirichlet problem for the Laplace equation by a
+double-layer representation (the boundary integral solve of Sec. 5, whose
+matrix-vector product is the layer potential evaluated on the boundary).
+
+Test infrastructure only: plain numpy in float64 (dense operator, direct
+solve).  Nothing here is imported by the product path.
+
+u = D[mu] is harmonic inside; its interior limit on the boundary is
+D_int[mu] = -mu/2 + (principal value of D[mu]), so the boundary condition
+u = g on the boundary is the second-kind equation D_int[mu] = g.  Here D_int
+at a boundary node is what the method computes for a target at that node with
+r = 0 and sgn = +1 (history part plus the local part's interior limit), the
+density's jets at the node coming from its panel interpolant
+(oracle.geometry).  The operator is linear in mu, so its matrix is assembled
+column by column from unit densities and the system is solved directly.
+"""
+import copy
+
+import numpy as np
+
+from . import geometry as G
+from .potential import delta1_of, evaluate
+
+
+class _Layer:
+    """Boundary nodes, targets with their frames and the layer densities: the
+    fields oracle.potential.evaluate reads (no volume nodes)."""
+
+    def __init__(self, bx, by, bnx, bny, bw, tx, ty, geom, mu=None, mu_jet=None, info=None):
+        e = np.zeros(0)
+        self.src_x = self.src_y = self.src_w = e
+        self.f_src = self.jet6 = self.sigma = self.sigma_jet = None
+        self.bnd_x, self.bnd_y, self.bnd_nx, self.bnd_ny, self.bnd_w = bx, by, bnx, bny, bw
+        self.tgt_x, self.tgt_y, self.geom = tx, ty, geom
+        self.mu, self.mu_jet = mu, mu_jet
+        self.info = info or {}
+
+    n_src = property(lambda self: 0)
+    n_bnd = property(lambda self: self.bnd_x.size)
+    n_tgt = property(lambda self: self.tgt_x.size)
+
+
+def on_boundary_problem(bx, by, bnx, bny, bw, q):
+    """Problem whose targets are the boundary nodes themselves, each with its
+    local frame from the panels and sgn = +1 (the interior limit)."""
+    bx, by = np.asarray(bx, float), np.asarray(by, float)
+    fr = G.boundary_frame(bx, by, q, bx, by)
+    geom = dict(r=np.zeros(bx.size), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
+                gamma4=fr["gamma4"], sgn=np.ones(bx.size, np.int8))
+    return _Layer(bx, by, np.asarray(bnx, float), np.asarray(bny, float), np.asarray(bw, float),
+                  bx.copy(), by.copy(), geom, info=dict(q=q, pan=fr["pan"], u=fr["u"]))
+
+
+def _jets(P, mu):
+    """mu's jets at the targets' closest points (weights cached on P)."""
+    if "jw" not in P.info:
+        P.info["jw"] = G.jet_weights(P.bnd_x, P.bnd_y, P.info["q"], P.info["pan"], P.info["u"], 4)
+    q = P.info["q"]
+    idx = np.asarray(P.info["pan"])[:, None] * q + np.arange(q)[None, :]
+    return np.einsum("kij,ij->ki", P.info["jw"], np.asarray(mu, float)[idx])
+
+
+def apply_interior_double_layer(P, mu):
+    """D_int[mu] at the nodes of the on-boundary problem P."""
+    Q = copy.copy(P)  # same nodes and frames, this density
+    Q.mu = np.asarray(mu, float)
+    Q.mu_jet = _jets(P, Q.mu)
+    return evaluate(Q, kinds="D")["D"]
+
+
+def interior_double_layer_matrix(P):
+    """Dense matrix of mu -> D_int[mu] at the nodes (column j: unit density at node j)."""
+    n = P.n_bnd
+    A = np.empty((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        A[:, j] = apply_interior_double_layer(P, e)
+    return A
+
+
+def solve_dirichlet(P, g):
+    """mu with D_int[mu] = g (direct solve of the assembled operator)."""
+    return np.linalg.solve(interior_double_layer_matrix(P), np.asarray(g, float))
+
+
+def double_layer_at(P, mu, tx, ty):
+    """u = D[mu] at targets (tx, ty), with their frames and the density's jets
+    from the panels."""
+    q = P.info["q"]
+    fr = G.boundary_frame(P.bnd_x, P.bnd_y, q, tx, ty)
+    geom = {k: fr[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    T = _Layer(P.bnd_x, P.bnd_y, P.bnd_nx, P.bnd_ny, P.bnd_w, np.asarray(tx, float), np.asarray(ty, float),
+               geom, np.asarray(mu, float), G.density_jets(P.bnd_x, P.bnd_y, q, mu, fr["pan"], fr["u"], 4))
+    return evaluate(T, kinds="D", delta=delta1_of(P))["D"]

@@ -151,3 +151,17 @@ def density_jets(node_x, node_y, q, dens, pan, u, nder):
         xi = dx * tau[0] + dy * tau[1]
         out[:, i] = inverse_chain(xi, _derivs(cs[pan[i]], u[i], 4))[: nder + 1]
     return out
+
+
+def jet_weights(node_x, node_y, q, pan, u, nder):
+    """Weights w[k, i, j] with jets[k, i] = sum_j w[k, i, j] dens[pan[i] q + j]:
+    density_jets as the linear map it is (the jets of the q unit densities of
+    each target's panel), for applying it to many densities."""
+    n = len(pan)
+    w = np.zeros((nder + 1, n, q))
+    n_pan = np.asarray(node_x).size // q
+    for j in range(q):
+        e = np.zeros(n_pan * q)
+        e[j::q] = 1.0                       # node j of every panel
+        w[:, :, j] = density_jets(node_x, node_y, q, e, pan, u, nder)
+    return w
