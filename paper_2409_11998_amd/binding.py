@@ -22,7 +22,7 @@ EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "v
             "vp_batch_create", "vp_batch_eval", "vp_batch_destroy", "vp_batch_last_error",
             "vp_server_create", "vp_server_submit", "vp_server_poll", "vp_server_wait", "vp_server_get_stats",
             "vp_server_destroy", "vp_server_last_error", "vp_refine_attach", "vp_layer_refine",
-            "vp_boundary_frame", "vp_boundary_jets"]
+            "vp_boundary_frame", "vp_boundary_jets", "vp_dirichlet_solve"]
 
 
 class VPError(RuntimeError):
@@ -117,6 +117,9 @@ def lib():
         L.vp_boundary_frame.restype = ctypes.c_int
         L.vp_boundary_jets.argtypes = [i64, ctypes.c_int, vp, vp, vp, i64, vp, vp, ctypes.c_int, vp, vp]
         L.vp_boundary_jets.restype = ctypes.c_int
+        L.vp_dirichlet_solve.argtypes = [vp, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        L.vp_dirichlet_solve.restype = ctypes.c_int
         L.vp_destroy.argtypes = [vp]
         L.vp_destroy.restype = ctypes.c_int
         L.vp_last_error.argtypes = []
@@ -452,3 +455,20 @@ def boundary_jets(bnd_x, bnd_y, q, dens, pan, u, nder):
     _check(lib().vp_boundary_jets(nb // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64), _ptr(dens, f64), n,
                                   _ptr(pan, torch.int32), _ptr(u, f64), nder, _ptr(out), _stream(pan)))
     return out
+
+
+def dirichlet_solve(plan, q, bnd_x, bnd_y, pan, u, g, mu=None, tol=1e-12, max_iter=200, restart=50):
+    """mu with D_int[mu] = g at the panel nodes (vp_dirichlet_solve); plan's
+    boundary nodes and targets are the nodes (targets with r = 0, sgn = +1).
+    Returns (mu, products, relative residual)."""
+    import torch
+    f64 = torch.float64
+    n = bnd_x.numel()
+    if mu is None:
+        mu = torch.zeros(n, dtype=f64, device=g.device)
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    _check(lib().vp_dirichlet_solve(plan.handle, n // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64),
+                                    _ptr(pan, torch.int32), _ptr(u, f64), _ptr(g, f64), _ptr(mu, f64), tol,
+                                    max_iter, restart, ctypes.byref(it), ctypes.byref(res)))
+    return mu, it.value, res.value

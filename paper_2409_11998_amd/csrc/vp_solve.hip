@@ -1,0 +1,202 @@
+// Interior Dirichlet problem for the Laplace equation by a double-layer
+// representation (the boundary integral solve of Sec. 5): u = D[mu] inside,
+// with mu on the boundary nodes solving D_int[mu] = g, where D_int is the
+// interior limit of the double layer at each node.  Restarted GMRES (modified
+// Gram-Schmidt, Givens rotations) whose product is this library's evaluation:
+// the density's jets at the nodes from its panel interpolant
+// (vp_boundary_jets), then vp_eval of the double layer at the plan's targets,
+// which are the nodes themselves with r = 0 and sgn = +1.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "vp_internal.hpp"
+
+namespace vp {
+namespace {
+
+constexpr int kSolveThreads = 256;
+constexpr int kDotBlocks = 256;
+
+__global__ __launch_bounds__(kSolveThreads) void k_dot(int64_t n, const double* __restrict__ a,
+                                                       const double* __restrict__ b, double* __restrict__ part)
+{
+    __shared__ double red[kSolveThreads / 64];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s = fma(a[i], b[i], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+        part[blockIdx.x] = t;
+    }
+}
+
+// y = a x + b y (b = 0: y is not read, so uninitialized memory may be the target)
+__global__ __launch_bounds__(kSolveThreads) void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
+                                                         double* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
+}
+
+struct Solver {
+    vp_plan_t plan;
+    int64_t n_pan, n;
+    int q;
+    const double *bx, *by, *upar;
+    const int32_t* pan;
+    hipStream_t st;
+    double* jets = nullptr;  // [5][n]
+    double* part = nullptr;  // [kDotBlocks]
+    std::vector<double> h_part = std::vector<double>(kDotBlocks);
+
+    vp_status matvec(const double* x, double* y)
+    {
+        vp_status s = vp_boundary_jets(n_pan, q, bx, by, x, n, pan, upar, 4, jets, (void*)st);
+        if (s != VP_OK) return s;
+        return vp_eval(plan, nullptr, nullptr, nullptr, nullptr, x, jets, y);
+    }
+    vp_status dot(const double* a, const double* b, double* out)
+    {
+        hipLaunchKernelGGL(k_dot, dim3(kDotBlocks), dim3(kSolveThreads), 0, st, n, a, b, part);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h_part.data(), part, kDotBlocks * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
+        double t = 0.0;
+        for (double v : h_part) t += v;  // fixed order
+        *out = t;
+        return VP_OK;
+    }
+    vp_status axpby(double a, const double* x, double b, double* y)
+    {
+        hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + kSolveThreads - 1) / kSolveThreads)), dim3(kSolveThreads), 0,
+                           st, n, a, x, b, y);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? VP_OK : set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
+    }
+};
+
+}  // namespace
+}  // namespace vp
+
+using namespace vp;
+
+extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
+                                        const double* bnd_y, const int32_t* pan, const double* u, const double* g,
+                                        double* mu, double tol, int max_iter, int restart, int* iters,
+                                        double* resid)
+{
+    if (!plan) return set_error(VP_ERR_ARG, "plan is NULL");
+    if (!(plan->kinds & VP_KIND_D)) return set_error(VP_ERR_ARG, "the plan does not support the double layer");
+    if (n_pan < 2 || q < 5 || q > 32 || plan->n_bnd != n_pan * q || plan->n_tgt != plan->n_bnd)
+        return set_error(VP_ERR_ARG, "the plan's boundary nodes and targets must be the n_pan*q panel nodes");
+    if (!bnd_x || !bnd_y || !pan || !u || !g || !mu) return set_error(VP_ERR_ARG, "NULL array");
+    if (!(tol > 0 && tol < 1) || max_iter < 1 || restart < 1 || restart > 200)
+        return set_error(VP_ERR_ARG, "tol in (0,1), max_iter >= 1, restart in [1, 200]");
+    const int64_t n = plan->n_bnd;
+    const int m = restart;
+    Solver S{plan, n_pan, n, q, bnd_x, bnd_y, u, pan, plan->stream};
+    double* V = nullptr;  // [m+1][n] Krylov basis
+    double* w = nullptr;  // [n]
+    hipError_t e = hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&w, (size_t)n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&S.jets, (size_t)5 * n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&S.part, kDotBlocks * sizeof(double));
+    vp_status s = e == hipSuccess ? VP_OK : set_error(VP_ERR_OOM, "solve workspace");
+    double gnorm = 0.0, rel = INFINITY;
+    int it = 0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), z(m + 1), y(m);
+    auto Vc = [&](int k) { return V + (size_t)k * n; };
+    if (s == VP_OK) s = S.dot(g, g, &gnorm);
+    gnorm = std::sqrt(gnorm);
+    if (s == VP_OK && gnorm == 0.0) {  // zero data: zero density
+        e = hipMemsetAsync(mu, 0, (size_t)n * sizeof(double), S.st);
+        if (e != hipSuccess) s = set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
+        rel = 0.0;
+    }
+    while (s == VP_OK && gnorm > 0.0 && it < max_iter) {
+        // r = g - A mu in V_0
+        if ((s = S.matvec(mu, Vc(0))) != VP_OK) break;
+        if ((s = S.axpby(1.0, g, -1.0, Vc(0))) != VP_OK) break;
+        double beta = 0.0;
+        if ((s = S.dot(Vc(0), Vc(0), &beta)) != VP_OK) break;
+        beta = std::sqrt(beta);
+        rel = beta / gnorm;
+        if (rel <= tol) break;
+        if ((s = S.axpby(0.0, g, 1.0 / beta, Vc(0))) != VP_OK) break;
+        std::fill(z.begin(), z.end(), 0.0);
+        z[0] = beta;
+        int k = 0;
+        for (; k < m && it < max_iter; ++k, ++it) {
+            if ((s = S.matvec(Vc(k), w)) != VP_OK) break;
+            for (int i = 0; i <= k; ++i) {  // modified Gram-Schmidt
+                double hik = 0.0;
+                if ((s = S.dot(w, Vc(i), &hik)) != VP_OK) break;
+                H[(size_t)i * m + k] = hik;
+                if ((s = S.axpby(-hik, Vc(i), 1.0, w)) != VP_OK) break;
+            }
+            if (s != VP_OK) break;
+            double hn = 0.0;
+            if ((s = S.dot(w, w, &hn)) != VP_OK) break;
+            hn = std::sqrt(hn);
+            H[(size_t)(k + 1) * m + k] = hn;
+            if (hn > 0.0 && (s = S.axpby(1.0 / hn, w, 0.0, Vc(k + 1))) != VP_OK) break;
+            for (int i = 0; i < k; ++i) {  // earlier rotations on the new column
+                const double a = H[(size_t)i * m + k], b = H[(size_t)(i + 1) * m + k];
+                H[(size_t)i * m + k] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[(size_t)k * m + k], b = H[(size_t)(k + 1) * m + k];
+            const double rr = std::hypot(a, b);
+            cs[k] = rr > 0.0 ? a / rr : 1.0;
+            sn[k] = rr > 0.0 ? b / rr : 0.0;
+            H[(size_t)k * m + k] = rr;
+            H[(size_t)(k + 1) * m + k] = 0.0;
+            z[k + 1] = -sn[k] * z[k];
+            z[k] = cs[k] * z[k];
+            rel = std::fabs(z[k + 1]) / gnorm;
+            if (rel <= tol || hn == 0.0) {
+                ++k;
+                ++it;
+                break;
+            }
+        }
+        if (s != VP_OK) break;
+        // mu += V y with H y = z (upper triangular, k columns)
+        for (int i = k - 1; i >= 0; --i) {
+            double t = z[i];
+            for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * y[j];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        for (int i = 0; i < k && s == VP_OK; ++i) s = S.axpby(y[i], Vc(i), 1.0, mu);
+        if (rel <= tol) {
+            // true residual of the update
+            if (s == VP_OK) s = S.matvec(mu, w);
+            if (s == VP_OK) s = S.axpby(1.0, g, -1.0, w);
+            double rn = 0.0;
+            if (s == VP_OK) s = S.dot(w, w, &rn);
+            rel = std::sqrt(rn) / gnorm;
+            if (rel <= tol * 10.0) break;  // the recurrence and the true residual agree to rounding
+        }
+    }
+    if (s == VP_OK) {
+        e = hipStreamSynchronize(plan->stream);
+        if (e != hipSuccess) s = set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
+    }
+    if (V) (void)hipFree(V);
+    if (w) (void)hipFree(w);
+    if (S.jets) (void)hipFree(S.jets);
+    if (S.part) (void)hipFree(S.part);
+    if (iters) *iters = it;
+    if (resid) *resid = rel;
+    if (s == VP_OK && !(rel <= tol * 10.0)) s = set_error(VP_ERR_TOL, "GMRES did not reach the tolerance");
+    return s;
+}

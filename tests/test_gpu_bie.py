@@ -1,0 +1,127 @@
+"""GPU parity of vp_dirichlet_solve (interior Dirichlet problem by a
+double-layer representation, GMRES over this library's evaluation) against the
+oracle's direct solve of the same operator, the unit circle's closed form and
+a harmonic function recovered inside a lobed star."""
+import numpy as np
+import pytest
+from numpy.polynomial.legendre import leggauss
+
+import oracle
+from oracle import bie
+from workloads.problems import StarCurve, panel_nodes, star_params
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def _t(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def _circle(n_pan, q=16):
+    xg, wg = leggauss(q)
+    e = np.linspace(0, 2 * np.pi, n_pan + 1)
+    a, b = e[:-1, None], e[1:, None]
+    t = (0.5 * (a + b) + 0.5 * (b - a) * xg[None]).ravel()
+    w = (0.5 * (b - a) * wg[None]).ravel()
+    return np.cos(t), np.sin(t), np.cos(t), np.sin(t), w, t
+
+
+def _solve(torch, bx, by, bnx, bny, bw, q, g, **kw):
+    """Plan on the nodes (targets = nodes, r = 0, sgn = +1, frames from the panels), then the solve."""
+    from paper_2409_11998_amd import Plan, boundary_frame, dirichlet_solve
+    dx, dy = _t(torch, bx), _t(torch, by)
+    fr = boundary_frame(dx, dy, q, dx, dy)
+    geom = dict(r=torch.zeros_like(dx), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
+                gamma4=fr["gamma4"], sgn=torch.ones(dx.numel(), dtype=torch.int8, device="cuda"))
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    plan = Plan(e, e, e, dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw), dx, dy, geom, tol=1e-10,
+                precision=1, kinds=4)
+    mu, its, res = dirichlet_solve(plan, q, dx, dy, fr["pan"], fr["u"], _t(torch, g), **kw)
+    torch.cuda.synchronize()
+    return plan, mu.cpu().numpy(), its, res
+
+
+def test_circle_matches_oracle_and_closed_form():
+    torch = _gpu()
+    bx, by, nx, ny, w, t = _circle(32)
+    g = np.cos(3 * t)
+    plan, mu, its, res = _solve(torch, bx, by, nx, ny, w, 16, g)
+    P = bie.on_boundary_problem(bx, by, nx, ny, w, 16)
+    ref = bie.solve_dirichlet(P, g)
+    e = oracle.rel_linf(mu, ref)
+    print("circle: GMRES products", its, "residual", res, "mu vs oracle", e, "vs -2g", np.max(np.abs(mu + 2 * g)))
+    assert res <= 1e-11
+    assert e <= 1e-8
+    assert np.max(np.abs(mu + 2 * g)) <= 5e-7
+    plan.close()
+
+
+def test_star_interior_values():
+    torch = _gpu()
+    from paper_2409_11998_amd import Plan, boundary_frame, boundary_jets
+    curve = StarCurve(**star_params(3, r=0.8))
+    q = 16
+    bx, by, bnx, bny, bw, _ = panel_nodes(curve, 24, q)
+    z0 = complex(0.1, -0.05)
+
+    def uex(x, y):
+        return ((x + 1j * y - z0) ** 3).real + 0.3 * x - 0.2 * y + 1.0
+
+    plan, mu, its, res = _solve(torch, bx, by, bnx, bny, bw, q, uex(bx, by))
+    plan.close()
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q)
+    ref = bie.solve_dirichlet(P, uex(bx, by))
+    e_mu = oracle.rel_linf(mu, ref)
+    # u = D[mu] at interior points through vp_eval, frames and jets from the panels
+    rng = np.random.default_rng(1)
+    k = rng.integers(0, bx.size, 300)
+    s = rng.uniform(0.3, 0.97, 300)
+    cx, cy = np.mean(bx), np.mean(by)
+    tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
+    dx, dy = _t(torch, bx), _t(torch, by)
+    fr = boundary_frame(dx, dy, q, _t(torch, tx), _t(torch, ty))
+    geom = {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    e0 = torch.zeros(0, dtype=torch.float64, device="cuda")
+    # the interior evaluation keeps the boundary problem's delta_1 (3 mean(w)^2): no volume nodes
+    pl = Plan(e0, e0, e0, dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw), _t(torch, tx), _t(torch, ty),
+              geom, tol=1e-10, precision=1, kinds=4)
+    mu_t = _t(torch, mu)
+    mj = boundary_jets(dx, dy, q, mu_t, fr["pan"], fr["u"], 4).contiguous()
+    u = pl.eval(mu=mu_t, mu_jet=mj).cpu().numpy()
+    pl.close()
+    u_ref = bie.double_layer_at(P, ref, tx, ty)
+    e_u = np.max(np.abs(u - uex(tx, ty)))
+    print("star: products", its, "residual", res, "mu vs oracle", e_mu, "u vs oracle", oracle.rel_linf(u, u_ref),
+          "u vs exact", e_u)
+    assert res <= 1e-11
+    assert e_mu <= 1e-8
+    assert oracle.rel_linf(u, u_ref) <= 1e-8
+    assert e_u <= 1e-4
+
+
+def test_solve_argument_errors_and_non_convergence():
+    torch = _gpu()
+    from paper_2409_11998_amd import dirichlet_solve
+    from paper_2409_11998_amd.binding import VP_ERR_ARG, VP_ERR_TOL, VPError
+    bx, by, nx, ny, w, t = _circle(16)
+    g = np.random.default_rng(7).standard_normal(bx.size)     # many modes: three products cannot reach 1e-12
+    with pytest.raises(VPError) as ei:
+        _solve(torch, bx, by, nx, ny, w, 16, g, max_iter=3)
+    assert ei.value.status == VP_ERR_TOL
+    plan, mu, its, res = _solve(torch, bx, by, nx, ny, w, 16, g)
+    dx = _t(torch, bx)
+    with pytest.raises(VPError) as ei:       # 5-node panels cannot hold the plan's 256 nodes
+        dirichlet_solve(plan, 5, dx, dx, torch.zeros(dx.numel(), dtype=torch.int32, device="cuda"), dx, dx)
+    assert ei.value.status == VP_ERR_ARG
+    z, its0, res0 = dirichlet_solve(plan, 16, dx, _t(torch, by), torch.zeros(dx.numel(), dtype=torch.int32,
+                                    device="cuda"), dx, torch.zeros_like(dx))
+    torch.cuda.synchronize()
+    assert its0 == 0 and float(z.abs().max()) == 0.0        # zero data: zero density
+    plan.close()
