@@ -1,13 +1,16 @@
-"""Oracle: the interior Dirichlet problem for the Laplace equation by a
-double-layer representation (the boundary integral solve of Sec. 5, whose
-matrix-vector product is the layer potential evaluated on the boundary).
+"""Oracle: the interior Dirichlet problem -Lap u = f in the domain, u = g on
+its boundary, by the representation u = V[f] + D[mu] (Sec. 1 and the boundary
+integral correction of Sec. 5, whose matrix-vector product is the layer
+potential evaluated on the boundary).
 
 Test infrastructure only: plain numpy in float64 (dense operator, direct
 solve).  Nothing here is imported by the product path.
 
-u = D[mu] is harmonic inside; its interior limit on the boundary is
+D[mu] is harmonic inside; its interior limit on the boundary is
 D_int[mu] = -mu/2 + (principal value of D[mu]), so the boundary condition
-u = g on the boundary is the second-kind equation D_int[mu] = g.  Here D_int
+u = g on the boundary is the second-kind equation D_int[mu] = g - V[f]
+(f = 0: the Laplace equation).  With volume nodes present, delta_1 follows
+their rule 3 sum(w)/N for every part, as in the method.  Here D_int
 at a boundary node is what the method computes for a target at that node with
 r = 0 and sgn = +1 (history part plus the local part's interior limit), the
 density's jets at the node coming from its panel interpolant
@@ -23,32 +26,35 @@ from .potential import delta1_of, evaluate
 
 
 class _Layer:
-    """Boundary nodes, targets with their frames and the layer densities: the
-    fields oracle.potential.evaluate reads (no volume nodes)."""
+    """Volume nodes (optional), boundary nodes, targets with their frames and
+    the densities: the fields oracle.potential.evaluate reads."""
 
-    def __init__(self, bx, by, bnx, bny, bw, tx, ty, geom, mu=None, mu_jet=None, info=None):
+    def __init__(self, bx, by, bnx, bny, bw, tx, ty, geom, mu=None, mu_jet=None, info=None, src=None,
+                 f_src=None, jet6=None):
         e = np.zeros(0)
-        self.src_x = self.src_y = self.src_w = e
-        self.f_src = self.jet6 = self.sigma = self.sigma_jet = None
+        self.src_x, self.src_y, self.src_w = (e, e, e) if src is None else (np.asarray(a, float) for a in src)
+        self.f_src, self.jet6 = f_src, jet6
+        self.sigma = self.sigma_jet = None
         self.bnd_x, self.bnd_y, self.bnd_nx, self.bnd_ny, self.bnd_w = bx, by, bnx, bny, bw
         self.tgt_x, self.tgt_y, self.geom = tx, ty, geom
         self.mu, self.mu_jet = mu, mu_jet
         self.info = info or {}
 
-    n_src = property(lambda self: 0)
+    n_src = property(lambda self: self.src_x.size)
     n_bnd = property(lambda self: self.bnd_x.size)
     n_tgt = property(lambda self: self.tgt_x.size)
 
 
-def on_boundary_problem(bx, by, bnx, bny, bw, q):
+def on_boundary_problem(bx, by, bnx, bny, bw, q, src=None):
     """Problem whose targets are the boundary nodes themselves, each with its
-    local frame from the panels and sgn = +1 (the interior limit)."""
+    local frame from the panels and sgn = +1 (the interior limit); src =
+    (x, y, w) of the volume nodes, if any."""
     bx, by = np.asarray(bx, float), np.asarray(by, float)
     fr = G.boundary_frame(bx, by, q, bx, by)
     geom = dict(r=np.zeros(bx.size), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
                 gamma4=fr["gamma4"], sgn=np.ones(bx.size, np.int8))
     return _Layer(bx, by, np.asarray(bnx, float), np.asarray(bny, float), np.asarray(bw, float),
-                  bx.copy(), by.copy(), geom, info=dict(q=q, pan=fr["pan"], u=fr["u"]))
+                  bx.copy(), by.copy(), geom, info=dict(q=q, pan=fr["pan"], u=fr["u"]), src=src)
 
 
 def _jets(P, mu):
@@ -79,17 +85,35 @@ def interior_double_layer_matrix(P):
     return A
 
 
-def solve_dirichlet(P, g):
-    """mu with D_int[mu] = g (direct solve of the assembled operator)."""
-    return np.linalg.solve(interior_double_layer_matrix(P), np.asarray(g, float))
+def volume_at_nodes(P, f_src, jet6):
+    """V[f] at the nodes of the on-boundary problem P (volume nodes of P; jet6:
+    f and its derivatives at the nodes)."""
+    Q = copy.copy(P)
+    Q.f_src, Q.jet6 = np.asarray(f_src, float), np.asarray(jet6, float)
+    return evaluate(Q, kinds="V")["V"]
 
 
-def double_layer_at(P, mu, tx, ty):
-    """u = D[mu] at targets (tx, ty), with their frames and the density's jets
-    from the panels."""
+def solve_dirichlet(P, g, f_src=None, jet6=None):
+    """mu with D_int[mu] = g - V[f] at the nodes (direct solve of the assembled
+    operator); f_src = None: the Laplace equation."""
+    b = np.asarray(g, float)
+    if f_src is not None:
+        b = b - volume_at_nodes(P, f_src, jet6)
+    return np.linalg.solve(interior_double_layer_matrix(P), b)
+
+
+def solution_at(P, mu, tx, ty, f_src=None, jet6=None):
+    """u = V[f] + D[mu] at targets (tx, ty): their frames and the density's jets
+    from the panels, jet6 = f's jets at the targets (with f_src)."""
     q = P.info["q"]
     fr = G.boundary_frame(P.bnd_x, P.bnd_y, q, tx, ty)
     geom = {k: fr[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
     T = _Layer(P.bnd_x, P.bnd_y, P.bnd_nx, P.bnd_ny, P.bnd_w, np.asarray(tx, float), np.asarray(ty, float),
-               geom, np.asarray(mu, float), G.density_jets(P.bnd_x, P.bnd_y, q, mu, fr["pan"], fr["u"], 4))
-    return evaluate(T, kinds="D", delta=delta1_of(P))["D"]
+               geom, np.asarray(mu, float), G.density_jets(P.bnd_x, P.bnd_y, q, mu, fr["pan"], fr["u"], 4),
+               src=(P.src_x, P.src_y, P.src_w), f_src=f_src, jet6=jet6)
+    return evaluate(T, kinds="VD" if f_src is not None else "D", delta=delta1_of(P))["total"]
+
+
+def double_layer_at(P, mu, tx, ty):
+    """u = D[mu] at targets (tx, ty)."""
+    return solution_at(P, mu, tx, ty)

@@ -5,13 +5,23 @@ D_int assembled from the method's evaluation at the boundary nodes):
 * the unit circle in closed form: D[cos n t] = -r^n cos(n t) / 2 inside, so
   D_int[mu] = cos(n t) has mu = -2 cos(n t), and u = r^n cos(n t) inside;
 * a lobed star: u = Re((z - z0)^3) + linear recovered inside;
-* every error falls with refinement of the panels (delta_1 ~ spacing^2).
+* every error falls with refinement of the panels (delta_1 ~ spacing^2);
+* the Poisson problem -Lap u = exp(-r^2/s) on the unit disk with u = cos 3t on
+  the circle, u = w(r) + r^3 cos 3t, where the radial part
+  w(r) = (s/4)(2 ln(1/r) - E1(r^2/s) + E1(1/s)) has -Lap w = exp(-r^2/s),
+  w(1) = 0; and V[f] = 0 on the circle for a radial f (Newton's theorem:
+  outside a radial mass, V is -M ln|x| / (2 pi));
+* the same source inside a lobed star, u = w(|x|) + Re((z - z0)^3): there V[f]
+  on the boundary is far from zero, so the sign of the volume term in the
+  boundary equation is checked too.
 """
 import numpy as np
 from numpy.polynomial.legendre import leggauss
+from scipy.special import exp1
 
 from oracle import bie
-from workloads.problems import StarCurve, panel_nodes, star_params
+from workloads.mesh import curve_mesh
+from workloads.problems import StarCurve, disk_problem, gauss_jets, panel_nodes, star_params
 
 
 def _circle(n_pan, q=16):
@@ -61,3 +71,53 @@ def test_star_harmonic_recovered():
     e = np.max(np.abs(bie.double_layer_at(P, mu, tx, ty) - uex(tx, ty)))
     print("star: interior error", e)
     assert e <= 1e-4
+
+
+def _disk_poisson_errors(n_tri, n_pan, s2=0.1):
+    gauss = ((1.0, 0.0, 0.0, np.sqrt(s2)),)
+    D = disk_problem(n_tri, seed=1, gauss=gauss)
+    bx, by, nx, ny, w, t = _circle(n_pan)
+    P = bie.on_boundary_problem(bx, by, nx, ny, w, 16, src=(D.src_x, D.src_y, D.src_w))
+    v_bnd = np.max(np.abs(bie.volume_at_nodes(P, D.f_src, gauss_jets(bx, by, gauss))))
+    mu = bie.solve_dirichlet(P, np.cos(3 * t), D.f_src, gauss_jets(bx, by, gauss))
+    rng = np.random.default_rng(0)
+    th, rr = rng.uniform(0, 2 * np.pi, 150), rng.uniform(0.1, 0.95, 150)
+    tx, ty = rr * np.cos(th), rr * np.sin(th)
+    u = bie.solution_at(P, mu, tx, ty, D.f_src, gauss_jets(tx, ty, gauss))
+    w_r = 0.25 * s2 * (2 * np.log(1 / rr) - exp1(rr * rr / s2) + exp1(1 / s2))
+    return v_bnd, np.max(np.abs(u - w_r - rr ** 3 * np.cos(3 * th)))
+
+
+def test_disk_poisson_closed_form_and_convergence():
+    coarse = _disk_poisson_errors(2000, 48)
+    fine = _disk_poisson_errors(8000, 64)
+    print("disk Poisson (|V| on the circle, interior error): coarse", coarse, "fine", fine)
+    assert coarse[0] <= 1e-8 and fine[0] <= 1e-9
+    assert coarse[1] <= 1e-5 and fine[1] <= 1e-7 and fine[1] <= coarse[1] / 10
+
+
+def test_star_poisson_recovered():
+    s2 = 0.1
+    gauss = ((1.0, 0.0, 0.0, np.sqrt(s2)),)
+    curve = StarCurve(**star_params(3, r=0.8))
+    z0 = complex(0.1, -0.05)
+
+    def uex(x, y):
+        r = np.hypot(x, y)
+        return 0.25 * s2 * (2 * np.log(1 / r) - exp1(r * r / s2) + exp1(1 / s2)) + ((x + 1j * y - z0) ** 3).real
+
+    x, y, w, _ = curve_mesh(curve, 1500, 3)
+    bx, by, bnx, bny, bw, _ = panel_nodes(curve, 32, 16)
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, 16, src=(x, y, w))
+    f = gauss_jets(x, y, gauss)[0]
+    v_bnd = bie.volume_at_nodes(P, f, gauss_jets(bx, by, gauss))
+    mu = bie.solve_dirichlet(P, uex(bx, by), f, gauss_jets(bx, by, gauss))
+    rng = np.random.default_rng(1)
+    k = rng.integers(0, bx.size, 150)
+    s = rng.uniform(0.3, 0.97, 150)
+    cx, cy = np.mean(bx), np.mean(by)
+    tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
+    e = np.max(np.abs(bie.solution_at(P, mu, tx, ty, f, gauss_jets(tx, ty, gauss)) - uex(tx, ty)))
+    print("star Poisson: max |V| on the boundary", np.max(np.abs(v_bnd)), "interior error", e)
+    assert np.max(np.abs(v_bnd)) >= 0.01          # the volume term matters on this boundary
+    assert e <= 1e-5
