@@ -243,30 +243,39 @@ vp_status vp_boundary_jets(int64_t n_pan, int q, const double* bnd_x, const doub
                            int64_t n_tgt, const int32_t* pan, const double* u, int nder, double* out, void* stream);
 
 /* ------------------------------------------------------------------------
- * Interior Dirichlet problem for the Laplace equation by a double-layer
- * representation (the boundary integral solve of Sec. 5): u = D[mu] inside,
- * with mu at the boundary nodes solving D_int[mu] = g, D_int the interior
- * limit of the double layer at each node.  Restarted GMRES(restart) with
+ * Interior Dirichlet problem -Lap u = f inside, u = g on the boundary, by
+ * the representation u = V[f] + D[mu] (Sec. 1; the boundary integral
+ * correction of Sec. 5): mu at the boundary nodes solves
+ * D_int[mu] = g - V[f], D_int the interior limit of the double layer at each
+ * node (f absent: the Laplace equation, u = D[mu]).  Restarted GMRES(restart) with
  * modified Gram-Schmidt, whose product is this library's evaluation: mu's
  * jets at the nodes from its panel interpolant (vp_boundary_jets), then
  * vp_eval of the double layer.
  *
- * plan: kind D; its boundary nodes are the n_pan*q panel nodes (bnd_x, bnd_y,
+ * plan: kind D (and V with a source); its boundary nodes are the n_pan*q panel nodes (bnd_x, bnd_y,
  *   device, the layout of vp_boundary_frame) and its targets are those same
  *   nodes, each with r = 0, sgn = +1 (the interior limit) and its frame from
  *   vp_boundary_frame at the nodes; pan, u: that call's locations.
- * g [n_pan*q] (device): boundary values.  mu [n_pan*q] (device): in, the
+ * g [n_pan*q] (device): boundary values.  f_src [n_src] (device): f at the
+ *   plan's volume nodes, jet6 [6][n_pan*q] (device): f and its derivatives at
+ *   the boundary nodes (vp_eval's layout); both NULL for f = 0.  V[f] at the
+ *   nodes is one vp_volume call on the plan; its delta_1 (from the volume
+ *   nodes) then serves the double layer too, as in the method.
+ *   mu [n_pan*q] (device): in, the
  *   initial guess; out, the solution (the last iterate on VP_ERR_TOL).
  * tol: relative residual ||g - D_int mu|| / ||g||; max_iter >= 1 products;
  *   restart in [1, 200].  iters, resid (host, may be NULL): products taken
  *   and final relative residual.
  * Runs on the plan's stream and synchronizes it before returning.  Scratch
- * of (restart + 7) n doubles is allocated for the call.  VP_ERR_ARG for a
- * plan without D, or whose nodes or targets are not the n_pan*q panel nodes;
+ * of (restart + 7) n doubles (one more n with a source) is allocated for the call.  VP_ERR_ARG for a
+ * plan without D, or whose nodes or targets are not the n_pan*q panel nodes,
+ * for only one of f_src and jet6, or for a source on a plan without V or
+ * volume nodes;
  * VP_ERR_TOL when max_iter products do not reach tol. */
 vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,
-                             const int32_t* pan, const double* u, const double* g, double* mu, double tol,
-                             int max_iter, int restart, int* iters, double* resid);
+                             const int32_t* pan, const double* u, const double* g, const double* f_src,
+                             const double* jet6, double* mu, double tol, int max_iter, int restart, int* iters,
+                             double* resid);
 
 /* Release the plan and its device memory (synchronizes its stream). NULL is a no-op. */
 vp_status vp_destroy(vp_plan_t plan);

@@ -117,8 +117,8 @@ def lib():
         L.vp_boundary_frame.restype = ctypes.c_int
         L.vp_boundary_jets.argtypes = [i64, ctypes.c_int, vp, vp, vp, i64, vp, vp, ctypes.c_int, vp, vp]
         L.vp_boundary_jets.restype = ctypes.c_int
-        L.vp_dirichlet_solve.argtypes = [vp, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int,
-                                         ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        L.vp_dirichlet_solve.argtypes = [vp, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.vp_dirichlet_solve.restype = ctypes.c_int
         L.vp_destroy.argtypes = [vp]
         L.vp_destroy.restype = ctypes.c_int
@@ -457,10 +457,12 @@ def boundary_jets(bnd_x, bnd_y, q, dens, pan, u, nder):
     return out
 
 
-def dirichlet_solve(plan, q, bnd_x, bnd_y, pan, u, g, mu=None, tol=1e-12, max_iter=200, restart=50):
-    """mu with D_int[mu] = g at the panel nodes (vp_dirichlet_solve); plan's
-    boundary nodes and targets are the nodes (targets with r = 0, sgn = +1).
-    Returns (mu, products, relative residual)."""
+def dirichlet_solve(plan, q, bnd_x, bnd_y, pan, u, g, mu=None, tol=1e-12, max_iter=200, restart=50, f=None,
+                    jet6=None):
+    """mu with D_int[mu] = g - V[f] at the panel nodes (vp_dirichlet_solve);
+    plan's boundary nodes and targets are the nodes (targets with r = 0,
+    sgn = +1); f at the plan's volume nodes and jet6 [6, n_bnd] at the boundary
+    nodes, or neither.  Returns (mu, products, relative residual)."""
     import torch
     f64 = torch.float64
     n = bnd_x.numel()
@@ -469,6 +471,7 @@ def dirichlet_solve(plan, q, bnd_x, bnd_y, pan, u, g, mu=None, tol=1e-12, max_it
     it = ctypes.c_int(0)
     res = ctypes.c_double(0.0)
     _check(lib().vp_dirichlet_solve(plan.handle, n // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64),
-                                    _ptr(pan, torch.int32), _ptr(u, f64), _ptr(g, f64), _ptr(mu, f64), tol,
+                                    _ptr(pan, torch.int32), _ptr(u, f64), _ptr(g, f64), _ptr(f, f64),
+                                    _ptr(jet6, f64), _ptr(mu, f64), tol,
                                     max_iter, restart, ctypes.byref(it), ctypes.byref(res)))
     return mu, it.value, res.value

@@ -1,7 +1,9 @@
-// Interior Dirichlet problem for the Laplace equation by a double-layer
-// representation (the boundary integral solve of Sec. 5): u = D[mu] inside,
-// with mu on the boundary nodes solving D_int[mu] = g, where D_int is the
-// interior limit of the double layer at each node.  Restarted GMRES (modified
+// Interior Dirichlet problem -Lap u = f inside, u = g on the boundary, by the
+// representation u = V[f] + D[mu] (Sec. 1; the boundary integral correction of
+// Sec. 5): mu on the boundary nodes solves D_int[mu] = g - V[f], where D_int is
+// the interior limit of the double layer at each node and V[f] is this
+// library's volume potential at the nodes (f = 0: the Laplace equation,
+// u = D[mu]).  Restarted GMRES (modified
 // Gram-Schmidt, Givens rotations) whose product is this library's evaluation:
 // the density's jets at the nodes from its panel interpolant
 // (vp_boundary_jets), then vp_eval of the double layer at the plan's targets,
@@ -91,14 +93,17 @@ using namespace vp;
 
 extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
                                         const double* bnd_y, const int32_t* pan, const double* u, const double* g,
-                                        double* mu, double tol, int max_iter, int restart, int* iters,
-                                        double* resid)
+                                        const double* f_src, const double* jet6, double* mu, double tol,
+                                        int max_iter, int restart, int* iters, double* resid)
 {
     if (!plan) return set_error(VP_ERR_ARG, "plan is NULL");
     if (!(plan->kinds & VP_KIND_D)) return set_error(VP_ERR_ARG, "the plan does not support the double layer");
     if (n_pan < 2 || q < 5 || q > 32 || plan->n_bnd != n_pan * q || plan->n_tgt != plan->n_bnd)
         return set_error(VP_ERR_ARG, "the plan's boundary nodes and targets must be the n_pan*q panel nodes");
     if (!bnd_x || !bnd_y || !pan || !u || !g || !mu) return set_error(VP_ERR_ARG, "NULL array");
+    if ((f_src == nullptr) != (jet6 == nullptr)) return set_error(VP_ERR_ARG, "f_src and jet6 go together");
+    if (f_src && (!(plan->kinds & VP_KIND_V) || plan->n_src == 0))
+        return set_error(VP_ERR_ARG, "a volume source needs a plan with volume nodes and the volume kind");
     if (!(tol > 0 && tol < 1) || max_iter < 1 || restart < 1 || restart > 200)
         return set_error(VP_ERR_ARG, "tol in (0,1), max_iter >= 1, restart in [1, 200]");
     const int64_t n = plan->n_bnd;
@@ -106,8 +111,10 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
     Solver S{plan, n_pan, n, q, bnd_x, bnd_y, u, pan, plan->stream};
     double* V = nullptr;  // [m+1][n] Krylov basis
     double* w = nullptr;  // [n]
+    double* rhs = nullptr;  // [n] g - V[f], with a volume source
     hipError_t e = hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&w, (size_t)n * sizeof(double));
+    if (e == hipSuccess && f_src) e = hipMalloc((void**)&rhs, (size_t)n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.jets, (size_t)5 * n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.part, kDotBlocks * sizeof(double));
     vp_status s = e == hipSuccess ? VP_OK : set_error(VP_ERR_OOM, "solve workspace");
@@ -115,6 +122,11 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
     int it = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), z(m + 1), y(m);
     auto Vc = [&](int k) { return V + (size_t)k * n; };
+    if (s == VP_OK && f_src) {  // rhs = g - V[f] at the nodes
+        s = vp_volume(plan, f_src, jet6, rhs);
+        if (s == VP_OK) s = S.axpby(1.0, g, -1.0, rhs);
+        if (s == VP_OK) g = rhs;
+    }
     if (s == VP_OK) s = S.dot(g, g, &gnorm);
     gnorm = std::sqrt(gnorm);
     if (s == VP_OK && gnorm == 0.0) {  // zero data: zero density
@@ -193,6 +205,7 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
     }
     if (V) (void)hipFree(V);
     if (w) (void)hipFree(w);
+    if (rhs) (void)hipFree(rhs);
     if (S.jets) (void)hipFree(S.jets);
     if (S.part) (void)hipFree(S.part);
     if (iters) *iters = it;

@@ -1,14 +1,17 @@
-"""GPU parity of vp_dirichlet_solve (interior Dirichlet problem by a
-double-layer representation, GMRES over this library's evaluation) against the
-oracle's direct solve of the same operator, the unit circle's closed form and
-a harmonic function recovered inside a lobed star."""
+"""GPU parity of vp_dirichlet_solve (interior Dirichlet problem by the
+representation u = V[f] + D[mu], GMRES over this library's evaluation) against
+the oracle's direct solve of the same operator, the unit circle's closed form,
+a harmonic function recovered inside a lobed star, and the Poisson problem with
+a Gaussian source on the disk and the star in closed form."""
 import numpy as np
 import pytest
 from numpy.polynomial.legendre import leggauss
+from scipy.special import exp1
 
 import oracle
 from oracle import bie
-from workloads.problems import StarCurve, panel_nodes, star_params
+from workloads.mesh import curve_mesh
+from workloads.problems import StarCurve, disk_problem, gauss_jets, panel_nodes, star_params
 
 pytestmark = pytest.mark.gpu
 
@@ -33,16 +36,20 @@ def _circle(n_pan, q=16):
     return np.cos(t), np.sin(t), np.cos(t), np.sin(t), w, t
 
 
-def _solve(torch, bx, by, bnx, bny, bw, q, g, **kw):
-    """Plan on the nodes (targets = nodes, r = 0, sgn = +1, frames from the panels), then the solve."""
+def _solve(torch, bx, by, bnx, bny, bw, q, g, src=None, f=None, jet6=None, **kw):
+    """Plan on the nodes (targets = nodes, r = 0, sgn = +1, frames from the panels), then the solve;
+    src = (x, y, w) of volume nodes with f there and jet6 at the boundary nodes."""
     from paper_2409_11998_amd import Plan, boundary_frame, dirichlet_solve
     dx, dy = _t(torch, bx), _t(torch, by)
     fr = boundary_frame(dx, dy, q, dx, dy)
     geom = dict(r=torch.zeros_like(dx), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
                 gamma4=fr["gamma4"], sgn=torch.ones(dx.numel(), dtype=torch.int8, device="cuda"))
     e = torch.zeros(0, dtype=torch.float64, device="cuda")
-    plan = Plan(e, e, e, dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw), dx, dy, geom, tol=1e-10,
-                precision=1, kinds=4)
+    sx, sy, sw = (e, e, e) if src is None else (_t(torch, a) for a in src)
+    plan = Plan(sx, sy, sw, dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw), dx, dy, geom, tol=1e-10,
+                precision=1, kinds=4 if src is None else 5)
+    if f is not None:
+        kw.update(f=_t(torch, f), jet6=_t(torch, jet6))
     mu, its, res = dirichlet_solve(plan, q, dx, dy, fr["pan"], fr["u"], _t(torch, g), **kw)
     torch.cuda.synchronize()
     return plan, mu.cpu().numpy(), its, res
@@ -125,3 +132,74 @@ def test_solve_argument_errors_and_non_convergence():
     torch.cuda.synchronize()
     assert its0 == 0 and float(z.abs().max()) == 0.0        # zero data: zero density
     plan.close()
+
+
+S2 = 0.1
+GAUSS = ((1.0, 0.0, 0.0, np.sqrt(S2)),)
+
+
+def _w_radial(r):
+    """-Lap w = exp(-r^2/S2), w(1) = 0 (radial)."""
+    return 0.25 * S2 * (2 * np.log(1 / r) - exp1(r * r / S2) + exp1(1 / S2))
+
+
+@pytest.mark.parametrize("domain", ["disk", "star"])
+def test_poisson_with_volume_source(domain):
+    """-Lap u = exp(-|x|^2/S2): the right-hand side g - V[f] formed on the device,
+    mu against the oracle's direct solve, u = V[f] + D[mu] inside against the
+    oracle and the closed form."""
+    torch = _gpu()
+    from paper_2409_11998_amd import Plan, boundary_frame, boundary_jets
+    q = 16
+    if domain == "disk":
+        D = disk_problem(2000, seed=1, gauss=GAUSS)
+        x, y, w = D.src_x, D.src_y, D.src_w
+        bx, by, bnx, bny, bw, t = _circle(48)
+        uex = lambda px, py: _w_radial(np.hypot(px, py)) + np.real((px + 1j * py) ** 3)
+    else:
+        curve = StarCurve(**star_params(3, r=0.8))
+        x, y, w, _ = curve_mesh(curve, 1500, 3)
+        bx, by, bnx, bny, bw, _ = panel_nodes(curve, 32, q)
+        z0 = complex(0.1, -0.05)
+        uex = lambda px, py: _w_radial(np.hypot(px, py)) + np.real((px + 1j * py - z0) ** 3)
+    f = gauss_jets(x, y, GAUSS)[0]
+    jb = gauss_jets(bx, by, GAUSS)
+    plan, mu, its, res = _solve(torch, bx, by, bnx, bny, bw, q, uex(bx, by), src=(x, y, w), f=f, jet6=jb)
+    plan.close()
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q, src=(x, y, w))
+    ref = bie.solve_dirichlet(P, uex(bx, by), f, jb)
+    e_mu = oracle.rel_linf(mu, ref)
+    rng = np.random.default_rng(2)
+    k = rng.integers(0, bx.size, 300)
+    s = rng.uniform(0.2, 0.95, 300)
+    cx, cy = np.mean(bx), np.mean(by)
+    tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
+    dx, dy = _t(torch, bx), _t(torch, by)
+    ftx, fty = _t(torch, tx), _t(torch, ty)
+    fr = boundary_frame(dx, dy, q, ftx, fty)
+    geom = {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    pl = Plan(_t(torch, x), _t(torch, y), _t(torch, w), dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw),
+              ftx, fty, geom, tol=1e-10, precision=1, kinds=5)
+    mu_t = _t(torch, mu)
+    u = pl.eval(f=_t(torch, f), jet6=_t(torch, gauss_jets(tx, ty, GAUSS)), mu=mu_t,
+                mu_jet=boundary_jets(dx, dy, q, mu_t, fr["pan"], fr["u"], 4)).cpu().numpy()
+    pl.close()
+    u_ref = bie.solution_at(P, ref, tx, ty, f, gauss_jets(tx, ty, GAUSS))
+    e_u = oracle.rel_linf(u, u_ref)
+    e_x = np.max(np.abs(u - uex(tx, ty)))
+    print(domain, "products", its, "residual", res, "mu vs oracle", e_mu, "u vs oracle", e_u, "u vs exact", e_x)
+    assert res <= 1e-11
+    assert e_mu <= 1e-8
+    assert e_u <= 1e-8
+    assert e_x <= 1e-5
+
+
+def test_source_arguments():
+    torch = _gpu()
+    from paper_2409_11998_amd.binding import VP_ERR_ARG, VPError
+    bx, by, nx, ny, w, t = _circle(16)
+    g = np.cos(3 * t)
+    jb = gauss_jets(bx, by, GAUSS)
+    with pytest.raises(VPError) as ei:          # a source on a plan without volume nodes
+        _solve(torch, bx, by, nx, ny, w, 16, g, f=np.ones(4), jet6=jb)
+    assert ei.value.status == VP_ERR_ARG
