@@ -193,6 +193,7 @@ def main():
     ap.add_argument("--no-geometry-leg", action="store_true")
     ap.add_argument("--no-solve-leg", action="store_true")
     ap.add_argument("--solve-panels", type=int, default=256, help="panels of 16 nodes in the Dirichlet-solve leg")
+    ap.add_argument("--solve-triangles", type=int, default=60000, help="triangles of the Dirichlet-solve leg's mesh")
     ap.add_argument("--refine-levels", type=int, default=3)
     ap.add_argument("--no-serve-leg", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
@@ -290,7 +291,8 @@ def main():
         rec["geometry"] = geometry_leg(torch, P, args.steps)
     if not args.no_solve_leg:
         log("bench: Dirichlet solve leg, %d panels" % args.solve_panels)
-        rec["solve"] = solve_leg(torch, args.solve_panels, max(1, min(args.steps, 10)))
+        rec["solve"] = solve_leg(torch, args.solve_panels, int(args.solve_triangles * args.scale),
+                                 max(1, min(args.steps, 10)))
     if not args.no_fp32_leg:
         log("bench: generating disk-2M workload")
         Q = config_problem(3, scale=args.scale)
@@ -357,37 +359,45 @@ def geometry_leg(torch, P, steps):
                                               and np.all(sgn[sgn != np.asarray(P.geom["sgn"])] == 0))}
 
 
-def solve_leg(torch, n_pan, steps, q=16):
-    """Interior Dirichlet problem inside a three-lobed star (vp_dirichlet_solve):
-    GMRES whose product is the double layer at the boundary nodes, from a zero
-    start in each timed solve; then u = D[mu] at interior points against the
-    exact harmonic function whose trace is the data."""
+def solve_leg(torch, n_pan, n_tri, steps, q=16):
+    """Interior Dirichlet problem -Lap u = f inside a three-lobed star
+    (vp_dirichlet_solve): f a Gaussian at the volume nodes of a curved
+    triangulation, the right-hand side g - V[f] and GMRES whose product is the
+    double layer at the boundary nodes, from a zero start in each timed solve;
+    then u = V[f] + D[mu] at interior points against the exact solution
+    w(|x|) + Re((z - z0)^3), w the radial solution of the Gaussian source."""
+    from scipy.special import exp1
     from paper_2409_11998_amd import Plan, boundary_frame, boundary_jets, dirichlet_solve
-    from workloads.problems import StarCurve, panel_nodes, star_params
+    from workloads.mesh import curve_mesh
+    from workloads.problems import StarCurve, gauss_jets, panel_nodes, star_params
     f64 = torch.float64
-    bx, by, bnx, bny, bw, _ = panel_nodes(StarCurve(**star_params(3, r=0.8)), n_pan, q)
-    z0 = complex(0.1, -0.05)
+    curve = StarCurve(**star_params(3, r=0.8))
+    x, y, w, _ = curve_mesh(curve, n_tri, 3)
+    bx, by, bnx, bny, bw, _ = panel_nodes(curve, n_pan, q)
+    s2, z0 = 0.1, complex(0.1, -0.05)
+    gauss = ((1.0, 0.0, 0.0, np.sqrt(s2)),)
 
-    def uex(x, y):
-        return ((x + 1j * y - z0) ** 3).real + 0.3 * x - 0.2 * y + 1.0
+    def uex(px, py):
+        r = np.hypot(px, py)
+        return 0.25 * s2 * (2 * np.log(1 / r) - exp1(r * r / s2) + exp1(1 / s2)) + ((px + 1j * py - z0) ** 3).real
 
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=f64, device="cuda")
+    sx, sy, sw, fs = t(x), t(y), t(w), t(gauss_jets(x, y, gauss)[0])
     dx, dy, dnx, dny, dw = (t(a) for a in (bx, by, bnx, bny, bw))
-    e0 = torch.zeros(0, dtype=f64, device="cuda")
     t0 = time.perf_counter()
     fr = boundary_frame(dx, dy, q, dx, dy)
     geom = dict(r=torch.zeros_like(dx), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
                 gamma4=fr["gamma4"], sgn=torch.ones(dx.numel(), dtype=torch.int8, device="cuda"))
-    plan = Plan(e0, e0, e0, dx, dy, dnx, dny, dw, dx, dy, geom, tol=1e-10, precision=1, kinds=4)
+    plan = Plan(sx, sy, sw, dx, dy, dnx, dny, dw, dx, dy, geom, tol=1e-10, precision=1, kinds=5)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
-    g = t(uex(bx, by))
+    g, jb = t(uex(bx, by)), t(gauss_jets(bx, by, gauss))
     mu = torch.zeros_like(dx)
     stat = {}
 
     def solve():
         mu.zero_()
-        _, stat["its"], stat["res"] = dirichlet_solve(plan, q, dx, dy, fr["pan"], fr["u"], g, mu=mu)
+        _, stat["its"], stat["res"] = dirichlet_solve(plan, q, dx, dy, fr["pan"], fr["u"], g, mu=mu, f=fs, jet6=jb)
 
     solve()
     el = time_steps(torch, solve, steps)
@@ -402,14 +412,15 @@ def solve_leg(torch, n_pan, steps, q=16):
     ftx, fty = t(tx), t(ty)
     fi = boundary_frame(dx, dy, q, ftx, fty)
     gi = {kk: fi[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
-    pi = Plan(e0, e0, e0, dx, dy, dnx, dny, dw, ftx, fty, gi, tol=1e-10, precision=1, kinds=4)
-    u = pi.eval(mu=mu, mu_jet=boundary_jets(dx, dy, q, mu, fi["pan"], fi["u"], 4)).cpu().numpy()
+    pi = Plan(sx, sy, sw, dx, dy, dnx, dny, dw, ftx, fty, gi, tol=1e-10, precision=1, kinds=5)
+    u = pi.eval(f=fs, jet6=t(gauss_jets(tx, ty, gauss)), mu=mu,
+                mu_jet=boundary_jets(dx, dy, q, mu, fi["pan"], fi["u"], 4)).cpu().numpy()
     pi.close()
-    return {"workload": "three-lobed star, %d panels of %d Gauss-Legendre nodes, harmonic data, fp64 tol1e-10"
-                        % (n_pan, q), "n_nodes": int(bx.size), "fine_grid": list(info["fine"]),
+    return {"workload": "three-lobed star, Gaussian source at %d volume nodes (%d curved triangles), %d panels of "
+                        "%d Gauss-Legendre nodes, fp64 tol1e-10" % (x.size, n_tri, n_pan, q),
+            "n_src": int(x.size), "n_nodes": int(bx.size), "delta1": info["delta1"], "fine_grid": list(info["fine"]),
             "gmres_products": stat["its"], "rel_residual": stat["res"], "solve_ms": round(1e3 * el / steps, 3),
-            "ms_per_product": round(1e3 * el / steps / max(1, stat["its"] + 2), 4), "solves_timed": steps,
-            "plan_s": round(plan_s, 3), "interior_points": int(tx.size),
+            "solves_timed": steps, "plan_s": round(plan_s, 3), "interior_points": int(tx.size),
             "max_abs_err_interior_vs_exact": float(np.max(np.abs(u - uex(tx, ty))))}
 
 
