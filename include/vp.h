@@ -248,7 +248,7 @@ vp_status vp_boundary_jets(int64_t n_pan, int q, const double* bnd_x, const doub
  * correction of Sec. 5): mu at the boundary nodes solves
  * D_int[mu] = g - V[f], D_int the interior limit of the double layer at each
  * node (f absent: the Laplace equation, u = D[mu]).  Restarted GMRES(restart) with
- * modified Gram-Schmidt, whose product is this library's evaluation: mu's
+ * classical Gram-Schmidt applied twice, whose product is this library's evaluation: mu's
  * jets at the nodes from its panel interpolant (vp_boundary_jets), then
  * vp_eval of the double layer.
  *

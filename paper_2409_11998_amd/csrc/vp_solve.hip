@@ -3,13 +3,17 @@
 // Sec. 5): mu on the boundary nodes solves D_int[mu] = g - V[f], where D_int is
 // the interior limit of the double layer at each node and V[f] is this
 // library's volume potential at the nodes (f = 0: the Laplace equation,
-// u = D[mu]).  Restarted GMRES (modified
-// Gram-Schmidt, Givens rotations) whose product is this library's evaluation:
+// u = D[mu]).  Restarted GMRES (Givens rotations) whose product is this
+// library's evaluation:
 // the density's jets at the nodes from its panel interpolant
 // (vp_boundary_jets), then vp_eval of the double layer at the plan's targets,
-// which are the nodes themselves with r = 0 and sgn = +1.
+// which are the nodes themselves with r = 0 and sgn = +1.  Each Arnoldi step
+// orthogonalizes by classical Gram-Schmidt applied twice: the projections on
+// all basis vectors, then the norm, come back to the host in one copy, and
+// every sum is taken in a fixed order (the result does not depend on timing).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -21,6 +25,7 @@ namespace {
 
 constexpr int kSolveThreads = 256;
 constexpr int kDotBlocks = 256;
+constexpr int kMaxRestart = 200;
 
 __global__ __launch_bounds__(kSolveThreads) void k_dot(int64_t n, const double* __restrict__ a,
                                                        const double* __restrict__ b, double* __restrict__ part)
@@ -39,6 +44,52 @@ __global__ __launch_bounds__(kSolveThreads) void k_dot(int64_t n, const double* 
     }
 }
 
+// part[j][b] = block b's partial sum of V_j . w over its grid-stride share, for
+// the k1 vectors V_j = V + j ldv (grid: kDotBlocks x k1)
+__global__ __launch_bounds__(kSolveThreads) void k_proj_part(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                                             const double* __restrict__ w, double* __restrict__ part)
+{
+    __shared__ double red[kSolveThreads / 64];
+    const double* v = V + (int64_t)blockIdx.y * ldv;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s = fma(v[i], w[i], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+        part[(int64_t)blockIdx.y * kDotBlocks + blockIdx.x] = t;
+    }
+}
+
+// h[j] (+)= sum over b of part[j][b], a fixed binary tree per j (grid: k1 blocks of kDotBlocks threads)
+__global__ __launch_bounds__(kDotBlocks) void k_proj_sum(const double* __restrict__ part, double* __restrict__ h,
+                                                         int accumulate)
+{
+    __shared__ double t[kDotBlocks];
+    t[threadIdx.x] = part[(int64_t)blockIdx.x * kDotBlocks + threadIdx.x];
+    __syncthreads();
+    for (int o = kDotBlocks / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) t[threadIdx.x] += t[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) h[blockIdx.x] = accumulate ? h[blockIdx.x] + t[0] : t[0];
+}
+
+// w -= sum_j c[j] V_j, j < k1 (c on the device)
+__global__ __launch_bounds__(kSolveThreads) void k_sub_proj(int64_t n, int k1, const double* __restrict__ V,
+                                                            int64_t ldv, const double* __restrict__ c,
+                                                            double* __restrict__ w)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = w[i];
+    for (int j = 0; j < k1; ++j) s = fma(-c[j], V[(int64_t)j * ldv + i], s);
+    w[i] = s;
+}
+
 // y = a x + b y (b = 0: y is not read, so uninitialized memory may be the target)
 __global__ __launch_bounds__(kSolveThreads) void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
                                                          double* __restrict__ y)
@@ -55,8 +106,51 @@ struct Solver {
     const int32_t* pan;
     hipStream_t st;
     double* jets = nullptr;  // [5][n]
-    double* part = nullptr;  // [kDotBlocks]
+    double* part = nullptr;  // [kMaxRestart + 2][kDotBlocks]
+    double* hd = nullptr;    // [kMaxRestart + 2]: projections of the current step, then its norm squared
+    double* tmp = nullptr;   // [kMaxRestart + 1]: the second Gram-Schmidt pass's projections
     std::vector<double> h_part = std::vector<double>(kDotBlocks);
+    std::vector<double> h_host = std::vector<double>(kMaxRestart + 2);
+
+    vp_status launched()
+    {
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? VP_OK : set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
+    }
+    // out[j] (+)= V_j . w for j < k1, on the device
+    vp_status project(const double* V, int k1, const double* w, double* out, bool accumulate)
+    {
+        hipLaunchKernelGGL(k_proj_part, dim3(kDotBlocks, (unsigned)k1), dim3(kSolveThreads), 0, st, n, V, n, w, part);
+        hipLaunchKernelGGL(k_proj_sum, dim3((unsigned)k1), dim3(kDotBlocks), 0, st, part, out, accumulate ? 1 : 0);
+        return launched();
+    }
+    // w -= V c over k1 vectors
+    vp_status subtract(const double* V, int k1, const double* c, double* w)
+    {
+        hipLaunchKernelGGL(k_sub_proj, dim3((unsigned)((n + kSolveThreads - 1) / kSolveThreads)), dim3(kSolveThreads),
+                           0, st, n, k1, V, n, c, w);
+        return launched();
+    }
+    // Arnoldi step on w against V_0..V_k: two classical Gram-Schmidt passes, then
+    // ||w||^2; h[0..k] and h[k+1] = ||w|| on the host after one copy
+    vp_status orthogonalize(const double* V, int k, double* w, double* h)
+    {
+        const int k1 = k + 1;
+        vp_status s = project(V, k1, w, hd, false);
+        if (s == VP_OK) s = subtract(V, k1, hd, w);
+        if (s == VP_OK) s = project(V, k1, w, tmp, false);
+        if (s == VP_OK) s = subtract(V, k1, tmp, w);
+        if (s != VP_OK) return s;
+        hipLaunchKernelGGL(k_axpby, dim3((unsigned)((k1 + kSolveThreads - 1) / kSolveThreads)), dim3(kSolveThreads), 0,
+                           st, (int64_t)k1, 1.0, tmp, 1.0, hd);
+        if ((s = launched()) != VP_OK) return s;
+        if ((s = project(w, 1, w, hd + k1, false)) != VP_OK) return s;
+        hipError_t e = hipMemcpyAsync(h, hd, (size_t)(k1 + 1) * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
+        h[k1] = std::sqrt(std::max(h[k1], 0.0));
+        return VP_OK;
+    }
 
     vp_status matvec(const double* x, double* y)
     {
@@ -104,7 +198,7 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
     if ((f_src == nullptr) != (jet6 == nullptr)) return set_error(VP_ERR_ARG, "f_src and jet6 go together");
     if (f_src && (!(plan->kinds & VP_KIND_V) || plan->n_src == 0))
         return set_error(VP_ERR_ARG, "a volume source needs a plan with volume nodes and the volume kind");
-    if (!(tol > 0 && tol < 1) || max_iter < 1 || restart < 1 || restart > 200)
+    if (!(tol > 0 && tol < 1) || max_iter < 1 || restart < 1 || restart > kMaxRestart)
         return set_error(VP_ERR_ARG, "tol in (0,1), max_iter >= 1, restart in [1, 200]");
     const int64_t n = plan->n_bnd;
     const int m = restart;
@@ -116,7 +210,9 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
     if (e == hipSuccess) e = hipMalloc((void**)&w, (size_t)n * sizeof(double));
     if (e == hipSuccess && f_src) e = hipMalloc((void**)&rhs, (size_t)n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.jets, (size_t)5 * n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&S.part, kDotBlocks * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&S.part, (size_t)(kMaxRestart + 2) * kDotBlocks * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&S.hd, (kMaxRestart + 2) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&S.tmp, (kMaxRestart + 1) * sizeof(double));
     vp_status s = e == hipSuccess ? VP_OK : set_error(VP_ERR_OOM, "solve workspace");
     double gnorm = 0.0, rel = INFINITY;
     int it = 0;
@@ -149,16 +245,9 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
         int k = 0;
         for (; k < m && it < max_iter; ++k, ++it) {
             if ((s = S.matvec(Vc(k), w)) != VP_OK) break;
-            for (int i = 0; i <= k; ++i) {  // modified Gram-Schmidt
-                double hik = 0.0;
-                if ((s = S.dot(w, Vc(i), &hik)) != VP_OK) break;
-                H[(size_t)i * m + k] = hik;
-                if ((s = S.axpby(-hik, Vc(i), 1.0, w)) != VP_OK) break;
-            }
-            if (s != VP_OK) break;
-            double hn = 0.0;
-            if ((s = S.dot(w, w, &hn)) != VP_OK) break;
-            hn = std::sqrt(hn);
+            if ((s = S.orthogonalize(V, k, w, S.h_host.data())) != VP_OK) break;
+            for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = S.h_host[i];
+            const double hn = S.h_host[k + 1];
             H[(size_t)(k + 1) * m + k] = hn;
             if (hn > 0.0 && (s = S.axpby(1.0 / hn, w, 0.0, Vc(k + 1))) != VP_OK) break;
             for (int i = 0; i < k; ++i) {  // earlier rotations on the new column
@@ -208,6 +297,8 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
     if (rhs) (void)hipFree(rhs);
     if (S.jets) (void)hipFree(S.jets);
     if (S.part) (void)hipFree(S.part);
+    if (S.hd) (void)hipFree(S.hd);
+    if (S.tmp) (void)hipFree(S.tmp);
     if (iters) *iters = it;
     if (resid) *resid = rel;
     if (s == VP_OK && !(rel <= tol * 10.0)) s = set_error(VP_ERR_TOL, "GMRES did not reach the tolerance");
