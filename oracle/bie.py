@@ -117,3 +117,64 @@ def solution_at(P, mu, tx, ty, f_src=None, jet6=None):
 def double_layer_at(P, mu, tx, ty):
     """u = D[mu] at targets (tx, ty)."""
     return solution_at(P, mu, tx, ty)
+
+
+# ---------------------------------------------------------------------------
+# The exterior Dirichlet and the interior Neumann problems (Sec. 5).  Both
+# lead to the operator A+[x] = x/2 + (principal value of D[x]) + (sum of
+# w_j x_j), which in terms of the interior limit is D_int[x] + x + (w . x):
+# * exterior Dirichlet, u = D_E[mu] outside, D_E the double layer plus the
+#   integral of mu (the kernel's +1); its exterior limit on the boundary is
+#   mu/2 + D[mu] + integral of mu = g (bounded solutions: no logarithmic
+#   term; for growth A log|x - x0| the caller moves that term into g);
+# * interior Neumann, Green's representation u = V[f] + S[du/dnu] - D[u]; on
+#   the boundary u/2 + D[u] = V[f] + S[g].  That operator annihilates
+#   constants (D_int[1] = -1); the added integral of u makes it invertible
+#   and picks the solution whose boundary integral vanishes (the data are
+#   consistent by Gauss's theorem, so the added term is zero at the solution).
+
+
+def plus_operator_matrix(P):
+    """Dense matrix of x -> D_int[x] + x + (w . x) at the nodes of P."""
+    n = P.n_bnd
+    return interior_double_layer_matrix(P) + np.eye(n) + np.outer(np.ones(n), P.bnd_w)
+
+
+def single_layer_at_nodes(P, g):
+    """S[g] at the nodes of the on-boundary problem P (g's jets from the panels)."""
+    Q = copy.copy(P)
+    Q.sigma = np.asarray(g, float)
+    Q.sigma_jet = G.density_jets(P.bnd_x, P.bnd_y, P.info["q"], Q.sigma, P.info["pan"], P.info["u"], 2)
+    return evaluate(Q, kinds="S")["S"]
+
+
+def solve_exterior_dirichlet(P, g):
+    """mu with mu/2 + D[mu] + (integral of mu) = g at the nodes."""
+    return np.linalg.solve(plus_operator_matrix(P), np.asarray(g, float))
+
+
+def exterior_solution_at(P, mu, tx, ty):
+    """u = D[mu] + integral of mu at exterior targets (tx, ty)."""
+    return solution_at(P, mu, tx, ty) + float(np.dot(P.bnd_w, mu))
+
+
+def solve_neumann(P, g, f_src=None, jet6=None):
+    """Boundary values u with u/2 + D[u] = V[f] + S[g] and zero boundary integral."""
+    b = single_layer_at_nodes(P, g)
+    if f_src is not None:
+        b = b + volume_at_nodes(P, f_src, jet6)
+    return np.linalg.solve(plus_operator_matrix(P), b)
+
+
+def neumann_solution_at(P, ub, g, tx, ty, f_src=None, jet6=None):
+    """u = V[f] + S[g] - D[ub] at interior targets (tx, ty)."""
+    q = P.info["q"]
+    fr = G.boundary_frame(P.bnd_x, P.bnd_y, q, tx, ty)
+    geom = {k: fr[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    mu = -np.asarray(ub, float)
+    T = _Layer(P.bnd_x, P.bnd_y, P.bnd_nx, P.bnd_ny, P.bnd_w, np.asarray(tx, float), np.asarray(ty, float),
+               geom, mu, G.density_jets(P.bnd_x, P.bnd_y, q, mu, fr["pan"], fr["u"], 4),
+               src=(P.src_x, P.src_y, P.src_w), f_src=f_src, jet6=jet6)
+    T.sigma = np.asarray(g, float)
+    T.sigma_jet = G.density_jets(P.bnd_x, P.bnd_y, q, T.sigma, fr["pan"], fr["u"], 2)
+    return evaluate(T, kinds="VSD" if f_src is not None else "SD", delta=delta1_of(P))["total"]

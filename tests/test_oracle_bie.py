@@ -13,7 +13,15 @@ D_int assembled from the method's evaluation at the boundary nodes):
   outside a radial mass, V is -M ln|x| / (2 pi));
 * the same source inside a lobed star, u = w(|x|) + Re((z - z0)^3): there V[f]
   on the boundary is far from zero, so the sign of the volume term in the
-  boundary equation is checked too.
+  boundary equation is checked too;
+* the exterior Dirichlet problem (u = D[mu] + integral of mu outside): on the
+  circle g = cos 3t gives mu = 2 cos 3t and u = r^-3 cos 3t; outside a lobed
+  star u = Re(1/(z - z0)) + 0.3 is recovered with integral of mu = u at
+  infinity = 0.3;
+* the interior Neumann problem (Green's representation, boundary values of
+  zero mean): on the circle g = 3 cos 3t gives u = cos 3t on it and r^3 cos 3t
+  inside; with the Gaussian source on the disk and inside the star, the
+  closed forms above up to their boundary mean.
 """
 import numpy as np
 from numpy.polynomial.legendre import leggauss
@@ -121,3 +129,85 @@ def test_star_poisson_recovered():
     print("star Poisson: max |V| on the boundary", np.max(np.abs(v_bnd)), "interior error", e)
     assert np.max(np.abs(v_bnd)) >= 0.01          # the volume term matters on this boundary
     assert e <= 1e-5
+
+
+def _wr(r, s2=0.1):
+    return 0.25 * s2 * (2 * np.log(1 / r) - exp1(r * r / s2) + exp1(1 / s2))
+
+
+def _wdr(r, s2=0.1):
+    """w'(r)."""
+    return -(s2 / (2 * r)) * (1 - np.exp(-r * r / s2))
+
+
+def _circle_ext_neu_errors(n_pan):
+    bx, by, nx, ny, w, t = _circle(n_pan)
+    P = bie.on_boundary_problem(bx, by, nx, ny, w, 16)
+    rng = np.random.default_rng(0)
+    mu = bie.solve_exterior_dirichlet(P, np.cos(3 * t))
+    th, rr = rng.uniform(0, 2 * np.pi, 100), rng.uniform(1.05, 3, 100)
+    ue = bie.exterior_solution_at(P, mu, rr * np.cos(th), rr * np.sin(th))
+    ub = bie.solve_neumann(P, 3 * np.cos(3 * t))
+    th2, rr2 = rng.uniform(0, 2 * np.pi, 100), rng.uniform(0.1, 0.95, 100)
+    un = bie.neumann_solution_at(P, ub, 3 * np.cos(3 * t), rr2 * np.cos(th2), rr2 * np.sin(th2))
+    return (np.max(np.abs(mu - 2 * np.cos(3 * t))), np.max(np.abs(ue - rr ** -3 * np.cos(3 * th))),
+            np.max(np.abs(ub - np.cos(3 * t))), np.max(np.abs(un - rr2 ** 3 * np.cos(3 * th2))))
+
+
+def test_circle_exterior_dirichlet_and_neumann_closed_forms():
+    coarse = _circle_ext_neu_errors(16)
+    fine = _circle_ext_neu_errors(32)
+    print("circle (ext mu, ext u, neu u_b, neu u): 16 panels", coarse, "32 panels", fine)
+    assert max(fine) <= 1e-6
+    assert all(f <= c / 10 for f, c in zip(fine, coarse))
+
+
+def test_disk_neumann_with_source():
+    gauss = ((1.0, 0.0, 0.0, np.sqrt(0.1)),)
+    D = disk_problem(2000, seed=1, gauss=gauss)
+    bx, by, nx, ny, w, t = _circle(48)
+    P = bie.on_boundary_problem(bx, by, nx, ny, w, 16, src=(D.src_x, D.src_y, D.src_w))
+    g = _wdr(1.0) + 3 * np.cos(3 * t)
+    ub = bie.solve_neumann(P, g, D.f_src, gauss_jets(bx, by, gauss))
+    rng = np.random.default_rng(3)
+    th, rr = rng.uniform(0, 2 * np.pi, 100), rng.uniform(0.1, 0.95, 100)
+    tx, ty = rr * np.cos(th), rr * np.sin(th)
+    u = bie.neumann_solution_at(P, ub, g, tx, ty, D.f_src, gauss_jets(tx, ty, gauss))
+    e_b, e_u = np.max(np.abs(ub - np.cos(3 * t))), np.max(np.abs(u - _wr(rr) - rr ** 3 * np.cos(3 * th)))
+    print("disk Neumann with source: boundary", e_b, "interior", e_u)
+    assert e_b <= 2e-6 and e_u <= 5e-6
+
+
+def test_star_exterior_dirichlet_and_neumann():
+    gauss = ((1.0, 0.0, 0.0, np.sqrt(0.1)),)
+    curve = StarCurve(**star_params(3, r=0.8))
+    bx, by, bnx, bny, bw, _ = panel_nodes(curve, 32, 16)
+    z0 = complex(0.1, -0.05)
+    rng = np.random.default_rng(4)
+    k = rng.integers(0, bx.size, 150)
+    cx, cy = np.mean(bx), np.mean(by)
+    # exterior: a decaying harmonic plus a constant
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, 16)
+    uext = lambda x, y: (1 / (x + 1j * y - z0)).real + 0.3
+    mu = bie.solve_exterior_dirichlet(P, uext(bx, by))
+    s = rng.uniform(1.03, 2.5, 150)
+    tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
+    e_ext = np.max(np.abs(bie.exterior_solution_at(P, mu, tx, ty) - uext(tx, ty)))
+    # Neumann with the source
+    x, y, w, _ = curve_mesh(curve, 1500, 3)
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, 16, src=(x, y, w))
+    z = bx + 1j * by
+    rb = np.abs(z)
+    g = ((_wdr(rb) * bx / rb + (3 * (z - z0) ** 2).real) * bnx
+         + (_wdr(rb) * by / rb - (3 * (z - z0) ** 2).imag) * bny)
+    uin = lambda px, py: _wr(np.hypot(px, py)) + ((px + 1j * py - z0) ** 3).real
+    f = gauss_jets(x, y, gauss)[0]
+    ub = bie.solve_neumann(P, g, f, gauss_jets(bx, by, gauss))
+    c = np.dot(bw, uin(bx, by)) / np.sum(bw)
+    s = rng.uniform(0.3, 0.97, 150)
+    tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
+    u = bie.neumann_solution_at(P, ub, g, tx, ty, f, gauss_jets(tx, ty, gauss))
+    e_b, e_u = np.max(np.abs(ub - uin(bx, by) + c)), np.max(np.abs(u - uin(tx, ty) + c))
+    print("star: exterior", e_ext, "integral of mu", np.dot(bw, mu), "Neumann boundary", e_b, "interior", e_u)
+    assert e_ext <= 2e-4 and abs(np.dot(bw, mu) - 0.3) <= 1e-6
+    assert e_b <= 1e-5 and e_u <= 1e-5
