@@ -267,7 +267,7 @@ vp_status vp_boundary_jets(int64_t n_pan, int q, const double* bnd_x, const doub
  *   restart in [1, 200].  iters, resid (host, may be NULL): products taken
  *   and final relative residual.
  * Runs on the plan's stream and synchronizes it before returning.  Scratch
- * of (restart + 7) n doubles (one more n with a source) is allocated for the call.  VP_ERR_ARG for a
+ * of (restart + 8) n doubles is allocated for the call.  VP_ERR_ARG for a
  * plan without D, or whose nodes or targets are not the n_pan*q panel nodes,
  * for only one of f_src and jet6, or for a source on a plan without V or
  * volume nodes;
@@ -276,6 +276,43 @@ vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double*
                              const int32_t* pan, const double* u, const double* g, const double* f_src,
                              const double* jet6, double* mu, double tol, int max_iter, int restart, int* iters,
                              double* resid);
+
+/* ------------------------------------------------------------------------
+ * The exterior Dirichlet and the interior Neumann problems (Sec. 5).  Both
+ * solve A x = b at the nodes with A x = x/2 + D[x] + (w . x), that is
+ * D_int[x] + x + sum_j w_j x_j (w = bnd_w, the boundary quadrature weights),
+ * by the GMRES of vp_dirichlet_solve, on the same kind of plan (its targets
+ * the boundary nodes with r = 0, sgn = +1 and their frames; pan, u from
+ * vp_boundary_frame at the nodes).  bnd_w [n_pan*q] (device).
+ *
+ * vp_exterior_dirichlet_solve: Laplace's equation outside the curve with
+ *   u = g on it and u bounded: u = D[mu] + (integral of mu) outside (the
+ *   double layer with the kernel's +1), whose exterior limit on the boundary
+ *   is mu/2 + D[mu] + (integral of mu) = g.  For growth A log|x - x0| at
+ *   infinity pass g - A log|x' - x0|.  mu [n_pan*q]: initial guess in,
+ *   solution out.
+ * vp_neumann_solve: -Lap u = f inside with du/dnu = g on the boundary, by
+ *   Green's representation u = V[f] + S[g] - D[u]; on the boundary
+ *   u/2 + D[u] = V[f] + S[g].  The added integral of u removes the constants
+ *   that operator annihilates, so ub [n_pan*q] (initial guess in, boundary
+ *   values out) has zero boundary integral (u is fixed up to a constant;
+ *   the data are consistent when the integral of g is minus that of f).
+ *   The plan needs S and D (and V with a source: f_src at its volume nodes,
+ *   jet6 [6][n_pan*q] f's jets at the boundary nodes, or both NULL).  g's
+ *   jets come from its panel interpolant.  The interior solution is then
+ *   vp_eval with f, sigma = g and mu = -ub on a plan with interior targets.
+ *
+ * Both synchronize the plan's stream, allocate (restart + 8) n doubles of
+ * scratch, and return VP_ERR_ARG / VP_ERR_TOL as vp_dirichlet_solve does
+ * (and VP_ERR_ARG for a NULL bnd_w, or a Neumann plan without S). */
+vp_status vp_exterior_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
+                                      const double* bnd_y, const double* bnd_w, const int32_t* pan, const double* u,
+                                      const double* g, double* mu, double tol, int max_iter, int restart,
+                                      int* iters, double* resid);
+vp_status vp_neumann_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,
+                           const double* bnd_w, const int32_t* pan, const double* u, const double* g,
+                           const double* f_src, const double* jet6, double* ub, double tol, int max_iter,
+                           int restart, int* iters, double* resid);
 
 /* Release the plan and its device memory (synchronizes its stream). NULL is a no-op. */
 vp_status vp_destroy(vp_plan_t plan);

@@ -22,7 +22,8 @@ EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "v
             "vp_batch_create", "vp_batch_eval", "vp_batch_destroy", "vp_batch_last_error",
             "vp_server_create", "vp_server_submit", "vp_server_poll", "vp_server_wait", "vp_server_get_stats",
             "vp_server_destroy", "vp_server_last_error", "vp_refine_attach", "vp_layer_refine",
-            "vp_boundary_frame", "vp_boundary_jets", "vp_dirichlet_solve"]
+            "vp_boundary_frame", "vp_boundary_jets", "vp_dirichlet_solve", "vp_exterior_dirichlet_solve",
+            "vp_neumann_solve"]
 
 
 class VPError(RuntimeError):
@@ -120,6 +121,14 @@ def lib():
         L.vp_dirichlet_solve.argtypes = [vp, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.vp_dirichlet_solve.restype = ctypes.c_int
+        L.vp_exterior_dirichlet_solve.argtypes = [vp, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
+                                                  ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ctypes.c_double)]
+        L.vp_exterior_dirichlet_solve.restype = ctypes.c_int
+        L.vp_neumann_solve.argtypes = [vp, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
+                                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.vp_neumann_solve.restype = ctypes.c_int
         L.vp_destroy.argtypes = [vp]
         L.vp_destroy.restype = ctypes.c_int
         L.vp_last_error.argtypes = []
@@ -475,3 +484,39 @@ def dirichlet_solve(plan, q, bnd_x, bnd_y, pan, u, g, mu=None, tol=1e-12, max_it
                                     _ptr(jet6, f64), _ptr(mu, f64), tol,
                                     max_iter, restart, ctypes.byref(it), ctypes.byref(res)))
     return mu, it.value, res.value
+
+
+def exterior_dirichlet_solve(plan, q, bnd_x, bnd_y, bnd_w, pan, u, g, mu=None, tol=1e-12, max_iter=200, restart=50):
+    """mu with mu/2 + D[mu] + (integral of mu) = g at the panel nodes
+    (vp_exterior_dirichlet_solve); u = D[mu] + (integral of mu) outside.
+    Returns (mu, products, relative residual)."""
+    import torch
+    f64 = torch.float64
+    n = bnd_x.numel()
+    if mu is None:
+        mu = torch.zeros(n, dtype=f64, device=g.device)
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    _check(lib().vp_exterior_dirichlet_solve(plan.handle, n // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64),
+                                             _ptr(bnd_w, f64), _ptr(pan, torch.int32), _ptr(u, f64), _ptr(g, f64),
+                                             _ptr(mu, f64), tol, max_iter, restart, ctypes.byref(it),
+                                             ctypes.byref(res)))
+    return mu, it.value, res.value
+
+
+def neumann_solve(plan, q, bnd_x, bnd_y, bnd_w, pan, u, g, ub=None, tol=1e-12, max_iter=200, restart=50, f=None,
+                  jet6=None):
+    """Boundary values ub (zero boundary integral) with ub/2 + D[ub] = V[f] + S[g]
+    (vp_neumann_solve); u = V[f] + S[g] - D[ub] inside.  Returns (ub, products,
+    relative residual)."""
+    import torch
+    f64 = torch.float64
+    n = bnd_x.numel()
+    if ub is None:
+        ub = torch.zeros(n, dtype=f64, device=g.device)
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    _check(lib().vp_neumann_solve(plan.handle, n // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64), _ptr(bnd_w, f64),
+                                  _ptr(pan, torch.int32), _ptr(u, f64), _ptr(g, f64), _ptr(f, f64), _ptr(jet6, f64),
+                                  _ptr(ub, f64), tol, max_iter, restart, ctypes.byref(it), ctypes.byref(res)))
+    return ub, it.value, res.value

@@ -90,6 +90,14 @@ __global__ __launch_bounds__(kSolveThreads) void k_sub_proj(int64_t n, int k1, c
     w[i] = s;
 }
 
+// y += x + c[0] (c on the device: the weighted integral of x)
+__global__ __launch_bounds__(kSolveThreads) void k_plus(int64_t n, const double* __restrict__ x,
+                                                        const double* __restrict__ c, double* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += x[i] + c[0];
+}
+
 // y = a x + b y (b = 0: y is not read, so uninitialized memory may be the target)
 __global__ __launch_bounds__(kSolveThreads) void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
                                                          double* __restrict__ y)
@@ -105,10 +113,11 @@ struct Solver {
     const double *bx, *by, *upar;
     const int32_t* pan;
     hipStream_t st;
+    const double* bw = nullptr;  // boundary weights: the operator x/2 + D[x] + (w . x) when set
     double* jets = nullptr;  // [5][n]
     double* part = nullptr;  // [kMaxRestart + 2][kDotBlocks]
     double* hd = nullptr;    // [kMaxRestart + 2]: projections of the current step, then its norm squared
-    double* tmp = nullptr;   // [kMaxRestart + 1]: the second Gram-Schmidt pass's projections
+    double* tmp = nullptr;   // [kMaxRestart + 1]: the second Gram-Schmidt pass's projections; last: w . x
     std::vector<double> h_part = std::vector<double>(kDotBlocks);
     std::vector<double> h_host = std::vector<double>(kMaxRestart + 2);
 
@@ -152,11 +161,16 @@ struct Solver {
         return VP_OK;
     }
 
+    // y = D_int[x], or D_int[x] + x + (w . x) = x/2 + D[x] + (w . x) with weights
     vp_status matvec(const double* x, double* y)
     {
         vp_status s = vp_boundary_jets(n_pan, q, bx, by, x, n, pan, upar, 4, jets, (void*)st);
-        if (s != VP_OK) return s;
-        return vp_eval(plan, nullptr, nullptr, nullptr, nullptr, x, jets, y);
+        if (s == VP_OK) s = vp_eval(plan, nullptr, nullptr, nullptr, nullptr, x, jets, y);
+        if (s != VP_OK || !bw) return s;
+        if ((s = project(bw, 1, x, tmp + kMaxRestart, false)) != VP_OK) return s;
+        hipLaunchKernelGGL(k_plus, dim3((unsigned)((n + kSolveThreads - 1) / kSolveThreads)), dim3(kSolveThreads), 0,
+                           st, n, x, tmp + kMaxRestart, y);
+        return launched();
     }
     vp_status dot(const double* a, const double* b, double* out)
     {
@@ -180,66 +194,73 @@ struct Solver {
     }
 };
 
-}  // namespace
-}  // namespace vp
-
-using namespace vp;
-
-extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
-                                        const double* bnd_y, const int32_t* pan, const double* u, const double* g,
-                                        const double* f_src, const double* jet6, double* mu, double tol,
-                                        int max_iter, int restart, int* iters, double* resid)
+vp_status check_solve_args(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,
+                           const int32_t* pan, const double* u, const double* g, const double* x, double tol,
+                           int max_iter, int restart)
 {
     if (!plan) return set_error(VP_ERR_ARG, "plan is NULL");
     if (!(plan->kinds & VP_KIND_D)) return set_error(VP_ERR_ARG, "the plan does not support the double layer");
     if (n_pan < 2 || q < 5 || q > 32 || plan->n_bnd != n_pan * q || plan->n_tgt != plan->n_bnd)
         return set_error(VP_ERR_ARG, "the plan's boundary nodes and targets must be the n_pan*q panel nodes");
-    if (!bnd_x || !bnd_y || !pan || !u || !g || !mu) return set_error(VP_ERR_ARG, "NULL array");
+    if (!bnd_x || !bnd_y || !pan || !u || !g || !x) return set_error(VP_ERR_ARG, "NULL array");
+    if (!(tol > 0 && tol < 1) || max_iter < 1 || restart < 1 || restart > kMaxRestart)
+        return set_error(VP_ERR_ARG, "tol in (0,1), max_iter >= 1, restart in [1, 200]");
+    return VP_OK;
+}
+
+vp_status check_source(vp_plan_t plan, const double* f_src, const double* jet6)
+{
     if ((f_src == nullptr) != (jet6 == nullptr)) return set_error(VP_ERR_ARG, "f_src and jet6 go together");
     if (f_src && (!(plan->kinds & VP_KIND_V) || plan->n_src == 0))
         return set_error(VP_ERR_ARG, "a volume source needs a plan with volume nodes and the volume kind");
-    if (!(tol > 0 && tol < 1) || max_iter < 1 || restart < 1 || restart > kMaxRestart)
-        return set_error(VP_ERR_ARG, "tol in (0,1), max_iter >= 1, restart in [1, 200]");
+    return VP_OK;
+}
+
+// Restarted GMRES for A x = b at the nodes, A = D_int or, with weights bw,
+// x/2 + D[x] + (w . x); make_rhs(S, b) writes b on the plan's stream.  x holds
+// the initial guess on entry.
+template <class MakeRhs>
+vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,
+                      const int32_t* pan, const double* u, const double* bw, MakeRhs&& make_rhs, double* x,
+                      double tol, int max_iter, int restart, int* iters, double* resid)
+{
     const int64_t n = plan->n_bnd;
     const int m = restart;
     Solver S{plan, n_pan, n, q, bnd_x, bnd_y, u, pan, plan->stream};
+    S.bw = bw;
     double* V = nullptr;  // [m+1][n] Krylov basis
     double* w = nullptr;  // [n]
-    double* rhs = nullptr;  // [n] g - V[f], with a volume source
+    double* b = nullptr;  // [n] right-hand side
     hipError_t e = hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&w, (size_t)n * sizeof(double));
-    if (e == hipSuccess && f_src) e = hipMalloc((void**)&rhs, (size_t)n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&b, (size_t)n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.jets, (size_t)5 * n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.part, (size_t)(kMaxRestart + 2) * kDotBlocks * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.hd, (kMaxRestart + 2) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.tmp, (kMaxRestart + 1) * sizeof(double));
     vp_status s = e == hipSuccess ? VP_OK : set_error(VP_ERR_OOM, "solve workspace");
-    double gnorm = 0.0, rel = INFINITY;
+    double bnorm = 0.0, rel = INFINITY;
     int it = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), z(m + 1), y(m);
     auto Vc = [&](int k) { return V + (size_t)k * n; };
-    if (s == VP_OK && f_src) {  // rhs = g - V[f] at the nodes
-        s = vp_volume(plan, f_src, jet6, rhs);
-        if (s == VP_OK) s = S.axpby(1.0, g, -1.0, rhs);
-        if (s == VP_OK) g = rhs;
-    }
-    if (s == VP_OK) s = S.dot(g, g, &gnorm);
-    gnorm = std::sqrt(gnorm);
-    if (s == VP_OK && gnorm == 0.0) {  // zero data: zero density
-        e = hipMemsetAsync(mu, 0, (size_t)n * sizeof(double), S.st);
+    if (s == VP_OK) s = make_rhs(S, b);
+    if (s == VP_OK) s = S.dot(b, b, &bnorm);
+    bnorm = std::sqrt(bnorm);
+    if (s == VP_OK && bnorm == 0.0) {  // zero data: zero solution
+        e = hipMemsetAsync(x, 0, (size_t)n * sizeof(double), S.st);
         if (e != hipSuccess) s = set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
         rel = 0.0;
     }
-    while (s == VP_OK && gnorm > 0.0 && it < max_iter) {
-        // r = g - A mu in V_0
-        if ((s = S.matvec(mu, Vc(0))) != VP_OK) break;
-        if ((s = S.axpby(1.0, g, -1.0, Vc(0))) != VP_OK) break;
+    while (s == VP_OK && bnorm > 0.0 && it < max_iter) {
+        // r = b - A x in V_0
+        if ((s = S.matvec(x, Vc(0))) != VP_OK) break;
+        if ((s = S.axpby(1.0, b, -1.0, Vc(0))) != VP_OK) break;
         double beta = 0.0;
         if ((s = S.dot(Vc(0), Vc(0), &beta)) != VP_OK) break;
         beta = std::sqrt(beta);
-        rel = beta / gnorm;
+        rel = beta / bnorm;
         if (rel <= tol) break;
-        if ((s = S.axpby(0.0, g, 1.0 / beta, Vc(0))) != VP_OK) break;
+        if ((s = S.axpby(0.0, b, 1.0 / beta, Vc(0))) != VP_OK) break;
         std::fill(z.begin(), z.end(), 0.0);
         z[0] = beta;
         int k = 0;
@@ -251,19 +272,19 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
             H[(size_t)(k + 1) * m + k] = hn;
             if (hn > 0.0 && (s = S.axpby(1.0 / hn, w, 0.0, Vc(k + 1))) != VP_OK) break;
             for (int i = 0; i < k; ++i) {  // earlier rotations on the new column
-                const double a = H[(size_t)i * m + k], b = H[(size_t)(i + 1) * m + k];
-                H[(size_t)i * m + k] = cs[i] * a + sn[i] * b;
-                H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * b;
+                const double a = H[(size_t)i * m + k], c = H[(size_t)(i + 1) * m + k];
+                H[(size_t)i * m + k] = cs[i] * a + sn[i] * c;
+                H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * c;
             }
-            const double a = H[(size_t)k * m + k], b = H[(size_t)(k + 1) * m + k];
-            const double rr = std::hypot(a, b);
+            const double a = H[(size_t)k * m + k], c = H[(size_t)(k + 1) * m + k];
+            const double rr = std::hypot(a, c);
             cs[k] = rr > 0.0 ? a / rr : 1.0;
-            sn[k] = rr > 0.0 ? b / rr : 0.0;
+            sn[k] = rr > 0.0 ? c / rr : 0.0;
             H[(size_t)k * m + k] = rr;
             H[(size_t)(k + 1) * m + k] = 0.0;
             z[k + 1] = -sn[k] * z[k];
             z[k] = cs[k] * z[k];
-            rel = std::fabs(z[k + 1]) / gnorm;
+            rel = std::fabs(z[k + 1]) / bnorm;
             if (rel <= tol || hn == 0.0) {
                 ++k;
                 ++it;
@@ -271,20 +292,20 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
             }
         }
         if (s != VP_OK) break;
-        // mu += V y with H y = z (upper triangular, k columns)
+        // x += V y with H y = z (upper triangular, k columns)
         for (int i = k - 1; i >= 0; --i) {
             double t = z[i];
             for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * y[j];
             y[i] = t / H[(size_t)i * m + i];
         }
-        for (int i = 0; i < k && s == VP_OK; ++i) s = S.axpby(y[i], Vc(i), 1.0, mu);
+        for (int i = 0; i < k && s == VP_OK; ++i) s = S.axpby(y[i], Vc(i), 1.0, x);
         if (rel <= tol) {
             // true residual of the update
-            if (s == VP_OK) s = S.matvec(mu, w);
-            if (s == VP_OK) s = S.axpby(1.0, g, -1.0, w);
+            if (s == VP_OK) s = S.matvec(x, w);
+            if (s == VP_OK) s = S.axpby(1.0, b, -1.0, w);
             double rn = 0.0;
             if (s == VP_OK) s = S.dot(w, w, &rn);
-            rel = std::sqrt(rn) / gnorm;
+            rel = std::sqrt(rn) / bnorm;
             if (rel <= tol * 10.0) break;  // the recurrence and the true residual agree to rounding
         }
     }
@@ -294,7 +315,7 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
     }
     if (V) (void)hipFree(V);
     if (w) (void)hipFree(w);
-    if (rhs) (void)hipFree(rhs);
+    if (b) (void)hipFree(b);
     if (S.jets) (void)hipFree(S.jets);
     if (S.part) (void)hipFree(S.part);
     if (S.hd) (void)hipFree(S.hd);
@@ -303,4 +324,54 @@ extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, co
     if (resid) *resid = rel;
     if (s == VP_OK && !(rel <= tol * 10.0)) s = set_error(VP_ERR_TOL, "GMRES did not reach the tolerance");
     return s;
+}
+
+}  // namespace
+}  // namespace vp
+
+using namespace vp;
+
+extern "C" vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
+                                        const double* bnd_y, const int32_t* pan, const double* u, const double* g,
+                                        const double* f_src, const double* jet6, double* mu, double tol,
+                                        int max_iter, int restart, int* iters, double* resid)
+{
+    vp_status s = check_solve_args(plan, n_pan, q, bnd_x, bnd_y, pan, u, g, mu, tol, max_iter, restart);
+    if (s == VP_OK) s = check_source(plan, f_src, jet6);
+    if (s != VP_OK) return s;
+    auto rhs = [&](Solver& S, double* b) {  // b = g - V[f]
+        if (!f_src) return S.axpby(1.0, g, 0.0, b);
+        vp_status r = vp_volume(plan, f_src, jet6, b);
+        return r == VP_OK ? S.axpby(1.0, g, -1.0, b) : r;
+    };
+    return gmres_solve(plan, n_pan, q, bnd_x, bnd_y, pan, u, nullptr, rhs, mu, tol, max_iter, restart, iters, resid);
+}
+
+extern "C" vp_status vp_exterior_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
+                                                 const double* bnd_y, const double* bnd_w, const int32_t* pan,
+                                                 const double* u, const double* g, double* mu, double tol,
+                                                 int max_iter, int restart, int* iters, double* resid)
+{
+    vp_status s = check_solve_args(plan, n_pan, q, bnd_x, bnd_y, pan, u, g, mu, tol, max_iter, restart);
+    if (s != VP_OK) return s;
+    if (!bnd_w) return set_error(VP_ERR_ARG, "NULL array");
+    auto rhs = [&](Solver& S, double* b) { return S.axpby(1.0, g, 0.0, b); };
+    return gmres_solve(plan, n_pan, q, bnd_x, bnd_y, pan, u, bnd_w, rhs, mu, tol, max_iter, restart, iters, resid);
+}
+
+extern "C" vp_status vp_neumann_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,
+                                      const double* bnd_w, const int32_t* pan, const double* u, const double* g,
+                                      const double* f_src, const double* jet6, double* ub, double tol, int max_iter,
+                                      int restart, int* iters, double* resid)
+{
+    vp_status s = check_solve_args(plan, n_pan, q, bnd_x, bnd_y, pan, u, g, ub, tol, max_iter, restart);
+    if (s == VP_OK) s = check_source(plan, f_src, jet6);
+    if (s != VP_OK) return s;
+    if (!bnd_w) return set_error(VP_ERR_ARG, "NULL array");
+    if (!(plan->kinds & VP_KIND_S)) return set_error(VP_ERR_ARG, "the plan does not support the single layer");
+    auto rhs = [&](Solver& S, double* b) {  // b = V[f] + S[g]; g's jets staged in the product's jet buffer
+        vp_status r = vp_boundary_jets(n_pan, q, bnd_x, bnd_y, g, S.n, pan, u, 2, S.jets, (void*)S.st);
+        return r == VP_OK ? vp_eval(plan, f_src, jet6, g, S.jets, nullptr, nullptr, b) : r;
+    };
+    return gmres_solve(plan, n_pan, q, bnd_x, bnd_y, pan, u, bnd_w, rhs, ub, tol, max_iter, restart, iters, resid);
 }

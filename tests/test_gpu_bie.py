@@ -203,3 +203,133 @@ def test_source_arguments():
     with pytest.raises(VPError) as ei:          # a source on a plan without volume nodes
         _solve(torch, bx, by, nx, ny, w, 16, g, f=np.ones(4), jet6=jb)
     assert ei.value.status == VP_ERR_ARG
+
+
+def _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, src=None, f=None, sigma=None, mu=None):
+    """V[f] + S[sigma] + D[mu] at (tx, ty) through vp_eval, frames and jets from the panels."""
+    from paper_2409_11998_amd import Plan, boundary_frame, boundary_jets
+    dx, dy = _t(torch, bx), _t(torch, by)
+    ftx, fty = _t(torch, tx), _t(torch, ty)
+    fr = boundary_frame(dx, dy, q, ftx, fty)
+    geom = {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    e0 = torch.zeros(0, dtype=torch.float64, device="cuda")
+    sx, sy, sw = (e0, e0, e0) if src is None else (_t(torch, a) for a in src)
+    kinds = (1 if f is not None else 0) | (2 if sigma is not None else 0) | (4 if mu is not None else 0)
+    pl = Plan(sx, sy, sw, dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw), ftx, fty, geom, tol=1e-10,
+              precision=1, kinds=kinds)
+    args = {}
+    if f is not None:
+        args.update(f=_t(torch, f), jet6=_t(torch, gauss_jets(tx, ty, GAUSS)))
+    if sigma is not None:
+        st = _t(torch, sigma)
+        args.update(sigma=st, sigma_jet=boundary_jets(dx, dy, q, st, fr["pan"], fr["u"], 2).contiguous())
+    if mu is not None:
+        mt = _t(torch, mu)
+        args.update(mu=mt, mu_jet=boundary_jets(dx, dy, q, mt, fr["pan"], fr["u"], 4).contiguous())
+    out = pl.eval(**args).cpu().numpy()
+    pl.close()
+    return out
+
+
+def _node_plan(torch, bx, by, bnx, bny, bw, q, src=None, kinds=4):
+    from paper_2409_11998_amd import Plan, boundary_frame
+    dx, dy = _t(torch, bx), _t(torch, by)
+    fr = boundary_frame(dx, dy, q, dx, dy)
+    geom = dict(r=torch.zeros_like(dx), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
+                gamma4=fr["gamma4"], sgn=torch.ones(dx.numel(), dtype=torch.int8, device="cuda"))
+    e0 = torch.zeros(0, dtype=torch.float64, device="cuda")
+    sx, sy, sw = (e0, e0, e0) if src is None else (_t(torch, a) for a in src)
+    plan = Plan(sx, sy, sw, dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw), dx, dy, geom, tol=1e-10,
+                precision=1, kinds=kinds)
+    return plan, dx, dy, fr
+
+
+@pytest.mark.parametrize("domain", ["circle", "star"])
+def test_exterior_dirichlet(domain):
+    """mu/2 + D[mu] + integral of mu = g: mu against the oracle's direct solve,
+    u = D[mu] + integral of mu outside against the oracle and the closed form."""
+    torch = _gpu()
+    from paper_2409_11998_amd import exterior_dirichlet_solve
+    q = 16
+    if domain == "circle":
+        bx, by, bnx, bny, bw, t = _circle(32)
+        uext = lambda x, y: np.real((x + 1j * y) ** -3)
+    else:
+        bx, by, bnx, bny, bw, _ = panel_nodes(StarCurve(**star_params(3, r=0.8)), 32, q)
+        z0 = complex(0.1, -0.05)
+        uext = lambda x, y: np.real(1 / (x + 1j * y - z0)) + 0.3
+    plan, dx, dy, fr = _node_plan(torch, bx, by, bnx, bny, bw, q)
+    mu, its, res = exterior_dirichlet_solve(plan, q, dx, dy, _t(torch, bw), fr["pan"], fr["u"],
+                                            _t(torch, uext(bx, by)))
+    torch.cuda.synchronize()
+    plan.close()
+    mu = mu.cpu().numpy()
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q)
+    ref = bie.solve_exterior_dirichlet(P, uext(bx, by))
+    rng = np.random.default_rng(5)
+    k = rng.integers(0, bx.size, 300)
+    s = rng.uniform(1.03, 2.5, 300)
+    cx, cy = np.mean(bx), np.mean(by)
+    tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
+    u = _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, mu=mu) + float(np.dot(bw, mu))
+    u_ref = bie.exterior_solution_at(P, ref, tx, ty)
+    e_mu, e_u, e_x = oracle.rel_linf(mu, ref), oracle.rel_linf(u, u_ref), np.max(np.abs(u - uext(tx, ty)))
+    print(domain, "exterior: products", its, "residual", res, "mu vs oracle", e_mu, "u vs oracle", e_u, "vs exact", e_x)
+    assert res <= 1e-11 and e_mu <= 1e-8 and e_u <= 1e-8
+    assert e_x <= (5e-6 if domain == "circle" else 2e-4)      # targets reach r = 1.03 from the curve
+
+
+@pytest.mark.parametrize("domain", ["circle", "disk", "star"])
+def test_neumann(domain):
+    """u/2 + D[u] = V[f] + S[g] with zero boundary mean: boundary values against
+    the oracle's direct solve, u = V[f] + S[g] - D[u] inside against the oracle
+    and the closed form up to its boundary mean."""
+    torch = _gpu()
+    from paper_2409_11998_amd import neumann_solve
+    q = 16
+    wdr = lambda r: -(S2 / (2 * r)) * (1 - np.exp(-r * r / S2))
+    z0 = 0j
+    src = f = jb = None
+    if domain in ("circle", "disk"):
+        bx, by, bnx, bny, bw, t = _circle(32 if domain == "circle" else 48)
+        if domain == "disk":
+            D = disk_problem(2000, seed=1, gauss=GAUSS)
+            src, f = (D.src_x, D.src_y, D.src_w), D.f_src
+    else:
+        curve = StarCurve(**star_params(3, r=0.8))
+        bx, by, bnx, bny, bw, _ = panel_nodes(curve, 32, q)
+        x, y, w, _ = curve_mesh(curve, 1500, 3)
+        src, f = (x, y, w), gauss_jets(x, y, GAUSS)[0]
+        z0 = complex(0.1, -0.05)
+    z = bx + 1j * by
+    rb = np.abs(z)
+    with_src = src is not None
+    g = ((3 * (z - z0) ** 2).real * bnx - (3 * (z - z0) ** 2).imag * bny
+         + ((wdr(rb) * (bx * bnx + by * bny) / rb) if with_src else 0.0))
+    uin = lambda px, py: ((_w_radial(np.hypot(px, py)) if with_src else 0.0) + np.real((px + 1j * py - z0) ** 3))
+    if with_src:
+        jb = gauss_jets(bx, by, GAUSS)
+    plan, dx, dy, fr = _node_plan(torch, bx, by, bnx, bny, bw, q, src=src, kinds=7 if with_src else 6)
+    kw = dict(f=_t(torch, f), jet6=_t(torch, jb)) if with_src else {}
+    ub, its, res = neumann_solve(plan, q, dx, dy, _t(torch, bw), fr["pan"], fr["u"], _t(torch, g), **kw)
+    torch.cuda.synchronize()
+    plan.close()
+    ub = ub.cpu().numpy()
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q, src=src)
+    ref = bie.solve_neumann(P, g, f, jb)
+    rng = np.random.default_rng(6)
+    k = rng.integers(0, bx.size, 300)
+    s = rng.uniform(0.2, 0.95, 300)
+    cx, cy = np.mean(bx), np.mean(by)
+    tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
+    u = _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, src=src, f=f, sigma=g, mu=-ub)
+    u_ref = bie.neumann_solution_at(P, ref, g, tx, ty, f, gauss_jets(tx, ty, GAUSS) if with_src else None)
+    c = np.dot(bw, uin(bx, by)) / np.sum(bw)
+    e_b, e_u = oracle.rel_linf(ub, ref), oracle.rel_linf(u, u_ref)
+    e_x = np.max(np.abs(u - uin(tx, ty) + c))
+    print(domain, "Neumann: products", its, "residual", res, "u_b vs oracle", e_b, "u vs oracle", e_u, "vs exact", e_x,
+          "boundary integral", float(np.dot(bw, ub)))
+    assert res <= 1e-11 and e_b <= 1e-8 and e_u <= 1e-8
+    assert e_x <= 1e-5
+    # zero up to the data's discrete inconsistency (the integrals of g and -f agree to ~1e-9 here)
+    assert abs(np.dot(bw, ub)) <= 1e-7 * np.max(np.abs(ub))
