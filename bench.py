@@ -365,9 +365,11 @@ def solve_leg(torch, n_pan, n_tri, steps, q=16):
     triangulation, the right-hand side g - V[f] and GMRES whose product is the
     double layer at the boundary nodes, from a zero start in each timed solve;
     then u = V[f] + D[mu] at interior points against the exact solution
-    w(|x|) + Re((z - z0)^3), w the radial solution of the Gaussian source."""
+    w(|x|) + Re((z - z0)^3), w the radial solution of the Gaussian source.
+    The interior Neumann problem with the same source and solution follows
+    (vp_neumann_solve; u = V[f] + S[g] - D[u_b], exact up to a constant)."""
     from scipy.special import exp1
-    from paper_2409_11998_amd import Plan, boundary_frame, boundary_jets, dirichlet_solve
+    from paper_2409_11998_amd import Plan, boundary_frame, boundary_jets, dirichlet_solve, neumann_solve
     from workloads.mesh import curve_mesh
     from workloads.problems import StarCurve, gauss_jets, panel_nodes, star_params
     f64 = torch.float64
@@ -388,7 +390,7 @@ def solve_leg(torch, n_pan, n_tri, steps, q=16):
     fr = boundary_frame(dx, dy, q, dx, dy)
     geom = dict(r=torch.zeros_like(dx), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
                 gamma4=fr["gamma4"], sgn=torch.ones(dx.numel(), dtype=torch.int8, device="cuda"))
-    plan = Plan(sx, sy, sw, dx, dy, dnx, dny, dw, dx, dy, geom, tol=1e-10, precision=1, kinds=5)
+    plan = Plan(sx, sy, sw, dx, dy, dnx, dny, dw, dx, dy, geom, tol=1e-10, precision=1, kinds=7)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     g, jb = t(uex(bx, by)), t(gauss_jets(bx, by, gauss))
@@ -401,6 +403,20 @@ def solve_leg(torch, n_pan, n_tri, steps, q=16):
 
     solve()
     el = time_steps(torch, solve, steps)
+    # Neumann data: the normal derivative of the same solution
+    z = bx + 1j * by
+    rb = np.abs(z)
+    wd = -(s2 / (2 * rb)) * (1 - np.exp(-rb * rb / s2))
+    gn = t((wd * bx / rb + (3 * (z - z0) ** 2).real) * bnx + (wd * by / rb - (3 * (z - z0) ** 2).imag) * bny)
+    ub = torch.zeros_like(dx)
+
+    def solve_n():
+        ub.zero_()
+        _, stat["its_n"], stat["res_n"] = neumann_solve(plan, q, dx, dy, dw, fr["pan"], fr["u"], gn, ub=ub, f=fs,
+                                                        jet6=jb)
+
+    solve_n()
+    el_n = time_steps(torch, solve_n, steps)
     info = plan.info()
     plan.close()
     # interior values: seeded points pulled toward the centroid from the nodes
@@ -412,16 +428,24 @@ def solve_leg(torch, n_pan, n_tri, steps, q=16):
     ftx, fty = t(tx), t(ty)
     fi = boundary_frame(dx, dy, q, ftx, fty)
     gi = {kk: fi[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
-    pi = Plan(sx, sy, sw, dx, dy, dnx, dny, dw, ftx, fty, gi, tol=1e-10, precision=1, kinds=5)
-    u = pi.eval(f=fs, jet6=t(gauss_jets(tx, ty, gauss)), mu=mu,
-                mu_jet=boundary_jets(dx, dy, q, mu, fi["pan"], fi["u"], 4)).cpu().numpy()
+    pi = Plan(sx, sy, sw, dx, dy, dnx, dny, dw, ftx, fty, gi, tol=1e-10, precision=1, kinds=7)
+    jt = t(gauss_jets(tx, ty, gauss))
+    u = pi.eval(f=fs, jet6=jt, mu=mu, mu_jet=boundary_jets(dx, dy, q, mu, fi["pan"], fi["u"], 4)).cpu().numpy()
+    mub = -ub
+    un = pi.eval(f=fs, jet6=jt, sigma=gn, sigma_jet=boundary_jets(dx, dy, q, gn, fi["pan"], fi["u"], 2).contiguous(),
+                 mu=mub, mu_jet=boundary_jets(dx, dy, q, mub, fi["pan"], fi["u"], 4)).cpu().numpy()
     pi.close()
+    cmean = float(np.dot(bw, uex(bx, by)) / np.sum(bw))
     return {"workload": "three-lobed star, Gaussian source at %d volume nodes (%d curved triangles), %d panels of "
                         "%d Gauss-Legendre nodes, fp64 tol1e-10" % (x.size, n_tri, n_pan, q),
             "n_src": int(x.size), "n_nodes": int(bx.size), "delta1": info["delta1"], "fine_grid": list(info["fine"]),
             "gmres_products": stat["its"], "rel_residual": stat["res"], "solve_ms": round(1e3 * el / steps, 3),
             "solves_timed": steps, "plan_s": round(plan_s, 3), "interior_points": int(tx.size),
-            "max_abs_err_interior_vs_exact": float(np.max(np.abs(u - uex(tx, ty))))}
+            "max_abs_err_interior_vs_exact": float(np.max(np.abs(u - uex(tx, ty)))),
+            "neumann": {"gmres_products": stat["its_n"], "rel_residual": stat["res_n"],
+                        "solve_ms": round(1e3 * el_n / steps, 3),
+                        "max_abs_err_interior_vs_exact_up_to_boundary_mean":
+                            float(np.max(np.abs(un - uex(tx, ty) + cmean)))}}
 
 
 def refine_leg(torch, P, levels, steps):
