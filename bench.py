@@ -331,7 +331,7 @@ def geometry_leg(torch, P, steps):
     """Local frame and double-layer jets of every target from the boundary panels
     alone (vp_boundary_frame, vp_boundary_jets) on the square workload; the
     distance and side against the exact square."""
-    from paper_2409_11998_amd import boundary_frame, boundary_jets
+    from paper_2409_11998_amd import boundary_frame, boundary_jets, volume_jets
     q = P.info["q"]
     f64 = torch.float64
     bx, by = (torch.as_tensor(a, dtype=f64, device="cuda") for a in (P.bnd_x, P.bnd_y))
@@ -345,6 +345,26 @@ def geometry_leg(torch, P, steps):
         jets()
     el_f = time_steps(torch, frame, steps)
     el_j = time_steps(torch, jets, steps)
+    # f's jets at the volume nodes from the triangles' quadratic interpolants
+    sx, sy, sf = (torch.as_tensor(a, dtype=f64, device="cuda") for a in (P.src_x, P.src_y, P.f_src))
+    vj = lambda: volume_jets(sx, sy, sf)
+    for _ in range(3):
+        vj()
+    el_v = time_steps(torch, vj, steps)
+    J = vj().cpu().numpy()
+    fin = np.all(np.isfinite(J), axis=0)
+    n_tri = P.n_src // 6
+    # triangles whose node spread has an axis ratio of at least 0.1 (not slivers)
+    X, Y = (np.asarray(a).reshape(-1, 6) for a in (P.src_x, P.src_y))
+    dxm, dym = X - X.mean(1, keepdims=True), Y - Y.mean(1, keepdims=True)
+    sxx, sxy, syy = (dxm * dxm).sum(1), (dxm * dym).sum(1), (dym * dym).sum(1)
+    rad = np.hypot(0.5 * (sxx - syy), sxy)
+    ratio = np.sqrt(np.maximum(0.5 * (sxx + syy) - rad, 0) / np.maximum(0.5 * (sxx + syy) + rad, 1e-300))
+    shaped = np.repeat(ratio >= 0.1, 6) & fin
+
+    def rel(rows, sel=fin):
+        ref = np.asarray(P.jet6)[rows]
+        return float(np.max(np.abs(J[rows][:, sel] - ref[:, sel])) / np.max(np.abs(ref)))
     r = fr["r"].cpu().numpy()
     sgn = fr["sgn"].cpu().numpy()
     return {"workload": "square-200k targets (%d) against %d boundary nodes in %d panels of %d" %
@@ -355,6 +375,13 @@ def geometry_leg(torch, P, steps):
             # the workload labels targets on the curve (mesh nodes on the square's edges)
             # with their interior limit +1; the frame reports them as on the curve, 0
             "sgn_differs_from_exact": int(np.count_nonzero(sgn != np.asarray(P.geom["sgn"]))),
+            "volume_jets_ms": round(1e3 * el_v / steps, 4), "volume_jets_triangles": n_tri,
+            "volume_jets_gbs": round(432.0 * n_tri * steps / el_v / 1e9, 1),
+            "volume_jets_nan_triangles": int(np.count_nonzero(~fin.reshape(-1, 6).all(1))),
+            "volume_jets_rel_err_vs_analytic": {"gradient": rel([1, 2]), "hessian": rel([3, 4, 5])},
+            "volume_jets_rel_err_vs_analytic_axis_ratio_ge_0.1": {"gradient": rel([1, 2], shaped),
+                                                                  "hessian": rel([3, 4, 5], shaped),
+                                                                  "triangles": int(shaped.sum() // 6)},
             "sgn_differs_only_on_curve": bool(np.all(np.asarray(P.geom["r"])[sgn != np.asarray(P.geom["sgn"])] <= 1e-12)
                                               and np.all(sgn[sgn != np.asarray(P.geom["sgn"])] == 0))}
 

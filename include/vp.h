@@ -243,6 +243,26 @@ vp_status vp_boundary_jets(int64_t n_pan, int q, const double* bnd_x, const doub
                            int64_t n_tgt, const int32_t* pan, const double* u, int nder, double* out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Volume-density jets from the triangulation (the derivatives of f the
+ * volume local part of Sec. 4, Lemma 4.1, takes, for a density known only at
+ * the nodes of Sec. 2.2's triangles).
+ *
+ * x, y, f [6 n_tri] (device): the nodes of triangle j at 6j .. 6j+5 and f
+ * there.  jet6 [6][6 n_tri] (device, out): f, f_x, f_y, f_xx, f_xy, f_yy at
+ * each node from the quadratic interpolant of f at its triangle's six nodes
+ * (vp_eval's jet6 for targets that are the volume nodes, in their order; the
+ * value row is f itself).  The gradient is O(h^2) and the Hessian O(h)
+ * accurate, so the volume potential with these jets carries an O(h^4)-like
+ * error of its own (2.5e-5 relative on a 12k-node disk, 8e-7 at 48k): callers
+ * who know f's derivatives pass those instead.  A triangle whose nodes do
+ * not determine a quadratic (collinear nodes, a conic through all six) gets
+ * NaN derivatives.  Enqueues one launch on stream (a hipStream_t; NULL: the
+ * null stream), allocates nothing; VP_ERR_ARG for NULL arrays or n_tri < 0
+ * (n_tri = 0 is a no-op). */
+vp_status vp_volume_jets(int64_t n_tri, const double* x, const double* y, const double* f, double* jet6,
+                         void* stream);
+
+/* ------------------------------------------------------------------------
  * Interior Dirichlet problem -Lap u = f inside, u = g on the boundary, by
  * the representation u = V[f] + D[mu] (Sec. 1; the boundary integral
  * correction of Sec. 5): mu at the boundary nodes solves

@@ -9,7 +9,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvp.so")
-SOURCES = ["vp_kernels.hip", "vp_plan.hip", "vp_batch.hip", "vp_server.hip", "vp_refine.hip", "vp_geom.hip", "vp_solve.hip"]
+SOURCES = ["vp_kernels.hip", "vp_plan.hip", "vp_batch.hip", "vp_server.hip", "vp_refine.hip", "vp_geom.hip", "vp_solve.hip",
+           "vp_volume_jets.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-I" + os.path.join(ROOT, "include"),

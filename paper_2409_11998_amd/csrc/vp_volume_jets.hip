@@ -1,0 +1,171 @@
+// Jets of the volume density at the volume nodes from per-triangle quadratic
+// interpolants: f, f_x, f_y, f_xx, f_xy, f_yy, the derivatives the volume
+// local part of Sec. 4 (Lemma 4.1) takes, when f is known only at the nodes of
+// the triangulation of Sec. 2.2 (six nodes per triangle).
+//
+// A triangle's six nodes determine the quadratic through them.  It is fitted
+// in the nodes' principal-axis coordinates, each axis scaled by its own
+// spread (u = e1.(x - c)/s1, v = e2.(x - c)/s2): the same interpolant as in
+// any affine coordinates, but its 6x6 system stays well conditioned on
+// slivers, whose extents differ by orders of magnitude.  Derivatives come
+// back to (x, y) through the constant Jacobian of that map.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "vp_internal.hpp"
+
+namespace vp {
+namespace {
+
+constexpr int kJetThreads = 256;
+
+// one thread per triangle; jet [6][6 n_tri], the nodes' order
+__global__ __launch_bounds__(kJetThreads) void k_volume_jets(int64_t n_tri, const double* __restrict__ x,
+                                                             const double* __restrict__ y,
+                                                             const double* __restrict__ f, double* __restrict__ jet)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tri) return;
+    const int64_t n = 6 * n_tri;
+    const int64_t o = 6 * t;
+    double px[6], py[6], pf[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        px[l] = x[o + l];
+        py[l] = y[o + l];
+        pf[l] = f[o + l];
+    }
+    double cx = 0.0, cy = 0.0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        cx += px[l];
+        cy += py[l];
+    }
+    cx /= 6.0;
+    cy /= 6.0;
+    double sxx = 0.0, sxy = 0.0, syy = 0.0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        const double dx = px[l] - cx, dy = py[l] - cy;
+        sxx += dx * dx;
+        sxy += dx * dy;
+        syy += dy * dy;
+    }
+    // principal axes of the nodes' spread
+    const double half = 0.5 * (sxx - syy);
+    const double rad = sqrt(half * half + sxy * sxy);
+    const double l1 = 0.5 * (sxx + syy) + rad, l2 = 0.5 * (sxx + syy) - rad;
+    double e1x, e1y;
+    if (sxx >= syy) {
+        e1x = l1 - syy;
+        e1y = sxy;
+    } else {
+        e1x = sxy;
+        e1y = l1 - sxx;
+    }
+    const double en = hypot(e1x, e1y);
+    // else the nodes lie on a line within rounding (collinear sets give l2 ~ 1e-16 l1; a
+    // sliver of aspect 1e4 has l2 ~ 1e-8 l1)
+    bool ok = l1 > 0.0 && l2 > 1e-14 * l1;
+    if (en > 0.0) {
+        e1x /= en;
+        e1y /= en;
+    } else {  // isotropic spread: every direction is principal
+        e1x = 1.0;
+        e1y = 0.0;
+    }
+    const double e2x = -e1y, e2y = e1x;
+    const double s1 = ok ? sqrt(l1 / 6.0) : 1.0, s2 = ok ? sqrt(l2 / 6.0) : 1.0;
+    // rows [1, u, v, u^2, uv, v^2 | f]
+    double A[6][7], uu[6], vv[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        const double dx = px[l] - cx, dy = py[l] - cy;
+        const double u = (e1x * dx + e1y * dy) / s1, v = (e2x * dx + e2y * dy) / s2;
+        uu[l] = u;
+        vv[l] = v;
+        A[l][0] = 1.0;
+        A[l][1] = u;
+        A[l][2] = v;
+        A[l][3] = u * u;
+        A[l][4] = u * v;
+        A[l][5] = v * v;
+        A[l][6] = pf[l];
+    }
+    // Gaussian elimination with partial pivoting; a pivot below 1e-10 of the
+    // columns' scale (O(1) here) means the nodes do not determine a quadratic
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        int p = k;
+        double best = fabs(A[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < 6; ++r)
+            if (fabs(A[r][k]) > best) {
+                best = fabs(A[r][k]);
+                p = r;
+            }
+        if (!(best > 1e-10)) ok = false;
+        if (p != k) {
+#pragma unroll
+            for (int cidx = 0; cidx < 7; ++cidx) {
+                const double tmp = A[k][cidx];
+                A[k][cidx] = A[p][cidx];
+                A[p][cidx] = tmp;
+            }
+        }
+        const double inv = best > 0.0 ? 1.0 / A[k][k] : 0.0;
+#pragma unroll
+        for (int r = k + 1; r < 6; ++r) {
+            const double m = A[r][k] * inv;
+#pragma unroll
+            for (int cidx = k; cidx < 7; ++cidx) A[r][cidx] -= m * A[k][cidx];
+        }
+    }
+    double c[6];
+#pragma unroll
+    for (int k = 5; k >= 0; --k) {
+        double s = A[k][6];
+#pragma unroll
+        for (int j = k + 1; j < 6; ++j) s -= A[k][j] * c[j];
+        c[k] = A[k][k] != 0.0 ? s / A[k][k] : 0.0;
+    }
+    // (u, v) = J (x - c): J rows e1/s1, e2/s2
+    const double j00 = e1x / s1, j01 = e1y / s1, j10 = e2x / s2, j11 = e2y / s2;
+    const double quu = 2.0 * c[3], quv = c[4], qvv = 2.0 * c[5];
+    const double hxx = j00 * j00 * quu + 2.0 * j00 * j10 * quv + j10 * j10 * qvv;
+    const double hxy = j00 * j01 * quu + (j00 * j11 + j10 * j01) * quv + j10 * j11 * qvv;
+    const double hyy = j01 * j01 * quu + 2.0 * j01 * j11 * quv + j11 * j11 * qvv;
+    const double bad = NAN;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        const double qu = c[1] + 2.0 * c[3] * uu[l] + c[4] * vv[l];
+        const double qv = c[2] + c[4] * uu[l] + 2.0 * c[5] * vv[l];
+        jet[o + l] = pf[l];
+        jet[n + o + l] = ok ? qu * j00 + qv * j10 : bad;
+        jet[2 * n + o + l] = ok ? qu * j01 + qv * j11 : bad;
+        jet[3 * n + o + l] = ok ? hxx : bad;
+        jet[4 * n + o + l] = ok ? hxy : bad;
+        jet[5 * n + o + l] = ok ? hyy : bad;
+    }
+}
+
+}  // namespace
+}  // namespace vp
+
+using namespace vp;
+
+extern "C" vp_status vp_volume_jets(int64_t n_tri, const double* x, const double* y, const double* f, double* jet6,
+                                    void* stream)
+{
+    if (n_tri < 0) return set_error(VP_ERR_ARG, "negative triangle count");
+    if (n_tri == 0) return VP_OK;
+    if (!x || !y || !f || !jet6) return set_error(VP_ERR_ARG, "NULL array");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_volume_jets, dim3((unsigned)((n_tri + kJetThreads - 1) / kJetThreads)), dim3(kJetThreads), 0,
+                       st, n_tri, x, y, f, jet6);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(VP_ERR_DEVICE, std::string("volume jets: ") + hipGetErrorString(e));
+    return VP_OK;
+}
