@@ -287,7 +287,7 @@ vp_status vp_volume_jets(int64_t n_tri, const double* x, const double* y, const 
  *   restart in [1, 200].  iters, resid (host, may be NULL): products taken
  *   and final relative residual.
  * Runs on the plan's stream and synchronizes it before returning.  Scratch
- * of (restart + 8) n doubles is allocated for the call.  VP_ERR_ARG for a
+ * of (restart + 11) n doubles is allocated for the call.  VP_ERR_ARG for a
  * plan without D, or whose nodes or targets are not the n_pan*q panel nodes,
  * for only one of f_src and jet6, or for a source on a plan without V or
  * volume nodes;
@@ -322,7 +322,7 @@ vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double*
  *   jets come from its panel interpolant.  The interior solution is then
  *   vp_eval with f, sigma = g and mu = -ub on a plan with interior targets.
  *
- * Both synchronize the plan's stream, allocate (restart + 8) n doubles of
+ * Both synchronize the plan's stream, allocate (restart + 11) n doubles of
  * scratch, and return VP_ERR_ARG / VP_ERR_TOL as vp_dirichlet_solve does
  * (and VP_ERR_ARG for a NULL bnd_w, or a Neumann plan without S). */
 vp_status vp_exterior_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,

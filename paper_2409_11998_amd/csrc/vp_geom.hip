@@ -16,6 +16,7 @@
 #include <cmath>
 #include <string>
 
+#include "vp_geom.hpp"
 #include "vp_internal.hpp"
 
 namespace vp {
@@ -302,6 +303,27 @@ hipError_t alloc_async(double** p, size_t n, hipStream_t st)
 }
 
 }  // namespace
+
+vp_status boundary_jets_ws(int64_t n_pan, int q, const double* bnd_x, const double* bnd_y, const double* dens,
+                           int64_t n_tgt, const int32_t* pan, const double* u, int nder, double* out, hipStream_t st,
+                           double* ws)
+{
+    if (n_tgt == 0) return VP_OK;
+    double* cx = ws;
+    double* cy = ws + (size_t)n_pan * q;
+    double* cs = ws + (size_t)2 * n_pan * q;
+    hipLaunchKernelGGL(k_panel_coef, dim3((unsigned)n_pan), dim3(64), 0, st, n_pan, q, bnd_x, bnd_y, dens, cx, cy, cs,
+                       (double*)nullptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_jets, dim3((unsigned)((n_tgt + kGeomThreads - 1) / kGeomThreads)), dim3(kGeomThreads), 0,
+                           st, n_pan, q, n_tgt, cx, cy, cs, pan, u, nder, out);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return gfail(VP_ERR_DEVICE, std::string("boundary jets: ") + hipGetErrorString(e));
+    return VP_OK;
+}
+
 }  // namespace vp
 
 using namespace vp;
@@ -352,25 +374,12 @@ extern "C" vp_status vp_boundary_jets(int64_t n_pan, int q, const double* bnd_x,
     if (n_tgt == 0) return VP_OK;
     if (!dens || !pan || !u || !out) return gfail(VP_ERR_ARG, "NULL density, location or output array");
     hipStream_t st = (hipStream_t)stream;
-    double *cx = nullptr, *cy = nullptr, *cs = nullptr;
-    hipError_t e = alloc_async(&cx, (size_t)n_pan * q, st);
-    if (e == hipSuccess) e = alloc_async(&cy, (size_t)n_pan * q, st);
-    if (e == hipSuccess) e = alloc_async(&cs, (size_t)n_pan * q, st);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_panel_coef, dim3((unsigned)n_pan), dim3(64), 0, st, n_pan, q, bnd_x, bnd_y, dens, cx, cy,
-                           cs, (double*)nullptr);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_jets, dim3((unsigned)((n_tgt + kGeomThreads - 1) / kGeomThreads)), dim3(kGeomThreads), 0,
-                           st, n_pan, q, n_tgt, cx, cy, cs, pan, u, nder, out);
-        e = hipGetLastError();
-    }
-    if (cx) (void)hipFreeAsync(cx, st);
-    if (cy) (void)hipFreeAsync(cy, st);
-    if (cs) (void)hipFreeAsync(cs, st);
+    double* ws = nullptr;  // coefficients of x, y and the density, one allocation
+    hipError_t e = alloc_async(&ws, (size_t)3 * n_pan * q, st);
     if (e != hipSuccess)
         return gfail(e == hipErrorOutOfMemory ? VP_ERR_OOM : VP_ERR_DEVICE,
                     std::string("boundary jets: ") + hipGetErrorString(e));
-    return VP_OK;
+    s = boundary_jets_ws(n_pan, q, bnd_x, bnd_y, dens, n_tgt, pan, u, nder, out, st, ws);
+    (void)hipFreeAsync(ws, st);
+    return s;
 }

@@ -18,6 +18,7 @@
 #include <string>
 #include <vector>
 
+#include "vp_geom.hpp"
 #include "vp_internal.hpp"
 
 namespace vp {
@@ -115,6 +116,7 @@ struct Solver {
     hipStream_t st;
     const double* bw = nullptr;  // boundary weights: the operator x/2 + D[x] + (w . x) when set
     double* jets = nullptr;  // [5][n]
+    double* gws = nullptr;   // [3][n]: panel coefficients of x, y and the density (the jets' scratch)
     double* part = nullptr;  // [kMaxRestart + 2][kDotBlocks]
     double* hd = nullptr;    // [kMaxRestart + 2]: projections of the current step, then its norm squared
     double* tmp = nullptr;   // [kMaxRestart + 1]: the second Gram-Schmidt pass's projections; last: w . x
@@ -164,7 +166,7 @@ struct Solver {
     // y = D_int[x], or D_int[x] + x + (w . x) = x/2 + D[x] + (w . x) with weights
     vp_status matvec(const double* x, double* y)
     {
-        vp_status s = vp_boundary_jets(n_pan, q, bx, by, x, n, pan, upar, 4, jets, (void*)st);
+        vp_status s = boundary_jets_ws(n_pan, q, bx, by, x, n, pan, upar, 4, jets, st, gws);
         if (s == VP_OK) s = vp_eval(plan, nullptr, nullptr, nullptr, nullptr, x, jets, y);
         if (s != VP_OK || !bw) return s;
         if ((s = project(bw, 1, x, tmp + kMaxRestart, false)) != VP_OK) return s;
@@ -235,6 +237,7 @@ vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
     if (e == hipSuccess) e = hipMalloc((void**)&w, (size_t)n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&b, (size_t)n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.jets, (size_t)5 * n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&S.gws, (size_t)3 * n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.part, (size_t)(kMaxRestart + 2) * kDotBlocks * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.hd, (kMaxRestart + 2) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&S.tmp, (kMaxRestart + 1) * sizeof(double));
@@ -317,6 +320,7 @@ vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
     if (w) (void)hipFree(w);
     if (b) (void)hipFree(b);
     if (S.jets) (void)hipFree(S.jets);
+    if (S.gws) (void)hipFree(S.gws);
     if (S.part) (void)hipFree(S.part);
     if (S.hd) (void)hipFree(S.hd);
     if (S.tmp) (void)hipFree(S.tmp);
@@ -370,7 +374,7 @@ extern "C" vp_status vp_neumann_solve(vp_plan_t plan, int64_t n_pan, int q, cons
     if (!bnd_w) return set_error(VP_ERR_ARG, "NULL array");
     if (!(plan->kinds & VP_KIND_S)) return set_error(VP_ERR_ARG, "the plan does not support the single layer");
     auto rhs = [&](Solver& S, double* b) {  // b = V[f] + S[g]; g's jets staged in the product's jet buffer
-        vp_status r = vp_boundary_jets(n_pan, q, bnd_x, bnd_y, g, S.n, pan, u, 2, S.jets, (void*)S.st);
+        vp_status r = boundary_jets_ws(n_pan, q, bnd_x, bnd_y, g, S.n, pan, u, 2, S.jets, S.st, S.gws);
         return r == VP_OK ? vp_eval(plan, f_src, jet6, g, S.jets, nullptr, nullptr, b) : r;
     };
     return gmres_solve(plan, n_pan, q, bnd_x, bnd_y, pan, u, bnd_w, rhs, ub, tol, max_iter, restart, iters, resid);
