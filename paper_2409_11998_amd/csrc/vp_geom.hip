@@ -44,7 +44,9 @@ __device__ void gauss_legendre(int q, int j, double* x, double* w)
         dp = q * (t * p1 - p0) / (t * t - 1.0);
         const double dt = p1 / dp;
         t -= dt;
-        if (fabs(dt) <= 1e-16) break;
+        // quadratic convergence: a step of a few ulps leaves t at rounding level (a
+        // tighter test can miss, the iterate then alternating between neighbours)
+        if (fabs(dt) <= 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(t))) break;
     }
     double p0 = 1.0, p1 = t;
     for (int n = 1; n < q; ++n) {
@@ -65,6 +67,7 @@ __global__ __launch_bounds__(64) void k_panel_coef(int64_t n_pan, int q, const d
                                                    double* __restrict__ c2, double* __restrict__ circ)
 {
     __shared__ double xs[kGeomQMax], ws[kGeomQMax], fv[3][kGeomQMax], fabsmax[3];
+    __shared__ double Pk[kGeomQMax][kGeomQMax + 1];  // Pk[k][j] = P_k(u_j)
     const int64_t p = blockIdx.x;
     const int t = threadIdx.x;
     const double* src[3] = {f0, f1, f2};
@@ -74,6 +77,17 @@ __global__ __launch_bounds__(64) void k_panel_coef(int64_t n_pan, int q, const d
         for (int a = 0; a < 3; ++a) fv[a][t] = src[a] ? src[a][p * q + t] : 0.0;
     }
     __syncthreads();
+    if (t < q) {  // P_0 .. P_{q-1} at this thread's node, by the three-term recurrence
+        const double u = xs[t];
+        double pk = 1.0, pkm1 = 0.0;
+        Pk[0][t] = 1.0;
+        for (int n = 0; n + 1 < q; ++n) {
+            const double pn = ((2.0 * n + 1.0) * u * pk - n * pkm1) / (n + 1.0);
+            pkm1 = pk;
+            pk = pn;
+            Pk[n + 1][t] = pk;
+        }
+    }
     if (t < 3) {
         double m = 0.0;
         for (int j = 0; j < q; ++j) m = fmax(m, fabs(fv[t][j]));
@@ -97,14 +111,7 @@ __global__ __launch_bounds__(64) void k_panel_coef(int64_t n_pan, int q, const d
     if (t < q) {
         double acc[3] = {0.0, 0.0, 0.0};
         for (int j = 0; j < q; ++j) {
-            // P_t(u_j) by the three-term recurrence
-            const double u = xs[j];
-            double pk = 1.0, pkm1 = 0.0;
-            for (int n = 0; n < t; ++n) {
-                const double pn = ((2.0 * n + 1.0) * u * pk - n * pkm1) / (n + 1.0);
-                pkm1 = pk;
-                pk = pn;
-            }
+            const double pk = Pk[t][j];
             for (int a = 0; a < 3; ++a) acc[a] += ws[j] * pk * fv[a][j];
         }
         const double floor_scale = 4.0 * q * 2.220446049250313e-16;
