@@ -178,3 +178,31 @@ def neumann_solution_at(P, ub, g, tx, ty, f_src=None, jet6=None):
     T.sigma = np.asarray(g, float)
     T.sigma_jet = G.density_jets(P.bnd_x, P.bnd_y, q, T.sigma, fr["pan"], fr["u"], 2)
     return evaluate(T, kinds="VSD" if f_src is not None else "SD", delta=delta1_of(P))["total"]
+
+
+# ---------------------------------------------------------------------------
+# Exterior problems with a volume source.  The volume local part needs the
+# domain on the interior side of a target's frame.  Traversing the boundary
+# clockwise makes the outside that side: the frames from the reversed panels
+# carry the normal pointing into the curve (the exterior domain's outward
+# normal), the matching curvature and sgn = +1 outside.  V[f] is then
+# evaluated on the reversed boundary and enters the exterior Dirichlet
+# equation as data: mu/2 + D[mu] + integral of mu = g - V[f].
+
+
+def reversed_boundary(bx, by, bnx, bny, bw):
+    """The same nodes traversed clockwise (panel order and node order within
+    each panel reversed; Gauss-Legendre nodes are symmetric), normals flipped."""
+    return (np.asarray(bx, float)[::-1], np.asarray(by, float)[::-1], -np.asarray(bnx, float)[::-1],
+            -np.asarray(bny, float)[::-1], np.asarray(bw, float)[::-1])
+
+
+def volume_at(P, f_src, jet6, tx, ty, delta=None):
+    """V[f] at targets (tx, ty) with their frames from P's panels (P's volume
+    nodes; jet6 = f's jets at the targets)."""
+    q = P.info["q"]
+    fr = G.boundary_frame(P.bnd_x, P.bnd_y, q, tx, ty)
+    geom = {k: fr[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    T = _Layer(P.bnd_x, P.bnd_y, P.bnd_nx, P.bnd_ny, P.bnd_w, np.asarray(tx, float), np.asarray(ty, float), geom,
+               src=(P.src_x, P.src_y, P.src_w), f_src=np.asarray(f_src, float), jet6=np.asarray(jet6, float))
+    return evaluate(T, kinds="V", delta=delta1_of(P) if delta is None else delta)["V"]

@@ -21,10 +21,15 @@ D_int assembled from the method's evaluation at the boundary nodes):
 * the interior Neumann problem (Green's representation, boundary values of
   zero mean): on the circle g = 3 cos 3t gives u = cos 3t on it and r^3 cos 3t
   inside; with the Gaussian source on the disk and inside the star, the
-  closed forms above up to their boundary mean.
+  closed forms above up to their boundary mean;
+* the exterior Dirichlet problem with a volume source (a Gaussian ring
+  outside the unit circle), V[f] taken on the clockwise-traversed boundary:
+  against the radial solution by nested adaptive quadrature plus
+  r^-3 cos 3t, converging as the nodes are refined.
 """
 import numpy as np
 from numpy.polynomial.legendre import leggauss
+from scipy.integrate import quad
 from scipy.special import exp1
 
 from oracle import bie
@@ -211,3 +216,51 @@ def test_star_exterior_dirichlet_and_neumann():
     print("star: exterior", e_ext, "integral of mu", np.dot(bw, mu), "Neumann boundary", e_b, "interior", e_u)
     assert e_ext <= 2e-4 and abs(np.dot(bw, mu) - 0.3) <= 1e-6
     assert e_b <= 1e-5 and e_u <= 1e-5
+
+
+def _ring(x, y, r0=1.3, s=0.05):
+    """f = exp(-(r - r0)^2 / s) and its Cartesian jets."""
+    r = np.hypot(x, y)
+    c, sn = x / r, y / r
+    f = np.exp(-(r - r0) ** 2 / s)
+    f1 = -2 * (r - r0) / s * f
+    f2 = (4 * (r - r0) ** 2 / s ** 2 - 2 / s) * f
+    return np.stack([f, f1 * c, f1 * sn, f2 * c * c + f1 * sn * sn / r, (f2 - f1 / r) * c * sn,
+                     f2 * sn * sn + f1 * c * c / r])
+
+
+def _ring_radial_solution(r, r0=1.3, s=0.05):
+    """-Lap w = the ring outside the unit circle, w(1) = 0, w'(r) = -(1/r) int_1^r f t dt."""
+    f = lambda t: np.exp(-(t - r0) ** 2 / s)
+    inner = lambda u: quad(lambda t: f(t) * t, 1.0, u, epsabs=1e-15, epsrel=1e-13)[0]
+    return -quad(lambda u: inner(u) / u, 1.0, r, epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+
+
+def _exterior_source_error(n_r, n_t, n_pan, R=2.6):
+    xr, wr = leggauss(n_r)
+    rr = 1 + (R - 1) * (xr + 1) / 2
+    wr = wr * (R - 1) / 2
+    th = 2 * np.pi * np.arange(n_t) / n_t
+    RR, TT = np.meshgrid(rr, th, indexing="ij")
+    src = ((RR * np.cos(TT)).ravel(), (RR * np.sin(TT)).ravel(), np.outer(wr * rr, np.full(n_t, 2 * np.pi / n_t)).ravel())
+    f = _ring(src[0], src[1])[0]
+    bx, by, nx, ny, w, t = _circle(n_pan)
+    rb = bie.reversed_boundary(bx, by, nx, ny, w)
+    Pcw = bie.on_boundary_problem(*rb, 16, src=src)
+    vb = bie.volume_at_nodes(Pcw, f, _ring(rb[0], rb[1]))[::-1]
+    P = bie.on_boundary_problem(bx, by, nx, ny, w, 16, src=src)
+    mu = bie.solve_exterior_dirichlet(P, np.cos(3 * t) - vb)
+    rng = np.random.default_rng(0)
+    tq, rq = rng.uniform(0, 2 * np.pi, 40), rng.uniform(1.05, 2.2, 40)
+    tx, ty = rq * np.cos(tq), rq * np.sin(tq)
+    u = bie.volume_at(Pcw, f, _ring(tx, ty), tx, ty) + bie.exterior_solution_at(P, mu, tx, ty)
+    ue = np.array([_ring_radial_solution(r) for r in rq]) + rq ** -3 * np.cos(3 * tq)
+    return np.max(np.abs(vb)), np.max(np.abs(u - ue))
+
+
+def test_exterior_dirichlet_with_source():
+    coarse = _exterior_source_error(60, 240, 32)
+    fine = _exterior_source_error(120, 480, 48)
+    print("exterior with source (max |V| on the circle, error): coarse", coarse, "fine", fine)
+    assert coarse[0] >= 0.1                       # the volume term matters on the boundary
+    assert coarse[1] <= 2e-4 and fine[1] <= 2e-6 and fine[1] <= coarse[1] / 30
