@@ -310,7 +310,12 @@ vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double*
  *   double layer with the kernel's +1), whose exterior limit on the boundary
  *   is mu/2 + D[mu] + (integral of mu) = g.  For growth A log|x - x0| at
  *   infinity pass g - A log|x' - x0|.  mu [n_pan*q]: initial guess in,
- *   solution out.
+ *   solution out.  With a volume source outside (u = V[f] + D_E[mu] +
+ *   A log), pass g - V[f] - A log: V[f] at the nodes and at exterior
+ *   targets comes from plans on the same nodes traversed clockwise (panel
+ *   and node order reversed, normals flipped), whose frames from
+ *   vp_boundary_frame put the outside on their interior side, where the
+ *   volume local part applies.
  * vp_neumann_solve: -Lap u = f inside with du/dnu = g on the boundary, by
  *   Green's representation u = V[f] + S[g] - D[u]; on the boundary
  *   u/2 + D[u] = V[f] + S[g].  The added integral of u removes the constants

@@ -333,3 +333,64 @@ def test_neumann(domain):
     assert e_x <= 1e-5
     # zero up to the data's discrete inconsistency (the integrals of g and -f agree to ~1e-9 here)
     assert abs(np.dot(bw, ub)) <= 1e-7 * np.max(np.abs(ub))
+
+
+def test_exterior_dirichlet_with_volume_source():
+    """A Gaussian ring source outside the unit circle: V[f] at the nodes and at
+    the targets from plans on the clockwise-traversed boundary (the outside is
+    their frames' interior side), then the exterior solve with g - V[f] on the
+    counter-clockwise plan; against the oracle's same pipeline and the radial
+    solution by nested quadrature."""
+    torch = _gpu()
+    from paper_2409_11998_amd import Plan, boundary_frame, exterior_dirichlet_solve
+    import test_oracle_bie as T
+    q, R, n_r, n_t = 16, 2.6, 60, 240
+    xr, wr = leggauss(n_r)
+    rr = 1 + (R - 1) * (xr + 1) / 2
+    wr = wr * (R - 1) / 2
+    th = 2 * np.pi * np.arange(n_t) / n_t
+    RR, TT = np.meshgrid(rr, th, indexing="ij")
+    src = ((RR * np.cos(TT)).ravel(), (RR * np.sin(TT)).ravel(),
+           np.outer(wr * rr, np.full(n_t, 2 * np.pi / n_t)).ravel())
+    f = T._ring(src[0], src[1])[0]
+    bx, by, nx, ny, w, t = _circle(32)
+    rb = bie.reversed_boundary(bx, by, nx, ny, w)
+
+    def volume(tx, ty, on_nodes):
+        """V[f] at (tx, ty) through a plan on the clockwise boundary."""
+        dx, dy = _t(torch, rb[0]), _t(torch, rb[1])
+        ftx, fty = _t(torch, tx), _t(torch, ty)
+        fr = boundary_frame(dx, dy, q, ftx, fty)
+        geom = {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+        if on_nodes:   # the interior limit at the nodes
+            geom["r"] = torch.zeros_like(ftx)
+            geom["sgn"] = torch.ones(ftx.numel(), dtype=torch.int8, device="cuda")
+        pl = Plan(_t(torch, src[0]), _t(torch, src[1]), _t(torch, src[2]), dx, dy, _t(torch, rb[2]),
+                  _t(torch, rb[3]), _t(torch, rb[4]), ftx, fty, geom, tol=1e-10, precision=1, kinds=1)
+        out = pl.eval(f=_t(torch, f), jet6=_t(torch, T._ring(tx, ty))).cpu().numpy()
+        pl.close()
+        return out
+
+    vb = volume(rb[0], rb[1], True)[::-1]
+    plan, dx, dy, fr = _node_plan(torch, bx, by, nx, ny, w, q, src=src, kinds=4)
+    mu, its, res = exterior_dirichlet_solve(plan, q, dx, dy, _t(torch, w), fr["pan"], fr["u"],
+                                            _t(torch, np.cos(3 * t) - vb))
+    torch.cuda.synchronize()
+    plan.close()
+    mu = mu.cpu().numpy()
+    Pcw = bie.on_boundary_problem(*rb, q, src=src)
+    vb_ref = bie.volume_at_nodes(Pcw, f, T._ring(rb[0], rb[1]))[::-1]
+    P = bie.on_boundary_problem(bx, by, nx, ny, w, q, src=src)
+    ref = bie.solve_exterior_dirichlet(P, np.cos(3 * t) - vb_ref)
+    rng = np.random.default_rng(0)
+    tq, rq = rng.uniform(0, 2 * np.pi, 40), rng.uniform(1.05, 2.2, 40)
+    tx, ty = rq * np.cos(tq), rq * np.sin(tq)
+    u = volume(tx, ty, False) + _eval_at(torch, bx, by, nx, ny, w, q, tx, ty, src=src, mu=mu) + float(np.dot(w, mu))
+    u_ref = bie.volume_at(Pcw, f, T._ring(tx, ty), tx, ty) + bie.exterior_solution_at(P, ref, tx, ty)
+    ue = np.array([T._ring_radial_solution(r) for r in rq]) + rq ** -3 * np.cos(3 * tq)
+    e_v, e_mu = oracle.rel_linf(vb, vb_ref), oracle.rel_linf(mu, ref)
+    e_u, e_x = oracle.rel_linf(u, u_ref), np.max(np.abs(u - ue))
+    print("exterior with source: products", its, "residual", res, "V at nodes vs oracle", e_v, "mu vs oracle", e_mu,
+          "u vs oracle", e_u, "vs exact", e_x)
+    assert res <= 1e-11 and e_v <= 1e-10 and e_mu <= 1e-8 and e_u <= 1e-8
+    assert e_x <= 2e-4
