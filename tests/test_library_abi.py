@@ -38,3 +38,28 @@ def test_opts_defaults_without_device():
     o = binding.default_opts()
     assert o.tol == 1e-10 and o.precision == binding.VP_FP64 and o.c_delta == 3.0
     assert o.delta_ratio == 32.0 and o.kinds == 7
+
+
+def test_host_side_argument_checks():
+    """The binding and the library reject malformed arguments before any device
+    work: these run without a GPU."""
+    import torch
+    from paper_2409_11998_amd import binding, boundary_frame, boundary_jets, volume_jets
+    x = torch.zeros(30, dtype=torch.float64)
+    with pytest.raises(ValueError):           # 30 nodes are not whole panels of 16
+        boundary_frame(x, x, 16, x, x)
+    with pytest.raises(ValueError):
+        boundary_jets(x, x, 16, x, torch.zeros(30, dtype=torch.int32), x, 4)
+    with pytest.raises(ValueError):           # nodes come six per triangle
+        volume_jets(torch.zeros(7, dtype=torch.float64), x[:7], x[:7])
+    with pytest.raises(ValueError):           # host tensors are refused before the call
+        volume_jets(torch.zeros(12, dtype=torch.float64), x[:12], x[:12])
+    L = binding.lib()
+    assert L.vp_volume_jets(0, None, None, None, None, None) == binding.VP_OK
+    assert L.vp_volume_jets(-1, None, None, None, None, None) == binding.VP_ERR_ARG
+    assert L.vp_boundary_jets(1, 16, None, None, None, 0, None, None, 4, None, None) == binding.VP_ERR_ARG
+    assert L.vp_boundary_jets(4, 40, None, None, None, 0, None, None, 4, None, None) == binding.VP_ERR_ARG
+    assert L.vp_dirichlet_solve(None, 4, 16, None, None, None, None, None, None, None, None, 1e-12, 10, 10, None,
+                                None) == binding.VP_ERR_ARG
+    assert L.vp_neumann_solve(None, 4, 16, None, None, None, None, None, None, None, None, None, 1e-12, 10, 10, None,
+                              None) == binding.VP_ERR_ARG
