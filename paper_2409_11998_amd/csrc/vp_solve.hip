@@ -27,6 +27,8 @@ namespace {
 constexpr int kSolveThreads = 256;
 constexpr int kDotBlocks = 256;
 constexpr int kMaxRestart = 200;
+constexpr int kSmallThreads = 1024;       // one workgroup per basis vector at small n
+constexpr int64_t kSmallN = 1 << 16;      // up to this many nodes the projections take one launch
 
 __global__ __launch_bounds__(kSolveThreads) void k_dot(int64_t n, const double* __restrict__ a,
                                                        const double* __restrict__ b, double* __restrict__ part)
@@ -62,6 +64,26 @@ __global__ __launch_bounds__(kSolveThreads) void k_proj_part(int64_t n, const do
         double t = 0.0;
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
         part[(int64_t)blockIdx.y * kDotBlocks + blockIdx.x] = t;
+    }
+}
+
+// out[j] (+)= V_j . w for n <= kSmallN in one launch: workgroup j sums the whole
+// vector in a fixed order (grid: k1 workgroups of kSmallThreads)
+__global__ __launch_bounds__(kSmallThreads) void k_proj_small(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                                              const double* __restrict__ w, double* __restrict__ out,
+                                                              int accumulate)
+{
+    __shared__ double red[kSmallThreads / 64];
+    const double* v = V + (int64_t)blockIdx.x * ldv;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kSmallThreads) s = fma(v[i], w[i], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kSmallThreads / 64; ++k) t += red[k];
+        out[blockIdx.x] = accumulate ? out[blockIdx.x] + t : t;
     }
 }
 
@@ -131,6 +153,11 @@ struct Solver {
     // out[j] (+)= V_j . w for j < k1, on the device
     vp_status project(const double* V, int k1, const double* w, double* out, bool accumulate)
     {
+        if (n <= kSmallN) {
+            hipLaunchKernelGGL(k_proj_small, dim3((unsigned)k1), dim3(kSmallThreads), 0, st, n, V, n, w, out,
+                               accumulate ? 1 : 0);
+            return launched();
+        }
         hipLaunchKernelGGL(k_proj_part, dim3(kDotBlocks, (unsigned)k1), dim3(kSolveThreads), 0, st, n, V, n, w, part);
         hipLaunchKernelGGL(k_proj_sum, dim3((unsigned)k1), dim3(kDotBlocks), 0, st, part, out, accumulate ? 1 : 0);
         return launched();
