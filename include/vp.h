@@ -286,8 +286,10 @@ vp_status vp_volume_jets(int64_t n_tri, const double* x, const double* y, const 
  * tol: relative residual ||g - D_int mu|| / ||g||; max_iter >= 1 products;
  *   restart in [1, 200].  iters, resid (host, may be NULL): products taken
  *   and final relative residual.
- * Verified on boundaries of up to 4096 nodes; on a 70,400-node circle GMRES
- * stalled above 1e-9 (cause not established).
+ * The boundary should be resolved near the scale sqrt(delta_1) (about sqrt(N)
+ * boundary nodes for N volume nodes): far finer panels make the local
+ * expansions' derivative terms grow with the density's frequency, and the
+ * attainable residual stalls (1.9e-7 at 100x over-resolution).
  * Runs on the plan's stream and synchronizes it before returning.  Scratch
  * of (restart + 11) n doubles is allocated for the call.  VP_ERR_ARG for a
  * plan without D, or whose nodes or targets are not the n_pan*q panel nodes,
