@@ -242,6 +242,23 @@ vp_status vp_boundary_frame(int64_t n_pan, int q, const double* bnd_x, const dou
 vp_status vp_boundary_jets(int64_t n_pan, int q, const double* bnd_x, const double* bnd_y, const double* dens,
                            int64_t n_tgt, const int32_t* pan, const double* u, int nder, double* out, void* stream);
 
+/* vp_boundary_jets for callers that cannot allocate device memory: code
+ * under HIP stream capture, tight serving or solver loops, hosts that forbid
+ * hipMalloc.  Same arguments, kernels and results as vp_boundary_jets, but the
+ * panel coefficients go to a fixed scratch array compiled into the library
+ * (3 * VP_NOALLOC_MAX_NODES doubles, 1.5 MiB on every device the call runs
+ * on, held until the process ends) instead of stream-ordered scratch; it calls
+ * no hipMalloc/hipFree.  n_pan * q must not exceed VP_NOALLOC_MAX_NODES
+ * (VP_ERR_ARG otherwise).  Every call on one device shares that device's
+ * scratch: calls that overlap on the device (different streams or threads
+ * without ordering between them) race and must be serialized by the caller;
+ * calls on one stream are ordered.  The first call on a device looks up the
+ * scratch's device address with that device current. */
+#define VP_NOALLOC_MAX_NODES 65536
+vp_status vp_boundary_jets_noalloc(int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,
+                                   const double* dens, int64_t n_tgt, const int32_t* pan, const double* u, int nder,
+                                   double* out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Volume-density jets from the triangulation (the derivatives of f the
  * volume local part of Sec. 4, Lemma 4.1, takes, for a density known only at

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvp.so")
 
 VP_FP32, VP_FP64 = 0, 1
+NOALLOC_MAX_NODES = 65536   # VP_NOALLOC_MAX_NODES of include/vp.h
 VP_KIND_V, VP_KIND_S, VP_KIND_D = 1, 2, 4
 (VP_OK, VP_ERR_ARG, VP_ERR_OOM, VP_ERR_DEVICE, VP_ERR_GEOMETRY, VP_ERR_TOL, VP_ERR_BUSY,
  VP_ERR_INTERNAL) = range(8)
@@ -23,7 +24,7 @@ EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "v
             "vp_server_create", "vp_server_submit", "vp_server_poll", "vp_server_wait", "vp_server_get_stats",
             "vp_server_destroy", "vp_server_last_error", "vp_refine_attach", "vp_layer_refine",
             "vp_boundary_frame", "vp_boundary_jets", "vp_dirichlet_solve", "vp_exterior_dirichlet_solve",
-            "vp_neumann_solve", "vp_volume_jets"]
+            "vp_neumann_solve", "vp_volume_jets", "vp_boundary_jets_noalloc"]
 
 
 class VPError(RuntimeError):
@@ -118,6 +119,8 @@ def lib():
         L.vp_boundary_frame.restype = ctypes.c_int
         L.vp_boundary_jets.argtypes = [i64, ctypes.c_int, vp, vp, vp, i64, vp, vp, ctypes.c_int, vp, vp]
         L.vp_boundary_jets.restype = ctypes.c_int
+        L.vp_boundary_jets_noalloc.argtypes = [i64, ctypes.c_int, vp, vp, vp, i64, vp, vp, ctypes.c_int, vp, vp]
+        L.vp_boundary_jets_noalloc.restype = ctypes.c_int
         L.vp_dirichlet_solve.argtypes = [vp, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.vp_dirichlet_solve.restype = ctypes.c_int
@@ -454,17 +457,23 @@ def boundary_frame(bnd_x, bnd_y, q, tgt_x, tgt_y):
     return out
 
 
-def boundary_jets(bnd_x, bnd_y, q, dens, pan, u, nder):
+def boundary_jets(bnd_x, bnd_y, q, dens, pan, u, nder, out=None, noalloc=False):
     """d^k dens / d xi^k, k = 0..nder, at each target's closest boundary point
-    (vp_boundary_jets): device tensor [nder + 1, n_tgt]."""
+    (vp_boundary_jets; with noalloc, vp_boundary_jets_noalloc, which writes
+    into a caller-given out and allocates nothing): device tensor
+    [nder + 1, n_tgt]."""
     import torch
     f64 = torch.float64
     nb, n = bnd_x.numel(), pan.numel()
     if q <= 0 or nb % q:
         raise ValueError("the boundary must hold whole panels of q nodes")
-    out = torch.empty((nder + 1, n), dtype=f64, device=pan.device)
-    _check(lib().vp_boundary_jets(nb // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64), _ptr(dens, f64), n,
-                                  _ptr(pan, torch.int32), _ptr(u, f64), nder, _ptr(out), _stream(pan)))
+    if out is None:
+        out = torch.empty((nder + 1, n), dtype=f64, device=pan.device)
+    elif tuple(out.shape) != (nder + 1, n) or out.dtype != f64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of shape (nder + 1, n_tgt)")
+    fn = lib().vp_boundary_jets_noalloc if noalloc else lib().vp_boundary_jets
+    _check(fn(nb // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64), _ptr(dens, f64), n,
+              _ptr(pan, torch.int32), _ptr(u, f64), nder, _ptr(out), _stream(pan)))
     return out
 
 

@@ -14,10 +14,18 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "vp_geom.hpp"
 #include "vp_internal.hpp"
+
+// Fixed scratch of the allocation-free jets (vp_boundary_jets_noalloc): the
+// Legendre coefficients of x, y and the density, 3 n_pan q doubles for up to
+// VP_NOALLOC_MAX_NODES nodes (1.5 MiB).  Every device the library runs on
+// holds its own copy until the process ends.  In host code this name is a
+// host-side stand-in: its device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[3 * VP_NOALLOC_MAX_NODES];
 
 namespace vp {
 namespace {
@@ -309,6 +317,30 @@ hipError_t alloc_async(double** p, size_t n, hipStream_t st)
     return hipMallocAsync((void**)p, n * sizeof(double), st);
 }
 
+// Device address of the fixed scratch on the current device, looked up once
+// per device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+vp_status scratch_address(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return gfail(VP_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return gfail(VP_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return gfail(VP_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return VP_OK;
+}
+
 }  // namespace
 
 vp_status boundary_jets_ws(int64_t n_pan, int q, const double* bnd_x, const double* bnd_y, const double* dens,
@@ -389,4 +421,22 @@ extern "C" vp_status vp_boundary_jets(int64_t n_pan, int q, const double* bnd_x,
     s = boundary_jets_ws(n_pan, q, bnd_x, bnd_y, dens, n_tgt, pan, u, nder, out, st, ws);
     (void)hipFreeAsync(ws, st);
     return s;
+}
+
+extern "C" vp_status vp_boundary_jets_noalloc(int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,
+                                              const double* dens, int64_t n_tgt, const int32_t* pan, const double* u,
+                                              int nder, double* out, void* stream)
+{
+    vp_status s = geom_check(n_pan, q, bnd_x, bnd_y, n_tgt);
+    if (s != VP_OK) return s;
+    if (nder < 0 || nder > 4) return gfail(VP_ERR_ARG, "nder must be in [0, 4]");
+    if (n_pan * q > VP_NOALLOC_MAX_NODES)
+        return gfail(VP_ERR_ARG, "n_pan * q = " + std::to_string(n_pan * q) + " exceeds VP_NOALLOC_MAX_NODES = " +
+                                     std::to_string(VP_NOALLOC_MAX_NODES));
+    double* ws = nullptr;  // resolved before the n_tgt = 0 return: set-up on the first call either way
+    if ((s = scratch_address(&ws)) != VP_OK) return s;
+    if (n_tgt == 0) return VP_OK;
+    if (!dens || !pan || !u || !out) return gfail(VP_ERR_ARG, "NULL density, location or output array");
+    // k_panel_coef writes every coefficient the jets read, so nothing is cleared
+    return boundary_jets_ws(n_pan, q, bnd_x, bnd_y, dens, n_tgt, pan, u, nder, out, (hipStream_t)stream, ws);
 }

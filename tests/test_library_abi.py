@@ -63,3 +63,10 @@ def test_host_side_argument_checks():
                                 None) == binding.VP_ERR_ARG
     assert L.vp_neumann_solve(None, 4, 16, None, None, None, None, None, None, None, None, None, 1e-12, 10, 10, None,
                               None) == binding.VP_ERR_ARG
+
+
+def test_noalloc_limit_matches_header():
+    from paper_2409_11998_amd import binding
+    text = open(os.path.join(ROOT, "include", "vp.h")).read()
+    m = re.search(r"#define\s+VP_NOALLOC_MAX_NODES\s+(\d+)", text)
+    assert m and int(m.group(1)) == binding.NOALLOC_MAX_NODES
