@@ -300,18 +300,32 @@ vp_status vp_volume_jets(int64_t n_tri, const double* x, const double* y, const 
  *   nodes) then serves the double layer too, as in the method.
  *   mu [n_pan*q] (device): in, the
  *   initial guess; out, the solution (the last iterate on VP_ERR_TOL).
- * tol: relative residual ||g - D_int mu|| / ||g||; max_iter >= 1 products;
- *   restart in [1, 200].  iters, resid (host, may be NULL): products taken
- *   and final relative residual.
- * The boundary should be resolved near the scale sqrt(delta_1) (about sqrt(N)
- * boundary nodes for N volume nodes): far finer panels make the local
- * expansions' derivative terms grow with the density's frequency, and the
- * attainable residual stalls (1.9e-7 at 100x over-resolution).
+ * tol: relative residual ||b - A mu|| / ||b|| (b = g - V[f], A = D_int), computed
+ *   from mu itself: the solve returns VP_OK only when that residual is <= tol
+ *   (each restart cycle begins with it; the Arnoldi recurrence's estimate
+ *   only ends a cycle).  max_iter >= 1 bounds every operator product, those
+ *   residuals included; restart in [1, 200].  iters, resid (host, may be
+ *   NULL): products taken, and the last relative residual (computed from mu
+ *   on VP_OK, the recurrence's estimate when max_iter ran out inside a
+ *   cycle).
+ * Resolution: at a node the double layer's local part carries, from its
+ *   delta^{3/2} term on, mu'' and mu' from the panel interpolant, of size
+ *   delta_1^{3/2} |kappa| / h^2 next to mu/2 for a density varying on the
+ *   node spacing h.  A boundary resolved far finer than sqrt(delta_1) makes
+ *   the operator strongly non-normal and GMRES stalls (measured on circles:
+ *   condition number 1.2e4 at chi = 1.1, 1.6e8 at 4; 1.9e-7 attainable at
+ *   chi = 100).  With order_d >= 3 the solve computes
+ *   chi = delta_1^{3/2} max|kappa| / h^2 over the panels (h = panel length / q,
+ *   from the plan's boundary weights and its targets' kappa) and returns
+ *   VP_ERR_GEOMETRY above 4 (above 2 for the exterior Dirichlet and Neumann
+ *   operator of the next block, which degrades earlier: 9.4e7 at chi = 2),
+ *   where residuals of data with every frequency stall above 1e-10.  Remedies: coarser panels (about sqrt(N) boundary nodes for N
+ *   volume nodes keeps chi small), a smaller delta_1, or order_d <= 2.
  * Runs on the plan's stream and synchronizes it before returning.  Scratch
  * of (restart + 11) n doubles is allocated for the call.  VP_ERR_ARG for a
  * plan without D, or whose nodes or targets are not the n_pan*q panel nodes,
  * for only one of f_src and jet6, or for a source on a plan without V or
- * volume nodes;
+ * volume nodes; VP_ERR_GEOMETRY past the resolution limit;
  * VP_ERR_TOL when max_iter products do not reach tol. */
 vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,
                              const int32_t* pan, const double* u, const double* g, const double* f_src,
@@ -349,8 +363,9 @@ vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double*
  *   vp_eval with f, sigma = g and mu = -ub on a plan with interior targets.
  *
  * Both synchronize the plan's stream, allocate (restart + 11) n doubles of
- * scratch, and return VP_ERR_ARG / VP_ERR_TOL as vp_dirichlet_solve does
- * (and VP_ERR_ARG for a NULL bnd_w, or a Neumann plan without S). */
+ * scratch, count products and accept residuals as vp_dirichlet_solve does, and
+ * return VP_ERR_ARG / VP_ERR_GEOMETRY (resolution limit 2) / VP_ERR_TOL as
+ * it does (and VP_ERR_ARG for a NULL bnd_w, or a Neumann plan without S). */
 vp_status vp_exterior_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
                                       const double* bnd_y, const double* bnd_w, const int32_t* pan, const double* u,
                                       const double* g, double* mu, double tol, int max_iter, int restart,

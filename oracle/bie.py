@@ -16,6 +16,12 @@ r = 0 and sgn = +1 (history part plus the local part's interior limit), the
 density's jets at the node coming from its panel interpolant
 (oracle.geometry).  The operator is linear in mu, so its matrix is assembled
 column by column from unit densities and the system is solved directly.
+
+A problem may carry the curve's exact derivatives (curvature=: a callable
+giving kappa, gamma3, gamma4 at the closest points of given points) in place
+of the panel interpolant's, whose higher derivatives hold the nodal
+coordinates' rounding amplified; the closest point, normal and density jets
+still come from the panels.
 """
 import copy
 
@@ -45,16 +51,31 @@ class _Layer:
     n_tgt = property(lambda self: self.tgt_x.size)
 
 
-def on_boundary_problem(bx, by, bnx, bny, bw, q, src=None):
+def _curvature_override(geom, curvature, tx, ty):
+    if curvature is not None:
+        c = curvature(np.asarray(tx, float), np.asarray(ty, float))
+        geom.update({k: np.asarray(c[k], float) for k in ("kappa", "gamma3", "gamma4")})
+    return geom
+
+
+def on_boundary_problem(bx, by, bnx, bny, bw, q, src=None, curvature=None):
     """Problem whose targets are the boundary nodes themselves, each with its
     local frame from the panels and sgn = +1 (the interior limit); src =
-    (x, y, w) of the volume nodes, if any."""
+    (x, y, w) of the volume nodes, if any; curvature: see the module header."""
     bx, by = np.asarray(bx, float), np.asarray(by, float)
     fr = G.boundary_frame(bx, by, q, bx, by)
     geom = dict(r=np.zeros(bx.size), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
                 gamma4=fr["gamma4"], sgn=np.ones(bx.size, np.int8))
+    _curvature_override(geom, curvature, bx, by)
     return _Layer(bx, by, np.asarray(bnx, float), np.asarray(bny, float), np.asarray(bw, float),
-                  bx.copy(), by.copy(), geom, info=dict(q=q, pan=fr["pan"], u=fr["u"]), src=src)
+                  bx.copy(), by.copy(), geom, info=dict(q=q, pan=fr["pan"], u=fr["u"], curvature=curvature), src=src)
+
+
+def _target_frames(P, tx, ty):
+    """Frames of targets (tx, ty) from P's panels (with P's exact curve derivatives, if any)."""
+    fr = G.boundary_frame(P.bnd_x, P.bnd_y, P.info["q"], tx, ty)
+    geom = {k: fr[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    return _curvature_override(geom, P.info.get("curvature"), tx, ty), fr
 
 
 def _jets(P, mu):
@@ -106,8 +127,7 @@ def solution_at(P, mu, tx, ty, f_src=None, jet6=None):
     """u = V[f] + D[mu] at targets (tx, ty): their frames and the density's jets
     from the panels, jet6 = f's jets at the targets (with f_src)."""
     q = P.info["q"]
-    fr = G.boundary_frame(P.bnd_x, P.bnd_y, q, tx, ty)
-    geom = {k: fr[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    geom, fr = _target_frames(P, tx, ty)
     T = _Layer(P.bnd_x, P.bnd_y, P.bnd_nx, P.bnd_ny, P.bnd_w, np.asarray(tx, float), np.asarray(ty, float),
                geom, np.asarray(mu, float), G.density_jets(P.bnd_x, P.bnd_y, q, mu, fr["pan"], fr["u"], 4),
                src=(P.src_x, P.src_y, P.src_w), f_src=f_src, jet6=jet6)
@@ -169,8 +189,7 @@ def solve_neumann(P, g, f_src=None, jet6=None):
 def neumann_solution_at(P, ub, g, tx, ty, f_src=None, jet6=None):
     """u = V[f] + S[g] - D[ub] at interior targets (tx, ty)."""
     q = P.info["q"]
-    fr = G.boundary_frame(P.bnd_x, P.bnd_y, q, tx, ty)
-    geom = {k: fr[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    geom, fr = _target_frames(P, tx, ty)
     mu = -np.asarray(ub, float)
     T = _Layer(P.bnd_x, P.bnd_y, P.bnd_nx, P.bnd_ny, P.bnd_w, np.asarray(tx, float), np.asarray(ty, float),
                geom, mu, G.density_jets(P.bnd_x, P.bnd_y, q, mu, fr["pan"], fr["u"], 4),
@@ -200,9 +219,7 @@ def reversed_boundary(bx, by, bnx, bny, bw):
 def volume_at(P, f_src, jet6, tx, ty, delta=None):
     """V[f] at targets (tx, ty) with their frames from P's panels (P's volume
     nodes; jet6 = f's jets at the targets)."""
-    q = P.info["q"]
-    fr = G.boundary_frame(P.bnd_x, P.bnd_y, q, tx, ty)
-    geom = {k: fr[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    geom, _ = _target_frames(P, tx, ty)
     T = _Layer(P.bnd_x, P.bnd_y, P.bnd_nx, P.bnd_ny, P.bnd_w, np.asarray(tx, float), np.asarray(ty, float), geom,
                src=(P.src_x, P.src_y, P.src_w), f_src=np.asarray(f_src, float), jet6=np.asarray(jet6, float))
     return evaluate(T, kinds="V", delta=delta1_of(P) if delta is None else delta)["V"]

@@ -8,9 +8,11 @@ Nothing here is imported by the product path.
 Boundary: n_pan panels in order along the curve, counter-clockwise (interior
 on the left), each holding q nodes at the Gauss-Legendre points of its own
 parameter u in [-1, 1], ascending.  On a panel each coordinate (and a density)
-is its degree q-1 interpolant in u, here as a Legendre series fitted with
-numpy, less the coefficients below the rounding of the fit (see
-_panel_series).
+is its degree q-1 interpolant in u, here as the Legendre series through the
+q nodal values (numpy's fit of degree q-1 at q points, which interpolates).
+Its derivatives are taken as they are: the high coefficients of a finely
+resolved panel hold mostly the nodal values' rounding, which the derivatives
+amplify (fourth derivatives most), and nothing here removes it.
 
 Frame of a target p:
 1. the nearest boundary node (lowest index on ties) gives a panel and u;
@@ -35,14 +37,10 @@ ON_CURVE = 1e-12   # r <= ON_CURVE |x'(u*)|: the target is on the boundary (sgn 
 
 
 def _panel_series(vals, q):
-    """Legendre coefficients of the interpolants of vals[n_pan, q] at the GL points,
-    with those below the transform's own rounding bound 4 q eps max|vals| of the
-    panel set to zero: they carry only rounding, which the derivatives amplify
-    by up to k^(2m) near the panel ends."""
+    """Legendre coefficients of the degree q-1 interpolants of vals[n_pan, q]
+    at the Gauss-Legendre points of each panel."""
     xg, _ = L.leggauss(q)
-    c = np.stack([L.legfit(xg, v, q - 1) for v in vals])
-    floor = 4 * q * np.finfo(float).eps * np.max(np.abs(vals), axis=1, keepdims=True)
-    return np.where(np.abs(c) < floor, 0.0, c)
+    return np.stack([L.legfit(xg, v, q - 1) for v in vals])
 
 
 def _derivs(c, u, nmax):

@@ -34,19 +34,24 @@ def _c(r, delta):
     return np.asarray(r, float) / np.sqrt(delta)
 
 
-def volume_local(delta, r, kappa, f, f_eta, f_xixi, f_etaeta, order=4):
+def volume_local(delta, r, kappa, f, f_eta, f_xixi, f_etaeta, order=4, sgn=None):
     """V_L[f] at targets inside or on the boundary (Lemma 4.5, sign reading above).
 
-    Far targets (c > 12) use the interior limit delta f + delta^2 (f_xixi+f_etaeta)/2.
+    Far targets (c > 12) inside use the interior limit delta f + delta^2 (f_xixi+f_etaeta)/2;
+    far targets outside (sgn < 0) get zero: V_L is the time integral over [0, delta] of the
+    heat kernel against f, which vanishes off the domain, and the kernel's mass within the
+    domain is below 1e-14 there (Sec. 2.2's 12 sqrt(delta) cutoff).  Near exterior targets
+    are outside the lemma (the caller rejects them).
     """
     c = _c(r, delta)
     near = c <= C_FAR
+    inside = np.ones_like(c, bool) if sgn is None else np.asarray(sgn) >= 0
     E = erfc(c / 2)
     e = np.exp(-c * c / 4)
     out = np.zeros_like(c)
     if order >= 2:
         t = delta / 4 * (2 * erf(c / 2) + 2 * e * c / SQPI - c * c * E + 2) * f
-        out += np.where(near, t, delta * f)
+        out += np.where(near, t, np.where(inside, delta * f, 0.0))
     if order >= 3:
         t = delta ** 1.5 * ((4 - 2 * c * c) * e + SQPI * c ** 3 * E) * (2 * f_eta - kappa * f) / (12 * SQPI)
         out += np.where(near, t, 0.0)
@@ -56,7 +61,7 @@ def volume_local(delta, r, kappa, f, f_eta, f_xixi, f_etaeta, order=4):
             E * (4 * c4 * kappa * f_eta - 3 * (c4 + 4) * f_etaeta + (c4 - 12) * f_xixi - 3 * c4 * kappa ** 2 * f)
             + 2 * c * (c * c - 2) * e * (-4 * kappa * f_eta + 3 * f_etaeta - f_xixi + 3 * kappa ** 2 * f) / SQPI
             + 24 * (f_xixi + f_etaeta))
-        out += np.where(near, t, delta ** 2 / 2 * (f_xixi + f_etaeta))
+        out += np.where(near, t, np.where(inside, delta ** 2 / 2 * (f_xixi + f_etaeta), 0.0))
     return out
 
 

@@ -48,7 +48,7 @@ def evaluate(problem, delta=None, order_v=4, order_s=3, order_d=3, kinds="VSD", 
         if np.any((g["sgn"] < 0) & (c_ <= 12.0)):
             raise ValueError("volume local part is defined for targets in the closed domain")
         f, fe, fxx, fee = rotate_jets(problem.jet6, g["nx"], g["ny"])
-        vl = volume_local(delta, g["r"], g["kappa"], f, fe, fxx, fee, order=order_v)
+        vl = volume_local(delta, g["r"], g["kappa"], f, fe, fxx, fee, order=order_v, sgn=g["sgn"])
         out["V_hist"], out["V_loc"], out["V"] = vh, vl, vh + vl
         total += out["V"]
     if use_s:

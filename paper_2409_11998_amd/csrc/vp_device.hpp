@@ -1188,8 +1188,10 @@ __device__ void dev_local(const LocalArgs& a, int64_t i)
     if (a.dc) u += a.dc_weight * dcv;
     const int64_t n = a.n;
     if (!near) {
-        // beyond 12 sqrt(delta): only the interior limit of V_L (frame and layer data not read)
-        if (a.jet6) {
+        // beyond 12 sqrt(delta): only the interior limit of V_L inside the domain; outside it the
+        // local part of V is exponentially small (f vanishes off the domain) and is zero (frame
+        // and layer data not read)
+        if (a.jet6 && a.sgn[i] >= 0) {
             const double f = a.jet6[i], lap = a.jet6[3 * n + i] + a.jet6[5 * n + i];
             double v = 0.0;
             if (a.order_v >= 2) v += d * f;

@@ -11,9 +11,41 @@ from scipy.special import exp1
 import oracle
 from oracle import bie
 from workloads.mesh import curve_mesh
-from workloads.problems import StarCurve, disk_problem, gauss_jets, panel_nodes, star_params
+from workloads.problems import StarCurve, curve_frame_jets, disk_problem, gauss_jets, panel_nodes, star_params
 
 pytestmark = pytest.mark.gpu
+
+# Device and oracle take the curve's exact derivatives (kappa, gamma3, gamma4)
+# at every closest point: the panel interpolant's higher derivatives carry the
+# nodal rounding amplified, which the device and the oracle treat differently
+# (the device drops coefficients below that rounding), so with panel curvature
+# the two operators would differ by rounding amplified by the solve.  The
+# panel frames themselves are compared with the oracle's in the geometry tests.
+
+
+def _circle_curv(R=1.0, sense=1):
+    """Exact derivatives of a circle of radius R (sense -1: traversed clockwise)."""
+    def c(x, y):
+        n = np.size(x)
+        return dict(kappa=np.full(n, sense / R), gamma3=np.zeros(n), gamma4=np.full(n, sense * 3.0 / R ** 3))
+    return c
+
+
+def _star_curv(curve):
+    """Exact derivatives of a star curve at the closest points (series reversion)."""
+    def c(x, y):
+        t = curve.closest(np.stack([np.asarray(x, float), np.asarray(y, float)], 1))
+        fr, _ = curve_frame_jets(curve, t, [])
+        return dict(kappa=fr["kappa"], gamma3=fr["gamma3"], gamma4=fr["gamma4"])
+    return c
+
+
+def _with_curv(torch, geom, curv, x, y):
+    if curv is not None:
+        c = curv(np.asarray(x, float), np.asarray(y, float))
+        for k in ("kappa", "gamma3", "gamma4"):
+            geom[k] = _t(torch, c[k])
+    return geom
 
 
 def _gpu():
@@ -36,7 +68,7 @@ def _circle(n_pan, q=16):
     return np.cos(t), np.sin(t), np.cos(t), np.sin(t), w, t
 
 
-def _solve(torch, bx, by, bnx, bny, bw, q, g, src=None, f=None, jet6=None, **kw):
+def _solve(torch, bx, by, bnx, bny, bw, q, g, src=None, f=None, jet6=None, curv=None, **kw):
     """Plan on the nodes (targets = nodes, r = 0, sgn = +1, frames from the panels), then the solve;
     src = (x, y, w) of volume nodes with f there and jet6 at the boundary nodes."""
     from paper_2409_11998_amd import Plan, boundary_frame, dirichlet_solve
@@ -44,6 +76,7 @@ def _solve(torch, bx, by, bnx, bny, bw, q, g, src=None, f=None, jet6=None, **kw)
     fr = boundary_frame(dx, dy, q, dx, dy)
     geom = dict(r=torch.zeros_like(dx), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
                 gamma4=fr["gamma4"], sgn=torch.ones(dx.numel(), dtype=torch.int8, device="cuda"))
+    _with_curv(torch, geom, curv, bx, by)
     e = torch.zeros(0, dtype=torch.float64, device="cuda")
     sx, sy, sw = (e, e, e) if src is None else (_t(torch, a) for a in src)
     plan = Plan(sx, sy, sw, dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw), dx, dy, geom, tol=1e-10,
@@ -59,8 +92,8 @@ def test_circle_matches_oracle_and_closed_form():
     torch = _gpu()
     bx, by, nx, ny, w, t = _circle(32)
     g = np.cos(3 * t)
-    plan, mu, its, res = _solve(torch, bx, by, nx, ny, w, 16, g)
-    P = bie.on_boundary_problem(bx, by, nx, ny, w, 16)
+    plan, mu, its, res = _solve(torch, bx, by, nx, ny, w, 16, g, curv=_circle_curv())
+    P = bie.on_boundary_problem(bx, by, nx, ny, w, 16, curvature=_circle_curv())
     ref = bie.solve_dirichlet(P, g)
     e = oracle.rel_linf(mu, ref)
     print("circle: GMRES products", its, "residual", res, "mu vs oracle", e, "vs -2g", np.max(np.abs(mu + 2 * g)))
@@ -81,9 +114,10 @@ def test_star_interior_values():
     def uex(x, y):
         return ((x + 1j * y - z0) ** 3).real + 0.3 * x - 0.2 * y + 1.0
 
-    plan, mu, its, res = _solve(torch, bx, by, bnx, bny, bw, q, uex(bx, by))
+    curv = _star_curv(curve)
+    plan, mu, its, res = _solve(torch, bx, by, bnx, bny, bw, q, uex(bx, by), curv=curv)
     plan.close()
-    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q)
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q, curvature=curv)
     ref = bie.solve_dirichlet(P, uex(bx, by))
     e_mu = oracle.rel_linf(mu, ref)
     # u = D[mu] at interior points through vp_eval, frames and jets from the panels
@@ -94,7 +128,7 @@ def test_star_interior_values():
     tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
     dx, dy = _t(torch, bx), _t(torch, by)
     fr = boundary_frame(dx, dy, q, _t(torch, tx), _t(torch, ty))
-    geom = {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    geom = _with_curv(torch, {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}, curv, tx, ty)
     e0 = torch.zeros(0, dtype=torch.float64, device="cuda")
     # the interior evaluation keeps the boundary problem's delta_1 (3 mean(w)^2): no volume nodes
     pl = Plan(e0, e0, e0, dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw), _t(torch, tx), _t(torch, ty),
@@ -156,17 +190,19 @@ def test_poisson_with_volume_source(domain):
         x, y, w = D.src_x, D.src_y, D.src_w
         bx, by, bnx, bny, bw, t = _circle(48)
         uex = lambda px, py: _w_radial(np.hypot(px, py)) + np.real((px + 1j * py) ** 3)
+        curv = _circle_curv()
     else:
         curve = StarCurve(**star_params(3, r=0.8))
         x, y, w, _ = curve_mesh(curve, 1500, 3)
         bx, by, bnx, bny, bw, _ = panel_nodes(curve, 32, q)
         z0 = complex(0.1, -0.05)
         uex = lambda px, py: _w_radial(np.hypot(px, py)) + np.real((px + 1j * py - z0) ** 3)
+        curv = _star_curv(curve)
     f = gauss_jets(x, y, GAUSS)[0]
     jb = gauss_jets(bx, by, GAUSS)
-    plan, mu, its, res = _solve(torch, bx, by, bnx, bny, bw, q, uex(bx, by), src=(x, y, w), f=f, jet6=jb)
+    plan, mu, its, res = _solve(torch, bx, by, bnx, bny, bw, q, uex(bx, by), src=(x, y, w), f=f, jet6=jb, curv=curv)
     plan.close()
-    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q, src=(x, y, w))
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q, src=(x, y, w), curvature=curv)
     ref = bie.solve_dirichlet(P, uex(bx, by), f, jb)
     e_mu = oracle.rel_linf(mu, ref)
     rng = np.random.default_rng(2)
@@ -177,7 +213,7 @@ def test_poisson_with_volume_source(domain):
     dx, dy = _t(torch, bx), _t(torch, by)
     ftx, fty = _t(torch, tx), _t(torch, ty)
     fr = boundary_frame(dx, dy, q, ftx, fty)
-    geom = {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    geom = _with_curv(torch, {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}, curv, tx, ty)
     pl = Plan(_t(torch, x), _t(torch, y), _t(torch, w), dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw),
               ftx, fty, geom, tol=1e-10, precision=1, kinds=5)
     mu_t = _t(torch, mu)
@@ -205,13 +241,13 @@ def test_source_arguments():
     assert ei.value.status == VP_ERR_ARG
 
 
-def _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, src=None, f=None, sigma=None, mu=None):
+def _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, src=None, f=None, sigma=None, mu=None, curv=None):
     """V[f] + S[sigma] + D[mu] at (tx, ty) through vp_eval, frames and jets from the panels."""
     from paper_2409_11998_amd import Plan, boundary_frame, boundary_jets
     dx, dy = _t(torch, bx), _t(torch, by)
     ftx, fty = _t(torch, tx), _t(torch, ty)
     fr = boundary_frame(dx, dy, q, ftx, fty)
-    geom = {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+    geom = _with_curv(torch, {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}, curv, tx, ty)
     e0 = torch.zeros(0, dtype=torch.float64, device="cuda")
     sx, sy, sw = (e0, e0, e0) if src is None else (_t(torch, a) for a in src)
     kinds = (1 if f is not None else 0) | (2 if sigma is not None else 0) | (4 if mu is not None else 0)
@@ -231,16 +267,18 @@ def _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, src=None, f=None, sigma=Non
     return out
 
 
-def _node_plan(torch, bx, by, bnx, bny, bw, q, src=None, kinds=4):
+def _node_plan(torch, bx, by, bnx, bny, bw, q, src=None, kinds=4, curv=None, order_d=None):
     from paper_2409_11998_amd import Plan, boundary_frame
     dx, dy = _t(torch, bx), _t(torch, by)
     fr = boundary_frame(dx, dy, q, dx, dy)
     geom = dict(r=torch.zeros_like(dx), nx=fr["nx"], ny=fr["ny"], kappa=fr["kappa"], gamma3=fr["gamma3"],
                 gamma4=fr["gamma4"], sgn=torch.ones(dx.numel(), dtype=torch.int8, device="cuda"))
+    _with_curv(torch, geom, curv, bx, by)
     e0 = torch.zeros(0, dtype=torch.float64, device="cuda")
     sx, sy, sw = (e0, e0, e0) if src is None else (_t(torch, a) for a in src)
+    kw = {} if order_d is None else dict(order_d=order_d)
     plan = Plan(sx, sy, sw, dx, dy, _t(torch, bnx), _t(torch, bny), _t(torch, bw), dx, dy, geom, tol=1e-10,
-                precision=1, kinds=kinds)
+                precision=1, kinds=kinds, **kw)
     return plan, dx, dy, fr
 
 
@@ -254,24 +292,27 @@ def test_exterior_dirichlet(domain):
     if domain == "circle":
         bx, by, bnx, bny, bw, t = _circle(32)
         uext = lambda x, y: np.real((x + 1j * y) ** -3)
+        curv = _circle_curv()
     else:
-        bx, by, bnx, bny, bw, _ = panel_nodes(StarCurve(**star_params(3, r=0.8)), 32, q)
+        curve = StarCurve(**star_params(3, r=0.8))
+        bx, by, bnx, bny, bw, _ = panel_nodes(curve, 32, q)
         z0 = complex(0.1, -0.05)
         uext = lambda x, y: np.real(1 / (x + 1j * y - z0)) + 0.3
-    plan, dx, dy, fr = _node_plan(torch, bx, by, bnx, bny, bw, q)
+        curv = _star_curv(curve)
+    plan, dx, dy, fr = _node_plan(torch, bx, by, bnx, bny, bw, q, curv=curv)
     mu, its, res = exterior_dirichlet_solve(plan, q, dx, dy, _t(torch, bw), fr["pan"], fr["u"],
                                             _t(torch, uext(bx, by)))
     torch.cuda.synchronize()
     plan.close()
     mu = mu.cpu().numpy()
-    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q)
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q, curvature=curv)
     ref = bie.solve_exterior_dirichlet(P, uext(bx, by))
     rng = np.random.default_rng(5)
     k = rng.integers(0, bx.size, 300)
     s = rng.uniform(1.03, 2.5, 300)
     cx, cy = np.mean(bx), np.mean(by)
     tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
-    u = _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, mu=mu) + float(np.dot(bw, mu))
+    u = _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, mu=mu, curv=curv) + float(np.dot(bw, mu))
     u_ref = bie.exterior_solution_at(P, ref, tx, ty)
     e_mu, e_u, e_x = oracle.rel_linf(mu, ref), oracle.rel_linf(u, u_ref), np.max(np.abs(u - uext(tx, ty)))
     print(domain, "exterior: products", its, "residual", res, "mu vs oracle", e_mu, "u vs oracle", e_u, "vs exact", e_x)
@@ -292,12 +333,14 @@ def test_neumann(domain):
     src = f = jb = None
     if domain in ("circle", "disk"):
         bx, by, bnx, bny, bw, t = _circle(32 if domain == "circle" else 48)
+        curv = _circle_curv()
         if domain == "disk":
             D = disk_problem(2000, seed=1, gauss=GAUSS)
             src, f = (D.src_x, D.src_y, D.src_w), D.f_src
     else:
         curve = StarCurve(**star_params(3, r=0.8))
         bx, by, bnx, bny, bw, _ = panel_nodes(curve, 32, q)
+        curv = _star_curv(curve)
         x, y, w, _ = curve_mesh(curve, 1500, 3)
         src, f = (x, y, w), gauss_jets(x, y, GAUSS)[0]
         z0 = complex(0.1, -0.05)
@@ -309,20 +352,20 @@ def test_neumann(domain):
     uin = lambda px, py: ((_w_radial(np.hypot(px, py)) if with_src else 0.0) + np.real((px + 1j * py - z0) ** 3))
     if with_src:
         jb = gauss_jets(bx, by, GAUSS)
-    plan, dx, dy, fr = _node_plan(torch, bx, by, bnx, bny, bw, q, src=src, kinds=7 if with_src else 6)
+    plan, dx, dy, fr = _node_plan(torch, bx, by, bnx, bny, bw, q, src=src, kinds=7 if with_src else 6, curv=curv)
     kw = dict(f=_t(torch, f), jet6=_t(torch, jb)) if with_src else {}
     ub, its, res = neumann_solve(plan, q, dx, dy, _t(torch, bw), fr["pan"], fr["u"], _t(torch, g), **kw)
     torch.cuda.synchronize()
     plan.close()
     ub = ub.cpu().numpy()
-    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q, src=src)
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q, src=src, curvature=curv)
     ref = bie.solve_neumann(P, g, f, jb)
     rng = np.random.default_rng(6)
     k = rng.integers(0, bx.size, 300)
     s = rng.uniform(0.2, 0.95, 300)
     cx, cy = np.mean(bx), np.mean(by)
     tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
-    u = _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, src=src, f=f, sigma=g, mu=-ub)
+    u = _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, src=src, f=f, sigma=g, mu=-ub, curv=curv)
     u_ref = bie.neumann_solution_at(P, ref, g, tx, ty, f, gauss_jets(tx, ty, GAUSS) if with_src else None)
     c = np.dot(bw, uin(bx, by)) / np.sum(bw)
     e_b, e_u = oracle.rel_linf(ub, ref), oracle.rel_linf(u, u_ref)
@@ -361,7 +404,8 @@ def test_exterior_dirichlet_with_volume_source():
         dx, dy = _t(torch, rb[0]), _t(torch, rb[1])
         ftx, fty = _t(torch, tx), _t(torch, ty)
         fr = boundary_frame(dx, dy, q, ftx, fty)
-        geom = {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+        geom = _with_curv(torch, {kk: fr[kk] for kk in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")},
+                          _circle_curv(1.0, -1), tx, ty)
         if on_nodes:   # the interior limit at the nodes
             geom["r"] = torch.zeros_like(ftx)
             geom["sgn"] = torch.ones(ftx.numel(), dtype=torch.int8, device="cuda")
@@ -372,20 +416,21 @@ def test_exterior_dirichlet_with_volume_source():
         return out
 
     vb = volume(rb[0], rb[1], True)[::-1]
-    plan, dx, dy, fr = _node_plan(torch, bx, by, nx, ny, w, q, src=src, kinds=4)
+    plan, dx, dy, fr = _node_plan(torch, bx, by, nx, ny, w, q, src=src, kinds=4, curv=_circle_curv())
     mu, its, res = exterior_dirichlet_solve(plan, q, dx, dy, _t(torch, w), fr["pan"], fr["u"],
                                             _t(torch, np.cos(3 * t) - vb))
     torch.cuda.synchronize()
     plan.close()
     mu = mu.cpu().numpy()
-    Pcw = bie.on_boundary_problem(*rb, q, src=src)
+    Pcw = bie.on_boundary_problem(*rb, q, src=src, curvature=_circle_curv(1.0, -1))
     vb_ref = bie.volume_at_nodes(Pcw, f, T._ring(rb[0], rb[1]))[::-1]
-    P = bie.on_boundary_problem(bx, by, nx, ny, w, q, src=src)
+    P = bie.on_boundary_problem(bx, by, nx, ny, w, q, src=src, curvature=_circle_curv())
     ref = bie.solve_exterior_dirichlet(P, np.cos(3 * t) - vb_ref)
     rng = np.random.default_rng(0)
     tq, rq = rng.uniform(0, 2 * np.pi, 40), rng.uniform(1.05, 2.2, 40)
     tx, ty = rq * np.cos(tq), rq * np.sin(tq)
-    u = volume(tx, ty, False) + _eval_at(torch, bx, by, nx, ny, w, q, tx, ty, src=src, mu=mu) + float(np.dot(w, mu))
+    u = (volume(tx, ty, False) + _eval_at(torch, bx, by, nx, ny, w, q, tx, ty, src=src, mu=mu, curv=_circle_curv())
+         + float(np.dot(w, mu)))
     u_ref = bie.volume_at(Pcw, f, T._ring(tx, ty), tx, ty) + bie.exterior_solution_at(P, ref, tx, ty)
     ue = np.array([T._ring_radial_solution(r) for r in rq]) + rq ** -3 * np.cos(3 * tq)
     e_v, e_mu = oracle.rel_linf(vb, vb_ref), oracle.rel_linf(mu, ref)
@@ -396,28 +441,36 @@ def test_exterior_dirichlet_with_volume_source():
     assert e_x <= 2e-4
 
 
-def test_large_boundary_two_pass_projections():
-    """70,400 boundary nodes (4400 panels on a circle of radius 3): the solver's
-    projections above 65,536 nodes take the two-pass reduction.  delta_1 comes
-    from a disk's volume nodes (no volume kind); mu against the closed form
-    -2 cos 3t, which holds at any radius (the oracle's dense operator is out of
-    reach at this size).  This boundary is resolved ~100x finer than
-    sqrt(delta_1), where the local expansions' derivative terms grow with the
-    density's frequency, so the discrete operator is badly conditioned at high
-    frequencies: the oracle's own operator, applied matrix-free under GMRES,
-    stalls at a relative residual of 1.9e-7 (mu 6.2e-6 from the closed form).
-    The solve runs to 1e-6, which the oracle reaches within three products."""
+def test_large_boundary_guard_and_two_pass_projections():
+    """70,400 boundary nodes (4400 panels on a circle of radius 3) with delta_1
+    from a disk's volume nodes (sqrt(delta_1) = 0.028 against a node spacing
+    of 2.7e-4).  With the default order the double layer's local part takes
+    mu'' and mu' from the panels at size delta^{3/2} kappa / h^2 = 103 times the
+    jump term's scale: the solve refuses it (VP_ERR_GEOMETRY).  Planned with
+    order_d = 2 (no density derivatives at the nodes) the same boundary solves
+    to 1e-11 in a few products, the projections above 65,536 nodes taking
+    their two-pass reduction; mu against the closed form -2 cos 3t within the
+    dropped delta^{3/2} terms (about 5e-6 here: delta^{3/2} (10 kappa^3 / 16 -
+    gamma4 / 4 + kappa 9 / (2 R^2)) / sqrt(pi) times |mu| = 2, over the jump 1/2)."""
     torch = _gpu()
     from paper_2409_11998_amd import dirichlet_solve
+    from paper_2409_11998_amd.binding import VP_ERR_GEOMETRY, VPError
     D = disk_problem(2000, seed=1, gauss=GAUSS)
     bx, by, nx, ny, w, t = _circle(4400)
     bx, by, w = 3.0 * bx, 3.0 * by, 3.0 * w
     assert bx.size > 1 << 16
-    plan, dx, dy, fr = _node_plan(torch, bx, by, nx, ny, w, 16, src=(D.src_x, D.src_y, D.src_w), kinds=4)
-    mu, its, res = dirichlet_solve(plan, 16, dx, dy, fr["pan"], fr["u"], _t(torch, np.cos(3 * t)), tol=1e-6)
+    src = (D.src_x, D.src_y, D.src_w)
+    plan, dx, dy, fr = _node_plan(torch, bx, by, nx, ny, w, 16, src=src, kinds=4, curv=_circle_curv(3.0))
+    with pytest.raises(VPError) as ei:
+        dirichlet_solve(plan, 16, dx, dy, fr["pan"], fr["u"], _t(torch, np.cos(3 * t)))
+    assert ei.value.status == VP_ERR_GEOMETRY
+    print("order_d = 3:", ei.value)
+    plan.close()
+    plan, dx, dy, fr = _node_plan(torch, bx, by, nx, ny, w, 16, src=src, kinds=4, curv=_circle_curv(3.0), order_d=2)
+    mu, its, res = dirichlet_solve(plan, 16, dx, dy, fr["pan"], fr["u"], _t(torch, np.cos(3 * t)), tol=1e-11)
     torch.cuda.synchronize()
     plan.close()
     e = np.max(np.abs(mu.cpu().numpy() + 2 * np.cos(3 * t)))
-    print("70,400 nodes: products", its, "residual", res, "mu vs -2 cos 3t", e)
-    assert res <= 1e-5 and its <= 20
+    print("70,400 nodes, order_d = 2: products", its, "residual", res, "mu vs -2 cos 3t", e)
+    assert res <= 1e-11 and its <= 20
     assert e <= 2e-5

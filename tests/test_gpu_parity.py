@@ -201,3 +201,60 @@ def test_looser_tolerances_narrow_widths(precision, tol):
     e = oracle.rel_linf(got, ref)
     print("precision", precision, "tol", tol, "widths", info["width"], "tiles", info["tile"], "e_inf", e)
     assert e <= tol
+
+
+def test_disk_volume_outside_matches_oracle_and_newton():
+    """V[f] at targets outside the unit disk, beyond 12 sqrt(delta_1) (the local
+    part vanishes there, whatever f's jets say): against the oracle and the
+    point-mass closed form -log(r)/2 for f = 1."""
+    from workloads.problems import disk_at_targets
+    P = disk_problem(2000, seed=7, gauss=((1.0, 0.0, 0.0, 1e6),))
+    rng = np.random.default_rng(11)
+    th, rr = rng.uniform(0, 2 * np.pi, 3000), rng.uniform(1.4, 3.0, 3000)
+    Q = disk_at_targets(P, rr * np.cos(th), rr * np.sin(th))
+    got, plan = _run(Q, "V", tol=1e-10, kinds=1)
+    plan.close()
+    ref = oracle.evaluate(Q, kinds="V")["V"]
+    e, ex = oracle.rel_linf(got, ref), np.max(np.abs(got + np.log(rr) / 2))
+    print("outside the disk: e_inf vs oracle", e, "max |V + log(r)/2|", ex)
+    assert e <= 1e-10 and ex <= 1e-7
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-10), (0, 1e-6)])
+def test_circle_layers_every_side_and_distance(precision, tol):
+    """S[sigma] + D[mu] through vp_eval on the unit circle, sigma = cos 2t,
+    mu = cos 3t, targets on the circle (sgn 0) and at c = r / sqrt(delta_1) from
+    0.3 to 40 inside (sgn +1) and outside (sgn -1), layer orders through
+    delta^2: against the oracle at the precision's tolerance and the closed
+    forms S = r^{+-2} cos 2t / 4, D = -r^3 cos 3t / 2 inside, 0 on, r^-3 cos 3t / 2
+    outside (up to the method's discretization error)."""
+    from workloads import circle_layer_problem
+    from workloads.problems import trig_density
+    nb = 1200
+    delta = 3 * (2 * np.pi / nb) ** 2
+    sd = np.sqrt(delta)
+    th = np.linspace(0.05, 2 * np.pi, 97, endpoint=False)
+    pts = [np.stack([np.cos(th), np.sin(th)], 1)]
+    for c in (0.3, 1.0, 2.5, 6.0, 11.0, 15.0, 40.0):
+        for sgn in (1, -1):
+            rad = 1 - sgn * c * sd
+            pts.append(np.stack([rad * np.cos(th + c), rad * np.sin(th + c)], 1))
+    tg = np.concatenate(pts)
+    _, s2 = trig_density([0.0, 0.0, 1.0], [])
+    _, s3 = trig_density([0.0, 0.0, 0.0, 1.0], [])
+    P = circle_layer_problem(nb, tg, sigma_fn=s2, mu_fn=s3)
+    assert set(np.unique(P.geom["sgn"])) == {-1, 0, 1}
+    got, plan = _run(P, "SD", tol=tol, precision=precision, kinds=6, order_s=4, order_d=4)
+    info = plan.info()
+    plan.close()
+    assert abs(info["delta1"] / delta - 1) <= 1e-14
+    ref = oracle.evaluate(P, kinds="SD", order_s=4, order_d=4)["total"]
+    e = oracle.rel_linf(got, ref)
+    r, t = np.hypot(tg[:, 0], tg[:, 1]), np.arctan2(tg[:, 1], tg[:, 0])
+    sg = P.geom["sgn"]
+    S_ex = np.where(r <= 1, r ** 2, r ** -2.0) * np.cos(2 * t) / 4
+    D_ex = np.where(sg > 0, -r ** 3 * np.cos(3 * t) / 2, np.where(sg == 0, 0.0, r ** -3.0 * np.cos(3 * t) / 2))
+    ex = np.max(np.abs(got - S_ex - D_ex))
+    print("precision", precision, "circle layers: e_inf vs oracle", e, "vs closed forms", ex)
+    assert e <= tol
+    assert ex <= 1e-6

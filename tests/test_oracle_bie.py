@@ -264,3 +264,78 @@ def test_exterior_dirichlet_with_source():
     print("exterior with source (max |V| on the circle, error): coarse", coarse, "fine", fine)
     assert coarse[0] >= 0.1                       # the volume term matters on the boundary
     assert coarse[1] <= 2e-4 and fine[1] <= 2e-6 and fine[1] <= coarse[1] / 30
+
+
+def _circle_operator(n_pan, delta, order_d=3, exact=False):
+    """The oracle's D_int on the unit circle (16-node panels) at a given delta_1,
+    its frames from the panels or exact (kappa = 1, gamma3 = 0, gamma4 = 3)."""
+    import copy
+    from oracle.potential import evaluate
+    bx, by, nx, ny, w, t = _circle(n_pan)
+    P = bie.on_boundary_problem(bx, by, nx, ny, w, 16)
+    if exact:
+        P.geom = dict(P.geom, kappa=np.ones(bx.size), gamma3=np.zeros(bx.size), gamma4=np.full(bx.size, 3.0))
+    A = np.empty((bx.size, bx.size))
+    for j in range(bx.size):
+        e = np.zeros(bx.size)
+        e[j] = 1.0
+        Q = copy.copy(P)
+        Q.mu, Q.mu_jet = e, bie._jets(P, e)
+        A[:, j] = evaluate(Q, kinds="D", delta=delta, order_d=order_d)["D"]
+    h = 2 * np.pi / bx.size
+    return A, w, delta ** 1.5 / h ** 2
+
+
+def _gmres_reaches(A, tol, maxiter):
+    from scipy.sparse.linalg import gmres
+    b = np.random.default_rng(0).standard_normal(A.shape[0])   # every frequency the panels carry
+    x, _ = gmres(A, b, rtol=tol, restart=50, maxiter=maxiter)
+    return np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= tol
+
+
+def test_operator_conditioning_grows_with_resolution():
+    """Why the solves refuse boundaries resolved far finer than sqrt(delta_1).
+    At a node the double layer's local part carries delta^{3/2} (kappa mu'' +
+    gamma3 mu') terms with mu's derivatives from the panel interpolant: for
+    the node spacing's frequency they are of size chi = delta^{3/2} kappa / h^2
+    next to the jump 1/2.  On the unit circle the oracle's D_int grows in
+    condition number with chi (2.4, 13, 254 at chi = 0.005, 0.05, 0.42), the
+    same with exact curve derivatives as with the panels' (so the frames do
+    not cause it), not at all without those terms (order_d = 2: about 2.1
+    throughout), and its eigenvalues stay near -1/2 (besides -1 for the
+    constants): the growth is non-normality.  GMRES(50) on a right-hand side
+    holding every frequency reaches the solves' default 1e-12 at chi = 0.21
+    within two cycles but not at chi = 1.7 within twenty (n = 512); the
+    operator x/2 + D[x] + (w . x) of the exterior and Neumann problems fails
+    already at chi = 0.59.  Smooth data converge far beyond those points; the
+    device solves refuse chi above 4 and 2, where the condition numbers pass
+    1e8 (1.6e8 and 9.4e7) and GMRES on every frequency reaches 1e-8 but not
+    1e-10."""
+    conds = []
+    for d in (2e-4, 1e-3, 4e-3):
+        A, _, chi = _circle_operator(16, d)
+        A2, _, _ = _circle_operator(16, d, order_d=2)
+        c, c2 = np.linalg.cond(A), np.linalg.cond(A2)
+        ev = np.sort(np.linalg.eigvals(A).real)   # ev[0] ~ -1: the constants (D_int[1] = -1)
+        print("chi %.3g: cond %.3g (order_d = 2: %.3g), eigenvalues' real parts: %.4f, then [%.3f, %.3f]"
+              % (chi, c, c2, ev[0], ev[1], ev[-1]))
+        conds.append(c)
+        assert c2 <= 2.5
+        assert abs(ev[0] + 1) <= 1e-3 and ev[1] > -0.6 and ev[-1] < -0.45
+    assert conds[0] <= 3 and conds[1] >= 4 * conds[0] and conds[2] >= 10 * conds[1]
+    Ae, _, _ = _circle_operator(16, 4e-3, exact=True)
+    assert abs(np.linalg.cond(Ae) / conds[2] - 1) <= 0.1
+    A, w, chi = _circle_operator(32, 1e-3)
+    assert 0.2 <= chi <= 0.22 and _gmres_reaches(A, 1e-12, 2)
+    A, w, chi = _circle_operator(32, 4e-3)
+    assert 1.6 <= chi <= 1.7 and not _gmres_reaches(A, 1e-12, 20)
+    A, w, chi = _circle_operator(32, 2e-3)
+    Aplus = A + np.eye(w.size) + np.outer(np.ones(w.size), w)
+    assert 0.58 <= chi <= 0.6 and not _gmres_reaches(Aplus, 1e-12, 20)
+    A, w, chi = _circle_operator(32, 7.13e-3)
+    assert 3.99 <= chi <= 4.01 and 1e8 <= np.linalg.cond(A) <= 1e9
+    assert _gmres_reaches(A, 1e-8, 20) and not _gmres_reaches(A, 1e-10, 20)
+    A, w, chi = _circle_operator(32, 4.49e-3)
+    Aplus = A + np.eye(w.size) + np.outer(np.ones(w.size), w)
+    assert 1.99 <= chi <= 2.01 and 5e7 <= np.linalg.cond(Aplus) <= 5e8
+    assert _gmres_reaches(Aplus, 1e-8, 20) and not _gmres_reaches(Aplus, 1e-10, 20)

@@ -8,7 +8,12 @@ panels) against quantities fixed independently of its formulas:
 * the star domains of the workloads, whose frames and density jets are built
   from the analytic curve by series reversion (a different route);
 * brute force: no sample of the panel interpolants lies closer to a target
-  than the closest point found.
+  than the closest point found;
+* the plain interpolant's curve derivatives and density jets on finely
+  resolved circles (where the nodal rounding dominates them) stay within the
+  rounding bound of tests/geometry_bounds.py against the exact values, and
+  the evaluation with panel geometry moves from the analytic-geometry one by
+  no more than the local expansions' response to those bounds.
 """
 import numpy as np
 import pytest
@@ -16,6 +21,7 @@ from numpy.polynomial import polynomial as Pm
 from numpy.polynomial.legendre import leggauss
 
 from oracle import geometry as G
+from tests.geometry_bounds import frame_bounds, jet_bounds
 from workloads import star_problem
 
 
@@ -123,29 +129,87 @@ def test_closest_point_beats_dense_sampling():
     assert np.all(dmin - fr["r"] <= 1e-5)   # the samples are 1/400 of a panel apart
 
 
-def test_panel_geometry_serves_the_method_at_fp64_tolerance():
+def _local_response(P, geom, bounds):
+    """Per target, the local parts' change (V, S, D at the oracle's default orders)
+    when kappa, gamma3 and gamma4 each move by their bound, summed over the three."""
+    import copy
+    import oracle
+    base = oracle.evaluate(P, kinds="VSD")["total"]
+    acc = np.zeros(P.n_tgt)
+    for k, name in enumerate(("kappa", "gamma3", "gamma4")):
+        Q = copy.copy(P)
+        Q.geom = dict(geom, **{name: geom[name] + bounds[k]})
+        acc += np.abs(oracle.evaluate(Q, kinds="VSD")["total"] - base)
+    return acc
+
+
+def test_panel_geometry_error_is_the_rounding_bound():
     """The whole evaluation (history + local parts of V, S, D) with frames and
-    layer jets taken from the panels agrees with the one from the analytic
-    curve: the layer jets are float64-grade, and the curve's fourth derivative,
-    which the double layer's local part uses, is limited by the nodal
-    coordinates' rounding amplified by the panel interpolant (finer panels
-    amplify it more): ~1.5e-9 on this lobed star (gamma4 up to 7e3)."""
+    layer jets taken from the panels against the one from the analytic curve.
+    The layer jets and the frame's position and normal are float64-grade: with
+    the analytic kappa, gamma3, gamma4 put back the two agree to 1e-11.  The
+    curve derivatives of the plain interpolant carry the nodal coordinates'
+    rounding amplified by the derivatives (gamma4 most, finer panels more); on
+    this lobed star they stay within their rounding bound of the analytic
+    values, and the evaluation moves by at most the local parts' response to
+    those bounds (a bit over 1e-7 of the largest value here)."""
     import copy
     import oracle
     P = star_problem(1500, seed=6)
     q = P.info["q"]
     fr = G.boundary_frame(P.bnd_x, P.bnd_y, q, P.tgt_x, P.tgt_y)
+    B = frame_bounds(P.bnd_x, P.bnd_y, q, fr["pan"], fr["u"], q)
+    near = P.info["near_mask"]   # the workload's exact frames (farther targets only need r)
+    for k, name in enumerate(("kappa", "gamma3", "gamma4")):
+        assert np.all((np.abs(fr[name] - P.geom[name]) <= B[k])[near]), name
     Q = copy.copy(P)
     Q.geom = {k: fr[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
     Q.sigma_jet = G.density_jets(P.bnd_x, P.bnd_y, q, P.sigma, fr["pan"], fr["u"], 2)
     Q.mu_jet = G.density_jets(P.bnd_x, P.bnd_y, q, P.mu, fr["pan"], fr["u"], 4)
     a = oracle.evaluate(P, kinds="VSD")["total"]
     b = oracle.evaluate(Q, kinds="VSD")["total"]
-    e = oracle.rel_linf(b, a)
-    print("panel vs analytic geometry: e_inf", e)
-    assert e <= 5e-9
-    # without the curve's derivatives (analytic kappa, gamma3, gamma4) the rest is float64-grade
+    resp = _local_response(P, P.geom, B)
+    print("panel vs analytic geometry: e_inf", oracle.rel_linf(b, a), "response bound", np.max(resp) / np.max(np.abs(a)))
+    assert np.all(np.abs(b - a) <= resp + 1e-11 * np.max(np.abs(a)))
+    # with the analytic curve derivatives put back the rest is float64-grade
     Q.geom = dict(Q.geom, kappa=P.geom["kappa"], gamma3=P.geom["gamma3"], gamma4=P.geom["gamma4"])
     e2 = oracle.rel_linf(oracle.evaluate(Q, kinds="VSD")["total"], a)
     print("with analytic curve derivatives: e_inf", e2)
     assert e2 <= 1e-11
+
+
+def _circle_xi_jets(R, tb):
+    """xi-derivatives 0..4 at b = R(cos tb, sin tb) of mu = cos 3t on the circle
+    of radius R: along the tangent line t = tb + asin(xi/R), and the series of
+    cos(3 tb + 3 asin(xi/R)) through xi^4 gives these."""
+    ca, sa = np.cos(3 * tb), np.sin(3 * tb)
+    return np.stack([ca, -3 * sa / R, -9 * ca / R ** 2, 24 * sa / R ** 3, 45 * ca / R ** 4])
+
+
+@pytest.mark.parametrize("R,shift,n_pan", [(3.0, 0.0, 4400), (3.0, 50.0, 4400), (1.3, 0.0, 24)])
+def test_plain_interpolant_within_rounding_bound_on_circles(R, shift, n_pan):
+    """On circles the exact frame is kappa = 1/R, gamma3 = 0, gamma4 = 3/R^3.
+    At 4400 panels of 16 (70,400 nodes, panels 4.3e-3 long) the nodal
+    coordinates' rounding dominates the interpolant's higher derivatives
+    (gamma4 wrong by up to ~5e3 at the origin, ~8e4 shifted by 50); each error
+    stays within the rounding bound (q ulps of the panel's largest coordinate
+    per Legendre coefficient) and reaches about a third of it."""
+    q = 16
+    xg, _ = leggauss(q)
+    e = np.linspace(0, 2 * np.pi, n_pan + 1)
+    t = (0.5 * (e[:-1, None] + e[1:, None]) + 0.5 * (e[1:, None] - e[:-1, None]) * xg[None]).ravel()
+    bx, by = shift + R * np.cos(t), R * np.sin(t)
+    k = np.random.default_rng(0).choice(bx.size, 150, replace=False)
+    tx, ty = bx[k] - 0.01 * np.cos(t[k]), by[k] - 0.01 * np.sin(t[k])
+    fr = G.boundary_frame(bx, by, q, tx, ty)
+    B = frame_bounds(bx, by, q, fr["pan"], fr["u"], q)
+    err = np.abs(np.stack([fr["kappa"] - 1 / R, fr["gamma3"], fr["gamma4"] - 3 / R ** 3]))
+    print("R", R, "shift", shift, "panels", n_pan, "max error / bound", np.max(err / B, axis=1),
+          "max error", np.max(err, axis=1))
+    assert np.all(err <= B)
+    mu = np.cos(3 * t)
+    mj = G.density_jets(bx, by, q, mu, fr["pan"], fr["u"], 4)
+    Bj = jet_bounds(bx, by, q, mu, fr["pan"], fr["u"], q)
+    ex = _circle_xi_jets(R, np.arctan2(ty, tx - shift))
+    # derivatives 1..4 at the found closest point (the value itself also moves with b's position)
+    assert np.all(np.abs(mj[1:] - ex[1:]) <= Bj[1:])

@@ -119,3 +119,57 @@ def test_green_representation_on_disk():
     u = out["V"] + out["S"] - out["D"]
     exact = P.tgt_x ** 2 + P.tgt_y ** 2
     assert np.max(np.abs(u - exact)) < 1e-4
+
+
+def test_delta1_from_known_areas():
+    """delta_1 = 3 dx^2 with dx^2 the area per node (Sec. 6 set-up: delta = 3 dx^2,
+    dx the average grid spacing), fixed here by areas known exactly rather than
+    by the weights: a 2 x 2 square cut into 2 m^2 right triangles carries
+    N = 12 m^2 nodes, so delta_1 = 3 * 4 / N = 1 / m^2; the unit disk's P2 mesh
+    (curved boundary edges) has area pi up to its geometric error; a boundary
+    alone (no volume nodes) uses dx = mean weight, 2 pi R / n on a circle of
+    radius R with n Gauss-Legendre nodes."""
+    import copy
+    from workloads.mesh import quadrature_nodes
+    m = 37
+    g = np.linspace(0.0, 2.0, m + 1)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], 1)
+    idx = np.arange((m + 1) ** 2).reshape(m + 1, m + 1)
+    a, b, c, d = idx[:-1, :-1].ravel(), idx[1:, :-1].ravel(), idx[1:, 1:].ravel(), idx[:-1, 1:].ravel()
+    tri = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)])
+    x, y, w = quadrature_nodes(pts, tri)
+    assert x.size == 12 * m * m
+    P = copy.copy(disk_problem(2000, seed=1))
+    P.src_x, P.src_y, P.src_w = x, y, w
+    assert abs(oracle.delta1_of(P) * m * m - 1.0) <= 1e-13
+    D = disk_problem(2000, seed=1)
+    assert abs(oracle.delta1_of(D) * D.n_src / (3 * np.pi) - 1.0) <= 1e-6
+    from numpy.polynomial.legendre import leggauss
+    q, n_pan, R = 16, 40, 1.7
+    xg, wg = leggauss(q)
+    e = np.linspace(0, 2 * np.pi, n_pan + 1)
+    wb = (0.5 * (e[1:, None] - e[:-1, None]) * wg[None] * R).ravel()
+    B = copy.copy(D)
+    B.src_x = B.src_y = B.src_w = np.zeros(0)
+    B.bnd_w = wb
+    assert abs(oracle.delta1_of(B) / (3 * (2 * np.pi * R / (q * n_pan)) ** 2) - 1.0) <= 1e-13
+
+
+def test_volume_potential_outside_the_disk():
+    """Outside the unit disk a radial source acts as a point mass (Newton's
+    theorem): V = -(integral of f) log r / (2 pi).  With f = 1 (integral pi,
+    f's jets 1 and zeros) V = -log(r) / 2 for r > 1.  The targets lie beyond
+    12 sqrt(delta_1) of the circle, where the local part of V vanishes: adding
+    the interior limit delta f there would be an error of delta_1 = 7.9e-4."""
+    from workloads.problems import disk_at_targets
+    P = disk_problem(2000, seed=7, gauss=((1.0, 0.0, 0.0, 1e6),))  # f == 1 to 1e-12
+    rng = np.random.default_rng(11)
+    th, rr = rng.uniform(0, 2 * np.pi, 300), rng.uniform(1.4, 3.0, 300)
+    Q = disk_at_targets(P, rr * np.cos(th), rr * np.sin(th))
+    assert np.all(Q.geom["r"] > 12 * np.sqrt(oracle.delta1_of(Q)))
+    out = oracle.evaluate(Q, kinds="V")
+    e = np.max(np.abs(out["V"] + np.log(rr) / 2))
+    print("outside the disk: max |V + log(r)/2|", e)
+    assert e <= 1e-7
+    assert np.max(np.abs(out["V_loc"])) == 0.0

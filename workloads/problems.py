@@ -289,6 +289,19 @@ def disk_problem(n_tri, seed=1, gauss=((1.0, 0.0, 0.0, np.sqrt(0.1)),), name="di
                    None, None, None, None, info)
 
 
+def disk_at_targets(P, tx, ty):
+    """The disk problem P with its targets replaced by (tx, ty), inside or outside
+    the unit circle: exact frames of the circle and f's analytic jets there."""
+    tx, ty = np.asarray(tx, float), np.asarray(ty, float)
+    rr = np.hypot(tx, ty)
+    geom = dict(r=np.abs(1.0 - rr), nx=tx / rr, ny=ty / rr, kappa=np.ones_like(tx),
+                gamma3=np.zeros_like(tx), gamma4=np.full_like(tx, 3.0),
+                sgn=np.where(rr < 1.0, 1, np.where(rr > 1.0, -1, 0)).astype(np.int8))
+    return Problem(P.name + "[targets]", P.src_x, P.src_y, P.src_w, P.bnd_x, P.bnd_y, P.bnd_nx, P.bnd_ny,
+                   P.bnd_w, tx.copy(), ty.copy(), geom, P.f_src, gauss_jets(tx, ty, P.info["gauss"]),
+                   None, None, None, None, dict(P.info))
+
+
 def square_problem(n_tri=180_000, n_split=20_000, seed=2, n_panels=250, q=20, name="square"):
     """[-1,1]^2 with slivers/degenerate triangles/gaps; f = 5 Gaussians; mu = cos(3 theta)."""
     rng = np.random.default_rng(seed)
