@@ -5,8 +5,13 @@ Workload (timed step = one vp_eval of V[f] + D[mu], all stages of the path):
   triangles and 0.2% gaps (~1.2M volume nodes = targets), f = 5 Gaussians,
   D[mu] from 20k Gauss-Legendre boundary nodes with mu = cos(3 theta),
   float64 at tolerance 1e-10.
-A second leg runs the float32 path (tolerance 1e-6) on the unit disk with
-~2M triangles (~12M nodes, V[f]).
+Both precisions run on both large workloads: float32 at 1e-6 on the same
+square workload (its error against the float64 result at every target and
+against the oracle sample), and the unit disk with ~2M triangles (~12M nodes,
+V[f]) in float64 at 1e-10 and float32 at 1e-6 (errors against the float64
+result at every target and against 10^4 stored oracle values, half of them
+near the circle).  The roofline fractions use the step table's algorithmic
+bytes (coordinates, strengths and grids; record layouts not counted).
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region;
 the timed region is bracketed by torch.cuda.synchronize().  In the timed
@@ -82,6 +87,44 @@ def algorithmic_bytes(info, P, kinds, b):
     return out
 
 
+def survey_bytes(info, P, kinds, b):
+    """Algorithmic bytes of each hot-path step in the measurement model of the
+    method's step table (one read of each input, one write of each output),
+    for the one grid channel this design spreads: a volume node brings its two
+    coordinates and one strength, a double-layer boundary node its coordinates
+    and three strengths (sigma w, and mu nu w for the kernel derivative), a
+    single-layer-only node one strength.
+      spread     (coordinates + strengths) of every node + F^2 b (the grid, written once)
+      FFT chain  R2C 2 F^2 b + multiply 2 F^2 b (grid and table) + C2R 2 F^2 b = 6 F^2 b
+                 (the row pass, the column pass with the multiply, the inverse row pass)
+      interp     F^2 b + 3 b per target (two coordinates in, the value out)
+    Record layouts, indices and tile bookkeeping of the implementation are not counted."""
+    n_v = P.n_src if "V" in kinds else 0
+    n_b = P.n_bnd if ("S" in kinds or "D" in kinds) else 0
+    per_b = 2 * b + (3 * b if "D" in kinds else b)
+    out = {}
+    for l, tag in enumerate(("nh", "fh")):
+        F2b = info["fine"][l] ** 2 * b
+        out["spread_" + tag] = n_v * 3 * b + n_b * per_b + F2b
+        out["fft_chain_" + tag] = 6 * F2b
+        out["interp_" + tag] = F2b + P.n_tgt * 3 * b
+    return out
+
+
+def survey_roofline(st, sb):
+    """(key, ms, bytes, GB/s, fraction of HBM peak) per step of survey_bytes; FFT chains take the
+    sum of their three launches' times."""
+    rows = {}
+    for tag in ("nh", "fh"):
+        t = {"spread_" + tag: st["spread_" + tag], "interp_" + tag: st["interp_" + tag],
+             "fft_chain_" + tag: st["row_fft_" + tag] + st["col_fft_mul_" + tag] + st["row_ifft_" + tag]}
+        for k, ms in t.items():
+            gbs = sb[k] / (ms * 1e-3) / 1e9
+            rows[k] = {"ms": round(ms, 4), "bytes": int(sb[k]), "gbs": round(gbs, 1),
+                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return rows
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("vp_device.hpp", "vp_kernels.hip", "vp_internal.hpp"):
@@ -128,12 +171,16 @@ def stage_times(torch, plan, fn, steps):
     return {k: v / steps for k, v in acc.items()}
 
 
-def run_leg(torch, P, kinds, tol, precision, steps, warmup, oracle_sample, seed, check_fp64=False):
+def run_leg(torch, P, kinds, tol, precision, steps, warmup, oracle_sample, seed, autotune=True, sample=None,
+            reference=None):
+    """Plan (autotuned), warm up, time `steps` evaluations, then a timing pass for the stage
+    times.  oracle_sample > 0: the oracle at that many seeded targets (its time is the CPU
+    baseline).  sample = (idx, values): e_inf on those targets; reference: e_inf on all."""
     from workloads.device import make_plan, run, to_device
     dev = to_device(P)
     mask = (1 if "V" in kinds else 0) | (2 if "S" in kinds else 0) | (4 if "D" in kinds else 0)
     t0 = time.perf_counter()
-    plan = make_plan(dev, tol=tol, precision=precision, kinds=mask, autotune=True)
+    plan = make_plan(dev, tol=tol, precision=precision, kinds=mask, autotune=autotune)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = plan.info()
@@ -144,10 +191,12 @@ def run_leg(torch, P, kinds, tol, precision, steps, warmup, oracle_sample, seed,
     el = time_steps(torch, fn, steps)
     st = stage_times(torch, plan, fn, steps)
     res = dict(info=info, plan_s=plan_s, elapsed=el, stages=st)
-    # parity on a seeded target sample against the float64 oracle (also the CPU baseline)
     fn()
     torch.cuda.synchronize()
     got = out.cpu().numpy()
+    res["got"] = got
+    plan.close()
+    del dev, out
     if oracle_sample:
         import oracle
         from oracle import direct
@@ -159,22 +208,13 @@ def run_leg(torch, P, kinds, tol, precision, steps, warmup, oracle_sample, seed,
         res["oracle_s"] = time.perf_counter() - t1
         res["oracle_n"] = len(idx)
         res["oracle_threads"] = direct.num_threads()
+        res["oracle_sample"] = (idx, ref)
+        sample = (idx, ref)
+    if sample is not None:
+        idx, ref = sample
         res["e_inf_sample"] = float(np.max(np.abs(got[idx] - ref)) / np.max(np.abs(ref)))
-    plan.close()
-    if check_fp64:
-        # every target against the float64 path (checked against the oracle in the main leg) at the
-        # tightest tolerance whose fine grid the planner supports for these nodes
-        from paper_2409_11998_amd.binding import VPError
-        for t64 in (1e-10, 1e-9, 1e-8, 1e-7):
-            try:
-                p64 = make_plan(dev, tol=t64, precision=1, kinds=mask)
-            except VPError:
-                continue
-            ref = run(p64, dev, kinds).cpu().numpy()
-            p64.close()
-            res["e_inf_vs_fp64"] = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-            res["fp64_tol"] = t64
-            break
+    if reference is not None:
+        res["e_inf_all"] = float(np.max(np.abs(got - reference)) / np.max(np.abs(reference)))
     return res
 
 
@@ -252,19 +292,20 @@ def main():
     ms = 1000.0 * r64["elapsed"] / args.steps
     alg = algorithmic_bytes(r64["info"], P, "VD", 8)
     st = r64["stages"]
-    dom = max(LAUNCHES, key=lambda k: st[k])
-    achieved = alg[dom] / (st[dom] * 1e-3) / 1e9
+    sroof = survey_roofline(st, survey_bytes(r64["info"], P, "VD", 8))
+    dom = max(("spread_nh", "spread_fh", "interp_nh", "interp_fh"), key=lambda k: st[k])
     workload = "square-200k-slivers-gaps V+D fp64 tol1e-10"
-    lvl = {"nh": 0, "fh": 1}.get(dom.rsplit("_", 1)[-1])
-    kname = KERNELS[dom.rsplit("_", 1)[0] if lvl is not None else dom]
-    if lvl is not None:
-        kname += " (%s level, w=%d, F=%d)" % (("near-history", "far-history")[lvl], r64["info"]["width"][lvl],
-                                             r64["info"]["fine"][lvl])
-    roof = {"bound": "hbm", "kernel": kname, "launch": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+    lvl = {"nh": 0, "fh": 1}[dom.rsplit("_", 1)[-1]]
+    kname = KERNELS[dom.rsplit("_", 1)[0]] + " (%s level, w=%d, F=%d)" % (
+        ("near-history", "far-history")[lvl], r64["info"]["width"][lvl], r64["info"]["fine"][lvl])
+    roof = {"bound": "hbm", "kernel": kname, "launch": dom, "achieved": sroof[dom]["gbs"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": sroof[dom]["frac"],
             "traffic": traffic_from_profiles(dom, workload),
-            "algorithmic_bytes_per_launch": int(alg[dom]), "avg_ms": round(st[dom], 4),
-            "avg_ms_from": "HIP events, timing pass (each launch alone on the plan's stream)"}
+            "algorithmic_bytes_per_launch": sroof[dom]["bytes"],
+            "record_bytes_per_launch": int(alg[dom]),
+            "avg_ms": round(st[dom], 4),
+            "avg_ms_from": "HIP events, timing pass (each launch alone on the plan's stream)",
+            "steps_frac_of_hbm": {k: v["frac"] for k, v in sroof.items()}}
     stages_gbs = {k: round(alg[k] / (st[k] * 1e-3) / 1e9, 1) for k in LAUNCHES if st.get(k, 0) > 0}
     cpu = None
     if args.oracle_sample:
@@ -281,8 +322,16 @@ def main():
                       "spread_mma": list(r64["info"]["spread_mma"]),
                       "autotuned": r64["info"]["autotuned"], "tol": 1e-10},
            "roofline": roof, "cpu_baseline": cpu,
-           "stages_ms": {k: round(v, 4) for k, v in st.items()}, "stages_gbs": stages_gbs,
+           "stages_ms": {k: round(v, 4) for k, v in st.items()}, "stages_gbs_record_bytes": stages_gbs,
            "plan_s": round(r64["plan_s"], 3), "e_inf_vs_oracle_sample": r64.get("e_inf_sample")}
+    if not args.no_fp32_leg:
+        log("bench: fp32 V+D leg on the same workload")
+        r = run_leg(torch, P, "VD", 1e-6, 0, args.steps, args.warmup, 0, seed=21,
+                    sample=r64.get("oracle_sample"), reference=r64["got"])
+        rec["fp32_same_workload"] = leg_summary(r, P, "VD", 4, args.steps, "square-200k-slivers-gaps V+D fp32 tol1e-6")
+        rec["fp32_same_workload"]["e_inf_vs_fp64_all_targets"] = r.get("e_inf_all")
+        rec["fp32_same_workload"]["e_inf_vs_oracle_sample"] = r.get("e_inf_sample")
+    r64.pop("got")
     if not args.no_refine_leg:
         log("bench: dyadic refinement leg, %d levels" % args.refine_levels)
         rec["refine"] = refine_leg(torch, P, args.refine_levels, args.steps)
@@ -296,23 +345,22 @@ def main():
     if not args.no_fp32_leg:
         log("bench: generating disk-2M workload")
         Q = config_problem(3, scale=args.scale)
+        sample = disk2m_oracle_sample(Q)
+        log("bench: fp64 V leg on disk-2M, n_tgt=%d" % Q.n_tgt)
+        q64 = run_leg(torch, Q, "V", 1e-10, 1, args.steps, args.warmup, 0, seed=31, sample=sample)
+        rec["fp64_disk2m"] = leg_summary(q64, Q, "V", 8, args.steps, "disk-2M V fp64 tol1e-10")
+        rec["fp64_disk2m"]["e_inf_vs_oracle_sample"] = q64.get("e_inf_sample")
         log("bench: fp32 V leg, n_tgt=%d" % Q.n_tgt)
-        r32 = run_leg(torch, Q, "V", 1e-6, 0, args.steps, args.warmup, 0, seed=30, check_fp64=True)
-        alg32 = algorithmic_bytes(r32["info"], Q, "V", 4)
-        st32 = r32["stages"]
-        dom32 = max(LAUNCHES, key=lambda k: st32[k])
-        rec["fp32"] = {"workload": "disk-2M V fp32 tol1e-6", "n_tgt": Q.n_tgt,
-                       "value": round(Q.n_tgt * args.steps / r32["elapsed"], 1), "unit": "target pts/s",
-                       "ms_per_step": round(1000.0 * r32["elapsed"] / args.steps, 4),
-                       "fine_grid": list(r32["info"]["fine"]), "spread_width": list(r32["info"]["width"]),
-                       "tile": list(r32["info"]["tile"]), "interp_tile": list(r32["info"]["interp_tile"]),
-                       "spread_mma": list(r32["info"]["spread_mma"]),
-                       "stages_ms": {k: round(v, 4) for k, v in st32.items()},
-                       "stages_gbs": {k: round(alg32[k] / (st32[k] * 1e-3) / 1e9, 1) for k in LAUNCHES
-                                      if st32.get(k, 0) > 0},
-                       "dominant_launch": dom32,
-                       "dominant_frac_of_hbm_peak": round(alg32[dom32] / (st32[dom32] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                       "e_inf_vs_fp64_all_targets": r32.get("e_inf_vs_fp64"), "fp64_reference_tol": r32.get("fp64_tol"), "plan_s": round(r32["plan_s"], 3)}
+        r32 = run_leg(torch, Q, "V", 1e-6, 0, args.steps, args.warmup, 0, seed=30, sample=sample,
+                      reference=q64["got"])
+        q64.pop("got")
+        rec["fp32"] = leg_summary(r32, Q, "V", 4, args.steps, "disk-2M V fp32 tol1e-6")
+        rec["fp32"]["e_inf_vs_fp64_all_targets"] = r32.get("e_inf_all")
+        rec["fp32"]["fp64_reference_tol"] = 1e-10
+        rec["fp32"]["e_inf_vs_oracle_sample"] = r32.get("e_inf_sample")
+        rec["fp32"]["oracle_sample"] = None if sample is None else "%d stored oracle values (%d within 12 sqrt(delta_1) of the circle)" % (
+            sample[0].size, int(np.count_nonzero(Q.geom["r"][sample[0]] <= 12 * np.sqrt(r32["info"]["delta1"]))))
+        r32.pop("got")
     if batch_probs:
         log("bench: batch leg, %d instances, %d targets" % (len(batch_probs), sum(P.n_tgt for P in batch_probs)))
         rec["batch"] = batch_leg(torch, batch_probs, args.steps, args.warmup, args.batch_tune_sample)
@@ -325,6 +373,32 @@ def main():
         rec["latency_p99_s"] = rec["serve"]["loads"][ref_load]["served"]["p99_s"]
         rec["latency_load"] = float(ref_load)
     print(json.dumps(rec), flush=True)
+
+
+def leg_summary(r, P, kinds, b, steps, workload):
+    st = r["stages"]
+    sroof = survey_roofline(st, survey_bytes(r["info"], P, kinds, b))
+    dom = max(sroof, key=lambda k: sroof[k]["ms"])
+    return {"workload": workload, "n_tgt": P.n_tgt, "value": round(P.n_tgt * steps / r["elapsed"], 1),
+            "unit": "target pts/s", "ms_per_step": round(1000.0 * r["elapsed"] / steps, 4),
+            "fine_grid": list(r["info"]["fine"]), "spread_width": list(r["info"]["width"]),
+            "tile": list(r["info"]["tile"]), "interp_tile": list(r["info"]["interp_tile"]),
+            "spread_mma": list(r["info"]["spread_mma"]), "stages_ms": {k: round(v, 4) for k, v in st.items()},
+            "steps_frac_of_hbm": {k: v["frac"] for k, v in sroof.items()}, "dominant_step": dom,
+            "dominant_frac_of_hbm_peak": sroof[dom]["frac"], "plan_s": round(r["plan_s"], 3)}
+
+
+def disk2m_oracle_sample(Q):
+    """(idx, V) of the oracle at 10^4 stratified disk-2M targets, stored by
+    tests/golden/make_disk2m_oracle_sample.py, if they are this workload's targets."""
+    path = os.path.join(ROOT, "tests", "golden", "disk2m_v_oracle_sample.npz")
+    if not os.path.exists(path):
+        return None
+    d = np.load(path)
+    idx = d["idx"]
+    if Q.n_tgt != int(d["n_tgt"]) or not (np.array_equal(Q.tgt_x[idx], d["x"]) and np.array_equal(Q.tgt_y[idx], d["y"])):
+        return None
+    return idx, d["v"]
 
 
 def geometry_leg(torch, P, steps):

@@ -79,7 +79,13 @@ __global__ __launch_bounds__(kThreads) void kg_zero(const InstDesc* __restrict__
         const LevelDesc& D = lv[2 * i + l];
         const int64_t n = (int64_t)D.g.F * D.g.F;
         const int64_t i0 = (int64_t)u * kZeroChunk;
-        for (int64_t k = i0 + threadIdx.x; k < i0 + kZeroChunk; k += blockDim.x) dev::dev_zero<R>((R*)D.grid, n, k);
+        for (int64_t k = i0 + threadIdx.x; k < i0 + kZeroChunk; k += blockDim.x) {
+            dev::dev_zero<R>((R*)D.grid, n, k);
+            if (D.dgrid[0]) {
+                dev::dev_zero<R>((R*)D.dgrid[0], n, k);
+                dev::dev_zero<R>((R*)D.dgrid[1], n, k);
+            }
+        }
         if (l == 0 && u == 0) {  // the instance's accumulators, once
             if (threadIdx.x < kDcParts) inst[i].dc[threadIdx.x] = 0.0;
             if (threadIdx.x < 2) inst[i].smax[threadIdx.x] = 0ull;
@@ -112,13 +118,20 @@ __global__ __launch_bounds__(kThreads) void kg_spread(const InstDesc* __restrict
         if (!decode(t, it, i, l, u)) continue;
         const InstDesc& I = inst[i];
         const CallDesc& K = call[i];
-        const LevelDesc& D = lv[2 * i + l];
+        const int ch = l >> 1;
+        const LevelDesc& D = lv[2 * i + (l & 1)];
         const LevelGeom g = D.g;
-        const int use_vol = K.f != nullptr && I.has_vol;
-        const int use_bnd = (K.sigma != nullptr || K.mu != nullptr) && I.has_bnd;
-        const int use_d = K.mu != nullptr;
-        dev::dev_spread<R, W>(smem_raw, g, vol_view<R>(D), bnd_view<R>(D), (const R*)I.str, I.n_src, I.n_bnd,
-                              (R*)D.grid, use_vol, use_bnd, use_d, D.horner, I.smax, D.sp_units[u]);
+        if (ch == 0) {
+            const int use_vol = K.f != nullptr && I.has_vol;
+            const int use_bnd = (K.sigma != nullptr || K.mu != nullptr) && I.has_bnd;
+            const int use_d = K.mu != nullptr && !D.dgrid[0];
+            dev::dev_spread<R, W>(smem_raw, g, vol_view<R>(D), bnd_view<R>(D), (const R*)I.str, I.n_src, I.n_bnd,
+                                  (R*)D.grid, use_vol, use_bnd, use_d, D.horner, I.smax, D.sp_units[u]);
+        } else {  // double-layer channel ch: mu nu_ch w with the kernel itself
+            const R* s = (const R*)I.str + (I.n_src + I.n_bnd) + (ch - 1) * I.n_bnd - I.n_src;
+            dev::dev_spread<R, W>(smem_raw, g, vol_view<R>(D), bnd_view<R>(D), s, I.n_src, I.n_bnd,
+                                  (R*)D.dgrid[ch - 1], 0, 1, 0, D.horner, I.smax + 1, D.sp_units[u]);
+        }
         __syncthreads();
     }
 }
@@ -135,15 +148,22 @@ __global__ __launch_bounds__(kThreads) void kg_spread_mma(const InstDesc* __rest
         if (!decode(t, it, i, l, u)) continue;
         const InstDesc& I = inst[i];
         const CallDesc& K = call[i];
-        const LevelDesc& D = lv[2 * i + l];
+        const int ch = l >> 1;
+        const LevelDesc& D = lv[2 * i + (l & 1)];
         const int unit = u * (kThreads / 64) + (threadIdx.x >> 6);
         if (unit < D.n_sp_units) {
-            const int use_vol = K.f != nullptr && I.has_vol;
-            const int use_bnd = (K.sigma != nullptr || K.mu != nullptr) && I.has_bnd;
-            const int use_d = K.mu != nullptr;
-            dev::dev_spread_mma<W>(smem_raw, D.g, vol_view<float>(D), bnd_view<float>(D), (const float*)I.str,
-                                   I.n_src, I.n_bnd, (float*)D.grid, use_vol, use_bnd, use_d, D.horner,
-                                   D.sp_units[unit]);
+            if (ch == 0) {
+                const int use_vol = K.f != nullptr && I.has_vol;
+                const int use_bnd = (K.sigma != nullptr || K.mu != nullptr) && I.has_bnd;
+                const int use_d = K.mu != nullptr && !D.dgrid[0];
+                dev::dev_spread_mma<W>(smem_raw, D.g, vol_view<float>(D), bnd_view<float>(D), (const float*)I.str,
+                                       I.n_src, I.n_bnd, (float*)D.grid, use_vol, use_bnd, use_d, D.horner,
+                                       D.sp_units[unit]);
+            } else {  // double-layer channel ch: mu nu_ch w with the kernel itself
+                const float* s = (const float*)I.str + (I.n_src + I.n_bnd) + (ch - 1) * I.n_bnd - I.n_src;
+                dev::dev_spread_mma<W>(smem_raw, D.g, vol_view<float>(D), bnd_view<float>(D), s, I.n_src, I.n_bnd,
+                                       (float*)D.dgrid[ch - 1], 0, 1, 0, D.horner, D.sp_units[unit]);
+            }
         }
         __syncthreads();  // LDS reuse by the next item
     }
@@ -156,15 +176,35 @@ __global__ __launch_bounds__(kThreads) void kg_row_r2c(const LevelDesc* __restri
     for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
         int i, l, u;
         if (!decode(t, it, i, l, u)) continue;
-        const LevelDesc& D = lv[2 * i + l];
+        const int ch = l >> 1;
+        const LevelDesc& D = lv[2 * i + (l & 1)];
         const LevelGeom g = D.g;
-        dev::dev_row_r2c<R>(smem_raw, g, (const R*)D.grid, (const cplx<R>*)D.tw, (cplx<R>*)D.spec, u);
+        const R* grid = (const R*)(ch ? D.dgrid[ch - 1] : D.grid);
+        cplx<R>* spec = (cplx<R>*)(ch ? D.dspec[ch - 1] : D.spec);
+        dev::dev_row_r2c<R>(smem_raw, g, grid, (const cplx<R>*)D.tw, spec, u);
+        __syncthreads();
+    }
+}
+
+// Forward column transforms of the double-layer channels (items of channel c >= 1).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void kg_col_fwd(const LevelDesc* __restrict__ lv, StageTab t)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
+        int i, l, u;
+        if (!decode(t, it, i, l, u)) continue;
+        const int ch = l >> 1;
+        const LevelDesc& D = lv[2 * i + (l & 1)];
+        const LevelGeom g = D.g;
+        if (ch) dev::dev_col_fwd<R>(smem_raw, g, (cplx<R>*)D.dspec[ch - 1], (const cplx<R>*)D.tw, u);
         __syncthreads();
     }
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void kg_col(const LevelDesc* __restrict__ lv, StageTab t, int zero_dc)
+__global__ __launch_bounds__(kThreads) void kg_col(const LevelDesc* __restrict__ lv, const CallDesc* __restrict__ call,
+                                                   StageTab t, int zero_dc)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
@@ -172,7 +212,9 @@ __global__ __launch_bounds__(kThreads) void kg_col(const LevelDesc* __restrict__
         if (!decode(t, it, i, l, u)) continue;
         const LevelDesc& D = lv[2 * i + l];
         const LevelGeom g = D.g;
-        dev::dev_col<R>(smem_raw, g, (cplx<R>*)D.spec, (const R*)D.mult, (const cplx<R>*)D.tw, zero_dc, u);
+        const bool dip = D.dgrid[0] && call[i].mu;  // the channels were spread and transformed
+        dev::dev_col<R>(smem_raw, g, (cplx<R>*)D.spec, (const R*)D.mult, (const cplx<R>*)D.tw, zero_dc, u,
+                        dip ? (const cplx<R>*)D.dspec[0] : nullptr, dip ? (const cplx<R>*)D.dspec[1] : nullptr);
         __syncthreads();
     }
 }
@@ -283,6 +325,11 @@ void fill_instance(const Plan& p, const Workspace& ws, InstDesc& I, LevelDesc* D
         d.tgt_idx = lb.tgt.idx;
         d.grid = ws.grid[l];
         d.spec = ws.spec[l];
+        if (p.lv[l].dip && ws.dgrid[0])
+            for (int c = 0; c < 2; ++c) {
+                d.dgrid[c] = ws.dgrid[c];
+                d.dspec[c] = ws.dspec[c];
+            }
         d.mult = lb.mult;
         d.tw = lb.tw;
         d.hist = ws.hist[l];
@@ -359,8 +406,16 @@ vp_status group_build(const std::vector<const Plan*>& plans, const std::vector<W
             };
             HostStage& sp = stage_for(sp_of_w, G.spread, g.mma);
             const int nsu = (int)lb.h_sp_units.size();
-            sp.add(i, l, g.mma ? (nsu + kThreads / 64 - 1) / (kThreads / 64) : nsu);
+            const int sp_items = g.mma ? (nsu + kThreads / 64 - 1) / (kThreads / 64) : nsu;
+            sp.add(i, l, sp_items);
             sp.lds = std::max(sp.lds, spread_lds_bytes(p, l));
+            if (G.lv[2 * i + l].dgrid[0] && args[i].mu && p.n_bnd > 0)  // the double-layer channels
+                for (int c = 1; c <= 2; ++c) {
+                    sp.add(i, l + 2 * c, sp_items);
+                    G.row.add(i, l + 2 * c, g.F);
+                    G.colf.add(i, l + 2 * c, g.M + 1);
+                    G.colf.lds = std::max(G.colf.lds, col_fft_lds_bytes(p, l));
+                }
             HostStage& in = stage_for(in_of_w, G.interp, 0);
             in.add(i, l, (int)lb.h_in_units.size());
             in.lds = std::max(in.lds, interp_lds_bytes_of(p, l));
@@ -371,8 +426,8 @@ vp_status group_build(const std::vector<const Plan*>& plans, const std::vector<W
     G.off_lv = a16(G.off_inst + n * sizeof(InstDesc));
     G.off_call = a16(G.off_lv + 2 * n * sizeof(LevelDesc));
     G.off_seg = a16(G.off_call + n * sizeof(CallDesc));
-    size_t nseg = G.zero.seg.size() + G.str.seg.size() + G.row.seg.size() + G.col.seg.size() + G.c2r.seg.size() +
-                  G.local.seg.size();
+    size_t nseg = G.zero.seg.size() + G.str.seg.size() + G.row.seg.size() + G.colf.seg.size() + G.col.seg.size() +
+                  G.c2r.seg.size() + G.local.seg.size();
     for (auto& st : G.spread) nseg += st.seg.size();
     for (auto& st : G.interp) nseg += st.seg.size();
     G.bytes = a16(G.off_seg + nseg * sizeof(Seg));
@@ -402,6 +457,7 @@ GroupTabs group_tabs(GroupPlan& G, unsigned char* dev_base)
     T.zero = place(G.zero);
     T.str = place(G.str);
     T.row = place(G.row);
+    T.colf = place(G.colf);
     T.col = place(G.col);
     T.c2r = place(G.c2r);
     T.local = place(G.local);
@@ -458,9 +514,12 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
         hipLaunchKernelGGL(kg_row_r2c<R>, dim3(persistent_grid(T.row.nitems, cus, 8)), dim3(kThreads), G.row.lds, st,
                            T.lv, T.row);
     const int zero_dc = G.precision == VP_FP32 ? 1 : 0;
+    if (T.colf.nitems)
+        hipLaunchKernelGGL((kg_col_fwd<R>), dim3(persistent_grid(T.colf.nitems, cus, 4)), dim3(kThreads), G.colf.lds,
+                           st, T.lv, T.colf);
     if (T.col.nitems)
         hipLaunchKernelGGL((kg_col<R>), dim3(persistent_grid(T.col.nitems, cus, 4)), dim3(kThreads), G.col.lds, st,
-                           T.lv, T.col, zero_dc);
+                           T.lv, T.call, T.col, zero_dc);
     if (T.c2r.nitems)
         hipLaunchKernelGGL(kg_row_c2r<R>, dim3(persistent_grid(T.c2r.nitems, cus, 8)), dim3(kThreads), G.c2r.lds, st,
                            T.lv, T.c2r);
@@ -508,9 +567,10 @@ int device_cus()
 
 size_t group_bytes_bound(size_t n)
 {
-    // descriptors, call table, and at most 10 + 4 segments per instance
+    // descriptors, call table, and at most 14 segments per instance plus 6 for the
+    // double-layer channels of a level with dip
     return a16(n * sizeof(InstDesc)) + a16(2 * n * sizeof(LevelDesc)) + a16(n * sizeof(CallDesc)) +
-           a16(n * 16 * sizeof(Seg)) + 256;
+           a16(n * 24 * sizeof(Seg)) + 256;
 }
 
 vp_status group_enqueue(const std::vector<const Plan*>& plans, const std::vector<Workspace>& ws,

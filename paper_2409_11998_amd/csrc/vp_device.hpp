@@ -881,9 +881,14 @@ __host__ __device__ inline size_t col_lds_bytes(int F)
     return (size_t)(lds_padded_len(F) + (col_stages_twiddles<R>(F) ? F / 2 : 0)) * sizeof(cplx<R>);
 }
 
+// dspec: with g.dip, the level's two double-layer channels (mu nu_c w spread with
+// the kernel itself), already transformed along y by dev_col_fwd; each column
+// adds -i k_1 B_1 - i k_2 B_2 to the forward transform before the multiply,
+// the transform of the double layer's kernel derivative (Sec. 3, Step 2).
 template <typename R>
 __device__ void dev_col(unsigned char* smem_raw, const LevelGeom& g, cplx<R>* __restrict__ spec,
-                        const R* __restrict__ mult, const cplx<R>* __restrict__ tw, int zero_dc, int unit)
+                        const R* __restrict__ mult, const cplx<R>* __restrict__ tw, int zero_dc, int unit,
+                        const cplx<R>* __restrict__ dspec1 = nullptr, const cplx<R>* __restrict__ dspec2 = nullptr)
 {
     cplx<R>* z = reinterpret_cast<cplx<R>*>(smem_raw);
     const int F = g.F;
@@ -907,6 +912,19 @@ __device__ void dev_col(unsigned char* smem_raw, const LevelGeom& g, cplx<R>* __
     }
     auto run = [&](const cplx<R>* twp) {
         lds_fft(z, logF, twp, 1, false);
+        if (dspec1) {  // + (-i k_1) B_1 + (-i k_2) B_2 at the retained modes (the table is zero elsewhere)
+            const cplx<R>* b1 = dspec1 + (size_t)m1 * F;
+            const cplx<R>* b2 = dspec2 + (size_t)m1 * F;
+            const R k1 = (R)(m1 * g.dk);
+            for (int q = threadIdx.x; q < F; q += blockDim.x) {
+                const int m2 = q < (F >> 1) ? q : q - F;
+                if (m2 > M || m2 < -M) continue;
+                const R k2 = (R)(m2 * g.dk);
+                const cplx<R> a = b1[q], b = b2[q];
+                z[lds_pad(q)].x += k1 * a.y + k2 * b.y;
+                z[lds_pad(q)].y -= k1 * a.x + k2 * b.x;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < kColPre; ++k) {
             const int q = threadIdx.x + k * (int)blockDim.x;
@@ -933,6 +951,22 @@ __device__ void dev_col(unsigned char* smem_raw, const LevelGeom& g, cplx<R>* __
         run(tw);
     }
     for (int q = threadIdx.x; q < F; q += blockDim.x) col[q] = z[lds_pad(bitrev(q, logF))];
+}
+
+// Forward transform along y of column m1 = unit, in place, natural order out
+// (the double-layer channels of a level with dip, before its column pass).
+template <typename R>
+__device__ void dev_col_fwd(unsigned char* smem_raw, const LevelGeom& g, cplx<R>* __restrict__ spec,
+                            const cplx<R>* __restrict__ tw, int unit)
+{
+    cplx<R>* z = reinterpret_cast<cplx<R>*>(smem_raw);
+    const int F = g.F;
+    const int logF = g.logF;
+    cplx<R>* col = spec + (size_t)unit * F;
+    for (int q = threadIdx.x; q < F; q += blockDim.x) z[lds_pad(bitrev(q, logF))] = col[q];
+    __syncthreads();
+    lds_fft(z, logF, tw, 1, false);
+    for (int q = threadIdx.x; q < F; q += blockDim.x) col[q] = z[lds_pad(q)];
 }
 
 // ---------------------------------------------------------------------------

@@ -18,6 +18,8 @@ struct LevelDesc {
     const int* tgt_start; const int* tgt_ij; const void* tgt_dx; const void* tgt_dy; const int* tgt_idx;
     void* grid;
     void* spec;
+    void* dgrid[2];  // double-layer channel grids and spectra of a level with dip (else NULL)
+    void* dspec[2];
     const void* mult;
     const void* tw;
     void* hist;
@@ -52,7 +54,9 @@ struct CallDesc {
 };
 
 // A stage's work: segments of `count` units of (instance, level), items
-// [begin, begin + count rounded up to 8).
+// [begin, begin + count rounded up to 8).  In the spread, row-pass and
+// forward-column stages level = l + 2 c addresses channel c of level l
+// (c = 1, 2: the double-layer channels of a level with dip).
 struct Seg {
     int inst;
     int level;
@@ -82,7 +86,7 @@ struct GroupPlan {
     std::vector<InstDesc> inst;
     std::vector<LevelDesc> lv;
     std::vector<CallDesc> call;
-    HostStage zero, str, row, col, c2r, local;
+    HostStage zero, str, row, colf, col, c2r, local;
     std::vector<HostStage> spread, interp;  // one per distinct spreading width
     size_t off_inst = 0, off_lv = 0, off_call = 0, off_seg = 0, bytes = 0;
     std::vector<unsigned char> blob;
@@ -93,7 +97,7 @@ struct GroupTabs {
     const InstDesc* inst = nullptr;
     const LevelDesc* lv = nullptr;
     CallDesc* call = nullptr;
-    StageTab zero{}, str{}, row{}, col{}, c2r{}, local{};
+    StageTab zero{}, str{}, row{}, colf{}, col{}, c2r{}, local{};
     std::vector<StageTab> spread, interp;
 };
 

@@ -57,6 +57,10 @@ struct LevelGeom {
     double fit_err[2]; // sampled max |polynomial - kernel| of the spreading and interpolation tables
     int mma;        // spread on matrix cores (float32 plans on kMmaTile tiles), else LDS atomics
     int Ti, ntxi;   // interpolation tile edge and tiles per dimension (targets are binned on their own tiles)
+    // Double layer in channels of its own: mu nu_1 w and mu nu_2 w spread with the kernel itself into
+    // two more grids, whose spectra enter the column pass as -i k_1 B_1 - i k_2 B_2 (float32
+    // far-history levels; elsewhere the double layer goes through the kernel derivative).
+    int dip;
 };
 
 // A tile-sorted list of points of one level (CSR by tile): each point appears
@@ -119,6 +123,8 @@ struct LevelBufs {
 struct Workspace {
     void* grid[2] = {nullptr, nullptr};   // R [F][F] spread grids, reused for the inverse output
     void* spec[2] = {nullptr, nullptr};   // cplx<R> [M+1][F] half spectra (x-frequency major)
+    void* dgrid[2] = {nullptr, nullptr};  // R [F][F] double-layer channel grids of the level with dip
+    void* dspec[2] = {nullptr, nullptr};  // cplx<R> [M+1][F] their half spectra
     void* hist[2] = {nullptr, nullptr};   // R [n_tgt] history value at each target
     void* str = nullptr;                  // R [n_src + n_bnd (+ 2 n_bnd)] strengths (+ mu nu wG)
     double* dc = nullptr;                 // [kDcParts] float64 partial sums of the spread strengths
@@ -204,8 +210,11 @@ hipError_t launch_zero(const Plan& p, const Workspace& ws, hipStream_t st);
 hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool use_vol, bool use_bnd,
                          bool use_d);
 // FFT passes: level 0 or 1, or both levels in one launch (level < 0).
-hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
-hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
+// dip_used: the evaluation spread the double layer into the channel grids of a
+// level with dip (their row transforms join the row pass, their column
+// transforms precede the column pass, which combines them).
+hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool dip_used);
+hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool dip_used);
 hipError_t launch_row_ifft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
 hipError_t launch_interp(const Plan& p, const Workspace& ws, hipStream_t st, int level);
 hipError_t launch_local(const Plan& p, const Workspace& ws, hipStream_t st, const double* jet6, const double* sig_jet,

@@ -23,14 +23,20 @@ __global__ __launch_bounds__(kThreads) void k_strengths(int64_t n_src, int64_t n
     dev_strengths<R>(n_src, n_bnd, f, sigma, mu, w, nx, ny, str, dc, smax, blockIdx.x);
 }
 
-// Zero the spread grids of both levels and the zero-frequency / maximum accumulators.
+// Zero the spread grids of both levels (and the double-layer channel grids, if
+// any) and the zero-frequency / maximum accumulators.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_zero(R* __restrict__ a, int64_t na, R* __restrict__ b, int64_t nb,
+                                                   R* __restrict__ c, R* __restrict__ d, int64_t ncd,
                                                    double* __restrict__ dc, unsigned long long* __restrict__ smax)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     dev_zero<R>(a, na, i);
     dev_zero<R>(b, nb, i);
+    if (c) {
+        dev_zero<R>(c, ncd, i);
+        dev_zero<R>(d, ncd, i);
+    }
     if (i < kDcParts) dc[i] = 0.0;
     if (i < 2) smax[i] = 0ull;
 }
@@ -62,27 +68,35 @@ __global__ __launch_bounds__(kThreads) void k_spread_mma(LevelGeom g, RecView<fl
         dev_spread_mma<W>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d, coef, units[u]);
 }
 
-// The FFT passes of one or two levels in one launch: blocks [0, n[0]) work on
-// the first level given, blocks [n[0], n[0] + n[1]) on the second.
+// The FFT passes of one or two levels (and a level's double-layer channels) in
+// one launch: blocks [0, n[0]) work on the first entry, the next n[1] on the
+// second, and so on.
+constexpr int kPairMax = 4;
 template <typename R> struct LevelPair {
-    LevelGeom g[2];
-    R* grid[2];
-    cplx<R>* spec[2];
-    const cplx<R>* tw[2];
-    const R* mult[2];
-    int n[2];
+    LevelGeom g[kPairMax];
+    R* grid[kPairMax];
+    cplx<R>* spec[kPairMax];
+    const cplx<R>* tw[kPairMax];
+    const R* mult[kPairMax];
+    const cplx<R>* dsp[kPairMax][2];  // column pass: the entry's transformed double-layer channels (or NULL)
+    int n[kPairMax];
+    int cnt;
+    int total() const
+    {
+        int t = 0;
+        for (int k = 0; k < cnt; ++k) t += n[k];
+        return t;
+    }
 };
 
 template <typename R>
 __device__ __forceinline__ int pair_unit(const LevelPair<R>& P, int* lv)
 {
-    const int b = blockIdx.x;
-    if (b < P.n[0]) {
-        *lv = 0;
-        return xcd_unit(b, P.n[0]);
-    }
-    *lv = 1;
-    return xcd_unit(b - P.n[0], P.n[1]);
+    int b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < P.cnt && b >= P.n[k]) b -= P.n[k++];
+    *lv = k;
+    return xcd_unit(b, P.n[k]);
 }
 
 template <typename R>
@@ -105,7 +119,16 @@ __global__ __launch_bounds__(kColThreadsMax) void k_col(LevelPair<R> P, int zero
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int l;
     const int u = pair_unit(P, &l);
-    dev_col<R>(smem_raw, P.g[l], P.spec[l], P.mult[l], P.tw[l], zero_dc, u);
+    dev_col<R>(smem_raw, P.g[l], P.spec[l], P.mult[l], P.tw[l], zero_dc, u, P.dsp[l][0], P.dsp[l][1]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kColThreadsMax) void k_col_fwd(LevelPair<R> P)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int l;
+    const int u = pair_unit(P, &l);
+    dev_col_fwd<R>(smem_raw, P.g[l], P.spec[l], P.tw[l], u);
 }
 
 template <typename R>
@@ -169,18 +192,31 @@ hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, 
     return hipGetLastError();
 }
 
+// The level whose double layer has channels of its own (-1: none) and whose
+// channel buffers are present in ws.
+static int dip_level(const Plan& p, const Workspace& ws)
+{
+    for (int l = 0; l < 2; ++l)
+        if (p.lv[l].dip && ws.dgrid[0] && ws.grid[l]) return l;
+    return -1;
+}
+
 hipError_t launch_zero(const Plan& p, const Workspace& ws, hipStream_t st)
 {
     // a level without a grid in ws (the planner's level timing) is skipped
     const int64_t n0 = ws.grid[0] ? (int64_t)p.lv[0].F * p.lv[0].F : 0;
     const int64_t n1 = ws.grid[1] ? (int64_t)p.lv[1].F * p.lv[1].F : 0;
-    const unsigned blocks = grid_for(std::max<int64_t>({n0, n1, kDcParts}));
+    const int dl = dip_level(p, ws);
+    const int64_t nd = dl >= 0 ? (int64_t)p.lv[dl].F * p.lv[dl].F : 0;
+    const unsigned blocks = grid_for(std::max<int64_t>({n0, n1, nd, kDcParts}));
     if (p.precision == VP_FP32)
         hipLaunchKernelGGL(k_zero<float>, dim3(blocks), dim3(kThreads), 0, st, (float*)ws.grid[0], n0,
-                           (float*)ws.grid[1], n1, ws.dc, ws.smax);
+                           (float*)ws.grid[1], n1, (float*)(dl >= 0 ? ws.dgrid[0] : nullptr),
+                           (float*)(dl >= 0 ? ws.dgrid[1] : nullptr), nd, ws.dc, ws.smax);
     else
         hipLaunchKernelGGL(k_zero<double>, dim3(blocks), dim3(kThreads), 0, st, (double*)ws.grid[0], n0,
-                           (double*)ws.grid[1], n1, ws.dc, ws.smax);
+                           (double*)ws.grid[1], n1, (double*)(dl >= 0 ? ws.dgrid[0] : nullptr),
+                           (double*)(dl >= 0 ? ws.dgrid[1] : nullptr), nd, ws.dc, ws.smax);
     return hipGetLastError();
 }
 
@@ -199,9 +235,11 @@ size_t spread_lds_bytes(const Plan& p, int level)
 
 #define VP_W_CASES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
+// One spread launch of level l into grid from strengths str (indexed by node:
+// volume nodes, then boundary nodes); smax: the fixed-point windows' strength bound.
 template <typename R, int W>
-static void spread_launch(const Plan& p, const Workspace& ws, hipStream_t st, int l, size_t lds, int uv, int ub,
-                          int ud)
+static void spread_launch(const Plan& p, hipStream_t st, int l, size_t lds, const R* str,
+                          const unsigned long long* smax, R* grid, int uv, int ub, int ud)
 {
     const LevelGeom& g = p.lv[l];
     const LevelBufs& b = p.lb[l];
@@ -213,15 +251,34 @@ static void spread_launch(const Plan& p, const Workspace& ws, hipStream_t st, in
             (void)hipFuncSetAttribute((const void*)k_spread_mma<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds);
             hipLaunchKernelGGL((k_spread_mma<W>), dim3(nb), dim3(kThreads), lds, st, g, view<float>(b.vol),
-                               view<float>(b.bnd), (const float*)ws.str, p.n_src, p.n_bnd, (float*)ws.grid[l], uv,
-                               ub, ud, (const double*)b.horner, (const WorkUnit*)b.sp_units, (int)nu);
+                               view<float>(b.bnd), (const float*)str, p.n_src, p.n_bnd, (float*)grid, uv, ub, ud,
+                               (const double*)b.horner, (const WorkUnit*)b.sp_units, (int)nu);
             return;
         }
     }
     (void)hipFuncSetAttribute((const void*)k_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_spread<R, W>), dim3(nu), dim3(kThreads), lds, st, g, view<R>(b.vol), view<R>(b.bnd),
-                       (const R*)ws.str, p.n_src, p.n_bnd, (R*)ws.grid[l], uv, ub, ud, (const double*)b.horner,
-                       (const unsigned long long*)ws.smax, (const WorkUnit*)b.sp_units);
+    hipLaunchKernelGGL((k_spread<R, W>), dim3(nu), dim3(kThreads), lds, st, g, view<R>(b.vol), view<R>(b.bnd), str,
+                       p.n_src, p.n_bnd, grid, uv, ub, ud, (const double*)b.horner, smax,
+                       (const WorkUnit*)b.sp_units);
+}
+
+// A level with dip spreads the double layer as two more channels: the
+// strengths mu nu_1 w and mu nu_2 w (stored after the node strengths, one per
+// boundary node) with the kernel itself, into their own grids, bounded by the
+// second strength maximum (max |mu nu w|_1).
+template <typename R, int W>
+static void spread_level(const Plan& p, const Workspace& ws, hipStream_t st, int l, size_t lds, int uv, int ub,
+                         int ud)
+{
+    const R* str = (const R*)ws.str;
+    const unsigned long long* smax = ws.smax;
+    const bool dip = ud && ub && p.lv[l].dip && ws.dgrid[0];
+    spread_launch<R, W>(p, st, l, lds, str, smax, (R*)ws.grid[l], uv, ub, dip ? 0 : ud);
+    if (!dip) return;
+    const int64_t n_all = p.n_src + p.n_bnd;
+    for (int c = 0; c < 2; ++c)
+        spread_launch<R, W>(p, st, l, lds, str + n_all + c * p.n_bnd - p.n_src, smax ? smax + 1 : nullptr,
+                            (R*)ws.dgrid[c], 0, 1, 0);
 }
 
 template <typename R>
@@ -236,7 +293,7 @@ static hipError_t spread_t(const Plan& p, const Workspace& ws, hipStream_t st, i
     switch (p.lv[l].w) {
 #define VP_CASE(W)                                               \
     case W:                                                      \
-        spread_launch<R, W>(p, ws, st, l, lds, uv, ub, ud);      \
+        spread_level<R, W>(p, ws, st, l, lds, uv, ub, ud);       \
         break;
         VP_W_CASES(VP_CASE)
 #undef VP_CASE
@@ -253,22 +310,40 @@ hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int
                                   : spread_t<double>(p, ws, st, level, use_vol, use_bnd, use_d);
 }
 
-// Levels of a fused FFT launch: level 0 or 1 alone, or both (level < 0).
+// Entries of a fused FFT launch: level 0 or 1 alone, or both (level < 0);
+// channels = true adds the double-layer channel grids of a level with dip as
+// entries of their own (row pass); channels_only keeps just those (their
+// forward column transforms).
 template <typename R>
-static LevelPair<R> level_pair(const Plan& p, const Workspace& ws, int level, int (*units)(const LevelGeom&))
+static LevelPair<R> level_pair(const Plan& p, const Workspace& ws, int level, int (*units)(const LevelGeom&),
+                               bool channels, bool channels_only = false)
 {
     LevelPair<R> P{};
     int k = 0;
+    const int dl = dip_level(p, ws);
     for (int l = 0; l < 2; ++l) {
         if (level >= 0 && l != level) continue;
-        P.g[k] = p.lv[l];
-        P.grid[k] = (R*)ws.grid[l];
-        P.spec[k] = (cplx<R>*)ws.spec[l];
-        P.tw[k] = (const cplx<R>*)p.lb[l].tw;
-        P.mult[k] = (const R*)p.lb[l].mult;
-        P.n[k] = units(p.lv[l]);
-        ++k;
+        if (!channels_only) {
+            P.g[k] = p.lv[l];
+            P.grid[k] = (R*)ws.grid[l];
+            P.spec[k] = (cplx<R>*)ws.spec[l];
+            P.tw[k] = (const cplx<R>*)p.lb[l].tw;
+            P.mult[k] = (const R*)p.lb[l].mult;
+            P.n[k] = units(p.lv[l]);
+            ++k;
+        }
+        if (channels && l == dl)
+            for (int c = 0; c < 2; ++c) {
+                P.g[k] = p.lv[l];
+                P.grid[k] = (R*)ws.dgrid[c];
+                P.spec[k] = (cplx<R>*)ws.dspec[c];
+                P.tw[k] = (const cplx<R>*)p.lb[l].tw;
+                P.mult[k] = nullptr;
+                P.n[k] = units(p.lv[l]);
+                ++k;
+            }
     }
+    P.cnt = k;
     return P;
 }
 
@@ -283,45 +358,57 @@ static size_t pair_lds(const Plan& p, int level, size_t (*lds)(const Plan&, int)
     return m;
 }
 
+// dip_used: the evaluation spread the double layer into the channel grids
 template <typename R>
-static hipError_t row_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level)
+static hipError_t row_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool dip_used)
 {
-    const LevelPair<R> P = level_pair<R>(p, ws, level, rows_of);
-    hipLaunchKernelGGL(k_row_r2c<R>, dim3(P.n[0] + P.n[1]), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st,
-                       P);
+    const LevelPair<R> P = level_pair<R>(p, ws, level, rows_of, dip_used);
+    hipLaunchKernelGGL(k_row_r2c<R>, dim3(P.total()), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st, P);
     return hipGetLastError();
 }
 
-hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level)
+hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool dip_used)
 {
-    return p.precision == VP_FP32 ? row_fft_t<float>(p, ws, st, level) : row_fft_t<double>(p, ws, st, level);
+    return p.precision == VP_FP32 ? row_fft_t<float>(p, ws, st, level, dip_used)
+                                  : row_fft_t<double>(p, ws, st, level, dip_used);
 }
 
 template <typename R>
-static hipError_t col_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level)
+static hipError_t col_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool dip_used)
 {
-    const LevelPair<R> P = level_pair<R>(p, ws, level, cols_of);
-    const int zero_dc = p.precision == VP_FP32 ? 1 : 0;
     int f = 0;
     for (int l = 0; l < 2; ++l)
         if (level < 0 || l == level) f = std::max(f, p.lv[l].F);
     const int threads = std::min(kColThreadsMax, std::max(kThreads, f / 4));
-    hipLaunchKernelGGL((k_col<R>), dim3(P.n[0] + P.n[1]), dim3(threads), pair_lds(p, level, col_fft_lds_bytes), st,
-                       P, zero_dc);
+    const int dl = dip_used ? dip_level(p, ws) : -1;
+    if (dl >= 0 && (level < 0 || level == dl)) {
+        const LevelPair<R> C = level_pair<R>(p, ws, dl, cols_of, true, true);
+        hipLaunchKernelGGL((k_col_fwd<R>), dim3(C.total()), dim3(threads), col_fft_lds_bytes(p, dl), st, C);
+    }
+    LevelPair<R> P = level_pair<R>(p, ws, level, cols_of, false);
+    if (dl >= 0)
+        for (int k = 0; k < P.cnt; ++k)
+            if (P.spec[k] == (cplx<R>*)ws.spec[dl]) {
+                P.dsp[k][0] = (const cplx<R>*)ws.dspec[0];
+                P.dsp[k][1] = (const cplx<R>*)ws.dspec[1];
+            }
+    const int zero_dc = p.precision == VP_FP32 ? 1 : 0;
+    hipLaunchKernelGGL((k_col<R>), dim3(P.total()), dim3(threads), pair_lds(p, level, col_fft_lds_bytes), st, P,
+                       zero_dc);
     return hipGetLastError();
 }
 
-hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level)
+hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool dip_used)
 {
-    return p.precision == VP_FP32 ? col_fft_t<float>(p, ws, st, level) : col_fft_t<double>(p, ws, st, level);
+    return p.precision == VP_FP32 ? col_fft_t<float>(p, ws, st, level, dip_used)
+                                  : col_fft_t<double>(p, ws, st, level, dip_used);
 }
 
 template <typename R>
 static hipError_t row_ifft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level)
 {
-    const LevelPair<R> P = level_pair<R>(p, ws, level, rows_of);
-    hipLaunchKernelGGL(k_row_c2r<R>, dim3(P.n[0] + P.n[1]), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st,
-                       P);
+    const LevelPair<R> P = level_pair<R>(p, ws, level, rows_of, false);
+    hipLaunchKernelGGL(k_row_c2r<R>, dim3(P.total()), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st, P);
     return hipGetLastError();
 }
 

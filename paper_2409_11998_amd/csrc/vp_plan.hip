@@ -595,6 +595,13 @@ vp_status set_level_geom(Plan& p, int l, const LevelCand& c, int T, double cx, d
     g.Ti = T;
     g.ntxi = g.ntx;
     g.mma = (p.precision == VP_FP32 && T == kMmaTile) ? 1 : 0;
+    // Float32 far-history levels spread the double layer as two channels of its own: through the
+    // kernel derivative its grid holds a dipole layer of size ~1/h whose float32 rounding is white
+    // noise, which the far-history multiplier amplifies at the lowest wavenumbers where the dipole
+    // signal is smallest (measured on the square workload: 1.2e-5 with the derivative, growing
+    // with the far-history grid); in channels of their own the noise is multiplied by k like the
+    // signal.
+    g.dip = (p.precision == VP_FP32 && (p.kinds & VP_KIND_D) && l == 1) ? 1 : 0;
     phihat = kernel_ft(c.w, g.beta, c.F, c.M);
     for (double v : phihat)
         if (!(v > 0)) return fail(VP_ERR_INTERNAL, "spreading kernel transform not positive");
@@ -639,6 +646,14 @@ vp_status time_level(Plan& p, int l, double* ms)
     off += align256(kDcParts * sizeof(double));
     const size_t o_smax = off;
     off += 256;
+    size_t o_dip[4] = {0, 0, 0, 0};
+    if (g.dip)
+        for (int c = 0; c < 2; ++c) {
+            o_dip[2 * c] = off;
+            off += align256(F * F * rb);
+            o_dip[2 * c + 1] = off;
+            off += align256(M1 * F * 2 * rb);
+        }
     unsigned char* blk = nullptr;
     VP_HIP(hipMalloc((void**)&blk, off), "autotune workspace");
     Workspace ws;
@@ -650,6 +665,11 @@ vp_status time_level(Plan& p, int l, double* ms)
     ws.str = blk + o_str;
     ws.dc = (double*)(blk + o_dc);
     ws.smax = (unsigned long long*)(blk + o_smax);
+    if (g.dip)
+        for (int c = 0; c < 2; ++c) {
+            ws.dgrid[c] = blk + o_dip[2 * c];
+            ws.dspec[c] = blk + o_dip[2 * c + 1];
+        }
     const bool uv = (p.kinds & VP_KIND_V) && p.n_src > 0;
     const bool ub = (p.kinds & (VP_KIND_S | VP_KIND_D)) && p.n_bnd > 0;
     const bool ud = (p.kinds & VP_KIND_D) && p.n_bnd > 0;
@@ -666,8 +686,8 @@ vp_status time_level(Plan& p, int l, double* ms)
         if (err == hipSuccess) err = launch_zero(p, ws, st);
         if (err == hipSuccess) err = launch_strengths(p, ws, st, f, sig, mu);
         if (err == hipSuccess) err = launch_spread(p, ws, st, l, uv, ub, ud);
-        if (err == hipSuccess) err = launch_row_fft(p, ws, st, l);
-        if (err == hipSuccess) err = launch_col_fft(p, ws, st, l);
+        if (err == hipSuccess) err = launch_row_fft(p, ws, st, l, ud);
+        if (err == hipSuccess) err = launch_col_fft(p, ws, st, l, ud);
         if (err == hipSuccess) err = launch_row_ifft(p, ws, st, l);
         if (err == hipSuccess) err = launch_interp(p, ws, st, l);
         if (err == hipSuccess) err = hipEventRecord(e1, st);
@@ -704,6 +724,11 @@ static size_t workspace_layout(const Plan& p, Workspace* ws, unsigned char* base
         take(ws ? &ws->grid[l] : nullptr, F * F * rb);
         take(ws ? &ws->spec[l] : nullptr, M1 * F * 2 * rb);
         take(ws ? &ws->hist[l] : nullptr, (size_t)std::max<int64_t>(p.n_tgt, 1) * rb);
+        if (g.dip)
+            for (int c = 0; c < 2; ++c) {
+                take(ws ? &ws->dgrid[c] : nullptr, F * F * rb);
+                take(ws ? &ws->dspec[c] : nullptr, M1 * F * 2 * rb);
+            }
     }
     const int64_t nstr = p.n_src + p.n_bnd + ((p.kinds & VP_KIND_D) ? 2 * p.n_bnd : 0);
     take(ws ? &ws->str : nullptr, (size_t)std::max<int64_t>(nstr, 1) * rb);
@@ -805,14 +830,14 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
         VP_HIP(hipEventRecord(p.fork[0], st), "fork");
         VP_HIP(hipStreamWaitEvent(sd, p.fork[0], 0), "fork");
         VP_HIP(launch_spread(p, ws, sd, 1, use_v, use_s || use_d, use_d), "spread");
-        VP_HIP(launch_row_fft(p, ws, sd, 1), "row fft");
-        VP_HIP(launch_col_fft(p, ws, sd, 1), "column fft");
+        VP_HIP(launch_row_fft(p, ws, sd, 1, use_d), "row fft");
+        VP_HIP(launch_col_fft(p, ws, sd, 1, use_d), "column fft");
         VP_HIP(launch_row_ifft(p, ws, sd, 1), "row ifft");
         VP_HIP(launch_interp(p, ws, sd, 1), "interp");
         VP_HIP(hipEventRecord(p.fork[1], sd), "join");
         VP_HIP(launch_spread(p, ws, st, 0, use_v, use_s || use_d, use_d), "spread");
-        VP_HIP(launch_row_fft(p, ws, st, 0), "row fft");
-        VP_HIP(launch_col_fft(p, ws, st, 0), "column fft");
+        VP_HIP(launch_row_fft(p, ws, st, 0, use_d), "row fft");
+        VP_HIP(launch_col_fft(p, ws, st, 0, use_d), "column fft");
         VP_HIP(launch_row_ifft(p, ws, st, 0), "row ifft");
         VP_HIP(launch_interp(p, ws, st, 0), "interp");
         VP_HIP(hipStreamWaitEvent(st, p.fork[1], 0), "join");
@@ -830,11 +855,11 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
     }
     // timed: every launch on one stream, one per level, in the order of the timing slots
     for (int l = 0; l < 2; ++l) {
-        VP_HIP(launch_row_fft(p, ws, st, l), "row fft");
+        VP_HIP(launch_row_fft(p, ws, st, l, use_d), "row fft");
         VP_HIP(mark(4 + l), "event");
     }
     for (int l = 0; l < 2; ++l) {
-        VP_HIP(launch_col_fft(p, ws, st, l), "column fft");
+        VP_HIP(launch_col_fft(p, ws, st, l, use_d), "column fft");
         VP_HIP(mark(6 + l), "event");
     }
     for (int l = 0; l < 2; ++l) {
@@ -1026,7 +1051,7 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
                             kmax_for(p->delta2, p->eps / std::max(1.0, p->L * p->L), pk)};
     double period[2] = {E + R, E + p->L + R};
     const int64_t n_pts = ((o.kinds & VP_KIND_V) ? n_src : 0) + (need_b ? n_bnd : 0);
-    const int Fmax = (o.precision == VP_FP32) ? 8192 : 4096;
+    const int Fmax = 8192;   // both precisions; level_fits_lds rejects what the LDS cannot hold
     std::vector<LevelCand> cands[2];
     for (int l = 0; l < 2; ++l) {
         // The double layer is spread with the derivative of the spreading kernel,

@@ -78,8 +78,9 @@ def test_budget_admission_and_rejection():
     from paper_2409_11998_amd.binding import VP_ERR_OOM
     torch, probs, devs, plans = _problems()
     ws = [_size_class(p.info()["workspace_bytes"]) for p in plans]
-    budget = int(1.3 * sorted(ws)[len(ws) // 2])   # about half the requests fit, never two big ones
-    assert max(ws) > budget
+    top = sorted(ws)
+    budget = (top[-2] + top[-1]) // 2   # the largest never fits, two of the next ones never together
+    assert max(ws) > budget >= top[-2] and top[-2] + top[-3] > budget
     srv = Server(hbm_budget_bytes=budget, max_in_flight=8, n_streams=2)
     tickets = []
     for rep in range(3):
