@@ -607,6 +607,31 @@ def batch_leg(torch, probs, steps, warmup, tune_sample):
         batch.eval(args, graph=True)
     batch.stream.synchronize()
     el_b = time.perf_counter() - t0
+    # stage times of the batched launch (a pass of its own: events between stages, no graph)
+    batch.set_timing(True)
+    stages = {}
+    for _ in range(steps):
+        batch.eval(args, graph=False)
+        for k, v in batch.timing().items():
+            stages[k] = stages.get(k, 0.0) + v / steps
+    batch.set_timing(False)
+    batch.stream.synchronize()
+    # step-table bytes of the stages over all instances (float32: b = 4; one read of each input and
+    # one write of each output), as for the single-plan legs
+    b = 4
+    sb = {"spread": 0, "fft": 0, "interp": 0}
+    for P, p in zip(probs, plans):
+        inf = p.info()
+        for l in range(2):
+            F2b = inf["fine"][l] ** 2 * b
+            sb["spread"] += P.n_src * 3 * b + P.n_bnd * 5 * b + F2b + (2 * F2b if l == 1 else 0)
+            sb["fft"] += 6 * F2b + (4 * F2b if l == 1 else 0)
+            sb["interp"] += F2b + P.n_tgt * 3 * b
+    fft_ms = stages["row_fft"] + stages["col_fwd_channels"] + stages["col_fft_mul"] + stages["row_ifft"]
+    cells = int(sum(sum(F * F for F in p_.info()["fine"]) for p_ in plans))
+    stage_frac = {"spread": sb["spread"] / (stages["spread"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "fft_chain": sb["fft"] / (fft_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "interp": sb["interp"] / (stages["interp"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
     got = [o.cpu().numpy() for o in outs]
     # the same plans, one plain launch sequence each
     seq_outs = [torch.empty_like(o) for o in outs]
@@ -633,6 +658,9 @@ def batch_leg(torch, probs, steps, warmup, tune_sample):
             "value": round(n_t * steps / el_b, 1), "unit": "target pts/s", "ms_per_step": round(1e3 * el_b / steps, 4),
             "sequential_value": round(n_t * steps / el_s, 1), "sequential_ms_per_step": round(1e3 * el_s / steps, 4),
             "max_rel_dev_vs_single_plans": dev_single,
+            "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+            "steps_frac_of_hbm": {k: round(v, 4) for k, v in stage_frac.items()},
+            "grid_cells_total": cells,
             "spread_width": widths, "fine_grids": [list(g) for g in grids], "autotune_sample": tune_sample,
             "plan_s": round(plan_s, 2)}
 

@@ -461,6 +461,18 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
  * replay).  Enqueues on the batch stream and returns. */
 vp_status vp_batch_eval(vp_batch_t batch, const vp_eval_args* args, int use_graph);
 
+/* Stage times of the batched launch.  vp_batch_set_timing(batch, 1) makes
+ * vp_batch_eval record HIP events on the batch stream around each stage kind
+ * (and run without the graph); vp_batch_get_timing waits for the last timed
+ * call and writes VP_BATCH_STAGES times in ms (host array of n >= that):
+ * grid zeroing, strengths, spreading (every width), row pass, column
+ * transforms of double-layer channels, column pass with the multiply,
+ * inverse row pass, interpolation (every width), local part.  VP_ERR_ARG
+ * without a timed call or for n too small. */
+#define VP_BATCH_STAGES 9
+vp_status vp_batch_set_timing(vp_batch_t batch, int enable);
+vp_status vp_batch_get_timing(vp_batch_t batch, float* ms, int n);
+
 /* Release the batch (synchronizes its stream); the plans are not destroyed. */
 vp_status vp_batch_destroy(vp_batch_t batch);
 

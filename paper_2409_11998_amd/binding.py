@@ -21,6 +21,7 @@ STATUS = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_OOM", 3: "VP_ERR_DEVICE", 4: "
 EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "vp_destroy",
             "vp_last_error", "vp_get_plan_info", "vp_set_timing", "vp_get_timing",
             "vp_batch_create", "vp_batch_eval", "vp_batch_destroy", "vp_batch_last_error",
+            "vp_batch_set_timing", "vp_batch_get_timing",
             "vp_server_create", "vp_server_submit", "vp_server_poll", "vp_server_wait", "vp_server_get_stats",
             "vp_server_destroy", "vp_server_last_error", "vp_refine_attach", "vp_layer_refine",
             "vp_boundary_frame", "vp_boundary_jets", "vp_dirichlet_solve", "vp_exterior_dirichlet_solve",
@@ -150,6 +151,10 @@ def lib():
         L.vp_batch_eval.restype = ctypes.c_int
         L.vp_batch_destroy.argtypes = [vp]
         L.vp_batch_destroy.restype = ctypes.c_int
+        L.vp_batch_set_timing.argtypes = [vp, ctypes.c_int]
+        L.vp_batch_set_timing.restype = ctypes.c_int
+        L.vp_batch_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+        L.vp_batch_get_timing.restype = ctypes.c_int
         L.vp_batch_last_error.argtypes = []
         L.vp_batch_last_error.restype = ctypes.c_char_p
         L.vp_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(VPServerOpts)]
@@ -362,6 +367,19 @@ class Batch:
             a[i].mu_jet5 = _ptr(d.get("mu_jet"), f64)
             a[i].out = _ptr(d["out"], f64)
         _bcheck(lib().vp_batch_eval(self.handle, a, 1 if graph else 0))
+
+    BATCH_STAGES = ("zero", "strengths", "spread", "row_fft", "col_fwd_channels", "col_fft_mul", "row_ifft",
+                    "interp", "local")
+
+    def set_timing(self, on):
+        """Record stage events in later eval calls (vp_batch_set_timing; those calls run without the graph)."""
+        _bcheck(lib().vp_batch_set_timing(self.handle, 1 if on else 0))
+
+    def timing(self):
+        """{stage: ms} of the last timed eval (vp_batch_get_timing)."""
+        ms = (ctypes.c_float * len(self.BATCH_STAGES))()
+        _bcheck(lib().vp_batch_get_timing(self.handle, ms, len(self.BATCH_STAGES)))
+        return dict(zip(self.BATCH_STAGES, [float(v) for v in ms]))
 
     def close(self):
         if getattr(self, "handle", None):

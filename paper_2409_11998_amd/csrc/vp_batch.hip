@@ -48,6 +48,13 @@ template <typename R> __device__ inline RecView<R> tgt_view(const LevelDesc& d)
     return RecView<R>{d.tgt_start, d.tgt_ij, (const R*)d.tgt_dx, (const R*)d.tgt_dy, d.tgt_idx};
 }
 
+// The interpolation tap table of a level for plan precision R.
+template <typename R> __device__ inline const typename dev::TapT<R>::T* interp_table(const LevelDesc& d)
+{
+    if constexpr (sizeof(R) == 4) return d.horner_if;
+    else return d.horner_i;
+}
+
 // Item `it` of a stage -> (instance, level, unit); false for padding items.
 __device__ __forceinline__ bool decode(const StageTab& t, int it, int& inst, int& level, int& unit)
 {
@@ -242,7 +249,8 @@ __global__ __launch_bounds__(kThreads) void kg_interp(const LevelDesc* __restric
         if (!decode(t, it, i, l, u)) continue;
         const LevelDesc& D = lv[2 * i + l];
         const LevelGeom g = D.g;
-        dev::dev_interp<R, W>(smem_raw, g, (const R*)D.grid, tgt_view<R>(D), (R*)D.hist, D.horner_i, D.in_units[u]);
+        dev::dev_interp<R, W>(smem_raw, g, (const R*)D.grid, tgt_view<R>(D), (R*)D.hist, interp_table<R>(D),
+                              D.in_units[u]);
         __syncthreads();
     }
 }
@@ -335,6 +343,7 @@ void fill_instance(const Plan& p, const Workspace& ws, InstDesc& I, LevelDesc* D
         d.hist = ws.hist[l];
         d.horner = lb.horner;
         d.horner_i = lb.horner_i;
+        d.horner_if = lb.horner_if;
         d.sp_units = lb.sp_units;
         d.in_units = lb.in_units;
         d.n_sp_units = (int)lb.h_sp_units.size();
@@ -362,7 +371,7 @@ void HostStage::add(int inst, int level, int count)
 }
 
 vp_status group_build(const std::vector<const Plan*>& plans, const std::vector<Workspace>& ws,
-                      const std::vector<vp_eval_args>& args, GroupPlan& G)
+                      const std::vector<vp_eval_args>& args, GroupPlan& G, int kinds)
 {
     const int n = (int)plans.size();
     if (n == 0) return set_error(VP_ERR_ARG, "empty group");
@@ -409,7 +418,8 @@ vp_status group_build(const std::vector<const Plan*>& plans, const std::vector<W
             const int sp_items = g.mma ? (nsu + kThreads / 64 - 1) / (kThreads / 64) : nsu;
             sp.add(i, l, sp_items);
             sp.lds = std::max(sp.lds, spread_lds_bytes(p, l));
-            if (G.lv[2 * i + l].dgrid[0] && args[i].mu && p.n_bnd > 0)  // the double-layer channels
+            // the double-layer channels, when the calls pass mu
+            if (G.lv[2 * i + l].dgrid[0] && (args[i].mu || (kinds & VP_KIND_D)) && p.n_bnd > 0)
                 for (int c = 1; c <= 2; ++c) {
                     sp.add(i, l + 2 * c, sp_items);
                     G.row.add(i, l + 2 * c, g.F);
@@ -466,15 +476,24 @@ GroupTabs group_tabs(GroupPlan& G, unsigned char* dev_base)
     return T;
 }
 
+// ev (optional): kBatchStages + 1 events, recorded before the first stage and
+// after each stage kind (zero, strengths, spread, row pass, double-layer
+// column transforms, column pass, inverse row pass, interpolation, local part).
 template <typename R>
-static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStream_t st, int cus)
+static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStream_t st, int cus, hipEvent_t* ev)
 {
+    auto mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], st);
+    };
+    mark(0);
     if (T.zero.nitems)
         hipLaunchKernelGGL(kg_zero<R>, dim3(persistent_grid(T.zero.nitems, cus, 8)), dim3(kThreads), 0, st, T.inst,
                            T.lv, T.zero);
+    mark(1);
     if (T.str.nitems)
         hipLaunchKernelGGL(kg_strengths<R>, dim3(persistent_grid(T.str.nitems, cus, 8)), dim3(kThreads), 0, st,
                            T.inst, T.call, T.str);
+    mark(2);
     for (size_t k = 0; k < G.spread.size(); ++k) {
         const StageTab& t = T.spread[k];
         if (!t.nitems) continue;
@@ -510,19 +529,24 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
             return hipErrorInvalidValue;
         }
     }
+    mark(3);
     if (T.row.nitems)
         hipLaunchKernelGGL(kg_row_r2c<R>, dim3(persistent_grid(T.row.nitems, cus, 8)), dim3(kThreads), G.row.lds, st,
                            T.lv, T.row);
+    mark(4);
     const int zero_dc = G.precision == VP_FP32 ? 1 : 0;
     if (T.colf.nitems)
         hipLaunchKernelGGL((kg_col_fwd<R>), dim3(persistent_grid(T.colf.nitems, cus, 4)), dim3(kThreads), G.colf.lds,
                            st, T.lv, T.colf);
+    mark(5);
     if (T.col.nitems)
         hipLaunchKernelGGL((kg_col<R>), dim3(persistent_grid(T.col.nitems, cus, 4)), dim3(kThreads), G.col.lds, st,
                            T.lv, T.call, T.col, zero_dc);
+    mark(6);
     if (T.c2r.nitems)
         hipLaunchKernelGGL(kg_row_c2r<R>, dim3(persistent_grid(T.c2r.nitems, cus, 8)), dim3(kThreads), G.c2r.lds, st,
                            T.lv, T.c2r);
+    mark(7);
     for (size_t k = 0; k < G.interp.size(); ++k) {
         const StageTab& t = T.interp[k];
         if (!t.nitems) continue;
@@ -539,16 +563,18 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
             return hipErrorInvalidValue;
         }
     }
+    mark(8);
     if (T.local.nitems)
         hipLaunchKernelGGL(kg_local, dim3(persistent_grid(T.local.nitems, cus, 8)), dim3(kThreads), 0, st, T.inst,
                            T.call, T.local);
+    mark(9);
     return hipGetLastError();
 }
 
-hipError_t group_launch(const GroupPlan& G, const GroupTabs& T, hipStream_t st)
+hipError_t group_launch(const GroupPlan& G, const GroupTabs& T, hipStream_t st, hipEvent_t* ev)
 {
-    return G.precision == VP_FP32 ? group_launch_t<float>(G, T, st, device_cus())
-                                  : group_launch_t<double>(G, T, st, device_cus());
+    return G.precision == VP_FP32 ? group_launch_t<float>(G, T, st, device_cus(), ev)
+                                  : group_launch_t<double>(G, T, st, device_cus(), ev);
 }
 
 int device_cus()
@@ -616,6 +642,8 @@ struct vp_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool have_graph = false;
+    bool timing = false;                    // record stage events (no graph) in vp_batch_eval
+    hipEvent_t tev[kBatchStages + 1] = {};
 };
 
 namespace {
@@ -633,6 +661,8 @@ void free_batch(vp_batch_s* b)
     else hipDeviceSynchronize();
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
+    for (auto& e : b->tev)
+        if (e) hipEventDestroy(e);
     hipFree(b->d_buf);
     for (int k = 0; k < kCallSlots; ++k) {
         if (b->h_call[k]) hipHostFree(b->h_call[k]);
@@ -678,7 +708,7 @@ vp_status vp_batch_create(vp_batch_t* out, int n, const vp_plan_t* plans, int ki
         ws[i] = p.ws;
         std::memset(&args[i], 0, sizeof(args[i]));
     }
-    vp_status s = group_build(pp, ws, args, b->G);
+    vp_status s = group_build(pp, ws, args, b->G, kinds);   // every call passes the kinds' densities
     if (s != VP_OK) return bail(bfail(s, vp_last_error()));
     if (hipMalloc((void**)&b->d_buf, b->G.bytes) != hipSuccess) return bail(bfail(VP_ERR_OOM, "batch tables"));
     b->T = group_tabs(b->G, b->d_buf);
@@ -723,11 +753,16 @@ vp_status vp_batch_eval(vp_batch_t b, const vp_eval_args* args, int use_graph)
                        b->stream) != hipSuccess)
         return bfail(VP_ERR_DEVICE, "call table");
     if (hipEventRecord(b->call_ev[k], b->stream) != hipSuccess) return bfail(VP_ERR_DEVICE, "call slot event");
+    if (b->timing) {
+        hipError_t e = group_launch(b->G, b->T, b->stream, b->tev);
+        if (e != hipSuccess) return bfail(VP_ERR_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+        return VP_OK;
+    }
     if (use_graph) {
         if (!b->have_graph) {
             if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
                 return bfail(VP_ERR_DEVICE, "begin capture");
-            hipError_t e = group_launch(b->G, b->T, b->stream);
+            hipError_t e = group_launch(b->G, b->T, b->stream, nullptr);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -742,8 +777,31 @@ vp_status vp_batch_eval(vp_batch_t b, const vp_eval_args* args, int use_graph)
         if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return bfail(VP_ERR_DEVICE, "graph launch");
         return VP_OK;
     }
-    hipError_t e = group_launch(b->G, b->T, b->stream);
+    hipError_t e = group_launch(b->G, b->T, b->stream, nullptr);
     if (e != hipSuccess) return bfail(VP_ERR_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    return VP_OK;
+}
+
+vp_status vp_batch_set_timing(vp_batch_t b, int enable)
+{
+    b_last_error.clear();
+    if (!b) return bfail(VP_ERR_ARG, "NULL batch");
+    if (enable && !b->tev[0])
+        for (auto& e : b->tev)
+            if (hipEventCreate(&e) != hipSuccess) return bfail(VP_ERR_DEVICE, "event create");
+    b->timing = enable != 0;
+    return VP_OK;
+}
+
+vp_status vp_batch_get_timing(vp_batch_t b, float* ms, int n)
+{
+    b_last_error.clear();
+    if (!b || !ms || n < kBatchStages) return bfail(VP_ERR_ARG, "NULL argument or n < VP_BATCH_STAGES");
+    if (!b->tev[0]) return bfail(VP_ERR_ARG, "timing was never enabled");
+    if (hipEventSynchronize(b->tev[kBatchStages]) != hipSuccess) return bfail(VP_ERR_DEVICE, "timing event");
+    for (int k = 0; k < kBatchStages; ++k)
+        if (hipEventElapsedTime(&ms[k], b->tev[k], b->tev[k + 1]) != hipSuccess)
+            return bfail(VP_ERR_DEVICE, "no timed evaluation yet");
     return VP_OK;
 }
 

@@ -351,12 +351,20 @@ __device__ __forceinline__ T lane_value(T v, int lane)
     }
 }
 
-// The tap polynomials are evaluated in float64 for both precisions.  An error
-// in the kernel values that is the same for every node at a given offset acts
-// as a change of the kernel's shape, which the deconvolution by 1/phihat^2
-// amplifies near the band edge: float32 Horner (about one ulp, coherent across
-// nodes) tripled the float32 path's end-to-end error.  One rounding of a
-// float64 value to float32 carries no such bias.
+// Precision of the tap polynomials.  An error in the kernel values that is the
+// same for every node at a given offset acts as a change of the kernel's shape,
+// which the deconvolution by 1/phihat^2 amplifies near the band edge.  The
+// planner therefore divides by the transforms of the very polynomials the
+// device evaluates (the interpolation table of float32 plans with float32
+// coefficients), so the only shape change left is the evaluation's own
+// rounding, which varies from node to node like noise.  Spreading evaluates
+// its taps in float64 in both precisions: its rounding noise lands on the grid,
+// where the far-history multiplier amplifies it at low wavenumbers (float32
+// taps raised the float32 error on the square workload from 6.8e-7 to 9.9e-7
+// for 7% of spreading time).  Interpolation noise stays with its target and is
+// not amplified, so float32 plans interpolate with float32 taps.
+template <typename R> struct TapT { using T = double; };
+template <> struct TapT<float> { using T = float; };
 
 // Horner evaluation of one tap's polynomial and its derivative in u.
 template <int P, typename H>
@@ -375,14 +383,14 @@ __device__ __forceinline__ void tap_value_deriv(const H* __restrict__ c, H u, H&
 // The kernel is even: tap w-1-a at offset u equals tap a at -u.  With tap a's
 // polynomial split as E(u^2) + u O(u^2) (ce[k] = c[2k], co[k] = c[2k+1]), one
 // evaluation gives both taps.
-template <int P>
-__device__ __forceinline__ void tap_pair(const double* ce, const double* co, double u, double& v_a, double& v_mirror)
+template <int P, typename T>
+__device__ __forceinline__ void tap_pair(const T* ce, const T* co, T u, T& v_a, T& v_mirror)
 {
-    const double u2 = u * u;
-    double e = ce[(P + 1) / 2 - 1];
+    const T u2 = u * u;
+    T e = ce[(P + 1) / 2 - 1];
 #pragma unroll
     for (int k = (P + 1) / 2 - 2; k >= 0; --k) e = fma(e, u2, ce[k]);
-    double o = co[P / 2 - 1];
+    T o = co[P / 2 - 1];
 #pragma unroll
     for (int k = P / 2 - 2; k >= 0; --k) o = fma(o, u2, co[k]);
     v_a = fma(u, o, e);
@@ -394,17 +402,16 @@ __device__ __forceinline__ void tap_pair(const double* ce, const double* co, dou
 // coefficient x power of u^2, the powers pw[k] = u^(2k) being shared by all
 // pairs of a lane, so every coefficient is a multiplicand (or the final
 // addend) and none has to be copied into a vector register first.
-template <int P>
-__device__ __forceinline__ void tap_pair_pow(const double* __restrict__ c, const double* pw, double u,
-                                             double& v_a, double& v_mirror)
+template <int P, typename T>
+__device__ __forceinline__ void tap_pair_pow(const T* __restrict__ c, const T* pw, T u, T& v_a, T& v_mirror)
 {
     constexpr int NE = (P + 1) / 2, NO = P / 2;
     static_assert(NO >= 2, "at least four terms");
-    double e = c[2 * (NE - 1)] * pw[NE - 1];
+    T e = c[2 * (NE - 1)] * pw[NE - 1];
 #pragma unroll
     for (int k = NE - 2; k >= 1; --k) e = fma(c[2 * k], pw[k], e);
     e += c[0];
-    double o = c[2 * (NO - 1) + 1] * pw[NO - 1];
+    T o = c[2 * (NO - 1) + 1] * pw[NO - 1];
 #pragma unroll
     for (int k = NO - 2; k >= 1; --k) o = fma(c[2 * k + 1], pw[k], o);
     o += c[1];
@@ -1026,9 +1033,10 @@ __host__ __device__ inline size_t interp_lds_bytes(int T, int W, size_t rb)
 
 template <typename R, int W>
 __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R* __restrict__ grid,
-                           const RecView<R>& L, R* __restrict__ hist, const double* __restrict__ coef,
+                           const RecView<R>& L, R* __restrict__ hist, const typename TapT<R>::T* __restrict__ coef,
                            const WorkUnit unit)
 {
+    using TT = typename TapT<R>::T;
     constexpr int P = interp_terms(W, sizeof(R) == 4);
     constexpr int NT = kInterpTargets;
     constexpr int VS = 2 * W + 1;  // odd stride: the targets' rows fall in different LDS banks
@@ -1070,16 +1078,16 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
         if (on) {
             p = L.ij[base + q];
             id = L.idx[base + q];
-            const double u = 2.0 * (double)(half ? L.dy[base + q] : L.dx[base + q]) - 1.0;
-            double pw[(P + 1) / 2];
-            pw[0] = 1.0;
+            const TT u = TT(2) * (TT)(half ? L.dy[base + q] : L.dx[base + q]) - TT(1);
+            TT pw[(P + 1) / 2];
+            pw[0] = TT(1);
             pw[1] = u * u;
 #pragma unroll
             for (int k = 2; k < (P + 1) / 2; ++k) pw[k] = pw[k - 1] * pw[1];
             R* dst = v + half * W;
 #pragma unroll
             for (int kp = 0; kp < NP; ++kp) {
-                double va, vm;
+                TT va, vm;
                 tap_pair_pow<P>(coef + kp * P, pw, u, va, vm);
                 dst[kp] = (R)va;
                 if (kp != W - 1 - kp) dst[W - 1 - kp] = (R)vm;

@@ -25,6 +25,7 @@ struct LevelDesc {
     void* hist;
     const double* horner;
     const double* horner_i;
+    const float* horner_if;  // float32 plans: the interpolation table as float32
     const WorkUnit* sp_units;
     const WorkUnit* in_units;
     int n_sp_units;
@@ -102,13 +103,18 @@ struct GroupTabs {
 };
 
 // Build the host image of a group (all plans of one precision).  args[i]:
-// densities of instance i (NULL = kind not evaluated).
+// densities of instance i (NULL = kind not evaluated); kinds: VP_KIND_* the
+// calls will pass whatever args holds now (a batch fixes its kinds when it is
+// built and its densities per call).
 vp_status group_build(const std::vector<const Plan*>& plans, const std::vector<Workspace>& ws,
-                      const std::vector<vp_eval_args>& args, GroupPlan& G);
+                      const std::vector<vp_eval_args>& args, GroupPlan& G, int kinds = 0);
 // Place the segment tables into G's image for a device buffer at dev_base.
 GroupTabs group_tabs(GroupPlan& G, unsigned char* dev_base);
-// Enqueue every stage of a group whose image has been copied to the device.
-hipError_t group_launch(const GroupPlan& G, const GroupTabs& T, hipStream_t st);
+// Stage kinds a group launch times (vp_batch_get_timing).
+constexpr int kBatchStages = VP_BATCH_STAGES;
+// Enqueue every stage of a group whose image has been copied to the device;
+// ev: NULL, or kBatchStages + 1 events recorded around the stage kinds.
+hipError_t group_launch(const GroupPlan& G, const GroupTabs& T, hipStream_t st, hipEvent_t* ev = nullptr);
 // Upper bound of the device image of a group of n instances.
 size_t group_bytes_bound(size_t n);
 // Build a group, stage its image in host_buf (pinned), copy it to dev_buf

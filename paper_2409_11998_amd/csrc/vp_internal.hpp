@@ -115,6 +115,7 @@ struct LevelBufs {
     void* tw = nullptr;        // cplx<R> [F/2] twiddles exp(-2 pi i k / F)
     double* horner = nullptr;  // [w][w+2] per-tap polynomial of the spreading kernel in u = 2d - 1
     double* horner_i = nullptr; // [w][interp_terms] the same pieces, values-only fit for interpolation
+    float* horner_if = nullptr; // float32 plans: the interpolation table as float32 (its values are float32)
 };
 
 // Per-evaluation device memory (everything an evaluation writes).  A plan may

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_row_c2r(LevelPair<R> P)
 
 template <typename R, int W>
 __global__ __launch_bounds__(kThreads) void k_interp(LevelGeom g, const R* __restrict__ grid, RecView<R> tgt,
-                                                     R* __restrict__ hist, const double* __restrict__ coef,
+                                                     R* __restrict__ hist, const typename TapT<R>::T* __restrict__ coef,
                                                      const WorkUnit* __restrict__ units)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -152,6 +152,14 @@ __global__ __launch_bounds__(kThreads) void k_interp(LevelGeom g, const R* __res
 __global__ __launch_bounds__(kThreads) void k_local(LocalArgs a)
 {
     dev_local(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The interpolation tap table a kernel of plan precision R evaluates.
+template <typename R>
+inline const typename TapT<R>::T* tap_table(const double* d, const float* f)
+{
+    if constexpr (std::is_same<R, float>::value) return f;
+    else return d;
 }
 
 inline unsigned grid_for(int64_t n, int per = kThreads)
@@ -426,7 +434,8 @@ static void interp_launch(const Plan& p, const Workspace& ws, hipStream_t st, in
     const unsigned nu = (unsigned)b.h_in_units.size();
     if (nu == 0) return;
     hipLaunchKernelGGL((k_interp<R, W>), dim3(nu), dim3(kThreads), lds, st, g, (const R*)ws.grid[l],
-                       view<R>(b.tgt), (R*)ws.hist[l], (const double*)b.horner_i, (const WorkUnit*)b.in_units);
+                       view<R>(b.tgt), (R*)ws.hist[l], tap_table<R>(b.horner_i, b.horner_if),
+                       (const WorkUnit*)b.in_units);
 }
 
 template <typename R>

@@ -118,27 +118,6 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
     }
 }
 
-// Fourier transform of the spreading kernel phi(x) = exp(beta (sqrt(1-(2x/w)^2) - 1)),
-// |x| < w/2 (grid units), at integer frequencies m of an F-periodic grid:
-// phihat(m) = int phi(x) exp(-2 pi i m x / F) dx.
-std::vector<double> kernel_ft(int w, double beta, int F, int M)
-{
-    std::vector<double> gx, gw;
-    gauss_legendre(std::max(2 * w + 40, 80), gx, gw);
-    std::vector<double> out(M + 1);
-    for (int m = 0; m <= M; ++m) {
-        double s = 0.0;
-        for (size_t q = 0; q < gx.size(); ++q) {
-            const double z = gx[q];
-            const double phi = std::exp(beta * (std::sqrt(1.0 - z * z) - 1.0));
-            const double x = 0.5 * w * z;
-            s += gw[q] * phi * std::cos(2.0 * M_PI * m * x / F);
-        }
-        out[m] = 0.5 * w * s;
-    }
-    return out;
-}
-
 // Near-history multiplier (exp(-k^2 d1) - exp(-k^2 d2)) / k^2 (Lemma 2.1), k -> 0 limit d2 - d1.
 double mult_nh(double k2, double d1, double d2)
 {
@@ -471,6 +450,54 @@ static std::vector<double> fit_tap_polynomials(int W, int P, double beta)
     return coef;
 }
 
+// Make the table exactly even, as the kernel is: tap w-1-a at u is tap a at -u, so
+// its coefficients are tap a's with the odd ones negated (the middle tap of an odd
+// width keeps only even terms); float32 plans then round every coefficient to
+// float32, the values their kernels evaluate with.
+static void settle_tap_table(std::vector<double>& coef, int W, int P, bool fp32)
+{
+    for (int a = 0; a < W; ++a) {
+        const int m = W - 1 - a;
+        for (int i = 0; i < P; ++i) {
+            double& c = coef[(size_t)a * P + i];
+            if (m < a) c = (i & 1) ? -coef[(size_t)m * P + i] : coef[(size_t)m * P + i];
+            else if (m == a && (i & 1)) c = 0.0;
+            if (fp32) c = (double)(float)c;
+        }
+    }
+}
+
+// Fourier transform of the kernel the device applies: tap a's piece is the
+// polynomial coef[a] in u = 2d - 1 over the cell [a - w/2, a - w/2 + 1) of the
+// support (grid units, node at the origin), so at F-periodic integer frequencies
+// phihat(m) = sum_a int_0^1 p_a(2d - 1) cos(2 pi m (a - w/2 + d) / F) dd
+// (the table is even, so the sine part vanishes).  Gauss-Legendre per cell,
+// exact for the polynomial times the cosine to rounding (at most half a turn
+// of phase per cell).
+static std::vector<double> poly_kernel_ft(const std::vector<double>& coef, int W, int P, int F, int M)
+{
+    std::vector<double> gx, gw;
+    gauss_legendre(P + 24, gx, gw);
+    std::vector<double> val((size_t)W * gx.size());
+    for (int a = 0; a < W; ++a)
+        for (size_t q = 0; q < gx.size(); ++q) {
+            double v = 0.0;
+            for (int i = P - 1; i >= 0; --i) v = v * gx[q] + coef[(size_t)a * P + i];
+            val[(size_t)a * gx.size() + q] = v;
+        }
+    std::vector<double> out(M + 1);
+    for (int m = 0; m <= M; ++m) {
+        double s = 0.0;
+        for (int a = 0; a < W; ++a)
+            for (size_t q = 0; q < gx.size(); ++q) {
+                const double x = a - 0.5 * W + 0.5 * (gx[q] + 1.0);
+                s += gw[q] * val[(size_t)a * gx.size() + q] * std::cos(2.0 * M_PI * m * x / F);
+            }
+        out[m] = 0.5 * s;   // dd = du / 2
+    }
+    return out;
+}
+
 // max |polynomial - kernel| over taps and 513 offsets per tap
 static double tap_fit_error(const std::vector<double>& coef, int W, int P, double beta)
 {
@@ -486,29 +513,41 @@ static double tap_fit_error(const std::vector<double>& coef, int W, int P, doubl
 }
 
 template <typename R>
-vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, double d1, double d2)
+vp_status build_level_tables(Plan& p, int l, double d1, double d2)
 {
     LevelGeom& g = p.lv[l];
     LevelBufs& b = p.lb[l];
     const int M = g.M;
     const double s = g.dk / (2.0 * M_PI);
     const double scale = s * s;
+    const bool fp32 = p.precision == VP_FP32;
+    // Spreading kernel per tap as a polynomial in the node offset (spreading
+    // table, horner_terms(w) terms; interpolation table, interp_terms(w)), made
+    // exactly even and, for the interpolation of float32 plans, rounded to float32.  The multiplier
+    // divides by the transforms of exactly these polynomials, so the tables'
+    // fit to the exponential of the semicircle is no error of the method's
+    // discretization: the spread and the interpolation apply kernels whose
+    // transforms are divided out exactly.
+    const int W = g.w, P = horner_terms(W);
+    const int PI = interp_terms(W, fp32);
+    std::vector<double> coef = fit_tap_polynomials(W, P, g.beta);
+    std::vector<double> coef_i = fit_tap_polynomials(W, PI, g.beta);
+    settle_tap_table(coef, W, P, false);      // spreading taps are evaluated in float64
+    settle_tap_table(coef_i, W, PI, fp32);    // interpolation taps in the plan's precision
+    const std::vector<double> ph_s = poly_kernel_ft(coef, W, P, g.F, M);
+    const std::vector<double> ph_i = poly_kernel_ft(coef_i, W, PI, g.F, M);
+    for (int m = 0; m <= M; ++m)
+        if (!(ph_s[m] > 0 && ph_i[m] > 0)) return fail(VP_ERR_INTERNAL, "spreading kernel transform not positive");
     std::vector<R> mult((size_t)(M + 1) * (M + 1));
     for (int a = 0; a <= M; ++a)
         for (int c = 0; c <= M; ++c) {
             const double k2 = g.dk * g.dk * ((double)a * a + (double)c * c);
             const double m = (l == 0) ? mult_nh(k2, d1, d2) : mult_fh(k2, d2, p.L);
-            const double ph = phihat[a] * phihat[c];
-            mult[(size_t)a * (M + 1) + c] = (R)(scale * m / (ph * ph));
+            const double ph = ph_s[a] * ph_s[c] * ph_i[a] * ph_i[c];
+            mult[(size_t)a * (M + 1) + c] = (R)(scale * m / ph);
         }
     g.dc_coef = scale * ((l == 0) ? mult_nh(0.0, d1, d2) : mult_fh(0.0, d2, p.L));
-    // Spreading kernel per tap as a polynomial in the node offset (spreading
-    // table, horner_terms(w) terms; interpolation table, interp_terms(w)).
     {
-        const int W = g.w, P = horner_terms(W);
-        const int PI = interp_terms(W, p.precision == VP_FP32);
-        const std::vector<double> coef = fit_tap_polynomials(W, P, g.beta);
-        const std::vector<double> coef_i = fit_tap_polynomials(W, PI, g.beta);
         g.fit_err[0] = tap_fit_error(coef, W, P, g.beta);
         g.fit_err[1] = tap_fit_error(coef_i, W, PI, g.beta);
         // bound on |d/dy tap value| = (2/h) |dp/du| over taps and offsets (sampled, 5% margin)
@@ -524,6 +563,11 @@ vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, 
         vp_status st2;
         if ((st2 = upload(p, &b.horner, coef, "kernel polynomials")) != VP_OK) return st2;
         if ((st2 = upload(p, &b.horner_i, coef_i, "interpolation kernel polynomials")) != VP_OK) return st2;
+        if (fp32) {  // the same values as float32, for the float32 interpolation
+            const std::vector<float> cif(coef_i.begin(), coef_i.end());
+            if ((st2 = upload(p, &b.horner_if, cif, "interpolation kernel polynomials (float32)")) != VP_OK)
+                return st2;
+        }
     }
     std::vector<cplx<R>> tw(g.F / 2);
     for (int k = 0; k < g.F / 2; ++k) {
@@ -540,7 +584,7 @@ vp_status build_level_tables(Plan& p, int l, const std::vector<double>& phihat, 
 template <typename R>
 vp_status build_level(Plan& p, int l, const std::vector<double>& sxv, const std::vector<double>& syv,
                       const std::vector<int>& vol_ids, const std::vector<int>& bnd_ids, const std::vector<double>& tx,
-                      const std::vector<double>& ty, const std::vector<double>& phihat)
+                      const std::vector<double>& ty)
 {
     vp_status s;
     std::vector<int> tids(p.n_tgt);
@@ -550,7 +594,7 @@ vp_status build_level(Plan& p, int l, const std::vector<double>& sxv, const std:
     if ((s = build_records<R>(p, l, sxv, syv, bnd_ids, &b.bnd)) != VP_OK) return s;
     if ((s = build_records<R>(p, l, tx, ty, tids, &b.tgt, p.lv[l].Ti + p.lv[l].w - 1, p.lv[l].Ti)) != VP_OK) return s;
     if ((s = build_units(p, l)) != VP_OK) return s;
-    if ((s = build_level_tables<R>(p, l, phihat, p.delta1, p.delta2)) != VP_OK) return s;
+    if ((s = build_level_tables<R>(p, l, p.delta1, p.delta2)) != VP_OK) return s;
     return VP_OK;
 }
 
@@ -571,10 +615,8 @@ struct LevelCand {
     double cost;    // static cost model (used without autotune)
 };
 
-// Geometry of level l for candidate c and tile edge T; phihat receives the
-// spreading kernel's transform at modes 0..M.
-vp_status set_level_geom(Plan& p, int l, const LevelCand& c, int T, double cx, double cy,
-                         std::vector<double>& phihat)
+// Geometry of level l for candidate c and tile edge T.
+vp_status set_level_geom(Plan& p, int l, const LevelCand& c, int T, double cx, double cy)
 {
     LevelGeom& g = p.lv[l];
     g.F = c.F;
@@ -602,9 +644,6 @@ vp_status set_level_geom(Plan& p, int l, const LevelCand& c, int T, double cx, d
     // with the far-history grid); in channels of their own the noise is multiplied by k like the
     // signal.
     g.dip = (p.precision == VP_FP32 && (p.kinds & VP_KIND_D) && l == 1) ? 1 : 0;
-    phihat = kernel_ft(c.w, g.beta, c.F, c.M);
-    for (double v : phihat)
-        if (!(v > 0)) return fail(VP_ERR_INTERNAL, "spreading kernel transform not positive");
     return VP_OK;
 }
 
@@ -1123,9 +1162,9 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
 
     // ---- levels: static cost model, or measured selection (opts.autotune)
     const bool fp32 = o.precision == VP_FP32;
-    auto build = [&](int l, const std::vector<double>& ph) {
-        return fp32 ? build_level<float>(*p, l, ax, ay, vol_ids, bnd_ids, tx, ty, ph)
-                    : build_level<double>(*p, l, ax, ay, vol_ids, bnd_ids, tx, ty, ph);
+    auto build = [&](int l) {
+        return fp32 ? build_level<float>(*p, l, ax, ay, vol_ids, bnd_ids, tx, ty)
+                    : build_level<double>(*p, l, ax, ay, vol_ids, bnd_ids, tx, ty);
     };
     std::vector<int> tiles;
     if (o.tile > 0) tiles.push_back(o.tile);
@@ -1133,16 +1172,15 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
     else tiles.push_back(0);  // by width, below
     p->autotuned = o.autotune ? 1 : 0;
     for (int l = 0; l < 2; ++l) {
-        std::vector<double> ph;
         int best_c = -1, best_T = 0;
         if (o.autotune) {
             double best_ms = INFINITY;
             for (size_t ci = 0; ci < cands[l].size(); ++ci)
                 for (int T : tiles) {
-                    if ((s = set_level_geom(*p, l, cands[l][ci], T, cx, cy, ph)) != VP_OK) return bail(s);
+                    if ((s = set_level_geom(*p, l, cands[l][ci], T, cx, cy)) != VP_OK) return bail(s);
                     if (!level_fits_lds(*p, l)) continue;
                     const size_t mark = p->allocs.size(), bytes0 = p->device_bytes;
-                    if ((s = build(l, ph)) != VP_OK) return bail(s);
+                    if ((s = build(l)) != VP_OK) return bail(s);
                     double ms = INFINITY;
                     s = time_level(*p, l, &ms);
                     drop_level(*p, l, mark, bytes0);
@@ -1161,7 +1199,7 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
                 // (measured faster there; at narrower widths the LDS path is as fast and its
                 // exact fixed-point windows round less), 32-cell tiles otherwise
                 const int T = tiles[0] > 0 ? tiles[0] : (fp32 && cands[l][ci].w >= 12 ? kMmaTile : 32);
-                if ((s = set_level_geom(*p, l, cands[l][ci], T, cx, cy, ph)) != VP_OK) return bail(s);
+                if ((s = set_level_geom(*p, l, cands[l][ci], T, cx, cy)) != VP_OK) return bail(s);
                 if (level_fits_lds(*p, l)) {
                     best_c = (int)ci;
                     best_T = T;
@@ -1173,10 +1211,10 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
         if (o.autotune) {
             // the interpolation's own tile: the chosen level timed again with each other tile
             for (int Ti : tiles) {
-                if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy, ph)) != VP_OK) return bail(s);
+                if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy)) != VP_OK) return bail(s);
                 if (Ti == p->lv[l].T || !set_interp_tile(p->lv[l], Ti) || !level_fits_lds(*p, l)) continue;
                 const size_t mark = p->allocs.size(), bytes0 = p->device_bytes;
-                if ((s = build(l, ph)) != VP_OK) return bail(s);
+                if ((s = build(l)) != VP_OK) return bail(s);
                 double ms = INFINITY;
                 s = time_level(*p, l, &ms);
                 drop_level(*p, l, mark, bytes0);
@@ -1188,9 +1226,9 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
                 }
             }
         }
-        if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy, ph)) != VP_OK) return bail(s);
+        if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy)) != VP_OK) return bail(s);
         if (best_Ti > 0) set_interp_tile(p->lv[l], best_Ti);
-        if ((s = build(l, ph)) != VP_OK) return bail(s);
+        if ((s = build(l)) != VP_OK) return bail(s);
     }
     if (!o.no_workspace) {
         hipError_t e = workspace_alloc(*p, p->ws, p->stream, false);

@@ -27,13 +27,19 @@ def _setup(precision, sizes, kinds="VD", seed0=40):
 def test_batch_matches_single_plans_and_oracle(precision):
     from paper_2409_11998_amd import Batch
     torch, probs, devs, plans, run, mask = _setup(precision, [300, 1200, 700, 2500, 450])
+    batch = Batch(plans, mask)
+    outs = [torch.full((P.n_tgt,), np.nan, dtype=torch.float64, device="cuda") for P in probs]
+    args = [dict(f=d["f"], jet6=d["jet6"], mu=d["mu"], mu_jet=d["mu_jet"], out=o) for d, o in zip(devs, outs)]
+    # the batch runs first: its plans' workspaces hold nothing of a single-plan evaluation yet
+    batch.eval(args, graph=False)
+    batch.stream.synchronize()
+    first = [o.cpu().numpy() for o in outs]
     single = []
     for p, d in zip(plans, devs):
         single.append(run(p, d, "VD").clone())
     torch.cuda.synchronize()
-    batch = Batch(plans, mask)
-    outs = [torch.full((P.n_tgt,), np.nan, dtype=torch.float64, device="cuda") for P in probs]
-    args = [dict(f=d["f"], jet6=d["jet6"], mu=d["mu"], mu_jet=d["mu_jet"], out=o) for d, o in zip(devs, outs)]
+    for i, (g, s1) in enumerate(zip(first, single)):
+        assert oracle.rel_linf(g, s1.cpu().numpy()) <= (1e-13 if precision == 1 else 1e-6), i
     tol = 1e-10 if precision == 1 else 1e-6
     refs = [oracle.evaluate(P, kinds="VD")["total"] for P in probs]
     for rep, graph in enumerate([False, True, True, True]):
@@ -54,6 +60,18 @@ def test_batch_matches_single_plans_and_oracle(precision):
                   "single vs oracle", oracle.rel_linf(s1.cpu().numpy(), ref))
             assert e_single <= (1e-13 if precision == 1 else 1e-6), (rep, i, e_single)
             assert e_oracle <= tol, (rep, i, e_oracle)
+    # a timed call (events between the stage kinds, no graph) gives the same results
+    batch.set_timing(True)
+    for o in outs:
+        o.fill_(np.nan)
+    batch.eval(args, graph=True)
+    t = batch.timing()
+    batch.set_timing(False)
+    print("batch stage times (ms)", t)
+    assert set(t) == set(Batch.BATCH_STAGES) and all(v >= 0 for v in t.values())
+    assert t["spread"] > 0 and t["interp"] > 0 and t["col_fft_mul"] > 0
+    for o, s1 in zip(outs, single):
+        assert oracle.rel_linf(o.cpu().numpy(), s1.cpu().numpy()) <= (1e-13 if precision == 1 else 1e-6)
     batch.close()
 
 

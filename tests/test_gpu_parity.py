@@ -85,9 +85,12 @@ def test_spread_paths_match_oracle(precision, tile):
     print("spread path precision", precision, "tile", tile, "e_inf", e, plan.info()["width"])
     assert e <= tol
     # the interpolation's values-only kernel table: fewer terms, fit as good as the
-    # spreading table's up to what the plan's arithmetic resolves
+    # spreading table's up to what the plan's arithmetic resolves (float32 plans
+    # round its coefficients to float32, about 3e-8 of the kernel's peak; the
+    # multiplier divides by the transforms of the tables as rounded, so their
+    # fit to the exponential of the semicircle is not an error of the result)
     cap = 10 if precision == 0 else 13
-    floor = 5e-10 if precision == 0 else 5e-14
+    floor = 1e-7 if precision == 0 else 5e-14
     for lv in range(2):
         w = info["width"][lv]
         assert info["spread_terms"][lv] == w + 2
