@@ -235,6 +235,9 @@ def main():
     ap.add_argument("--solve-panels", type=int, default=256, help="panels of 16 nodes in the Dirichlet-solve leg")
     ap.add_argument("--solve-triangles", type=int, default=60000, help="triangles of the Dirichlet-solve leg's mesh")
     ap.add_argument("--refine-levels", type=int, default=3)
+    ap.add_argument("--no-neumann-leg", action="store_true")
+    ap.add_argument("--neumann-sizes", type=str, default="674664,1198728,2695248",
+                    help="volume node counts of the paper-size interior Neumann leg")
     ap.add_argument("--no-serve-leg", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-max-tri", type=float, default=2e5)
@@ -342,6 +345,10 @@ def main():
         log("bench: Dirichlet solve leg, %d panels" % args.solve_panels)
         rec["solve"] = solve_leg(torch, args.solve_panels, int(args.solve_triangles * args.scale),
                                  max(1, min(args.steps, 10)))
+    if not args.no_neumann_leg:
+        log("bench: interior Neumann leg at the paper's sizes")
+        rec["neumann_paper"] = neumann_paper_leg(torch, [int(float(v) * args.scale) for v in
+                                                         args.neumann_sizes.split(",")])
     if not args.no_fp32_leg:
         log("bench: generating disk-2M workload")
         Q = config_problem(3, scale=args.scale)
@@ -547,6 +554,126 @@ def solve_leg(torch, n_pan, n_tri, steps, q=16):
                         "solve_ms": round(1e3 * el_n / steps, 3),
                         "max_abs_err_interior_vs_exact_up_to_boundary_mean":
                             float(np.max(np.abs(un - uex(tx, ty) + cmean)))}}
+
+
+def neumann_paper_leg(torch, sizes, q=16, levels=3, reps=3):
+    """The interior Neumann experiment of the paper's numerical section at its
+    sizes: the curve with r = 1, alpha_0 = 5/6, beta_3 = 1/30, alpha_5 = 1/15,
+    alpha_{6,8,10} = 1/30; u = (x-a)/((x-a)^2+(y-b)^2) + x^2/9 - y + 8 +
+    exp(-5x^2), a = 1.1, b = 1.3, so -Lap u = -(2/9 + (100x^2 - 10) exp(-5x^2));
+    g = nu . grad u.  History tolerance 1e-6, GMRES 1e-8, local terms up to
+    O(delta) with three levels of dyadic refinement of the layer parts, as
+    there; float64.  Timed from the mesh (not generated in the timed region)
+    to u at every volume node: frames at the boundary nodes, the boundary
+    plan, the Neumann solve, frames at the volume nodes, the evaluation plan,
+    the layer jets, u = V[f] + S[g] - D[u_b], and the refinement.  Also timed
+    with the plans and frames already built ("resident": the solve, the jets,
+    the evaluation and the refinement).  Error as the paper defines it, about
+    the value at a seeded node."""
+    from paper_2409_11998_amd import Plan, boundary_frame, boundary_jets, neumann_solve
+    from workloads.mesh import curve_mesh
+    from workloads.problems import StarCurve, panel_nodes
+    f64 = torch.float64
+    curve = StarCurve(r=1.0, alpha=(5 / 6, 0, 0, 0, 0, 1 / 15, 1 / 30, 0, 1 / 30, 0, 1 / 30), beta=(0, 0, 1 / 30))
+    a_, b_ = 1.1, 1.3
+
+    def u_exact(x, y):
+        return (x - a_) / ((x - a_) ** 2 + (y - b_) ** 2) + x * x / 9 - y + 8 + np.exp(-5 * x * x)
+
+    def grad_u(x, y):
+        dx, dy = x - a_, y - b_
+        r4 = (dx * dx + dy * dy) ** 2
+        return ((dy * dy - dx * dx) / r4 + 2 * x / 9 - 10 * x * np.exp(-5 * x * x), -2 * dx * dy / r4 - 1.0)
+
+    def f_jets(x, y):   # f = -Lap u and its derivatives (f depends on x only)
+        e = np.exp(-5 * x * x)
+        z = np.zeros_like(x)
+        return np.stack([-2 / 9 - (100 * x * x - 10) * e, -(300 * x - 1000 * x ** 3) * e, z,
+                         -(300 - 6000 * x * x + 10000 * x ** 4) * e, z, z])
+
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=f64, device="cuda")
+    m = 2 ** levels
+    rows = []
+    for n_nodes in sizes:
+        x, y, w, _ = curve_mesh(curve, int(round(n_nodes / 6)), 5)
+        n_pan = int(np.ceil(2.5 * np.sqrt(x.size) / q))
+        bx, by, bnx, bny, bw, _ = panel_nodes(curve, n_pan, q)
+        fx, fy, fnx, fny, fw, _ = panel_nodes(curve, n_pan * m, q)
+        gx, gy = grad_u(bx, by)
+        g = gx * bnx + gy * bny
+        gfx, gfy = grad_u(fx, fy)
+        g_fine = gfx * fnx + gfy * fny
+        # fine node (panel p, child c, point j) sits at u = -1 + (2c + 1 + x_j) / m of coarse panel p
+        xg, _ = np.polynomial.legendre.leggauss(q)
+        cc = np.arange(m)
+        uf = (-1 + (2 * cc[:, None] + 1 + xg[None, :]) / m).ravel()
+        pan_f = t(np.repeat(np.arange(n_pan), m * q)).to(torch.int32)
+        u_f = t(np.tile(uf, n_pan))
+        sx, sy, sw = t(x), t(y), t(w)
+        fs, jv = t(f_jets(x, y)[0]), t(f_jets(x, y))
+        jb = t(f_jets(bx, by))
+        dx, dy, dnx, dny, dw, dg = (t(a) for a in (bx, by, bnx, bny, bw, g))
+        ddx, ddy, ddnx, ddny, ddw, dgf = (t(a) for a in (fx, fy, fnx, fny, fw, g_fine))
+        opts = dict(tol=1e-6, precision=1, kinds=7, order_v=2, order_s=2, order_d=2)
+        torch.cuda.synchronize()
+        st = {}
+
+        def build():
+            frb = boundary_frame(dx, dy, q, dx, dy)
+            geom = dict(r=torch.zeros_like(dx), nx=frb["nx"], ny=frb["ny"], kappa=frb["kappa"],
+                        gamma3=frb["gamma3"], gamma4=frb["gamma4"],
+                        sgn=torch.ones(dx.numel(), dtype=torch.int8, device="cuda"))
+            pb = Plan(sx, sy, sw, dx, dy, dnx, dny, dw, dx, dy, geom, **opts)
+            frv = boundary_frame(dx, dy, q, sx, sy)
+            gv = {k: frv[k] for k in ("r", "nx", "ny", "kappa", "gamma3", "gamma4", "sgn")}
+            pv = Plan(sx, sy, sw, dx, dy, dnx, dny, dw, sx, sy, gv, **opts)
+            pv.refine_attach(levels, ddx, ddy, ddnx, ddny, ddw, sx, sy)
+            return frb, pb, frv, pv
+
+        def solve(frb, pb, frv, pv):
+            ub, st["its"], st["res"] = neumann_solve(pb, q, dx, dy, dw, frb["pan"], frb["u"], dg, f=fs, jet6=jb,
+                                                     tol=1e-8)
+            mub = -ub
+            sj = boundary_jets(dx, dy, q, dg, frv["pan"], frv["u"], 2)
+            mj = boundary_jets(dx, dy, q, mub, frv["pan"], frv["u"], 4)
+            out = pv.eval(f=fs, jet6=jv, sigma=dg, sigma_jet=sj, mu=mub, mu_jet=mj)
+            mu_fine = boundary_jets(dx, dy, q, mub, pan_f, u_f, 0)[0].contiguous()
+            pv.layer_refine(out, sigma_jet=sj, fine_sigma=dgf, mu_jet=mj, fine_mu=mu_fine)
+            return out
+
+        # end to end (from the mesh): frames, plans, solve, evaluation, refinement
+        t0 = time.perf_counter()
+        frb, pb, frv, pv = build()
+        out = solve(frb, pb, frv, pv)
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t0
+        for _ in range(reps):   # resident: plans and frames built
+            out = solve(frb, pb, frv, pv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = solve(frb, pb, frv, pv)
+        torch.cuda.synchronize()
+        t_res = (time.perf_counter() - t0) / reps
+        info = pv.info()
+        pb.close()
+        pv.close()
+        uc = out.cpu().numpy()
+        ue = u_exact(x, y)
+        c = int(np.random.default_rng(7).integers(0, x.size))
+        du = (uc - uc[c]) - (ue - ue[c])
+        e_inf = float(np.max(np.abs(du)) / np.max(np.abs(ue - ue[c])))
+        e_2 = float(np.linalg.norm(du) / np.linalg.norm(ue - ue[c]))
+        rows.append({"n_volume_nodes": int(x.size), "n_boundary_nodes": int(bx.size), "n_fine_boundary": int(fx.size),
+                     "delta1": info["delta1"], "fine_grid": list(info["fine"]), "gmres_products": st["its"],
+                     "rel_residual": st["res"], "end_to_end_s": round(t_total, 4),
+                     "end_to_end_pts_per_s": round(x.size / t_total, 1), "resident_ms": round(1e3 * t_res, 3),
+                     "resident_pts_per_s": round(x.size / t_res, 1), "e_inf": e_inf, "e_2": e_2})
+        log("bench: Neumann (paper) N_V=%d end-to-end %.3f s, resident %.2f ms, e_inf %.2e" %
+            (x.size, t_total, 1e3 * t_res, e_inf))
+    return {"workload": "interior Neumann problem of the paper's numerical section (its curve, u, f, tolerances, "
+                        "three refinement levels), float64", "rows": rows,
+            "paper_one_core_pts_per_s": {"674664": 8.3e5, "1198728": 8.7e5, "2695248": 8.4e5}}
 
 
 def refine_leg(torch, P, levels, steps):
