@@ -322,7 +322,8 @@ vp_status vp_volume_jets(int64_t n_tri, const double* x, const double* y, const 
  *   where residuals of data with every frequency stall above 1e-10.  Remedies: coarser panels (about sqrt(N) boundary nodes for N
  *   volume nodes keeps chi small), a smaller delta_1, or order_d <= 2.
  * Runs on the plan's stream and synchronizes it before returning.  Scratch
- * of (restart + 11) n doubles is allocated for the call.  VP_ERR_ARG for a
+ * of (restart + 11) n doubles is allocated by the first solve on the plan and
+ * kept with it (grown if a later solve needs more, freed by vp_destroy).  VP_ERR_ARG for a
  * plan without D, or whose nodes or targets are not the n_pan*q panel nodes,
  * for only one of f_src and jet6, or for a source on a plan without V or
  * volume nodes; VP_ERR_GEOMETRY past the resolution limit;
@@ -362,8 +363,8 @@ vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double*
  *   jets come from its panel interpolant.  The interior solution is then
  *   vp_eval with f, sigma = g and mu = -ub on a plan with interior targets.
  *
- * Both synchronize the plan's stream, allocate (restart + 11) n doubles of
- * scratch, count products and accept residuals as vp_dirichlet_solve does, and
+ * Both synchronize the plan's stream, use the plan's solve scratch as
+ * vp_dirichlet_solve does, count products and accept residuals as vp_dirichlet_solve does, and
  * return VP_ERR_ARG / VP_ERR_GEOMETRY (resolution limit 2) / VP_ERR_TOL as
  * it does (and VP_ERR_ARG for a NULL bnd_w, or a Neumann plan without S). */
 vp_status vp_exterior_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,

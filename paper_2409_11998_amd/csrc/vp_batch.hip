@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kThreads) void kg_zero(const InstDesc* __restrict__
         }
         if (l == 0 && u == 0) {  // the instance's accumulators, once
             if (threadIdx.x < kDcParts) inst[i].dc[threadIdx.x] = 0.0;
-            if (threadIdx.x < 2) inst[i].smax[threadIdx.x] = 0ull;
+            if (threadIdx.x < kSmaxEntries) inst[i].smax[threadIdx.x] = 0ull;
         }
     }
 }
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void kg_strengths(const InstDesc* __restr
         const InstDesc& I = inst[i];
         const CallDesc& K = call[i];
         dev::dev_strengths<R>(I.n_src, I.n_bnd, K.f, K.sigma, K.mu, I.w, I.nx, I.ny, (R*)I.str,
-                              sizeof(R) == 4 ? I.dc : nullptr, sizeof(R) == 4 ? I.smax : nullptr, u);
+                              sizeof(R) == 4 ? I.dc : nullptr, I.smax, u);
     }
 }
 
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void kg_spread(const InstDesc* __restrict
         } else {  // double-layer channel ch: mu nu_ch w with the kernel itself
             const R* s = (const R*)I.str + (I.n_src + I.n_bnd) + (ch - 1) * I.n_bnd - I.n_src;
             dev::dev_spread<R, W>(smem_raw, g, vol_view<R>(D), bnd_view<R>(D), s, I.n_src, I.n_bnd,
-                                  (R*)D.dgrid[ch - 1], 0, 1, 0, D.horner, I.smax + 1, D.sp_units[u]);
+                                  (R*)D.dgrid[ch - 1], 0, 1, 0, D.horner, I.smax + kDcParts, D.sp_units[u]);
         }
         __syncthreads();
     }

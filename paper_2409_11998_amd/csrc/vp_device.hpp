@@ -258,8 +258,9 @@ __device__ void dev_strengths(int64_t n_src, int64_t n_bnd, const double* __rest
             b = fmax(b, red[2][k]);
         }
         if (dc && t != 0.0) atomicAdd(dc + (unit % kDcParts), t);
-        if (smax && a > 0.0) atomicMax(smax, (unsigned long long)__double_as_longlong(a));
-        if (smax && b > 0.0) atomicMax(smax + 1, (unsigned long long)__double_as_longlong(b));
+        if (smax && a > 0.0) atomicMax(smax + (unit % kDcParts), (unsigned long long)__double_as_longlong(a));
+        if (smax && b > 0.0)
+            atomicMax(smax + kDcParts + (unit % kDcParts), (unsigned long long)__double_as_longlong(b));
     }
     __syncthreads();
 }
@@ -426,21 +427,21 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Window cell type and conversions (see above).
-template <typename R> struct FixedPoint;
-template <> struct FixedPoint<float> {
+// Window cells: 64-bit fixed point (exact, order-independent integer sums,
+// ds_add_u64 at 6.5 cycles) or float64 (ds_add_f64, 8.5 cycles).
+struct CellFixed {
     using T = unsigned long long;
     static constexpr bool kScaled = true;
     static constexpr double kRange = 562949953421312.0;  // 2^49
     // round(v) via the 1.5 2^52 shift: exact for |v| < 2^51
-    __device__ static T enc(float v)
+    __device__ static T enc(double v)
     {
-        const double t = (double)v + 6755399441055744.0;
+        const double t = v + 6755399441055744.0;
         return (T)(__double_as_longlong(t) - 0x4338000000000000LL);
     }
     __device__ static double dec(T a, double inv_q) { return (double)(long long)a * inv_q; }
 };
-template <> struct FixedPoint<double> {
+struct CellF64 {
     using T = double;
     static constexpr bool kScaled = false;
     static constexpr double kRange = 1.0;
@@ -448,13 +449,22 @@ template <> struct FixedPoint<double> {
     __device__ static double dec(T a, double) { return a; }
 };
 
-template <typename R, int W>
-__device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const RecView<R>& vol, const RecView<R>& bnd,
-                           const R* __restrict__ str, int64_t n_src, int64_t n_bnd, R* __restrict__ grid,
-                           int use_vol, int use_bnd, int use_d, const double* __restrict__ coef,
-                           const unsigned long long* __restrict__ smax, const WorkUnit unit)
+// max over the kDcParts partial maxima at smax (bit patterns of non-negative doubles)
+__device__ __forceinline__ double smax_bound(const unsigned long long* __restrict__ smax)
 {
-    using FP = FixedPoint<R>;
+    const int lane = threadIdx.x & 63;
+    double m = lane < kDcParts ? __longlong_as_double((long long)smax[lane]) : 0.0;
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    return m;
+}
+
+template <typename R, int W, typename FP>
+__device__ void dev_spread_cells(unsigned char* smem_raw, const LevelGeom& g, const RecView<R>& vol,
+                                 const RecView<R>& bnd, const R* __restrict__ str, int64_t n_src, int64_t n_bnd,
+                                 R* __restrict__ grid, int use_vol, int use_bnd, int use_d,
+                                 const double* __restrict__ coef, const unsigned long long* __restrict__ smax,
+                                 const WorkUnit unit)
+{
     using A = typename FP::T;
     static_assert(sizeof(A) == 8, "spread_lds_layout sizes the window for 8-byte cells");
     using SS = SpreadShape<R>;
@@ -473,12 +483,14 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
     const int nv = use_vol ? unit.a1 - unit.a0 : 0;
     const int nbd = use_bnd ? unit.b1 - unit.b0 : 0;
     if (nv == 0 && nbd == 0) return;  // nothing lands in this unit (uniform across the workgroup)
-    // scale of this unit's fixed-point window (float32 plans)
+    // scale of this unit's fixed-point window: the strength bound (plus the
+    // derivative taps' when the unit spreads the double layer through them) times
+    // the most records whose supports share one window cell
     R q = R(1);
     double inv_q = 1.0;
     if constexpr (FP::kScaled) {
-        const double cmax = __longlong_as_double((long long)smax[0]) +
-                            (use_d ? __longlong_as_double((long long)smax[1]) * g.dmax : 0.0);
+        const bool dl = use_d && nbd > 0;
+        const double cmax = smax_bound(smax) + (dl ? smax_bound(smax + kDcParts) * g.dmax : 0.0);
         const double bound = 1.01 * (double)unit.cover * cmax;
         if (!(bound > 0.0)) return;  // every contribution is zero
         q = (R)(FP::kRange / bound);
@@ -657,6 +669,30 @@ __device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const Re
             if (a != A(0)) unsafeAtomicAdd(grid + (size_t)gy * F + gx, (R)FP::dec(a, inv_q));
         }
     }
+}
+
+// Window cells of a unit: float32 plans always use 64-bit fixed point.
+// Float64 plans use it too for units that spread no double-layer derivative
+// taps (the strengths alone bound their contributions, so 2^49 / (cover x
+// bound) resolves each cell to ~1e-15 of the largest strength per record);
+// units with derivative taps keep float64 cells, whose contributions the
+// derivative bound would otherwise coarsen ~10^4-fold.
+template <typename R, int W>
+__device__ void dev_spread(unsigned char* smem_raw, const LevelGeom& g, const RecView<R>& vol, const RecView<R>& bnd,
+                           const R* __restrict__ str, int64_t n_src, int64_t n_bnd, R* __restrict__ grid,
+                           int use_vol, int use_bnd, int use_d, const double* __restrict__ coef,
+                           const unsigned long long* __restrict__ smax, const WorkUnit unit)
+{
+    if constexpr (sizeof(R) == 8) {
+        const bool dl = use_d && use_bnd && unit.b1 > unit.b0;
+        if (dl || !smax) {
+            dev_spread_cells<R, W, CellF64>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d,
+                                            coef, smax, unit);
+            return;
+        }
+    }
+    dev_spread_cells<R, W, CellFixed>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d, coef,
+                                      smax, unit);
 }
 
 // ---------------------------------------------------------------------------

@@ -15,6 +15,9 @@ constexpr int kWMax = 16;        // largest spreading width (grid cells per dime
 constexpr int kWMin = 4;         // smallest spreading width
 constexpr int kThreads = 256;    // threads per workgroup for grid kernels
 constexpr int kDcParts = 64;     // partial sums of the zero-frequency term (one wavefront reads them)
+// Strength maxima: kDcParts partial maxima per quantity (|strength|, |mu nu w|_1),
+// so the strengths units' atomic maxima spread over as many addresses.
+constexpr int kSmaxEntries = 2 * kDcParts;
 // Terms of the per-tap polynomials of the spreading kernel (degree + 1).  Each
 // tap's piece of the kernel over one grid cell is fitted in u = 2d - 1 by
 // Chebyshev interpolation (converted to monomial form) with w + 2 terms: fit
@@ -129,7 +132,7 @@ struct Workspace {
     void* hist[2] = {nullptr, nullptr};   // R [n_tgt] history value at each target
     void* str = nullptr;                  // R [n_src + n_bnd (+ 2 n_bnd)] strengths (+ mu nu wG)
     double* dc = nullptr;                 // [kDcParts] float64 partial sums of the spread strengths
-    unsigned long long* smax = nullptr;   // [2] bit patterns of max |strength| and max |mu nu wG|_1
+    unsigned long long* smax = nullptr;   // [2][kDcParts] partial maxima: bit patterns of |strength|, |mu nu wG|_1
     void* block = nullptr;                // single allocation holding all of the above
     size_t bytes = 0;
 };
@@ -198,6 +201,10 @@ struct Plan {
     hipEvent_t fork[2]{};
     bool side_made = false;
     Refinement ref;               // dyadic refinement of the local layer parts (optional)
+    // scratch of the boundary integral solves (vp_solve.hip): allocated by the first
+    // solve on the plan, grown when a later one needs more, freed with the plan
+    void* solve_ws = nullptr;
+    size_t solve_ws_bytes = 0;
 };
 
 // Free a plan's refinement data (vp_refine.hip).

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kThreads) void k_zero(R* __restrict__ a, int64_t na
         dev_zero<R>(d, ncd, i);
     }
     if (i < kDcParts) dc[i] = 0.0;
-    if (i < 2) smax[i] = 0ull;
+    if (i < kSmaxEntries) smax[i] = 0ull;
 }
 
 template <typename R, int W>
@@ -193,10 +193,9 @@ hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, 
     if (p.precision == VP_FP32)
         hipLaunchKernelGGL(k_strengths<float>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
                            p.d_w, p.d_nx, p.d_ny, (float*)ws.str, ws.dc, ws.smax);
-    else  // the zero-frequency sum and the strength maxima are used by the float32 path only
+    else  // the zero-frequency sum is used by the float32 path only; the maxima scale fixed-point windows
         hipLaunchKernelGGL(k_strengths<double>, dim3(blocks), dim3(kThreads), 0, st, p.n_src, p.n_bnd, f, sigma, mu,
-                           p.d_w, p.d_nx, p.d_ny, (double*)ws.str, (double*)nullptr,
-                           (unsigned long long*)nullptr);
+                           p.d_w, p.d_nx, p.d_ny, (double*)ws.str, (double*)nullptr, ws.smax);
     return hipGetLastError();
 }
 
@@ -216,7 +215,7 @@ hipError_t launch_zero(const Plan& p, const Workspace& ws, hipStream_t st)
     const int64_t n1 = ws.grid[1] ? (int64_t)p.lv[1].F * p.lv[1].F : 0;
     const int dl = dip_level(p, ws);
     const int64_t nd = dl >= 0 ? (int64_t)p.lv[dl].F * p.lv[dl].F : 0;
-    const unsigned blocks = grid_for(std::max<int64_t>({n0, n1, nd, kDcParts}));
+    const unsigned blocks = grid_for(std::max<int64_t>({n0, n1, nd, (int64_t)kSmaxEntries}));
     if (p.precision == VP_FP32)
         hipLaunchKernelGGL(k_zero<float>, dim3(blocks), dim3(kThreads), 0, st, (float*)ws.grid[0], n0,
                            (float*)ws.grid[1], n1, (float*)(dl >= 0 ? ws.dgrid[0] : nullptr),
@@ -285,7 +284,7 @@ static void spread_level(const Plan& p, const Workspace& ws, hipStream_t st, int
     if (!dip) return;
     const int64_t n_all = p.n_src + p.n_bnd;
     for (int c = 0; c < 2; ++c)
-        spread_launch<R, W>(p, st, l, lds, str + n_all + c * p.n_bnd - p.n_src, smax ? smax + 1 : nullptr,
+        spread_launch<R, W>(p, st, l, lds, str + n_all + c * p.n_bnd - p.n_src, smax ? smax + kDcParts : nullptr,
                             (R*)ws.dgrid[c], 0, 1, 0);
 }
 

@@ -213,6 +213,7 @@ void free_plan(vp_plan_s* p)
     p->allocs.clear();
     refinement_free(p->ref);
     workspace_free(p->ws, nullptr, false);
+    if (p->solve_ws) hipFree(p->solve_ws);
     if (p->ev_made)
         for (auto& e : p->ev) hipEventDestroy(e);
     if (p->side_made) {
@@ -684,7 +685,7 @@ vp_status time_level(Plan& p, int l, double* ms)
     const size_t o_dc = off;
     off += align256(kDcParts * sizeof(double));
     const size_t o_smax = off;
-    off += 256;
+    off += align256(kSmaxEntries * sizeof(unsigned long long));
     size_t o_dip[4] = {0, 0, 0, 0};
     if (g.dip)
         for (int c = 0; c < 2; ++c) {
@@ -775,7 +776,7 @@ static size_t workspace_layout(const Plan& p, Workspace* ws, unsigned char* base
     take(ws ? &dcp : nullptr, kDcParts * sizeof(double));
     if (ws) ws->dc = (double*)dcp;
     void* smp = nullptr;
-    take(ws ? &smp : nullptr, 2 * sizeof(unsigned long long));
+    take(ws ? &smp : nullptr, kSmaxEntries * sizeof(unsigned long long));
     if (ws) ws->smax = (unsigned long long*)smp;
     return off;
 }

@@ -308,17 +308,36 @@ vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
     const int m = restart;
     Solver S{plan, n_pan, n, q, bnd_x, bnd_y, u, pan, plan->stream};
     S.bw = bw;
-    double* V = nullptr;  // [m+1][n] Krylov basis
-    double* w = nullptr;  // [n]
-    double* b = nullptr;  // [n] right-hand side
-    hipError_t e = hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&w, (size_t)n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&b, (size_t)n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&S.jets, (size_t)5 * n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&S.gws, (size_t)3 * n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&S.part, (size_t)(kMaxRestart + 2) * kDotBlocks * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&S.hd, (kMaxRestart + 2) * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&S.tmp, (kMaxRestart + 1) * sizeof(double));
+    // scratch in one block kept on the plan (allocated by the first solve, grown if needed)
+    const size_t parts[8] = {(size_t)(m + 1) * n, (size_t)n, (size_t)n, (size_t)5 * n, (size_t)3 * n,
+                             (size_t)(kMaxRestart + 2) * kDotBlocks, (size_t)(kMaxRestart + 2),
+                             (size_t)(kMaxRestart + 1)};
+    size_t need = 0;
+    for (size_t c : parts) need += (c * sizeof(double) + 255) & ~(size_t)255;
+    hipError_t e = hipSuccess;
+    if (plan->solve_ws_bytes < need) {
+        if (plan->solve_ws) (void)hipFree(plan->solve_ws);
+        plan->solve_ws = nullptr;
+        plan->solve_ws_bytes = 0;
+        e = hipMalloc(&plan->solve_ws, need);
+        if (e == hipSuccess) plan->solve_ws_bytes = need;
+    }
+    double* ptr[8] = {};
+    if (e == hipSuccess) {
+        unsigned char* q = (unsigned char*)plan->solve_ws;
+        for (int k = 0; k < 8; ++k) {
+            ptr[k] = (double*)q;
+            q += (parts[k] * sizeof(double) + 255) & ~(size_t)255;
+        }
+    }
+    double* V = ptr[0];  // [m+1][n] Krylov basis
+    double* w = ptr[1];  // [n]
+    double* b = ptr[2];  // [n] right-hand side
+    S.jets = ptr[3];
+    S.gws = ptr[4];
+    S.part = ptr[5];
+    S.hd = ptr[6];
+    S.tmp = ptr[7];
     vp_status s = e == hipSuccess ? VP_OK : set_error(VP_ERR_OOM, "solve workspace");
     if (s == VP_OK && plan->loc.order_d >= 3) {   // the resolution guard (header)
         const double chi_max = bw ? kChiPlus : kChiInterior;
@@ -411,14 +430,6 @@ vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
         e = hipStreamSynchronize(plan->stream);
         if (e != hipSuccess) s = set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
     }
-    if (V) (void)hipFree(V);
-    if (w) (void)hipFree(w);
-    if (b) (void)hipFree(b);
-    if (S.jets) (void)hipFree(S.jets);
-    if (S.gws) (void)hipFree(S.gws);
-    if (S.part) (void)hipFree(S.part);
-    if (S.hd) (void)hipFree(S.hd);
-    if (S.tmp) (void)hipFree(S.tmp);
     if (iters) *iters = it;
     if (resid) *resid = rel;
     if (s == VP_OK && !done) s = set_error(VP_ERR_TOL, "GMRES did not reach the tolerance within max_iter products");
