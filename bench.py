@@ -241,8 +241,10 @@ def main():
     ap.add_argument("--no-serve-leg", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-max-tri", type=float, default=2e5)
-    ap.add_argument("--batch-tune-sample", type=int, default=8,
-                    help="instances timed by the autotuner to choose the batch's spreading widths")
+    ap.add_argument("--batch-tune-sample", type=int, default=3,
+                    help="instances per width class timed by the autotuner to choose its spreading widths")
+    ap.add_argument("--batch-classes", type=int, default=4,
+                    help="width classes of the batch (instances cut by size, one width pair per class)")
     ap.add_argument("--serve-meshes", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--serve-loads", type=str, default="0.2,0.5,0.8,0.95",
@@ -370,7 +372,8 @@ def main():
         r32.pop("got")
     if batch_probs:
         log("bench: batch leg, %d instances, %d targets" % (len(batch_probs), sum(P.n_tgt for P in batch_probs)))
-        rec["batch"] = batch_leg(torch, batch_probs, args.steps, args.warmup, args.batch_tune_sample)
+        rec["batch"] = batch_leg(torch, batch_probs, args.steps, args.warmup, args.batch_tune_sample,
+                                 args.batch_classes)
     if serve_probs:
         log("bench: serving leg, %d meshes" % len(serve_probs))
         loads = [float(x) for x in args.serve_loads.split(",")]
@@ -713,14 +716,14 @@ def refine_leg(torch, P, levels, steps):
             "max_abs_correction_far_from_boundary": float(np.max(np.abs(corr[far]))) if far.size else 0.0}
 
 
-def batch_leg(torch, probs, steps, warmup, tune_sample):
+def batch_leg(torch, probs, steps, warmup, tune_sample, classes):
     """Float32 V+D on many star instances: one persistent launch per stage (hipGraph)
     against the same plans launched one after another."""
     from paper_2409_11998_amd import Batch
     from workloads.device import make_batch_plans, run, to_device
     devs = [to_device(P) for P in probs]
     t0 = time.perf_counter()
-    plans = make_batch_plans(devs, autotune_sample=tune_sample, tol=1e-6, precision=0, kinds=5)
+    plans = make_batch_plans(devs, autotune_sample=tune_sample, classes=classes, tol=1e-6, precision=0, kinds=5)
     plan_s = time.perf_counter() - t0
     batch = Batch(plans, 5)
     outs = [torch.empty(P.n_tgt, dtype=torch.float64, device="cuda") for P in probs]
@@ -774,7 +777,14 @@ def batch_leg(torch, probs, steps, warmup, tune_sample):
     dev_single = max(float(np.max(np.abs(g - s.cpu().numpy())) / max(np.max(np.abs(s.cpu().numpy())), 1e-300))
                      for g, s in zip(got, seq_outs))
     sizes = [P.n_src for P in probs]
-    widths = list(plans[0].info()["width"])
+    wc = {}
+    for P, p_ in zip(probs, plans):
+        inf = p_.info()
+        c = wc.setdefault((tuple(inf["width"]), tuple(inf["tile"])), [0, P.n_src, P.n_src])
+        c[0] += 1
+        c[1], c[2] = min(c[1], P.n_src), max(c[2], P.n_src)
+    widths = [{"width": list(k[0]), "tile": list(k[1]), "instances": v[0], "nodes": [int(v[1]), int(v[2])]}
+              for k, v in sorted(wc.items())]
     grids = sorted({tuple(p.info()["fine"]) for p in plans})
     batch.close()
     for p in plans:
@@ -788,7 +798,8 @@ def batch_leg(torch, probs, steps, warmup, tune_sample):
             "stages_ms": {k: round(v, 4) for k, v in stages.items()},
             "steps_frac_of_hbm": {k: round(v, 4) for k, v in stage_frac.items()},
             "grid_cells_total": cells,
-            "spread_width": widths, "fine_grids": [list(g) for g in grids], "autotune_sample": tune_sample,
+            "width_classes": widths, "fine_grids": [list(g) for g in grids],
+            "autotune_sample_per_class": tune_sample,
             "plan_s": round(plan_s, 2)}
 
 

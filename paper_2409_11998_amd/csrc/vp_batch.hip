@@ -1,5 +1,5 @@
 // Group execution: several (plan, workspace, densities) instances evaluated
-// together by one persistent kernel per stage.  Used by the batched API
+// together by one kernel per stage over a table of all their units.  Used by the batched API
 // (vp_batch_*: a fixed group, optionally replayed as a hipGraph) and by the
 // serving loop (a group per admission of queued requests).
 //
@@ -7,8 +7,8 @@
 // level) -- or per instance for the node and target stages -- holding a unit
 // count: tiles/units for spreading and interpolation, rows and columns for
 // the FFT passes, chunks for zeroing, strengths and the local part.  Segments
-// are padded to multiples of 8 items, the persistent workgroups take items
-// round-robin, and an item decodes to (instance, level, unit) by binary search
+// are padded to multiples of 8 items, each item is one workgroup, and an
+// item decodes to (instance, level, unit) by binary search
 // over the segment starts and the XCD-aware unit order within its segment,
 // so every XCD works on contiguous units of each instance.  Spreading and
 // interpolation are templated on the spreading width: one launch per distinct
@@ -55,16 +55,31 @@ template <typename R> __device__ inline const typename dev::TapT<R>::T* interp_t
     else return d.horner_i;
 }
 
+// Descriptors (instances, levels, calls, segments) do not change while a
+// kernel runs: they are read through the constant address space, which makes
+// their loads scalar and lets the compiler treat the pointers they hold as
+// global memory (global rather than flat loads, stores and atomics; uniform
+// reads of tables such as the tap coefficients then also become scalar).
+// (The host pass only type-checks device code and has no such address space.)
+template <typename T> __device__ __forceinline__ T desc(const T* p, int64_t k)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) T*)p)[k];
+#else
+    return p[k];
+#endif
+}
+
 // Item `it` of a stage -> (instance, level, unit); false for padding items.
 __device__ __forceinline__ bool decode(const StageTab& t, int it, int& inst, int& level, int& unit)
 {
     int lo = 0, hi = t.nseg - 1;
     while (lo < hi) {  // last segment with begin <= it
         const int mid = (lo + hi + 1) >> 1;
-        if (t.seg[mid].begin <= it) lo = mid;
+        if (desc(t.seg, mid).begin <= it) lo = mid;
         else hi = mid - 1;
     }
-    const Seg s = t.seg[lo];
+    const Seg s = desc(t.seg, lo);
     const int j = it - s.begin;
     const int padded = (s.count + 7) & ~7;
     if (j < 0 || j >= padded) return false;
@@ -80,23 +95,23 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void kg_zero(const InstDesc* __restrict__ inst, const LevelDesc* __restrict__ lv,
                                                     StageTab t)
 {
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        const LevelDesc& D = lv[2 * i + l];
-        const int64_t n = (int64_t)D.g.F * D.g.F;
-        const int64_t i0 = (int64_t)u * kZeroChunk;
-        for (int64_t k = i0 + threadIdx.x; k < i0 + kZeroChunk; k += blockDim.x) {
-            dev::dev_zero<R>((R*)D.grid, n, k);
-            if (D.dgrid[0]) {
-                dev::dev_zero<R>((R*)D.dgrid[0], n, k);
-                dev::dev_zero<R>((R*)D.dgrid[1], n, k);
-            }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    const LevelDesc D = desc(lv, 2 * i + l);
+    const int64_t n = (int64_t)D.g.F * D.g.F;
+    const int64_t i0 = (int64_t)u * kZeroChunk;
+    for (int64_t k = i0 + threadIdx.x; k < i0 + kZeroChunk; k += blockDim.x) {
+        dev::dev_zero<R>((R*)D.grid, n, k);
+        if (D.dgrid[0]) {
+            dev::dev_zero<R>((R*)D.dgrid[0], n, k);
+            dev::dev_zero<R>((R*)D.dgrid[1], n, k);
         }
-        if (l == 0 && u == 0) {  // the instance's accumulators, once
-            if (threadIdx.x < kDcParts) inst[i].dc[threadIdx.x] = 0.0;
-            if (threadIdx.x < kSmaxEntries) inst[i].smax[threadIdx.x] = 0ull;
-        }
+    }
+    if (l == 0 && u == 0) {  // the instance's accumulators, once
+        const InstDesc I = desc(inst, i);
+        if (threadIdx.x < kDcParts) I.dc[threadIdx.x] = 0.0;
+        if (threadIdx.x < kSmaxEntries) I.smax[threadIdx.x] = 0ull;
     }
 }
 
@@ -104,14 +119,13 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void kg_strengths(const InstDesc* __restrict__ inst,
                                                          const CallDesc* __restrict__ call, StageTab t)
 {
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        const InstDesc& I = inst[i];
-        const CallDesc& K = call[i];
-        dev::dev_strengths<R>(I.n_src, I.n_bnd, K.f, K.sigma, K.mu, I.w, I.nx, I.ny, (R*)I.str,
-                              sizeof(R) == 4 ? I.dc : nullptr, I.smax, u);
-    }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    const InstDesc I = desc(inst, i);
+    const CallDesc K = desc(call, i);
+    dev::dev_strengths<R>(I.n_src, I.n_bnd, K.f, K.sigma, K.mu, I.w, I.nx, I.ny, (R*)I.str,
+                          sizeof(R) == 4 ? I.dc : nullptr, I.smax, u);
 }
 
 template <typename R, int W>
@@ -120,27 +134,25 @@ __global__ __launch_bounds__(kThreads) void kg_spread(const InstDesc* __restrict
                                                       const CallDesc* __restrict__ call, StageTab t)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        const InstDesc& I = inst[i];
-        const CallDesc& K = call[i];
-        const int ch = l >> 1;
-        const LevelDesc& D = lv[2 * i + (l & 1)];
-        const LevelGeom g = D.g;
-        if (ch == 0) {
-            const int use_vol = K.f != nullptr && I.has_vol;
-            const int use_bnd = (K.sigma != nullptr || K.mu != nullptr) && I.has_bnd;
-            const int use_d = K.mu != nullptr && !D.dgrid[0];
-            dev::dev_spread<R, W>(smem_raw, g, vol_view<R>(D), bnd_view<R>(D), (const R*)I.str, I.n_src, I.n_bnd,
-                                  (R*)D.grid, use_vol, use_bnd, use_d, D.horner, I.smax, D.sp_units[u]);
-        } else {  // double-layer channel ch: mu nu_ch w with the kernel itself
-            const R* s = (const R*)I.str + (I.n_src + I.n_bnd) + (ch - 1) * I.n_bnd - I.n_src;
-            dev::dev_spread<R, W>(smem_raw, g, vol_view<R>(D), bnd_view<R>(D), s, I.n_src, I.n_bnd,
-                                  (R*)D.dgrid[ch - 1], 0, 1, 0, D.horner, I.smax + kDcParts, D.sp_units[u]);
-        }
-        __syncthreads();
-    }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    const InstDesc I = desc(inst, i);
+    const CallDesc K = desc(call, i);
+    const int ch = l >> 1;
+    const LevelDesc D = desc(lv, 2 * i + (l & 1));
+    // channel 0: the node strengths (volume, and boundary through the kernel
+    // derivative unless the level has double-layer channels); channel ch >= 1:
+    // mu nu_ch w on the boundary with the kernel itself.  One call site keeps
+    // the register allocation of a single spread.
+    const bool chan = ch != 0;
+    const R* s = (const R*)I.str + (chan ? (I.n_src + I.n_bnd) + (ch - 1) * I.n_bnd - I.n_src : 0);
+    R* grid = (R*)(ch == 0 ? D.grid : ch == 1 ? D.dgrid[0] : D.dgrid[1]);  // no dynamic index: stays scalar
+    const int use_vol = !chan && K.f != nullptr && I.has_vol;
+    const int use_bnd = chan || ((K.sigma != nullptr || K.mu != nullptr) && I.has_bnd);
+    const int use_d = !chan && K.mu != nullptr && !D.dgrid[0];
+    dev::dev_spread<R, W>(smem_raw, D.g, vol_view<R>(D), bnd_view<R>(D), s, I.n_src, I.n_bnd, grid, use_vol, use_bnd,
+                          use_d, D.horner, chan ? I.smax + kDcParts : I.smax, D.sp_units[u]);
 }
 
 // Matrix-core spread of float32 levels: an item is four work units, one per wavefront.
@@ -150,47 +162,38 @@ __global__ __launch_bounds__(kThreads) void kg_spread_mma(const InstDesc* __rest
                                                           const CallDesc* __restrict__ call, StageTab t)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        const InstDesc& I = inst[i];
-        const CallDesc& K = call[i];
-        const int ch = l >> 1;
-        const LevelDesc& D = lv[2 * i + (l & 1)];
-        const int unit = u * (kThreads / 64) + (threadIdx.x >> 6);
-        if (unit < D.n_sp_units) {
-            if (ch == 0) {
-                const int use_vol = K.f != nullptr && I.has_vol;
-                const int use_bnd = (K.sigma != nullptr || K.mu != nullptr) && I.has_bnd;
-                const int use_d = K.mu != nullptr && !D.dgrid[0];
-                dev::dev_spread_mma<W>(smem_raw, D.g, vol_view<float>(D), bnd_view<float>(D), (const float*)I.str,
-                                       I.n_src, I.n_bnd, (float*)D.grid, use_vol, use_bnd, use_d, D.horner,
-                                       D.sp_units[unit]);
-            } else {  // double-layer channel ch: mu nu_ch w with the kernel itself
-                const float* s = (const float*)I.str + (I.n_src + I.n_bnd) + (ch - 1) * I.n_bnd - I.n_src;
-                dev::dev_spread_mma<W>(smem_raw, D.g, vol_view<float>(D), bnd_view<float>(D), s, I.n_src, I.n_bnd,
-                                       (float*)D.dgrid[ch - 1], 0, 1, 0, D.horner, D.sp_units[unit]);
-            }
-        }
-        __syncthreads();  // LDS reuse by the next item
-    }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    const InstDesc I = desc(inst, i);
+    const CallDesc K = desc(call, i);
+    const int ch = l >> 1;
+    const LevelDesc D = desc(lv, 2 * i + (l & 1));
+    const int unit = u * (kThreads / 64) + (threadIdx.x >> 6);
+    if (unit >= D.n_sp_units) return;  // no barrier follows: each wavefront spreads its own unit
+    const bool chan = ch != 0;  // as in kg_spread
+    const float* s = (const float*)I.str + (chan ? (I.n_src + I.n_bnd) + (ch - 1) * I.n_bnd - I.n_src : 0);
+    float* grid = (float*)(ch == 0 ? D.grid : ch == 1 ? D.dgrid[0] : D.dgrid[1]);
+    const int use_vol = !chan && K.f != nullptr && I.has_vol;
+    const int use_bnd = chan || ((K.sigma != nullptr || K.mu != nullptr) && I.has_bnd);
+    const int use_d = !chan && K.mu != nullptr && !D.dgrid[0];
+    dev::dev_spread_mma<W>(smem_raw, D.g, vol_view<float>(D), bnd_view<float>(D), s, I.n_src, I.n_bnd, grid, use_vol,
+                           use_bnd, use_d, D.horner, D.sp_units[unit]);
 }
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void kg_row_r2c(const LevelDesc* __restrict__ lv, StageTab t)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        const int ch = l >> 1;
-        const LevelDesc& D = lv[2 * i + (l & 1)];
-        const LevelGeom g = D.g;
-        const R* grid = (const R*)(ch ? D.dgrid[ch - 1] : D.grid);
-        cplx<R>* spec = (cplx<R>*)(ch ? D.dspec[ch - 1] : D.spec);
-        dev::dev_row_r2c<R>(smem_raw, g, grid, (const cplx<R>*)D.tw, spec, u);
-        __syncthreads();
-    }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    const int ch = l >> 1;
+    const LevelDesc D = desc(lv, 2 * i + (l & 1));
+    const LevelGeom g = D.g;
+    const R* grid = (const R*)(ch == 0 ? D.grid : ch == 1 ? D.dgrid[0] : D.dgrid[1]);
+    cplx<R>* spec = (cplx<R>*)(ch == 0 ? D.spec : ch == 1 ? D.dspec[0] : D.dspec[1]);
+    dev::dev_row_r2c<R>(smem_raw, g, grid, (const cplx<R>*)D.tw, spec, u);
 }
 
 // Forward column transforms of the double-layer channels (items of channel c >= 1).
@@ -198,15 +201,13 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void kg_col_fwd(const LevelDesc* __restrict__ lv, StageTab t)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        const int ch = l >> 1;
-        const LevelDesc& D = lv[2 * i + (l & 1)];
-        const LevelGeom g = D.g;
-        if (ch) dev::dev_col_fwd<R>(smem_raw, g, (cplx<R>*)D.dspec[ch - 1], (const cplx<R>*)D.tw, u);
-        __syncthreads();
-    }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    const int ch = l >> 1;
+    const LevelDesc D = desc(lv, 2 * i + (l & 1));
+    const LevelGeom g = D.g;
+    if (ch) dev::dev_col_fwd<R>(smem_raw, g, (cplx<R>*)(ch == 1 ? D.dspec[0] : D.dspec[1]), (const cplx<R>*)D.tw, u);
 }
 
 template <typename R>
@@ -214,70 +215,66 @@ __global__ __launch_bounds__(kThreads) void kg_col(const LevelDesc* __restrict__
                                                    StageTab t, int zero_dc)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        const LevelDesc& D = lv[2 * i + l];
-        const LevelGeom g = D.g;
-        const bool dip = D.dgrid[0] && call[i].mu;  // the channels were spread and transformed
-        dev::dev_col<R>(smem_raw, g, (cplx<R>*)D.spec, (const R*)D.mult, (const cplx<R>*)D.tw, zero_dc, u,
-                        dip ? (const cplx<R>*)D.dspec[0] : nullptr, dip ? (const cplx<R>*)D.dspec[1] : nullptr);
-        __syncthreads();
-    }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    const LevelDesc D = desc(lv, 2 * i + l);
+    const LevelGeom g = D.g;
+    const bool dip = D.dgrid[0] && desc(call, i).mu;  // the channels were spread and transformed
+    dev::dev_col<R>(smem_raw, g, (cplx<R>*)D.spec, (const R*)D.mult, (const cplx<R>*)D.tw, zero_dc, u,
+                    dip ? (const cplx<R>*)D.dspec[0] : nullptr, dip ? (const cplx<R>*)D.dspec[1] : nullptr);
 }
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void kg_row_c2r(const LevelDesc* __restrict__ lv, StageTab t)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        const LevelDesc& D = lv[2 * i + l];
-        const LevelGeom g = D.g;
-        dev::dev_row_c2r<R>(smem_raw, g, (const cplx<R>*)D.spec, (const cplx<R>*)D.tw, (R*)D.grid, u);
-        __syncthreads();
-    }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    const LevelDesc D = desc(lv, 2 * i + l);
+    const LevelGeom g = D.g;
+    dev::dev_row_c2r<R>(smem_raw, g, (const cplx<R>*)D.spec, (const cplx<R>*)D.tw, (R*)D.grid, u);
 }
 
 template <typename R, int W>
 __global__ __launch_bounds__(kThreads) void kg_interp(const LevelDesc* __restrict__ lv, StageTab t)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        const LevelDesc& D = lv[2 * i + l];
-        const LevelGeom g = D.g;
-        dev::dev_interp<R, W>(smem_raw, g, (const R*)D.grid, tgt_view<R>(D), (R*)D.hist, interp_table<R>(D),
-                              D.in_units[u]);
-        __syncthreads();
-    }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    const LevelDesc D = desc(lv, 2 * i + l);
+    const LevelGeom g = D.g;
+    dev::dev_interp<R, W>(smem_raw, g, (const R*)D.grid, tgt_view<R>(D), (R*)D.hist, interp_table<R>(D),
+                          D.in_units[u]);
 }
 
 __global__ __launch_bounds__(kThreads) void kg_local(const InstDesc* __restrict__ inst,
                                                      const CallDesc* __restrict__ call, StageTab t)
 {
-    for (int it = blockIdx.x; it < t.nitems; it += gridDim.x) {
-        int i, l, u;
-        if (!decode(t, it, i, l, u)) continue;
-        dev::LocalArgs a = inst[i].loc;
-        const CallDesc& K = call[i];
-        a.jet6 = K.jet6;
-        a.sj = K.sj;
-        a.mj = K.mj;
-        a.out = K.out;
-        dev::dev_local(a, (int64_t)u * blockDim.x + threadIdx.x);
-    }
+    const int it = blockIdx.x;  // one item per workgroup
+    int i, l, u;
+    if (it >= t.nitems || !decode(t, it, i, l, u)) return;
+    dev::LocalArgs a = desc(inst, i).loc;
+    const CallDesc K = desc(call, i);
+    a.jet6 = K.jet6;
+    a.sj = K.sj;
+    a.mj = K.mj;
+    a.out = K.out;
+    dev::dev_local(a, (int64_t)u * blockDim.x + threadIdx.x);
 }
 
 #define VP_W_CASES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-unsigned persistent_grid(int n_items, int cus, int per_cu)
+// One workgroup per item, the count rounded up to a multiple of 8: workgroup
+// i then runs on XCD i mod 8, and the dispatcher hands items to CUs as they
+// free up, which balances units of very different cost (a fixed round-robin
+// share per resident workgroup leaves most of them idle behind the few that
+// drew the dense tiles).
+unsigned item_grid(int n_items)
 {
-    int g = std::min(n_items, cus * per_cu);
-    g = (g + 7) & ~7;  // a multiple of 8: item i then runs on XCD i mod 8
-    return (unsigned)std::max(g, 8);
+    return (unsigned)std::max((n_items + 7) & ~7, 8);
 }
 
 size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -480,18 +477,18 @@ GroupTabs group_tabs(GroupPlan& G, unsigned char* dev_base)
 // after each stage kind (zero, strengths, spread, row pass, double-layer
 // column transforms, column pass, inverse row pass, interpolation, local part).
 template <typename R>
-static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStream_t st, int cus, hipEvent_t* ev)
+static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStream_t st, hipEvent_t* ev)
 {
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
     if (T.zero.nitems)
-        hipLaunchKernelGGL(kg_zero<R>, dim3(persistent_grid(T.zero.nitems, cus, 8)), dim3(kThreads), 0, st, T.inst,
+        hipLaunchKernelGGL(kg_zero<R>, dim3(item_grid(T.zero.nitems)), dim3(kThreads), 0, st, T.inst,
                            T.lv, T.zero);
     mark(1);
     if (T.str.nitems)
-        hipLaunchKernelGGL(kg_strengths<R>, dim3(persistent_grid(T.str.nitems, cus, 8)), dim3(kThreads), 0, st,
+        hipLaunchKernelGGL(kg_strengths<R>, dim3(item_grid(T.str.nitems)), dim3(kThreads), 0, st,
                            T.inst, T.call, T.str);
     mark(2);
     for (size_t k = 0; k < G.spread.size(); ++k) {
@@ -505,7 +502,7 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
     case W:                                                                                                     \
         (void)hipFuncSetAttribute((const void*)kg_spread_mma<W>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
                                   (int)lds);                                                                    \
-        hipLaunchKernelGGL((kg_spread_mma<W>), dim3(persistent_grid(t.nitems, cus, 4)), dim3(kThreads), lds,   \
+        hipLaunchKernelGGL((kg_spread_mma<W>), dim3(item_grid(t.nitems)), dim3(kThreads), lds,   \
                            st, T.inst, T.lv, T.call, t);                                                        \
         break;
                 VP_W_CASES(VP_CASE)
@@ -520,7 +517,7 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
     case W:                                                                                                     \
         (void)hipFuncSetAttribute((const void*)kg_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize,    \
                                   (int)lds);                                                                    \
-        hipLaunchKernelGGL((kg_spread<R, W>), dim3(persistent_grid(t.nitems, cus, 4)), dim3(kThreads), lds, st, \
+        hipLaunchKernelGGL((kg_spread<R, W>), dim3(item_grid(t.nitems)), dim3(kThreads), lds, st, \
                            T.inst, T.lv, T.call, t);                                                            \
         break;
             VP_W_CASES(VP_CASE)
@@ -531,20 +528,20 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
     }
     mark(3);
     if (T.row.nitems)
-        hipLaunchKernelGGL(kg_row_r2c<R>, dim3(persistent_grid(T.row.nitems, cus, 8)), dim3(kThreads), G.row.lds, st,
+        hipLaunchKernelGGL(kg_row_r2c<R>, dim3(item_grid(T.row.nitems)), dim3(kThreads), G.row.lds, st,
                            T.lv, T.row);
     mark(4);
     const int zero_dc = G.precision == VP_FP32 ? 1 : 0;
     if (T.colf.nitems)
-        hipLaunchKernelGGL((kg_col_fwd<R>), dim3(persistent_grid(T.colf.nitems, cus, 4)), dim3(kThreads), G.colf.lds,
+        hipLaunchKernelGGL((kg_col_fwd<R>), dim3(item_grid(T.colf.nitems)), dim3(kThreads), G.colf.lds,
                            st, T.lv, T.colf);
     mark(5);
     if (T.col.nitems)
-        hipLaunchKernelGGL((kg_col<R>), dim3(persistent_grid(T.col.nitems, cus, 4)), dim3(kThreads), G.col.lds, st,
+        hipLaunchKernelGGL((kg_col<R>), dim3(item_grid(T.col.nitems)), dim3(kThreads), G.col.lds, st,
                            T.lv, T.call, T.col, zero_dc);
     mark(6);
     if (T.c2r.nitems)
-        hipLaunchKernelGGL(kg_row_c2r<R>, dim3(persistent_grid(T.c2r.nitems, cus, 8)), dim3(kThreads), G.c2r.lds, st,
+        hipLaunchKernelGGL(kg_row_c2r<R>, dim3(item_grid(T.c2r.nitems)), dim3(kThreads), G.c2r.lds, st,
                            T.lv, T.c2r);
     mark(7);
     for (size_t k = 0; k < G.interp.size(); ++k) {
@@ -554,7 +551,7 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
         switch (G.interp[k].w) {
 #define VP_CASE(W)                                                                                              \
     case W:                                                                                                     \
-        hipLaunchKernelGGL((kg_interp<R, W>), dim3(persistent_grid(t.nitems, cus, 8)), dim3(kThreads), lds, st, \
+        hipLaunchKernelGGL((kg_interp<R, W>), dim3(item_grid(t.nitems)), dim3(kThreads), lds, st, \
                            T.lv, t);                                                                            \
         break;
             VP_W_CASES(VP_CASE)
@@ -565,7 +562,7 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
     }
     mark(8);
     if (T.local.nitems)
-        hipLaunchKernelGGL(kg_local, dim3(persistent_grid(T.local.nitems, cus, 8)), dim3(kThreads), 0, st, T.inst,
+        hipLaunchKernelGGL(kg_local, dim3(item_grid(T.local.nitems)), dim3(kThreads), 0, st, T.inst,
                            T.call, T.local);
     mark(9);
     return hipGetLastError();
@@ -573,22 +570,7 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
 
 hipError_t group_launch(const GroupPlan& G, const GroupTabs& T, hipStream_t st, hipEvent_t* ev)
 {
-    return G.precision == VP_FP32 ? group_launch_t<float>(G, T, st, device_cus(), ev)
-                                  : group_launch_t<double>(G, T, st, device_cus(), ev);
-}
-
-int device_cus()
-{
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
-               prop.multiProcessorCount > 0)
-                  ? prop.multiProcessorCount
-                  : 256;
-    }
-    return cus;
+    return G.precision == VP_FP32 ? group_launch_t<float>(G, T, st, ev) : group_launch_t<double>(G, T, st, ev);
 }
 
 size_t group_bytes_bound(size_t n)

@@ -1,6 +1,6 @@
 #pragma once
 // Device code shared by the per-plan kernels (vp_kernels.hip) and the batched
-// persistent kernels (vp_batch.hip) for gfx950: strengths, spread, 2-D FFT with the history
+// group kernels (vp_batch.hip) for gfx950: strengths, spread, 2-D FFT with the history
 // multiplier fused into the column pass, interpolation, local part.
 //
 // Data flow of one evaluation (history part, Sec. 3 Steps 1-4; local part,

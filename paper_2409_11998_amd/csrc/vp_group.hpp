@@ -125,6 +125,5 @@ size_t group_bytes_bound(size_t n);
 vp_status group_enqueue(const std::vector<const Plan*>& plans, const std::vector<Workspace>& ws,
                         const std::vector<vp_eval_args>& args, void* dev_buf, unsigned char* host_buf,
                         size_t buf_bytes, hipStream_t st, bool* enqueued);
-int device_cus();
 
 }  // namespace vp

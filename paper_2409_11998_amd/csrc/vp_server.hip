@@ -6,7 +6,7 @@
 // in-flight slots and HBM are free it admits the queued requests that fit --
 // in FIFO order, all of one precision (the first admissible request's), a
 // request that does not fit never blocking smaller ones behind it -- and runs
-// them as one group: the persistent per-stage kernels of the batched
+// them as one group: the per-stage group kernels of the batched
 // execution, one launch per stage for the whole group, on an idle one of
 // several streams.  At most one group per stream is in flight: while every
 // stream is busy, arrivals wait on the host and the next free stream takes

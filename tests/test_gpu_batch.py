@@ -1,4 +1,4 @@
-"""Batched persistent execution: every instance's result equals its own
+"""Batched execution (one kernel per stage for all instances): every instance's result equals its own
 single-plan result (the same kernels; only LDS atomic order may differ) and the
 oracle, eagerly and on repeated graph replays with eager work in between."""
 import numpy as np
@@ -19,7 +19,7 @@ def _setup(precision, sizes, kinds="VD", seed0=40):
     tol = 1e-10 if precision == 1 else 1e-6
     mask = (1 if "V" in kinds else 0) | (2 if "S" in kinds else 0) | (4 if "D" in kinds else 0)
     devs = [to_device(P) for P in probs]
-    plans = make_batch_plans(devs, tol=tol, precision=precision, kinds=mask)
+    plans = make_batch_plans(devs, classes=2, tol=tol, precision=precision, kinds=mask)
     return torch, probs, devs, plans, run, mask
 
 

@@ -46,44 +46,67 @@ def run(plan, dev, kinds="VSD", out=None):
                      out=out)
 
 
-def make_batch_plans(devs, autotune_sample=0, **opts):
-    """Plans for a batch: one spreading width per level for all instances.
+def _class_choice(devs, members, sample, opts):
+    """Widths and tile edge for the instances `members` (sorted by size).
 
-    Without autotune_sample, the width is the largest the static planner picks
-    for any instance.  With autotune_sample = k > 0, k instances spread over
-    the size range are planned with the measured level selection (autotune)
-    and the batch takes the widest of their chosen widths.  Every instance is
-    then planned at that width, which fixes its fine grids (the smallest on
-    which the width meets the tolerance)."""
-    order = sorted(range(len(devs)), key=lambda i: devs[i]["tgt_x"].numel())
-    if autotune_sample > 0:
-        pick = sorted({order[int(round(j * (len(order) - 1) / max(1, autotune_sample - 1)))]
-                       for j in range(autotune_sample)})
-        w = [0, 0]
-        for i in pick:
-            p = make_plan(devs[i], autotune=True, **opts)
-            w = [max(w[l], p.info()["width"][l]) for l in range(2)]
-            p.close()
+    Widths: the widest the planner picks for `sample` of them spread over the
+    size range, measured (autotune) when sample > 0, else the static choice
+    for every member.  Tile: the edge the measured selection chose for every
+    sampled level when it chose one edge throughout, else 0 (the planner's
+    static rule per level)."""
+    if sample > 0:
+        pick = sorted({members[int(round(j * (len(members) - 1) / max(1, sample - 1)))] for j in range(sample)})
+        tune = True
     else:
-        w = [0, 0]
-        for d in devs:
-            p = make_plan(d, **opts)
-            w = [max(w[l], p.info()["width"][l]) for l in range(2)]
-            p.close()
-    while True:
-        out, widen = [], None
-        for d in devs:
-            try:
-                out.append(make_plan(d, spread_width=tuple(w), **opts))
-            except Exception:  # this instance needs a wider kernel: widen the batch and start over
-                p = make_plan(d, **opts)
-                widen = [max(w[l], p.info()["width"][l]) for l in range(2)]
-                p.close()
+        pick, tune = members, False
+    w, tiles = [0, 0], set()
+    for i in pick:
+        p = make_plan(devs[i], autotune=tune, **opts)
+        inf = p.info()
+        w = [max(w[l], inf["width"][l]) for l in range(2)]
+        tiles.update(inf["tile"])
+        p.close()
+    return w, (tiles.pop() if tune and len(tiles) == 1 else 0)
+
+
+def make_batch_plans(devs, autotune_sample=0, classes=1, **opts):
+    """Plans for a batch, one spreading width per level within each width class.
+
+    The instances, sorted by target count, are cut into `classes` classes of
+    about equal count.  A class's width per level is the largest the planner
+    picks for its members: with autotune_sample = k > 0, for k of them spread
+    over the class's size range with the measured level selection (autotune),
+    else the static choice for every member; with autotune the class also
+    takes the tile edge the measurements agreed on.  Every member is then
+    planned at its class's width (and tile), which fixes its fine grids (the
+    smallest on which the width meets the tolerance); a member that needs a
+    wider kernel widens its class, which is planned again.  Returns the plans
+    in the order of devs."""
+    order = sorted(range(len(devs)), key=lambda i: devs[i]["tgt_x"].numel())
+    classes = max(1, min(classes, len(order)))
+    cut = [round(c * len(order) / classes) for c in range(classes + 1)]
+    out = [None] * len(devs)
+    for c in range(classes):
+        members = order[cut[c]:cut[c + 1]]
+        w, tile = _class_choice(devs, members, autotune_sample, opts)
+        copts = dict(opts, tile=tile) if tile and "tile" not in opts else opts
+        while True:
+            made, widen = [], None
+            for i in members:
+                try:
+                    made.append(make_plan(devs[i], spread_width=tuple(w), **copts))
+                except Exception:  # this member needs a wider kernel: widen the class and start over
+                    p = make_plan(devs[i], **copts)
+                    widen = [max(w[l], p.info()["width"][l]) for l in range(2)]
+                    p.close()
+                    break
+            if widen is None:
                 break
-        if widen is None:
-            return out
-        for p in out:
-            p.close()
-        if widen == w:
-            raise RuntimeError("no common spreading width for the batch")
-        w = widen
+            for p in made:
+                p.close()
+            if widen == w:
+                raise RuntimeError("no common spreading width for a batch class")
+            w = widen
+        for i, p in zip(members, made):
+            out[i] = p
+    return out
