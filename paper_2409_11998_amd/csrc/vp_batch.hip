@@ -155,8 +155,8 @@ __global__ __launch_bounds__(kThreads) void kg_spread(const InstDesc* __restrict
                           use_d, D.horner, chan ? I.smax + kDcParts : I.smax, D.sp_units[u]);
 }
 
-// Matrix-core spread of float32 levels: an item is four work units, one per wavefront.
-template <int W>
+// Matrix-core spread: an item is four work units, one per wavefront.
+template <typename R, int W>
 __global__ __launch_bounds__(kThreads) void kg_spread_mma(const InstDesc* __restrict__ inst,
                                                           const LevelDesc* __restrict__ lv,
                                                           const CallDesc* __restrict__ call, StageTab t)
@@ -172,13 +172,17 @@ __global__ __launch_bounds__(kThreads) void kg_spread_mma(const InstDesc* __rest
     const int unit = u * (kThreads / 64) + (threadIdx.x >> 6);
     if (unit >= D.n_sp_units) return;  // no barrier follows: each wavefront spreads its own unit
     const bool chan = ch != 0;  // as in kg_spread
-    const float* s = (const float*)I.str + (chan ? (I.n_src + I.n_bnd) + (ch - 1) * I.n_bnd - I.n_src : 0);
-    float* grid = (float*)(ch == 0 ? D.grid : ch == 1 ? D.dgrid[0] : D.dgrid[1]);
+    const R* s = (const R*)I.str + (chan ? (I.n_src + I.n_bnd) + (ch - 1) * I.n_bnd - I.n_src : 0);
+    R* grid = (R*)(ch == 0 ? D.grid : ch == 1 ? D.dgrid[0] : D.dgrid[1]);
     const int use_vol = !chan && K.f != nullptr && I.has_vol;
     const int use_bnd = chan || ((K.sigma != nullptr || K.mu != nullptr) && I.has_bnd);
     const int use_d = !chan && K.mu != nullptr && !D.dgrid[0];
-    dev::dev_spread_mma<W>(smem_raw, D.g, vol_view<float>(D), bnd_view<float>(D), s, I.n_src, I.n_bnd, grid, use_vol,
-                           use_bnd, use_d, D.horner, D.sp_units[unit]);
+    if constexpr (sizeof(R) == 4)
+        dev::dev_spread_mma<W>(smem_raw, D.g, vol_view<float>(D), bnd_view<float>(D), s, I.n_src, I.n_bnd, grid,
+                               use_vol, use_bnd, use_d, D.horner, D.sp_units[unit]);
+    else
+        dev::dev_spread_mma64<W>(smem_raw, D.g, vol_view<double>(D), bnd_view<double>(D), s, I.n_src, I.n_bnd,
+                                 grid, use_vol, use_bnd, use_d, D.horner, D.sp_units[unit]);
 }
 
 template <typename R>
@@ -496,13 +500,12 @@ static hipError_t group_launch_t(const GroupPlan& G, const GroupTabs& T, hipStre
         if (!t.nitems) continue;
         const size_t lds = G.spread[k].lds;
         if (G.spread[k].mma) {
-            if constexpr (!std::is_same<R, float>::value) return hipErrorInvalidValue;
             switch (G.spread[k].w) {
 #define VP_CASE(W)                                                                                              \
     case W:                                                                                                     \
-        (void)hipFuncSetAttribute((const void*)kg_spread_mma<W>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+        (void)hipFuncSetAttribute((const void*)kg_spread_mma<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                   (int)lds);                                                                    \
-        hipLaunchKernelGGL((kg_spread_mma<W>), dim3(item_grid(t.nitems)), dim3(kThreads), lds,   \
+        hipLaunchKernelGGL((kg_spread_mma<R, W>), dim3(item_grid(t.nitems)), dim3(kThreads), lds,               \
                            st, T.inst, T.lv, T.call, t);                                                        \
         break;
                 VP_W_CASES(VP_CASE)

@@ -871,6 +871,197 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
 }
 
 // ---------------------------------------------------------------------------
+// Spread on matrix cores for float64 plans (16 x 16 tiles, w <= 17).
+//
+// The same outer-product form as the float32 kernel above, with
+// v_mfma_f64_16x16x4_f64: the window of 32 x 32 cells is four 16 x 16 blocks,
+// each in four float64 accumulation registers per lane, and one instruction per
+// block advances it by four rank-1 terms (a volume node is one term,
+// (s phi_x) (x) phi_y; a double-layer node two, as above).  Accumulation stays
+// in float64 throughout, so nothing is rounded to float32.
+//
+// Per chunk of 32 terms each lane evaluates the w taps of one (term, axis)
+// (coefficients uniform across the wavefront: scalar registers) into compact
+// LDS rows of w values with the term's corner offset beside them; the matrix
+// step then gives lane (k, i) = (lane / 16, lane % 16) the entry of row
+// 16 b + i of term k's factor, zero outside the factor's w taps.  No LDS
+// atomics and no zeroing: 6 LDS reads per lane per four terms, against w^2
+// LDS atomics per node in the LDS path.
+//
+// Lane layout of the instruction (checked on the device): lane 16 k + i
+// supplies A[i][k] and B[k][i]; result element e of lane l is C[l / 16 + 4 e][l % 16].
+constexpr int kM64Terms = 32;  // rank-1 terms per chunk
+constexpr int kM64Row = 17;    // doubles per factor row (w <= 17; odd, so rows start in different banks)
+using mma_f64x4 = double __attribute__((ext_vector_type(4)));
+__host__ __device__ constexpr size_t mma64_wave_bytes()
+{
+    return (size_t)kM64Terms * 2 * kM64Row * sizeof(double) + (size_t)kM64Terms * 2 * sizeof(int);
+}
+
+template <int W>
+__device__ void dev_spread_mma64(unsigned char* smem_raw, const LevelGeom& g, const RecView<double>& vol,
+                                 const RecView<double>& bnd, const double* __restrict__ str, int64_t n_src,
+                                 int64_t n_bnd, double* __restrict__ grid, int use_vol, int use_bnd, int use_d,
+                                 const double* __restrict__ coef, const WorkUnit unit_in)
+{
+    constexpr int NT = kM64Terms;
+    constexpr int P = horner_terms(W);
+    static_assert(kMmaTile + W - 1 <= 32 && W <= kM64Row, "window of 32 cells, rows of kM64Row");
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    unsigned char* base = smem_raw + (size_t)wv * mma64_wave_bytes();
+    double* X = reinterpret_cast<double*>(base);  // [NT][kM64Row] x factors (strength folded in)
+    double* Y = X + NT * kM64Row;                 // [NT][kM64Row] y factors
+    int* OFF = reinterpret_cast<int*>(Y + NT * kM64Row);  // [NT][2] corner offsets (x, y) in the window
+    // the unit is the wavefront's own: its fields are uniform (scalar loop control)
+    WorkUnit unit;
+    unit.tile = __builtin_amdgcn_readfirstlane(unit_in.tile);
+    unit.a0 = __builtin_amdgcn_readfirstlane(unit_in.a0);
+    unit.a1 = __builtin_amdgcn_readfirstlane(unit_in.a1);
+    unit.b0 = __builtin_amdgcn_readfirstlane(unit_in.b0);
+    unit.b1 = __builtin_amdgcn_readfirstlane(unit_in.b1);
+    const int t = unit.tile;
+    const int gx0 = (t % g.ntx) * kMmaTile, gy0 = (t / g.ntx) * kMmaTile;
+    const int nv = use_vol ? unit.a1 - unit.a0 : 0;
+    const int nbd = use_bnd ? unit.b1 - unit.b0 : 0;
+    if (nv == 0 && nbd == 0) return;  // uniform across the wavefront
+    const int64_t n_all = n_src + n_bnd;
+    const double dscale = -2.0 / g.h;  // d/dy of a tap value = -(2/h) d/du
+    const int axis = lane & 1;         // evaluation: 0 x factor, 1 y factor
+    const int rec = lane >> 1;
+    const int mk = lane >> 4, mi = lane & 15;  // matrix step: term mk of the four, row / column mi of a block
+    mma_f64x4 acc[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[b][c] = mma_f64x4{0.0, 0.0, 0.0, 0.0};
+
+    auto path = [&](const RecView<double>& L, int r0, int r1, auto dl_tag) {
+        constexpr bool DL = decltype(dl_tag)::value;
+        constexpr int NRC = DL ? NT / 2 : NT;  // records per chunk
+        int p_off = 0;
+        double p_d = 0.0, p_s = 0.0, p_gx = 0.0, p_gy = 0.0;
+        auto fetch = [&](int c0) {  // this lane's record of the chunk at c0, its axis
+            const int r = c0 + rec;
+            if (rec < NRC && r < r1) {
+                const int ij = L.ij[r];
+                const int idx = L.idx[r];
+                p_d = axis ? L.dy[r] : L.dx[r];
+                p_off = axis ? (ij >> 16) - gy0 : (ij & 0xffff) - gx0;
+                p_s = str[idx];
+                if (DL) {
+                    p_gx = str[n_all + (idx - n_src)];
+                    p_gy = str[n_all + n_bnd + (idx - n_src)];
+                }
+            }
+        };
+        fetch(r0);
+        for (int c0 = r0; c0 < r1; c0 += NRC) {
+            const int n = min(NRC, r1 - c0);
+            const int nterm = DL ? 2 * n : n;
+            const double u = 2.0 * p_d - 1.0;
+            const int off = p_off;
+            const double s_ = p_s, gx_ = p_gx, gy_ = p_gy;
+            if (c0 + NRC < r1) fetch(c0 + NRC);
+            const bool on = rec < n;
+            if constexpr (!DL) {
+                // term rec: x row s phi_x, y row phi_y (tap pairs from the even kernel, as above)
+                double* row = (axis ? Y : X) + rec * kM64Row;
+                double pw[(P + 1) / 2];
+                pw[0] = 1.0;
+                pw[1] = u * u;
+#pragma unroll
+                for (int k = 2; k < (P + 1) / 2; ++k) pw[k] = pw[k - 1] * pw[1];
+                const double sc = axis == 0 ? s_ : 1.0;
+#pragma unroll
+                for (int a = 0; a < (W + 1) / 2; ++a) {
+                    double va, vm;
+                    tap_pair_pow<P>(coef + a * P, pw, u, va, vm);
+                    if (on) {
+                        row[a] = sc * va;
+                        if (a != W - 1 - a) row[W - 1 - a] = sc * vm;
+                    }
+                }
+                if (on) OFF[2 * rec + axis] = off;
+            } else {
+                // terms 2 rec and 2 rec + 1: (s phi_x + gx phi_x') (x) phi_y and phi_x (x) (gy phi_y')
+                double* r0w = (axis ? Y : X) + (2 * rec) * kM64Row;
+                double* r1w = r0w + kM64Row;
+#pragma unroll 2
+                for (int a = 0; a < W; ++a) {
+                    double v, dv;
+                    tap_value_deriv<P>(coef + a * P, u, v, dv);  // uniform coefficients: scalar loads
+                    dv *= dscale;
+                    if (on) {
+                        if (axis == 0) {
+                            r0w[a] = s_ * v + gx_ * dv;
+                            r1w[a] = v;
+                        } else {
+                            r0w[a] = v;
+                            r1w[a] = gy_ * dv;
+                        }
+                    }
+                }
+                if (on) {
+                    OFF[2 * (2 * rec) + axis] = off;
+                    OFF[2 * (2 * rec + 1) + axis] = off;
+                }
+            }
+            wave_sync_lds();
+            // matrix steps of four terms (terms past nterm contribute zero rows); the
+            // factors of the next step are read before this step's instructions issue
+            auto factors = [&](int m, double* a, double* b) {
+                const int tm = m + mk;
+                const bool live = tm < nterm;
+                const int ox = live ? OFF[2 * tm] : 64, oy = live ? OFF[2 * tm + 1] : 64;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int iy = 16 * q + mi - oy, ix = 16 * q + mi - ox;
+                    const bool iny = (unsigned)iy < (unsigned)W, inx = (unsigned)ix < (unsigned)W;
+                    const double yv = Y[tm * kM64Row + (iny ? iy : 0)];
+                    const double xv = X[tm * kM64Row + (inx ? ix : 0)];
+                    a[q] = iny ? yv : 0.0;
+                    b[q] = inx ? xv : 0.0;
+                }
+            };
+            double a[2], b[2];
+            factors(0, a, b);
+            for (int m = 0; m < nterm; m += 4) {
+                double an[2], bn[2];
+                if (m + 4 < nterm) factors(m + 4, an, bn);
+#pragma unroll
+                for (int by = 0; by < 2; ++by)
+#pragma unroll
+                    for (int bx = 0; bx < 2; ++bx)
+                        acc[by][bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[by], b[bx], acc[by][bx], 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    a[q] = an[q];
+                    b[q] = bn[q];
+                }
+            }
+            wave_sync_lds();
+        }
+    };
+    if (nv) path(vol, unit.a0, unit.a1, std::false_type{});
+    if (nbd && !use_d) path(bnd, unit.b0, unit.b1, std::false_type{});
+    if (nbd && use_d) path(bnd, unit.b0, unit.b1, std::true_type{});
+    const int F = g.F;
+#pragma unroll
+    for (int by = 0; by < 2; ++by)
+#pragma unroll
+        for (int bx = 0; bx < 2; ++bx) {
+            const int gx = gx0 + 16 * bx + mi;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gy = gy0 + 16 * by + mk + 4 * e;
+                const double v = acc[by][bx][e];
+                if (v != 0.0 && gx < F && gy < F) unsafeAtomicAdd(grid + (size_t)gy * F + gx, v);
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Row pass: real FFT along x of each row (length F via a complex FFT of length
 // F/2), keeping only x-frequencies 0..M.  Output spec[c][m1][row] so that the
 // column pass reads contiguous columns.

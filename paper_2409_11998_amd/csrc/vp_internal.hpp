@@ -58,7 +58,7 @@ struct LevelGeom {
     double dc_coef; // (dk/2pi)^2 * multiplier(0): the zero mode's kernel weight
     double dmax;    // max over taps and offsets of |d/dy tap value| (double-layer spreading bound)
     double fit_err[2]; // sampled max |polynomial - kernel| of the spreading and interpolation tables
-    int mma;        // spread on matrix cores (float32 plans on kMmaTile tiles), else LDS atomics
+    int mma;        // spread on matrix cores (kMmaTile tiles, either precision), else LDS atomics
     int Ti, ntxi;   // interpolation tile edge and tiles per dimension (targets are binned on their own tiles)
     // Double layer in channels of its own: mu nu_1 w and mu nu_2 w spread with the kernel itself into
     // two more grids, whose spectra enter the column pass as -i k_1 B_1 - i k_2 B_2 (float32
@@ -104,6 +104,8 @@ struct WorkUnit {
 };
 constexpr int kUnitNodes = 1024;     // volume nodes per spreading unit
 constexpr int kUnitBnd = 256;        // boundary nodes per spreading unit
+constexpr int kUnitNodesMma = 128;   // volume nodes per matrix-core spreading unit (one wavefront)
+constexpr int kUnitBndMma = 64;      // boundary nodes per matrix-core spreading unit
 constexpr int kUnitTargets = 2048;   // targets per interpolation unit
 
 // Device buffers of one level.  R = float or double (plan precision).

@@ -54,18 +54,23 @@ __global__ __launch_bounds__(kThreads) void k_spread(LevelGeom g, RecView<R> vol
                      units[xcd_unit(blockIdx.x, gridDim.x)]);
 }
 
-// Matrix-core spread (float32 plans, kMmaTile tiles): one wavefront per work unit.
-template <int W>
-__global__ __launch_bounds__(kThreads) void k_spread_mma(LevelGeom g, RecView<float> vol, RecView<float> bnd,
-                                                         const float* __restrict__ str, int64_t n_src,
-                                                         int64_t n_bnd, float* __restrict__ grid, int use_vol,
-                                                         int use_bnd, int use_d, const double* __restrict__ coef,
+// Matrix-core spread (kMmaTile tiles; float32 or float64 matrix instructions by
+// plan precision): one wavefront per work unit.
+template <typename R, int W>
+__global__ __launch_bounds__(kThreads) void k_spread_mma(LevelGeom g, RecView<R> vol, RecView<R> bnd,
+                                                         const R* __restrict__ str, int64_t n_src, int64_t n_bnd,
+                                                         R* __restrict__ grid, int use_vol, int use_bnd, int use_d,
+                                                         const double* __restrict__ coef,
                                                          const WorkUnit* __restrict__ units, int n_units)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int u = xcd_unit(blockIdx.x, gridDim.x) * (kThreads / 64) + (threadIdx.x >> 6);
-    if (u < n_units)
+    if (u >= n_units) return;
+    if constexpr (sizeof(R) == 4)
         dev_spread_mma<W>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d, coef, units[u]);
+    else
+        dev_spread_mma64<W>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d, coef,
+                            units[u]);
 }
 
 // The FFT passes of one or two levels (and a level's double-layer channels) in
@@ -234,7 +239,7 @@ size_t interp_lds_bytes_of(const Plan& p, int level)
 
 size_t spread_lds_bytes(const Plan& p, int level)
 {
-    if (p.lv[level].mma) return (kThreads / 64) * mma_wave_bytes();
+    if (p.lv[level].mma) return (kThreads / 64) * (p.precision == VP_FP32 ? mma_wave_bytes() : mma64_wave_bytes());
     size_t a;
     return spread_lds_layout(p.lv[level].T, p.lv[level].w, p.precision == VP_FP32 ? sizeof(float) : sizeof(double),
                              &a);
@@ -252,16 +257,14 @@ static void spread_launch(const Plan& p, hipStream_t st, int l, size_t lds, cons
     const LevelBufs& b = p.lb[l];
     const unsigned nu = (unsigned)b.h_sp_units.size();
     if (nu == 0) return;
-    if constexpr (std::is_same<R, float>::value) {
-        if (g.mma) {  // four units per workgroup, one per wavefront
-            const unsigned nb = (nu + kThreads / 64 - 1) / (kThreads / 64);
-            (void)hipFuncSetAttribute((const void*)k_spread_mma<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds);
-            hipLaunchKernelGGL((k_spread_mma<W>), dim3(nb), dim3(kThreads), lds, st, g, view<float>(b.vol),
-                               view<float>(b.bnd), (const float*)str, p.n_src, p.n_bnd, (float*)grid, uv, ub, ud,
-                               (const double*)b.horner, (const WorkUnit*)b.sp_units, (int)nu);
-            return;
-        }
+    if (g.mma) {  // four units per workgroup, one per wavefront
+        const unsigned nb = (nu + kThreads / 64 - 1) / (kThreads / 64);
+        (void)hipFuncSetAttribute((const void*)k_spread_mma<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        hipLaunchKernelGGL((k_spread_mma<R, W>), dim3(nb), dim3(kThreads), lds, st, g, view<R>(b.vol), view<R>(b.bnd),
+                           str, p.n_src, p.n_bnd, grid, uv, ub, ud, (const double*)b.horner,
+                           (const WorkUnit*)b.sp_units, (int)nu);
+        return;
     }
     (void)hipFuncSetAttribute((const void*)k_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_spread<R, W>), dim3(nu), dim3(kThreads), lds, st, g, view<R>(b.vol), view<R>(b.bnd), str,

@@ -336,8 +336,9 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
 }
 
 // Work units of one level: each tile with records becomes one or more units
-// of at most kUnitNodes volume / kUnitBnd boundary nodes (spreading) or
-// kUnitTargets targets (interpolation).
+// of at most kUnitNodes volume / kUnitBnd boundary nodes (spreading on LDS;
+// kUnitNodesMma / kUnitBndMma on matrix cores) or kUnitTargets targets
+// (interpolation).
 vp_status build_units(Plan& p, int l)
 {
     LevelBufs& b = p.lb[l];
@@ -375,17 +376,21 @@ vp_status build_units(Plan& p, int l)
             }
         return best;
     };
+    // a matrix-core unit is one wavefront's work: smaller units keep more
+    // wavefronts in flight on dense tiles (and need no cover: no fixed point)
+    const bool mma = p.lv[l].mma != 0;
+    const int cap_v = mma ? kUnitNodesMma : kUnitNodes, cap_b = mma ? kUnitBndMma : kUnitBnd;
     for (int t = 0; t < ntiles; ++t) {
         const int nv = cnt_of(b.vol, t), nb = cnt_of(b.bnd, t);
-        const int ku = std::max((nv + kUnitNodes - 1) / kUnitNodes, (nb + kUnitBnd - 1) / kUnitBnd);
+        const int ku = std::max((nv + cap_v - 1) / cap_v, (nb + cap_b - 1) / cap_b);
         for (int k = 0; k < ku; ++k) {
             WorkUnit u;
             u.tile = t;
-            u.a0 = beg_of(b.vol, t) + std::min(nv, k * kUnitNodes);
-            u.a1 = beg_of(b.vol, t) + std::min(nv, (k + 1) * kUnitNodes);
-            u.b0 = beg_of(b.bnd, t) + std::min(nb, k * kUnitBnd);
-            u.b1 = beg_of(b.bnd, t) + std::min(nb, (k + 1) * kUnitBnd);
-            u.cover = cover_of(t, u.a0, u.a1, u.b0, u.b1);
+            u.a0 = beg_of(b.vol, t) + std::min(nv, k * cap_v);
+            u.a1 = beg_of(b.vol, t) + std::min(nv, (k + 1) * cap_v);
+            u.b0 = beg_of(b.bnd, t) + std::min(nb, k * cap_b);
+            u.b1 = beg_of(b.bnd, t) + std::min(nb, (k + 1) * cap_b);
+            u.cover = mma ? 0 : cover_of(t, u.a0, u.a1, u.b0, u.b1);
             b.h_sp_units.push_back(u);
         }
     }
@@ -637,7 +642,7 @@ vp_status set_level_geom(Plan& p, int l, const LevelCand& c, int T, double cx, d
     g.ntx = c.F / T;
     g.Ti = T;
     g.ntxi = g.ntx;
-    g.mma = (p.precision == VP_FP32 && T == kMmaTile) ? 1 : 0;
+    g.mma = T == kMmaTile ? 1 : 0;  // both precisions: float32 or float64 matrix instructions
     // Float32 far-history levels spread the double layer as two channels of its own: through the
     // kernel derivative its grid holds a dipole layer of size ~1/h whose float32 rounding is white
     // noise, which the far-history multiplier amplifies at the lowest wavenumbers where the dipole
@@ -1196,10 +1201,11 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
             p->level_ms[l] = best_ms;
         } else {
             for (size_t ci = 0; ci < cands[l].size() && best_c < 0; ++ci) {
-                // without a measurement: the matrix-core spread for float32 levels of width >= 12
-                // (measured faster there; at narrower widths the LDS path is as fast and its
-                // exact fixed-point windows round less), 32-cell tiles otherwise
-                const int T = tiles[0] > 0 ? tiles[0] : (fp32 && cands[l][ci].w >= 12 ? kMmaTile : 32);
+                // without a measurement: the matrix-core spread for levels of width >= 12
+                // (measured faster there in both precisions: float32 at widths 12-16, float64
+                // at 13 and 16 on the square workload, 0.12 against 0.15-0.18 ms per level),
+                // 32-cell tiles and the LDS path otherwise
+                const int T = tiles[0] > 0 ? tiles[0] : (cands[l][ci].w >= 12 ? kMmaTile : 32);
                 if ((s = set_level_geom(*p, l, cands[l][ci], T, cx, cy)) != VP_OK) return bail(s);
                 if (level_fits_lds(*p, l)) {
                     best_c = (int)ci;

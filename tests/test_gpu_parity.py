@@ -70,16 +70,17 @@ def test_star_fp32_all_kinds_match_oracle():
 
 @pytest.mark.parametrize("precision,tile", [(0, 16), (0, 32), (1, 16), (1, 32)])
 def test_spread_paths_match_oracle(precision, tile):
-    """Both spreading kernels: float32 plans on 16-cell tiles spread on matrix
-    cores, float32 on 32-cell tiles through int64 fixed-point LDS windows,
-    float64 through float64 LDS windows; all kinds (the double layer as two
-    rank-1 terms per node on matrix cores)."""
+    """Both spreading kernels in both precisions: 16-cell tiles spread on matrix
+    cores (float32 or float64 instructions), 32-cell tiles through LDS windows
+    (int64 fixed point; float64 cells for float64 units with double-layer
+    derivative taps); all kinds (the double layer as two rank-1 terms per node
+    on matrix cores)."""
     P = star_problem(2500, seed=12)
     tol = 1e-10 if precision == 1 else 1e-6
     got, plan = _run(P, "VSD", tol=tol, precision=precision, kinds=7, tile=tile)
     info = plan.info()
     assert info["tile"] == (tile, tile)
-    assert info["spread_mma"] == ((1, 1) if (precision == 0 and tile == 16) else (0, 0))
+    assert info["spread_mma"] == ((1, 1) if tile == 16 else (0, 0))
     ref = oracle.evaluate(P, kinds="VSD")["total"]
     e = oracle.rel_linf(got, ref)
     print("spread path precision", precision, "tile", tile, "e_inf", e, plan.info()["width"])
