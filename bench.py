@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "target pts/s for V[f]+D[mu] at 1e-6 FP32 vs 1e-10 FP64; p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense float64 (vector and matrix)
 STAGES = ["strengths", "spread", "row_fft", "col_fft_mul", "row_ifft", "interp", "local"]
 LAUNCHES = ["strengths", "spread_nh", "spread_fh", "row_fft_nh", "row_fft_fh", "col_fft_mul_nh", "col_fft_mul_fh",
             "row_ifft_nh", "row_ifft_fh", "interp_nh", "interp_fh", "local"]
@@ -301,8 +302,11 @@ def main():
     dom = max(("spread_nh", "spread_fh", "interp_nh", "interp_fh"), key=lambda k: st[k])
     workload = "square-200k-slivers-gaps V+D fp64 tol1e-10"
     lvl = {"nh": 0, "fh": 1}[dom.rsplit("_", 1)[-1]]
-    kname = KERNELS[dom.rsplit("_", 1)[0]] + " (%s level, w=%d, F=%d)" % (
-        ("near-history", "far-history")[lvl], r64["info"]["width"][lvl], r64["info"]["fine"][lvl])
+    step = dom.rsplit("_", 1)[0]
+    mma = step == "spread" and r64["info"]["spread_mma"][lvl]
+    kname = ("k_spread_mma<double, %d>" % r64["info"]["width"][lvl] if mma else KERNELS[step]) + \
+        " (%s level, w=%d, F=%d)" % (("near-history", "far-history")[lvl], r64["info"]["width"][lvl],
+                                     r64["info"]["fine"][lvl])
     roof = {"bound": "hbm", "kernel": kname, "launch": dom, "achieved": sroof[dom]["gbs"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": sroof[dom]["frac"],
             "traffic": traffic_from_profiles(dom, workload),
@@ -311,6 +315,16 @@ def main():
             "avg_ms": round(st[dom], 4),
             "avg_ms_from": "HIP events, timing pass (each launch alone on the plan's stream)",
             "steps_frac_of_hbm": {k: v["frac"] for k, v in sroof.items()}}
+    if mma:
+        # the spread as rank-1 updates: useful FMAs w^2 per term (a volume node is one term,
+        # a double-layer boundary node two); the matrix instructions cover the 32 x 32 window,
+        # 1024 FMAs per term
+        w_ = r64["info"]["width"][lvl]
+        terms = P.n_src + 2 * P.n_bnd
+        t_s = st[dom] * 1e-3
+        roof["flops"] = {"useful_tflops": round(2.0 * terms * w_ * w_ / t_s / 1e12, 2),
+                         "matrix_tflops": round(2.0 * terms * 1024 / t_s / 1e12, 2),
+                         "peak_tflops": FP64_PEAK_TFLOPS}
     stages_gbs = {k: round(alg[k] / (st[k] * 1e-3) / 1e9, 1) for k in LAUNCHES if st.get(k, 0) > 0}
     cpu = None
     if args.oracle_sample:
