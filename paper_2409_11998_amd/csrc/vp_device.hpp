@@ -763,30 +763,39 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
     auto path = [&](const RecView<float>& L, int r0, int r1, auto dl_tag) {
         constexpr bool DL = decltype(dl_tag)::value;
         constexpr int NRC = DL ? NPC / 2 : NPC;  // records per chunk
-        int p_off = 0;
+        int p_off = 0, p_idx = 0;
         float p_d = 0.f, p_s = 0.f, p_gx = 0.f, p_gy = 0.f;
-        auto fetch = [&](int c0) {  // this lane's record of the chunk at c0, its axis
+        // this lane's record of the chunk at c0, its axis: the record first, its
+        // strengths (gathered through the record's node index) one phase later,
+        // so that neither load's latency stalls the wavefront
+        auto fetch_rec = [&](int c0) {
             const int r = c0 + rec;
             if (rec < NRC && r < r1) {
                 const int ij = L.ij[r];
-                const int idx = L.idx[r];
+                p_idx = L.idx[r];
                 p_d = axis ? L.dy[r] : L.dx[r];
                 p_off = axis ? (ij >> 16) - gy0 : (ij & 0xffff) - gx0;
-                p_s = str[idx];
+            }
+        };
+        auto fetch_str = [&](int c0) {
+            if (rec < NRC && c0 + rec < r1) {
+                p_s = str[p_idx];
                 if (DL) {
-                    p_gx = str[n_all + (idx - n_src)];
-                    p_gy = str[n_all + n_bnd + (idx - n_src)];
+                    p_gx = str[n_all + (p_idx - n_src)];
+                    p_gy = str[n_all + n_bnd + (p_idx - n_src)];
                 }
             }
         };
-        fetch(r0);
+        fetch_rec(r0);
+        fetch_str(r0);
         for (int c0 = r0; c0 < r1; c0 += NRC) {
             const int n = min(NRC, r1 - c0);
             const int np = DL ? 2 * n : n;
             const double u = 2.0 * (double)p_d - 1.0;
             const int off = p_off;
             const double s_ = p_s, gx_ = p_gx, gy_ = p_gy;
-            if (c0 + NRC < r1) fetch(c0 + NRC);
+            const bool more = c0 + NRC < r1;
+            if (more) fetch_rec(c0 + NRC);
             // this lane's factor row(s): zero, then the w taps at the corner offset
             float* row = (axis ? Ay : Bx) + (DL ? 2 * rec : rec) * kMmaRow;
             if (rec < NRC) {
@@ -843,6 +852,7 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
                 }
             }
             wave_sync_lds();
+            if (more) fetch_str(c0 + NRC);  // the next chunk's node indices have arrived by now
             // rank-1 terms [0, np) (rows up to the next even index are zero)
             const int i = lane & 31;
             mma_f32x16 acc = {};
@@ -871,7 +881,7 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
 }
 
 // ---------------------------------------------------------------------------
-// Spread on matrix cores for float64 plans (16 x 16 tiles, w <= 17).
+// Spread on matrix cores for float64 plans (16 x 16 tiles, w <= 16).
 //
 // The same outer-product form as the float32 kernel above, with
 // v_mfma_f64_16x16x4_f64: the window of 32 x 32 cells is four 16 x 16 blocks,
@@ -885,13 +895,14 @@ __device__ void dev_spread_mma(unsigned char* smem_raw, const LevelGeom& g, cons
 // LDS rows of w values with the term's corner offset beside them; the matrix
 // step then gives lane (k, i) = (lane / 16, lane % 16) the entry of row
 // 16 b + i of term k's factor, zero outside the factor's w taps.  No LDS
-// atomics and no zeroing: 6 LDS reads per lane per four terms, against w^2
-// LDS atomics per node in the LDS path.
+// atomics, and each row's zero (entry w, written once) serves every entry
+// outside the taps: 6 LDS reads per lane per four terms, against w^2 LDS
+// atomics per node in the LDS path.
 //
 // Lane layout of the instruction (checked on the device): lane 16 k + i
 // supplies A[i][k] and B[k][i]; result element e of lane l is C[l / 16 + 4 e][l % 16].
 constexpr int kM64Terms = 32;  // rank-1 terms per chunk
-constexpr int kM64Row = 17;    // doubles per factor row (w <= 17; odd, so rows start in different banks)
+constexpr int kM64Row = 17;    // doubles per factor row: w taps and a zero (w <= 16; odd, so rows start in different banks)
 using mma_f64x4 = double __attribute__((ext_vector_type(4)));
 __host__ __device__ constexpr size_t mma64_wave_bytes()
 {
@@ -906,7 +917,7 @@ __device__ void dev_spread_mma64(unsigned char* smem_raw, const LevelGeom& g, co
 {
     constexpr int NT = kM64Terms;
     constexpr int P = horner_terms(W);
-    static_assert(kMmaTile + W - 1 <= 32 && W <= kM64Row, "window of 32 cells, rows of kM64Row");
+    static_assert(kMmaTile + W - 1 <= 32 && W < kM64Row, "window of 32 cells, rows of w taps and a zero");
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     unsigned char* base = smem_raw + (size_t)wv * mma64_wave_bytes();
@@ -935,34 +946,46 @@ __device__ void dev_spread_mma64(unsigned char* smem_raw, const LevelGeom& g, co
     for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[b][c] = mma_f64x4{0.0, 0.0, 0.0, 0.0};
+    // entry W of every factor row stays zero (taps fill entries 0..W-1 only)
+    X[lane * kM64Row + W] = 0.0;  // the wavefront's 64 rows: 32 x rows, then 32 y rows
+    wave_sync_lds();
 
     auto path = [&](const RecView<double>& L, int r0, int r1, auto dl_tag) {
         constexpr bool DL = decltype(dl_tag)::value;
         constexpr int NRC = DL ? NT / 2 : NT;  // records per chunk
-        int p_off = 0;
+        int p_off = 0, p_idx = 0;
         double p_d = 0.0, p_s = 0.0, p_gx = 0.0, p_gy = 0.0;
-        auto fetch = [&](int c0) {  // this lane's record of the chunk at c0, its axis
+        // this lane's record of the chunk at c0, its axis: the record first, its
+        // strengths (gathered through the record's node index) one phase later,
+        // so that neither load's latency stalls the wavefront
+        auto fetch_rec = [&](int c0) {
             const int r = c0 + rec;
             if (rec < NRC && r < r1) {
                 const int ij = L.ij[r];
-                const int idx = L.idx[r];
+                p_idx = L.idx[r];
                 p_d = axis ? L.dy[r] : L.dx[r];
                 p_off = axis ? (ij >> 16) - gy0 : (ij & 0xffff) - gx0;
-                p_s = str[idx];
+            }
+        };
+        auto fetch_str = [&](int c0) {
+            if (rec < NRC && c0 + rec < r1) {
+                p_s = str[p_idx];
                 if (DL) {
-                    p_gx = str[n_all + (idx - n_src)];
-                    p_gy = str[n_all + n_bnd + (idx - n_src)];
+                    p_gx = str[n_all + (p_idx - n_src)];
+                    p_gy = str[n_all + n_bnd + (p_idx - n_src)];
                 }
             }
         };
-        fetch(r0);
+        fetch_rec(r0);
+        fetch_str(r0);
         for (int c0 = r0; c0 < r1; c0 += NRC) {
             const int n = min(NRC, r1 - c0);
             const int nterm = DL ? 2 * n : n;
             const double u = 2.0 * p_d - 1.0;
             const int off = p_off;
             const double s_ = p_s, gx_ = p_gx, gy_ = p_gy;
-            if (c0 + NRC < r1) fetch(c0 + NRC);
+            const bool more = c0 + NRC < r1;
+            if (more) fetch_rec(c0 + NRC);
             const bool on = rec < n;
             if constexpr (!DL) {
                 // term rec: x row s phi_x, y row phi_y (tap pairs from the even kernel, as above)
@@ -1008,20 +1031,21 @@ __device__ void dev_spread_mma64(unsigned char* smem_raw, const LevelGeom& g, co
                 }
             }
             wave_sync_lds();
+            if (more) fetch_str(c0 + NRC);  // the next chunk's node indices have arrived by now
             // matrix steps of four terms (terms past nterm contribute zero rows); the
             // factors of the next step are read before this step's instructions issue
             auto factors = [&](int m, double* a, double* b) {
                 const int tm = m + mk;
                 const bool live = tm < nterm;
                 const int ox = live ? OFF[2 * tm] : 64, oy = live ? OFF[2 * tm + 1] : 64;
+                const double* yr = Y + tm * kM64Row;
+                const double* xr = X + tm * kM64Row;
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const int iy = 16 * q + mi - oy, ix = 16 * q + mi - ox;
-                    const bool iny = (unsigned)iy < (unsigned)W, inx = (unsigned)ix < (unsigned)W;
-                    const double yv = Y[tm * kM64Row + (iny ? iy : 0)];
-                    const double xv = X[tm * kM64Row + (inx ? ix : 0)];
-                    a[q] = iny ? yv : 0.0;
-                    b[q] = inx ? xv : 0.0;
+                    // entries outside the w taps (negative offsets wrap to large unsigned
+                    // values) read the row's zero at index W
+                    a[q] = yr[min((unsigned)(16 * q + mi - oy), (unsigned)W)];
+                    b[q] = xr[min((unsigned)(16 * q + mi - ox), (unsigned)W)];
                 }
             };
             double a[2], b[2];
