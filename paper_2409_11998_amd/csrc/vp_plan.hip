@@ -25,6 +25,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "vp_internal.hpp"
@@ -34,6 +35,24 @@ namespace vp {
 namespace {
 
 thread_local std::string g_last_error;
+
+// Host loops over millions of points or thousands of tiles run on up to 16
+// threads, each on its own contiguous range [b, e) of [0, n) (no shared
+// writes); ranges shorter than grain stay on the calling thread.
+template <typename Fn>
+void parallel_ranges(int64_t n, int64_t grain, Fn&& fn)
+{
+    const int64_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const int64_t nt = std::min<int64_t>(std::min<int64_t>(hw, 16), (n + grain - 1) / std::max<int64_t>(grain, 1));
+    if (nt <= 1) {
+        fn((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int64_t k = 0; k < nt; ++k) th.emplace_back([&fn, n, nt, k] { fn(n * k / nt, n * (k + 1) / nt); });
+    for (auto& t : th) t.join();
+}
 
 vp_status fail(vp_status s, const std::string& msg)
 {
@@ -240,19 +259,28 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
     const size_t n = ids.size();
     std::vector<int> i0(n), j0(n);
     std::vector<R> sx(n), sy(n);
-    for (size_t q = 0; q < n; ++q) {
-        const int k = ids[q];
-        const double tx = (x[k] - g.x0) / g.h;
-        const double ty = (y[k] - g.y0) / g.h;
-        const double ax = std::ceil(tx - 0.5 * w);
-        const double ay = std::ceil(ty - 0.5 * w);
-        if (ax < 0 || ay < 0 || ax + w > g.F || ay + w > g.F)
-            return fail(VP_ERR_INTERNAL, "support outside the fine grid (planner margin)");
-        i0[q] = (int)ax;
-        j0[q] = (int)ay;
-        sx[q] = (R)(ax - tx + 0.5 * w);   // fractional offset in [0, 1)
-        sy[q] = (R)(ay - ty + 0.5 * w);
-    }
+    std::vector<char> outside(16, 0);  // per range: a support left the grid
+    parallel_ranges((int64_t)n, 1 << 16, [&](int64_t b, int64_t e) {
+        bool out = false;
+        for (int64_t q = b; q < e; ++q) {
+            const int k = ids[q];
+            const double tx = (x[k] - g.x0) / g.h;
+            const double ty = (y[k] - g.y0) / g.h;
+            const double ax = std::ceil(tx - 0.5 * w);
+            const double ay = std::ceil(ty - 0.5 * w);
+            if (ax < 0 || ay < 0 || ax + w > g.F || ay + w > g.F) {
+                out = true;
+                continue;
+            }
+            i0[q] = (int)ax;
+            j0[q] = (int)ay;
+            sx[q] = (R)(ax - tx + 0.5 * w);   // fractional offset in [0, 1)
+            sy[q] = (R)(ay - ty + 0.5 * w);
+        }
+        if (out) outside[(size_t)(b * 16 / std::max<int64_t>((int64_t)n, 1)) & 15] = 1;
+    });
+    for (char c : outside)
+        if (c) return fail(VP_ERR_INTERNAL, "support outside the fine grid (planner margin)");
     std::vector<int> cnt(ntiles + 1, 0);
     for (size_t q = 0; q < n; ++q) cnt[(j0[q] / T) * ntx + i0[q] / T + 1]++;
     for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
@@ -272,51 +300,60 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
         constexpr int NB = 32;
         std::vector<int> rij2(rij), ridx2(ridx);
         std::vector<R> rsx2(rsx), rsy2(rsy);
-        std::vector<std::vector<int>> grp(NB);
-        std::vector<int> next(NB), order(NB);
-        std::vector<std::pair<int, int>> chunk;  // (residue, record) of the chunk being formed
-        for (int t = 0; t < ntiles; ++t) {
-            const int b0 = cnt[t], b1 = cnt[t + 1];
-            if (b1 - b0 < 2) continue;
-            const int gx0 = (t % ntx) * T, gy0 = (t / ntx) * T;
-            for (auto& v : grp) v.clear();
-            for (int r = b0; r < b1; ++r) {
-                const int ii = (rij[r] & 0xffff) - gx0, jj = (rij[r] >> 16) - gy0;
-                grp[(jj * pitch + ii) % NB].push_back(r);
-            }
-            std::fill(next.begin(), next.end(), 0);
-            // chunks of NB records: each takes one record from each of the residues
-            // with the most records left (so all NB residues last as long as they
-            // can), more from the largest only when fewer than NB remain; within a
-            // chunk the records go in ascending residue (a full chunk: record q has
-            // residue q, so any grouping of its lanes reads distinct banks)
-            int out = b0;
-            while (out < b1) {
-                const int chunk_end = std::min(b1, out + NB);
-                chunk.clear();
-                while ((int)chunk.size() < chunk_end - out) {
-                    for (int k = 0; k < NB; ++k) order[k] = k;
-                    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-                        return (int)grp[x].size() - next[x] > (int)grp[y].size() - next[y];
-                    });
-                    for (int k = 0; k < NB && (int)chunk.size() < chunk_end - out; ++k) {
-                        const int g = order[k];
-                        if (next[g] == (int)grp[g].size()) break;  // sorted: the rest are empty too
-                        chunk.push_back({g, grp[g][next[g]++]});
+        // tiles are independent: ranges of tiles with about equal record counts per thread
+        const int nth = 16;
+        std::vector<int> tcut(nth + 1, ntiles);
+        tcut[0] = 0;
+        for (int k = 1; k < nth; ++k)
+            tcut[k] = (int)(std::lower_bound(cnt.begin(), cnt.end() - 1, (int)(nrec * k / nth)) - cnt.begin());
+        for (int k = 1; k <= nth; ++k) tcut[k] = std::max(tcut[k], tcut[k - 1]);
+        parallel_ranges(nth, 1, [&](int64_t kb, int64_t ke) {
+            std::vector<std::vector<int>> grp(NB);
+            std::vector<int> next(NB), order(NB);
+            std::vector<std::pair<int, int>> chunk;  // (residue, record) of the chunk being formed
+            for (int t = tcut[kb]; t < tcut[ke]; ++t) {
+                const int b0 = cnt[t], b1 = cnt[t + 1];
+                if (b1 - b0 < 2) continue;
+                const int gx0 = (t % ntx) * T, gy0 = (t / ntx) * T;
+                for (auto& v : grp) v.clear();
+                for (int r = b0; r < b1; ++r) {
+                    const int ii = (rij[r] & 0xffff) - gx0, jj = (rij[r] >> 16) - gy0;
+                    grp[(jj * pitch + ii) % NB].push_back(r);
+                }
+                std::fill(next.begin(), next.end(), 0);
+                // chunks of NB records: each takes one record from each of the residues
+                // with the most records left (so all NB residues last as long as they
+                // can), more from the largest only when fewer than NB remain; within a
+                // chunk the records go in ascending residue (a full chunk: record q has
+                // residue q, so any grouping of its lanes reads distinct banks)
+                int out = b0;
+                while (out < b1) {
+                    const int chunk_end = std::min(b1, out + NB);
+                    chunk.clear();
+                    while ((int)chunk.size() < chunk_end - out) {
+                        for (int k = 0; k < NB; ++k) order[k] = k;
+                        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+                            return (int)grp[x].size() - next[x] > (int)grp[y].size() - next[y];
+                        });
+                        for (int k = 0; k < NB && (int)chunk.size() < chunk_end - out; ++k) {
+                            const int g = order[k];
+                            if (next[g] == (int)grp[g].size()) break;  // sorted: the rest are empty too
+                            chunk.push_back({g, grp[g][next[g]++]});
+                        }
+                    }
+                    std::stable_sort(chunk.begin(), chunk.end(),
+                                     [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.first < y.first; });
+                    for (const auto& c : chunk) {
+                        const int r = c.second;
+                        rij2[out] = rij[r];
+                        ridx2[out] = ridx[r];
+                        rsx2[out] = rsx[r];
+                        rsy2[out] = rsy[r];
+                        ++out;
                     }
                 }
-                std::stable_sort(chunk.begin(), chunk.end(),
-                                 [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.first < y.first; });
-                for (const auto& c : chunk) {
-                    const int r = c.second;
-                    rij2[out] = rij[r];
-                    ridx2[out] = ridx[r];
-                    rsx2[out] = rsx[r];
-                    rsy2[out] = rsy[r];
-                    ++out;
-                }
             }
-        }
+        });
         rij.swap(rij2);
         ridx.swap(ridx2);
         rsx.swap(rsx2);
@@ -1064,18 +1101,43 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
     // diameter bound: max width over 32 directions, divided by cos(pi/64)
     double D = 0.0;
     {
-        const int nd = 32;
+        constexpr int nd = 32;
         std::vector<double> lo(nd, INFINITY), hi(nd, -INFINITY), cs(nd), sn(nd);
         for (int d = 0; d < nd; ++d) {
             cs[d] = std::cos(M_PI * d / nd);
             sn[d] = std::sin(M_PI * d / nd);
         }
         auto scan = [&](const std::vector<double>& X, const std::vector<double>& Y) {
-            for (size_t i = 0; i < X.size(); ++i)
+            const int64_t n = (int64_t)X.size();
+            std::vector<double> plo(16 * nd, INFINITY), phi(16 * nd, -INFINITY);  // per range
+            parallel_ranges(n, 1 << 16, [&](int64_t b, int64_t e) {
+                double l2[nd], h2[nd], c2[nd], s2[nd];  // this range's extremes, in registers
                 for (int d = 0; d < nd; ++d) {
-                    const double v = (X[i] - cx) * cs[d] + (Y[i] - cy) * sn[d];
-                    lo[d] = std::min(lo[d], v);
-                    hi[d] = std::max(hi[d], v);
+                    l2[d] = INFINITY;
+                    h2[d] = -INFINITY;
+                    c2[d] = cs[d];
+                    s2[d] = sn[d];
+                }
+                const double* xp = X.data();
+                const double* yp = Y.data();
+                for (int64_t i = b; i < e; ++i) {
+                    const double px = xp[i] - cx, py = yp[i] - cy;
+                    for (int d = 0; d < nd; ++d) {
+                        const double v = px * c2[d] + py * s2[d];
+                        l2[d] = std::min(l2[d], v);
+                        h2[d] = std::max(h2[d], v);
+                    }
+                }
+                const int64_t part = b * 16 / std::max<int64_t>(n, 1);
+                for (int d = 0; d < nd; ++d) {
+                    plo[part * nd + d] = l2[d];
+                    phi[part * nd + d] = h2[d];
+                }
+            });
+            for (int k = 0; k < 16; ++k)
+                for (int d = 0; d < nd; ++d) {
+                    lo[d] = std::min(lo[d], plo[k * nd + d]);
+                    hi[d] = std::max(hi[d], phi[k * nd + d]);
                 }
         };
         if (o.kinds & VP_KIND_V) scan(sx, sy);
