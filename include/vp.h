@@ -307,7 +307,10 @@ vp_status vp_volume_jets(int64_t n_tri, const double* x, const double* y, const 
  *   residuals included; restart in [1, 200].  iters, resid (host, may be
  *   NULL): products taken, and the last relative residual (computed from mu
  *   on VP_OK, the recurrence's estimate when max_iter ran out inside a
- *   cycle).
+ *   cycle).  The Arnoldi steps run on the device without a host copy per
+ *   step: the host enqueues the next step before reading the previous one's
+ *   convergence flag (from mapped host memory), so a cycle that converges
+ *   takes one more product than it uses (counted in iters).
  * Resolution: at a node the double layer's local part carries, from its
  *   delta^{3/2} term on, mu'' and mu' from the panel interpolant, of size
  *   delta_1^{3/2} |kappa| / h^2 next to mu/2 for a density varying on the
@@ -322,8 +325,10 @@ vp_status vp_volume_jets(int64_t n_tri, const double* x, const double* y, const 
  *   where residuals of data with every frequency stall above 1e-10.  Remedies: coarser panels (about sqrt(N) boundary nodes for N
  *   volume nodes keeps chi small), a smaller delta_1, or order_d <= 2.
  * Runs on the plan's stream and synchronizes it before returning.  Scratch
- * of (restart + 11) n doubles is allocated by the first solve on the plan and
- * kept with it (grown if a later solve needs more, freed by vp_destroy).  VP_ERR_ARG for a
+ * of about (restart + 11) n + restart^2 doubles, 24 bytes of mapped host
+ * memory and two events are allocated by the first solve on the plan and kept
+ * with it (the scratch grown if a later solve needs more; all freed by
+ * vp_destroy).  VP_ERR_ARG for a
  * plan without D, or whose nodes or targets are not the n_pan*q panel nodes,
  * for only one of f_src and jet6, or for a source on a plan without V or
  * volume nodes; VP_ERR_GEOMETRY past the resolution limit;

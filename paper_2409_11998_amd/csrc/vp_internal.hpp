@@ -207,6 +207,12 @@ struct Plan {
     // solve on the plan, grown when a later one needs more, freed with the plan
     void* solve_ws = nullptr;
     size_t solve_ws_bytes = 0;
+    // host memory the solves' Arnoldi kernel writes its state into (mapped, so
+    // the host reads it without a copy); allocated by the first solve
+    void* solve_host = nullptr;
+    void* solve_host_dev = nullptr;  // the same memory's device address
+    hipEvent_t solve_ev[2]{};
+    bool solve_ev_made = false;
 };
 
 // Free a plan's refinement data (vp_refine.hip).

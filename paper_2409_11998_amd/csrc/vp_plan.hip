@@ -233,6 +233,9 @@ void free_plan(vp_plan_s* p)
     refinement_free(p->ref);
     workspace_free(p->ws, nullptr, false);
     if (p->solve_ws) hipFree(p->solve_ws);
+    if (p->solve_host) hipHostFree(p->solve_host);
+    if (p->solve_ev_made)
+        for (auto& e : p->solve_ev) hipEventDestroy(e);
     if (p->ev_made)
         for (auto& e : p->ev) hipEventDestroy(e);
     if (p->side_made) {

@@ -8,11 +8,17 @@
 // the density's jets at the nodes from its panel interpolant
 // (vp_boundary_jets), then vp_eval of the double layer at the plan's targets,
 // which are the nodes themselves with r = 0 and sgn = +1.  Each Arnoldi step
-// orthogonalizes by classical Gram-Schmidt applied twice: the projections on
-// all basis vectors, then the norm, come back to the host in one copy, and
-// every sum is taken in a fixed order (the result does not depend on timing).
-// A solve ends only on a residual b - A x computed from x itself (each cycle
-// starts from it), never on the Arnoldi recurrence's estimate alone.
+// orthogonalizes by classical Gram-Schmidt applied twice, every sum taken in a
+// fixed order (the result does not depend on timing).  The step stays on the
+// device: one kernel writes the new Hessenberg column, applies the Givens
+// rotations, updates the residual estimate and the next basis vector's scale,
+// and sets a done flag; it also writes that state into mapped host memory.
+// The host enqueues step k + 1 before it looks at step k's flag, so the device
+// never waits for the host; a step enqueued after the flag was set is wasted
+// (at most one per cycle, and counted among the products).  The host reads the
+// Hessenberg matrix once per cycle, to update x.  A solve ends only on a
+// residual b - A x computed from x itself (each cycle starts from it), never on
+// the Arnoldi recurrence's estimate alone.
 //
 // Resolution guard.  At a node (r = 0) the double layer's local part of
 // Lemma 4.3 carries, from its delta^{3/2} term on, derivatives of the density
@@ -177,6 +183,71 @@ __global__ __launch_bounds__(kSolveThreads) void k_resolution(int64_t n_pan, int
     }
 }
 
+// State of one restart cycle's Arnoldi recurrence, on the device (and mirrored
+// into mapped host memory by k_arnoldi).
+struct ArnoldiState {
+    int done;       // the estimate reached tol, or the step broke down (h[k+1][k] = 0)
+    int k;          // Hessenberg columns in use
+    double rel;     // |z[k]| / ||b||: the recurrence's residual estimate
+    double inv_hn;  // 1 / h[k+1][k] of the last step (0 after a breakdown)
+};
+
+// Start a cycle: z = (beta, 0, ...), state cleared (one thread)
+__global__ void k_cycle_init(int m, double beta, double bnorm, double* __restrict__ z, ArnoldiState* __restrict__ st,
+                             ArnoldiState* __restrict__ mirror)
+{
+    if (threadIdx.x != 0) return;
+    z[0] = beta;
+    for (int i = 1; i <= m; ++i) z[i] = 0.0;
+    const ArnoldiState s0{0, 0, beta / bnorm, 0.0};
+    *st = s0;
+    *mirror = s0;
+    __threadfence_system();
+}
+
+// Arnoldi step k of a cycle (one thread; nothing once the cycle is done):
+// column k of H from hd (projections h[0..k], then ||w||^2), the earlier
+// rotations applied to it, a new rotation zeroing h[k+1][k], and z rotated.
+__global__ void k_arnoldi(int k, int m, const double* __restrict__ hd, double* __restrict__ H,
+                          double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ z, double tol,
+                          double bnorm, ArnoldiState* __restrict__ st, ArnoldiState* __restrict__ mirror)
+{
+    if (threadIdx.x != 0 || st->done) return;
+    const int k1 = k + 1;
+    for (int i = 0; i <= k; ++i) H[(int64_t)i * m + k] = hd[i];
+    const double hn = sqrt(fmax(hd[k1], 0.0));
+    for (int i = 0; i < k; ++i) {  // earlier rotations on the new column
+        const double a = H[(int64_t)i * m + k], c = H[(int64_t)(i + 1) * m + k];
+        H[(int64_t)i * m + k] = cs[i] * a + sn[i] * c;
+        H[(int64_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * c;
+    }
+    const double a = H[(int64_t)k * m + k];
+    const double rr = hypot(a, hn);
+    cs[k] = rr > 0.0 ? a / rr : 1.0;
+    sn[k] = rr > 0.0 ? hn / rr : 0.0;
+    H[(int64_t)k * m + k] = rr;
+    H[(int64_t)k1 * m + k] = 0.0;
+    z[k1] = -sn[k] * z[k];
+    z[k] = cs[k] * z[k];
+    ArnoldiState s1;
+    s1.k = k1;
+    s1.rel = fabs(z[k1]) / bnorm;
+    s1.inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
+    s1.done = (s1.rel <= tol || hn == 0.0) ? 1 : 0;
+    *st = s1;
+    *mirror = s1;
+    __threadfence_system();
+}
+
+// y = x * inv_hn (the next basis vector; zero after a breakdown)
+__global__ __launch_bounds__(kSolveThreads) void k_scale_dev(int64_t n, const double* __restrict__ x,
+                                                             const ArnoldiState* __restrict__ st,
+                                                             double* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i] * st->inv_hn;
+}
+
 constexpr double kChiInterior = 4.0;   // resolution limits of the guard above
 constexpr double kChiPlus = 2.0;
 
@@ -194,7 +265,6 @@ struct Solver {
     double* hd = nullptr;    // [kMaxRestart + 2]: projections of the current step, then its norm squared
     double* tmp = nullptr;   // [kMaxRestart + 1]: the second Gram-Schmidt pass's projections; last: w . x
     std::vector<double> h_part = std::vector<double>(kDotBlocks);
-    std::vector<double> h_host = std::vector<double>(kMaxRestart + 2);
 
     vp_status launched()
     {
@@ -220,9 +290,9 @@ struct Solver {
                            0, st, n, k1, V, n, c, w);
         return launched();
     }
-    // Arnoldi step on w against V_0..V_k: two classical Gram-Schmidt passes, then
-    // ||w||^2; h[0..k] and h[k+1] = ||w|| on the host after one copy
-    vp_status orthogonalize(const double* V, int k, double* w, double* h)
+    // Arnoldi step on w against V_0..V_k: two classical Gram-Schmidt passes,
+    // leaving hd[0..k] (the projections) and hd[k+1] = ||w||^2 on the device
+    vp_status orthogonalize(const double* V, int k, double* w)
     {
         const int k1 = k + 1;
         vp_status s = project(V, k1, w, hd, false);
@@ -233,12 +303,7 @@ struct Solver {
         hipLaunchKernelGGL(k_axpby, dim3((unsigned)((k1 + kSolveThreads - 1) / kSolveThreads)), dim3(kSolveThreads), 0,
                            st, (int64_t)k1, 1.0, tmp, 1.0, hd);
         if ((s = launched()) != VP_OK) return s;
-        if ((s = project(w, 1, w, hd + k1, false)) != VP_OK) return s;
-        hipError_t e = hipMemcpyAsync(h, hd, (size_t)(k1 + 1) * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
-        h[k1] = std::sqrt(std::max(h[k1], 0.0));
-        return VP_OK;
+        return project(w, 1, w, hd + k1, false);
     }
 
     // y = D_int[x], or D_int[x] + x + (w . x) = x/2 + D[x] + (w . x) with weights
@@ -308,10 +373,14 @@ vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
     const int m = restart;
     Solver S{plan, n_pan, n, q, bnd_x, bnd_y, u, pan, plan->stream};
     S.bw = bw;
-    // scratch in one block kept on the plan (allocated by the first solve, grown if needed)
-    const size_t parts[8] = {(size_t)(m + 1) * n, (size_t)n, (size_t)n, (size_t)5 * n, (size_t)3 * n,
-                             (size_t)(kMaxRestart + 2) * kDotBlocks, (size_t)(kMaxRestart + 2),
-                             (size_t)(kMaxRestart + 1)};
+    // scratch in one block kept on the plan (allocated by the first solve, grown if needed):
+    // basis, w, b, jets, jet scratch, partial sums, projections, second-pass projections,
+    // Hessenberg matrix, rotations (cos, sin), z, cycle state
+    constexpr int kParts = 13;
+    const size_t parts[kParts] = {(size_t)(m + 1) * n, (size_t)n, (size_t)n, (size_t)5 * n, (size_t)3 * n,
+                                  (size_t)(kMaxRestart + 2) * kDotBlocks, (size_t)(kMaxRestart + 2),
+                                  (size_t)(kMaxRestart + 1), (size_t)(m + 1) * m, (size_t)m, (size_t)m,
+                                  (size_t)(m + 1), (sizeof(ArnoldiState) + 7) / 8};
     size_t need = 0;
     for (size_t c : parts) need += (c * sizeof(double) + 255) & ~(size_t)255;
     hipError_t e = hipSuccess;
@@ -322,10 +391,19 @@ vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
         e = hipMalloc(&plan->solve_ws, need);
         if (e == hipSuccess) plan->solve_ws_bytes = need;
     }
-    double* ptr[8] = {};
+    if (e == hipSuccess && !plan->solve_host) {
+        e = hipHostMalloc(&plan->solve_host, sizeof(ArnoldiState), hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(&plan->solve_host_dev, plan->solve_host, 0);
+    }
+    if (e == hipSuccess && !plan->solve_ev_made) {
+        e = hipEventCreateWithFlags(&plan->solve_ev[0], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->solve_ev[1], hipEventDisableTiming);
+        if (e == hipSuccess) plan->solve_ev_made = true;
+    }
+    double* ptr[kParts] = {};
     if (e == hipSuccess) {
         unsigned char* q = (unsigned char*)plan->solve_ws;
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < kParts; ++k) {
             ptr[k] = (double*)q;
             q += (parts[k] * sizeof(double) + 255) & ~(size_t)255;
         }
@@ -338,6 +416,13 @@ vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
     S.part = ptr[5];
     S.hd = ptr[6];
     S.tmp = ptr[7];
+    double* Hd = ptr[8];   // [m+1][m] Hessenberg matrix of the cycle, rotated
+    double* csd = ptr[9];
+    double* snd = ptr[10];
+    double* zd = ptr[11];  // [m+1] rotated right-hand side of the least-squares problem
+    ArnoldiState* std_ = (ArnoldiState*)ptr[12];
+    ArnoldiState* mirror_dev = (ArnoldiState*)plan->solve_host_dev;
+    volatile ArnoldiState* mirror = (volatile ArnoldiState*)plan->solve_host;
     vp_status s = e == hipSuccess ? VP_OK : set_error(VP_ERR_OOM, "solve workspace");
     if (s == VP_OK && plan->loc.order_d >= 3) {   // the resolution guard (header)
         const double chi_max = bw ? kChiPlus : kChiInterior;
@@ -361,17 +446,19 @@ vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
     double bnorm = 0.0, rel = INFINITY;
     int it = 0;          // operator products, every one counted
     bool done = false;   // rel is a residual computed from x and is <= tol
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), z(m + 1), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), z(m + 1), y(m);
     auto Vc = [&](int k) { return V + (size_t)k * n; };
+    auto dev_err = [&](hipError_t er) { return set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(er)); };
     if (s == VP_OK) s = make_rhs(S, b);
     if (s == VP_OK) s = S.dot(b, b, &bnorm);
     bnorm = std::sqrt(bnorm);
     if (s == VP_OK && bnorm == 0.0) {  // zero data: zero solution
         e = hipMemsetAsync(x, 0, (size_t)n * sizeof(double), S.st);
-        if (e != hipSuccess) s = set_error(VP_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(e));
+        if (e != hipSuccess) s = dev_err(e);
         rel = 0.0;
         done = true;
     }
+    const unsigned gn = (unsigned)((n + kSolveThreads - 1) / kSolveThreads);
     while (s == VP_OK && !done && it < max_iter) {
         // r = b - A x in V_0: the residual of x itself
         if ((s = S.matvec(x, Vc(0))) != VP_OK) break;
@@ -387,38 +474,47 @@ vp_status gmres_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
         }
         if (it >= max_iter) break;
         if ((s = S.axpby(0.0, b, 1.0 / beta, Vc(0))) != VP_OK) break;
-        std::fill(z.begin(), z.end(), 0.0);
-        z[0] = beta;
-        int k = 0;
-        for (; k < m && it < max_iter; ++k) {
-            if ((s = S.matvec(Vc(k), w)) != VP_OK) break;
+        hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, S.st, m, beta, bnorm, zd, std_, mirror_dev);
+        if ((s = S.launched()) != VP_OK) break;
+        // steps on the device; the host checks step k's flag after enqueuing step k + 1
+        int kq = 0;
+        bool stop = false;
+        while (kq < m && it < max_iter && !stop) {
+            if ((s = S.matvec(Vc(kq), w)) != VP_OK) break;
             ++it;
-            if ((s = S.orthogonalize(V, k, w, S.h_host.data())) != VP_OK) break;
-            for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = S.h_host[i];
-            const double hn = S.h_host[k + 1];
-            H[(size_t)(k + 1) * m + k] = hn;
-            if (hn > 0.0 && (s = S.axpby(1.0 / hn, w, 0.0, Vc(k + 1))) != VP_OK) break;
-            for (int i = 0; i < k; ++i) {  // earlier rotations on the new column
-                const double a = H[(size_t)i * m + k], c = H[(size_t)(i + 1) * m + k];
-                H[(size_t)i * m + k] = cs[i] * a + sn[i] * c;
-                H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * c;
-            }
-            const double a = H[(size_t)k * m + k], c = H[(size_t)(k + 1) * m + k];
-            const double rr = std::hypot(a, c);
-            cs[k] = rr > 0.0 ? a / rr : 1.0;
-            sn[k] = rr > 0.0 ? c / rr : 0.0;
-            H[(size_t)k * m + k] = rr;
-            H[(size_t)(k + 1) * m + k] = 0.0;
-            z[k + 1] = -sn[k] * z[k];
-            z[k] = cs[k] * z[k];
-            rel = std::fabs(z[k + 1]) / bnorm;   // the recurrence's estimate; the next cycle checks it
-            if (rel <= tol || hn == 0.0) {
-                ++k;
+            if ((s = S.orthogonalize(V, kq, w)) != VP_OK) break;
+            hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, S.st, kq, m, S.hd, Hd, csd, snd, zd, tol, bnorm, std_,
+                               mirror_dev);
+            hipLaunchKernelGGL(k_scale_dev, dim3(gn), dim3(kSolveThreads), 0, S.st, n, w, std_, Vc(kq + 1));
+            if ((s = S.launched()) != VP_OK) break;
+            if ((e = hipEventRecord(plan->solve_ev[kq & 1], S.st)) != hipSuccess) {
+                s = dev_err(e);
                 break;
+            }
+            ++kq;
+            if (kq >= 2) {  // step kq - 2 has been followed by step kq - 1: wait for it, read its flag
+                if ((e = hipEventSynchronize(plan->solve_ev[kq & 1])) != hipSuccess) {
+                    s = dev_err(e);
+                    break;
+                }
+                stop = mirror->done != 0;
             }
         }
         if (s != VP_OK) break;
-        // x += V y with H y = z (upper triangular, k columns)
+        if ((e = hipStreamSynchronize(S.st)) != hipSuccess) {
+            s = dev_err(e);
+            break;
+        }
+        const int k = mirror->k;
+        rel = mirror->rel;   // the recurrence's estimate; the next cycle checks it
+        if (k == 0) break;
+        // the cycle's rotated Hessenberg matrix and z, once per cycle; x += V y with H y = z
+        e = hipMemcpy(H.data(), Hd, (size_t)k * m * sizeof(double), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(z.data(), zd, (size_t)k * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            s = dev_err(e);
+            break;
+        }
         for (int i = k - 1; i >= 0; --i) {
             double t = z[i];
             for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * y[j];
