@@ -252,6 +252,29 @@ void free_plan(vp_plan_s* p)
 // their window offset (j0 - gy0) * pitch + (i0 - gx0) modulo 32 wherever the
 // tile allows, so that the 32 targets a wavefront handles together read 32
 // different LDS banks.
+// Host arrays of record building, kept across the builds of one vp_plan call
+// (the autotuner builds a level once per candidate): reusing them saves
+// allocating and first-touching hundreds of MB per build.  Released when the
+// call returns (ScratchRelease in vp_plan).
+template <typename R>
+struct RecScratch {
+    std::vector<int> i0, j0, rij, ridx, rij2, ridx2, hist;
+    std::vector<R> sx, sy, rsx, rsy, rsx2, rsy2;
+};
+template <typename R>
+RecScratch<R>& rec_scratch()
+{
+    thread_local RecScratch<R> s;
+    return s;
+}
+struct ScratchRelease {
+    ~ScratchRelease()
+    {
+        rec_scratch<float>() = RecScratch<float>();
+        rec_scratch<double>() = RecScratch<double>();
+    }
+};
+
 template <typename R>
 vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std::vector<double>& y,
                         const std::vector<int>& ids, RecList* list, int pitch = 0, int tile = 0)
@@ -260,8 +283,15 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
     const int T = tile > 0 ? tile : g.T, ntx = g.F / T, w = g.w;
     const int ntiles = ntx * ntx;
     const size_t n = ids.size();
-    std::vector<int> i0(n), j0(n);
-    std::vector<R> sx(n), sy(n);
+    RecScratch<R>& S = rec_scratch<R>();
+    std::vector<int>& i0 = S.i0;
+    std::vector<int>& j0 = S.j0;
+    std::vector<R>& sx = S.sx;
+    std::vector<R>& sy = S.sy;
+    i0.resize(n);
+    j0.resize(n);
+    sx.resize(n);
+    sy.resize(n);
     std::vector<char> outside(16, 0);  // per range: a support left the grid
     parallel_ranges((int64_t)n, 1 << 16, [&](int64_t b, int64_t e) {
         bool out = false;
@@ -284,25 +314,75 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
     });
     for (char c : outside)
         if (c) return fail(VP_ERR_INTERNAL, "support outside the fine grid (planner margin)");
+    // counting sort by tile in 16 point ranges: per-range counts, then each
+    // range places its points after the earlier ranges' points of the same tile
+    // (the order within a tile is the points' order, as a sequential pass gives)
+    constexpr int NR = 16;
+    const bool split = n >= ((size_t)1 << 16);
+    const int nr = split ? NR : 1;
+    auto rng_of = [&](int r, int64_t& b, int64_t& e) {
+        b = (int64_t)n * r / nr;
+        e = (int64_t)n * (r + 1) / nr;
+    };
+    std::vector<int>& hist = S.hist;
+    hist.assign((size_t)nr * ntiles, 0);
+    auto tile_of = [&](int64_t q) { return (j0[q] / T) * ntx + i0[q] / T; };
+    parallel_ranges(nr, 1, [&](int64_t rb, int64_t re) {
+        for (int64_t r = rb; r < re; ++r) {
+            int64_t b, e;
+            rng_of((int)r, b, e);
+            int* h = &hist[(size_t)r * ntiles];
+            for (int64_t q = b; q < e; ++q) h[tile_of(q)]++;
+        }
+    });
     std::vector<int> cnt(ntiles + 1, 0);
-    for (size_t q = 0; q < n; ++q) cnt[(j0[q] / T) * ntx + i0[q] / T + 1]++;
-    for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+    for (int t = 0; t < ntiles; ++t) {
+        int c = 0;
+        for (int r = 0; r < nr; ++r) c += hist[(size_t)r * ntiles + t];
+        cnt[t + 1] = cnt[t] + c;
+    }
     const int64_t nrec = cnt[ntiles];
     if (nrec > INT32_MAX) return fail(VP_ERR_ARG, "too many (node, tile) records");
-    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    std::vector<int> rij(nrec), ridx(nrec);
-    std::vector<R> rsx(nrec), rsy(nrec);
-    for (size_t q = 0; q < n; ++q) {
-        const int at = pos[(j0[q] / T) * ntx + i0[q] / T]++;
-        rij[at] = i0[q] | (j0[q] << 16);
-        rsx[at] = sx[q];
-        rsy[at] = sy[q];
-        ridx[at] = ids[q];
+    for (int t = 0; t < ntiles; ++t) {  // hist becomes each range's first position in each tile
+        int at = cnt[t];
+        for (int r = 0; r < nr; ++r) {
+            const int c = hist[(size_t)r * ntiles + t];
+            hist[(size_t)r * ntiles + t] = at;
+            at += c;
+        }
     }
+    std::vector<int>& rij = S.rij;
+    std::vector<int>& ridx = S.ridx;
+    std::vector<R>& rsx = S.rsx;
+    std::vector<R>& rsy = S.rsy;
+    rij.resize(nrec);
+    ridx.resize(nrec);
+    rsx.resize(nrec);
+    rsy.resize(nrec);
+    parallel_ranges(nr, 1, [&](int64_t rb, int64_t re) {
+        for (int64_t r = rb; r < re; ++r) {
+            int64_t b, e;
+            rng_of((int)r, b, e);
+            int* pos = &hist[(size_t)r * ntiles];
+            for (int64_t q = b; q < e; ++q) {
+                const int at = pos[tile_of(q)]++;
+                rij[at] = i0[q] | (j0[q] << 16);
+                rsx[at] = sx[q];
+                rsy[at] = sy[q];
+                ridx[at] = ids[q];
+            }
+        }
+    });
     if (pitch > 0) {
         constexpr int NB = 32;
-        std::vector<int> rij2(rij), ridx2(ridx);
-        std::vector<R> rsx2(rsx), rsy2(rsy);
+        std::vector<int>& rij2 = S.rij2;
+        std::vector<int>& ridx2 = S.ridx2;
+        std::vector<R>& rsx2 = S.rsx2;
+        std::vector<R>& rsy2 = S.rsy2;
+        rij2 = rij;
+        ridx2 = ridx;
+        rsx2 = rsx;
+        rsy2 = rsy;
         // tiles are independent: ranges of tiles with about equal record counts per thread
         const int nth = 16;
         std::vector<int> tcut(nth + 1, ntiles);
@@ -388,9 +468,9 @@ vp_status build_units(Plan& p, int l)
     b.h_sp_units.clear();
     b.h_in_units.clear();
     const int T = p.lv[l].T, w = p.lv[l].w, E = T + w - 1, ntx = p.lv[l].ntx;
-    std::vector<int> cov((size_t)(E + 1) * (E + 1));
     // most records of [a0, a1) of va and [b0, b1) of vb whose w x w supports share a window cell
-    auto cover_of = [&](int t, int a0, int a1, int b0, int b1) {
+    // (cov: the caller's (E + 1)^2 scratch)
+    auto cover_of = [&](std::vector<int>& cov, int t, int a0, int a1, int b0, int b1) {
         std::fill(cov.begin(), cov.end(), 0);
         const int gx0 = (t % ntx) * T, gy0 = (t / ntx) * T;
         auto add = [&](const std::vector<int>& ij, int r0, int r1) {
@@ -430,10 +510,18 @@ vp_status build_units(Plan& p, int l)
             u.a1 = beg_of(b.vol, t) + std::min(nv, (k + 1) * cap_v);
             u.b0 = beg_of(b.bnd, t) + std::min(nb, k * cap_b);
             u.b1 = beg_of(b.bnd, t) + std::min(nb, (k + 1) * cap_b);
-            u.cover = mma ? 0 : cover_of(t, u.a0, u.a1, u.b0, u.b1);
+            u.cover = 0;
             b.h_sp_units.push_back(u);
         }
     }
+    if (!mma)
+        parallel_ranges((int64_t)b.h_sp_units.size(), 256, [&](int64_t u0, int64_t u1) {
+            std::vector<int> cov((size_t)(E + 1) * (E + 1));
+            for (int64_t k = u0; k < u1; ++k) {
+                WorkUnit& u = b.h_sp_units[k];
+                u.cover = cover_of(cov, u.tile, u.a0, u.a1, u.b0, u.b1);
+            }
+        });
     // targets on the interpolation's own tiles
     const int ntiles_i = p.lv[l].ntxi * p.lv[l].ntxi;
     for (int t = 0; t < ntiles_i; ++t) {
@@ -585,13 +673,15 @@ vp_status build_level_tables(Plan& p, int l, double d1, double d2)
     for (int m = 0; m <= M; ++m)
         if (!(ph_s[m] > 0 && ph_i[m] > 0)) return fail(VP_ERR_INTERNAL, "spreading kernel transform not positive");
     std::vector<R> mult((size_t)(M + 1) * (M + 1));
-    for (int a = 0; a <= M; ++a)
-        for (int c = 0; c <= M; ++c) {
-            const double k2 = g.dk * g.dk * ((double)a * a + (double)c * c);
-            const double m = (l == 0) ? mult_nh(k2, d1, d2) : mult_fh(k2, d2, p.L);
-            const double ph = ph_s[a] * ph_s[c] * ph_i[a] * ph_i[c];
-            mult[(size_t)a * (M + 1) + c] = (R)(scale * m / ph);
-        }
+    parallel_ranges(M + 1, 16, [&](int64_t a0, int64_t a1) {  // rows of the table
+        for (int64_t a = a0; a < a1; ++a)
+            for (int c = 0; c <= M; ++c) {
+                const double k2 = g.dk * g.dk * ((double)a * a + (double)c * c);
+                const double m = (l == 0) ? mult_nh(k2, d1, d2) : mult_fh(k2, d2, p.L);
+                const double ph = ph_s[a] * ph_s[c] * ph_i[a] * ph_i[c];
+                mult[(size_t)a * (M + 1) + c] = (R)(scale * m / ph);
+            }
+    });
     g.dc_coef = scale * ((l == 0) ? mult_nh(0.0, d1, d2) : mult_fh(0.0, d2, p.L));
     {
         g.fit_err[0] = tap_fit_error(coef, W, P, g.beta);
@@ -990,6 +1080,7 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
                   const double* tgt_y, const vp_local_geom* geom, const vp_opts* opts_in)
 {
     g_last_error.clear();
+    ScratchRelease scratch_release;  // record-building scratch lives for this call only
     if (!out) return fail(VP_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (n_src < 0 || n_bnd < 0 || n_tgt < 0) return fail(VP_ERR_ARG, "negative count");
