@@ -84,11 +84,25 @@ double ksum(const double* a, int64_t n)
     return s + c;
 }
 
+// true if pred holds for some element (ranges on host threads)
+template <typename T, typename Pred>
+bool any_parallel(const std::vector<T>& v, Pred pred)
+{
+    std::vector<char> hit(16, 0);
+    const int64_t n = (int64_t)v.size();
+    parallel_ranges(n, 1 << 18, [&](int64_t b, int64_t e) {
+        bool h = false;
+        for (int64_t i = b; i < e && !h; ++i) h = pred(v[i]);
+        if (h) hit[(size_t)(b * 16 / std::max<int64_t>(n, 1)) & 15] = 1;
+    });
+    for (char c : hit)
+        if (c) return true;
+    return false;
+}
+
 bool all_finite(const std::vector<double>& v)
 {
-    for (double x : v)
-        if (!std::isfinite(x)) return false;
-    return true;
+    return !any_parallel(v, [](double x) { return !std::isfinite(x); });
 }
 
 // Smallest k > 0 with k^p exp(-k^2 delta) <= eps (decreasing branch).
@@ -1119,45 +1133,59 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
         if (e != hipSuccess) return bail(fail(VP_ERR_DEVICE, std::string("stream sync: ") + hipGetErrorString(e)));
     }
 
-    // ---- inputs to the host
+    // ---- inputs to the host (one copy per array, the copies on host threads)
     std::vector<double> sx, sy, sw, bx, by, bnx, bny, bw, tx, ty;
     std::vector<double> gr, gnx, gny, gk, g3, g4;
     std::vector<int8_t> gs;
     vp_status s;
-#define DL(v, ptr, n, name)                                            \
-    if ((s = download(v, ptr, n, name)) != VP_OK) return bail(s);
-    DL(sx, src_x, n_src, "src_x");
-    DL(sy, src_y, n_src, "src_y");
-    DL(sw, src_w, n_src, "src_w");
     const bool need_b = (o.kinds & (VP_KIND_S | VP_KIND_D)) != 0;
-    DL(bx, bnd_x, need_b ? n_bnd : 0, "bnd_x");
-    DL(by, bnd_y, need_b ? n_bnd : 0, "bnd_y");
-    DL(bnx, bnd_nx, need_b ? n_bnd : 0, "bnd_nx");
-    DL(bny, bnd_ny, need_b ? n_bnd : 0, "bnd_ny");
-    DL(bw, bnd_w, need_b ? n_bnd : 0, "bnd_w");
-    DL(tx, tgt_x, n_tgt, "tgt_x");
-    DL(ty, tgt_y, n_tgt, "tgt_y");
-    if (n_tgt) {
-        DL(gr, geom->r, n_tgt, "geom.r");
-        DL(gnx, geom->nx, n_tgt, "geom.nx");
-        DL(gny, geom->ny, n_tgt, "geom.ny");
-        DL(gk, geom->kappa, n_tgt, "geom.kappa");
-        if (geom->gamma3) DL(g3, geom->gamma3, n_tgt, "geom.gamma3");
-        if (geom->gamma4) DL(g4, geom->gamma4, n_tgt, "geom.gamma4");
-        if ((s = download(gs, geom->sgn, n_tgt, "geom.sgn")) != VP_OK) return bail(s);
+    {
+        struct Item {
+            std::vector<double>* v;
+            const double* src;
+            int64_t n;
+            const char* name;
+        };
+        std::vector<Item> items = {{&sx, src_x, n_src, "src_x"}, {&sy, src_y, n_src, "src_y"},
+                                   {&sw, src_w, n_src, "src_w"}, {&tx, tgt_x, n_tgt, "tgt_x"},
+                                   {&ty, tgt_y, n_tgt, "tgt_y"}};
+        if (need_b)
+            for (Item it : {Item{&bx, bnd_x, n_bnd, "bnd_x"}, Item{&by, bnd_y, n_bnd, "bnd_y"},
+                            Item{&bnx, bnd_nx, n_bnd, "bnd_nx"}, Item{&bny, bnd_ny, n_bnd, "bnd_ny"},
+                            Item{&bw, bnd_w, n_bnd, "bnd_w"}})
+                items.push_back(it);
+        if (n_tgt) {
+            for (Item it : {Item{&gr, geom->r, n_tgt, "geom.r"}, Item{&gnx, geom->nx, n_tgt, "geom.nx"},
+                            Item{&gny, geom->ny, n_tgt, "geom.ny"}, Item{&gk, geom->kappa, n_tgt, "geom.kappa"}})
+                items.push_back(it);
+            if (geom->gamma3) items.push_back({&g3, geom->gamma3, n_tgt, "geom.gamma3"});
+            if (geom->gamma4) items.push_back({&g4, geom->gamma4, n_tgt, "geom.gamma4"});
+        }
+        for (const Item& it : items) {
+            if (it.n > 0 && !it.src) return bail(fail(VP_ERR_ARG, std::string(it.name) + " is NULL"));
+            it.v->resize(it.n);
+        }
+        std::vector<hipError_t> err(items.size(), hipSuccess);
+        parallel_ranges((int64_t)items.size(), 1, [&](int64_t b, int64_t e) {
+            for (int64_t k = b; k < e; ++k)
+                if (items[k].n > 0)
+                    err[k] = hipMemcpy(items[k].v->data(), items[k].src, items[k].n * sizeof(double),
+                                       hipMemcpyDeviceToHost);
+        });
+        for (size_t k = 0; k < items.size(); ++k)
+            if (err[k] != hipSuccess)
+                return bail(fail(VP_ERR_DEVICE, std::string(items[k].name) + ": " + hipGetErrorString(err[k])));
+        if (n_tgt && (s = download(gs, geom->sgn, n_tgt, "geom.sgn")) != VP_OK) return bail(s);
     }
-#undef DL
     if (!need_b) p->n_bnd = 0;
     for (auto* v : {&sx, &sy, &sw, &bx, &by, &bnx, &bny, &bw, &tx, &ty, &gr, &gnx, &gny, &gk, &g3, &g4})
         if (!all_finite(*v)) return bail(fail(VP_ERR_ARG, "non-finite input value"));
-    for (double v : sw)
-        if (v < 0) return bail(fail(VP_ERR_ARG, "negative volume weight"));
-    for (double v : bw)
-        if (v < 0) return bail(fail(VP_ERR_ARG, "negative boundary weight"));
-    for (double v : gr)
-        if (v < 0) return bail(fail(VP_ERR_ARG, "negative target distance r"));
-    for (int8_t v : gs)
-        if (v < -1 || v > 1) return bail(fail(VP_ERR_ARG, "sgn must be -1, 0 or +1"));
+    auto negative = [](double v) { return v < 0; };
+    if (any_parallel(sw, negative)) return bail(fail(VP_ERR_ARG, "negative volume weight"));
+    if (any_parallel(bw, negative)) return bail(fail(VP_ERR_ARG, "negative boundary weight"));
+    if (any_parallel(gr, negative)) return bail(fail(VP_ERR_ARG, "negative target distance r"));
+    if (any_parallel(gs, [](int8_t v) { return v < -1 || v > 1; }))
+        return bail(fail(VP_ERR_ARG, "sgn must be -1, 0 or +1"));
 
     // ---- delta_1 (Sec. 6: delta = 3 dx^2, dx^2 = sum w / N)
     double dx2;
