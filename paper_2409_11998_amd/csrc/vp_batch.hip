@@ -99,13 +99,14 @@ __global__ __launch_bounds__(kThreads) void kg_zero(const InstDesc* __restrict__
     int i, l, u;
     if (it >= t.nitems || !decode(t, it, i, l, u)) return;
     const LevelDesc D = desc(lv, 2 * i + l);
-    const int64_t n = (int64_t)D.g.F * D.g.F;
+    const int64_t n = (int64_t)(D.g.rd1 - D.g.rd0) * D.g.F;  // the rows the spread writes
+    const size_t o = (size_t)D.g.rd0 * D.g.F;
     const int64_t i0 = (int64_t)u * kZeroChunk;
     for (int64_t k = i0 + threadIdx.x; k < i0 + kZeroChunk; k += blockDim.x) {
-        dev::dev_zero<R>((R*)D.grid, n, k);
+        dev::dev_zero<R>((R*)D.grid + o, n, k);
         if (D.dgrid[0]) {
-            dev::dev_zero<R>((R*)D.dgrid[0], n, k);
-            dev::dev_zero<R>((R*)D.dgrid[1], n, k);
+            dev::dev_zero<R>((R*)D.dgrid[0] + o, n, k);
+            dev::dev_zero<R>((R*)D.dgrid[1] + o, n, k);
         }
     }
     if (l == 0 && u == 0) {  // the instance's accumulators, once
@@ -394,10 +395,10 @@ vp_status group_build(const std::vector<const Plan*>& plans, const std::vector<W
         for (int l = 0; l < 2; ++l) {
             const LevelGeom& g = p.lv[l];
             const LevelBufs& lb = p.lb[l];
-            G.zero.add(i, l, (int)(((int64_t)g.F * g.F + kZeroChunk - 1) / kZeroChunk));
-            G.row.add(i, l, g.F);
+            G.zero.add(i, l, (int)(((int64_t)(g.rd1 - g.rd0) * g.F + kZeroChunk - 1) / kZeroChunk));
+            G.row.add(i, l, g.rd1 - g.rd0);
             G.col.add(i, l, g.M + 1);
-            G.c2r.add(i, l, g.F);
+            G.c2r.add(i, l, g.rt1 - g.rt0);
             G.row.lds = std::max(G.row.lds, row_fft_lds_bytes(p, l));
             G.c2r.lds = G.row.lds;
             G.col.lds = std::max(G.col.lds, col_fft_lds_bytes(p, l));
@@ -423,7 +424,7 @@ vp_status group_build(const std::vector<const Plan*>& plans, const std::vector<W
             if (G.lv[2 * i + l].dgrid[0] && (args[i].mu || (kinds & VP_KIND_D)) && p.n_bnd > 0)
                 for (int c = 1; c <= 2; ++c) {
                     sp.add(i, l + 2 * c, sp_items);
-                    G.row.add(i, l + 2 * c, g.F);
+                    G.row.add(i, l + 2 * c, g.rd1 - g.rd0);
                     G.colf.add(i, l + 2 * c, g.M + 1);
                     G.colf.lds = std::max(G.colf.lds, col_fft_lds_bytes(p, l));
                 }

@@ -1100,7 +1100,7 @@ __device__ void dev_row_r2c(unsigned char* smem_raw, const LevelGeom& g, const R
     const int N = F >> 1;
     const int logN = g.logF - 1;
     const int M = g.M;
-    const int row = unit;
+    const int row = g.rd0 + unit;  // the rows the spread wrote
     const R* x = grid + (size_t)row * F;
     for (int n = threadIdx.x; n < N; n += blockDim.x) z[lds_pad(bitrev(n, logN))] = {x[2 * n], x[2 * n + 1]};
     __syncthreads();
@@ -1163,7 +1163,9 @@ __device__ void dev_col(unsigned char* smem_raw, const LevelGeom& g, cplx<R>* __
         if (zero_dc && m1 == 0 && q == 0) t = R(0);
         return t;
     };
-    for (int q = threadIdx.x; q < F; q += blockDim.x) z[lds_pad(bitrev(q, logF))] = col[q];
+    // rows outside [rd0, rd1) hold no spread data (the row pass skipped them): zero
+    for (int q = threadIdx.x; q < F; q += blockDim.x)
+        z[lds_pad(bitrev(q, logF))] = (q >= g.rd0 && q < g.rd1) ? col[q] : cplx<R>{R(0), R(0)};
     R mv[kColPre];
 #pragma unroll
     for (int k = 0; k < kColPre; ++k) {
@@ -1210,7 +1212,7 @@ __device__ void dev_col(unsigned char* smem_raw, const LevelGeom& g, cplx<R>* __
         __syncthreads();
         run(tw);
     }
-    for (int q = threadIdx.x; q < F; q += blockDim.x) col[q] = z[lds_pad(bitrev(q, logF))];
+    for (int q = g.rt0 + (int)threadIdx.x; q < g.rt1; q += blockDim.x) col[q] = z[lds_pad(bitrev(q, logF))];
 }
 
 // Forward transform along y of column m1 = unit, in place, natural order out
@@ -1223,7 +1225,8 @@ __device__ void dev_col_fwd(unsigned char* smem_raw, const LevelGeom& g, cplx<R>
     const int F = g.F;
     const int logF = g.logF;
     cplx<R>* col = spec + (size_t)unit * F;
-    for (int q = threadIdx.x; q < F; q += blockDim.x) z[lds_pad(bitrev(q, logF))] = col[q];
+    for (int q = threadIdx.x; q < F; q += blockDim.x)
+        z[lds_pad(bitrev(q, logF))] = (q >= g.rd0 && q < g.rd1) ? col[q] : cplx<R>{R(0), R(0)};
     __syncthreads();
     lds_fft(z, logF, tw, 1, false);
     for (int q = threadIdx.x; q < F; q += blockDim.x) col[q] = z[lds_pad(q)];
@@ -1241,7 +1244,7 @@ __device__ void dev_row_c2r(unsigned char* smem_raw, const LevelGeom& g, const c
     const int N = F >> 1;
     const int logN = g.logF - 1;
     const int M = g.M;
-    const int row = unit;
+    const int row = g.rt0 + unit;  // the rows the interpolation reads
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         cplx<R> a = {R(0), R(0)};
         cplx<R> b = {R(0), R(0)};

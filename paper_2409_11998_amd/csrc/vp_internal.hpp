@@ -64,6 +64,12 @@ struct LevelGeom {
     // two more grids, whose spectra enter the column pass as -i k_1 B_1 - i k_2 B_2 (float32
     // far-history levels; elsewhere the double layer goes through the kernel derivative).
     int dip;
+    // Grid rows the history chain must handle: the spread writes only rows [rd0, rd1) (the
+    // nodes' supports) and the interpolation reads only rows [rt0, rt1) (the targets'
+    // supports, plus the zero-weight row below each odd-width support).  Zeroing and the
+    // forward row pass cover the first band, the inverse row pass the second; the column
+    // pass reads the first and writes the second.
+    int rd0, rd1, rt0, rt1;
 };
 
 // A tile-sorted list of points of one level (CSR by tile): each point appears

@@ -215,20 +215,28 @@ static int dip_level(const Plan& p, const Workspace& ws)
 
 hipError_t launch_zero(const Plan& p, const Workspace& ws, hipStream_t st)
 {
-    // a level without a grid in ws (the planner's level timing) is skipped
-    const int64_t n0 = ws.grid[0] ? (int64_t)p.lv[0].F * p.lv[0].F : 0;
-    const int64_t n1 = ws.grid[1] ? (int64_t)p.lv[1].F * p.lv[1].F : 0;
+    // the rows the spread writes, [rd0, rd1) of each level (the others are never
+    // read); a level without a grid in ws (the planner's level timing) is skipped
+    auto band = [&](int l) { return (int64_t)(p.lv[l].rd1 - p.lv[l].rd0) * p.lv[l].F; };
+    auto first = [&](int l) { return (size_t)p.lv[l].rd0 * p.lv[l].F; };
+    const int64_t n0 = ws.grid[0] ? band(0) : 0;
+    const int64_t n1 = ws.grid[1] ? band(1) : 0;
     const int dl = dip_level(p, ws);
-    const int64_t nd = dl >= 0 ? (int64_t)p.lv[dl].F * p.lv[dl].F : 0;
+    const int64_t nd = dl >= 0 ? band(dl) : 0;
+    const size_t od = dl >= 0 ? first(dl) : 0;
     const unsigned blocks = grid_for(std::max<int64_t>({n0, n1, nd, (int64_t)kSmaxEntries}));
     if (p.precision == VP_FP32)
-        hipLaunchKernelGGL(k_zero<float>, dim3(blocks), dim3(kThreads), 0, st, (float*)ws.grid[0], n0,
-                           (float*)ws.grid[1], n1, (float*)(dl >= 0 ? ws.dgrid[0] : nullptr),
-                           (float*)(dl >= 0 ? ws.dgrid[1] : nullptr), nd, ws.dc, ws.smax);
+        hipLaunchKernelGGL(k_zero<float>, dim3(blocks), dim3(kThreads), 0, st,
+                           ws.grid[0] ? (float*)ws.grid[0] + first(0) : nullptr, n0,
+                           ws.grid[1] ? (float*)ws.grid[1] + first(1) : nullptr, n1,
+                           dl >= 0 ? (float*)ws.dgrid[0] + od : nullptr, dl >= 0 ? (float*)ws.dgrid[1] + od : nullptr,
+                           nd, ws.dc, ws.smax);
     else
-        hipLaunchKernelGGL(k_zero<double>, dim3(blocks), dim3(kThreads), 0, st, (double*)ws.grid[0], n0,
-                           (double*)ws.grid[1], n1, (double*)(dl >= 0 ? ws.dgrid[0] : nullptr),
-                           (double*)(dl >= 0 ? ws.dgrid[1] : nullptr), nd, ws.dc, ws.smax);
+        hipLaunchKernelGGL(k_zero<double>, dim3(blocks), dim3(kThreads), 0, st,
+                           ws.grid[0] ? (double*)ws.grid[0] + first(0) : nullptr, n0,
+                           ws.grid[1] ? (double*)ws.grid[1] + first(1) : nullptr, n1,
+                           dl >= 0 ? (double*)ws.dgrid[0] + od : nullptr,
+                           dl >= 0 ? (double*)ws.dgrid[1] + od : nullptr, nd, ws.dc, ws.smax);
     return hipGetLastError();
 }
 
@@ -357,7 +365,8 @@ static LevelPair<R> level_pair(const Plan& p, const Workspace& ws, int level, in
     return P;
 }
 
-static int rows_of(const LevelGeom& g) { return g.F; }
+static int rows_of(const LevelGeom& g) { return g.rd1 - g.rd0; }   // forward row pass: the spread's rows
+static int trows_of(const LevelGeom& g) { return g.rt1 - g.rt0; }  // inverse row pass: the targets' rows
 static int cols_of(const LevelGeom& g) { return g.M + 1; }
 
 static size_t pair_lds(const Plan& p, int level, size_t (*lds)(const Plan&, int))
@@ -373,7 +382,9 @@ template <typename R>
 static hipError_t row_fft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool dip_used)
 {
     const LevelPair<R> P = level_pair<R>(p, ws, level, rows_of, dip_used);
-    hipLaunchKernelGGL(k_row_r2c<R>, dim3(P.total()), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st, P);
+    if (P.total() > 0)
+        hipLaunchKernelGGL(k_row_r2c<R>, dim3(P.total()), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st,
+                           P);
     return hipGetLastError();
 }
 
@@ -417,8 +428,10 @@ hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, in
 template <typename R>
 static hipError_t row_ifft_t(const Plan& p, const Workspace& ws, hipStream_t st, int level)
 {
-    const LevelPair<R> P = level_pair<R>(p, ws, level, rows_of, false);
-    hipLaunchKernelGGL(k_row_c2r<R>, dim3(P.total()), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st, P);
+    const LevelPair<R> P = level_pair<R>(p, ws, level, trows_of, false);
+    if (P.total() > 0)
+        hipLaunchKernelGGL(k_row_c2r<R>, dim3(P.total()), dim3(kThreads), pair_lds(p, level, row_fft_lds_bytes), st,
+                           P);
     return hipGetLastError();
 }
 

@@ -36,22 +36,33 @@ namespace {
 
 thread_local std::string g_last_error;
 
-// Host loops over millions of points or thousands of tiles run on up to 16
-// threads, each on its own contiguous range [b, e) of [0, n) (no shared
-// writes); ranges shorter than grain stay on the calling thread.
+// Host loops over millions of points or thousands of tiles run on up to
+// kHostParts threads, each on its own contiguous range [b, e) of [0, n) (no
+// shared writes); ranges shorter than grain stay on the calling thread.
+// parallel_parts also passes the range's index k < kHostParts, so that each
+// range can keep a partial result in a slot of its own.
+constexpr int kHostParts = 16;
+
 template <typename Fn>
-void parallel_ranges(int64_t n, int64_t grain, Fn&& fn)
+void parallel_parts(int64_t n, int64_t grain, Fn&& fn)
 {
     const int64_t hw = std::max(1u, std::thread::hardware_concurrency());
-    const int64_t nt = std::min<int64_t>(std::min<int64_t>(hw, 16), (n + grain - 1) / std::max<int64_t>(grain, 1));
+    const int64_t nt =
+        std::min<int64_t>(std::min<int64_t>(hw, kHostParts), (n + grain - 1) / std::max<int64_t>(grain, 1));
     if (nt <= 1) {
-        fn((int64_t)0, n);
+        fn(0, (int64_t)0, n);
         return;
     }
     std::vector<std::thread> th;
     th.reserve(nt);
-    for (int64_t k = 0; k < nt; ++k) th.emplace_back([&fn, n, nt, k] { fn(n * k / nt, n * (k + 1) / nt); });
+    for (int64_t k = 0; k < nt; ++k) th.emplace_back([&fn, n, nt, k] { fn((int)k, n * k / nt, n * (k + 1) / nt); });
     for (auto& t : th) t.join();
+}
+
+template <typename Fn>
+void parallel_ranges(int64_t n, int64_t grain, Fn&& fn)
+{
+    parallel_parts(n, grain, [&fn](int, int64_t b, int64_t e) { fn(b, e); });
 }
 
 vp_status fail(vp_status s, const std::string& msg)
@@ -88,12 +99,11 @@ double ksum(const double* a, int64_t n)
 template <typename T, typename Pred>
 bool any_parallel(const std::vector<T>& v, Pred pred)
 {
-    std::vector<char> hit(16, 0);
-    const int64_t n = (int64_t)v.size();
-    parallel_ranges(n, 1 << 18, [&](int64_t b, int64_t e) {
+    std::vector<char> hit(kHostParts, 0);
+    parallel_parts((int64_t)v.size(), 1 << 18, [&](int k, int64_t b, int64_t e) {
         bool h = false;
         for (int64_t i = b; i < e && !h; ++i) h = pred(v[i]);
-        if (h) hit[(size_t)(b * 16 / std::max<int64_t>(n, 1)) & 15] = 1;
+        hit[k] = h;
     });
     for (char c : hit)
         if (c) return true;
@@ -306,8 +316,8 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
     j0.resize(n);
     sx.resize(n);
     sy.resize(n);
-    std::vector<char> outside(16, 0);  // per range: a support left the grid
-    parallel_ranges((int64_t)n, 1 << 16, [&](int64_t b, int64_t e) {
+    std::vector<char> outside(kHostParts, 0);  // per range: a support left the grid
+    parallel_parts((int64_t)n, 1 << 16, [&](int part, int64_t b, int64_t e) {
         bool out = false;
         for (int64_t q = b; q < e; ++q) {
             const int k = ids[q];
@@ -324,7 +334,7 @@ vp_status build_records(Plan& p, int l, const std::vector<double>& x, const std:
             sx[q] = (R)(ax - tx + 0.5 * w);   // fractional offset in [0, 1)
             sy[q] = (R)(ay - ty + 0.5 * w);
         }
-        if (out) outside[(size_t)(b * 16 / std::max<int64_t>((int64_t)n, 1)) & 15] = 1;
+        outside[part] = out;
     });
     for (char c : outside)
         if (c) return fail(VP_ERR_INTERNAL, "support outside the fine grid (planner margin)");
@@ -743,6 +753,38 @@ vp_status build_level(Plan& p, int l, const std::vector<double>& sxv, const std:
     if ((s = build_records<R>(p, l, sxv, syv, vol_ids, &b.vol)) != VP_OK) return s;
     if ((s = build_records<R>(p, l, sxv, syv, bnd_ids, &b.bnd)) != VP_OK) return s;
     if ((s = build_records<R>(p, l, tx, ty, tids, &b.tgt, p.lv[l].Ti + p.lv[l].w - 1, p.lv[l].Ti)) != VP_OK) return s;
+    // row bands: the supports' corner rows j0 of the records (spread: rows j0 .. j0 + w - 1;
+    // interpolation: also row j0 + w, which an odd-width support reads with weight zero)
+    {
+        LevelGeom& g = p.lv[l];
+        auto rows = [&](const RecList& L, int& lo, int& hi) {
+            std::vector<int> plo(kHostParts, INT32_MAX), phi(kHostParts, -1);  // per range
+            parallel_parts((int64_t)L.h_ij.size(), 1 << 16, [&](int part, int64_t b0, int64_t b1) {
+                int a = INT32_MAX, z = -1;
+                for (int64_t r = b0; r < b1; ++r) {
+                    const int j0 = L.h_ij[r] >> 16;
+                    a = std::min(a, j0);
+                    z = std::max(z, j0);
+                }
+                plo[part] = a;
+                phi[part] = z;
+            });
+            for (int k = 0; k < kHostParts; ++k) {
+                lo = std::min(lo, plo[k]);
+                hi = std::max(hi, phi[k]);
+            }
+        };
+        int lo = INT32_MAX, hi = -1;
+        rows(b.vol, lo, hi);
+        rows(b.bnd, lo, hi);
+        g.rd0 = hi >= 0 ? lo : 0;
+        g.rd1 = hi >= 0 ? std::min(g.F, hi + g.w) : 0;
+        lo = INT32_MAX;
+        hi = -1;
+        rows(b.tgt, lo, hi);
+        g.rt0 = hi >= 0 ? lo : 0;
+        g.rt1 = hi >= 0 ? std::min(g.F, hi + g.w + 1) : 0;
+    }
     if ((s = build_units(p, l)) != VP_OK) return s;
     if ((s = build_level_tables<R>(p, l, p.delta1, p.delta2)) != VP_OK) return s;
     return VP_OK;
@@ -1231,8 +1273,8 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
         }
         auto scan = [&](const std::vector<double>& X, const std::vector<double>& Y) {
             const int64_t n = (int64_t)X.size();
-            std::vector<double> plo(16 * nd, INFINITY), phi(16 * nd, -INFINITY);  // per range
-            parallel_ranges(n, 1 << 16, [&](int64_t b, int64_t e) {
+            std::vector<double> plo(kHostParts * nd, INFINITY), phi(kHostParts * nd, -INFINITY);  // per range
+            parallel_parts(n, 1 << 16, [&](int part, int64_t b, int64_t e) {
                 double l2[nd], h2[nd], c2[nd], s2[nd];  // this range's extremes, in registers
                 for (int d = 0; d < nd; ++d) {
                     l2[d] = INFINITY;
@@ -1250,13 +1292,12 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
                         h2[d] = std::max(h2[d], v);
                     }
                 }
-                const int64_t part = b * 16 / std::max<int64_t>(n, 1);
                 for (int d = 0; d < nd; ++d) {
                     plo[part * nd + d] = l2[d];
                     phi[part * nd + d] = h2[d];
                 }
             });
-            for (int k = 0; k < 16; ++k)
+            for (int k = 0; k < kHostParts; ++k)
                 for (int d = 0; d < nd; ++d) {
                     lo[d] = std::min(lo[d], plo[k * nd + d]);
                     hi[d] = std::max(hi[d], phi[k * nd + d]);
