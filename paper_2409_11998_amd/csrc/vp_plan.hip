@@ -774,16 +774,34 @@ vp_status build_level(Plan& p, int l, const std::vector<double>& sxv, const std:
                 hi = std::max(hi, phi[k]);
             }
         };
+        // A band starts on a multiple of 8 rows and spans a multiple of 64: the row passes map
+        // blocks to XCDs in contiguous eighths only when the row count is a multiple of 8, and
+        // then each eighth starts on a 128-byte line of the column-major spectrum (8 complex
+        // float64 values), so no line is shared by two XCDs' L2s (a 1780-row band without this
+        // ran the float64 inverse row pass at 0.053 ms against 0.029 ms for all 2048 rows).
+        auto align = [&](int a, int z, int& b0, int& b1) {
+            if (z <= a) {
+                b0 = b1 = 0;
+                return;
+            }
+            b0 = a & ~7;
+            const int c = (z - b0 + 63) & ~63;
+            if (c >= g.F) {
+                b0 = 0;
+                b1 = g.F;
+                return;
+            }
+            b0 = std::min(b0, g.F - c);
+            b1 = b0 + c;
+        };
         int lo = INT32_MAX, hi = -1;
         rows(b.vol, lo, hi);
         rows(b.bnd, lo, hi);
-        g.rd0 = hi >= 0 ? lo : 0;
-        g.rd1 = hi >= 0 ? std::min(g.F, hi + g.w) : 0;
+        align(lo, hi >= 0 ? std::min(g.F, hi + g.w) : lo, g.rd0, g.rd1);
         lo = INT32_MAX;
         hi = -1;
         rows(b.tgt, lo, hi);
-        g.rt0 = hi >= 0 ? lo : 0;
-        g.rt1 = hi >= 0 ? std::min(g.F, hi + g.w + 1) : 0;
+        align(lo, hi >= 0 ? std::min(g.F, hi + g.w + 1) : lo, g.rt0, g.rt1);
     }
     if ((s = build_units(p, l)) != VP_OK) return s;
     if ((s = build_level_tables<R>(p, l, p.delta1, p.delta2)) != VP_OK) return s;
