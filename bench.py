@@ -173,7 +173,7 @@ def stage_times(torch, plan, fn, steps):
 
 
 def run_leg(torch, P, kinds, tol, precision, steps, warmup, oracle_sample, seed, autotune=True, sample=None,
-            reference=None):
+            reference=None, tile=0):
     """Plan (autotuned), warm up, time `steps` evaluations, then a timing pass for the stage
     times.  oracle_sample > 0: the oracle at that many seeded targets (its time is the CPU
     baseline).  sample = (idx, values): e_inf on those targets; reference: e_inf on all."""
@@ -181,7 +181,8 @@ def run_leg(torch, P, kinds, tol, precision, steps, warmup, oracle_sample, seed,
     dev = to_device(P)
     mask = (1 if "V" in kinds else 0) | (2 if "S" in kinds else 0) | (4 if "D" in kinds else 0)
     t0 = time.perf_counter()
-    plan = make_plan(dev, tol=tol, precision=precision, kinds=mask, autotune=autotune)
+    plan = make_plan(dev, tol=tol, precision=precision, kinds=mask, autotune=autotune,
+                     **({"tile": tile} if tile else {}))
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = plan.info()
@@ -250,6 +251,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--serve-loads", type=str, default="0.2,0.5,0.8,0.95",
                     help="arrival rates as fractions of the saturated rate")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="headline leg: restrict the autotuner to this spreading tile edge (profiling runs, "
+                         "so that every pass launches the kernels an unprofiled run picks)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -293,7 +297,7 @@ def main():
     log("bench: generating square-200k workload")
     P = config_problem(2, scale=args.scale)
     log("bench: fp64 V+D leg, n_tgt=%d n_bnd=%d" % (P.n_tgt, P.n_bnd))
-    r64 = run_leg(torch, P, "VD", 1e-10, 1, args.steps, args.warmup, args.oracle_sample, seed=20)
+    r64 = run_leg(torch, P, "VD", 1e-10, 1, args.steps, args.warmup, args.oracle_sample, seed=20, tile=args.tile)
     value = P.n_tgt * args.steps / r64["elapsed"]
     ms = 1000.0 * r64["elapsed"] / args.steps
     alg = algorithmic_bytes(r64["info"], P, "VD", 8)

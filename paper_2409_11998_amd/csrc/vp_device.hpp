@@ -1272,19 +1272,41 @@ __device__ void dev_row_c2r(unsigned char* smem_raw, const LevelGeom& g, const c
 // Interpolation (type-2, Sec. 3 Step 4 via the NUFFT): one workgroup per tile
 // stages the (T+w-1)^2 grid window in LDS (a target's support lies in the
 // window because the target is filed under the tile of its support corner).
-// Each wavefront takes chunks of 32 targets, two lanes per target: lane
-// (target q, coordinate c) evaluates the w kernel values of q's offset along
-// c (tap pairs a, w-1-a from one polynomial in u^2; the coefficients are the
-// same for every lane, so they come through scalar loads) into LDS, then the
-// lane sums half of q's support rows (odd w: the second half ends on a zero
-// row below the window, with weight zero, so both halves run alike).
+// Each wavefront takes chunks of 32 targets, two lanes per target, 32 apart:
+// lane (target q, coordinate c) evaluates the w kernel values of q's offset
+// along c in registers (tap pairs a, w-1-a from one polynomial in u^2; the
+// coefficients are the same for every lane, so they come through scalar
+// loads), the two lanes swap their values with v_permlane32_swap, and each
+// sums half of q's support rows (odd w: the second half ends on a zero row
+// below the window, with weight zero, so both halves run alike).  The LDS
+// holds the window only.
 constexpr int kInterpTargets = 32;  // targets per wavefront chunk
 
 __host__ __device__ inline size_t interp_lds_bytes(int T, int W, size_t rb)
 {
     const size_t E = (size_t)(T + W - 1);
-    const size_t win = ((E + 1) * E * rb + 15) & ~(size_t)15;  // window rows and the zero row
-    return win + (size_t)(kThreads / 64) * kInterpTargets * (2 * W + 1) * rb;
+    return ((E + 1) * E * rb + 15) & ~(size_t)15;  // window rows and the zero row
+}
+
+// The value of v held by lane l ^ 32 (the other half of the wavefront).
+// v_permlane32_swap(a, b) exchanges the upper 32 lanes of a with the lower 32
+// lanes of b; with a = b = v, the lower lanes find the upper lanes' values in
+// the second result and the upper lanes find the lower lanes' in the first.
+__device__ __forceinline__ unsigned lane_xor32(unsigned v, bool upper)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return upper ? r[0] : r[1];
+}
+__device__ __forceinline__ float lane_xor32(float v, bool upper)
+{
+    return __builtin_bit_cast(float, lane_xor32(__builtin_bit_cast(unsigned, v), upper));
+}
+__device__ __forceinline__ double lane_xor32(double v, bool upper)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = lane_xor32((unsigned)b, upper);
+    const unsigned hi = lane_xor32((unsigned)(b >> 32), upper);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 template <typename R, int W>
@@ -1295,8 +1317,7 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
     using TT = typename TapT<R>::T;
     constexpr int P = interp_terms(W, sizeof(R) == 4);
     constexpr int NT = kInterpTargets;
-    constexpr int VS = 2 * W + 1;  // odd stride: the targets' rows fall in different LDS banks
-    constexpr int HB = (W + 1) / 2;  // rows per half; slot 2W of a target holds the zero row's weight
+    constexpr int HB = (W + 1) / 2;  // rows per half (odd w: the last row of the second half is the zero row)
     constexpr int NP = (W + 1) / 2;  // tap pairs (the middle tap of odd w pairs with itself)
     const int t = unit.tile;
     const int r0 = unit.a0;
@@ -1308,8 +1329,6 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
     R* reg = reinterpret_cast<R*>(smem_raw);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    R* vals = reinterpret_cast<R*>(smem_raw + (((size_t)(E + 1) * E * sizeof(R) + 15) & ~(size_t)15)) +
-              (size_t)wv * (NT * VS);
     const int gx0 = (t % g.ntxi) * T;
     const int gy0 = (t / g.ntxi) * T;
     // window rows 0..E-1 from the grid, row E zero (32 lanes per row, no division)
@@ -1326,40 +1345,43 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
     // Each half-wavefront thus reads one relative row of 32 targets, whose window
     // offsets the target order makes distinct modulo 32: 32 different LDS banks.
     const int q = lane & 31;
-    const int half = lane >> 5;
-    R* const v = vals + q * VS;
+    const bool upper = lane >= 32;
     for (int base = r0 + wv * NT; base < r1; base += (kThreads / 64) * NT) {
-        const bool on = q < r1 - base;
+        const bool on = q < r1 - base;  // the same for both lanes of a target
         int p = 0, id = 0;
+        R own[W];  // this lane's kernel values along its coordinate
+#pragma unroll
+        for (int a = 0; a < W; ++a) own[a] = R(0);
         if (on) {
             p = L.ij[base + q];
             id = L.idx[base + q];
-            const TT u = TT(2) * (TT)(half ? L.dy[base + q] : L.dx[base + q]) - TT(1);
+            const TT u = TT(2) * (TT)(upper ? L.dy[base + q] : L.dx[base + q]) - TT(1);
             TT pw[(P + 1) / 2];
             pw[0] = TT(1);
             pw[1] = u * u;
 #pragma unroll
             for (int k = 2; k < (P + 1) / 2; ++k) pw[k] = pw[k - 1] * pw[1];
-            R* dst = v + half * W;
 #pragma unroll
             for (int kp = 0; kp < NP; ++kp) {
                 TT va, vm;
                 tap_pair_pow<P>(coef + kp * P, pw, u, va, vm);
-                dst[kp] = (R)va;
-                if (kp != W - 1 - kp) dst[W - 1 - kp] = (R)vm;
+                own[kp] = (R)va;
+                if (kp != W - 1 - kp) own[W - 1 - kp] = (R)vm;
             }
-            if ((W & 1) && half) dst[W] = R(0);
         }
-        wave_sync_lds();
+        // x values for both lanes (the lower lane's own), y weights of each lane's rows
+        R px[W], wy[HB];
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const R o = lane_xor32(own[a], upper);
+            px[a] = upper ? o : own[a];
+            if (a < HB) wy[a] = upper ? (HB + a < W ? own[HB + a] : R(0)) : o;
+        }
         R sum = R(0);
         if (on) {
             const int i0 = (p & 0xffff) - gx0;
             const int j0 = (p >> 16) - gy0;
-            R px[W];
-#pragma unroll
-            for (int a2 = 0; a2 < W; ++a2) px[a2] = v[a2];
-            const R* rowp = reg + (j0 + half * HB) * E + i0;
-            const R* wy = v + W + half * HB;
+            const R* rowp = reg + (j0 + (upper ? HB : 0)) * E + i0;
 #pragma unroll
             for (int bb = 0; bb < HB; ++bb) {
                 R acc = R(0);
@@ -1368,9 +1390,8 @@ __device__ void dev_interp(unsigned char* smem_raw, const LevelGeom& g, const R*
                 sum += wy[bb] * acc;
             }
         }
-        sum += __shfl_xor(sum, 32);
-        if (on && half == 0) hist[id] = sum;
-        wave_sync_lds();
+        sum += lane_xor32(sum, upper);
+        if (on && !upper) hist[id] = sum;
     }
 }
 
