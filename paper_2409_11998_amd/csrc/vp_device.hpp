@@ -1421,6 +1421,10 @@ struct LocalArgs {
     double dc_weight;        // sum over levels of the zero-mode weight (float32 path)
     const double* dc;        // float64 sum of channel-0 strengths
     double* out;
+    // kLocalAll: out = history values + zero mode + local part; kLocalPart: out = local part
+    // only (it needs neither history level, so it can run beside them); kLocalAddHistory:
+    // out = history values + zero mode + out (after a kLocalPart pass)
+    int part;
 };
 
 // Sum of the kDcParts zero-frequency partial sums, by one wavefront (every
@@ -1495,16 +1499,23 @@ __device__ inline double d_local_value(double d, double r, double sg, double kap
 
 __device__ void dev_local(const LocalArgs& a, int64_t i)
 {
-    const double dcv = a.dc ? dc_total(a.dc) : 0.0;  // before any lane leaves
+    const double dcv = a.dc && a.part != kLocalPart ? dc_total(a.dc) : 0.0;  // before any lane leaves
     if (i >= a.n) return;
+    double u = 0.0;
+    if (a.part != kLocalPart) {
+        u = hist_at(a.h0, a.fp32, i) + hist_at(a.h1, a.fp32, i);
+        if (a.dc) u += a.dc_weight * dcv;
+        if (a.part == kLocalAddHistory) {
+            a.out[i] = u + a.out[i];
+            return;
+        }
+    }
     const double SQPI = 1.7724538509055160273;
     const double d = a.delta;
     const double sd = sqrt(d);
     const double r = a.r[i];
     const double c = r / sd;
     const bool near = c <= 12.0;
-    double u = hist_at(a.h0, a.fp32, i) + hist_at(a.h1, a.fp32, i);
-    if (a.dc) u += a.dc_weight * dcv;
     const int64_t n = a.n;
     if (!near) {
         // beyond 12 sqrt(delta): only the interior limit of V_L inside the domain; outside it the

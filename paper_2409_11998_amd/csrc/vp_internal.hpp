@@ -34,6 +34,7 @@ __host__ __device__ constexpr int interp_terms(int w, bool fp32)
 {
     return (w + 2 < (fp32 ? 10 : 13)) ? w + 2 : (fp32 ? 10 : 13);
 }
+constexpr int kLocalAll = 0, kLocalPart = 1, kLocalAddHistory = 2;  // shares of the local kernel's sum
 constexpr int kMmaTile = 16;     // tile edge of the matrix-core spread (window of 32 x 32 cells)
 
 // Launches timed by vp_set_timing, in order: grid zeroing + strengths; spread NH, FH; row FFT NH,
@@ -239,8 +240,11 @@ hipError_t launch_row_fft(const Plan& p, const Workspace& ws, hipStream_t st, in
 hipError_t launch_col_fft(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool dip_used);
 hipError_t launch_row_ifft(const Plan& p, const Workspace& ws, hipStream_t st, int level);
 hipError_t launch_interp(const Plan& p, const Workspace& ws, hipStream_t st, int level);
+// part: which share of the final sum the local kernel writes (kLocalAll: all of it;
+// kLocalPart: the local part alone; kLocalAddHistory: the history values and zero mode
+// added to what a kLocalPart pass wrote)
 hipError_t launch_local(const Plan& p, const Workspace& ws, hipStream_t st, const double* jet6, const double* sig_jet,
-                        const double* mu_jet, bool use_v, bool use_s, bool use_d, double* out);
+                        const double* mu_jet, bool use_v, bool use_s, bool use_d, double* out, int part = kLocalAll);
 size_t row_fft_lds_bytes(const Plan& p, int level);
 size_t col_fft_lds_bytes(const Plan& p, int level);
 size_t spread_lds_bytes(const Plan& p, int level);

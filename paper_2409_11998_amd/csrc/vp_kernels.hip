@@ -475,9 +475,10 @@ hipError_t launch_interp(const Plan& p, const Workspace& ws, hipStream_t st, int
 }
 
 hipError_t launch_local(const Plan& p, const Workspace& ws, hipStream_t st, const double* jet6, const double* sig_jet,
-                        const double* mu_jet, bool use_v, bool use_s, bool use_d, double* out)
+                        const double* mu_jet, bool use_v, bool use_s, bool use_d, double* out, int part)
 {
     LocalArgs a{};
+    a.part = part;
     a.n = p.n_tgt;
     a.delta = p.delta1;
     a.order_v = p.loc.order_v;

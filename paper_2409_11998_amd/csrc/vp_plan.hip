@@ -1056,7 +1056,9 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
     if (!timing) {
         // the two levels are independent from the strengths to the history values:
         // the far-history level's whole chain (spread, FFT passes, interpolation)
-        // runs on the side stream beside the near-history level's
+        // runs on the side stream beside the near-history level's, after the local
+        // part (which needs neither level: memory-bound, it fills the matrix-core
+        // spreads' idle bandwidth); the history values are added at the join
         if (!p.side_made) {
             hipStream_t sd = nullptr;
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1078,6 +1080,8 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
         VP_HIP(launch_strengths(p, ws, st, f, sigma, mu), "strengths");
         VP_HIP(hipEventRecord(p.fork[0], st), "fork");
         VP_HIP(hipStreamWaitEvent(sd, p.fork[0], 0), "fork");
+        VP_HIP(launch_local(p, ws, sd, jet6, sigma_jet3, mu_jet5, use_v, use_s, use_d, out, kLocalPart),
+               "local");
         VP_HIP(launch_spread(p, ws, sd, 1, use_v, use_s || use_d, use_d), "spread");
         VP_HIP(launch_row_fft(p, ws, sd, 1, use_d), "row fft");
         VP_HIP(launch_col_fft(p, ws, sd, 1, use_d), "column fft");
@@ -1090,7 +1094,8 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
         VP_HIP(launch_row_ifft(p, ws, st, 0), "row ifft");
         VP_HIP(launch_interp(p, ws, st, 0), "interp");
         VP_HIP(hipStreamWaitEvent(st, p.fork[1], 0), "join");
-        VP_HIP(launch_local(p, ws, st, jet6, sigma_jet3, mu_jet5, use_v, use_s, use_d, out), "local");
+        VP_HIP(launch_local(p, ws, st, jet6, sigma_jet3, mu_jet5, use_v, use_s, use_d, out, kLocalAddHistory),
+               "history sum");
         return VP_OK;
     }
     auto mark = [&](int k) -> hipError_t { return hipEventRecord(p.ev[k], st); };
