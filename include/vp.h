@@ -78,9 +78,11 @@ typedef struct {
     int kinds;           /* VP_KIND_* bitmask this plan must support (default V|S|D)        */
     int fine_grid[2];    /* force fine-grid sizes F_NH, F_FH (0 = planner's choice)         */
     int spread_width[2]; /* force spreading widths w_NH, w_FH in grid cells (0 = planner)   */
-    int tile;            /* tile edge in grid cells for spread/interp (0 = planner); 16 on a
-                            float32 plan spreads on matrix cores (one 32x32 window of each
-                            tile in the MFMA accumulators), 32 through LDS windows          */
+    int tile;            /* spreading tile edge in grid cells (0 = planner); 16 spreads on
+                            matrix cores (one 32x32 window of each tile in the MFMA
+                            accumulators, either precision), 32 through LDS windows.  The
+                            interpolation bins targets on the same edge, or with autotune on
+                            whichever of 16 and 32 times faster                            */
     void* stream;        /* hipStream_t the plan's work is enqueued on (NULL = null stream) */
     int no_workspace;    /* 1: keep only the plan's resident data (sorted nodes, tables, geometry);
                             every evaluation then takes a stream-ordered workspace (grids,

@@ -1465,7 +1465,8 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
         int best_Ti = 0;
         if (o.autotune) {
             // the interpolation's own tile: the chosen level timed again with each other tile
-            for (int Ti : tiles) {
+            // edge (also when the spreading tile is forced)
+            for (int Ti : {32, 16}) {
                 if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy)) != VP_OK) return bail(s);
                 if (Ti == p->lv[l].T || !set_interp_tile(p->lv[l], Ti) || !level_fits_lds(*p, l)) continue;
                 const size_t mark = p->allocs.size(), bytes0 = p->device_bytes;
