@@ -319,3 +319,35 @@ def test_circle_layers_every_side_and_distance(precision, tol):
     print("precision", precision, "circle layers: e_inf vs oracle", e, "vs closed forms", ex)
     assert e <= tol
     assert ex <= 1e-6
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-10), (0, 1e-6)])
+def test_row_bands_strip_and_outside_targets(precision, tol):
+    """The FFT passes handle only the grid rows that some node's support covers
+    (forward) or some target's support covers (inverse).  Targets in a thin
+    horizontal strip through the disk (a target band far narrower than the
+    nodes'), targets in strips above and below it (rows that no node touches:
+    their history values are the convolution's tails), and both sets in one
+    plan: each against the oracle, and the union's values equal to each part's."""
+    from workloads.problems import disk_at_targets
+    P = disk_problem(2000, seed=3)
+    rng = np.random.default_rng(17)
+    n = 1200
+    inner = (rng.uniform(-0.9, 0.9, n), rng.uniform(-0.02, 0.02, n))
+    ys = rng.uniform(1.5, 1.7, n) * rng.choice([-1.0, 1.0], n)  # beyond 12 sqrt(delta_1) of the circle
+    outer = (rng.uniform(-1.0, 1.0, n), ys)
+    parts = {}
+    for name, (tx, ty) in (("strip", inner), ("outside", outer),
+                           ("union", (np.concatenate([inner[0], outer[0]]), np.concatenate([inner[1], outer[1]])))):
+        Q = disk_at_targets(P, tx, ty)
+        got, plan = _run(Q, "V", tol=tol, precision=precision, kinds=1)
+        plan.close()
+        ref = oracle.evaluate(Q, kinds="V")["V"]
+        e = oracle.rel_linf(got, ref)
+        print(name, "precision", precision, "e_inf", e)
+        assert e <= tol, (name, e)
+        parts[name] = got
+    both = np.concatenate([parts["strip"], parts["outside"]])
+    d = np.max(np.abs(parts["union"] - both)) / np.max(np.abs(both))
+    print("union against the parts", d)
+    assert d <= tol
