@@ -915,8 +915,7 @@ template <int W>
 __device__ void dev_spread_mma64(unsigned char* smem_raw, const LevelGeom& g, const RecView<double>& vol,
                                  const RecView<double>& bnd, const double* __restrict__ str, int64_t n_src,
                                  int64_t n_bnd, double* __restrict__ grid, int use_vol, int use_bnd, int use_d,
-                                 const double* __restrict__ coef, const WorkUnit unit_in,
-                                 const RawStr raw = RawStr{})
+                                 const double* __restrict__ coef, const WorkUnit unit_in)
 {
     constexpr int NT = kM64Terms;
     constexpr int P = horner_terms(W);
@@ -972,25 +971,10 @@ __device__ void dev_spread_mma64(unsigned char* smem_raw, const LevelGeom& g, co
         };
         auto fetch_str = [&](int c0) {
             if (rec < NRC && c0 + rec < r1) {
-                if (raw.w) {  // the strengths pass's products, formed here (same operations)
-                    const double wv = raw.w[p_idx];
-                    if (p_idx < n_src) {
-                        p_s = raw.f ? raw.f[p_idx] * wv : 0.0;
-                    } else {
-                        const int64_t j = p_idx - n_src;
-                        p_s = raw.sigma ? raw.sigma[j] * wv : 0.0;
-                        if (DL) {
-                            const double m = raw.mu[j] * wv;
-                            p_gx = m * raw.nx[j];
-                            p_gy = m * raw.ny[j];
-                        }
-                    }
-                } else {
-                    p_s = str[p_idx];
-                    if (DL) {
-                        p_gx = str[n_all + (p_idx - n_src)];
-                        p_gy = str[n_all + n_bnd + (p_idx - n_src)];
-                    }
+                p_s = str[p_idx];
+                if (DL) {
+                    p_gx = str[n_all + (p_idx - n_src)];
+                    p_gy = str[n_all + n_bnd + (p_idx - n_src)];
                 }
             }
         };

@@ -35,20 +35,6 @@ __host__ __device__ constexpr int interp_terms(int w, bool fp32)
     return (w + 2 < (fp32 ? 10 : 13)) ? w + 2 : (fp32 ? 10 : 13);
 }
 constexpr int kLocalAll = 0, kLocalPart = 1, kLocalAddHistory = 2;  // shares of the local kernel's sum
-
-// The inputs of the node strengths (Sec. 3, Step 2: f w at volume nodes, sigma w_G and
-// mu nu w_G at boundary nodes), for a float64 spread that forms them from its records'
-// node indices instead of reading them from the strengths pass.  w: the node weights
-// (volume nodes, then boundary nodes); nx, ny: the boundary normals; f, sigma or mu may be
-// null (that density absent).  w == nullptr: read the strengths array.
-struct RawStr {
-    const double* f;
-    const double* sigma;
-    const double* mu;
-    const double* w;
-    const double* nx;
-    const double* ny;
-};
 constexpr int kMmaTile = 16;     // tile edge of the matrix-core spread (window of 32 x 32 cells)
 
 // Launches timed by vp_set_timing, in order: grid zeroing + strengths; spread NH, FH; row FFT NH,
@@ -244,10 +230,8 @@ hipError_t launch_strengths(const Plan& p, const Workspace& ws, hipStream_t st, 
                             const double* mu);
 // Grids present in ws, zero-frequency partial sums and strength maxima to zero.
 hipError_t launch_zero(const Plan& p, const Workspace& ws, hipStream_t st);
-// raw: float64 matrix-core levels form the strengths from these inputs (the strengths
-// pass is then not needed for this level); null: read ws.str
 hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool use_vol, bool use_bnd,
-                         bool use_d, const RawStr* raw = nullptr);
+                         bool use_d);
 // FFT passes: level 0 or 1, or both levels in one launch (level < 0).
 // dip_used: the evaluation spread the double layer into the channel grids of a
 // level with dip (their row transforms join the row pass, their column

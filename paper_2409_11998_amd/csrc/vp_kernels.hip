@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kThreads) void k_spread_mma(LevelGeom g, RecView<R>
                                                          const R* __restrict__ str, int64_t n_src, int64_t n_bnd,
                                                          R* __restrict__ grid, int use_vol, int use_bnd, int use_d,
                                                          const double* __restrict__ coef,
-                                                         const WorkUnit* __restrict__ units, int n_units, RawStr raw)
+                                                         const WorkUnit* __restrict__ units, int n_units)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int u = xcd_unit(blockIdx.x, gridDim.x) * (kThreads / 64) + (threadIdx.x >> 6);
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kThreads) void k_spread_mma(LevelGeom g, RecView<R>
         dev_spread_mma<W>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d, coef, units[u]);
     else
         dev_spread_mma64<W>(smem_raw, g, vol, bnd, str, n_src, n_bnd, grid, use_vol, use_bnd, use_d, coef,
-                            units[u], raw);
+                            units[u]);
 }
 
 // The FFT passes of one or two levels (and a level's double-layer channels) in
@@ -259,7 +259,7 @@ size_t spread_lds_bytes(const Plan& p, int level)
 // volume nodes, then boundary nodes); smax: the fixed-point windows' strength bound.
 template <typename R, int W>
 static void spread_launch(const Plan& p, hipStream_t st, int l, size_t lds, const R* str,
-                          const unsigned long long* smax, R* grid, int uv, int ub, int ud, RawStr raw = RawStr{})
+                          const unsigned long long* smax, R* grid, int uv, int ub, int ud)
 {
     const LevelGeom& g = p.lv[l];
     const LevelBufs& b = p.lb[l];
@@ -271,7 +271,7 @@ static void spread_launch(const Plan& p, hipStream_t st, int l, size_t lds, cons
                                   (int)lds);
         hipLaunchKernelGGL((k_spread_mma<R, W>), dim3(nb), dim3(kThreads), lds, st, g, view<R>(b.vol), view<R>(b.bnd),
                            str, p.n_src, p.n_bnd, grid, uv, ub, ud, (const double*)b.horner,
-                           (const WorkUnit*)b.sp_units, (int)nu, raw);
+                           (const WorkUnit*)b.sp_units, (int)nu);
         return;
     }
     (void)hipFuncSetAttribute((const void*)k_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -286,12 +286,12 @@ static void spread_launch(const Plan& p, hipStream_t st, int l, size_t lds, cons
 // second strength maximum (max |mu nu w|_1).
 template <typename R, int W>
 static void spread_level(const Plan& p, const Workspace& ws, hipStream_t st, int l, size_t lds, int uv, int ub,
-                         int ud, RawStr raw)
+                         int ud)
 {
     const R* str = (const R*)ws.str;
     const unsigned long long* smax = ws.smax;
     const bool dip = ud && ub && p.lv[l].dip && ws.dgrid[0];
-    spread_launch<R, W>(p, st, l, lds, str, smax, (R*)ws.grid[l], uv, ub, dip ? 0 : ud, raw);
+    spread_launch<R, W>(p, st, l, lds, str, smax, (R*)ws.grid[l], uv, ub, dip ? 0 : ud);
     if (!dip) return;
     const int64_t n_all = p.n_src + p.n_bnd;
     for (int c = 0; c < 2; ++c)
@@ -301,7 +301,7 @@ static void spread_level(const Plan& p, const Workspace& ws, hipStream_t st, int
 
 template <typename R>
 static hipError_t spread_t(const Plan& p, const Workspace& ws, hipStream_t st, int l, bool use_vol, bool use_bnd,
-                           bool use_d, RawStr raw)
+                           bool use_d)
 {
     const LevelBufs& b = p.lb[l];
     const size_t lds = spread_lds_bytes(p, l);
@@ -311,7 +311,7 @@ static hipError_t spread_t(const Plan& p, const Workspace& ws, hipStream_t st, i
     switch (p.lv[l].w) {
 #define VP_CASE(W)                                               \
     case W:                                                      \
-        spread_level<R, W>(p, ws, st, l, lds, uv, ub, ud, raw);  \
+        spread_level<R, W>(p, ws, st, l, lds, uv, ub, ud);       \
         break;
         VP_W_CASES(VP_CASE)
 #undef VP_CASE
@@ -322,12 +322,10 @@ static hipError_t spread_t(const Plan& p, const Workspace& ws, hipStream_t st, i
 }
 
 hipError_t launch_spread(const Plan& p, const Workspace& ws, hipStream_t st, int level, bool use_vol, bool use_bnd,
-                         bool use_d, const RawStr* raw)
+                         bool use_d)
 {
-    RawStr r{};
-    if (raw && p.precision == VP_FP64 && p.lv[level].mma) r = *raw;  // only the float64 matrix spread forms them
-    return p.precision == VP_FP32 ? spread_t<float>(p, ws, st, level, use_vol, use_bnd, use_d, r)
-                                  : spread_t<double>(p, ws, st, level, use_vol, use_bnd, use_d, r);
+    return p.precision == VP_FP32 ? spread_t<float>(p, ws, st, level, use_vol, use_bnd, use_d)
+                                  : spread_t<double>(p, ws, st, level, use_vol, use_bnd, use_d);
 }
 
 // Entries of a fused FFT launch: level 0 or 1 alone, or both (level < 0);

@@ -1049,12 +1049,6 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
     const bool use_s = sigma != nullptr;
     const bool use_d = mu != nullptr;
     if (!ws.block) return fail(VP_ERR_ARG, "no workspace");
-    // float64 plans whose levels both spread on matrix cores form the node strengths
-    // inside the spreads (nothing else reads them: no zero-mode sum, no fixed-point
-    // scale), so the strengths pass is left out
-    const bool fused = p.precision == VP_FP64 && p.lv[0].mma && p.lv[1].mma;
-    const RawStr raw{f, sigma, mu, p.d_w, p.d_nx, p.d_ny};
-    const RawStr* rs = fused ? &raw : nullptr;
     if (timing && !p.ev_made) {
         for (auto& e : p.ev) VP_HIP(hipEventCreate(&e), "event create");
         p.ev_made = true;
@@ -1083,18 +1077,18 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
         }
         hipStream_t sd = p.side;
         VP_HIP(launch_zero(p, ws, st), "zero");
-        if (!fused) VP_HIP(launch_strengths(p, ws, st, f, sigma, mu), "strengths");
+        VP_HIP(launch_strengths(p, ws, st, f, sigma, mu), "strengths");
         VP_HIP(hipEventRecord(p.fork[0], st), "fork");
         VP_HIP(hipStreamWaitEvent(sd, p.fork[0], 0), "fork");
         VP_HIP(launch_local(p, ws, sd, jet6, sigma_jet3, mu_jet5, use_v, use_s, use_d, out, kLocalPart),
                "local");
-        VP_HIP(launch_spread(p, ws, sd, 1, use_v, use_s || use_d, use_d, rs), "spread");
+        VP_HIP(launch_spread(p, ws, sd, 1, use_v, use_s || use_d, use_d), "spread");
         VP_HIP(launch_row_fft(p, ws, sd, 1, use_d), "row fft");
         VP_HIP(launch_col_fft(p, ws, sd, 1, use_d), "column fft");
         VP_HIP(launch_row_ifft(p, ws, sd, 1), "row ifft");
         VP_HIP(launch_interp(p, ws, sd, 1), "interp");
         VP_HIP(hipEventRecord(p.fork[1], sd), "join");
-        VP_HIP(launch_spread(p, ws, st, 0, use_v, use_s || use_d, use_d, rs), "spread");
+        VP_HIP(launch_spread(p, ws, st, 0, use_v, use_s || use_d, use_d), "spread");
         VP_HIP(launch_row_fft(p, ws, st, 0, use_d), "row fft");
         VP_HIP(launch_col_fft(p, ws, st, 0, use_d), "column fft");
         VP_HIP(launch_row_ifft(p, ws, st, 0), "row ifft");
@@ -1107,10 +1101,10 @@ vp_status eval_enqueue(Plan& p, const Workspace& ws, hipStream_t st, const doubl
     auto mark = [&](int k) -> hipError_t { return hipEventRecord(p.ev[k], st); };
     VP_HIP(mark(0), "event");
     VP_HIP(launch_zero(p, ws, st), "zero");
-    if (!fused) VP_HIP(launch_strengths(p, ws, st, f, sigma, mu), "strengths");
+    VP_HIP(launch_strengths(p, ws, st, f, sigma, mu), "strengths");
     VP_HIP(mark(1), "event");
     for (int l = 0; l < 2; ++l) {
-        VP_HIP(launch_spread(p, ws, st, l, use_v, use_s || use_d, use_d, rs), "spread");
+        VP_HIP(launch_spread(p, ws, st, l, use_v, use_s || use_d, use_d), "spread");
         VP_HIP(mark(2 + l), "event");
     }
     // timed: every launch on one stream, one per level, in the order of the timing slots
