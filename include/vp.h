@@ -352,9 +352,10 @@ vp_status vp_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, const double*
  *   u = g on it and u bounded: u = D[mu] + (integral of mu) outside (the
  *   double layer with the kernel's +1), whose exterior limit on the boundary
  *   is mu/2 + D[mu] + (integral of mu) = g.  For growth A log|x - x0| at
- *   infinity pass g - A log|x' - x0|.  mu [n_pan*q]: initial guess in,
+ *   infinity use vp_exterior_dirichlet_solve_growth below (or pass
+ *   g - A log|x' - x0| here).  mu [n_pan*q]: initial guess in,
  *   solution out.  With a volume source outside (u = V[f] + D_E[mu] +
- *   A log), pass g - V[f] - A log: V[f] at the nodes and at exterior
+ *   A log), pass g - V[f]: V[f] at the nodes and at exterior
  *   targets comes from plans on the same nodes traversed clockwise (panel
  *   and node order reversed, normals flipped), whose frames from
  *   vp_boundary_frame put the outside on their interior side, where the
@@ -378,6 +379,29 @@ vp_status vp_exterior_dirichlet_solve(vp_plan_t plan, int64_t n_pan, int q, cons
                                       const double* bnd_y, const double* bnd_w, const int32_t* pan, const double* u,
                                       const double* g, double* mu, double tol, int max_iter, int restart,
                                       int* iters, double* resid);
+/* Growth at infinity of exterior solutions (Sec. 5, exterior representation
+ * u = V[f] + D_E[mu] + A log|x - x0|): the problem fixes A (A = 0: bounded
+ * solutions), and x0 is any point inside the curve (another interior point
+ * changes the growth term by a function harmonic outside and vanishing at
+ * infinity, which mu absorbs, so u does not change).
+ *
+ * vp_exterior_dirichlet_solve_growth: vp_exterior_dirichlet_solve with the
+ *   data g - A log|x' - x0| formed on the device at the nodes (bnd_x,
+ *   bnd_y); g is the boundary value of the whole solution (with a volume
+ *   source, pass g - V[f] as there).  Same arguments, scratch, iteration
+ *   count, residual and errors, plus VP_ERR_ARG for non-finite A, x0, y0.
+ * vp_add_log_growth: out[i] += A log|(x[i], y[i]) - (x0, y0)| for n points
+ *   (device arrays; no point may equal x0), enqueued on stream (a
+ *   hipStream_t, NULL = null stream): the representation's last term at
+ *   exterior targets, after the evaluation of D_E[mu] (and V[f]).
+ *   VP_ERR_ARG for n < 0, NULL arrays with n > 0 or non-finite A, x0, y0. */
+vp_status vp_exterior_dirichlet_solve_growth(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
+                                             const double* bnd_y, const double* bnd_w, const int32_t* pan,
+                                             const double* u, const double* g, double A, double x0, double y0,
+                                             double* mu, double tol, int max_iter, int restart, int* iters,
+                                             double* resid);
+vp_status vp_add_log_growth(int64_t n, const double* x, const double* y, double A, double x0, double y0, double* out,
+                            void* stream);
 vp_status vp_neumann_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,
                            const double* bnd_w, const int32_t* pan, const double* u, const double* g,
                            const double* f_src, const double* jet6, double* ub, double tol, int max_iter,

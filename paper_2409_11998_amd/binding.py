@@ -25,7 +25,8 @@ EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "v
             "vp_server_create", "vp_server_submit", "vp_server_poll", "vp_server_wait", "vp_server_get_stats",
             "vp_server_destroy", "vp_server_last_error", "vp_refine_attach", "vp_layer_refine",
             "vp_boundary_frame", "vp_boundary_jets", "vp_dirichlet_solve", "vp_exterior_dirichlet_solve",
-            "vp_neumann_solve", "vp_volume_jets", "vp_boundary_jets_noalloc"]
+            "vp_neumann_solve", "vp_volume_jets", "vp_boundary_jets_noalloc", "vp_exterior_dirichlet_solve_growth",
+            "vp_add_log_growth"]
 
 
 class VPError(RuntimeError):
@@ -129,6 +130,13 @@ def lib():
                                                   ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                                   ctypes.POINTER(ctypes.c_double)]
         L.vp_exterior_dirichlet_solve.restype = ctypes.c_int
+        L.vp_exterior_dirichlet_solve_growth.argtypes = [vp, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp,
+                                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, vp,
+                                                         ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        L.vp_exterior_dirichlet_solve_growth.restype = ctypes.c_int
+        L.vp_add_log_growth.argtypes = [i64, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.vp_add_log_growth.restype = ctypes.c_int
         L.vp_neumann_solve.argtypes = [vp, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
                                        ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_double)]
@@ -531,6 +539,34 @@ def exterior_dirichlet_solve(plan, q, bnd_x, bnd_y, bnd_w, pan, u, g, mu=None, t
                                              _ptr(mu, f64), tol, max_iter, restart, ctypes.byref(it),
                                              ctypes.byref(res)))
     return mu, it.value, res.value
+
+
+def exterior_dirichlet_solve_growth(plan, q, bnd_x, bnd_y, bnd_w, pan, u, g, A, x0, mu=None, tol=1e-12, max_iter=200,
+                                    restart=50):
+    """mu with mu/2 + D[mu] + (integral of mu) = g - A log|x' - x0| at the panel
+    nodes (vp_exterior_dirichlet_solve_growth); u = D[mu] + (integral of mu) +
+    A log|x - x0| outside.  x0 = (x, y).  Returns (mu, products, relative residual)."""
+    import torch
+    f64 = torch.float64
+    n = bnd_x.numel()
+    if mu is None:
+        mu = torch.zeros(n, dtype=f64, device=g.device)
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    _check(lib().vp_exterior_dirichlet_solve_growth(plan.handle, n // q, q, _ptr(bnd_x, f64), _ptr(bnd_y, f64),
+                                                    _ptr(bnd_w, f64), _ptr(pan, torch.int32), _ptr(u, f64),
+                                                    _ptr(g, f64), float(A), float(x0[0]), float(x0[1]), _ptr(mu, f64),
+                                                    tol, max_iter, restart, ctypes.byref(it), ctypes.byref(res)))
+    return mu, it.value, res.value
+
+
+def add_log_growth(x, y, A, x0, out):
+    """out += A log|(x, y) - x0| in place (vp_add_log_growth), on the current stream."""
+    import torch
+    f64 = torch.float64
+    _check(lib().vp_add_log_growth(x.numel(), _ptr(x, f64), _ptr(y, f64), float(A), float(x0[0]), float(x0[1]),
+                                   _ptr(out, f64), _stream(x)))
+    return out
 
 
 def neumann_solve(plan, q, bnd_x, bnd_y, bnd_w, pan, u, g, ub=None, tol=1e-12, max_iter=200, restart=50, f=None,

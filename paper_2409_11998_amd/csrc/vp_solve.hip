@@ -148,6 +148,16 @@ __global__ __launch_bounds__(kSolveThreads) void k_plus(int64_t n, const double*
     if (i < n) y[i] += x[i] + c[0];
 }
 
+// out = in + A log |(x, y) - (x0, y0)|: the growth term of the exterior representation
+// (in == out allowed)
+__global__ __launch_bounds__(kSolveThreads) void k_log_growth(int64_t n, const double* __restrict__ x,
+                                                              const double* __restrict__ y, double A, double x0,
+                                                              double y0, const double* in, double* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i] + A * log(hypot(x[i] - x0, y[i] - y0));
+}
+
 // y = a x + b y (b = 0: y is not read, so uninitialized memory may be the target)
 __global__ __launch_bounds__(kSolveThreads) void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
                                                          double* __restrict__ y)
@@ -329,6 +339,13 @@ struct Solver {
         for (double v : h_part) t += v;  // fixed order
         *out = t;
         return VP_OK;
+    }
+    // b = g - A log |x' - x0| at the nodes
+    vp_status minus_growth(const double* g, double A, double x0, double y0, double* b)
+    {
+        hipLaunchKernelGGL(k_log_growth, dim3((unsigned)((n + kSolveThreads - 1) / kSolveThreads)),
+                           dim3(kSolveThreads), 0, st, n, bx, by, -A, x0, y0, g, b);
+        return launched();
     }
     vp_status axpby(double a, const double* x, double b, double* y)
     {
@@ -563,6 +580,35 @@ extern "C" vp_status vp_exterior_dirichlet_solve(vp_plan_t plan, int64_t n_pan, 
     if (!bnd_w) return set_error(VP_ERR_ARG, "NULL array");
     auto rhs = [&](Solver& S, double* b) { return S.axpby(1.0, g, 0.0, b); };
     return gmres_solve(plan, n_pan, q, bnd_x, bnd_y, pan, u, bnd_w, rhs, mu, tol, max_iter, restart, iters, resid);
+}
+
+extern "C" vp_status vp_exterior_dirichlet_solve_growth(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x,
+                                                        const double* bnd_y, const double* bnd_w, const int32_t* pan,
+                                                        const double* u, const double* g, double A, double x0,
+                                                        double y0, double* mu, double tol, int max_iter, int restart,
+                                                        int* iters, double* resid)
+{
+    vp_status s = check_solve_args(plan, n_pan, q, bnd_x, bnd_y, pan, u, g, mu, tol, max_iter, restart);
+    if (s != VP_OK) return s;
+    if (!bnd_w) return set_error(VP_ERR_ARG, "NULL array");
+    if (!std::isfinite(A) || !std::isfinite(x0) || !std::isfinite(y0))
+        return set_error(VP_ERR_ARG, "non-finite growth coefficient or centre");
+    auto rhs = [&](Solver& S, double* b) { return S.minus_growth(g, A, x0, y0, b); };
+    return gmres_solve(plan, n_pan, q, bnd_x, bnd_y, pan, u, bnd_w, rhs, mu, tol, max_iter, restart, iters, resid);
+}
+
+extern "C" vp_status vp_add_log_growth(int64_t n, const double* x, const double* y, double A, double x0, double y0,
+                                       double* out, void* stream)
+{
+    if (n < 0) return set_error(VP_ERR_ARG, "negative count");
+    if (n == 0) return VP_OK;
+    if (!x || !y || !out) return set_error(VP_ERR_ARG, "NULL array");
+    if (!std::isfinite(A) || !std::isfinite(x0) || !std::isfinite(y0))
+        return set_error(VP_ERR_ARG, "non-finite growth coefficient or centre");
+    hipLaunchKernelGGL(k_log_growth, dim3((unsigned)((n + kSolveThreads - 1) / kSolveThreads)), dim3(kSolveThreads), 0,
+                       (hipStream_t)stream, n, x, y, A, x0, y0, out, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? VP_OK : set_error(VP_ERR_DEVICE, std::string("growth term: ") + hipGetErrorString(e));
 }
 
 extern "C" vp_status vp_neumann_solve(vp_plan_t plan, int64_t n_pan, int q, const double* bnd_x, const double* bnd_y,

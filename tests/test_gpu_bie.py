@@ -320,6 +320,58 @@ def test_exterior_dirichlet(domain):
     assert e_x <= (5e-6 if domain == "circle" else 2e-4)      # targets reach r = 1.03 from the curve
 
 
+@pytest.mark.parametrize("domain", ["circle", "star"])
+def test_exterior_dirichlet_with_growth(domain):
+    """Sec. 5's exterior representation with growth at infinity,
+    u = D_E[mu] + A log|x - x0| (A given, x0 inside the curve).  The exact
+    solution u = A log|x - xg| + (a harmonic function decaying outside) gives g
+    on the boundary.  vp_exterior_dirichlet_solve_growth must return the
+    density of the bounded problem with data g - A log|x' - x0| (the oracle's
+    direct solve), and D_E[mu] plus vp_add_log_growth at exterior targets must
+    match the exact u, for two different centres x0."""
+    torch = _gpu()
+    from paper_2409_11998_amd import add_log_growth, exterior_dirichlet_solve_growth
+    q, A = 16, 0.7
+    if domain == "circle":
+        bx, by, bnx, bny, bw, t = _circle(32)
+        decay = lambda x, y: np.real((x + 1j * y) ** -3)
+        curv = _circle_curv()
+        centres, xg = [(0.2, -0.1), (-0.3, 0.25)], (0.0, 0.05)
+    else:
+        curve = StarCurve(**star_params(3, r=0.8))
+        bx, by, bnx, bny, bw, _ = panel_nodes(curve, 32, q)
+        z0 = complex(0.1, -0.05)
+        decay = lambda x, y: np.real(1 / (x + 1j * y - z0))
+        curv = _star_curv(curve)
+        centres, xg = [(0.05, 0.0), (-0.1, 0.1)], (0.0, 0.05)
+    uext = lambda x, y: A * np.log(np.hypot(x - xg[0], y - xg[1])) + decay(x, y)
+    plan, dx, dy, fr = _node_plan(torch, bx, by, bnx, bny, bw, q, curv=curv)
+    P = bie.on_boundary_problem(bx, by, bnx, bny, bw, q, curvature=curv)
+    rng = np.random.default_rng(6)
+    k = rng.integers(0, bx.size, 300)
+    s = rng.uniform(1.03, 2.5, 300)
+    cx, cy = np.mean(bx), np.mean(by)
+    tx, ty = cx + s * (bx[k] - cx), cy + s * (by[k] - cy)
+    bound = 5e-6 if domain == "circle" else 2e-4      # targets reach r = 1.03 from the curve
+    us = []
+    for x0 in centres:
+        mu, its, res = exterior_dirichlet_solve_growth(plan, q, dx, dy, _t(torch, bw), fr["pan"], fr["u"],
+                                                       _t(torch, uext(bx, by)), A, x0)
+        torch.cuda.synchronize()
+        mu = mu.cpu().numpy()
+        ref = bie.solve_exterior_dirichlet(P, uext(bx, by) - A * np.log(np.hypot(bx - x0[0], by - x0[1])))
+        u = _t(torch, _eval_at(torch, bx, by, bnx, bny, bw, q, tx, ty, mu=mu, curv=curv) + float(np.dot(bw, mu)))
+        add_log_growth(_t(torch, tx), _t(torch, ty), A, x0, u)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()
+        e_mu, e_x = oracle.rel_linf(mu, ref), np.max(np.abs(u - uext(tx, ty)))
+        print(domain, "growth, centre", x0, "products", its, "residual", res, "mu vs oracle", e_mu, "u vs exact", e_x)
+        assert res <= 1e-11 and e_mu <= 1e-8 and e_x <= bound
+        us.append(u)
+    plan.close()
+    assert np.max(np.abs(us[0] - us[1])) <= 2 * bound
+
+
 @pytest.mark.parametrize("domain", ["circle", "disk", "star"])
 def test_neumann(domain):
     """u/2 + D[u] = V[f] + S[g] with zero boundary mean: boundary values against

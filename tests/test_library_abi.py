@@ -63,6 +63,17 @@ def test_host_side_argument_checks():
                                 None) == binding.VP_ERR_ARG
     assert L.vp_neumann_solve(None, 4, 16, None, None, None, None, None, None, None, None, None, 1e-12, 10, 10, None,
                               None) == binding.VP_ERR_ARG
+    assert L.vp_exterior_dirichlet_solve_growth(None, 4, 16, None, None, None, None, None, None, 1.0, 0.0, 0.0, None,
+                                                1e-12, 10, 10, None, None) == binding.VP_ERR_ARG
+    # the growth term: nothing to do for n = 0; negative counts, NULL arrays and
+    # non-finite coefficients or centres are rejected before any launch
+    inf = float("inf")
+    assert L.vp_add_log_growth(0, None, None, 1.0, 0.0, 0.0, None, None) == binding.VP_OK
+    assert L.vp_add_log_growth(-1, None, None, 1.0, 0.0, 0.0, None, None) == binding.VP_ERR_ARG
+    assert L.vp_add_log_growth(5, None, None, 1.0, 0.0, 0.0, None, None) == binding.VP_ERR_ARG
+    buf = (ctypes.c_double * 5)()
+    assert L.vp_add_log_growth(5, buf, buf, inf, 0.0, 0.0, buf, None) == binding.VP_ERR_ARG
+    assert L.vp_add_log_growth(5, buf, buf, 1.0, float("nan"), 0.0, buf, None) == binding.VP_ERR_ARG
 
 
 def test_noalloc_limit_matches_header():
