@@ -88,9 +88,9 @@ def algorithmic_bytes(info, P, kinds, b):
     return out
 
 
-def survey_bytes(info, P, kinds, b):
-    """Algorithmic bytes of each hot-path step in the measurement model of the
-    method's step table (one read of each input, one write of each output),
+def step_bytes(info, P, kinds, b):
+    """Algorithmic bytes of each hot-path step (one read of each input, one
+    write of each output),
     for the one grid channel this design spreads: a volume node brings its two
     coordinates and one strength, a double-layer boundary node its coordinates
     and three strengths (sigma w, and mu nu w for the kernel derivative), a
@@ -112,8 +112,8 @@ def survey_bytes(info, P, kinds, b):
     return out
 
 
-def survey_roofline(st, sb):
-    """(key, ms, bytes, GB/s, fraction of HBM peak) per step of survey_bytes; FFT chains take the
+def step_roofline(st, sb):
+    """(key, ms, bytes, GB/s, fraction of HBM peak) per step of step_bytes; FFT chains take the
     sum of their three launches' times."""
     rows = {}
     for tag in ("nh", "fh"):
@@ -302,7 +302,7 @@ def main():
     ms = 1000.0 * r64["elapsed"] / args.steps
     alg = algorithmic_bytes(r64["info"], P, "VD", 8)
     st = r64["stages"]
-    sroof = survey_roofline(st, survey_bytes(r64["info"], P, "VD", 8))
+    sroof = step_roofline(st, step_bytes(r64["info"], P, "VD", 8))
     dom = max(("spread_nh", "spread_fh", "interp_nh", "interp_fh"), key=lambda k: st[k])
     workload = "square-200k-slivers-gaps V+D fp64 tol1e-10"
     lvl = {"nh": 0, "fh": 1}[dom.rsplit("_", 1)[-1]]
@@ -405,7 +405,7 @@ def main():
 
 def leg_summary(r, P, kinds, b, steps, workload):
     st = r["stages"]
-    sroof = survey_roofline(st, survey_bytes(r["info"], P, kinds, b))
+    sroof = step_roofline(st, step_bytes(r["info"], P, kinds, b))
     dom = max(sroof, key=lambda k: sroof[k]["ms"])
     return {"workload": workload, "n_tgt": P.n_tgt, "value": round(P.n_tgt * steps / r["elapsed"], 1),
             "unit": "target pts/s", "ms_per_step": round(1000.0 * r["elapsed"] / steps, 4),
