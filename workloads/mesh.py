@@ -142,6 +142,26 @@ def curve_mesh(curve, n_tri, seed, margin=0.5):
     return x, y, w, info
 
 
+def triangle_neighbours(tri):
+    """[M, 3] int32: for each triangle the triangle across each of its edges
+    (edge e joins vertices e and e+1), -1 where no other triangle has that
+    edge (the boundary, a gap, or a nonconforming side)."""
+    tri = np.asarray(tri)
+    M = len(tri)
+    a = tri
+    b = np.roll(tri, -1, axis=1)
+    lo, hi = np.minimum(a, b).ravel(), np.maximum(a, b).ravel()
+    key = lo.astype(np.int64) * (int(tri.max()) + 1) + hi
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    out = np.full(3 * M, -1, np.int64)
+    same = np.nonzero(ks[1:] == ks[:-1])[0]           # pairs of half-edges on one edge
+    e0, e1 = order[same], order[same + 1]
+    out[e0] = e1 // 3
+    out[e1] = e0 // 3
+    return out.reshape(M, 3).astype(np.int32)
+
+
 def square_mesh(n_tri, seed, n_split, degenerate_frac=0.05, gap_frac=0.002):
     """Straight-sided mesh of [-1,1]^2, then random splits and gaps (Sec. 6.4).
 
