@@ -433,7 +433,8 @@ def geometry_leg(torch, P, steps):
     """Local frame and double-layer jets of every target from the boundary panels
     alone (vp_boundary_frame, vp_boundary_jets) on the square workload; the
     distance and side against the exact square."""
-    from paper_2409_11998_amd import boundary_frame, boundary_jets, volume_jets
+    from paper_2409_11998_amd import boundary_frame, boundary_jets, volume_jets, volume_jets_patch
+    from workloads.mesh import triangle_neighbours
     q = P.info["q"]
     f64 = torch.float64
     bx, by = (torch.as_tensor(a, dtype=f64, device="cuda") for a in (P.bnd_x, P.bnd_y))
@@ -464,9 +465,18 @@ def geometry_leg(torch, P, steps):
     ratio = np.sqrt(np.maximum(0.5 * (sxx + syy) - rad, 0) / np.maximum(0.5 * (sxx + syy) + rad, 1e-300))
     shaped = np.repeat(ratio >= 0.1, 6) & fin
 
-    def rel(rows, sel=fin):
+    def rel(rows, sel=fin, J=J):
         ref = np.asarray(P.jet6)[rows]
         return float(np.max(np.abs(J[rows][:, sel] - ref[:, sel])) / np.max(np.abs(ref)))
+    # the same jets from the least-squares quadratic over each triangle and its edge neighbours
+    nbr = torch.as_tensor(triangle_neighbours(P.info["tri"]), dtype=torch.int32, device="cuda")
+    vp_ = lambda: volume_jets_patch(sx, sy, sf, nbr)
+    for _ in range(3):
+        vp_()
+    el_p = time_steps(torch, vp_, steps)
+    Jp = vp_().cpu().numpy()
+    finp = np.all(np.isfinite(Jp), axis=0)
+    slivers = np.repeat(ratio < 0.1, 6) & finp
     r = fr["r"].cpu().numpy()
     sgn = fr["sgn"].cpu().numpy()
     return {"workload": "square-200k targets (%d) against %d boundary nodes in %d panels of %d" %
@@ -484,6 +494,13 @@ def geometry_leg(torch, P, steps):
             "volume_jets_rel_err_vs_analytic_axis_ratio_ge_0.1": {"gradient": rel([1, 2], shaped),
                                                                   "hessian": rel([3, 4, 5], shaped),
                                                                   "triangles": int(shaped.sum() // 6)},
+            "volume_jets_patch_ms": round(1e3 * el_p / steps, 4),
+            "volume_jets_patch_nan_triangles": int(np.count_nonzero(~finp.reshape(-1, 6).all(1))),
+            "volume_jets_patch_rel_err_vs_analytic": {"gradient": rel([1, 2], finp, Jp),
+                                                      "hessian": rel([3, 4, 5], finp, Jp)},
+            "volume_jets_patch_rel_err_vs_analytic_axis_ratio_lt_0.1": {"gradient": rel([1, 2], slivers, Jp),
+                                                                       "hessian": rel([3, 4, 5], slivers, Jp),
+                                                                       "triangles": int(slivers.sum() // 6)},
             "sgn_differs_only_on_curve": bool(np.all(np.asarray(P.geom["r"])[sgn != np.asarray(P.geom["sgn"])] <= 1e-12)
                                               and np.all(sgn[sgn != np.asarray(P.geom["sgn"])] == 0))}
 

@@ -281,6 +281,20 @@ vp_status vp_boundary_jets_noalloc(int64_t n_pan, int q, const double* bnd_x, co
 vp_status vp_volume_jets(int64_t n_tri, const double* x, const double* y, const double* f, double* jet6,
                          void* stream);
 
+/* vp_volume_jets_patch: the same jets from the least-squares quadratic over
+ * each triangle's six nodes and the six nodes of each of its edge neighbours:
+ * nbr [3 n_tri] (device, int32), the triangle across each edge, -1 for none
+ * (entries outside [0, n_tri), and the triangle itself, count as none).  The
+ * six nodes of a sliver lie close to a line and do not fix the derivatives
+ * across it; its neighbours' nodes do.  On the split square mesh the slivers'
+ * gradient and Hessian errors then converge like those of the well-shaped
+ * triangles (O(h^2) and O(h)).  Without neighbours the fit is the
+ * interpolant of vp_volume_jets.  A patch whose nodes fix no quadratic gets
+ * NaN derivatives.  One launch on stream, allocates nothing; VP_ERR_ARG for
+ * NULL arrays or n_tri < 0 (n_tri = 0 is a no-op). */
+vp_status vp_volume_jets_patch(int64_t n_tri, const double* x, const double* y, const double* f, const int32_t* nbr,
+                               double* jet6, void* stream);
+
 /* ------------------------------------------------------------------------
  * Interior Dirichlet problem -Lap u = f inside, u = g on the boundary, by
  * the representation u = V[f] + D[mu] (Sec. 1; the boundary integral

@@ -26,7 +26,7 @@ EXPORTED = ["vp_opts_default", "vp_plan", "vp_eval", "vp_volume", "vp_layer", "v
             "vp_server_destroy", "vp_server_last_error", "vp_refine_attach", "vp_layer_refine",
             "vp_boundary_frame", "vp_boundary_jets", "vp_dirichlet_solve", "vp_exterior_dirichlet_solve",
             "vp_neumann_solve", "vp_volume_jets", "vp_boundary_jets_noalloc", "vp_exterior_dirichlet_solve_growth",
-            "vp_add_log_growth"]
+            "vp_add_log_growth", "vp_volume_jets_patch"]
 
 
 class VPError(RuntimeError):
@@ -143,6 +143,8 @@ def lib():
         L.vp_neumann_solve.restype = ctypes.c_int
         L.vp_volume_jets.argtypes = [i64, vp, vp, vp, vp, vp]
         L.vp_volume_jets.restype = ctypes.c_int
+        L.vp_volume_jets_patch.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+        L.vp_volume_jets_patch.restype = ctypes.c_int
         L.vp_destroy.argtypes = [vp]
         L.vp_destroy.restype = ctypes.c_int
         L.vp_last_error.argtypes = []
@@ -585,6 +587,23 @@ def neumann_solve(plan, q, bnd_x, bnd_y, bnd_w, pan, u, g, ub=None, tol=1e-12, m
                                   _ptr(pan, torch.int32), _ptr(u, f64), _ptr(g, f64), _ptr(f, f64), _ptr(jet6, f64),
                                   _ptr(ub, f64), tol, max_iter, restart, ctypes.byref(it), ctypes.byref(res)))
     return ub, it.value, res.value
+
+
+def volume_jets_patch(x, y, f, nbr):
+    """As volume_jets, from the least-squares quadratic over each triangle and
+    its edge neighbours (vp_volume_jets_patch); nbr [n_tri, 3] int32 device
+    tensor, -1 where an edge has no neighbour.  Device tensor [6, n]."""
+    import torch
+    f64 = torch.float64
+    n = x.numel()
+    if n % 6:
+        raise ValueError("the nodes must come six per triangle")
+    if nbr.numel() != 3 * (n // 6):
+        raise ValueError("nbr must hold three entries per triangle")
+    out = torch.empty((6, n), dtype=f64, device=x.device)
+    _check(lib().vp_volume_jets_patch(n // 6, _ptr(x, f64), _ptr(y, f64), _ptr(f, f64), _ptr(nbr, torch.int32),
+                                      _ptr(out), _stream(x)))
+    return out
 
 
 def volume_jets(x, y, f):

@@ -87,3 +87,40 @@ def test_empty_and_argument_errors():
     assert lib().vp_volume_jets(0, None, None, None, None, None) == 0
     assert lib().vp_volume_jets(-1, None, None, None, None, None) == VP_ERR_ARG
     assert lib().vp_volume_jets(3, None, None, None, None, None) == VP_ERR_ARG
+
+
+def test_patch_jets_match_oracle_on_slivers():
+    """vp_volume_jets_patch against the oracle's least-squares patch jets on the
+    split square mesh (slivers, degenerate triangles, gaps), element by
+    element; exact for quadratics there; without neighbours equal to
+    vp_volume_jets."""
+    torch = _gpu()
+    from paper_2409_11998_amd import volume_jets_patch
+    from oracle.volume_jets import patch_jets
+    from workloads.mesh import square_mesh, triangle_neighbours
+    from workloads.problems import gauss_jets
+    t = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    x, y, _, info = square_mesh(3000, 5, 400)
+    nbr = triangle_neighbours(info["tri"])
+    f = gauss_jets(x, y, ((1.0, 0.1, -0.2, 0.3),))[0]
+    got = volume_jets_patch(t(x), t(y), t(f), t(nbr, torch.int32)).cpu().numpy()
+    ref = patch_jets(x, y, f, nbr)
+    assert np.all(np.isfinite(ref)) and np.all(np.isfinite(got))
+    e = np.max(np.abs(got - ref), axis=1) / np.max(np.abs(ref), axis=1)
+    print("patch jets against the oracle, relative per row:", e)
+    assert e[0] == 0.0 and np.all(e <= 1e-9)
+    rng = np.random.default_rng(3)
+    c = rng.standard_normal(6)
+    q = c[0] + c[1] * x + c[2] * y + c[3] * x * x + c[4] * x * y + c[5] * y * y
+    got = volume_jets_patch(t(x), t(y), t(q), t(nbr, torch.int32)).cpu().numpy()
+    ex = np.stack([q, c[1] + 2 * c[3] * x + c[4] * y, c[2] + c[4] * x + 2 * c[5] * y,
+                   np.full(x.size, 2 * c[3]), np.full(x.size, c[4]), np.full(x.size, 2 * c[5])])
+    print("quadratic: max error", np.max(np.abs(got - ex)))
+    assert np.max(np.abs(got - ex)) <= 1e-8
+    D = disk_problem(2000, seed=1, gauss=GAUSS)
+    none = np.full((D.src_x.size // 6, 3), -1, np.int32)
+    got = volume_jets_patch(t(D.src_x), t(D.src_y), t(D.f_src), t(none, torch.int32)).cpu().numpy()
+    ref = _jets(torch, D.src_x, D.src_y, D.f_src)
+    e = np.max(np.abs(got - ref), axis=1) / np.max(np.abs(ref), axis=1)
+    print("without neighbours against vp_volume_jets:", e)
+    assert np.all(e <= 1e-9)
