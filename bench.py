@@ -477,6 +477,16 @@ def geometry_leg(torch, P, steps):
     Jp = vp_().cpu().numpy()
     finp = np.all(np.isfinite(Jp), axis=0)
     slivers = np.repeat(ratio < 0.1, 6) & finp
+    # V[f] at the volume nodes (targets = nodes) with the device's patch jets against V[f]
+    # with the Gaussians' analytic jets: what nodal f alone gives the headline workload
+    from workloads.device import make_plan, to_device
+    dev = to_device(P)
+    plan = make_plan(dev, tol=1e-10, precision=1, kinds=1)
+    v_exact = plan.eval(f=dev["f"], jet6=dev["jet6"]).cpu().numpy()
+    v_patch = plan.eval(f=dev["f"], jet6=torch.as_tensor(Jp, device="cuda")).cpu().numpy()
+    plan.close()
+    del dev
+    v_diff = float(np.max(np.abs(v_patch - v_exact)) / np.max(np.abs(v_exact)))
     r = fr["r"].cpu().numpy()
     sgn = fr["sgn"].cpu().numpy()
     return {"workload": "square-200k targets (%d) against %d boundary nodes in %d panels of %d" %
@@ -501,6 +511,7 @@ def geometry_leg(torch, P, steps):
             "volume_jets_patch_rel_err_vs_analytic_axis_ratio_lt_0.1": {"gradient": rel([1, 2], slivers, Jp),
                                                                        "hessian": rel([3, 4, 5], slivers, Jp),
                                                                        "triangles": int(slivers.sum() // 6)},
+            "v_with_patch_jets_rel_diff_vs_analytic_jets": v_diff,
             "sgn_differs_only_on_curve": bool(np.all(np.asarray(P.geom["r"])[sgn != np.asarray(P.geom["sgn"])] <= 1e-12)
                                               and np.all(sgn[sgn != np.asarray(P.geom["sgn"])] == 0))}
 
