@@ -124,3 +124,31 @@ def test_patch_jets_match_oracle_on_slivers():
     e = np.max(np.abs(got - ref), axis=1) / np.max(np.abs(ref), axis=1)
     print("without neighbours against vp_volume_jets:", e)
     assert np.all(e <= 1e-9)
+
+
+def test_patch_jets_ignore_invalid_neighbours():
+    """Neighbour entries outside [0, n_tri) or naming the triangle itself count
+    as none: the result equals the one with -1 there."""
+    torch = _gpu()
+    from paper_2409_11998_amd import volume_jets_patch
+    from workloads.mesh import square_mesh, triangle_neighbours
+    t = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    x, y, _, info = square_mesh(1200, 7, 150)
+    nbr = triangle_neighbours(info["tri"])
+    m = len(nbr)
+    rng = np.random.default_rng(4)
+    bad = nbr.copy()
+    none = bad < 0
+    junk = rng.choice(np.array([m, m + 5, -7, 2 ** 31 - 1], np.int64), size=int(none.sum()))
+    bad[none] = junk.astype(np.int32)
+    self_rows = rng.choice(m, 20, replace=False)
+    ref_nbr = nbr.copy()
+    bad[self_rows, 0] = self_rows
+    ref_nbr[self_rows, 0] = -1
+    f = np.sin(3 * x) * np.cos(2 * y)
+    a = volume_jets_patch(t(x), t(y), t(f), t(bad, torch.int32)).cpu().numpy()
+    b = volume_jets_patch(t(x), t(y), t(f), t(ref_nbr, torch.int32)).cpu().numpy()
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    assert np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)])
+    empty = torch.zeros(0, dtype=torch.float64, device="cuda")
+    assert volume_jets_patch(empty, empty, empty, torch.zeros(0, dtype=torch.int32, device="cuda")).numel() == 0
