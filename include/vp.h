@@ -30,10 +30,12 @@
  *    serialized by the caller.  Distinct plans may be used from different
  *    threads.  vp_eval/vp_volume/vp_layer only enqueue work on that stream:
  *    the output is ready once the stream is synchronized.  Without timing
- *    (vp_set_timing) an evaluation also runs the far-history level on a
- *    second stream the plan owns (default priority), forked from and joined
- *    back into the plan's stream by events inside the same call, so ordering
- *    against the plan's stream (and stream capture of it) is unchanged.
+ *    (vp_set_timing) an evaluation also runs the local part and the
+ *    far-history level on a second stream the plan owns (default priority),
+ *    forked from and joined back into the plan's stream by events inside the
+ *    same call, so ordering against the plan's stream (and stream capture of
+ *    it) is unchanged.  The output array is written on both streams between
+ *    the fork and the join.
  */
 #ifndef VP_H
 #define VP_H
