@@ -121,8 +121,9 @@ struct LevelBufs {
     RecList bnd;               // boundary nodes (spread)
     RecList tgt;               // targets (interpolation)
     WorkUnit* sp_units = nullptr;  // spreading work units (tiles with nodes)
+    WorkUnit* sp_units_bnd = nullptr;  // the units with boundary nodes, volume ranges emptied (layer-only spreads)
     WorkUnit* in_units = nullptr;  // interpolation work units (tiles with targets)
-    std::vector<WorkUnit> h_sp_units, h_in_units;
+    std::vector<WorkUnit> h_sp_units, h_sp_units_bnd, h_in_units;
     void* mult = nullptr;      // R [M+1][M+1] (dk/2pi)^2 M(k) / (phihat(m1) phihat(m2))^2
     void* tw = nullptr;        // cplx<R> [F/2] twiddles exp(-2 pi i k / F)
     double* horner = nullptr;  // [w][w+2] per-tap polynomial of the spreading kernel in u = 2d - 1

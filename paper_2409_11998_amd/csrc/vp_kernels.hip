@@ -263,21 +263,21 @@ static void spread_launch(const Plan& p, hipStream_t st, int l, size_t lds, cons
 {
     const LevelGeom& g = p.lv[l];
     const LevelBufs& b = p.lb[l];
-    const unsigned nu = (unsigned)b.h_sp_units.size();
+    const bool layers_only = !uv && ub;  // only the units with boundary nodes have work
+    const unsigned nu = (unsigned)(layers_only ? b.h_sp_units_bnd.size() : b.h_sp_units.size());
+    const WorkUnit* units = layers_only ? b.sp_units_bnd : b.sp_units;
     if (nu == 0) return;
     if (g.mma) {  // four units per workgroup, one per wavefront
         const unsigned nb = (nu + kThreads / 64 - 1) / (kThreads / 64);
         (void)hipFuncSetAttribute((const void*)k_spread_mma<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         hipLaunchKernelGGL((k_spread_mma<R, W>), dim3(nb), dim3(kThreads), lds, st, g, view<R>(b.vol), view<R>(b.bnd),
-                           str, p.n_src, p.n_bnd, grid, uv, ub, ud, (const double*)b.horner,
-                           (const WorkUnit*)b.sp_units, (int)nu);
+                           str, p.n_src, p.n_bnd, grid, uv, ub, ud, (const double*)b.horner, units, (int)nu);
         return;
     }
     (void)hipFuncSetAttribute((const void*)k_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_spread<R, W>), dim3(nu), dim3(kThreads), lds, st, g, view<R>(b.vol), view<R>(b.bnd), str,
-                       p.n_src, p.n_bnd, grid, uv, ub, ud, (const double*)b.horner, smax,
-                       (const WorkUnit*)b.sp_units);
+                       p.n_src, p.n_bnd, grid, uv, ub, ud, (const double*)b.horner, smax, units);
 }
 
 // A level with dip spreads the double layer as two more channels: the

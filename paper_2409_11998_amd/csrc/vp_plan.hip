@@ -490,6 +490,7 @@ vp_status build_units(Plan& p, int l)
     auto cnt_of = [&](const RecList& L, int t) { return L.h_start.empty() ? 0 : L.h_start[t + 1] - L.h_start[t]; };
     auto beg_of = [&](const RecList& L, int t) { return L.h_start.empty() ? 0 : L.h_start[t]; };
     b.h_sp_units.clear();
+    b.h_sp_units_bnd.clear();
     b.h_in_units.clear();
     const int T = p.lv[l].T, w = p.lv[l].w, E = T + w - 1, ntx = p.lv[l].ntx;
     // most records of [a0, a1) of va and [b0, b1) of vb whose w x w supports share a window cell
@@ -546,6 +547,15 @@ vp_status build_units(Plan& p, int l)
                 u.cover = cover_of(cov, u.tile, u.a0, u.a1, u.b0, u.b1);
             }
         });
+    // a spread of the layers alone (the products of the boundary integral solves, the
+    // float32 double-layer channels) takes only the units with boundary nodes; the
+    // cover of the whole unit bounds its boundary part's
+    for (const WorkUnit& u : b.h_sp_units)
+        if (u.b1 > u.b0) {
+            WorkUnit v = u;
+            v.a1 = v.a0;
+            b.h_sp_units_bnd.push_back(v);
+        }
     // targets on the interpolation's own tiles
     const int ntiles_i = p.lv[l].ntxi * p.lv[l].ntxi;
     for (int t = 0; t < ntiles_i; ++t) {
@@ -562,6 +572,7 @@ vp_status build_units(Plan& p, int l)
     }
     vp_status s;
     if ((s = upload(p, &b.sp_units, b.h_sp_units, "spreading units")) != VP_OK) return s;
+    if ((s = upload(p, &b.sp_units_bnd, b.h_sp_units_bnd, "boundary spreading units")) != VP_OK) return s;
     if ((s = upload(p, &b.in_units, b.h_in_units, "interpolation units")) != VP_OK) return s;
     return VP_OK;
 }
