@@ -201,28 +201,30 @@ __global__ __launch_bounds__(kJetThreads) void k_volume_jets_patch(int64_t n_tri
         if (k >= 0 && k < n_tri && k != t) tri[nt++] = k;
     }
     const double np = 6.0 * nt;
-    double cx = 0.0, cy = 0.0;
+    // first and second moments in one pass, about the triangle's first node (no cancellation
+    // for patches far from the origin)
+    const double ox = x[6 * t], oy = y[6 * t];
+    double mx = 0.0, my = 0.0, mxx = 0.0, mxy = 0.0, myy = 0.0;
     for (int a = 0; a < nt; ++a)
         for (int l = 0; l < 6; ++l) {
-            cx += x[6 * tri[a] + l];
-            cy += y[6 * tri[a] + l];
+            const double dx = x[6 * tri[a] + l] - ox, dy = y[6 * tri[a] + l] - oy;
+            mx += dx;
+            my += dy;
+            mxx += dx * dx;
+            mxy += dx * dy;
+            myy += dy * dy;
         }
-    cx /= np;
-    cy /= np;
-    double sxx = 0.0, sxy = 0.0, syy = 0.0;
-    for (int a = 0; a < nt; ++a)
-        for (int l = 0; l < 6; ++l) {
-            const double dx = x[6 * tri[a] + l] - cx, dy = y[6 * tri[a] + l] - cy;
-            sxx += dx * dx;
-            sxy += dx * dy;
-            syy += dy * dy;
-        }
+    mx /= np;
+    my /= np;
+    const double cx = ox + mx, cy = oy + my;
+    const double sxx = mxx - np * mx * mx, sxy = mxy - np * mx * my, syy = myy - np * my * my;
     double e1x, e1y, l1, l2;
     principal_axes(sxx, sxy, syy, e1x, e1y, l1, l2);
     bool ok = l1 > 0.0 && l2 > 1e-14 * l1;  // else the patch's nodes lie on a line within rounding
     const double e2x = -e1y, e2y = e1x;
     const double s1 = ok ? sqrt(l1 / np) : 1.0, s2 = ok ? sqrt(l2 / np) : 1.0;
-    // normal equations [M | b], M = sum a a^T, b = sum a f, a = (1, u, v, u^2, uv, v^2)
+    // normal equations [M | b], M = sum a a^T (upper triangle accumulated), b = sum a f,
+    // a = (1, u, v, u^2, uv, v^2)
     double A[6][7];
 #pragma unroll
     for (int r = 0; r < 6; ++r)
@@ -237,8 +239,12 @@ __global__ __launch_bounds__(kJetThreads) void k_volume_jets_patch(int64_t n_tri
 #pragma unroll
             for (int r = 0; r < 6; ++r)
 #pragma unroll
-                for (int c = 0; c < 7; ++c) A[r][c] += m[r] * m[c];
+                for (int c = r; c < 7; ++c) A[r][c] += m[r] * m[c];
         }
+#pragma unroll
+    for (int r = 1; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c < r; ++c) A[r][c] = A[c][r];
     // Gaussian elimination with partial pivoting; a pivot below 1e-11 of the
     // point count (the scale of M here) means the patch does not fix a quadratic
 #pragma unroll
