@@ -21,6 +21,51 @@ namespace {
 
 constexpr int kJetThreads = 256;
 
+// Solve the 6 x 6 system in A[.][0..5] with right-hand side A[.][6] by Gaussian
+// elimination with partial pivoting; ok becomes false when a pivot is not above
+// thr.  Every loop has compile-time bounds and the row exchange is done with
+// selects at compile-time indices, so A stays in registers (a runtime row index
+// would put the array in scratch memory).
+__device__ __forceinline__ void solve6(double (&A)[6][7], double (&c)[6], double thr, bool& ok)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        int p = k;
+        double best = fabs(A[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < 6; ++r)
+            if (fabs(A[r][k]) > best) {
+                best = fabs(A[r][k]);
+                p = r;
+            }
+        if (!(best > thr)) ok = false;
+#pragma unroll
+        for (int r = k + 1; r < 6; ++r) {
+            const bool sw = r == p;
+#pragma unroll
+            for (int j = k; j < 7; ++j) {
+                const double a = A[k][j], b = A[r][j];
+                A[k][j] = sw ? b : a;
+                A[r][j] = sw ? a : b;
+            }
+        }
+        const double inv = best > 0.0 ? 1.0 / A[k][k] : 0.0;
+#pragma unroll
+        for (int r = k + 1; r < 6; ++r) {
+            const double m = A[r][k] * inv;
+#pragma unroll
+            for (int j = k; j < 7; ++j) A[r][j] -= m * A[k][j];
+        }
+    }
+#pragma unroll
+    for (int k = 5; k >= 0; --k) {
+        double sum = A[k][6];
+#pragma unroll
+        for (int j = k + 1; j < 6; ++j) sum -= A[k][j] * c[j];
+        c[k] = A[k][k] != 0.0 ? sum / A[k][k] : 0.0;
+    }
+}
+
 // one thread per triangle; jet [6][6 n_tri], the nodes' order
 __global__ __launch_bounds__(kJetThreads) void k_volume_jets(int64_t n_tri, const double* __restrict__ x,
                                                              const double* __restrict__ y,
@@ -94,43 +139,10 @@ __global__ __launch_bounds__(kJetThreads) void k_volume_jets(int64_t n_tri, cons
         A[l][5] = v * v;
         A[l][6] = pf[l];
     }
-    // Gaussian elimination with partial pivoting; a pivot below 1e-10 of the
-    // columns' scale (O(1) here) means the nodes do not determine a quadratic
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        int p = k;
-        double best = fabs(A[k][k]);
-#pragma unroll
-        for (int r = k + 1; r < 6; ++r)
-            if (fabs(A[r][k]) > best) {
-                best = fabs(A[r][k]);
-                p = r;
-            }
-        if (!(best > 1e-10)) ok = false;
-        if (p != k) {
-#pragma unroll
-            for (int cidx = 0; cidx < 7; ++cidx) {
-                const double tmp = A[k][cidx];
-                A[k][cidx] = A[p][cidx];
-                A[p][cidx] = tmp;
-            }
-        }
-        const double inv = best > 0.0 ? 1.0 / A[k][k] : 0.0;
-#pragma unroll
-        for (int r = k + 1; r < 6; ++r) {
-            const double m = A[r][k] * inv;
-#pragma unroll
-            for (int cidx = k; cidx < 7; ++cidx) A[r][cidx] -= m * A[k][cidx];
-        }
-    }
+    // a pivot below 1e-10 of the columns' scale (O(1) here) means the nodes do not
+    // determine a quadratic
     double c[6];
-#pragma unroll
-    for (int k = 5; k >= 0; --k) {
-        double s = A[k][6];
-#pragma unroll
-        for (int j = k + 1; j < 6; ++j) s -= A[k][j] * c[j];
-        c[k] = A[k][k] != 0.0 ? s / A[k][k] : 0.0;
-    }
+    solve6(A, c, 1e-10, ok);
     // (u, v) = J (x - c): J rows e1/s1, e2/s2
     const double j00 = e1x / s1, j01 = e1y / s1, j10 = e2x / s2, j11 = e2y / s2;
     const double quu = 2.0 * c[3], quv = c[4], qvv = 2.0 * c[5];
@@ -245,43 +257,10 @@ __global__ __launch_bounds__(kJetThreads) void k_volume_jets_patch(int64_t n_tri
     for (int r = 1; r < 6; ++r)
 #pragma unroll
         for (int c = 0; c < r; ++c) A[r][c] = A[c][r];
-    // Gaussian elimination with partial pivoting; a pivot below 1e-11 of the
-    // point count (the scale of M here) means the patch does not fix a quadratic
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        int p = k;
-        double best = fabs(A[k][k]);
-#pragma unroll
-        for (int r = k + 1; r < 6; ++r)
-            if (fabs(A[r][k]) > best) {
-                best = fabs(A[r][k]);
-                p = r;
-            }
-        if (!(best > 1e-11 * np)) ok = false;
-        if (p != k) {
-#pragma unroll
-            for (int c = 0; c < 7; ++c) {
-                const double tmp = A[k][c];
-                A[k][c] = A[p][c];
-                A[p][c] = tmp;
-            }
-        }
-        const double inv = best > 0.0 ? 1.0 / A[k][k] : 0.0;
-#pragma unroll
-        for (int r = k + 1; r < 6; ++r) {
-            const double m = A[r][k] * inv;
-#pragma unroll
-            for (int c = k; c < 7; ++c) A[r][c] -= m * A[k][c];
-        }
-    }
+    // a pivot below 1e-11 of the point count (the scale of M here) means the patch does
+    // not fix a quadratic
     double c[6];
-#pragma unroll
-    for (int k = 5; k >= 0; --k) {
-        double sum = A[k][6];
-#pragma unroll
-        for (int j = k + 1; j < 6; ++j) sum -= A[k][j] * c[j];
-        c[k] = A[k][k] != 0.0 ? sum / A[k][k] : 0.0;
-    }
+    solve6(A, c, 1e-11 * np, ok);
     const double j00 = e1x / s1, j01 = e1y / s1, j10 = e2x / s2, j11 = e2y / s2;
     const double quu = 2.0 * c[3], quv = c[4], qvv = 2.0 * c[5];
     const double hxx = j00 * j00 * quu + 2.0 * j00 * j10 * quv + j10 * j10 * qvv;
