@@ -884,10 +884,12 @@ void drop_level(Plan& p, int l, size_t mark, size_t bytes_before)
     p.lb[l] = LevelBufs{};
 }
 
-// Device time (ms, best of 3 after one warm-up) of one level's kernels:
-// grid zeroing, strengths, spread, row FFT, column pass, row inverse FFT and
-// interpolation, with the node weights standing in for the densities.
-vp_status time_level(Plan& p, int l, double* ms)
+// Device time (ms, best of 3 after one warm-up) of one level's kernels, in two
+// parts: grid zeroing, strengths, spread, row FFT, column pass and row inverse
+// FFT (*ms_grid), then the interpolation (*ms_interp), with the node weights
+// standing in for the densities.  The first part depends on the spreading tile
+// and not on the interpolation's, the second the other way round.
+vp_status time_level(Plan& p, int l, double* ms_grid, double* ms_interp)
 {
     const LevelGeom& g = p.lv[l];
     const size_t rb = p.precision == VP_FP32 ? sizeof(float) : sizeof(double);
@@ -937,10 +939,11 @@ vp_status time_level(Plan& p, int l, double* ms)
     const double* sig = ub && !ud ? p.d_w + p.n_src : nullptr;
     const double* mu = ud ? p.d_w + p.n_src : nullptr;
     hipStream_t st = p.stream;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t e0 = nullptr, em = nullptr, e1 = nullptr;
     hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&em);
     if (err == hipSuccess) err = hipEventCreate(&e1);
-    double best = INFINITY;
+    double best_g = INFINITY, best_i = INFINITY;
     for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
         err = hipEventRecord(e0, st);
         if (err == hipSuccess) err = launch_zero(p, ws, st);
@@ -949,18 +952,25 @@ vp_status time_level(Plan& p, int l, double* ms)
         if (err == hipSuccess) err = launch_row_fft(p, ws, st, l, ud);
         if (err == hipSuccess) err = launch_col_fft(p, ws, st, l, ud);
         if (err == hipSuccess) err = launch_row_ifft(p, ws, st, l);
+        if (err == hipSuccess) err = hipEventRecord(em, st);
         if (err == hipSuccess) err = launch_interp(p, ws, st, l);
         if (err == hipSuccess) err = hipEventRecord(e1, st);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float t = 0;
-        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
-        if (err == hipSuccess && rep > 0) best = std::min(best, (double)t);
+        float tg = 0, ti = 0;
+        if (err == hipSuccess) err = hipEventElapsedTime(&tg, e0, em);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ti, em, e1);
+        if (err == hipSuccess && rep > 0) {
+            best_g = std::min(best_g, (double)tg);
+            best_i = std::min(best_i, (double)ti);
+        }
     }
     if (e0) hipEventDestroy(e0);
+    if (em) hipEventDestroy(em);
     if (e1) hipEventDestroy(e1);
     hipFree(blk);
     if (err != hipSuccess) return fail(VP_ERR_DEVICE, std::string("autotune timing: ") + hipGetErrorString(err));
-    *ms = best;
+    *ms_grid = best_g;
+    *ms_interp = best_i;
     return VP_OK;
 }
 
@@ -1437,26 +1447,44 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
     else tiles.push_back(0);  // by width, below
     p->autotuned = o.autotune ? 1 : 0;
     for (int l = 0; l < 2; ++l) {
-        int best_c = -1, best_T = 0;
+        int best_c = -1, best_T = 0, best_Ti = 0;
         if (o.autotune) {
+            // Each candidate grid is timed with each tile edge T, the interpolation on the
+            // same edge.  The grid chain (zeroing to the inverse row pass) does not depend on
+            // the interpolation's tile, nor the interpolation on the spreading tile, so a
+            // candidate's time is its best grid chain plus its best interpolation, whichever
+            // edges they were timed with (a spreading tile and another interpolation tile
+            // may win together without being timed together).
             double best_ms = INFINITY;
-            for (size_t ci = 0; ci < cands[l].size(); ++ci)
+            for (size_t ci = 0; ci < cands[l].size(); ++ci) {
+                double g_best = INFINITY, i_best = INFINITY;
+                int g_T = 0, i_T = 0;
                 for (int T : tiles) {
                     if ((s = set_level_geom(*p, l, cands[l][ci], T, cx, cy)) != VP_OK) return bail(s);
                     if (!level_fits_lds(*p, l)) continue;
                     const size_t mark = p->allocs.size(), bytes0 = p->device_bytes;
                     if ((s = build(l)) != VP_OK) return bail(s);
-                    double ms = INFINITY;
-                    s = time_level(*p, l, &ms);
+                    double ms_g = INFINITY, ms_i = INFINITY;
+                    s = time_level(*p, l, &ms_g, &ms_i);
                     drop_level(*p, l, mark, bytes0);
                     if (s != VP_OK) return bail(s);
                     p->tune_cands[l]++;
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best_c = (int)ci;
-                        best_T = T;
+                    if (ms_g < g_best) {
+                        g_best = ms_g;
+                        g_T = T;
+                    }
+                    if (ms_i < i_best) {
+                        i_best = ms_i;
+                        i_T = T;
                     }
                 }
+                if (g_T > 0 && g_best + i_best < best_ms) {
+                    best_ms = g_best + i_best;
+                    best_c = (int)ci;
+                    best_T = g_T;
+                    best_Ti = i_T;
+                }
+            }
             p->level_ms[l] = best_ms;
         } else {
             for (size_t ci = 0; ci < cands[l].size() && best_c < 0; ++ci) {
@@ -1473,28 +1501,26 @@ vp_status vp_plan(vp_plan_t* out, int64_t n_src, const double* src_x, const doub
             }
         }
         if (best_c < 0) return bail(fail(VP_ERR_TOL, "working set too large for LDS"));
-        int best_Ti = 0;
-        if (o.autotune) {
-            // the interpolation's own tile: the chosen level timed again with each other tile
-            // edge (also when the spreading tile is forced)
+        if (o.autotune && tiles.size() == 1) {
+            // a forced spreading tile: the interpolation timed again on the other edge
             for (int Ti : {32, 16}) {
                 if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy)) != VP_OK) return bail(s);
                 if (Ti == p->lv[l].T || !set_interp_tile(p->lv[l], Ti) || !level_fits_lds(*p, l)) continue;
                 const size_t mark = p->allocs.size(), bytes0 = p->device_bytes;
                 if ((s = build(l)) != VP_OK) return bail(s);
-                double ms = INFINITY;
-                s = time_level(*p, l, &ms);
+                double ms_g = INFINITY, ms_i = INFINITY;
+                s = time_level(*p, l, &ms_g, &ms_i);
                 drop_level(*p, l, mark, bytes0);
                 if (s != VP_OK) return bail(s);
                 p->tune_cands[l]++;
-                if (ms < p->level_ms[l]) {
-                    p->level_ms[l] = ms;
+                if (ms_g + ms_i < p->level_ms[l]) {
+                    p->level_ms[l] = ms_g + ms_i;
                     best_Ti = p->lv[l].Ti;
                 }
             }
         }
         if ((s = set_level_geom(*p, l, cands[l][best_c], best_T, cx, cy)) != VP_OK) return bail(s);
-        if (best_Ti > 0) set_interp_tile(p->lv[l], best_Ti);
+        if (best_Ti > 0 && best_Ti != best_T) set_interp_tile(p->lv[l], best_Ti);
         if ((s = build(l)) != VP_OK) return bail(s);
     }
     if (!o.no_workspace) {
