@@ -229,6 +229,8 @@ def main():
                     help="targets of the main workload the CPU oracle evaluates (its timing is the "
                          "cpu_baseline, about 10 s on 16 cores; its values check the GPU result)")
     ap.add_argument("--no-fp32-leg", action="store_true")
+    ap.add_argument("--no-disk-legs", action="store_true",
+                    help="skip the 12M-node disk legs (FP64 and FP32) but keep FP32 on the square workload")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workloads (quick runs)")
     ap.add_argument("--no-batch-leg", action="store_true")
     ap.add_argument("--no-refine-leg", action="store_true")
@@ -369,7 +371,7 @@ def main():
         log("bench: interior Neumann leg at the paper's sizes")
         rec["neumann_paper"] = neumann_paper_leg(torch, [int(float(v) * args.scale) for v in
                                                          args.neumann_sizes.split(",")])
-    if not args.no_fp32_leg:
+    if not args.no_fp32_leg and not args.no_disk_legs:
         log("bench: generating disk-2M workload")
         Q = config_problem(3, scale=args.scale)
         sample = disk2m_oracle_sample(Q)
